@@ -1,0 +1,312 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix (no GPU).
+
+Each test fails on a plausible mistake in the oracle: a dropped term or wrong coefficient in A or F shows in
+the truncation or convergence order, a wrong gamma/zeta/grid placement shows in the paper's printed Table 2
+errors, a transposed eigenvector matrix shows in the EigT-vs-sparse-LU check, and so on.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg
+import scipy.sparse.linalg as spla
+
+import synth
+from oracle import krylov as kr
+from oracle import operators as op
+from oracle import precond as pc
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ------------------------------------------------------------------------------------------- 1D pieces
+
+def test_gamma_satisfies_two_point_closure():
+    """U_0 = gamma U_1 solves (U_1 - U_0)/h + i k0 (U_1 + U_0)/2 = 0 (Sec. 2.3); |gamma| = 1 for real k0."""
+    for k0, h in ((20.0, 1 / 33), (120.0, 1 / 257), (60.0, 0.01)):
+        g = op.gamma_abc(k0, h)
+        u1 = 0.7 - 0.2j
+        u0 = g * u1
+        assert abs((u1 - u0) / h + 1j * k0 * (u1 + u0) / 2) < 1e-12 * abs(u1) / h
+        assert abs(abs(g) - 1.0) < 1e-15 and g.imag > 0
+
+
+def test_dirichlet_eigenpairs_closed_form():
+    """gamma = 0: eigenvalues 2 cos(pi h i), orthonormal eigenvectors sqrt(2h) sin(pi h i l) (Sec. 3.1 eq. LMB_egv)."""
+    n = 17
+    d, V, Vi = pc.eig1d(n, 0.0)
+    S = pc.dst_matrix(n)
+    lam = 2 * np.cos(np.pi * np.arange(1, n + 1) / (n + 1))
+    assert np.allclose(np.sort(d.real), np.sort(lam), atol=1e-13) and abs(d.imag).max() < 1e-13
+    # each computed eigenvector is a multiple of one sine vector
+    C = np.abs(S.T @ (V / np.linalg.norm(V, axis=0)))
+    assert np.allclose(np.sort(C.max(axis=0)), 1.0, atol=1e-12)
+    assert np.allclose(S @ S.T, np.eye(n), atol=1e-13)
+
+
+def test_thomas_matches_dense_solve():
+    rng = np.random.default_rng(5)
+    nz, ny, nx = 9, 3, 4
+    b = rng.standard_normal((ny, nx)) * 0.3 - 2.0 + 1j * rng.uniform(0.05, 0.5, (ny, nx))
+    gz = 0.8 + 0.6j
+    r = rng.standard_normal((nz, ny, nx)) + 1j * rng.standard_normal((nz, ny, nx))
+    u = pc.thomas(b, gz, r)
+    for j in range(ny):
+        for i in range(nx):
+            T = np.diag(np.full(nz, b[j, i])) + np.diag(np.ones(nz - 1), 1) + np.diag(np.ones(nz - 1), -1)
+            T[0, 0] += gz
+            T[-1, -1] += gz
+            assert np.allclose(u[:, j, i], np.linalg.solve(T, r[:, j, i]), rtol=1e-12, atol=1e-12)
+
+
+# ------------------------------------------------------------------------------------------- operator A
+
+@pytest.mark.parametrize("order", [2, 4, 6])
+def test_kron_route_equals_stencil_route(order):
+    rng = np.random.default_rng(order)
+    shape = (5, 6, 7)
+    h3 = (0.1, 0.1, 0.1) if order == 6 else (0.1, 0.13, 0.07)
+    k2h = 30 + 10 * rng.random(tuple(s + 4 for s in shape))
+    k2i = k2h[2:-2, 2:-2, 2:-2]
+    g = (0.3 + 0.8j, 0.5 + 0.2j, -0.4 + 0.9j)
+    fields = op.derived_fields(k2h, h3[0]) if order == 6 else None
+    A1 = op.A_kron(order, k2i, h3, g, fields)
+    A2 = op.A_stencil(order, k2i, h3, g, fields)
+    assert abs(A1 - A2).max() <= 1e-14 * abs(A1).max()
+    assert np.diff(A1.indptr).max() == {2: 7, 4: 19, 6: 27}[order]
+
+
+def _smooth_case(n):
+    """u = exp(i k.x)(1 + 0.3 x y) with k = (2.1, -1.3, 1.7); k^2 = 30 (1 + 0.5 sin 2x cos(3y + z)), on the halo grid."""
+    c = synth.halo_coords(n)
+    z, y, x = c[:, None, None], c[None, :, None], c[None, None, :]
+    kv = np.array([2.1, -1.3, 1.7])
+    E = np.exp(1j * (kv[0] * x + kv[1] * y + kv[2] * z))
+    u = E * (1 + 0.3 * x * y)
+    lapu = E * (-(kv @ kv) * (1 + 0.3 * x * y) + 2j * 0.3 * (kv[0] * y + kv[1] * x))
+    k2 = 30.0 * (1 + 0.5 * np.sin(2 * x) * np.cos(3 * y + z))
+    return u, k2, lapu + k2 * u
+
+
+def _truncation(order, n):
+    h = 1.0 / (n + 1)
+    u, k2, f = _smooth_case(n)
+    fields = op.derived_fields(k2, h) if order == 6 else None
+    coefs = op.stencil_coefficients(order, (h, h, h), k2[1:-1, 1:-1, 1:-1], fields)
+    Au = op.apply_unfolded(coefs, u[1:-1, 1:-1, 1:-1])
+    F = op.rhs(order, f, (h, h, h), k2[2:-2, 2:-2, 2:-2], fields)
+    return np.abs(Au - F).max()
+
+
+@pytest.mark.parametrize("order,slope", [(2, 1.85), (4, 3.75), (6, 5.6)])
+def test_truncation_order(order, slope):
+    """Local truncation error of A u - F on smooth u and variable k^2 falls as h^order (Sec. 2.2, 2.3)."""
+    e1, e2 = _truncation(order, 16), _truncation(order, 32)
+    assert np.log2(e1 / e2) > slope
+
+
+def _exact_ghost_error(order, n):
+    """Global error with exact ghost data: A_D U = F - (ghost terms), A_D the gamma = 0 fold."""
+    h = 1.0 / (n + 1)
+    u, k2, f = _smooth_case(n)
+    fields = op.derived_fields(k2, h) if order == 6 else None
+    k2i = k2[2:-2, 2:-2, 2:-2]
+    A_D = op.A_stencil(order, k2i, (h, h, h), (0.0, 0.0, 0.0), fields)
+    coefs = op.stencil_coefficients(order, (h, h, h), k2[1:-1, 1:-1, 1:-1], fields)
+    ghost = u[1:-1, 1:-1, 1:-1].copy()
+    ghost[1:-1, 1:-1, 1:-1] = 0.0
+    F = op.rhs(order, f, (h, h, h), k2i, fields) - op.apply_unfolded(coefs, ghost)
+    U = spla.splu(A_D.tocsc()).solve(F.ravel())
+    ui = u[2:-2, 2:-2, 2:-2].ravel()
+    return np.linalg.norm(U - ui) / np.linalg.norm(ui)
+
+
+@pytest.mark.parametrize("order,slope", [(4, 3.6), (6, 5.5)])
+def test_global_order_with_exact_ghosts(order, slope):
+    e1, e2 = _exact_ghost_error(order, 8), _exact_ghost_error(order, 16)
+    assert np.log2(e1 / e2) > slope
+
+
+def test_derived_fields_fourth_order():
+    def err(n):
+        h = 1.0 / (n + 1)
+        c = synth.halo_coords(n)
+        z, y, x = c[:, None, None], c[None, :, None], c[None, None, :]
+        k2 = np.sin(2 * x) * np.cos(3 * y + z) + x * x * y
+        kx, ky, kz, lap = op.derived_fields(k2, h)
+        I = (slice(2, -2),) * 3
+        ex = (2 * np.cos(2 * x) * np.cos(3 * y + z) + 2 * x * y)[I]
+        ez = (-np.sin(2 * x) * np.sin(3 * y + z) + 0 * y)[I]
+        el = (-4 * np.sin(2 * x) * np.cos(3 * y + z) - 10 * np.sin(2 * x) * np.cos(3 * y + z) + 2 * y)[I]
+        return max(abs(kx - ex).max(), abs(kz - ez).max(), abs(lap - el).max())
+    assert np.log2(err(16) / err(32)) > 3.7
+
+
+def test_abc_manufactured_solution_second_order():
+    """With the first-order two-point absorbing closure the global error is O(h^2) whatever the interior order
+    (Sec. 6): phi(x)phi(y)phi(z) of Sec. 5.1 with a, b on the boundary planes solves the continuous problem."""
+    def err(order, n):
+        k0 = 6.0
+        h = 1.0 / n
+        xs = (np.arange(-2, n + 2) + 0.5) * h   # staggered nodes, boundary at 0 and 1
+        z, y, x = xs[:, None, None], xs[None, :, None], xs[None, None, :]
+        ph = lambda t: np.exp(1j * k0 * t) + np.exp(-1j * k0 * (t - 1)) - 2
+        p2 = lambda t: -k0 * k0 * (np.exp(1j * k0 * t) + np.exp(-1j * k0 * (t - 1)))
+        u = ph(x) * ph(y) * ph(z)
+        f = p2(x) * ph(y) * ph(z) + ph(x) * p2(y) * ph(z) + ph(x) * ph(y) * p2(z) + k0 * k0 * u
+        k2 = np.full(u.shape, k0 * k0)
+        A, F = op.problem(order, k2, f, h, k0)
+        U = spla.splu(A.tocsc()).solve(F)
+        ui = u[2:-2, 2:-2, 2:-2].ravel()
+        return np.linalg.norm(U - ui) / np.linalg.norm(ui)
+    for order in (4, 6):
+        assert 1.7 < np.log2(err(order, 8) / err(order, 16)) < 2.6
+
+
+# ------------------------------------------------------------------------------------------- the paper's Table 2
+
+def _test_problem_direct(n):
+    k0 = np.sqrt(439.2)
+    h = 1.0 / n
+    x = (np.arange(n) + 0.5) * h
+    X, Y, Z = x[None, None, :], x[None, :, None], x[:, None, None]
+    ph = lambda t: np.exp(1j * k0 * t) + np.exp(-1j * k0 * (t - 1.0)) - 2
+    p2 = lambda t: -k0 * k0 * (np.exp(1j * k0 * t) + np.exp(-1j * k0 * (t - 1.0)))
+    u = ph(X) * ph(Y) * ph(Z)
+    f = p2(X) * ph(Y) * ph(Z) + ph(X) * p2(Y) * ph(Z) + ph(X) * ph(Y) * p2(Z) + k0 * k0 * u
+    g = op.gamma_abc(k0, h)
+    U = pc.EigT((n, n, n), (h, h, h), k0, (g, g, g)).solve(f.ravel()).reshape(u.shape)
+    return np.abs(U - u).max(), np.linalg.norm(U - u) / np.linalg.norm(u)
+
+
+def test_paper_table2_direct_second_order_errors():
+    """EigT2 as a direct solver of the 2nd-order system reproduces the errors printed in Table 2."""
+    with open(os.path.join(GOLDEN, "table2_direct_2nd_order.json")) as fh:
+        g = json.load(fh)
+    for n, mx_p, l2_p in g["rows"]:
+        mx, l2 = _test_problem_direct(n)
+        assert abs(mx - mx_p) <= 0.006 * mx_p, (n, mx, mx_p)          # printed to 3 digits
+        assert abs(l2 - l2_p) <= 0.05 * l2_p, (n, l2, l2_p)           # printed to 2 digits
+
+
+# ------------------------------------------------------------------------------------------- preconditioners
+
+def _prec_case(n=10, k0=20.0):
+    h = 1.0 / (n + 1)
+    g = op.gamma_abc(k0, h)
+    shape = (n, n + 1, n + 2)
+    h3 = (h, h, h)
+    rng = np.random.default_rng(7)
+    y = rng.standard_normal(np.prod(shape)) + 1j * rng.standard_normal(np.prod(shape))
+    return shape, h3, k0, (g, g, g), y
+
+
+def test_eigt_inverts_M():
+    shape, h3, k0, gs, y = _prec_case()
+    M = pc.M_matrix(shape, h3, k0, gs)
+    z = pc.EigT(shape, h3, k0, gs).solve(y)
+    assert np.linalg.norm(M @ z - y) <= 1e-12 * np.linalg.norm(y)
+    zs = spla.splu(M.tocsc()).solve(y)
+    assert np.linalg.norm(z - zs) <= 1e-12 * np.linalg.norm(zs)
+
+
+def test_eigt_non_uniform_h():
+    n = 8
+    shape, h3 = (n, n, n), (0.1, 0.08, 0.12)
+    gs = tuple(op.gamma_abc(15.0, h) for h in h3)
+    rng = np.random.default_rng(3)
+    y = rng.standard_normal(n ** 3) + 0j
+    M = pc.M_matrix(shape, h3, 15.0, gs)
+    z = pc.EigT(shape, h3, 15.0, gs).solve(y)
+    assert np.linalg.norm(M @ z - y) <= 1e-12 * np.linalg.norm(y)
+
+
+def test_pfft_equals_eigt_and_sparse_transforms():
+    shape, h3, k0, gs, y = _prec_case()
+    e = pc.EigT(shape, h3, k0, gs)
+    z = e.solve(y)
+    zp = pc.PFFT(shape, h3, k0, gs).solve(y)
+    assert np.linalg.norm(zp - z) <= 1e-11 * np.linalg.norm(z)
+    rng = np.random.default_rng(9)
+    ring = np.zeros(shape, bool)
+    ring[:, :, [0, -1]] = True
+    ring[:, [0, -1], :] = True
+    Yr = np.where(ring, rng.standard_normal(shape), 0.0).astype(complex)
+    assert abs(pc.sparse_forward(e, Yr) - e.forward(Yr)).max() < 1e-13
+    Wb = rng.standard_normal(shape) + 0j
+    assert abs(pc.restricted_inverse(e, Wb) - np.where(ring, e.inverse(Wb), 0)).max() < 1e-13
+
+
+def test_dirichlet_eigt_is_the_sine_solver():
+    """gamma = 0 in x and y turns EigT into the sine-transform solver of A_p^F (Sec. 4.2)."""
+    shape, h3, k0, gs, y = _prec_case()
+    gz = gs[2]
+    e = pc.EigT(shape, h3, k0, (0.0, 0.0, gz))
+    p = pc.PFFT(shape, h3, k0, (0.0, 0.0, gz))
+    ys = h3[2] ** 2 * y.reshape(shape)
+    assert np.linalg.norm(e.solve(y) - p.solve_F(ys).ravel()) <= 1e-12 * np.linalg.norm(y)
+
+
+# ------------------------------------------------------------------------------------------- GMRES
+
+def _small_problem(order=6, n=14, k0=None):
+    k0 = k0 or 0.47 * (n + 1)
+    h = 1.0 / (n + 1)
+    k2 = synth.inclusions_k2(n, k0)
+    f = synth.gaussian_source(n)
+    A, F = op.problem(order, k2, f, h, k0)
+    g = op.gamma_abc(k0, h)
+    e = pc.EigT((n, n, n), (h, h, h), k0, (g, g, g))
+    return A, F, e
+
+
+@pytest.mark.parametrize("order", [4, 6])
+def test_gmres_matches_sparse_lu(order):
+    A, F, e = _small_problem(order)
+    xs = spla.splu(A.tocsc()).solve(F)
+    for flexible, m in ((False, 50), (True, 50), (False, 4)):
+        x, info = kr.gmres(lambda v: A @ v, e.solve, F, m=m, rtol=1e-10, flexible=flexible)
+        assert info["converged"]
+        assert np.linalg.norm(F - A @ x) <= 1e-10 * np.linalg.norm(F) * 1.0001
+        assert np.linalg.norm(x - xs) <= 1e-8 * np.linalg.norm(xs)
+        h = np.array(info["hist"])
+        if m == 50:
+            assert np.all(np.diff(h) <= 1e-12)      # residual is monotone within one cycle
+            assert info["iters"] <= 15
+
+
+def test_gmres_second_order_constant_k_one_iteration():
+    """order 2 with k^2 = k0^2 makes A equal to M, so preconditioned GMRES converges in one step."""
+    n, k0 = 12, 6.0
+    h = 1.0 / (n + 1)
+    A, F = op.problem(2, np.full((n + 4,) * 3, k0 * k0), synth.gaussian_source(n), h, k0)
+    g = op.gamma_abc(k0, h)
+    e = pc.EigT((n, n, n), (h, h, h), k0, (g, g, g))
+    x, info = kr.gmres(lambda v: A @ v, e.solve, F, m=10, rtol=1e-12)
+    assert info["iters"] == 1 and info["relres"] < 1e-12
+
+
+def test_gmres_zero_rhs_and_iteration_cap():
+    A, F, e = _small_problem(6, n=8, k0=4.0)
+    x, info = kr.gmres(lambda v: A @ v, e.solve, 0 * F, m=10)
+    assert info["iters"] == 0 and not np.any(x)
+    x, info = kr.gmres(lambda v: A @ v, e.solve, F, m=10, rtol=1e-14, maxit=2)
+    assert info["iters"] == 2 and not info["converged"]
+
+
+def test_constant_k_spectrum_clusters_near_one():
+    """Constant k: A6 and M share the eigenvectors V_z (x) V_y (x) V_x, and the eigenvalues of A M^{-1}
+    stay in a bounded cluster around 1 (1 + O((k h)^2) for the smooth modes, the 3D analogue of Sec. 3.1
+    eq. 1DEGV; the highest-frequency modes differ by O(1) between the compact and 7-point symbols)."""
+    n, k0 = 6, 3.0
+    h = 1.0 / (n + 1)
+    A, _ = op.problem(6, np.full((n + 4,) * 3, k0 * k0), synth.gaussian_source(n), h, k0)
+    g = op.gamma_abc(k0, h)
+    M = pc.M_matrix((n, n, n), (h, h, h), k0, (g, g, g))
+    lam = scipy.linalg.eigvals(A.toarray() @ np.linalg.inv(M.toarray()))
+    assert abs(lam - 1).max() < 0.6 and abs(lam - 1).min() < 0.05 and lam.real.min() > 0.4
+    _, V, Vi = pc.eig1d(n, g)
+    W = np.kron(V, np.kron(V, V))
+    D = np.kron(Vi, np.kron(Vi, Vi)) @ A.toarray() @ W
+    assert abs(D - np.diag(np.diag(D))).max() < 1e-9 * abs(D).max()
