@@ -1,0 +1,157 @@
+/*
+ * libhelm — compact 4th/6th-order 3D Helmholtz solver with the EigT / PFFT preconditioner on one MI355X GPU.
+ *
+ * Method: arXiv 2602.07711 (Gryazin, Gonzales, Li), "High-Resolution Solvers for 3D Helmholtz Scattering
+ * Problems Using PFFT and Eigenvector-Based Preconditioning".
+ *
+ *   PDE        nabla^2 u + k^2(x) u = f on a box, absorbing condition du/dn - i k0 u = 0 (Sec. 1, Sec. 2.1).
+ *   Grid       N_nu unknowns per axis at spacing h_nu; the absorbing condition sits half a cell outside the
+ *              first and last node and eliminates the ghosts as U_0 = gamma U_1, U_{N+1} = gamma U_N with
+ *              gamma = (2 + i k0 h)/(2 - i k0 h) (Sec. 2.3, eq. D_bc). Dirichlet uses gamma = 0.
+ *   Operator   A = compact 4th-order scheme (Sec. 2.2, eq. scheme4; 19 points, any h) or 6th-order scheme
+ *              (Sec. 2.3, eq. scheme6; 27 points, uniform h), or the plain 7-point 2nd-order operator.
+ *   Precond.   M = Delta_2 + k0^2 I, the 7-point operator with the same absorbing closure and the background
+ *              k0 (Sec. 4: A_p / h_z^2). Applied by EigT (Sec. 4.1, eq. EIG_SOLVER) or PFFT (Sec. 4.2, eq.
+ *              PFFT_SOLVER), in complex FP64 or complex FP32.
+ *   Krylov     restarted right-preconditioned GMRES(m) (Sec. 3.1 eq. Preconditioned_System, Sec. 5) or
+ *              flexible GMRES(m) (needed when the preconditioner runs in FP32 or changes between calls).
+ *
+ * Data layout.  Every vector is an array of complex128 (interleaved re, im; 16 bytes) in device memory with
+ * index i + Nx*(j + Ny*l): x fastest, then y, then z (the slice ordering of Sec. 4.1). Fields sampled with a
+ * two-cell halo have (Nx+4)*(Ny+4)*(Nz+4) entries in the same order, node (i,j,l) at (i+2, j+2, l+2).
+ *
+ * Ownership.  All pointers passed in are caller-owned device memory. The library reads them during the
+ * call (k^2 during helm_setup only) and keeps no reference afterwards. The context owns every buffer it
+ * allocates (eigen-data, derived fields, Krylov workspace) and helm_destroy frees them.
+ *
+ * Streams.  Every call enqueues its kernels on the stream given to helm_setup (NULL = the default stream)
+ * of the device that was current at helm_setup. helm_rhs, helm_matvec and helm_precond_apply return
+ * without waiting; helm_gmres_solve returns after the solve with `info` filled in. One context must not be
+ * used by two host threads at once.
+ *
+ * Errors.  Functions return a helm_status and never throw. The message of the last failure on a context is
+ * available from helm_last_error(ctx); helm_setup failures before a context exists are reported through
+ * helm_last_setup_error().
+ */
+#ifndef HELM_H
+#define HELM_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct helm_ctx helm_ctx;
+
+typedef enum {
+    HELM_OK = 0,
+    HELM_EINVAL = 1,       /* invalid argument: shape, order, h, halo, NULL pointer, NaN/Inf in k^2        */
+    HELM_ENOMEM = 2,       /* device allocation failed                                                     */
+    HELM_EDEVICE = 3,      /* a HIP runtime call failed                                                    */
+    HELM_ENOCONV = 4,      /* GMRES hit maxit; x holds the last iterate                                    */
+    HELM_EBREAKDOWN = 5,   /* Arnoldi breakdown with a residual above tolerance                            */
+    HELM_ENUMERIC = 6,     /* NaN/Inf appeared in a reduction, or the 1D eigen-decomposition failed checks */
+    HELM_EUNSUPPORTED = 7  /* a valid request that this build does not implement                           */
+} helm_status;
+
+typedef struct { int nx, ny, nz; } helm_grid;   /* unknowns per axis, each >= 3 */
+
+typedef enum {
+    HELM_BC_ABC2 = 0,      /* two-point absorbing closure, gamma = (2 + i k0 h)/(2 - i k0 h), zeta = 1 (Sec. 2.3) */
+    HELM_BC_DIRICHLET = 1  /* gamma = 0: zero ghost values                                                     */
+} helm_bc_kind;
+
+typedef struct {
+    int kind;              /* helm_bc_kind                                                                  */
+    double k0;             /* background wavenumber on the boundary (Sec. 2.1 eq. background); also the
+                              constant k0 of the preconditioner M                                           */
+} helm_bc;
+
+typedef enum {
+    HELM_PREC_EIGT = 0,    /* eigenvector transforms in x and y + z-tridiagonal solves (Sec. 4.1)            */
+    HELM_PREC_PFFT = 1,    /* sine transforms + boundary correction on the x/y faces (Sec. 4.2)               */
+    HELM_PREC_NONE = 2     /* identity (unpreconditioned GMRES)                                              */
+} helm_prec_kind;
+
+typedef struct {
+    int m;                 /* restart length, 1..256                                                         */
+    int maxit;             /* total iteration cap (> 0)                                                      */
+    double rtol;           /* stop when ||F - A x||_2 <= rtol * ||F||_2 (Sec. 5.1 rel-res with U^0 = 0)      */
+    int flexible;          /* 0: right-preconditioned GMRES, x = x0 + M^{-1} V y; 1: FGMRES, x = x0 + Z y    */
+    int prec_fp32;         /* 1: run the preconditioner in complex FP32 (requires flexible = 1)              */
+    int prec;              /* helm_prec_kind                                                                 */
+    int x0_given;          /* 1: x holds the initial guess on entry; 0: start from x = 0                     */
+    double *resid_hist;    /* optional host array receiving relative residual estimates, one per iteration
+                              plus one per restart (true residual); may be NULL                              */
+    int hist_len;          /* capacity of resid_hist                                                         */
+} helm_solve_opts;
+
+typedef struct {
+    int iters;             /* Arnoldi steps taken (= preconditioner applications inside cycles)             */
+    int restarts;          /* completed cycles                                                               */
+    int converged;         /* 1 if the true residual met rtol                                                */
+    int hist_used;         /* entries written to resid_hist                                                  */
+    double relres_est;     /* last Givens residual estimate / ||F||                                          */
+    double relres_true;    /* ||F - A x|| / ||F|| at exit                                                    */
+    double t_ms[6];        /* device time per phase: matvec, preconditioner, Arnoldi (dots + update),
+                              end-of-cycle update, host work (Givens, sync), total wall                      */
+} helm_solve_info;
+
+/* Create a context: validates the grid, computes gamma per axis, runs the 1D eigen-decompositions of
+ * Lambda-bar_x and Lambda-bar_y on the host (Sec. 4.1 EigT Step 1), uploads V, V^{-1}, D, and derives the
+ * per-node fields of the operator from k^2 (Sec. 2.3: grad k^2 and lap k^2 by 4th-order central differences).
+ *   g        unknowns per axis (each >= 3).
+ *   h        grid steps h_x, h_y, h_z (> 0). order 6 requires h_x = h_y = h_z (Sec. 2.3).
+ *   k2_dev   real k^2 samples (float64) in device memory, with a two-cell halo (k2_halo = 2) or on the
+ *            interior only (k2_halo = 0; allowed for order 2 and 4, which need no derivatives of k^2).
+ *   order    2, 4 or 6.
+ *   bc       closure kind and background k0 (k0 >= 0 and finite).
+ *   stream   hipStream_t to enqueue on, or NULL.
+ * On success *ctx owns its device buffers. Returns HELM_EINVAL for bad arguments or non-finite k^2,
+ * HELM_ENOMEM / HELM_EDEVICE on runtime failures, HELM_ENUMERIC if the eigen-decomposition fails its
+ * residual checks. */
+helm_status helm_setup(helm_ctx **ctx, helm_grid g, const double h[3], const double *k2_dev, int k2_halo,
+                       int order, helm_bc bc, void *stream);
+
+/* F = R_h f, the modified right-hand side of the scheme (Sec. 2.2 f^(IV), Sec. 2.3 f^(VI) together with the
+ * k^2 f and f_nu terms of Delta_h(k^2 U)). f_dev: complex128 samples of f with a two-cell halo.
+ * F_dev: n complex128. f is data: its halo samples are used as they are. */
+helm_status helm_rhs(helm_ctx *ctx, const void *f_dev, void *F_dev);
+
+/* y = A x (the compact operator with the ghost-eliminated absorbing closure). x_dev, y_dev: n complex128,
+ * must not overlap. */
+helm_status helm_matvec(helm_ctx *ctx, const void *x_dev, void *y_dev);
+
+/* z = M^{-1} y with M = Delta_2 + k0^2 I (Sec. 4). kind: HELM_PREC_EIGT or HELM_PREC_PFFT; fp32: 1 runs the
+ * transforms and tridiagonal solves in complex FP32 (input read as FP64, output written as FP64).
+ * y_dev, z_dev: n complex128; they may be the same buffer. */
+helm_status helm_precond_apply(helm_ctx *ctx, const void *y_dev, void *z_dev, int kind, int fp32);
+
+/* Solve A x = F by restarted (F)GMRES preconditioned on the right by M (Sec. 3.1, Sec. 4, Sec. 5).
+ * F_dev: n complex128. x_dev: n complex128, initial guess on entry when opts->x0_given, solution on exit.
+ * The Krylov workspace ((m+1) + (flexible ? m : 0) vectors of n complex128) is allocated on the first solve
+ * with a given (m, flexible) and kept by the context. Returns HELM_OK when converged, HELM_ENOCONV at maxit
+ * (x holds the last iterate), HELM_EBREAKDOWN, HELM_ENUMERIC on NaN/Inf, HELM_EINVAL for bad options. */
+helm_status helm_gmres_solve(helm_ctx *ctx, const void *F_dev, void *x_dev, const helm_solve_opts *opts,
+                             helm_solve_info *info);
+
+/* Number of unknowns n = Nx*Ny*Nz of a context. */
+long long helm_size(const helm_ctx *ctx);
+
+/* Message of the last failure on ctx (never NULL; "" if none). */
+const char *helm_last_error(const helm_ctx *ctx);
+
+/* Message of the last helm_setup failure in this process (never NULL). */
+const char *helm_last_setup_error(void);
+
+/* Free every buffer owned by ctx. NULL is allowed. */
+void helm_destroy(helm_ctx *ctx);
+
+/* Host-side 1D eigen-decomposition of Lambda-bar (Sec. 4.1, eq. lambda_mat_definition with zeta = 1):
+ * Lambda-bar = V diag(d) V^{-1}. n >= 2; gamma as (re, im). Outputs are host arrays of complex128 (re, im):
+ * d[n], V[n*n] and Vinv[n*n] in row-major order. Returns HELM_ENUMERIC if the residual checks fail. */
+helm_status helm_eig1d(int n, double gamma_re, double gamma_im, double *d, double *V, double *Vinv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HELM_H */

@@ -178,6 +178,50 @@ def A_kron(order: int, k2_int: np.ndarray, h3, gammas, fields=None) -> sp.csr_ma
 OFFSETS = [o for o in itertools.product((-1, 0, 1), repeat=3)]  # (dx, dy, dz)
 
 
+def _offset_coefficient(order, h3, o, kc, ko, fields):
+    """The unfolded coefficient of neighbour offset o = (dx, dy, dz) (see `stencil_coefficients`); kc is k^2 at
+    the node, ko k^2 at the neighbour, fields = (kx, ky, kz, lap) at the node (order 6). Works elementwise on
+    arrays of any shape. Returns None for offsets outside the stencil."""
+    nzs = [a for a in range(3) if o[a] != 0]
+    hs = [float(v) for v in h3]
+    if order == 2:
+        if len(nzs) == 0:
+            return -sum(2.0 / (x * x) for x in hs) + kc
+        if len(nzs) == 1:
+            return np.full(np.shape(kc), 1.0 / hs[nzs[0]] ** 2)
+        return None
+    if order == 4:
+        if len(nzs) == 0:
+            return (-sum(2.0 / (x * x) for x in hs)
+                    + sum((hs[a] ** 2 + hs[b] ** 2) / (3.0 * hs[a] ** 2 * hs[b] ** 2)
+                          for a, b in ((0, 1), (0, 2), (1, 2)))
+                    + 0.5 * kc)
+        if len(nzs) == 1:
+            a = nzs[0]
+            return (1.0 / hs[a] ** 2
+                    - sum((hs[a] ** 2 + hs[b] ** 2) / (6.0 * hs[a] ** 2 * hs[b] ** 2) for b in range(3) if b != a)
+                    + ko / 12.0)
+        if len(nzs) == 2:
+            a, b = nzs
+            return np.full(np.shape(kc), (hs[a] ** 2 + hs[b] ** 2) / (12.0 * hs[a] ** 2 * hs[b] ** 2))
+        return None
+    if order == 6:
+        h = hs[0]
+        h2 = h * h
+        grads = fields[:3]
+        lap = fields[3]
+        if len(nzs) == 0:
+            return -64.0 / (15.0 * h2) + 14.0 / 15.0 * kc + h2 / 20.0 * (lap - kc * kc)
+        if len(nzs) == 1:
+            a = nzs[0]
+            return 14.0 / (30.0 * h2) - ko / 90.0 + o[a] * h * grads[a] * (2.0 + h2 * ko) / 120.0
+        if len(nzs) == 2:
+            a, b = nzs
+            return 3.0 / (30.0 * h2) + ko / 90.0 + h * (o[a] * grads[a] + o[b] * grads[b]) / 120.0
+        return np.full(np.shape(kc), 1.0 / (30.0 * h2))
+    raise ValueError(order)
+
+
 def stencil_coefficients(order: int, h3, k2_ext: np.ndarray, fields=None):
     """Coefficient arrays c_o (interior shape) of the unfolded stencil, (A U)_p = sum_o c_o(p) U_{p+o}.
 
@@ -195,62 +239,51 @@ def stencil_coefficients(order: int, h3, k2_ext: np.ndarray, fields=None):
     nz, ny, nx = (s - 2 for s in k2_ext.shape)
     kc = k2_ext[1:-1, 1:-1, 1:-1]
     coefs = {}
-
-    def kn(o):
+    for o in OFFSETS:
         dx, dy, dz = o
-        return k2_ext[1 + dz:1 + dz + nz, 1 + dy:1 + dy + ny, 1 + dx:1 + dx + nx]
-
-    if order in (2, 4):
-        hs = [float(v) for v in h3]
-        for o in OFFSETS:
-            nzs = [a for a in range(3) if o[a] != 0]
-            if order == 2:
-                if len(nzs) == 0:
-                    c = -sum(2.0 / (x * x) for x in hs) + kc
-                elif len(nzs) == 1:
-                    c = np.full(kc.shape, 1.0 / hs[nzs[0]] ** 2)
-                else:
-                    continue
-            else:
-                if len(nzs) == 0:
-                    c = (-sum(2.0 / (x * x) for x in hs)
-                         + sum((hs[a] ** 2 + hs[b] ** 2) / (3.0 * hs[a] ** 2 * hs[b] ** 2)
-                               for a, b in ((0, 1), (0, 2), (1, 2)))
-                         + 0.5 * kc)
-                elif len(nzs) == 1:
-                    a = nzs[0]
-                    c = (1.0 / hs[a] ** 2
-                         - sum((hs[a] ** 2 + hs[b] ** 2) / (6.0 * hs[a] ** 2 * hs[b] ** 2) for b in range(3) if b != a)
-                         + kn(o) / 12.0)
-                elif len(nzs) == 2:
-                    a, b = nzs
-                    c = np.full(kc.shape, (hs[a] ** 2 + hs[b] ** 2) / (12.0 * hs[a] ** 2 * hs[b] ** 2))
-                else:
-                    continue
+        ko = k2_ext[1 + dz:1 + dz + nz, 1 + dy:1 + dy + ny, 1 + dx:1 + dx + nx]
+        c = _offset_coefficient(order, h3, o, kc, ko, fields)
+        if c is not None:
             coefs[o] = np.asarray(c, np.complex128)
-        return coefs
+    return coefs
 
+
+def sampled_matvec(order: int, k2_halo: np.ndarray, h3, gammas, x: np.ndarray, nodes: np.ndarray) -> np.ndarray:
+    """(A x)_p for the flat node indices `nodes` only, by the per-offset route (the same coefficients and ghost
+    folding as `A_stencil`), so that full-size grids can be checked row by row. k2_halo has a two-cell halo
+    (order 2/4 read only its interior); x is the flat vector."""
+    nz, ny, nx = (s - 4 for s in k2_halo.shape)
+    k2i = k2_halo[2:-2, 2:-2, 2:-2]
+    nodes = np.asarray(nodes, np.int64)
+    I = nodes % nx
+    J = (nodes // nx) % ny
+    L = nodes // (nx * ny)
+    kc = k2i[L, J, I]
+    fields = None
     if order == 6:
         h = float(h3[0])
-        h2 = h * h
-        grads = fields[:3]
-        lap = fields[3]
-        for o in OFFSETS:
-            nzs = [a for a in range(3) if o[a] != 0]
-            if len(nzs) == 0:
-                c = -64.0 / (15.0 * h2) + 14.0 / 15.0 * kc + h2 / 20.0 * (lap - kc * kc)
-            elif len(nzs) == 1:
-                a = nzs[0]
-                ko = kn(o)
-                c = 14.0 / (30.0 * h2) - ko / 90.0 + o[a] * h * grads[a] * (2.0 + h2 * ko) / 120.0
-            elif len(nzs) == 2:
-                a, b = nzs
-                c = 3.0 / (30.0 * h2) + kn(o) / 90.0 + h * (o[a] * grads[a] + o[b] * grads[b]) / 120.0
-            else:
-                c = np.full(kc.shape, 1.0 / (30.0 * h2))
-            coefs[o] = np.asarray(c, np.complex128)
-        return coefs
-    raise ValueError(order)
+        g = []
+        lap = np.zeros(len(nodes))
+        for ax, (di, dj, dl) in enumerate(((1, 0, 0), (0, 1, 0), (0, 0, 1))):
+            at = lambda s: k2_halo[L + 2 + s * dl, J + 2 + s * dj, I + 2 + s * di]
+            g.append((-at(2) + 8.0 * at(1) - 8.0 * at(-1) + at(-2)) / (12.0 * h))
+            lap = lap + (-at(2) + 16.0 * at(1) - 30.0 * at(0) + 16.0 * at(-1) - at(-2)) / (12.0 * h * h)
+        fields = (g[0], g[1], g[2], lap)
+    dims = (nx, ny, nz)
+    out = np.zeros(len(nodes), np.complex128)
+    for o in OFFSETS:
+        q = [I + o[0], J + o[1], L + o[2]]
+        fac = np.ones(len(nodes), np.complex128)
+        for a in range(3):
+            outside = (q[a] < 0) | (q[a] > dims[a] - 1)
+            fac = np.where(outside, fac * gammas[a], fac)
+            q[a] = np.clip(q[a], 0, dims[a] - 1)
+        ko = k2i[q[2], q[1], q[0]]
+        c = _offset_coefficient(order, h3, o, kc, ko, fields)
+        if c is None:
+            continue
+        out += c * fac * x[q[0] + nx * (q[1] + ny * q[2])]
+    return out
 
 
 def apply_unfolded(coefs, u_pad: np.ndarray) -> np.ndarray:

@@ -179,3 +179,24 @@ def restricted_inverse(eig: EigT, Wb: np.ndarray) -> np.ndarray:
     for a, i in enumerate((0, nx - 1)):                     # Step 3: W_{i,j} for j = 2..N_y-1
         out[:, 1:ny - 1, i] = s[:, :, a] @ Vy[1:ny - 1, :].T
     return out
+
+
+def sampled_M(shape, h3, k0: float, gammas, z: np.ndarray, nodes: np.ndarray) -> np.ndarray:
+    """(M z)_p for the flat node indices `nodes` only: the 7-point rows of Delta + k0^2 I with the ghost rule
+    U_0 = gamma U_1 per axis, for checking a preconditioner output on full-size grids row by row."""
+    nz, ny, nx = shape
+    nodes = np.asarray(nodes, np.int64)
+    P = [nodes % nx, (nodes // nx) % ny, nodes // (nx * ny)]
+    dims = (nx, ny, nz)
+    zc = z[nodes]
+    out = k0 * k0 * zc
+    for a in range(3):
+        for s in (-1, 1):
+            q = [P[0].copy(), P[1].copy(), P[2].copy()]
+            q[a] = q[a] + s
+            outside = (q[a] < 0) | (q[a] > dims[a] - 1)
+            q[a] = np.clip(q[a], 0, dims[a] - 1)
+            val = z[q[0] + nx * (q[1] + ny * q[2])]
+            val = np.where(outside, gammas[a] * val, val)
+            out = out + (val - zc) / (h3[a] * h3[a])
+    return out

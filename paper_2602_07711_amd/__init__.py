@@ -1,0 +1,15 @@
+"""MI355X-native compact-Helmholtz solver: EigT/PFFT-preconditioned (F)GMRES on hand-written HIP kernels.
+
+The compute path lives in libhelm.so (C ABI, include/helm.h); `helm` is its ctypes binding.
+"""
+from .helm import (  # noqa: F401
+    HelmError,
+    helm_destroy,
+    helm_eig1d,
+    helm_gmres_solve,
+    helm_matvec,
+    helm_precond_apply,
+    helm_rhs,
+    helm_setup,
+    lib,
+)

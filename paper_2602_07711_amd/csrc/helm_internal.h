@@ -1,0 +1,115 @@
+// Internal declarations of libhelm: the context, kernel launchers and parameter blocks.
+#pragma once
+
+#include <complex>
+#include <string>
+#include <vector>
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/helm.h"
+
+namespace helm {
+
+using cd = std::complex<double>;
+
+bool eig_lambda_bar(int n, cd gamma, std::vector<cd> &d, std::vector<cd> &V, std::vector<cd> &Vinv,
+                    std::string &err);
+
+// Stencil coefficients that depend only on the grid (the k^2-dependent parts are per node).
+struct StencilParams {
+    int nx, ny, nz;
+    int order;
+    double2 gx, gy, gz;          // ghost factors per axis
+    // order 2/4: constant coefficients
+    double c_center;             // centre coefficient without the k^2 part
+    double c_face[3];            // face coefficient per axis without the k^2 part
+    double c_edge[3];            // edge coefficients for axis pairs (x,y), (x,z), (y,z)
+    double w_center, w_face;     // k^2 U weights: centre and face (order 4: 1/2, 1/12; order 2: 1, 0)
+    // order 6 (uniform h)
+    double c1;                   // 1/(30 h^2)
+    double h2;                   // h^2
+    int zchunk;                  // z-planes per block
+    int tiles_x, tiles_y, zchunks;
+};
+
+// Complex GEMM description: C[b] = A[b] * B[b], row-major, complex, strides in complex elements.
+struct GemmDesc {
+    int M, N, K;
+    long long lda, ldb, ldc;
+    long long sA, sB, sC;        // batch strides (0 = shared operand)
+    int batch;
+};
+
+struct PfftPlan;   // PFFT second path (device data)
+
+struct KrylovWork {
+    int m = 0;
+    int flexible = 0;
+    double2 *V = nullptr;        // (m+1) * n
+    double2 *Z = nullptr;        // m * n (flexible only)
+    double2 *tmp = nullptr;      // n
+    double2 *partials = nullptr; // nblocks * (m + 2)
+    double2 *red = nullptr;      // m + 2 reduced values
+    double2 *red_host = nullptr; // pinned host copy
+    int nblocks = 0;
+};
+
+struct Ctx {
+    int nx, ny, nz;
+    long long n;
+    double hx, hy, hz;
+    int order;
+    int bc_kind;
+    double k0;
+    cd gamma[3];
+    hipStream_t stream = nullptr;
+    int device = 0;
+    std::string err;
+
+    StencilParams sp{};
+    double *k2 = nullptr;        // interior k^2 (n)
+    double4 *fld = nullptr;      // order 6: (diag, g_x, g_y, g_z) per node
+
+    // EigT data (complex, row-major N x N). x: transposed for the B operand, y: as is for the A operand.
+    double2 *BxF = nullptr, *BxI = nullptr, *AyF = nullptr, *AyI = nullptr;
+    float2 *BxF32 = nullptr, *BxI32 = nullptr, *AyF32 = nullptr, *AyI32 = nullptr;
+    double2 *dxe = nullptr, *dye = nullptr;    // eigenvalues d_x,i and d_y,j
+    double ax, ay, c0;                          // alpha_x, alpha_y, h_z^2 k0^2 - 2(alpha_x + alpha_y + 1)
+
+    // preconditioner work buffers
+    double2 *t1 = nullptr, *t2 = nullptr, *cp = nullptr;
+    float2 *t1f = nullptr, *t2f = nullptr, *cpf = nullptr;
+
+    PfftPlan *pfft = nullptr;
+    KrylovWork kw;
+    std::vector<void *> allocs;  // everything to free
+};
+
+// ----- kernel launchers (defined in the .hip files); all enqueue on `s` and return hipError_t -----
+hipError_t launch_derived_fields(const double *k2_halo, int halo, double *k2, double4 *fld, const StencilParams &p,
+                                 double h, hipStream_t s);
+hipError_t launch_matvec(const StencilParams &p, const double2 *x, const double *k2, const double4 *fld,
+                         const double2 *F, double2 *y, hipStream_t s);   // F != nullptr: y = F - A x
+hipError_t launch_rhs(const StencilParams &p, const double2 *f_halo, const double *k2, const double4 *fld,
+                      double h3[3], double2 *F, hipStream_t s);
+
+hipError_t launch_gemm_z64(const GemmDesc &d, const double2 *A, const double2 *B, double2 *C, hipStream_t s);
+hipError_t launch_gemm_z32(const GemmDesc &d, const float2 *A, const float2 *B, float2 *C, hipStream_t s);
+hipError_t launch_gemm_z32_in64(const GemmDesc &d, const double2 *A, const float2 *B, float2 *C, hipStream_t s);
+hipError_t launch_gemm_z32_out64(const GemmDesc &d, const float2 *A, const float2 *B, double2 *C, hipStream_t s);
+
+hipError_t launch_tridiag_z64(double2 *r, double2 *cp, const double2 *dx, const double2 *dy, int nx, int ny, int nz,
+                              double ax, double ay, double c0, double2 gz, double scale, hipStream_t s);
+hipError_t launch_tridiag_z32(float2 *r, float2 *cp, const double2 *dx, const double2 *dy, int nx, int ny, int nz,
+                              double ax, double ay, double c0, double2 gz, double scale, hipStream_t s);
+
+// Krylov helpers
+int dots_blocks(long long n);
+hipError_t launch_dots(const double2 *V, long long ldv, int nv, const double2 *w, long long n, double2 *partials,
+                       int nblocks, double2 *red, hipStream_t s);   // red[0..nv-1] = V_i^H w, red[nv] = (|w|^2, 0)
+hipError_t launch_lincomb(double2 *out, const double2 *base, double2 alpha, const double2 *V, long long ldv, int nv,
+                          const double2 *coef, long long n, hipStream_t s);   // out = alpha base + sum coef_i V_i
+hipError_t launch_fill_zero(double2 *x, long long n, hipStream_t s);
+
+}  // namespace helm

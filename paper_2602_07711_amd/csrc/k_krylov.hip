@@ -1,0 +1,148 @@
+// Krylov kernels of the (F)GMRES outer iteration: the block inner products V^H w together with ||w||^2 in
+// one pass over the data (classical Gram-Schmidt with the norm taken from ||w||^2 - sum |h_i|^2), a fixed-
+// order two-stage reduction (bitwise reproducible, no atomics), and the linear combination
+// out = alpha * base + sum_i c_i V_i used for the orthogonalisation update, the end-of-cycle update
+// x += Z y and the restart vector.
+#include "helm_internal.h"
+
+namespace helm {
+
+namespace {
+
+constexpr int DOT_EPT = 8;                 // elements per thread
+constexpr int DOT_CHUNK = 256 * DOT_EPT;   // elements per block
+constexpr int MAXV = 260;                  // up to m + 2 outputs
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__global__ __launch_bounds__(256) void k_dots(const double2 *__restrict__ V, long long ldv, int nv,
+                                              const double2 *__restrict__ w, long long n, double2 *__restrict__ part) {
+    __shared__ double2 red[4][MAXV];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const long long base = (long long)blockIdx.x * DOT_CHUNK + tid;
+    double2 wr[DOT_EPT];
+    double ww = 0.0;
+#pragma unroll
+    for (int e = 0; e < DOT_EPT; ++e) {
+        long long idx = base + (long long)e * 256;
+        wr[e] = idx < n ? w[idx] : make_double2(0.0, 0.0);
+        ww += wr[e].x * wr[e].x + wr[e].y * wr[e].y;
+    }
+    for (int i = 0; i < nv; ++i) {
+        const double2 *vi = V + (long long)i * ldv;
+        double re = 0.0, im = 0.0;
+#pragma unroll
+        for (int e = 0; e < DOT_EPT; ++e) {
+            long long idx = base + (long long)e * 256;
+            double2 v = idx < n ? vi[idx] : make_double2(0.0, 0.0);
+            re += v.x * wr[e].x + v.y * wr[e].y;   // conj(v) * w
+            im += v.x * wr[e].y - v.y * wr[e].x;
+        }
+        re = wave_sum(re);
+        im = wave_sum(im);
+        if (lane == 0) red[wave][i] = make_double2(re, im);
+    }
+    ww = wave_sum(ww);
+    if (lane == 0) red[wave][nv] = make_double2(ww, 0.0);
+    __syncthreads();
+    for (int t = tid; t <= nv; t += 256) {
+        double2 s = red[0][t];
+        for (int q = 1; q < 4; ++q) { s.x += red[q][t].x; s.y += red[q][t].y; }
+        part[(long long)blockIdx.x * (nv + 1) + t] = s;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_reduce(const double2 *__restrict__ part, int nblocks, int nout,
+                                                double2 *__restrict__ out) {
+    __shared__ double sr[256], si[256];
+    const int t = blockIdx.x, tid = threadIdx.x;
+    double re = 0.0, im = 0.0;
+    for (int b = tid; b < nblocks; b += 256) {
+        double2 v = part[(long long)b * nout + t];
+        re += v.x;
+        im += v.y;
+    }
+    sr[tid] = re;
+    si[tid] = im;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s) { sr[tid] += sr[tid + s]; si[tid] += si[tid + s]; }
+        __syncthreads();
+    }
+    if (tid == 0) out[t] = make_double2(sr[0], si[0]);
+}
+
+constexpr int LC_MAX = 48;
+struct LcCoef { double2 c[LC_MAX]; };
+
+__global__ __launch_bounds__(256) void k_lincomb(double2 *out, const double2 *base, double2 alpha,
+                                                 const double2 *__restrict__ V, long long ldv, int nv, LcCoef co,
+                                                 long long n) {
+    const long long stride = (long long)gridDim.x * 256;
+    for (long long idx = (long long)blockIdx.x * 256 + threadIdx.x; idx < n; idx += stride) {
+        double2 acc = make_double2(0.0, 0.0);
+        if (base) {
+            double2 b = base[idx];
+            acc.x = alpha.x * b.x - alpha.y * b.y;
+            acc.y = alpha.x * b.y + alpha.y * b.x;
+        }
+        for (int i = 0; i < nv; ++i) {
+            double2 v = V[(long long)i * ldv + idx];
+            double2 c = co.c[i];
+            acc.x += c.x * v.x - c.y * v.y;
+            acc.y += c.x * v.y + c.y * v.x;
+        }
+        out[idx] = acc;
+    }
+}
+
+__global__ void k_zero(double2 *x, long long n) {
+    long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (idx < n) x[idx] = make_double2(0.0, 0.0);
+}
+
+}  // namespace
+
+int dots_blocks(long long n) { return (int)((n + DOT_CHUNK - 1) / DOT_CHUNK); }
+
+hipError_t launch_dots(const double2 *V, long long ldv, int nv, const double2 *w, long long n, double2 *partials,
+                       int nblocks, double2 *red, hipStream_t s) {
+    if (nv + 1 > MAXV) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_dots, dim3(nblocks), dim3(256), 0, s, V, ldv, nv, w, n, partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_reduce, dim3(nv + 1), dim3(256), 0, s, partials, nblocks, nv + 1, red);
+    return hipGetLastError();
+}
+
+hipError_t launch_lincomb(double2 *out, const double2 *base, double2 alpha, const double2 *V, long long ldv, int nv,
+                          const double2 *coef, long long n, hipStream_t s) {
+    long long want = (n + 255) / 256;
+    int grid = (int)(want < 8192 ? want : 8192);
+    if (grid < 1) grid = 1;
+    int done = 0;
+    do {
+        int cnt = nv - done < LC_MAX ? nv - done : LC_MAX;
+        LcCoef co;
+        for (int i = 0; i < cnt; ++i) co.c[i] = coef[done + i];
+        const double2 *b = done == 0 ? base : out;
+        double2 a = done == 0 ? alpha : make_double2(1.0, 0.0);
+        hipLaunchKernelGGL(k_lincomb, dim3(grid), dim3(256), 0, s, out, b, a, V + (long long)done * ldv, ldv, cnt, co,
+                           n);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        done += cnt;
+    } while (done < nv);
+    return hipSuccess;
+}
+
+hipError_t launch_fill_zero(double2 *x, long long n, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, n);
+    return hipGetLastError();
+}
+
+}  // namespace helm

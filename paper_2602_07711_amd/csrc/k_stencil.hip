@@ -1,0 +1,321 @@
+// Compact-stencil kernels: derived k^2 fields, the modified right-hand side, and the matrix-vector product
+// y = A x of the 2nd/4th/6th-order schemes with the ghost-eliminated absorbing closure.
+//
+// Operator (per node p, neighbour offsets o in {-1,0,1}^3, U_o the neighbour value, k_o^2 its k^2):
+//   order 4 (Sec. 2.2 eq. scheme4):  sum_o c_o U_o + k_p^2 U_p / 2 + sum_faces k_o^2 U_o / 12, with the
+//     grid-only coefficients c_o of Delta + sum (h_nu^2+h_mu^2)/12 T_nu T_mu (19 points).
+//   order 6 (Sec. 2.3 eq. scheme6, uniform h): collecting the scheme by neighbour class,
+//     y = dg U_p + (S3 + 3 S2 + 14 S1)/(30 h^2) + (SW2 - SW1)/90 + sum_nu g_nu (2 D_nu U + D_nu E + h^2 D_nu W)
+//     with S1/S2/S3 the sums of U over faces/edges/corners, SW1/SW2 the sums of k^2 U over faces/edges,
+//     D_nu U = U(+nu) - U(-nu), D_nu W the same for k^2 U, D_nu E the difference of the edge sums on the
+//     +nu and -nu sides, g_nu = h (k^2)_nu / 120 and dg = -64/(15 h^2) + 14/15 k^2 + h^2/20 (lap k^2 - k^4).
+// Ghost rule (Sec. 2.3 eq. D_bc): a neighbour outside the grid along an axis takes the boundary node's value
+// times gamma of that axis (per clamped axis), and k^2 there is the boundary node's k^2, so the products
+// k^2 U obey the same rule.
+//
+// The matvec stages a (64+2) x (8+2) tile of U and k^2 per z-plane in LDS, keeps three planes in a ring and
+// marches along z; each thread produces two nodes per plane. Per node it streams x (16 B), k^2 (8 B), the
+// order-6 field block (32 B) and writes y (16 B).
+#include "helm_internal.h"
+
+namespace helm {
+
+namespace {
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+__device__ __forceinline__ double2 cfma(double s, double2 a, double2 acc) {
+    return make_double2(fma(s, a.x, acc.x), fma(s, a.y, acc.y));
+}
+
+// --------------------------------------------------------------------------- derived fields
+// k2 (interior copy) and, for order 6, fld = (dg, g_x, g_y, g_z). k2_halo has `halo` cells per side.
+__global__ void k_derived(const double *__restrict__ k2h, int halo, double *__restrict__ k2, double4 *__restrict__ fld,
+                          int nx, int ny, int nz, int order, double h, int *__restrict__ bad) {
+    long long n = (long long)nx * ny * nz;
+    long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    int i = (int)(p % nx);
+    int j = (int)((p / nx) % ny);
+    int l = (int)(p / ((long long)nx * ny));
+    const int px = nx + 2 * halo, py = ny + 2 * halo;
+    auto at = [&](int di, int dj, int dl) -> double {
+        return k2h[((long long)(l + halo + dl) * py + (j + halo + dj)) * px + (i + halo + di)];
+    };
+    double c = at(0, 0, 0);
+    if (!isfinite(c)) atomicOr(bad, 1);
+    k2[p] = c;
+    if (order != 6) return;
+    double g[3], lap = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        int dx = (a == 0), dy = (a == 1), dz = (a == 2);
+        double p1 = at(dx, dy, dz), m1 = at(-dx, -dy, -dz), p2 = at(2 * dx, 2 * dy, 2 * dz), m2 = at(-2 * dx, -2 * dy, -2 * dz);
+        if (!isfinite(p1) || !isfinite(m1) || !isfinite(p2) || !isfinite(m2)) atomicOr(bad, 1);
+        g[a] = (-p2 + 8.0 * p1 - 8.0 * m1 + m2) / (12.0 * h);
+        lap += (-p2 + 16.0 * p1 - 30.0 * c + 16.0 * m1 - m2) / (12.0 * h * h);
+    }
+    double h2 = h * h;
+    double dg = -64.0 / (15.0 * h2) + 14.0 / 15.0 * c + h2 / 20.0 * (lap - c * c);
+    fld[p] = make_double4(dg, h * g[0] / 120.0, h * g[1] / 120.0, h * g[2] / 120.0);
+}
+
+// --------------------------------------------------------------------------- right-hand side
+__global__ void k_rhs(const double2 *__restrict__ f, const double *__restrict__ k2, const double4 *__restrict__ fld,
+                      double2 *__restrict__ F, int nx, int ny, int nz, int order, double hx, double hy, double hz) {
+    long long n = (long long)nx * ny * nz;
+    long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    int i = (int)(p % nx);
+    int j = (int)((p / nx) % ny);
+    int l = (int)(p / ((long long)nx * ny));
+    const int px = nx + 4, py = ny + 4;
+    auto at = [&](int di, int dj, int dl) -> double2 {
+        return f[((long long)(l + 2 + dl) * py + (j + 2 + dj)) * px + (i + 2 + di)];
+    };
+    double2 c = at(0, 0, 0);
+    if (order == 2) { F[p] = c; return; }
+    double hs[3] = {hx, hy, hz};
+    double2 d2[3];
+    for (int a = 0; a < 3; ++a) {
+        int dx = (a == 0), dy = (a == 1), dz = (a == 2);
+        double2 s = cadd(at(dx, dy, dz), at(-dx, -dy, -dz));
+        d2[a] = cscale(csub(s, cscale(c, 2.0)), 1.0 / (hs[a] * hs[a]));
+    }
+    if (order == 4) {
+        double2 out = c;
+        for (int a = 0; a < 3; ++a) out = cfma(hs[a] * hs[a] / 12.0, d2[a], out);
+        F[p] = out;
+        return;
+    }
+    // order 6, uniform h: f + h^2/12 Lap_h f - h^4/240 sum delta^4 f + h^4/90 P_h f - h^2/20 k^2 f
+    //                    + h^4/60 sum (k^2)_nu delta_nu f      (the last uses (k^2)_nu = 120 g_nu / h)
+    double h = hx, h2 = h * h;
+    double2 out = c;
+    out = cfma(h2 / 12.0, cadd(cadd(d2[0], d2[1]), d2[2]), out);
+    double4 fl = fld[p];
+    double gg[3] = {fl.y, fl.z, fl.w};
+    for (int a = 0; a < 3; ++a) {
+        int dx = (a == 0), dy = (a == 1), dz = (a == 2);
+        double2 p1 = at(dx, dy, dz), m1 = at(-dx, -dy, -dz);
+        double2 p2 = at(2 * dx, 2 * dy, 2 * dz), m2 = at(-2 * dx, -2 * dy, -2 * dz);
+        double2 d4 = cadd(cadd(cadd(p2, m2), cscale(cadd(p1, m1), -4.0)), cscale(c, 6.0));
+        out = cfma(-1.0 / 240.0, d4, out);                       // h^4/240 * delta^4 f (delta^4 carries 1/h^4)
+        double2 d1 = csub(p1, m1);                               // 2 h delta f
+        out = cfma(h2 * gg[a], d1, out);                         // h^4/60 * (120 g/h) * d1/(2h) = h^2 g d1
+    }
+    const int pairs[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+    for (int q = 0; q < 3; ++q) {
+        double2 acc = make_double2(0.0, 0.0);
+        for (int sa = -1; sa <= 1; ++sa)
+            for (int sb = -1; sb <= 1; ++sb) {
+                int d[3] = {0, 0, 0};
+                d[pairs[q][0]] += sa;
+                d[pairs[q][1]] += sb;
+                double w = (sa == 0 ? -2.0 : 1.0) * (sb == 0 ? -2.0 : 1.0);
+                acc = cfma(w, at(d[0], d[1], d[2]), acc);
+            }
+        out = cfma(1.0 / 90.0, acc, out);                        // h^4/90 * P_h f (P_h carries 1/h^4)
+    }
+    out = cfma(-h2 / 20.0 * k2[p], c, out);
+    F[p] = out;
+}
+
+// --------------------------------------------------------------------------- matvec
+constexpr int TX = 64;       // tile width along x (one wavefront row)
+constexpr int TY = 8;        // tile height along y (each of the 4 thread rows computes 2 rows)
+constexpr int LX = TX + 2;
+constexpr int LY = TY + 2;
+
+template <int ORDER, bool RESID>
+__global__ __launch_bounds__(256) void k_matvec(const double2 *__restrict__ x, const double *__restrict__ k2,
+                                                const double4 *__restrict__ fld, const double2 *__restrict__ F,
+                                                double2 *__restrict__ y, StencilParams p) {
+    __shared__ double2 su[3][LY][LX];
+    __shared__ double sk[3][LY][LX];
+
+    const int T = p.tiles_x * p.tiles_y * p.zchunks;
+    const int per = (T + 7) / 8;
+    const int tile = (blockIdx.x % 8) * per + blockIdx.x / 8;   // consecutive tiles share an XCD (and its L2)
+    if (tile >= T) return;
+    const int tx_t = tile % p.tiles_x;
+    const int ty_t = (tile / p.tiles_x) % p.tiles_y;
+    const int tz_t = tile / (p.tiles_x * p.tiles_y);
+    const int x0 = tx_t * TX, y0 = ty_t * TY;
+    const int z0 = tz_t * p.zchunk;
+    const int z1 = min(z0 + p.zchunk, p.nz);
+    const int nx = p.nx, ny = p.ny, nz = p.nz;
+    const long long plane = (long long)nx * ny;
+    const int tid = threadIdx.y * 64 + threadIdx.x;
+
+    auto load_plane = [&](int slot, int z) {
+        double2 fz = make_double2(1.0, 0.0);
+        int cz = z;
+        if (z < 0) { cz = 0; fz = p.gz; }
+        else if (z >= nz) { cz = nz - 1; fz = p.gz; }
+        for (int e = tid; e < LX * LY; e += 256) {
+            int lx = e % LX, ly = e / LX;
+            int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
+            double2 fac = fz;
+            int cx = gx, cy = gy;
+            if (gx < 0) { cx = 0; fac = cmul(fac, p.gx); }
+            else if (gx >= nx) { cx = nx - 1; fac = cmul(fac, p.gx); }
+            if (gy < 0) { cy = 0; fac = cmul(fac, p.gy); }
+            else if (gy >= ny) { cy = ny - 1; fac = cmul(fac, p.gy); }
+            long long idx = (long long)cz * plane + (long long)cy * nx + cx;
+            su[slot][ly][lx] = cmul(fac, x[idx]);
+            sk[slot][ly][lx] = k2[idx];
+        }
+    };
+
+    load_plane(0, z0 - 1);
+    load_plane(1, z0);
+    const int lx = threadIdx.x + 1;
+    for (int z = z0; z < z1; ++z) {
+        const int t = z - z0;
+        load_plane((t + 2) % 3, z + 1);
+        __syncthreads();
+        const int sl[3] = {t % 3, (t + 1) % 3, (t + 2) % 3};   // planes z-1, z, z+1
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const int ly = threadIdx.y + 4 * r + 1;
+            const int gxo = x0 + threadIdx.x, gyo = y0 + ly - 1;
+            double2 u0 = su[sl[1]][ly][lx];
+            double k0 = sk[sl[1]][ly][lx];
+            double2 acc;
+            if (ORDER == 6) {
+                double2 S1 = make_double2(0, 0), S2 = S1, S3 = S1, SW1 = S1, SW2 = S1;
+                double2 DU[3] = {S1, S1, S1}, DE[3] = {S1, S1, S1}, DW[3] = {S1, S1, S1};
+#pragma unroll
+                for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+                    for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+                        for (int dx = -1; dx <= 1; ++dx) {
+                            const int nn = (dx != 0) + (dy != 0) + (dz != 0);
+                            if (nn == 0) continue;
+                            double2 u = su[sl[dz + 1]][ly + dy][lx + dx];
+                            if (nn == 3) { S3 = cadd(S3, u); continue; }
+                            double kk = sk[sl[dz + 1]][ly + dy][lx + dx];
+                            double2 w = cscale(u, kk);
+                            if (nn == 1) {
+                                S1 = cadd(S1, u);
+                                SW1 = cadd(SW1, w);
+                                const int a = dx ? 0 : (dy ? 1 : 2);
+                                const int s = dx + dy + dz;
+                                DU[a] = cfma((double)s, u, DU[a]);
+                                DW[a] = cfma((double)s, w, DW[a]);
+                            } else {
+                                S2 = cadd(S2, u);
+                                SW2 = cadd(SW2, w);
+                                if (dx) DE[0] = cfma((double)dx, u, DE[0]);
+                                if (dy) DE[1] = cfma((double)dy, u, DE[1]);
+                                if (dz) DE[2] = cfma((double)dz, u, DE[2]);
+                            }
+                        }
+                if (gxo < nx && gyo < ny) {
+                    long long pidx = (long long)z * plane + (long long)gyo * nx + gxo;
+                    double4 fl = fld[pidx];
+                    acc = cscale(u0, fl.x);
+                    double2 lapc = cadd(cadd(S3, cscale(S2, 3.0)), cscale(S1, 14.0));
+                    acc = cfma(p.c1, lapc, acc);
+                    acc = cfma(1.0 / 90.0, csub(SW2, SW1), acc);
+                    const double gg[3] = {fl.y, fl.z, fl.w};
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        double2 tnu = cadd(cadd(cscale(DU[a], 2.0), DE[a]), cscale(DW[a], p.h2));
+                        acc = cfma(gg[a], tnu, acc);
+                    }
+                    if (RESID) acc = csub(F[pidx], acc);
+                    y[pidx] = acc;
+                }
+            } else {
+                acc = cscale(u0, p.c_center + p.w_center * k0);
+                double2 fx = cadd(su[sl[1]][ly][lx - 1], su[sl[1]][ly][lx + 1]);
+                double2 fy = cadd(su[sl[1]][ly - 1][lx], su[sl[1]][ly + 1][lx]);
+                double2 fz = cadd(su[sl[0]][ly][lx], su[sl[2]][ly][lx]);
+                acc = cfma(p.c_face[0], fx, acc);
+                acc = cfma(p.c_face[1], fy, acc);
+                acc = cfma(p.c_face[2], fz, acc);
+                if (ORDER == 4) {
+                    double2 wf = cadd(cadd(cscale(su[sl[1]][ly][lx - 1], sk[sl[1]][ly][lx - 1]),
+                                           cscale(su[sl[1]][ly][lx + 1], sk[sl[1]][ly][lx + 1])),
+                                      cadd(cscale(su[sl[1]][ly - 1][lx], sk[sl[1]][ly - 1][lx]),
+                                           cscale(su[sl[1]][ly + 1][lx], sk[sl[1]][ly + 1][lx])));
+                    wf = cadd(wf, cadd(cscale(su[sl[0]][ly][lx], sk[sl[0]][ly][lx]),
+                                       cscale(su[sl[2]][ly][lx], sk[sl[2]][ly][lx])));
+                    acc = cfma(p.w_face, wf, acc);
+                    double2 exy = cadd(cadd(su[sl[1]][ly - 1][lx - 1], su[sl[1]][ly - 1][lx + 1]),
+                                       cadd(su[sl[1]][ly + 1][lx - 1], su[sl[1]][ly + 1][lx + 1]));
+                    double2 exz = cadd(cadd(su[sl[0]][ly][lx - 1], su[sl[0]][ly][lx + 1]),
+                                       cadd(su[sl[2]][ly][lx - 1], su[sl[2]][ly][lx + 1]));
+                    double2 eyz = cadd(cadd(su[sl[0]][ly - 1][lx], su[sl[0]][ly + 1][lx]),
+                                       cadd(su[sl[2]][ly - 1][lx], su[sl[2]][ly + 1][lx]));
+                    acc = cfma(p.c_edge[0], exy, acc);
+                    acc = cfma(p.c_edge[1], exz, acc);
+                    acc = cfma(p.c_edge[2], eyz, acc);
+                }
+                if (gxo < nx && gyo < ny) {
+                    long long pidx = (long long)z * plane + (long long)gyo * nx + gxo;
+                    if (RESID) acc = csub(F[pidx], acc);
+                    y[pidx] = acc;
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+hipError_t launch_derived_fields(const double *k2_halo, int halo, double *k2, double4 *fld, const StencilParams &p,
+                                 double h, hipStream_t s) {
+    long long n = (long long)p.nx * p.ny * p.nz;
+    int *bad = nullptr;
+    hipError_t e = hipMalloc(&bad, sizeof(int));
+    if (e != hipSuccess) return e;
+    e = hipMemsetAsync(bad, 0, sizeof(int), s);
+    if (e != hipSuccess) { hipFree(bad); return e; }
+    int blocks = (int)((n + 255) / 256);
+    hipLaunchKernelGGL(k_derived, dim3(blocks), dim3(256), 0, s, k2_halo, halo, k2, fld, p.nx, p.ny, p.nz, p.order, h,
+                       bad);
+    e = hipGetLastError();
+    int hbad = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    hipFree(bad);
+    if (e != hipSuccess) return e;
+    return hbad ? hipErrorInvalidValue : hipSuccess;
+}
+
+hipError_t launch_matvec(const StencilParams &p, const double2 *x, const double *k2, const double4 *fld,
+                         const double2 *F, double2 *y, hipStream_t s) {
+    int T = p.tiles_x * p.tiles_y * p.zchunks;
+    int grid = 8 * ((T + 7) / 8);
+    dim3 blk(64, 4);
+    if (p.order == 6) {
+        if (F) hipLaunchKernelGGL((k_matvec<6, true>), dim3(grid), blk, 0, s, x, k2, fld, F, y, p);
+        else hipLaunchKernelGGL((k_matvec<6, false>), dim3(grid), blk, 0, s, x, k2, fld, F, y, p);
+    } else if (p.order == 4) {
+        if (F) hipLaunchKernelGGL((k_matvec<4, true>), dim3(grid), blk, 0, s, x, k2, fld, F, y, p);
+        else hipLaunchKernelGGL((k_matvec<4, false>), dim3(grid), blk, 0, s, x, k2, fld, F, y, p);
+    } else {
+        if (F) hipLaunchKernelGGL((k_matvec<2, true>), dim3(grid), blk, 0, s, x, k2, fld, F, y, p);
+        else hipLaunchKernelGGL((k_matvec<2, false>), dim3(grid), blk, 0, s, x, k2, fld, F, y, p);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_rhs(const StencilParams &p, const double2 *f_halo, const double *k2, const double4 *fld,
+                      double h3[3], double2 *F, hipStream_t s) {
+    long long n = (long long)p.nx * p.ny * p.nz;
+    int blocks = (int)((n + 255) / 256);
+    hipLaunchKernelGGL(k_rhs, dim3(blocks), dim3(256), 0, s, f_halo, k2, fld, F, p.nx, p.ny, p.nz, p.order, h3[0],
+                       h3[1], h3[2]);
+    return hipGetLastError();
+}
+
+}  // namespace helm

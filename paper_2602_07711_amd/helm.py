@@ -1,0 +1,226 @@
+"""ctypes binding of libhelm (include/helm.h). Argument marshalling only: every step runs in the HIP library.
+
+Tensors are torch tensors on the GPU (complex128 vectors of n = Nx*Ny*Nz entries, x fastest; float64 k^2 and
+complex128 f on the interior plus a two-cell halo). The binding checks device, dtype, contiguity and size,
+then passes raw device pointers and torch's current HIP stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, byref, c_double, c_int, c_longlong, c_void_p
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhelm.so")
+
+HELM_OK, HELM_EINVAL, HELM_ENOMEM, HELM_EDEVICE, HELM_ENOCONV, HELM_EBREAKDOWN, HELM_ENUMERIC, HELM_EUNSUPPORTED = range(8)
+STATUS_NAMES = ["HELM_OK", "HELM_EINVAL", "HELM_ENOMEM", "HELM_EDEVICE", "HELM_ENOCONV", "HELM_EBREAKDOWN",
+                "HELM_ENUMERIC", "HELM_EUNSUPPORTED"]
+BC_ABC2, BC_DIRICHLET = 0, 1
+PREC_EIGT, PREC_PFFT, PREC_NONE = 0, 1, 2
+_PREC = {"eigt": PREC_EIGT, "pfft": PREC_PFFT, "none": PREC_NONE}
+_BC = {"abc": BC_ABC2, "dirichlet": BC_DIRICHLET}
+
+
+class HelmError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        self.status = status
+        super().__init__(f"{STATUS_NAMES[status] if 0 <= status < len(STATUS_NAMES) else status}: {msg}")
+
+
+class helm_grid(ctypes.Structure):
+    _fields_ = [("nx", c_int), ("ny", c_int), ("nz", c_int)]
+
+
+class helm_bc(ctypes.Structure):
+    _fields_ = [("kind", c_int), ("k0", c_double)]
+
+
+class helm_solve_opts(ctypes.Structure):
+    _fields_ = [("m", c_int), ("maxit", c_int), ("rtol", c_double), ("flexible", c_int), ("prec_fp32", c_int),
+                ("prec", c_int), ("x0_given", c_int), ("resid_hist", POINTER(c_double)), ("hist_len", c_int)]
+
+
+class helm_solve_info(ctypes.Structure):
+    _fields_ = [("iters", c_int), ("restarts", c_int), ("converged", c_int), ("hist_used", c_int),
+                ("relres_est", c_double), ("relres_true", c_double), ("t_ms", c_double * 6)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libhelm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2602_07711_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    L.helm_setup.argtypes = [POINTER(c_void_p), helm_grid, POINTER(c_double), c_void_p, c_int, c_int, helm_bc, c_void_p]
+    L.helm_setup.restype = c_int
+    L.helm_rhs.argtypes = [c_void_p, c_void_p, c_void_p]
+    L.helm_rhs.restype = c_int
+    L.helm_matvec.argtypes = [c_void_p, c_void_p, c_void_p]
+    L.helm_matvec.restype = c_int
+    L.helm_precond_apply.argtypes = [c_void_p, c_void_p, c_void_p, c_int, c_int]
+    L.helm_precond_apply.restype = c_int
+    L.helm_gmres_solve.argtypes = [c_void_p, c_void_p, c_void_p, POINTER(helm_solve_opts), POINTER(helm_solve_info)]
+    L.helm_gmres_solve.restype = c_int
+    L.helm_size.argtypes = [c_void_p]
+    L.helm_size.restype = c_longlong
+    L.helm_last_error.argtypes = [c_void_p]
+    L.helm_last_error.restype = ctypes.c_char_p
+    L.helm_last_setup_error.argtypes = []
+    L.helm_last_setup_error.restype = ctypes.c_char_p
+    L.helm_destroy.argtypes = [c_void_p]
+    L.helm_destroy.restype = None
+    L.helm_eig1d.argtypes = [c_int, c_double, c_double, c_void_p, c_void_p, c_void_p]
+    L.helm_eig1d.restype = c_int
+    _lib = L
+    return L
+
+
+def _stream_ptr():
+    return c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _check(t: torch.Tensor, dtype, numel: int, name: str):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
+
+
+class Context:
+    """Owns a helm_ctx*. Created by helm_setup, freed by helm_destroy (or when garbage-collected)."""
+
+    def __init__(self, ptr: c_void_p, shape, h, order, bc, k0, device):
+        self.ptr = ptr
+        self.shape = tuple(shape)     # (nz, ny, nx)
+        self.n = shape[0] * shape[1] * shape[2]
+        self.h = tuple(h)
+        self.order = order
+        self.bc = bc
+        self.k0 = k0
+        self.device = device
+
+    def error(self) -> str:
+        return lib().helm_last_error(self.ptr).decode()
+
+    def check(self, status: int):
+        if status != HELM_OK:
+            raise HelmError(status, self.error())
+
+    def __del__(self):
+        try:
+            if self.ptr:
+                lib().helm_destroy(self.ptr)
+                self.ptr = None
+        except Exception:
+            pass
+
+
+def helm_setup(k2: torch.Tensor, h, order: int, bc: str = "abc", k0: float = 0.0, shape=None) -> Context:
+    """Create a context from k^2 (float64 on the GPU). k2 has shape (Nz+4, Ny+4, Nx+4) (two-cell halo) or,
+    for order 2/4 only, (Nz, Ny, Nx); `shape` = (Nz, Ny, Nx) can be given to disambiguate."""
+    if not isinstance(k2, torch.Tensor) or not k2.is_cuda or k2.dtype != torch.float64 or not k2.is_contiguous():
+        raise ValueError("k2 must be a contiguous float64 GPU tensor")
+    if k2.dim() != 3:
+        raise ValueError("k2 must be 3-D (z, y, x)")
+    if shape is None:
+        halo = 2 if order == 6 else 2
+        shape = tuple(s - 4 for s in k2.shape) if halo else tuple(k2.shape)
+    nz, ny, nx = shape
+    if tuple(k2.shape) == (nz + 4, ny + 4, nx + 4):
+        halo = 2
+    elif tuple(k2.shape) == (nz, ny, nx):
+        halo = 0
+    else:
+        raise ValueError(f"k2 shape {tuple(k2.shape)} does not match grid {shape} with halo 0 or 2")
+    hh = (c_double * 3)(*(float(v) for v in (h if hasattr(h, "__len__") else (h, h, h))))
+    ptr = c_void_p()
+    st = lib().helm_setup(byref(ptr), helm_grid(nx, ny, nz), hh, c_void_p(k2.data_ptr()), halo, int(order),
+                          helm_bc(_BC[bc], float(k0)), _stream_ptr())
+    if st != HELM_OK:
+        raise HelmError(st, lib().helm_last_setup_error().decode())
+    return Context(ptr, shape, tuple(hh), order, bc, k0, k2.device)
+
+
+def helm_rhs(ctx: Context, f: torch.Tensor, F: torch.Tensor | None = None) -> torch.Tensor:
+    nz, ny, nx = ctx.shape
+    _check(f, torch.complex128, (nz + 4) * (ny + 4) * (nx + 4), "f")
+    if F is None:
+        F = torch.empty(ctx.n, dtype=torch.complex128, device=f.device)
+    _check(F, torch.complex128, ctx.n, "F")
+    ctx.check(lib().helm_rhs(ctx.ptr, c_void_p(f.data_ptr()), c_void_p(F.data_ptr())))
+    return F
+
+
+def helm_matvec(ctx: Context, x: torch.Tensor, y: torch.Tensor | None = None) -> torch.Tensor:
+    _check(x, torch.complex128, ctx.n, "x")
+    if y is None:
+        y = torch.empty_like(x)
+    _check(y, torch.complex128, ctx.n, "y")
+    ctx.check(lib().helm_matvec(ctx.ptr, c_void_p(x.data_ptr()), c_void_p(y.data_ptr())))
+    return y
+
+
+def helm_precond_apply(ctx: Context, y: torch.Tensor, z: torch.Tensor | None = None, kind: str = "eigt",
+                       fp32: bool = False) -> torch.Tensor:
+    _check(y, torch.complex128, ctx.n, "y")
+    if z is None:
+        z = torch.empty_like(y)
+    _check(z, torch.complex128, ctx.n, "z")
+    ctx.check(lib().helm_precond_apply(ctx.ptr, c_void_p(y.data_ptr()), c_void_p(z.data_ptr()), _PREC[kind],
+                                       int(bool(fp32))))
+    return z
+
+
+def helm_gmres_solve(ctx: Context, F: torch.Tensor, x: torch.Tensor | None = None, m: int = 50, maxit: int = 1000,
+                     rtol: float = 1e-8, flexible: bool = False, prec: str = "eigt", prec_fp32: bool = False,
+                     hist_len: int = 4096, raise_on_noconv: bool = True):
+    """Solve A x = F. Returns (x, info) with info a dict (iters, restarts, converged, relres_est, relres_true,
+    t_ms = {matvec, precond, arnoldi, update, host, total}, hist)."""
+    _check(F, torch.complex128, ctx.n, "F")
+    x0_given = x is not None
+    if x is None:
+        x = torch.empty_like(F)
+    _check(x, torch.complex128, ctx.n, "x")
+    hist = (c_double * max(1, hist_len))()
+    opts = helm_solve_opts(int(m), int(maxit), float(rtol), int(bool(flexible)), int(bool(prec_fp32)), _PREC[prec],
+                           int(x0_given), ctypes.cast(hist, POINTER(c_double)), int(hist_len))
+    info = helm_solve_info()
+    st = lib().helm_gmres_solve(ctx.ptr, c_void_p(F.data_ptr()), c_void_p(x.data_ptr()), byref(opts), byref(info))
+    out = dict(iters=info.iters, restarts=info.restarts, converged=bool(info.converged), relres_est=info.relres_est,
+               relres_true=info.relres_true, status=STATUS_NAMES[st],
+               t_ms=dict(zip(("matvec", "precond", "arnoldi", "update", "host", "total"), list(info.t_ms))),
+               hist=[hist[i] for i in range(info.hist_used)])
+    if st != HELM_OK and not (st == HELM_ENOCONV and not raise_on_noconv):
+        raise HelmError(st, ctx.error())
+    return x, out
+
+
+def helm_destroy(ctx: Context):
+    if ctx.ptr:
+        lib().helm_destroy(ctx.ptr)
+        ctx.ptr = None
+
+
+def helm_eig1d(n: int, gamma: complex):
+    """Host 1D eigen-decomposition of Lambda-bar (no GPU). Returns numpy (d, V, Vinv)."""
+    import numpy as np
+    d = np.zeros(n, np.complex128)
+    V = np.zeros((n, n), np.complex128)
+    Vi = np.zeros((n, n), np.complex128)
+    st = lib().helm_eig1d(int(n), float(gamma.real), float(gamma.imag), c_void_p(d.ctypes.data),
+                          c_void_p(V.ctypes.data), c_void_p(Vi.ctypes.data))
+    if st != HELM_OK:
+        raise HelmError(st, "helm_eig1d failed")
+    return d, V, Vi

@@ -1,0 +1,255 @@
+"""GPU parity of the HIP path (through the C ABI) against the CPU oracle on the same seeded inputs.
+
+Tolerances:
+  * matvec / right-hand side (FP64): each output sums <= 27 products of O(1/h^2) coefficients with the
+    inputs, so rounding is a few tens of ulps of max|coef||x|; the bound 1e-12 relative to max|y_ref| leaves
+    about a 10x margin for N <= 256.
+  * EigT preconditioner (FP64): four dense transforms with condition number kappa(V) <= 18 each and one
+    pivot-stable Thomas solve; 1e-11 relative (measured ~1e-14).
+  * EigT preconditioner (FP32): the same chain in binary32 (eps = 6e-8) with kappa(V)^2 ~ 300 and sums of
+    N terms; bound 2e-4 relative.
+  * solutions: both sides solve to rtol 1e-10, so each is within kappa(A) * 1e-10 of the exact discrete
+    solution; parity bar relative L2 <= 1e-8 (the parity bar of the method's target).
+"""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+import synth
+from oracle import krylov as kr
+from oracle import operators as op
+from oracle import precond as pc
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def H():
+    import paper_2602_07711_amd as mod
+    mod.lib()   # fails loudly if the HIP library is missing
+    return mod
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def medium(shape, h3, k0, seed, amp=0.3):
+    """Smooth seeded medium on the halo grid of an arbitrary box: k0^2 (1 + amp * sum of 3 Gaussians)."""
+    rng = np.random.default_rng(seed)
+    nz, ny, nx = shape
+    cs = [(np.arange(n + 4) - 1) * h for n, h in zip((nx, ny, nz), h3)]
+    x, y, z = cs[0][None, None, :], cs[1][None, :, None], cs[2][:, None, None]
+    L = [c[-1] for c in cs]
+    bump = np.zeros((nz + 4, ny + 4, nx + 4))
+    for _ in range(3):
+        c = rng.uniform(0.2, 0.8, 3) * np.array(L)
+        bump += np.exp(-((x - c[0]) ** 2 + (y - c[1]) ** 2 + (z - c[2]) ** 2) / (2 * (0.15 * max(L)) ** 2))
+    return k0 * k0 * (1 + amp * bump)
+
+
+def cvec(n, seed):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal(n) + 1j * rng.standard_normal(n)
+
+
+SHAPES = [(9, 13, 70), (16, 16, 16)]
+
+
+def _h3(shape, order):
+    nz, ny, nx = shape
+    if order == 6:
+        h = 1.0 / (max(shape) + 1)
+        return (h, h, h)
+    return (1.0 / (nx + 1), 1.0 / (ny + 1), 1.0 / (nz + 1))
+
+
+@pytest.mark.parametrize("order", [2, 4, 6])
+@pytest.mark.parametrize("bc", ["abc", "dirichlet"])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_matvec_parity(order, bc, shape):
+    h = H()
+    h3 = _h3(shape, order)
+    k0 = 0.5 / h3[0]
+    k2 = medium(shape, h3, k0, seed=11)
+    ctx = h.helm_setup(dev(k2), h3, order, bc=bc, k0=k0, shape=shape)
+    n = int(np.prod(shape))
+    x = cvec(n, 3)
+    y = host(h.helm_matvec(ctx, dev(x)))
+    g = op.gamma_abc(k0, h3[0]) if bc == "abc" else 0.0
+    gs = tuple(op.gamma_abc(k0, hh) for hh in h3) if bc == "abc" else (0.0, 0.0, 0.0)
+    fields = op.derived_fields(k2, h3[0]) if order == 6 else None
+    A = op.A_kron(order, k2[2:-2, 2:-2, 2:-2], h3, gs, fields)
+    yr = A @ x
+    assert np.abs(y - yr).max() <= 1e-12 * np.abs(yr).max()
+    del g
+
+
+@pytest.mark.parametrize("order", [2, 4, 6])
+def test_rhs_parity(order):
+    h = H()
+    shape = (9, 13, 70)
+    h3 = _h3(shape, order)
+    k0 = 0.5 / h3[0]
+    k2 = medium(shape, h3, k0, seed=12)
+    rng = np.random.default_rng(5)
+    f = rng.standard_normal(k2.shape) + 1j * rng.standard_normal(k2.shape)
+    ctx = h.helm_setup(dev(k2), h3, order, k0=k0, shape=shape)
+    F = host(h.helm_rhs(ctx, dev(f)))
+    fields = op.derived_fields(k2, h3[0]) if order == 6 else None
+    Fr = op.rhs(order, f, h3, k2[2:-2, 2:-2, 2:-2], fields).ravel()
+    assert np.abs(F - Fr).max() <= 1e-12 * np.abs(Fr).max()
+
+
+@pytest.mark.parametrize("shape,bc", [((12, 20, 70), "abc"), ((33, 33, 33), "abc"), ((24, 24, 24), "dirichlet"),
+                                      ((5, 7, 3), "abc")])
+def test_precond_parity_fp64(shape, bc):
+    h = H()
+    h3 = (1.0 / (shape[2] + 1), 1.0 / (shape[1] + 1), 1.0 / (shape[0] + 1))
+    k0 = 0.47 / h3[0]
+    k2 = np.full(tuple(s + 4 for s in shape), k0 * k0)
+    ctx = h.helm_setup(dev(k2), h3, 4, bc=bc, k0=k0, shape=shape)
+    n = int(np.prod(shape))
+    y = cvec(n, 4)
+    z = host(h.helm_precond_apply(ctx, dev(y)))
+    gs = tuple(op.gamma_abc(k0, hh) for hh in h3) if bc == "abc" else (0.0, 0.0, 0.0)
+    zr = pc.EigT(shape, h3, k0, gs).solve(y)
+    assert np.linalg.norm(z - zr) <= 1e-11 * np.linalg.norm(zr)
+    M = pc.M_matrix(shape, h3, k0, gs)
+    assert np.linalg.norm(M @ z - y) <= 1e-11 * np.linalg.norm(y)
+    # in place (y and z the same buffer)
+    yd = dev(y)
+    h.helm_precond_apply(ctx, yd, yd)
+    assert np.linalg.norm(host(yd) - zr) <= 1e-11 * np.linalg.norm(zr)
+
+
+@pytest.mark.parametrize("shape", [(12, 20, 70), (33, 33, 33)])
+def test_precond_parity_fp32(shape):
+    h = H()
+    h3 = (1.0 / (shape[2] + 1), 1.0 / (shape[1] + 1), 1.0 / (shape[0] + 1))
+    k0 = 0.47 / h3[0]
+    k2 = np.full(tuple(s + 4 for s in shape), k0 * k0)
+    ctx = h.helm_setup(dev(k2), h3, 4, k0=k0, shape=shape)
+    y = cvec(int(np.prod(shape)), 6)
+    z = host(h.helm_precond_apply(ctx, dev(y), fp32=True))
+    gs = tuple(op.gamma_abc(k0, hh) for hh in h3)
+    zr = pc.EigT(shape, h3, k0, gs).solve(y)
+    err = np.linalg.norm(z - zr) / np.linalg.norm(zr)
+    print(f"fp32 precond rel err {err:.3e}")
+    assert err <= 2e-4
+
+
+def _problem(order, n, k0, seed=2):
+    hh = 1.0 / (n + 1)
+    k2 = synth.inclusions_k2(n, k0, seed=seed)
+    f = synth.gaussian_source(n)
+    return hh, k2, f
+
+
+@pytest.mark.parametrize("variant", ["gmres64", "fgmres64", "fgmres32", "restart5"])
+def test_solve_matches_sparse_lu(variant):
+    h = H()
+    n, order = 20, 6
+    k0 = 0.47 * (n + 1)
+    hh, k2, f = _problem(order, n, k0)
+    ctx = h.helm_setup(dev(k2), hh, order, k0=k0)
+    F = h.helm_rhs(ctx, dev(f))
+    kw = dict(gmres64=dict(m=50), fgmres64=dict(m=50, flexible=True), fgmres32=dict(m=50, flexible=True, prec_fp32=True),
+              restart5=dict(m=5))[variant]
+    x, info = h.helm_gmres_solve(ctx, F, rtol=1e-10, maxit=500, **kw)
+    A, Fr = op.problem(order, k2, f, hh, k0)
+    assert np.abs(host(F) - Fr).max() <= 1e-12 * np.abs(Fr).max()
+    xs = spla.splu(A.tocsc()).solve(Fr)
+    xg = host(x)
+    rel = np.linalg.norm(xg - xs) / np.linalg.norm(xs)
+    print(variant, info["iters"], info["relres_true"], rel)
+    assert info["converged"] and info["relres_true"] <= 1e-10
+    assert np.linalg.norm(Fr - A @ xg) <= 1.01e-10 * np.linalg.norm(Fr)
+    assert rel <= 1e-8
+
+
+def test_solve_gauss32_matches_oracle_gmres():
+    """32^3, 4th order, k = 20, Gaussian source, GMRES(30): GPU vs the oracle's own GMRES, both at rtol 1e-10."""
+    h = H()
+    w = synth.workload("gauss32")
+    ctx = h.helm_setup(dev(w["k2"]), w["h"], w["order"], k0=w["k0"])
+    F = h.helm_rhs(ctx, dev(w["f"]))
+    x, info = h.helm_gmres_solve(ctx, F, m=w["m"], rtol=1e-10)
+    A, Fr = op.problem(w["order"], w["k2"], w["f"], w["h"], w["k0"])
+    n = w["n"]
+    g = op.gamma_abc(w["k0"], w["h"])
+    e = pc.EigT((n, n, n), (w["h"],) * 3, w["k0"], (g, g, g))
+    xr, ir = kr.gmres(lambda v: A @ v, e.solve, Fr, m=w["m"], rtol=1e-10)
+    xg = host(x)
+    rel = np.linalg.norm(xg - xr) / np.linalg.norm(xr)
+    print("gauss32", info["iters"], ir["iters"], rel)
+    assert rel <= 1e-8
+    assert abs(info["iters"] - ir["iters"]) <= 1
+
+
+def test_solve_inclusions_64_matches_oracle_gmres():
+    """6th order, four Gaussian inclusions, k0 h = 0.47 at 64^3: GPU (FP64 GMRES and FP32-EigT FGMRES) vs the oracle."""
+    h = H()
+    n = 64
+    k0 = 0.47 * (n + 1)
+    hh, k2, f = _problem(6, n, k0)
+    ctx = h.helm_setup(dev(k2), hh, 6, k0=k0)
+    F = h.helm_rhs(ctx, dev(f))
+    A, Fr = op.problem(6, k2, f, hh, k0)
+    g = op.gamma_abc(k0, hh)
+    e = pc.EigT((n, n, n), (hh,) * 3, k0, (g, g, g))
+    xr, ir = kr.gmres(lambda v: A @ v, e.solve, Fr, m=50, rtol=1e-10)
+    for kw in (dict(), dict(flexible=True, prec_fp32=True)):
+        x, info = h.helm_gmres_solve(ctx, F, m=50, rtol=1e-10, **kw)
+        rel = np.linalg.norm(host(x) - xr) / np.linalg.norm(xr)
+        print("incl64", kw, info["iters"], ir["iters"], rel)
+        assert rel <= 1e-8
+
+
+def _sample_nodes(shape, seed, count=3000):
+    nz, ny, nx = shape
+    rng = np.random.default_rng(seed)
+    pts = [rng.integers(0, nx * ny * nz, count)]
+    # every boundary face, edge and corner class
+    for l in (0, nz // 2, nz - 1):
+        for j in (0, ny // 2, ny - 1):
+            for i in (0, 1, nx // 2, nx - 2, nx - 1):
+                pts.append(np.array([i + nx * (j + ny * l)]))
+    return np.unique(np.concatenate(pts))
+
+
+@pytest.mark.parametrize("name", ["inclusions", "noise"])
+def test_fullsize_sampled(name):
+    """At the full sizes (128^3 and 256^3): matvec rows and preconditioner rows checked node by node with the
+    oracle's row-sampled operators, and the solve's residual checked on sampled rows."""
+    h = H()
+    w = synth.workload(name)
+    n = w["n"]
+    shape = (n, n, n)
+    hh, k0 = w["h"], w["k0"]
+    g = op.gamma_abc(k0, hh)
+    ctx = h.helm_setup(dev(w["k2"]), hh, w["order"], k0=k0)
+    nodes = _sample_nodes(shape, 1)
+    x = cvec(n ** 3, 8)
+    y = host(h.helm_matvec(ctx, dev(x)))
+    yr = op.sampled_matvec(w["order"], w["k2"], (hh,) * 3, (g, g, g), x, nodes)
+    assert np.abs(y[nodes] - yr).max() <= 1e-12 * np.abs(yr).max()
+    for fp32, tol in ((False, 1e-11), (True, 2e-4)):
+        z = host(h.helm_precond_apply(ctx, dev(x), fp32=fp32))
+        mz = pc.sampled_M(shape, (hh,) * 3, k0, (g, g, g), z, nodes)
+        err = np.abs(mz - x[nodes]).max() / np.abs(x).max()
+        print(name, "precond fp32" if fp32 else "precond fp64", err)
+        assert err <= tol
+    F = h.helm_rhs(ctx, dev(w["f"]))
+    xs, info = h.helm_gmres_solve(ctx, F, m=w["m"], rtol=1e-10, flexible=True, prec_fp32=True)
+    Fh = host(F)
+    r = Fh[nodes] - op.sampled_matvec(w["order"], w["k2"], (hh,) * 3, (g, g, g), host(xs), nodes)
+    print(name, info["iters"], info["relres_true"], np.abs(r).max() / np.linalg.norm(Fh))
+    assert info["converged"]
+    assert np.abs(r).max() <= 1.01e-10 * np.linalg.norm(Fh)
