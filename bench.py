@@ -1,0 +1,205 @@
+#!/usr/bin/env python3
+"""Benchmark of the compact-Helmholtz EigT-(F)GMRES solve on one MI355X.
+
+Workload (the 256^3 filtered-noise medium): 6th-order compact 27-point scheme, N = 256 per axis, h = 1/257,
+k0 = 120 (k0 h = 0.467), k^2 = k0^2 (1 + 0.2 w) with w seeded uniform noise filtered by a Gaussian of width
+8 cells and normalised to max|w| = 1, Gaussian point source (sigma = 2h) at the centre, two-point absorbing
+closure on all faces. Every input is synthetic and seeded.
+
+One step = one complete solve to ||F - A x|| <= 1e-8 ||F|| from x = 0 with inputs resident in HBM:
+  * headline form: FGMRES(50) in FP64 with the EigT preconditioner in complex FP32 on MFMA;
+  * reference form: plain right-preconditioned GMRES(50) with the EigT preconditioner in FP64.
+value = unknowns x iterations / s of the headline form; ms_per_step = its time-to-solution.
+
+Prints one JSON line. Per-kernel device times come from HIP events recorded on the solve's stream over the
+timed region (helm_profile_*); the roofline entry is the kernel class with the largest share of device time.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+PEAK = {"hbm_GBps": 8000.0, "fp64_TFLOPs": 78.6, "fp32_TFLOPs": 157.3}
+# kernel class -> (bound, unit, peak) ; work is bytes (hbm) or flops (mfma)
+KCLASS = {
+    "matvec": ("hbm", "GB/s", PEAK["hbm_GBps"]),
+    "gemm_x64": ("mfma", "TFLOP/s", PEAK["fp64_TFLOPs"]),
+    "gemm_y64": ("mfma", "TFLOP/s", PEAK["fp64_TFLOPs"]),
+    "gemm_x32": ("mfma", "TFLOP/s", PEAK["fp32_TFLOPs"]),
+    "gemm_y32": ("mfma", "TFLOP/s", PEAK["fp32_TFLOPs"]),
+    "tridiag64": ("hbm", "GB/s", PEAK["hbm_GBps"]),
+    "tridiag32": ("hbm", "GB/s", PEAK["hbm_GBps"]),
+    "dots": ("hbm", "GB/s", PEAK["hbm_GBps"]),
+    "lincomb": ("hbm", "GB/s", PEAK["hbm_GBps"]),
+    "pfft": ("mfma", "TFLOP/s", PEAK["fp32_TFLOPs"]),
+}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_table(prof):
+    out = {}
+    for name, v in prof.items():
+        bound, unit, peak = KCLASS[name]
+        avg_ms = v["ms"] / v["launches"]
+        rate = v["work"] / (v["ms"] * 1e-3)
+        achieved = rate / (1e9 if unit == "GB/s" else 1e12)
+        out[name] = dict(bound=bound, launches=v["launches"], total_ms=round(v["ms"], 4), avg_ms=round(avg_ms, 5),
+                         work_per_launch=v["work"] / v["launches"], achieved=round(achieved, 3), unit=unit,
+                         peak=peak, frac=round(achieved / peak, 4))
+    return out
+
+
+def cpu_baseline(n_cpu: int = 128):
+    """The oracle (numpy/scipy complex128 EigT + GMRES(50)) on the same workload recipe at a smaller grid with
+    the same k0 h, timed on the host. Assembly is timed separately and excluded from the rate."""
+    import threadpoolctl
+
+    import synth
+    from oracle import krylov as kr
+    from oracle import operators as op
+    from oracle import precond as pc
+    k0 = 120.0 * (n_cpu + 1) / 257.0
+    h = 1.0 / (n_cpu + 1)
+    k2 = synth.filtered_noise_k2(n_cpu, k0)
+    f = synth.gaussian_source(n_cpu)
+    t0 = time.perf_counter()
+    A, F = op.problem(6, k2, f, h, k0)
+    g = op.gamma_abc(k0, h)
+    e = pc.EigT((n_cpu,) * 3, (h,) * 3, k0, (g, g, g))
+    t_setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    x, info = kr.gmres(lambda v: A @ v, e.solve, F, m=50, rtol=1e-8)
+    t_solve = time.perf_counter() - t0
+    threads = max([p.get("num_threads", 1) for p in threadpoolctl.threadpool_info()] or [1])
+    rate = n_cpu ** 3 * info["iters"] / t_solve
+    return dict(value=rate, unit="unknowns*iterations/s", cores=int(threads), kind="oracle",
+                sample=(f"oracle FP64 EigT-GMRES(50) solve of the same recipe (6th order, 0.2 x filtered noise, "
+                        f"Gaussian source) at {n_cpu}^3 with k0 h = 0.467 (k0 = {k0:.2f}), rtol 1e-8: "
+                        f"{info['iters']} iterations in {t_solve:.2f} s; assembly + eigen set-up "
+                        f"{t_setup:.2f} s excluded"),
+                time_to_solution_s=round(t_solve, 3), iters=info["iters"])
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=256, help="grid points per axis (256 is the benchmark workload)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--forms", default="fp32_eigt_fgmres,fp64_eigt_gmres")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): this solver has no multi-GPU path; "
+              "the z-slab decomposition is a design note, not code.", file=sys.stderr)
+        sys.exit(2)
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    import torch
+
+    import paper_2602_07711_amd as H
+    import synth
+
+    n = args.n
+    log(f"generating the {n}^3 filtered-noise medium")
+    w = synth.workload("noise", n=n)
+    hh, k0 = w["h"], w["k0"]
+    if n != 256:
+        k0 = 120.0 * (n + 1) / 257.0
+        w = dict(w, k0=k0, k2=synth.filtered_noise_k2(n, k0))
+    dev = torch.device("cuda:0")
+    k2 = torch.from_numpy(w["k2"]).to(dev)
+    f = torch.from_numpy(w["f"]).to(dev)
+    t0 = time.perf_counter()
+    ctx = H.helm_setup(k2, hh, 6, k0=k0)
+    F = H.helm_rhs(ctx, f)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    log(f"setup {t_setup:.3f} s")
+    del k2, f
+    x = torch.empty_like(F)
+    unknowns = n ** 3
+    forms_def = {
+        "fp32_eigt_fgmres": dict(m=50, flexible=True, prec_fp32=True, prec="eigt"),
+        "fp64_eigt_gmres": dict(m=50, flexible=False, prec_fp32=False, prec="eigt"),
+        "fp64_eigt_fgmres": dict(m=50, flexible=True, prec_fp32=False, prec="eigt"),
+    }
+    forms = {}
+    for name in args.forms.split(","):
+        kw = forms_def[name]
+        for _ in range(args.warmup):
+            H.helm_gmres_solve(ctx, F, x, rtol=1e-8, x0_given=False, **kw)
+        torch.cuda.synchronize()
+        H.helm_profile_enable(ctx, True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        infos = []
+        for _ in range(args.steps):
+            _, info = H.helm_gmres_solve(ctx, F, x, rtol=1e-8, x0_given=False, **kw)
+            infos.append(info)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        prof = H.helm_profile_read(ctx)
+        H.helm_profile_enable(ctx, False)
+        iters = sum(i["iters"] for i in infos)
+        forms[name] = dict(ms_per_solve=round(1e3 * dt / args.steps, 3), iters=infos[-1]["iters"],
+                           reorths=infos[-1]["reorths"],
+                           unknowns_iters_per_s=unknowns * iters / dt, relres_true=infos[-1]["relres_true"],
+                           converged=all(i["converged"] for i in infos),
+                           phase_ms=dict((k, round(v, 3)) for k, v in infos[-1]["t_ms"].items()),
+                           kernels=kernel_table(prof))
+        log(f"{name}: {forms[name]['ms_per_solve']} ms/solve, {forms[name]['iters']} iterations, "
+            f"{forms[name]['unknowns_iters_per_s']:.3e} unknowns*it/s")
+    head = "fp32_eigt_fgmres" if "fp32_eigt_fgmres" in forms else next(iter(forms))
+    hf = forms[head]
+    dom = max(hf["kernels"].items(), key=lambda kv: kv[1]["total_ms"])
+    dname, dk = dom
+    roofline = dict(kernel=dname, bound=dk["bound"], achieved=dk["achieved"], peak=dk["peak"], unit=dk["unit"],
+                    frac=dk["frac"], traffic=None,
+                    note="achieved = algorithmic work per launch / average launch time (HIP events on the solve "
+                         "stream over the timed region)")
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a bounded sample")
+        cpu = cpu_baseline()
+        log(f"cpu oracle {cpu['value']:.3e} unknowns*it/s on {cpu['cores']} threads")
+    speedup = None
+    if "fp64_eigt_gmres" in forms and head != "fp64_eigt_gmres":
+        speedup = forms["fp64_eigt_gmres"]["ms_per_solve"] / hf["ms_per_solve"]
+    line = {
+        "metric": "time-to-solution & unknowns·iters/s at 256^3, rtol 1e-8: FP32/learned vs FP64 EigT",
+        "value": hf["unknowns_iters_per_s"],
+        "unit": "unknowns*iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": hf["ms_per_solve"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64 outer, f32 preconditioner" if head == "fp32_eigt_fgmres" else "f64",
+        "data": "synthetic",
+        "config": {"workload": (f"filtered-noise medium {n}^3: 6th-order compact 27-point Helmholtz, k0={k0:g} "
+                                f"(k0 h = {k0 * hh:.3f}), 0.2 x Gaussian-filtered (8 cells) seeded noise, "
+                                "Gaussian point source, two-point absorbing closure; FGMRES(50) + EigT "
+                                "complex-FP32 preconditioner, rtol 1e-8, x0 = 0"),
+                   "n": n, "order": 6, "restart": 50, "rtol": 1e-8, "form": head},
+        "time_to_solution_ms": hf["ms_per_solve"],
+        "speedup_vs_fp64_eigt": round(speedup, 3) if speedup else None,
+        "setup_s": round(t_setup, 3),
+        "forms": forms,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -90,6 +90,7 @@ typedef struct {
     int restarts;          /* completed cycles                                                               */
     int converged;         /* 1 if the true residual met rtol                                                */
     int hist_used;         /* entries written to resid_hist                                                  */
+    int reorths;           /* Arnoldi steps that needed a second Gram-Schmidt pass                           */
     double relres_est;     /* last Givens residual estimate / ||F||                                          */
     double relres_true;    /* ||F - A x|| / ||F|| at exit                                                    */
     double t_ms[6];        /* device time per phase: matvec, preconditioner, Arnoldi (dots + update),
@@ -133,6 +134,37 @@ helm_status helm_precond_apply(helm_ctx *ctx, const void *y_dev, void *z_dev, in
  * (x holds the last iterate), HELM_EBREAKDOWN, HELM_ENUMERIC on NaN/Inf, HELM_EINVAL for bad options. */
 helm_status helm_gmres_solve(helm_ctx *ctx, const void *F_dev, void *x_dev, const helm_solve_opts *opts,
                              helm_solve_info *info);
+
+/* Kernel classes for per-kernel timing. */
+typedef enum {
+    HELM_K_MATVEC = 0,     /* compact-stencil y = A x (also r = F - A x)                                     */
+    HELM_K_GEMM_X64 = 1,   /* EigT x-transform, complex FP64 MFMA (forward and inverse)                      */
+    HELM_K_GEMM_Y64 = 2,   /* EigT y-transform, complex FP64 MFMA, batched over slices                       */
+    HELM_K_GEMM_X32 = 3,   /* EigT x-transform, complex FP32 MFMA                                            */
+    HELM_K_GEMM_Y32 = 4,   /* EigT y-transform, complex FP32 MFMA                                            */
+    HELM_K_TRIDIAG64 = 5,  /* z-tridiagonal solves, FP64                                                     */
+    HELM_K_TRIDIAG32 = 6,  /* z-tridiagonal solves, FP32                                                     */
+    HELM_K_DOTS = 7,       /* Krylov block inner products + norm (both reduction stages)                     */
+    HELM_K_LINCOMB = 8,    /* Krylov linear combinations (orthogonalisation update, x += Z y, restart)       */
+    HELM_K_PFFT = 9,       /* PFFT sine transforms and boundary corrections                                  */
+    HELM_K_COUNT = 10
+} helm_kernel_class;
+
+/* Per-kernel device timing. With on = 1 every kernel the context launches is bracketed by HIP events on the
+ * context stream and its duration is accumulated by class (counters reset); on = 0 stops recording.
+ * Pending events are resolved at the library's own synchronisation points and in helm_profile_read. */
+helm_status helm_profile_enable(helm_ctx *ctx, int on);
+
+/* Accumulated device milliseconds, launch count and algorithmic work of one kernel class since the last
+ * enable. Work is the method's minimum per launch, summed: HBM bytes for the memory-bound classes (matvec:
+ * x, k^2 and the order-6 field block read once, y written once; tridiagonal: transformed data read and
+ * written once; Krylov kernels: every vector read or written once) and real flops for the GEMMs
+ * (8 M N K per complex product). Any output pointer may be NULL. Waits for the context stream. */
+helm_status helm_profile_read(helm_ctx *ctx, int kernel_class, double *ms_total, long long *launches,
+                              double *work);
+
+/* Short name of a kernel class ("matvec", "gemm_x64", ...), or "" for an unknown class. */
+const char *helm_profile_name(int kernel_class);
 
 /* Number of unknowns n = Nx*Ny*Nz of a context. */
 long long helm_size(const helm_ctx *ctx);

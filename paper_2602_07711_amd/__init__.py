@@ -9,6 +9,8 @@ from .helm import (  # noqa: F401
     helm_gmres_solve,
     helm_matvec,
     helm_precond_apply,
+    helm_profile_enable,
+    helm_profile_read,
     helm_rhs,
     helm_setup,
     lib,

@@ -74,6 +74,14 @@ helm_status upload_matrix(Ctx &c, const std::vector<cd> &M, int n, bool transpos
 // over slices), z-tridiagonal solves, inverse y-transform, inverse x-transform.
 // ---------------------------------------------------------------------------------------------------------
 
+double gemm_flops(const GemmDesc &d) { return 8.0 * d.M * (double)d.N * d.K * d.batch; }
+
+// minimum HBM bytes of one matvec: x, k^2 (and the order-6 field block) read once, y written once
+double matvec_bytes(const Ctx &c, bool resid) {
+    double per = 16.0 + 8.0 + 16.0 + (c.order == 6 ? 32.0 : 0.0) + (resid ? 16.0 : 0.0);
+    return per * c.n;
+}
+
 GemmDesc desc_x(const Ctx &c) {
     GemmDesc d{};
     d.M = c.ny * c.nz; d.N = c.nx; d.K = c.nx;
@@ -102,18 +110,18 @@ helm_status eigt_apply(Ctx &c, const double2 *y, double2 *z, bool fp32) {
     double2 gz = d2(c.gamma[2]);
     double scale = c.hz * c.hz;
     if (!fp32) {
-        HIP_TRY(launch_gemm_z64(dx, y, c.BxF, c.t1, c.stream));
-        HIP_TRY(launch_gemm_z64(dy, c.AyF, c.t1, c.t2, c.stream));
-        HIP_TRY(launch_tridiag_z64(c.t2, c.cp, c.dxe, c.dye, c.nx, c.ny, c.nz, c.ax, c.ay, c.c0, gz, scale, c.stream));
-        HIP_TRY(launch_gemm_z64(dy, c.AyI, c.t2, c.t1, c.stream));
-        HIP_TRY(launch_gemm_z64(dx, c.t1, c.BxI, z, c.stream));
+        HIP_TRY(timed(c, HELM_K_GEMM_X64, gemm_flops(dx), [&] { return launch_gemm_z64(dx, y, c.BxF, c.t1, c.stream); }));
+        HIP_TRY(timed(c, HELM_K_GEMM_Y64, gemm_flops(dy), [&] { return launch_gemm_z64(dy, c.AyF, c.t1, c.t2, c.stream); }));
+        HIP_TRY(timed(c, HELM_K_TRIDIAG64, 32.0 * c.n, [&] { return launch_tridiag_z64(c.t2, c.cp, c.dxe, c.dye, c.nx, c.ny, c.nz, c.ax, c.ay, c.c0, gz, scale, c.stream); }));
+        HIP_TRY(timed(c, HELM_K_GEMM_Y64, gemm_flops(dy), [&] { return launch_gemm_z64(dy, c.AyI, c.t2, c.t1, c.stream); }));
+        HIP_TRY(timed(c, HELM_K_GEMM_X64, gemm_flops(dx), [&] { return launch_gemm_z64(dx, c.t1, c.BxI, z, c.stream); }));
     } else {
         ST_TRY(ensure_fp32_work(c));
-        HIP_TRY(launch_gemm_z32_in64(dx, y, c.BxF32, c.t1f, c.stream));
-        HIP_TRY(launch_gemm_z32(dy, c.AyF32, c.t1f, c.t2f, c.stream));
-        HIP_TRY(launch_tridiag_z32(c.t2f, c.cpf, c.dxe, c.dye, c.nx, c.ny, c.nz, c.ax, c.ay, c.c0, gz, scale, c.stream));
-        HIP_TRY(launch_gemm_z32(dy, c.AyI32, c.t2f, c.t1f, c.stream));
-        HIP_TRY(launch_gemm_z32_out64(dx, c.t1f, c.BxI32, z, c.stream));
+        HIP_TRY(timed(c, HELM_K_GEMM_X32, gemm_flops(dx), [&] { return launch_gemm_z32_in64(dx, y, c.BxF32, c.t1f, c.stream); }));
+        HIP_TRY(timed(c, HELM_K_GEMM_Y32, gemm_flops(dy), [&] { return launch_gemm_z32(dy, c.AyF32, c.t1f, c.t2f, c.stream); }));
+        HIP_TRY(timed(c, HELM_K_TRIDIAG32, 16.0 * c.n, [&] { return launch_tridiag_z32(c.t2f, c.cpf, c.dxe, c.dye, c.nx, c.ny, c.nz, c.ax, c.ay, c.c0, gz, scale, c.stream); }));
+        HIP_TRY(timed(c, HELM_K_GEMM_Y32, gemm_flops(dy), [&] { return launch_gemm_z32(dy, c.AyI32, c.t2f, c.t1f, c.stream); }));
+        HIP_TRY(timed(c, HELM_K_GEMM_X32, gemm_flops(dx), [&] { return launch_gemm_z32_out64(dx, c.t1f, c.BxI32, z, c.stream); }));
     }
     return HELM_OK;
 }
@@ -157,9 +165,10 @@ helm_status ensure_krylov(Ctx &c, int m, int flexible) {
 // out[0..nv-1] = V_i^H w, out[nv] = ||w||^2 (host values, after a stream sync)
 helm_status dots(Ctx &c, const double2 *V, int nv, const double2 *w, std::vector<cd> &out) {
     KrylovWork &k = c.kw;
-    HIP_TRY(launch_dots(V, c.n, nv, w, c.n, k.partials, k.nblocks, k.red, c.stream));
+    HIP_TRY(timed(c, HELM_K_DOTS, 16.0 * c.n * (nv + 1), [&] { return launch_dots(V, c.n, nv, w, c.n, k.partials, k.nblocks, k.red, c.stream); }));
     HIP_TRY(hipMemcpyAsync(k.red_host, k.red, (nv + 1) * sizeof(double2), hipMemcpyDeviceToHost, c.stream));
     HIP_TRY(hipStreamSynchronize(c.stream));
+    prof_resolve(c);
     out.resize(nv + 1);
     for (int i = 0; i <= nv; ++i) out[i] = cd(k.red_host[i].x, k.red_host[i].y);
     for (int i = 0; i <= nv; ++i)
@@ -193,6 +202,35 @@ const char *helm_last_error(const helm_ctx *ctx) { return ctx ? ctx->c.err.c_str
 
 long long helm_size(const helm_ctx *ctx) { return ctx ? ctx->c.n : 0; }
 
+const char *helm_profile_name(int cls) {
+    static const char *names[HELM_K_COUNT] = {"matvec", "gemm_x64", "gemm_y64", "gemm_x32", "gemm_y32",
+                                              "tridiag64", "tridiag32", "dots", "lincomb", "pfft"};
+    return (cls >= 0 && cls < HELM_K_COUNT) ? names[cls] : "";
+}
+
+helm_status helm_profile_enable(helm_ctx *ctx, int on) {
+    if (!ctx) return HELM_EINVAL;
+    Ctx &c = ctx->c;
+    HIP_TRY(c.stream ? hipStreamSynchronize(c.stream) : hipDeviceSynchronize());
+    prof_resolve(c);
+    if (on) {
+        for (int i = 0; i < HELM_K_COUNT; ++i) { c.prof_ms[i] = 0.0; c.prof_n[i] = 0; c.prof_work[i] = 0.0; }
+    }
+    c.prof = on != 0;
+    return HELM_OK;
+}
+
+helm_status helm_profile_read(helm_ctx *ctx, int cls, double *ms_total, long long *launches, double *work) {
+    if (!ctx || cls < 0 || cls >= HELM_K_COUNT) return HELM_EINVAL;
+    Ctx &c = ctx->c;
+    HIP_TRY(c.stream ? hipStreamSynchronize(c.stream) : hipDeviceSynchronize());
+    prof_resolve(c);
+    if (ms_total) *ms_total = c.prof_ms[cls];
+    if (launches) *launches = c.prof_n[cls];
+    if (work) *work = c.prof_work[cls];
+    return HELM_OK;
+}
+
 helm_status helm_eig1d(int n, double gamma_re, double gamma_im, double *d, double *V, double *Vinv) {
     if (n < 2 || !d || !V || !Vinv) return HELM_EINVAL;
     std::vector<cd> dd, VV, VI;
@@ -214,6 +252,9 @@ void helm_destroy(helm_ctx *ctx) {
     hipSetDevice(c.device);
     if (c.stream) hipStreamSynchronize(c.stream);
     else hipDeviceSynchronize();
+    prof_resolve(c);
+    for (hipEvent_t e : c.prof_pool) hipEventDestroy(e);
+    c.prof_pool.clear();
     for (void *p : c.allocs) hipFree(p);
     c.allocs.clear();
     if (c.kw.red_host) hipHostFree(c.kw.red_host);
@@ -354,7 +395,7 @@ helm_status helm_matvec(helm_ctx *ctx, const void *x_dev, void *y_dev) {
     Ctx &c = ctx->c;
     if (!x_dev || !y_dev) { c.err = "NULL pointer"; return HELM_EINVAL; }
     if (x_dev == y_dev) { c.err = "matvec input and output must not overlap"; return HELM_EINVAL; }
-    HIP_TRY(launch_matvec(c.sp, (const double2 *)x_dev, c.k2, c.fld, nullptr, (double2 *)y_dev, c.stream));
+    HIP_TRY(timed(c, HELM_K_MATVEC, matvec_bytes(c, false), [&] { return launch_matvec(c.sp, (const double2 *)x_dev, c.k2, c.fld, nullptr, (double2 *)y_dev, c.stream); }));
     return HELM_OK;
 }
 
@@ -435,7 +476,7 @@ helm_status helm_gmres_solve(helm_ctx *ctx, const void *F_dev, void *x_dev, cons
         if (first && !opts->x0_given) {
             HIP_TRY(hipMemcpyAsync(k.V, F, n * sizeof(double2), hipMemcpyDeviceToDevice, c.stream));
         } else {
-            HIP_TRY(launch_matvec(c.sp, x, c.k2, c.fld, F, k.V, c.stream));
+            HIP_TRY(timed(c, HELM_K_MATVEC, matvec_bytes(c, true), [&] { return launch_matvec(c.sp, x, c.k2, c.fld, F, k.V, c.stream); }));
         }
         HIP_TRY(hipEventRecord(ev[1], c.stream));
         first = false;
@@ -446,7 +487,7 @@ helm_status helm_gmres_solve(helm_ctx *ctx, const void *F_dev, void *x_dev, cons
         push_hist(inf.relres_true);
         if (beta <= opts->rtol * bnorm) { result = HELM_OK; inf.converged = 1; break; }
         if (its >= opts->maxit) { result = HELM_ENOCONV; break; }
-        HIP_TRY(launch_lincomb(k.V, k.V, make_double2(1.0 / beta, 0.0), nullptr, n, 0, coef.data(), n, c.stream));
+        HIP_TRY(timed(c, HELM_K_LINCOMB, 16.0 * c.n * 2, [&] { return launch_lincomb(k.V, k.V, make_double2(1.0 / beta, 0.0), nullptr, n, 0, coef.data(), n, c.stream); }));
         std::fill(H.begin(), H.end(), cd(0.0));
         std::fill(g.begin(), g.end(), cd(0.0));
         g[0] = beta;
@@ -459,9 +500,13 @@ helm_status helm_gmres_solve(helm_ctx *ctx, const void *F_dev, void *x_dev, cons
             HIP_TRY(hipEventRecord(ev[2], c.stream));
             ST_TRY(precond(c, vj, z, opts->prec, opts->prec_fp32));
             HIP_TRY(hipEventRecord(ev[3], c.stream));
-            HIP_TRY(launch_matvec(c.sp, z, c.k2, c.fld, nullptr, w, c.stream));
+            // Arnoldi on A M^{-1} - I (same Krylov space; column j of H gains +1 on its diagonal): the matvec in
+            // residual form writes y = v_j - A z_j = -(A M^{-1} v_j - v_j). With a good preconditioner
+            // A M^{-1} v_j is close to v_j, so orthogonalising the shifted vector avoids the cancellation that
+            // classical Gram-Schmidt on A M^{-1} v_j itself would suffer.
+            HIP_TRY(timed(c, HELM_K_MATVEC, matvec_bytes(c, true), [&] { return launch_matvec(c.sp, z, c.k2, c.fld, vj, w, c.stream); }));
             HIP_TRY(hipEventRecord(ev[4], c.stream));
-            // classical Gram-Schmidt: h = V^H w and ||w||^2 in one pass
+            // classical Gram-Schmidt: V^H y and ||y||^2 in one pass
             ST_TRY(dots(c, k.V, j + 1, w, hv));
             flush_upd();
             inf.t_ms[1] += elapsed(ev[2], ev[3]);
@@ -473,24 +518,27 @@ helm_status helm_gmres_solve(helm_ctx *ctx, const void *F_dev, void *x_dev, cons
             HIP_TRY(hipEventRecord(ev[5], c.stream));
             if (!(eta2 > 0.5 * ww)) {
                 // cancellation: subtract, then re-orthogonalise once (and take the norm from the second pass)
+                ++inf.reorths;
                 for (int i = 0; i <= j; ++i) coef[i] = make_double2(-hv[i].real(), -hv[i].imag());
-                HIP_TRY(launch_lincomb(w, w, make_double2(1.0, 0.0), k.V, n, j + 1, coef.data(), n, c.stream));
+                HIP_TRY(timed(c, HELM_K_LINCOMB, 16.0 * c.n * (j + 3), [&] { return launch_lincomb(w, w, make_double2(1.0, 0.0), k.V, n, j + 1, coef.data(), n, c.stream); }));
                 ST_TRY(dots(c, k.V, j + 1, w, hv2));
                 double hh2 = 0.0;
                 for (int i = 0; i <= j; ++i) { hv[i] += hv2[i]; hh2 += std::norm(hv2[i]); }
                 eta2 = hv2[j + 1].real() - hh2;
-                for (int i = 0; i <= j; ++i) coef[i] = make_double2(-hv2[i].real(), -hv2[i].imag());
+                for (int i = 0; i <= j; ++i) coef[i] = make_double2(hv2[i].real(), hv2[i].imag());
             } else {
-                for (int i = 0; i <= j; ++i) coef[i] = make_double2(-hv[i].real(), -hv[i].imag());
+                for (int i = 0; i <= j; ++i) coef[i] = make_double2(hv[i].real(), hv[i].imag());
             }
             double eta = eta2 > 0.0 ? std::sqrt(eta2) : 0.0;
             if (eta > 0.0) {
+                // v_{j+1} = -(y - V h_y) / eta
                 for (int i = 0; i <= j; ++i) { coef[i].x /= eta; coef[i].y /= eta; }
-                HIP_TRY(launch_lincomb(w, w, make_double2(1.0 / eta, 0.0), k.V, n, j + 1, coef.data(), n, c.stream));
+                HIP_TRY(timed(c, HELM_K_LINCOMB, 16.0 * c.n * (j + 3), [&] { return launch_lincomb(w, w, make_double2(-1.0 / eta, 0.0), k.V, n, j + 1, coef.data(), n, c.stream); }));
             }
             HIP_TRY(hipEventRecord(ev[6], c.stream));
             // Hessenberg column j and Givens rotations
-            for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hv[i];
+            for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = -hv[i];
+            H[(size_t)j * m + j] += 1.0;
             H[(size_t)(j + 1) * m + j] = eta;
             for (int i = 0; i < j; ++i) {
                 cd a = H[(size_t)i * m + j], b = H[(size_t)(i + 1) * m + j];
@@ -533,15 +581,15 @@ helm_status helm_gmres_solve(helm_ctx *ctx, const void *F_dev, void *x_dev, cons
         for (int i = 0; i < kk; ++i) coef[i] = d2(yv[i]);
         HIP_TRY(hipEventRecord(ev[2], c.stream));
         if (flex) {
-            HIP_TRY(launch_lincomb(x, x, make_double2(1.0, 0.0), k.Z, n, kk, coef.data(), n, c.stream));
+            HIP_TRY(timed(c, HELM_K_LINCOMB, 16.0 * c.n * (kk + 2), [&] { return launch_lincomb(x, x, make_double2(1.0, 0.0), k.Z, n, kk, coef.data(), n, c.stream); }));
         } else {
-            HIP_TRY(launch_lincomb(k.tmp, nullptr, make_double2(0.0, 0.0), k.V, n, kk, coef.data(), n, c.stream));
+            HIP_TRY(timed(c, HELM_K_LINCOMB, 16.0 * c.n * (kk + 1), [&] { return launch_lincomb(k.tmp, nullptr, make_double2(0.0, 0.0), k.V, n, kk, coef.data(), n, c.stream); }));
             // z = M^{-1} (V y) lands in the slot of V_kk, which is no longer needed
             double2 *zz = k.V + (long long)kk * n;
             ST_TRY(precond(c, k.tmp, zz, opts->prec, opts->prec_fp32));
             cd one(1.0, 0.0);
             coef[0] = d2(one);
-            HIP_TRY(launch_lincomb(x, x, make_double2(1.0, 0.0), zz, n, 1, coef.data(), n, c.stream));
+            HIP_TRY(timed(c, HELM_K_LINCOMB, 16.0 * c.n * 3, [&] { return launch_lincomb(x, x, make_double2(1.0, 0.0), zz, n, 1, coef.data(), n, c.stream); }));
         }
         HIP_TRY(hipEventRecord(ev[3], c.stream));
         inf.t_ms[3] += elapsed(ev[2], ev[3]);

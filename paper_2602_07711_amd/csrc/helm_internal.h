@@ -55,6 +55,8 @@ struct KrylovWork {
     int nblocks = 0;
 };
 
+struct ProfPending { int cls; double work; hipEvent_t a, b; };
+
 struct Ctx {
     int nx, ny, nz;
     long long n;
@@ -84,7 +86,53 @@ struct Ctx {
     PfftPlan *pfft = nullptr;
     KrylovWork kw;
     std::vector<void *> allocs;  // everything to free
+
+    // per-kernel timing
+    bool prof = false;
+    double prof_ms[HELM_K_COUNT] = {};
+    long long prof_n[HELM_K_COUNT] = {};
+    double prof_work[HELM_K_COUNT] = {};
+    std::vector<ProfPending> prof_pending;
+    std::vector<hipEvent_t> prof_pool;
 };
+
+// Launch through `fn` (returning hipError_t), bracketed by profiling events when enabled.
+template <typename F> hipError_t timed(Ctx &c, int cls, double work, F fn) {
+    if (!c.prof) return fn();
+    hipEvent_t a, b;
+    if (c.prof_pool.size() >= 2) {
+        a = c.prof_pool.back(); c.prof_pool.pop_back();
+        b = c.prof_pool.back(); c.prof_pool.pop_back();
+    } else {
+        hipError_t e = hipEventCreate(&a);
+        if (e != hipSuccess) return e;
+        e = hipEventCreate(&b);
+        if (e != hipSuccess) return e;
+    }
+    hipError_t e = hipEventRecord(a, c.stream);
+    if (e != hipSuccess) return e;
+    e = fn();
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(b, c.stream);
+    if (e != hipSuccess) return e;
+    c.prof_pending.push_back({cls, work, a, b});
+    return hipSuccess;
+}
+
+// Accumulate every completed pending pair (call after a stream synchronisation).
+inline void prof_resolve(Ctx &c) {
+    for (auto &p : c.prof_pending) {
+        float ms = 0.f;
+        if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            c.prof_ms[p.cls] += ms;
+            c.prof_n[p.cls] += 1;
+            c.prof_work[p.cls] += p.work;
+        }
+        c.prof_pool.push_back(p.a);
+        c.prof_pool.push_back(p.b);
+    }
+    c.prof_pending.clear();
+}
 
 // ----- kernel launchers (defined in the .hip files); all enqueue on `s` and return hipError_t -----
 hipError_t launch_derived_fields(const double *k2_halo, int halo, double *k2, double4 *fld, const StencilParams &p,

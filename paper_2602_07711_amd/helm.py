@@ -45,7 +45,7 @@ class helm_solve_opts(ctypes.Structure):
 
 class helm_solve_info(ctypes.Structure):
     _fields_ = [("iters", c_int), ("restarts", c_int), ("converged", c_int), ("hist_used", c_int),
-                ("relres_est", c_double), ("relres_true", c_double), ("t_ms", c_double * 6)]
+                ("reorths", c_int), ("relres_est", c_double), ("relres_true", c_double), ("t_ms", c_double * 6)]
 
 
 _lib = None
@@ -79,6 +79,12 @@ def lib():
     L.helm_destroy.restype = None
     L.helm_eig1d.argtypes = [c_int, c_double, c_double, c_void_p, c_void_p, c_void_p]
     L.helm_eig1d.restype = c_int
+    L.helm_profile_enable.argtypes = [c_void_p, c_int]
+    L.helm_profile_enable.restype = c_int
+    L.helm_profile_read.argtypes = [c_void_p, c_int, POINTER(c_double), POINTER(c_longlong), POINTER(c_double)]
+    L.helm_profile_read.restype = c_int
+    L.helm_profile_name.argtypes = [c_int]
+    L.helm_profile_name.restype = ctypes.c_char_p
     _lib = L
     return L
 
@@ -185,11 +191,13 @@ def helm_precond_apply(ctx: Context, y: torch.Tensor, z: torch.Tensor | None = N
 
 def helm_gmres_solve(ctx: Context, F: torch.Tensor, x: torch.Tensor | None = None, m: int = 50, maxit: int = 1000,
                      rtol: float = 1e-8, flexible: bool = False, prec: str = "eigt", prec_fp32: bool = False,
-                     hist_len: int = 4096, raise_on_noconv: bool = True):
-    """Solve A x = F. Returns (x, info) with info a dict (iters, restarts, converged, relres_est, relres_true,
-    t_ms = {matvec, precond, arnoldi, update, host, total}, hist)."""
+                     hist_len: int = 4096, raise_on_noconv: bool = True, x0_given: bool | None = None):
+    """Solve A x = F. `x` (optional) is the output buffer; it is also the initial guess unless x0_given is
+    False (default: x0_given = x is not None). Returns (x, info) with info a dict (iters, restarts, converged,
+    relres_est, relres_true, t_ms = {matvec, precond, arnoldi, update, host, total}, hist)."""
     _check(F, torch.complex128, ctx.n, "F")
-    x0_given = x is not None
+    if x0_given is None:
+        x0_given = x is not None
     if x is None:
         x = torch.empty_like(F)
     _check(x, torch.complex128, ctx.n, "x")
@@ -198,13 +206,33 @@ def helm_gmres_solve(ctx: Context, F: torch.Tensor, x: torch.Tensor | None = Non
                            int(x0_given), ctypes.cast(hist, POINTER(c_double)), int(hist_len))
     info = helm_solve_info()
     st = lib().helm_gmres_solve(ctx.ptr, c_void_p(F.data_ptr()), c_void_p(x.data_ptr()), byref(opts), byref(info))
-    out = dict(iters=info.iters, restarts=info.restarts, converged=bool(info.converged), relres_est=info.relres_est,
+    out = dict(iters=info.iters, restarts=info.restarts, converged=bool(info.converged), reorths=info.reorths,
+               relres_est=info.relres_est,
                relres_true=info.relres_true, status=STATUS_NAMES[st],
                t_ms=dict(zip(("matvec", "precond", "arnoldi", "update", "host", "total"), list(info.t_ms))),
                hist=[hist[i] for i in range(info.hist_used)])
     if st != HELM_OK and not (st == HELM_ENOCONV and not raise_on_noconv):
         raise HelmError(st, ctx.error())
     return x, out
+
+
+KERNEL_CLASSES = 10
+
+
+def helm_profile_enable(ctx: Context, on: bool = True):
+    """Start (and reset) or stop per-kernel device timing on the context stream."""
+    ctx.check(lib().helm_profile_enable(ctx.ptr, int(bool(on))))
+
+
+def helm_profile_read(ctx: Context) -> dict:
+    """{class name: {"ms": total device ms, "launches": count, "work": algorithmic bytes or flops}}."""
+    out = {}
+    for k in range(KERNEL_CLASSES):
+        ms, n, w = c_double(), c_longlong(), c_double()
+        ctx.check(lib().helm_profile_read(ctx.ptr, k, byref(ms), byref(n), byref(w)))
+        if n.value:
+            out[lib().helm_profile_name(k).decode()] = dict(ms=ms.value, launches=n.value, work=w.value)
+    return out
 
 
 def helm_destroy(ctx: Context):
