@@ -96,6 +96,9 @@ def main():
     ap.add_argument("--n", type=int, default=256, help="grid points per axis (256 is the benchmark workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="fp32_eigt_fgmres,fp64_eigt_gmres")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run three plain 256 MiB device-to-device copies (reference dispatches for scaling "
+                         "hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): this solver has no multi-GPU path; "
@@ -126,6 +129,13 @@ def main():
     del k2, f
     x = torch.empty_like(F)
     unknowns = n ** 3
+    if args.copy_calib:
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)   # 256 MiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     forms_def = {
         "fp32_eigt_fgmres": dict(m=50, flexible=True, prec_fp32=True, prec="eigt"),
         "fp64_eigt_gmres": dict(m=50, flexible=False, prec_fp32=False, prec="eigt"),

@@ -7,7 +7,10 @@
 // In both the fastest memory index of the data lands on the MFMA column index, so tile loads and the
 // accumulator stores walk contiguous memory.
 //
-// Arithmetic: four real MFMA products per complex k-step (Cr += Ar Br - Ai Bi, Ci += Ar Bi + Ai Br) with
+// Arithmetic, FP32: three real MFMA products per complex k-step (Gauss / 3M form: T1 += Ar Br, T2 += Ai Bi,
+// T3 += (Ar + Ai)(Br + Bi); then Cr = T1 - T2, Ci = T3 - T1 - T2), 25% fewer MFMA issues than the four-product
+// form at a rounding error bounded by eps (|Ar| + |Ai|)(|Br| + |Bi|) per term. FP64: the four-product form
+// (Cr += Ar Br - Ai Bi, Ci += Ar Bi + Ai Br), since three f64 accumulator sets would halve occupancy. MFMA
 // v_mfma_f64_16x16x4f64 (FP64) or v_mfma_f32_16x16x4f32 (FP32). Lane layout of the 16x16x4 products
 // (checked on gfx950): A(row = lane%16, k = lane/16), B(k = lane/16, col = lane%16); accumulator register r
 // of a lane holds D(row = 4*r + lane/16, col = lane%16) for f64 and D(row = 4*(lane/16) + r, col = lane%16)
@@ -78,14 +81,15 @@ __global__ __launch_bounds__(256) void k_zgemm(const TA *__restrict__ A, const T
     const int lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
 
-    ACC accr[FM][FN], acci[FM][FN];
+    constexpr bool G3 = sizeof(T) == 4;   // 3M form for FP32, 4M for FP64
+    constexpr int NS = G3 ? 3 : 2;
+    ACC t[NS][FM][FN];
 #pragma unroll
-    for (int i = 0; i < FM; ++i)
+    for (int q = 0; q < NS; ++q)
 #pragma unroll
-        for (int j = 0; j < FN; ++j) {
-            accr[i][j] = ACC{0, 0, 0, 0};
-            acci[i][j] = ACC{0, 0, 0, 0};
-        }
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j) t[q][i][j] = ACC{0, 0, 0, 0};
 
     CT ra[EA], rb[EB];
     auto fetch = [&](int k0) {
@@ -134,20 +138,41 @@ __global__ __launch_bounds__(256) void k_zgemm(const TA *__restrict__ A, const T
             for (int i = 0; i < FM; ++i) fa[i] = sA[kk + kl][rowA + i * 16];
 #pragma unroll
             for (int j = 0; j < FN; ++j) fb[j] = sB[kk + kl][colB + j * 16];
+            if constexpr (G3) {
+                T sa[FM], sb[FN];
 #pragma unroll
-            for (int i = 0; i < FM; ++i)
+                for (int i = 0; i < FM; ++i) sa[i] = fa[i].x + fa[i].y;
 #pragma unroll
-                for (int j = 0; j < FN; ++j) {
-                    accr[i][j] = mfma(fa[i].x, fb[j].x, accr[i][j]);
-                    acci[i][j] = mfma(fa[i].x, fb[j].y, acci[i][j]);
-                }
+                for (int j = 0; j < FN; ++j) sb[j] = fb[j].x + fb[j].y;
 #pragma unroll
-            for (int i = 0; i < FM; ++i)
+                for (int i = 0; i < FM; ++i)
 #pragma unroll
-                for (int j = 0; j < FN; ++j) {
-                    accr[i][j] = mfma(-fa[i].y, fb[j].y, accr[i][j]);
-                    acci[i][j] = mfma(fa[i].y, fb[j].x, acci[i][j]);
-                }
+                    for (int j = 0; j < FN; ++j) t[0][i][j] = mfma(fa[i].x, fb[j].x, t[0][i][j]);
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+#pragma unroll
+                    for (int j = 0; j < FN; ++j) t[1][i][j] = mfma(fa[i].y, fb[j].y, t[1][i][j]);
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+#pragma unroll
+                    for (int j = 0; j < FN; ++j) t[NS - 1][i][j] = mfma(sa[i], sb[j], t[NS - 1][i][j]);
+            } else {
+                // t[0] = real part, t[1] = imaginary part
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+#pragma unroll
+                    for (int j = 0; j < FN; ++j) {
+                        t[0][i][j] = mfma(fa[i].x, fb[j].x, t[0][i][j]);
+                        t[1][i][j] = mfma(fa[i].x, fb[j].y, t[1][i][j]);
+                    }
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+#pragma unroll
+                    for (int j = 0; j < FN; ++j) {
+                        t[0][i][j] = mfma(-fa[i].y, fb[j].y, t[0][i][j]);
+                        t[1][i][j] = mfma(fa[i].y, fb[j].x, t[1][i][j]);
+                    }
+            }
         }
     }
 
@@ -160,8 +185,13 @@ __global__ __launch_bounds__(256) void k_zgemm(const TA *__restrict__ A, const T
             for (int r = 0; r < 4; ++r) {
                 const int rr = sizeof(T) == 8 ? 4 * r + (lane >> 4) : 4 * (lane >> 4) + r;
                 const int gm = m0 + wm * (BM / 2) + i * 16 + rr;
-                if (gm < d.M && gn < d.N)
-                    C[(long long)gm * d.ldc + gn] = pack<TC, T>(accr[i][j][r], acci[i][j][r]);
+                if (gm < d.M && gn < d.N) {
+                    if constexpr (G3)
+                        C[(long long)gm * d.ldc + gn] = pack<TC, T>(t[0][i][j][r] - t[1][i][j][r],
+                                                                    t[NS - 1][i][j][r] - t[0][i][j][r] - t[1][i][j][r]);
+                    else
+                        C[(long long)gm * d.ldc + gn] = pack<TC, T>(t[0][i][j][r], t[1][i][j][r]);
+                }
             }
         }
 }

@@ -32,14 +32,42 @@ __global__ __launch_bounds__(256) void k_dots(const double2 *__restrict__ V, lon
         wr[e] = idx < n ? w[idx] : make_double2(0.0, 0.0);
         ww += wr[e].x * wr[e].x + wr[e].y * wr[e].y;
     }
-    for (int i = 0; i < nv; ++i) {
+    // four vectors per round: their loads and the eight reduction chains overlap
+    int i = 0;
+    for (; i + 4 <= nv; i += 4) {
+        double re[4] = {0.0, 0.0, 0.0, 0.0}, im[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const double2 *vi = V + (long long)(i + q) * ldv;
+#pragma unroll
+            for (int e = 0; e < DOT_EPT; ++e) {
+                long long idx = base + (long long)e * 256;
+                double2 v = idx < n ? vi[idx] : make_double2(0.0, 0.0);
+                re[q] += v.x * wr[e].x + v.y * wr[e].y;   // conj(v) * w
+                im[q] += v.x * wr[e].y - v.y * wr[e].x;
+            }
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                re[q] += __shfl_xor(re[q], off, 64);
+                im[q] += __shfl_xor(im[q], off, 64);
+            }
+        }
+        if (lane == 0) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) red[wave][i + q] = make_double2(re[q], im[q]);
+        }
+    }
+    for (; i < nv; ++i) {
         const double2 *vi = V + (long long)i * ldv;
         double re = 0.0, im = 0.0;
 #pragma unroll
         for (int e = 0; e < DOT_EPT; ++e) {
             long long idx = base + (long long)e * 256;
             double2 v = idx < n ? vi[idx] : make_double2(0.0, 0.0);
-            re += v.x * wr[e].x + v.y * wr[e].y;   // conj(v) * w
+            re += v.x * wr[e].x + v.y * wr[e].y;
             im += v.x * wr[e].y - v.y * wr[e].x;
         }
         re = wave_sum(re);
@@ -78,25 +106,44 @@ __global__ __launch_bounds__(256) void k_reduce(const double2 *__restrict__ part
 
 constexpr int LC_MAX = 48;
 struct LcCoef { double2 c[LC_MAX]; };
+constexpr int LC_EPT = 4;   // elements per thread (independent loads in flight per vector)
 
 __global__ __launch_bounds__(256) void k_lincomb(double2 *out, const double2 *base, double2 alpha,
                                                  const double2 *__restrict__ V, long long ldv, int nv, LcCoef co,
                                                  long long n) {
-    const long long stride = (long long)gridDim.x * 256;
-    for (long long idx = (long long)blockIdx.x * 256 + threadIdx.x; idx < n; idx += stride) {
-        double2 acc = make_double2(0.0, 0.0);
-        if (base) {
+    const long long start = (long long)blockIdx.x * (256 * LC_EPT) + threadIdx.x;
+    double2 acc[LC_EPT];
+    bool ok[LC_EPT];
+#pragma unroll
+    for (int e = 0; e < LC_EPT; ++e) {
+        const long long idx = start + (long long)e * 256;
+        ok[e] = idx < n;
+        acc[e] = make_double2(0.0, 0.0);
+        if (base && ok[e]) {
             double2 b = base[idx];
-            acc.x = alpha.x * b.x - alpha.y * b.y;
-            acc.y = alpha.x * b.y + alpha.y * b.x;
+            acc[e].x = alpha.x * b.x - alpha.y * b.y;
+            acc[e].y = alpha.x * b.y + alpha.y * b.x;
         }
-        for (int i = 0; i < nv; ++i) {
-            double2 v = V[(long long)i * ldv + idx];
-            double2 c = co.c[i];
-            acc.x += c.x * v.x - c.y * v.y;
-            acc.y += c.x * v.y + c.y * v.x;
+    }
+    for (int i = 0; i < nv; ++i) {
+        const double2 *vi = V + (long long)i * ldv;
+        const double2 c = co.c[i];
+        double2 v[LC_EPT];
+#pragma unroll
+        for (int e = 0; e < LC_EPT; ++e) {
+            const long long idx = start + (long long)e * 256;
+            v[e] = ok[e] ? vi[idx] : make_double2(0.0, 0.0);
         }
-        out[idx] = acc;
+#pragma unroll
+        for (int e = 0; e < LC_EPT; ++e) {
+            acc[e].x += c.x * v[e].x - c.y * v[e].y;
+            acc[e].y += c.x * v[e].y + c.y * v[e].x;
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < LC_EPT; ++e) {
+        const long long idx = start + (long long)e * 256;
+        if (ok[e]) out[idx] = acc[e];
     }
 }
 
@@ -121,9 +168,8 @@ hipError_t launch_dots(const double2 *V, long long ldv, int nv, const double2 *w
 
 hipError_t launch_lincomb(double2 *out, const double2 *base, double2 alpha, const double2 *V, long long ldv, int nv,
                           const double2 *coef, long long n, hipStream_t s) {
-    long long want = (n + 255) / 256;
-    int grid = (int)(want < 8192 ? want : 8192);
-    if (grid < 1) grid = 1;
+    long long grid_ll = (n + 256 * LC_EPT - 1) / (256 * LC_EPT);
+    int grid = (int)(grid_ll < 1 ? 1 : grid_ll);
     int done = 0;
     do {
         int cnt = nv - done < LC_MAX ? nv - done : LC_MAX;
