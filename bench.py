@@ -8,7 +8,8 @@ closure on all faces. Every input is synthetic and seeded.
 
 One step = one complete solve to ||F - A x|| <= 1e-8 ||F|| from x = 0 with inputs resident in HBM:
   * headline form: FGMRES(50) in FP64 with the EigT preconditioner in complex FP32 on MFMA;
-  * reference form: plain right-preconditioned GMRES(50) with the EigT preconditioner in FP64.
+  * reference form: plain right-preconditioned GMRES(50) with the EigT preconditioner in FP64;
+  * the PFFT preconditioner (second path) in the same two forms.
 value = unknowns x iterations / s of the headline form; ms_per_step = its time-to-solution.
 
 Prints one JSON line. Per-kernel device times come from HIP events recorded on the solve's stream over the
@@ -36,7 +37,8 @@ KCLASS = {
     "tridiag32": ("hbm", "GB/s", PEAK["hbm_GBps"]),
     "dots": ("hbm", "GB/s", PEAK["hbm_GBps"]),
     "lincomb": ("hbm", "GB/s", PEAK["hbm_GBps"]),
-    "pfft": ("mfma", "TFLOP/s", PEAK["fp32_TFLOPs"]),
+    "sine": ("mfma", "TFLOP/s", None),      # peak by the form's precision (see kernel_table)
+    "ring": ("hbm", "GB/s", PEAK["hbm_GBps"]),
 }
 
 
@@ -44,10 +46,12 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_table(prof):
+def kernel_table(prof, fp32=False):
     out = {}
     for name, v in prof.items():
         bound, unit, peak = KCLASS[name]
+        if peak is None:
+            peak = PEAK["fp32_TFLOPs"] if fp32 else PEAK["fp64_TFLOPs"]
         avg_ms = v["ms"] / v["launches"]
         rate = v["work"] / (v["ms"] * 1e-3)
         achieved = rate / (1e9 if unit == "GB/s" else 1e12)
@@ -95,7 +99,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=256, help="grid points per axis (256 is the benchmark workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="fp32_eigt_fgmres,fp64_eigt_gmres")
+    ap.add_argument("--forms", default="fp32_eigt_fgmres,fp64_eigt_gmres,fp32_pfft_fgmres,fp64_pfft_gmres")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run three plain 256 MiB device-to-device copies (reference dispatches for scaling "
                          "hardware byte counters)")
@@ -140,6 +144,8 @@ def main():
         "fp32_eigt_fgmres": dict(m=50, flexible=True, prec_fp32=True, prec="eigt"),
         "fp64_eigt_gmres": dict(m=50, flexible=False, prec_fp32=False, prec="eigt"),
         "fp64_eigt_fgmres": dict(m=50, flexible=True, prec_fp32=False, prec="eigt"),
+        "fp32_pfft_fgmres": dict(m=50, flexible=True, prec_fp32=True, prec="pfft"),
+        "fp64_pfft_gmres": dict(m=50, flexible=False, prec_fp32=False, prec="pfft"),
     }
     forms = {}
     for name in args.forms.split(","):
@@ -164,7 +170,7 @@ def main():
                            unknowns_iters_per_s=unknowns * iters / dt, relres_true=infos[-1]["relres_true"],
                            converged=all(i["converged"] for i in infos),
                            phase_ms=dict((k, round(v, 3)) for k, v in infos[-1]["t_ms"].items()),
-                           kernels=kernel_table(prof))
+                           kernels=kernel_table(prof, fp32=kw["prec_fp32"]))
         log(f"{name}: {forms[name]['ms_per_solve']} ms/solve, {forms[name]['iters']} iterations, "
             f"{forms[name]['unknowns_iters_per_s']:.3e} unknowns*it/s")
     head = "fp32_eigt_fgmres" if "fp32_eigt_fgmres" in forms else next(iter(forms))

@@ -146,8 +146,9 @@ typedef enum {
     HELM_K_TRIDIAG32 = 6,  /* z-tridiagonal solves, FP32                                                     */
     HELM_K_DOTS = 7,       /* Krylov block inner products + norm (both reduction stages)                     */
     HELM_K_LINCOMB = 8,    /* Krylov linear combinations (orthogonalisation update, x += Z y, restart)       */
-    HELM_K_PFFT = 9,       /* PFFT sine transforms and boundary corrections                                  */
-    HELM_K_COUNT = 10
+    HELM_K_PFFT = 9,       /* PFFT sine transforms (MFMA GEMMs against the real sine matrix)                 */
+    HELM_K_RING = 10,      /* PFFT face-only transforms (restricted inverse, sparse forward)                  */
+    HELM_K_COUNT = 11
 } helm_kernel_class;
 
 /* Per-kernel device timing. With on = 1 every kernel the context launches is bracketed by HIP events on the

@@ -112,16 +112,128 @@ helm_status eigt_apply(Ctx &c, const double2 *y, double2 *z, bool fp32) {
     if (!fp32) {
         HIP_TRY(timed(c, HELM_K_GEMM_X64, gemm_flops(dx), [&] { return launch_gemm_z64(dx, y, c.BxF, c.t1, c.stream); }));
         HIP_TRY(timed(c, HELM_K_GEMM_Y64, gemm_flops(dy), [&] { return launch_gemm_z64(dy, c.AyF, c.t1, c.t2, c.stream); }));
-        HIP_TRY(timed(c, HELM_K_TRIDIAG64, 32.0 * c.n, [&] { return launch_tridiag_z64(c.t2, c.cp, c.dxe, c.dye, c.nx, c.ny, c.nz, c.ax, c.ay, c.c0, gz, scale, c.stream); }));
+        HIP_TRY(timed(c, HELM_K_TRIDIAG64, 32.0 * c.n, [&] { return launch_tridiag_z64(c.t2, c.t2, c.cp, c.dxe, c.dye, c.nx, c.ny, c.nz, c.ax, c.ay, c.c0, gz, scale, c.stream); }));
         HIP_TRY(timed(c, HELM_K_GEMM_Y64, gemm_flops(dy), [&] { return launch_gemm_z64(dy, c.AyI, c.t2, c.t1, c.stream); }));
         HIP_TRY(timed(c, HELM_K_GEMM_X64, gemm_flops(dx), [&] { return launch_gemm_z64(dx, c.t1, c.BxI, z, c.stream); }));
     } else {
         ST_TRY(ensure_fp32_work(c));
         HIP_TRY(timed(c, HELM_K_GEMM_X32, gemm_flops(dx), [&] { return launch_gemm_z32_in64(dx, y, c.BxF32, c.t1f, c.stream); }));
         HIP_TRY(timed(c, HELM_K_GEMM_Y32, gemm_flops(dy), [&] { return launch_gemm_z32(dy, c.AyF32, c.t1f, c.t2f, c.stream); }));
-        HIP_TRY(timed(c, HELM_K_TRIDIAG32, 16.0 * c.n, [&] { return launch_tridiag_z32(c.t2f, c.cpf, c.dxe, c.dye, c.nx, c.ny, c.nz, c.ax, c.ay, c.c0, gz, scale, c.stream); }));
+        HIP_TRY(timed(c, HELM_K_TRIDIAG32, 16.0 * c.n, [&] { return launch_tridiag_z32(c.t2f, c.t2f, c.cpf, c.dxe, c.dye, c.nx, c.ny, c.nz, c.ax, c.ay, c.c0, gz, scale, c.stream); }));
         HIP_TRY(timed(c, HELM_K_GEMM_Y32, gemm_flops(dy), [&] { return launch_gemm_z32(dy, c.AyI32, c.t2f, c.t1f, c.stream); }));
         HIP_TRY(timed(c, HELM_K_GEMM_X32, gemm_flops(dx), [&] { return launch_gemm_z32_out64(dx, c.t1f, c.BxI32, z, c.stream); }));
+    }
+    return HELM_OK;
+}
+
+// ---------------------------------------------------------------------------------------------------------
+// PFFT (Sec. 4.2, eq. PFFT_SOLVER), zeta = 1:
+//   Step 1  Theta = (A_p^F)^{-1} Y: sine transforms in x and y (MFMA GEMMs against the real sine matrix),
+//           z-solves with the Dirichlet eigenvalues, Theta evaluated on the faces only (restricted inverse).
+//   Step 2  W = A_p^{-1} (A_p^F - A_p) Theta on the faces: sparse forward EigT transform of the face data,
+//           z-solves with the absorbing eigenvalues, restricted inverse EigT transform.
+//   Step 3  U = (A_p^F)^{-1} [Y + (A_p^F - A_p)(Theta + W)]: the sine transform of Y from Step 1 plus the sparse
+//           forward sine transform of the face correction, z-solves, full inverse sine transforms.
+// ---------------------------------------------------------------------------------------------------------
+
+std::vector<cd> sine_matrix(int n) {
+    std::vector<cd> S((size_t)n * n);
+    const double h = 1.0 / (n + 1), sc = std::sqrt(2.0 * h);
+    const double pi = 3.14159265358979323846;
+    for (int i = 0; i < n; ++i)
+        for (int l = 0; l < n; ++l) S[(size_t)i * n + l] = sc * std::sin(pi * h * (i + 1) * (l + 1));
+    return S;
+}
+
+template <typename CT> helm_status upload_one(Ctx &c, const std::vector<cd> &M, int n, bool transpose, CT **d) {
+    std::vector<CT> hbuf((size_t)n * n);
+    for (int r = 0; r < n; ++r)
+        for (int k = 0; k < n; ++k) {
+            cd v = transpose ? M[(size_t)k * n + r] : M[(size_t)r * n + k];
+            hbuf[(size_t)r * n + k].x = (decltype(hbuf[0].x))v.real();
+            hbuf[(size_t)r * n + k].y = (decltype(hbuf[0].x))v.imag();
+        }
+    ST_TRY(dalloc(c, d, (size_t)n * n));
+    HIP_TRY(hipMemcpy(*d, hbuf.data(), hbuf.size() * sizeof(CT), hipMemcpyHostToDevice));
+    return HELM_OK;
+}
+
+template <typename CT> helm_status build_pfft_mats(Ctx &c, PfftMats<CT> &m) {
+    std::vector<cd> Sx = sine_matrix(c.nx), Sy = sine_matrix(c.ny);
+    ST_TRY(upload_one(c, Sx, c.nx, false, &m.Sx));
+    ST_TRY(upload_one(c, Sy, c.ny, false, &m.Sy));
+    ST_TRY(upload_one(c, c.hVxi, c.nx, false, &m.Vxi));
+    ST_TRY(upload_one(c, c.hVx, c.nx, false, &m.Vx));
+    ST_TRY(upload_one(c, c.hVyi, c.ny, true, &m.VyiT));
+    ST_TRY(upload_one(c, c.hVy, c.ny, true, &m.VyT));
+    ST_TRY(dalloc(c, &m.yhat, (size_t)c.n));
+    size_t ring = (size_t)c.nz * (2 * c.nx + 2 * c.ny);
+    ST_TRY(dalloc(c, &m.ringT, ring));
+    ST_TRY(dalloc(c, &m.ringW, ring));
+    return HELM_OK;
+}
+
+helm_status ensure_pfft(Ctx &c, bool fp32) {
+    if (c.nx > 256 || c.ny > 256) {
+        c.err = "the PFFT preconditioner supports N_x, N_y <= 256";
+        return HELM_EUNSUPPORTED;
+    }
+    if (!c.pfft) {
+        c.pfft = new PfftPlan();
+        std::vector<double2> fx(c.nx), fy(c.ny);
+        const double pi = 3.14159265358979323846;
+        for (int i = 0; i < c.nx; ++i) fx[i] = make_double2(2.0 * std::cos(pi * (i + 1) / (c.nx + 1)), 0.0);
+        for (int j = 0; j < c.ny; ++j) fy[j] = make_double2(2.0 * std::cos(pi * (j + 1) / (c.ny + 1)), 0.0);
+        ST_TRY(dalloc(c, &c.pfft->dFx, (size_t)c.nx));
+        ST_TRY(dalloc(c, &c.pfft->dFy, (size_t)c.ny));
+        HIP_TRY(hipMemcpy(c.pfft->dFx, fx.data(), fx.size() * sizeof(double2), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(c.pfft->dFy, fy.data(), fy.size() * sizeof(double2), hipMemcpyHostToDevice));
+        ST_TRY(build_pfft_mats(c, c.pfft->m64));
+    }
+    if (fp32 && !c.pfft->has32) {
+        ST_TRY(build_pfft_mats(c, c.pfft->m32));
+        c.pfft->has32 = true;
+    }
+    return HELM_OK;
+}
+
+helm_status pfft_apply(Ctx &c, const double2 *y, double2 *z, bool fp32) {
+    ST_TRY(ensure_pfft(c, fp32));
+    GemmDesc dx = desc_x(c), dy = desc_y(c);
+    PfftPlan &P = *c.pfft;
+    const double2 gz = d2(c.gamma[2]);
+    const double hz2 = c.hz * c.hz;
+    const double2 ex = d2(-c.ax * c.gamma[0]), ey = d2(-c.ay * c.gamma[1]);
+    const int nx = c.nx, ny = c.ny, nz = c.nz;
+    // the same z-systems with the Dirichlet eigenvalues in x and y (A_p^F) or the absorbing ones (A_p)
+    const double ring_work = 16.0 * nz * (2.0 * nx + 2.0 * ny);
+    if (!fp32) {
+        auto &m = P.m64;
+        HIP_TRY(timed(c, HELM_K_PFFT, 4.0 * dx.M * (double)dx.N * dx.K, [&] { return launch_gemm_z64(dx, y, m.Sx, c.t1, c.stream, 2); }));
+        HIP_TRY(timed(c, HELM_K_PFFT, 4.0 * dy.M * (double)dy.N * dy.K * dy.batch, [&] { return launch_gemm_z64(dy, m.Sy, c.t1, m.yhat, c.stream, 1); }));
+        HIP_TRY(timed(c, HELM_K_TRIDIAG64, 32.0 * c.n, [&] { return launch_tridiag_z64(m.yhat, c.t2, c.cp, P.dFx, P.dFy, nx, ny, nz, c.ax, c.ay, c.c0, gz, hz2, c.stream); }));
+        HIP_TRY(timed(c, HELM_K_RING, 16.0 * c.n + ring_work, [&] { return launch_ring_inverse_z64(c.t2, m.ringT, m.Sy, m.Sy, m.Sx, m.Sx, nx, ny, nz, c.stream); }));
+        HIP_TRY(timed(c, HELM_K_RING, 16.0 * c.n + ring_work, [&] { return launch_ring_forward_z64(m.ringT, nullptr, nullptr, 0.0, c.t2, c.AyF, m.VyiT, m.Vxi, c.BxF, ex, ey, nx, ny, nz, c.stream); }));
+        HIP_TRY(timed(c, HELM_K_TRIDIAG64, 32.0 * c.n, [&] { return launch_tridiag_z64(c.t2, c.t2, c.cp, c.dxe, c.dye, nx, ny, nz, c.ax, c.ay, c.c0, gz, 1.0, c.stream); }));
+        HIP_TRY(timed(c, HELM_K_RING, 16.0 * c.n + ring_work, [&] { return launch_ring_inverse_z64(c.t2, m.ringW, c.AyI, m.VyT, m.Vx, c.BxI, nx, ny, nz, c.stream); }));
+        HIP_TRY(timed(c, HELM_K_RING, 32.0 * c.n + 2 * ring_work, [&] { return launch_ring_forward_z64(m.ringT, m.ringW, m.yhat, hz2, c.t2, m.Sy, m.Sy, m.Sx, m.Sx, ex, ey, nx, ny, nz, c.stream); }));
+        HIP_TRY(timed(c, HELM_K_TRIDIAG64, 32.0 * c.n, [&] { return launch_tridiag_z64(c.t2, c.t2, c.cp, P.dFx, P.dFy, nx, ny, nz, c.ax, c.ay, c.c0, gz, 1.0, c.stream); }));
+        HIP_TRY(timed(c, HELM_K_PFFT, 4.0 * dy.M * (double)dy.N * dy.K * dy.batch, [&] { return launch_gemm_z64(dy, m.Sy, c.t2, c.t1, c.stream, 1); }));
+        HIP_TRY(timed(c, HELM_K_PFFT, 4.0 * dx.M * (double)dx.N * dx.K, [&] { return launch_gemm_z64(dx, c.t1, m.Sx, z, c.stream, 2); }));
+    } else {
+        ST_TRY(ensure_fp32_work(c));
+        auto &m = P.m32;
+        HIP_TRY(timed(c, HELM_K_PFFT, 4.0 * dx.M * (double)dx.N * dx.K, [&] { return launch_gemm_z32_in64(dx, y, m.Sx, c.t1f, c.stream, 2); }));
+        HIP_TRY(timed(c, HELM_K_PFFT, 4.0 * dy.M * (double)dy.N * dy.K * dy.batch, [&] { return launch_gemm_z32(dy, m.Sy, c.t1f, m.yhat, c.stream, 1); }));
+        HIP_TRY(timed(c, HELM_K_TRIDIAG32, 16.0 * c.n, [&] { return launch_tridiag_z32(m.yhat, c.t2f, c.cpf, P.dFx, P.dFy, nx, ny, nz, c.ax, c.ay, c.c0, gz, hz2, c.stream); }));
+        HIP_TRY(timed(c, HELM_K_RING, 8.0 * c.n + ring_work / 2, [&] { return launch_ring_inverse_z32(c.t2f, m.ringT, m.Sy, m.Sy, m.Sx, m.Sx, nx, ny, nz, c.stream); }));
+        HIP_TRY(timed(c, HELM_K_RING, 8.0 * c.n + ring_work / 2, [&] { return launch_ring_forward_z32(m.ringT, nullptr, nullptr, 0.0, c.t2f, c.AyF32, m.VyiT, m.Vxi, c.BxF32, ex, ey, nx, ny, nz, c.stream); }));
+        HIP_TRY(timed(c, HELM_K_TRIDIAG32, 16.0 * c.n, [&] { return launch_tridiag_z32(c.t2f, c.t2f, c.cpf, c.dxe, c.dye, nx, ny, nz, c.ax, c.ay, c.c0, gz, 1.0, c.stream); }));
+        HIP_TRY(timed(c, HELM_K_RING, 8.0 * c.n + ring_work / 2, [&] { return launch_ring_inverse_z32(c.t2f, m.ringW, c.AyI32, m.VyT, m.Vx, c.BxI32, nx, ny, nz, c.stream); }));
+        HIP_TRY(timed(c, HELM_K_RING, 16.0 * c.n + ring_work, [&] { return launch_ring_forward_z32(m.ringT, m.ringW, m.yhat, hz2, c.t2f, m.Sy, m.Sy, m.Sx, m.Sx, ex, ey, nx, ny, nz, c.stream); }));
+        HIP_TRY(timed(c, HELM_K_TRIDIAG32, 16.0 * c.n, [&] { return launch_tridiag_z32(c.t2f, c.t2f, c.cpf, P.dFx, P.dFy, nx, ny, nz, c.ax, c.ay, c.c0, gz, 1.0, c.stream); }));
+        HIP_TRY(timed(c, HELM_K_PFFT, 4.0 * dy.M * (double)dy.N * dy.K * dy.batch, [&] { return launch_gemm_z32(dy, m.Sy, c.t2f, c.t1f, c.stream, 1); }));
+        HIP_TRY(timed(c, HELM_K_PFFT, 4.0 * dx.M * (double)dx.N * dx.K, [&] { return launch_gemm_z32_out64(dx, c.t1f, m.Sx, z, c.stream, 2); }));
     }
     return HELM_OK;
 }
@@ -132,10 +244,7 @@ helm_status precond(Ctx &c, const double2 *y, double2 *z, int kind, int fp32) {
         if (y != z) HIP_TRY(hipMemcpyAsync(z, y, (size_t)c.n * sizeof(double2), hipMemcpyDeviceToDevice, c.stream));
         return HELM_OK;
     }
-    if (kind == HELM_PREC_PFFT) {
-        c.err = "PFFT preconditioner is not available in this build";
-        return HELM_EUNSUPPORTED;
-    }
+    if (kind == HELM_PREC_PFFT) return pfft_apply(c, y, z, fp32 != 0);
     c.err = "unknown preconditioner kind";
     return HELM_EINVAL;
 }
@@ -204,7 +313,8 @@ long long helm_size(const helm_ctx *ctx) { return ctx ? ctx->c.n : 0; }
 
 const char *helm_profile_name(int cls) {
     static const char *names[HELM_K_COUNT] = {"matvec", "gemm_x64", "gemm_y64", "gemm_x32", "gemm_y32",
-                                              "tridiag64", "tridiag32", "dots", "lincomb", "pfft"};
+                                              "tridiag64", "tridiag32", "dots", "lincomb", "sine",
+                                              "ring"};
     return (cls >= 0 && cls < HELM_K_COUNT) ? names[cls] : "";
 }
 
@@ -258,6 +368,8 @@ void helm_destroy(helm_ctx *ctx) {
     for (void *p : c.allocs) hipFree(p);
     c.allocs.clear();
     if (c.kw.red_host) hipHostFree(c.kw.red_host);
+    delete c.pfft;
+    c.pfft = nullptr;
     hipSetDevice(cur);
     delete ctx;
 }
@@ -354,6 +466,7 @@ helm_status helm_setup(helm_ctx **out, helm_grid g, const double h[3], const dou
     if (!eig_lambda_bar(c.nx, c.gamma[0], dxv, Vx, Vxi, c.err)) return bail(HELM_ENUMERIC);
     if (c.ny == c.nx && c.gamma[1] == c.gamma[0]) { dyv = dxv; Vy = Vx; Vyi = Vxi; }
     else if (!eig_lambda_bar(c.ny, c.gamma[1], dyv, Vy, Vyi, c.err)) return bail(HELM_ENUMERIC);
+    c.hVx = Vx; c.hVxi = Vxi; c.hVy = Vy; c.hVyi = Vyi;
     // x-transform uses the transposed matrices as the B operand; y-transform uses them as the A operand
     if ((st = upload_matrix(c, Vxi, c.nx, true, &c.BxF, &c.BxF32)) != HELM_OK) return bail(st);
     if ((st = upload_matrix(c, Vx, c.nx, true, &c.BxI, &c.BxI32)) != HELM_OK) return bail(st);

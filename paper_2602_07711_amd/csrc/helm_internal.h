@@ -41,7 +41,21 @@ struct GemmDesc {
     int batch;
 };
 
-struct PfftPlan;   // PFFT second path (device data)
+// PFFT second path (Sec. 4.2): sine matrices, Dirichlet eigenvalues, the plain/transposed eigenvector
+// matrices the thin ring transforms need, and work buffers. FP64 and FP32 copies.
+template <typename CT> struct PfftMats {
+    CT *Sx = nullptr, *Sy = nullptr;             // orthonormal sine matrices (symmetric; imaginary part 0)
+    CT *Vxi = nullptr, *Vx = nullptr;            // V_x^{-1}, V_x row-major (the transposes are BxF, BxI)
+    CT *VyiT = nullptr, *VyT = nullptr;          // transposes of V_y^{-1}, V_y (the plain ones are AyF, AyI)
+    CT *yhat = nullptr;                          // sine transform of the input (reused in step 3)
+    CT *ringT = nullptr, *ringW = nullptr;       // face values of Theta and W, (2 Nx + 2 Ny) per slice
+};
+struct PfftPlan {
+    double2 *dFx = nullptr, *dFy = nullptr;      // Dirichlet eigenvalues 2 cos(pi i/(N+1))
+    PfftMats<double2> m64;
+    PfftMats<float2> m32;
+    bool has32 = false;
+};
 
 struct KrylovWork {
     int m = 0;
@@ -84,6 +98,7 @@ struct Ctx {
     float2 *t1f = nullptr, *t2f = nullptr, *cpf = nullptr;
 
     PfftPlan *pfft = nullptr;
+    std::vector<cd> hVx, hVxi, hVy, hVyi;        // host copies of the eigenvector matrices (PFFT plan build)
     KrylovWork kw;
     std::vector<void *> allocs;  // everything to free
 
@@ -142,15 +157,29 @@ hipError_t launch_matvec(const StencilParams &p, const double2 *x, const double 
 hipError_t launch_rhs(const StencilParams &p, const double2 *f_halo, const double *k2, const double4 *fld,
                       double h3[3], double2 *F, hipStream_t s);
 
-hipError_t launch_gemm_z64(const GemmDesc &d, const double2 *A, const double2 *B, double2 *C, hipStream_t s);
-hipError_t launch_gemm_z32(const GemmDesc &d, const float2 *A, const float2 *B, float2 *C, hipStream_t s);
-hipError_t launch_gemm_z32_in64(const GemmDesc &d, const double2 *A, const float2 *B, float2 *C, hipStream_t s);
-hipError_t launch_gemm_z32_out64(const GemmDesc &d, const float2 *A, const float2 *B, double2 *C, hipStream_t s);
+// rw: 0 = both operands complex, 1 = A real (imaginary parts ignored), 2 = B real
+hipError_t launch_gemm_z64(const GemmDesc &d, const double2 *A, const double2 *B, double2 *C, hipStream_t s, int rw = 0);
+hipError_t launch_gemm_z32(const GemmDesc &d, const float2 *A, const float2 *B, float2 *C, hipStream_t s, int rw = 0);
+hipError_t launch_gemm_z32_in64(const GemmDesc &d, const double2 *A, const float2 *B, float2 *C, hipStream_t s,
+                                int rw = 0);
+hipError_t launch_gemm_z32_out64(const GemmDesc &d, const float2 *A, const float2 *B, double2 *C, hipStream_t s,
+                                 int rw = 0);
 
-hipError_t launch_tridiag_z64(double2 *r, double2 *cp, const double2 *dx, const double2 *dy, int nx, int ny, int nz,
-                              double ax, double ay, double c0, double2 gz, double scale, hipStream_t s);
-hipError_t launch_tridiag_z32(float2 *r, float2 *cp, const double2 *dx, const double2 *dy, int nx, int ny, int nz,
-                              double ax, double ay, double c0, double2 gz, double scale, hipStream_t s);
+// `in` (may equal r) supplies the right-hand side; the solution is written to r.
+hipError_t launch_tridiag_z64(const double2 *in, double2 *r, double2 *cp, const double2 *dx, const double2 *dy, int nx,
+                              int ny, int nz, double ax, double ay, double c0, double2 gz, double scale, hipStream_t s);
+hipError_t launch_ring_inverse_z64(const double2 *Xh, double2 *ring, const double2 *Vy, const double2 *VyT,
+                                   const double2 *Vx, const double2 *VxT, int nx, int ny, int nz, hipStream_t s);
+hipError_t launch_ring_inverse_z32(const float2 *Xh, float2 *ring, const float2 *Vy, const float2 *VyT,
+                                   const float2 *Vx, const float2 *VxT, int nx, int ny, int nz, hipStream_t s);
+hipError_t launch_ring_forward_z64(const double2 *ra, const double2 *rb, const double2 *base, double base_scale,
+                                   double2 *out, const double2 *Wy, const double2 *WyT, const double2 *Wx,
+                                   const double2 *WxT, double2 ex, double2 ey, int nx, int ny, int nz, hipStream_t s);
+hipError_t launch_ring_forward_z32(const float2 *ra, const float2 *rb, const float2 *base, double base_scale,
+                                   float2 *out, const float2 *Wy, const float2 *WyT, const float2 *Wx,
+                                   const float2 *WxT, double2 ex, double2 ey, int nx, int ny, int nz, hipStream_t s);
+hipError_t launch_tridiag_z32(const float2 *in, float2 *r, float2 *cp, const double2 *dx, const double2 *dy, int nx,
+                              int ny, int nz, double ax, double ay, double c0, double2 gz, double scale, hipStream_t s);
 
 // Krylov helpers
 int dots_blocks(long long n);

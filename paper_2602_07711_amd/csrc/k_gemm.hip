@@ -52,7 +52,7 @@ template <typename TC, typename T> __device__ __forceinline__ TC pack(T re, T im
     return r;
 }
 
-template <typename TA, typename TB, typename TC, typename T, int BM, int BN, int BK>
+template <typename TA, typename TB, typename TC, typename T, int BM, int BN, int BK, int RW>
 __global__ __launch_bounds__(256) void k_zgemm(const TA *__restrict__ A, const TB *__restrict__ B, TC *__restrict__ C,
                                                GemmDesc d) {
     typedef typename cplx<T>::t CT;
@@ -81,7 +81,9 @@ __global__ __launch_bounds__(256) void k_zgemm(const TA *__restrict__ A, const T
     const int lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
 
-    constexpr bool G3 = sizeof(T) == 4;   // 3M form for FP32, 4M for FP64
+    // RW = 1: A is real, RW = 2: B is real (the sine matrix of the PFFT transforms); then each complex MAC
+    // needs two real products. Otherwise 3M for FP32 and 4M for FP64.
+    constexpr bool G3 = sizeof(T) == 4 && RW == 0;
     constexpr int NS = G3 ? 3 : 2;
     ACC t[NS][FM][FN];
 #pragma unroll
@@ -138,7 +140,23 @@ __global__ __launch_bounds__(256) void k_zgemm(const TA *__restrict__ A, const T
             for (int i = 0; i < FM; ++i) fa[i] = sA[kk + kl][rowA + i * 16];
 #pragma unroll
             for (int j = 0; j < FN; ++j) fb[j] = sB[kk + kl][colB + j * 16];
-            if constexpr (G3) {
+            if constexpr (RW == 1) {
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+#pragma unroll
+                    for (int j = 0; j < FN; ++j) {
+                        t[0][i][j] = mfma(fa[i].x, fb[j].x, t[0][i][j]);
+                        t[1][i][j] = mfma(fa[i].x, fb[j].y, t[1][i][j]);
+                    }
+            } else if constexpr (RW == 2) {
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+#pragma unroll
+                    for (int j = 0; j < FN; ++j) {
+                        t[0][i][j] = mfma(fa[i].x, fb[j].x, t[0][i][j]);
+                        t[1][i][j] = mfma(fa[i].y, fb[j].x, t[1][i][j]);
+                    }
+            } else if constexpr (G3) {
                 T sa[FM], sb[FN];
 #pragma unroll
                 for (int i = 0; i < FM; ++i) sa[i] = fa[i].x + fa[i].y;
@@ -197,28 +215,35 @@ __global__ __launch_bounds__(256) void k_zgemm(const TA *__restrict__ A, const T
 }
 
 template <typename TA, typename TB, typename TC, typename T>
-hipError_t launch(const GemmDesc &d, const TA *A, const TB *B, TC *C, hipStream_t s) {
+hipError_t launch(const GemmDesc &d, const TA *A, const TB *B, TC *C, hipStream_t s, int rw = 0) {
     constexpr int BM = 64, BN = 64, BK = 16;
     long long tiles = (long long)((d.M + BM - 1) / BM) * ((d.N + BN - 1) / BN) * d.batch;
     long long grid = 8 * ((tiles + 7) / 8);
     if (tiles == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_zgemm<TA, TB, TC, T, BM, BN, BK>), dim3((unsigned)grid), dim3(256), 0, s, A, B, C, d);
+    if (rw == 1)
+        hipLaunchKernelGGL((k_zgemm<TA, TB, TC, T, BM, BN, BK, 1>), dim3((unsigned)grid), dim3(256), 0, s, A, B, C, d);
+    else if (rw == 2)
+        hipLaunchKernelGGL((k_zgemm<TA, TB, TC, T, BM, BN, BK, 2>), dim3((unsigned)grid), dim3(256), 0, s, A, B, C, d);
+    else
+        hipLaunchKernelGGL((k_zgemm<TA, TB, TC, T, BM, BN, BK, 0>), dim3((unsigned)grid), dim3(256), 0, s, A, B, C, d);
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_gemm_z64(const GemmDesc &d, const double2 *A, const double2 *B, double2 *C, hipStream_t s) {
-    return launch<double2, double2, double2, double>(d, A, B, C, s);
+hipError_t launch_gemm_z64(const GemmDesc &d, const double2 *A, const double2 *B, double2 *C, hipStream_t s, int rw) {
+    return launch<double2, double2, double2, double>(d, A, B, C, s, rw);
 }
-hipError_t launch_gemm_z32(const GemmDesc &d, const float2 *A, const float2 *B, float2 *C, hipStream_t s) {
-    return launch<float2, float2, float2, float>(d, A, B, C, s);
+hipError_t launch_gemm_z32(const GemmDesc &d, const float2 *A, const float2 *B, float2 *C, hipStream_t s, int rw) {
+    return launch<float2, float2, float2, float>(d, A, B, C, s, rw);
 }
-hipError_t launch_gemm_z32_in64(const GemmDesc &d, const double2 *A, const float2 *B, float2 *C, hipStream_t s) {
-    return launch<double2, float2, float2, float>(d, A, B, C, s);
+hipError_t launch_gemm_z32_in64(const GemmDesc &d, const double2 *A, const float2 *B, float2 *C, hipStream_t s,
+                                int rw) {
+    return launch<double2, float2, float2, float>(d, A, B, C, s, rw);
 }
-hipError_t launch_gemm_z32_out64(const GemmDesc &d, const float2 *A, const float2 *B, double2 *C, hipStream_t s) {
-    return launch<float2, float2, double2, float>(d, A, B, C, s);
+hipError_t launch_gemm_z32_out64(const GemmDesc &d, const float2 *A, const float2 *B, double2 *C, hipStream_t s,
+                                 int rw) {
+    return launch<float2, float2, double2, float>(d, A, B, C, s, rw);
 }
 
 }  // namespace helm

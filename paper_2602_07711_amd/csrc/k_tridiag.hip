@@ -7,8 +7,9 @@
 // Thomas elimination without pivoting: the eigenvalues of Lambda-bar lie in Im >= 0 for Im gamma >= 0, so
 // every pivot stays in the upper half plane and away from zero. One thread owns one line; consecutive
 // threads own consecutive i, so every access of a wavefront at a given l is one contiguous 64-element run.
-// The forward sweep writes the eliminated right-hand side in place and the reciprocal pivots to `cp`; the
-// backward sweep reads both. Loads are issued UNR levels ahead of use.
+// The forward sweep reads the right-hand side from `in` (which may be r itself), writes the eliminated
+// right-hand side to r and the reciprocal pivots to `cp`; the backward sweep reads both and overwrites r with
+// the solution. Loads are issued UNR levels ahead of use.
 #include "helm_internal.h"
 
 namespace helm {
@@ -42,7 +43,7 @@ template <typename CT> __device__ __forceinline__ CT crecip(CT a) {
 constexpr int UNR = 8;
 
 template <typename T>
-__global__ __launch_bounds__(64) void k_tridiag(typename c2<T>::t *__restrict__ r, typename c2<T>::t *__restrict__ cp,
+__global__ __launch_bounds__(64) void k_tridiag(const typename c2<T>::t *in, typename c2<T>::t *r, typename c2<T>::t *__restrict__ cp,
                                                 const double2 *__restrict__ dx, const double2 *__restrict__ dy, int nx,
                                                 int ny, int nz, double ax, double ay, double c0, double2 gz,
                                                 double scale) {
@@ -56,6 +57,7 @@ __global__ __launch_bounds__(64) void k_tridiag(typename c2<T>::t *__restrict__ 
     const CT g = mk<T, CT>((T)gz.x, (T)gz.y);
     const T sc = (T)scale;
     CT *rl = r + line;
+    const CT *il = in + line;
     CT *cl = cp + line;
 
     CT inv = mk<T, CT>(0, 0), dprev = mk<T, CT>(0, 0);
@@ -63,7 +65,7 @@ __global__ __launch_bounds__(64) void k_tridiag(typename c2<T>::t *__restrict__ 
         CT v[UNR];
 #pragma unroll
         for (int u = 0; u < UNR; ++u)
-            if (l0 + u < nz) v[u] = rl[(long long)(l0 + u) * lines];
+            if (l0 + u < nz) v[u] = il[(long long)(l0 + u) * lines];
 #pragma unroll
         for (int u = 0; u < UNR; ++u) {
             const int l = l0 + u;
@@ -100,19 +102,19 @@ __global__ __launch_bounds__(64) void k_tridiag(typename c2<T>::t *__restrict__ 
 
 }  // namespace
 
-hipError_t launch_tridiag_z64(double2 *r, double2 *cp, const double2 *dx, const double2 *dy, int nx, int ny, int nz,
-                              double ax, double ay, double c0, double2 gz, double scale, hipStream_t s) {
+hipError_t launch_tridiag_z64(const double2 *in, double2 *r, double2 *cp, const double2 *dx, const double2 *dy, int nx,
+                              int ny, int nz, double ax, double ay, double c0, double2 gz, double scale, hipStream_t s) {
     long long lines = (long long)nx * ny;
-    hipLaunchKernelGGL(k_tridiag<double>, dim3((unsigned)((lines + 63) / 64)), dim3(64), 0, s, r, cp, dx, dy, nx, ny,
-                       nz, ax, ay, c0, gz, scale);
+    hipLaunchKernelGGL(k_tridiag<double>, dim3((unsigned)((lines + 63) / 64)), dim3(64), 0, s, in, r, cp, dx, dy, nx,
+                       ny, nz, ax, ay, c0, gz, scale);
     return hipGetLastError();
 }
 
-hipError_t launch_tridiag_z32(float2 *r, float2 *cp, const double2 *dx, const double2 *dy, int nx, int ny, int nz,
-                              double ax, double ay, double c0, double2 gz, double scale, hipStream_t s) {
+hipError_t launch_tridiag_z32(const float2 *in, float2 *r, float2 *cp, const double2 *dx, const double2 *dy, int nx,
+                              int ny, int nz, double ax, double ay, double c0, double2 gz, double scale, hipStream_t s) {
     long long lines = (long long)nx * ny;
-    hipLaunchKernelGGL(k_tridiag<float>, dim3((unsigned)((lines + 63) / 64)), dim3(64), 0, s, r, cp, dx, dy, nx, ny,
-                       nz, ax, ay, c0, gz, scale);
+    hipLaunchKernelGGL(k_tridiag<float>, dim3((unsigned)((lines + 63) / 64)), dim3(64), 0, s, in, r, cp, dx, dy, nx,
+                       ny, nz, ax, ay, c0, gz, scale);
     return hipGetLastError();
 }
 

@@ -216,7 +216,7 @@ def helm_gmres_solve(ctx: Context, F: torch.Tensor, x: torch.Tensor | None = Non
     return x, out
 
 
-KERNEL_CLASSES = 10
+KERNEL_CLASSES = 11
 
 
 def helm_profile_enable(ctx: Context, on: bool = True):

@@ -253,3 +253,40 @@ def test_fullsize_sampled(name):
     print(name, info["iters"], info["relres_true"], np.abs(r).max() / np.linalg.norm(Fh))
     assert info["converged"]
     assert np.abs(r).max() <= 1.01e-10 * np.linalg.norm(Fh)
+
+
+@pytest.mark.parametrize("shape", [(12, 20, 70), (33, 33, 33), (9, 5, 7)])
+@pytest.mark.parametrize("fp32", [False, True])
+def test_pfft_precond_parity(shape, fp32):
+    """PFFT (Sec. 4.2) solves the same M z = y as EigT: compare with the oracle's EigT and with M z = y."""
+    h = H()
+    h3 = (1.0 / (shape[2] + 1), 1.0 / (shape[1] + 1), 1.0 / (shape[0] + 1))
+    k0 = 0.47 / h3[0]
+    k2 = np.full(tuple(s + 4 for s in shape), k0 * k0)
+    ctx = h.helm_setup(dev(k2), h3, 4, k0=k0, shape=shape)
+    y = cvec(int(np.prod(shape)), 14)
+    z = host(h.helm_precond_apply(ctx, dev(y), kind="pfft", fp32=fp32))
+    gs = tuple(op.gamma_abc(k0, hh) for hh in h3)
+    zr = pc.EigT(shape, h3, k0, gs).solve(y)
+    err = np.linalg.norm(z - zr) / np.linalg.norm(zr)
+    print(f"pfft {'fp32' if fp32 else 'fp64'} {shape} rel err {err:.3e}")
+    assert err <= (2e-4 if fp32 else 1e-11)
+    if not fp32:
+        zp = pc.PFFT(shape, h3, k0, gs).solve(y)
+        assert np.linalg.norm(z - zp) <= 1e-11 * np.linalg.norm(zp)
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+def test_solve_pfft_matches_sparse_lu(fp32):
+    h = H()
+    n, order = 20, 6
+    k0 = 0.47 * (n + 1)
+    hh, k2, f = _problem(order, n, k0)
+    ctx = h.helm_setup(dev(k2), hh, order, k0=k0)
+    F = h.helm_rhs(ctx, dev(f))
+    x, info = h.helm_gmres_solve(ctx, F, m=50, rtol=1e-10, prec="pfft", flexible=fp32, prec_fp32=fp32)
+    A, Fr = op.problem(order, k2, f, hh, k0)
+    xs = spla.splu(A.tocsc()).solve(Fr)
+    rel = np.linalg.norm(host(x) - xs) / np.linalg.norm(xs)
+    print("pfft solve", fp32, info["iters"], rel)
+    assert info["converged"] and rel <= 1e-8
