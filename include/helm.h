@@ -167,6 +167,39 @@ helm_status helm_profile_read(helm_ctx *ctx, int kernel_class, double *ms_total,
 /* Short name of a kernel class ("matvec", "gemm_x64", ...), or "" for an unknown class. */
 const char *helm_profile_name(int kernel_class);
 
+/* ---- Batched solves (many right-hand sides and/or many independent problems) ----
+ *
+ * A batch groups P FGMRES(m) solves with the EigT preconditioner. Problem p uses the operator and the
+ * eigen-data of contexts[p]; one context may appear several times (several right-hand sides, e.g. incident
+ * directions, on one medium), and different contexts may have different grid sizes and k0 (uneven problems).
+ * Every phase of an iteration (preconditioner transforms, z-solves, matvec, inner products, Givens updates,
+ * linear combinations) is one grouped launch over all problems, the GEMMs as one persistent launch striding
+ * over the tiles of every problem, and the Arnoldi/Givens/least-squares updates run on the device, so one
+ * whole restart cycle is a fixed launch sequence that is captured once in a hipGraph and replayed. Problems
+ * that have converged are skipped by every kernel. */
+typedef struct helm_batch helm_batch;
+
+/* Create a batch. All contexts must live on the current device, share the same order, and stay alive until
+ * helm_batch_destroy. m: restart length (1..128). prec_fp32: 1 = complex FP32 preconditioner.
+ * Allocates per problem (m+1) + m vectors (V, Z) of its size plus preconditioner work buffers, on a private
+ * stream of the batch. */
+helm_status helm_batch_create(helm_batch **batch, helm_ctx *const *contexts, int nprob, int m, int prec_fp32);
+
+/* Solve A_p x_p = F_p for every problem to ||F_p - A_p x_p|| <= rtol ||F_p|| or maxit iterations.
+ * F[p], x[p]: device vectors of problem p (complex128, n_p entries). x0_given = 1 starts from the x[p]
+ * contents, else from 0. use_graph = 1 captures one restart cycle in a hipGraph on the first call and replays
+ * it; 0 launches the same sequence directly. infos: NULL or an array of nprob. Work is ordered after prior
+ * work on the stream of contexts[0] and the call returns when the batch is done. Returns HELM_ENOCONV if any
+ * problem stopped at maxit. */
+helm_status helm_batch_solve(helm_batch *batch, const void *const *F, void *const *x, int x0_given, double rtol,
+                             int maxit, int use_graph, helm_solve_info *infos);
+
+/* Free the batch (not the contexts). NULL is allowed. */
+void helm_batch_destroy(helm_batch *batch);
+
+/* Message of the last failure of a batch, or of the last helm_batch_create failure when batch is NULL. */
+const char *helm_batch_last_error(const helm_batch *batch);
+
 /* Number of unknowns n = Nx*Ny*Nz of a context. */
 long long helm_size(const helm_ctx *ctx);
 

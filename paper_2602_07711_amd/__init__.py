@@ -4,6 +4,9 @@ The compute path lives in libhelm.so (C ABI, include/helm.h); `helm` is its ctyp
 """
 from .helm import (  # noqa: F401
     HelmError,
+    helm_batch_create,
+    helm_batch_destroy,
+    helm_batch_solve,
     helm_destroy,
     helm_eig1d,
     helm_gmres_solve,

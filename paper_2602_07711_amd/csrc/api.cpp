@@ -11,7 +11,6 @@
 
 using namespace helm;
 
-struct helm_ctx { Ctx c; };
 
 namespace {
 

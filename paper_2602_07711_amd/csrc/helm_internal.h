@@ -149,6 +149,41 @@ inline void prof_resolve(Ctx &c) {
     c.prof_pending.clear();
 }
 
+// ----- batched solves: per-problem descriptors and device-side GMRES state -----
+struct BProb {                    // constant during a batched solve
+    StencilParams sp;
+    const double *k2;
+    const double4 *fld;
+    const void *BxF, *BxI, *AyF, *AyI;     // eigenvector matrices (double2* or float2* by precision)
+    const double2 *dxe, *dye;
+    double ax, ay, c0, hz2;
+    double2 gz;
+    GemmDesc dx, dy;
+    double2 *V, *Z, *x;
+    const double2 *F;
+    void *t1, *t2, *cp;                    // preconditioner work (element type by precision)
+    double2 *part;                         // inner-product partials, nblk_dots * (m + 2)
+    long long n;
+    int nx, ny, nz, nblk_dots;
+};
+struct BState {                   // evolves on the device
+    double bnorm, beta, relres_est, relres_true;
+    double2 alpha;                // scale of the base vector in the next linear combination
+    int active;                   // 1 while the problem takes Arnoldi steps in the current cycle
+    int done;                     // converged or out of iterations
+    int converged, k, its, cycles, cancel, pad;
+};
+struct BParams { double rtol; int maxit; int m; };
+struct BArrays {                  // per-problem small arrays, problem p at p * stride
+    double2 *H;                   // (m+1) x m Hessenberg (rotated), row-major
+    double *cs;                   // m
+    double2 *sn, *g, *coef;       // m, m+1, m+1
+};
+struct BOffsets {                 // prefix sums of blocks/tiles per problem for each grouped launch
+    int *mv, *tri, *dot, *lc;     // np + 1 each
+    long long *gx, *gy;           // GEMM tiles of the x- and y-transforms
+};
+
 // ----- kernel launchers (defined in the .hip files); all enqueue on `s` and return hipError_t -----
 hipError_t launch_derived_fields(const double *k2_halo, int halo, double *k2, double4 *fld, const StencilParams &p,
                                  double h, hipStream_t s);
@@ -189,4 +224,23 @@ hipError_t launch_lincomb(double2 *out, const double2 *base, double2 alpha, cons
                           const double2 *coef, long long n, hipStream_t s);   // out = alpha base + sum coef_i V_i
 hipError_t launch_fill_zero(double2 *x, long long n, hipStream_t s);
 
+// grouped (batched) launches; see k_batch.hip
+struct BLaunch {
+    const BProb *P;               // device array of np descriptors
+    BState *st;                   // device array of np states
+    const BParams *prm;           // device
+    BArrays a;
+    BOffsets off;                 // device arrays
+    int np, m, order, fp32;
+    int tot_mv, tot_tri, tot_dot, tot_lc;       // total blocks per grouped launch
+    long long tot_gx, tot_gy;                   // total GEMM tiles
+    int gemm_grid;                              // persistent GEMM grid size
+};
+hipError_t bl_init(const BLaunch &L, hipStream_t s);                 // ||F||, state reset (outside graphs)
+hipError_t bl_zero_x(const BLaunch &L, hipStream_t s);
+hipError_t bl_cycle(const BLaunch &L, hipStream_t s);                // one restart cycle: restart + m steps + update
+hipError_t bl_restart(const BLaunch &L, hipStream_t s);              // the restart test alone
+
 }  // namespace helm
+
+struct helm_ctx { helm::Ctx c; };

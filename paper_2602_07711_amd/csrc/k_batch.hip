@@ -1,0 +1,396 @@
+// Grouped kernels of the batched FGMRES solve: every launch covers all problems of a batch (uneven sizes
+// included) through per-problem block or tile offsets, and every kernel skips problems that are not active.
+// The Arnoldi inner-product reduction, Givens rotations and the least-squares solve run on the device, so one
+// restart cycle (restart vector, m Arnoldi steps, x += Z y) is a fixed launch sequence that can be captured
+// once in a hipGraph and replayed.
+//
+// Per Arnoldi step j (the same for every problem): EigT preconditioner z_j = M^{-1} v_j (four grouped GEMMs,
+// the x- and y-transforms as one persistent launch each over all problems' tiles, and the grouped z-solves),
+// the shifted matvec y = v_j - A z_j, the block inner products V^H y and ||y||^2, the device Arnoldi step
+// (H column, Givens, residual estimate, stop test), and v_{j+1} = -(y - V h)/eta.
+#include "gemm_dev.h"
+#include "krylov_dev.h"
+#include "stencil_dev.h"
+#include "tridiag_dev.h"
+
+namespace helm {
+
+namespace {
+
+constexpr int BM = 64, BN = 64, BK = 16;
+
+__device__ __forceinline__ int find_prob(const int *off, int np, int b) {
+    int lo = 0, hi = np - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+__device__ __forceinline__ int find_prob64(const long long *off, int np, long long b) {
+    int lo = 0, hi = np - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// ---------------------------------------------------------------------------------------------- GEMMs
+// ROLE 0: x-forward  t1 = V_j  W_xF       ROLE 1: y-forward  t2 = W_yF t1
+// ROLE 2: y-inverse  t1 = W_yI t2         ROLE 3: x-inverse  Z_j = t1 W_xI
+template <int ROLE, typename T>
+__global__ __launch_bounds__(256) void k_b_gemm(const BProb *__restrict__ P, const BState *__restrict__ st,
+                                                const long long *__restrict__ toff, int np, int j) {
+    typedef typename cplx<T>::t CT;
+    const long long total = toff[np];
+    for (long long t = blockIdx.x; t < total; t += gridDim.x) {
+        const int p = find_prob64(toff, np, t);
+        if (!st[p].active) continue;
+        const BProb &q = P[p];
+        const long long lt = t - toff[p];
+        if (ROLE == 0)
+            gemm_tile<double2, CT, CT, T, BM, BN, BK, 0>(q.V + (long long)j * q.n, (const CT *)q.BxF, (CT *)q.t1, q.dx, lt);
+        else if (ROLE == 1)
+            gemm_tile<CT, CT, CT, T, BM, BN, BK, 0>((const CT *)q.AyF, (const CT *)q.t1, (CT *)q.t2, q.dy, lt);
+        else if (ROLE == 2)
+            gemm_tile<CT, CT, CT, T, BM, BN, BK, 0>((const CT *)q.AyI, (const CT *)q.t2, (CT *)q.t1, q.dy, lt);
+        else
+            gemm_tile<CT, CT, double2, T, BM, BN, BK, 0>((const CT *)q.t1, (const CT *)q.BxI, q.Z + (long long)j * q.n, q.dx, lt);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(64) void k_b_tridiag(const BProb *__restrict__ P, const BState *__restrict__ st,
+                                                  const int *__restrict__ off, int np) {
+    typedef typename c2<T>::t CT;
+    const int p = find_prob(off, np, blockIdx.x);
+    if (!st[p].active) return;
+    const BProb &q = P[p];
+    const long long line = (long long)(blockIdx.x - off[p]) * 64 + threadIdx.x;
+    if (line >= (long long)q.nx * q.ny) return;
+    tridiag_line<T>((const CT *)q.t2, (CT *)q.t2, (CT *)q.cp, q.dxe, q.dye, q.nx, q.ny, q.nz, q.ax, q.ay, q.c0, q.gz,
+                    q.hz2, line);
+}
+
+// ---------------------------------------------------------------------------------------------- matvec
+// mode 0: restart, V_0 = F - A x (problems not done); mode 1: step j, V_{j+1} = V_j - A Z_j (active problems)
+template <int ORDER>
+__global__ __launch_bounds__(256) void k_b_matvec(const BProb *__restrict__ P, const BState *__restrict__ st,
+                                                  const int *__restrict__ off, int np, int mode, int j) {
+    const int p = find_prob(off, np, blockIdx.x);
+    if (mode == 0 ? st[p].done : !st[p].active) return;
+    const BProb &q = P[p];
+    const int lb = blockIdx.x - off[p];
+    if (mode == 0)
+        matvec_tile<ORDER, true>(q.x, q.k2, q.fld, q.F, q.V, q.sp, lb);
+    else
+        matvec_tile<ORDER, true>(q.Z + (long long)j * q.n, q.k2, q.fld, q.V + (long long)j * q.n, q.V + (long long)(j + 1) * q.n,
+                                 q.sp, lb);
+}
+
+// ---------------------------------------------------------------------------------------------- inner products
+// mode 0: ||F||^2 (all problems); mode 1: ||V_0||^2 (not done); mode 2: V_{0..j}^H V_{j+1}, ||V_{j+1}||^2 (active)
+__global__ __launch_bounds__(256) void k_b_dots(const BProb *__restrict__ P, const BState *__restrict__ st,
+                                                const int *__restrict__ off, int np, int mode, int j) {
+    const int p = find_prob(off, np, blockIdx.x);
+    if (mode == 1 && st[p].done) return;
+    if (mode == 2 && !st[p].active) return;
+    const BProb &q = P[p];
+    const long long lb = blockIdx.x - off[p];
+    if (mode == 0) dots_chunk(nullptr, q.n, 0, q.F, q.n, q.part, lb);
+    else if (mode == 1) dots_chunk(nullptr, q.n, 0, q.V, q.n, q.part, lb);
+    else dots_chunk(q.V, q.n, j + 1, q.V + (long long)(j + 1) * q.n, q.n, q.part, lb);
+}
+
+// fixed-order block reduction of the partials of output t (nout outputs); result valid in thread 0
+__device__ double2 reduce_part(const double2 *part, int nblk, int nout, int t) {
+    __shared__ double sr[256], si[256];
+    const int tid = threadIdx.x;
+    double re = 0.0, im = 0.0;
+    for (int b = tid; b < nblk; b += 256) {
+        double2 v = part[(long long)b * nout + t];
+        re += v.x;
+        im += v.y;
+    }
+    __syncthreads();
+    sr[tid] = re;
+    si[tid] = im;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s) { sr[tid] += sr[tid + s]; si[tid] += si[tid + s]; }
+        __syncthreads();
+    }
+    return make_double2(sr[0], si[0]);
+}
+
+__device__ __forceinline__ double2 cmulb(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+__device__ __forceinline__ double cabs2(double2 a) { return hypot(a.x, a.y); }
+
+// one block per problem: ||F|| and a fresh state
+__global__ __launch_bounds__(256) void k_b_init(const BProb *__restrict__ P, BState *__restrict__ st, int np,
+                                                int m) {
+    const int p = blockIdx.x;
+    const BProb &q = P[p];
+    double2 r = reduce_part(q.part, q.nblk_dots, 1, 0);
+    if (threadIdx.x == 0) {
+        BState s{};
+        s.bnorm = sqrt(fmax(r.x, 0.0));
+        s.converged = s.bnorm == 0.0;
+        s.done = s.converged;
+        s.relres_true = 0.0;
+        s.alpha = make_double2(1.0, 0.0);
+        st[p] = s;
+    }
+}
+
+// one block per problem, after ||V_0||^2 of the restart vector: convergence test and the new cycle's g
+__global__ __launch_bounds__(256) void k_b_restart(const BProb *__restrict__ P, BState *__restrict__ st,
+                                                   BArrays a, const BParams *__restrict__ prm) {
+    const int p = blockIdx.x;
+    if (st[p].done) return;
+    const BProb &q = P[p];
+    const int m = prm->m;
+    double2 r = reduce_part(q.part, q.nblk_dots, 1, 0);
+    if (threadIdx.x != 0) return;
+    BState s = st[p];
+    s.beta = sqrt(fmax(r.x, 0.0));
+    s.relres_true = s.beta / s.bnorm;
+    s.k = 0;
+    s.active = 0;
+    if (!isfinite(s.beta)) {
+        s.done = 1;
+    } else if (s.beta <= prm->rtol * s.bnorm) {
+        s.converged = 1;
+        s.done = 1;
+    } else if (s.its >= prm->maxit) {
+        s.done = 1;
+    } else {
+        s.active = 1;
+        s.alpha = make_double2(1.0 / s.beta, 0.0);
+        double2 *g = a.g + (long long)p * (m + 1);
+        g[0] = make_double2(s.beta, 0.0);
+        for (int i = 1; i <= m; ++i) g[i] = make_double2(0.0, 0.0);
+    }
+    st[p] = s;
+}
+
+// one block per problem: reduce V^H y and ||y||^2, build column j of H (shifted Arnoldi: -h + e_j, eta),
+// apply the previous rotations, make the new one, update g, test convergence, and set the coefficients of
+// v_{j+1} = -(y - V h)/eta.
+__global__ __launch_bounds__(256) void k_b_arnoldi(const BProb *__restrict__ P, BState *__restrict__ st, BArrays a,
+                                                   const BParams *__restrict__ prm, int j) {
+    __shared__ double2 hv[130];
+    const int p = blockIdx.x;
+    if (!st[p].active) return;
+    const BProb &q = P[p];
+    const int m = prm->m;
+    const int nv = j + 1;
+    for (int t = 0; t <= nv; ++t) {
+        double2 r = reduce_part(q.part, q.nblk_dots, nv + 1, t);
+        if (threadIdx.x == 0) hv[t] = r;
+    }
+    if (threadIdx.x != 0) return;
+    BState s = st[p];
+    double2 *H = a.H + (long long)p * (m + 1) * m;
+    double *cs = a.cs + (long long)p * m;
+    double2 *sn = a.sn + (long long)p * m;
+    double2 *g = a.g + (long long)p * (m + 1);
+    double2 *coef = a.coef + (long long)p * (m + 1);
+    double hh = 0.0;
+    for (int i = 0; i <= j; ++i) hh += hv[i].x * hv[i].x + hv[i].y * hv[i].y;
+    const double ww = hv[nv].x;
+    double eta2 = ww - hh;
+    if (!(eta2 > 0.5 * ww)) s.cancel += 1;
+    const double eta = eta2 > 0.0 ? sqrt(eta2) : 0.0;
+    for (int i = 0; i <= j; ++i) H[(long long)i * m + j] = make_double2(-hv[i].x, -hv[i].y);
+    H[(long long)j * m + j].x += 1.0;
+    for (int i = 0; i < j; ++i) {
+        double2 x0 = H[(long long)i * m + j], x1 = H[(long long)(i + 1) * m + j];
+        double2 t0 = cmulb(sn[i], x1);
+        H[(long long)i * m + j] = make_double2(cs[i] * x0.x + t0.x, cs[i] * x0.y + t0.y);
+        double2 t1 = cmulb(cconj(sn[i]), x0);
+        H[(long long)(i + 1) * m + j] = make_double2(-t1.x + cs[i] * x1.x, -t1.y + cs[i] * x1.y);
+    }
+    {
+        double2 av = H[(long long)j * m + j];
+        double aa = cabs2(av);
+        if (eta == 0.0) { cs[j] = 1.0; sn[j] = make_double2(0.0, 0.0); }
+        else if (aa == 0.0) { cs[j] = 0.0; sn[j] = make_double2(1.0, 0.0); H[(long long)j * m + j] = make_double2(eta, 0.0); }
+        else {
+            double tt = hypot(aa, eta);
+            double2 ph = make_double2(av.x / aa, av.y / aa);
+            cs[j] = aa / tt;
+            sn[j] = make_double2(ph.x * eta / tt, ph.y * eta / tt);
+            H[(long long)j * m + j] = make_double2(ph.x * tt, ph.y * tt);
+        }
+        double2 gj = g[j];
+        double2 t1 = cmulb(cconj(sn[j]), gj);
+        g[j + 1] = make_double2(-t1.x, -t1.y);
+        g[j] = make_double2(cs[j] * gj.x, cs[j] * gj.y);
+    }
+    s.its += 1;
+    s.k = j + 1;
+    const double res = cabs2(g[j + 1]);
+    s.relres_est = res / s.bnorm;
+    if (eta == 0.0 || res <= prm->rtol * s.bnorm || s.its >= prm->maxit || j + 1 == m || !isfinite(res)) {
+        s.active = 0;
+    } else {
+        for (int i = 0; i <= j; ++i) coef[i] = make_double2(hv[i].x / eta, hv[i].y / eta);
+        s.alpha = make_double2(-1.0 / eta, 0.0);
+    }
+    st[p] = s;
+}
+
+// one thread per problem: y = R^{-1} g (k x k, upper triangular) into coef, for problems that iterated
+__global__ void k_b_trisolve(BState *__restrict__ st, BArrays a, const BParams *__restrict__ prm, int np) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np) return;
+    BState s = st[p];
+    if (s.done || s.k == 0) return;
+    const int m = prm->m, k = s.k;
+    const double2 *H = a.H + (long long)p * (m + 1) * m;
+    const double2 *g = a.g + (long long)p * (m + 1);
+    double2 *y = a.coef + (long long)p * (m + 1);
+    for (int i = k - 1; i >= 0; --i) {
+        double2 acc = g[i];
+        for (int c = i + 1; c < k; ++c) {
+            double2 t = cmulb(H[(long long)i * m + c], y[c]);
+            acc.x -= t.x;
+            acc.y -= t.y;
+        }
+        double2 d = H[(long long)i * m + i];
+        double dd = d.x * d.x + d.y * d.y;
+        y[i] = make_double2((acc.x * d.x + acc.y * d.y) / dd, (acc.y * d.x - acc.x * d.y) / dd);
+    }
+    s.alpha = make_double2(1.0, 0.0);
+    s.cycles += 1;
+    st[p] = s;
+}
+
+// ---------------------------------------------------------------------------------------------- linear combinations
+constexpr int BLC_EPT = 4;
+// kind 0: V_0 *= alpha (active); kind 1: V_{j+1} = alpha V_{j+1} + sum_{i<=j} c_i V_i (active);
+// kind 2: x += sum_{i<k} c_i Z_i (problems that iterated in this cycle and are not done)
+__global__ __launch_bounds__(256) void k_b_lincomb(const BProb *__restrict__ P, const BState *__restrict__ st,
+                                                   BArrays a, const BParams *__restrict__ prm,
+                                                   const int *__restrict__ off, int np, int kind, int j) {
+    const int p = find_prob(off, np, blockIdx.x);
+    const BState &s = st[p];
+    if (kind == 2 ? (s.done || s.k == 0) : !s.active) return;
+    const BProb &q = P[p];
+    const int m = prm->m;
+    const double2 *coef = a.coef + (long long)p * (m + 1);
+    double2 *out;
+    const double2 *V;
+    int nv;
+    double2 alpha = s.alpha;
+    if (kind == 0) { out = q.V; V = q.V; nv = 0; }
+    else if (kind == 1) { out = q.V + (long long)(j + 1) * q.n; V = q.V; nv = j + 1; }
+    else { out = q.x; V = q.Z; nv = s.k; alpha = make_double2(1.0, 0.0); }
+    const long long start = (long long)(blockIdx.x - off[p]) * (256 * BLC_EPT) + threadIdx.x;
+    double2 acc[BLC_EPT];
+    bool ok[BLC_EPT];
+#pragma unroll
+    for (int e = 0; e < BLC_EPT; ++e) {
+        const long long idx = start + (long long)e * 256;
+        ok[e] = idx < q.n;
+        acc[e] = make_double2(0.0, 0.0);
+        if (ok[e]) acc[e] = cmulb(alpha, out[idx]);
+    }
+    for (int i = 0; i < nv; ++i) {
+        const double2 *vi = V + (long long)i * q.n;
+        const double2 c = coef[i];
+        double2 v[BLC_EPT];
+#pragma unroll
+        for (int e = 0; e < BLC_EPT; ++e) {
+            const long long idx = start + (long long)e * 256;
+            v[e] = ok[e] ? vi[idx] : make_double2(0.0, 0.0);
+        }
+#pragma unroll
+        for (int e = 0; e < BLC_EPT; ++e) {
+            acc[e].x += c.x * v[e].x - c.y * v[e].y;
+            acc[e].y += c.x * v[e].y + c.y * v[e].x;
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < BLC_EPT; ++e) {
+        const long long idx = start + (long long)e * 256;
+        if (ok[e]) out[idx] = acc[e];
+    }
+}
+
+__global__ void k_b_zero_x(const BProb *__restrict__ P, const int *__restrict__ off, int np) {
+    const int p = find_prob(off, np, blockIdx.x);
+    const BProb &q = P[p];
+    const long long start = (long long)(blockIdx.x - off[p]) * (256 * BLC_EPT) + threadIdx.x;
+    for (int e = 0; e < BLC_EPT; ++e) {
+        const long long idx = start + (long long)e * 256;
+        if (idx < q.n) q.x[idx] = make_double2(0.0, 0.0);
+    }
+}
+
+template <typename T> hipError_t precond_steps(const BLaunch &L, hipStream_t s, int j) {
+    hipLaunchKernelGGL((k_b_gemm<0, T>), dim3(L.gemm_grid), dim3(256), 0, s, L.P, L.st, L.off.gx, L.np, j);
+    hipLaunchKernelGGL((k_b_gemm<1, T>), dim3(L.gemm_grid), dim3(256), 0, s, L.P, L.st, L.off.gy, L.np, j);
+    hipLaunchKernelGGL(k_b_tridiag<T>, dim3(L.tot_tri), dim3(64), 0, s, L.P, L.st, L.off.tri, L.np);
+    hipLaunchKernelGGL((k_b_gemm<2, T>), dim3(L.gemm_grid), dim3(256), 0, s, L.P, L.st, L.off.gy, L.np, j);
+    hipLaunchKernelGGL((k_b_gemm<3, T>), dim3(L.gemm_grid), dim3(256), 0, s, L.P, L.st, L.off.gx, L.np, j);
+    return hipGetLastError();
+}
+
+hipError_t matvec_step(const BLaunch &L, hipStream_t s, int mode, int j) {
+    if (L.order == 6)
+        hipLaunchKernelGGL(k_b_matvec<6>, dim3(L.tot_mv), dim3(64, 4), 0, s, L.P, L.st, L.off.mv, L.np, mode, j);
+    else if (L.order == 4)
+        hipLaunchKernelGGL(k_b_matvec<4>, dim3(L.tot_mv), dim3(64, 4), 0, s, L.P, L.st, L.off.mv, L.np, mode, j);
+    else
+        hipLaunchKernelGGL(k_b_matvec<2>, dim3(L.tot_mv), dim3(64, 4), 0, s, L.P, L.st, L.off.mv, L.np, mode, j);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t bl_zero_x(const BLaunch &L, hipStream_t s) {
+    hipLaunchKernelGGL(k_b_zero_x, dim3(L.tot_lc), dim3(256), 0, s, L.P, L.off.lc, L.np);
+    return hipGetLastError();
+}
+
+hipError_t bl_init(const BLaunch &L, hipStream_t s) {
+    hipLaunchKernelGGL(k_b_dots, dim3(L.tot_dot), dim3(256), 0, s, L.P, L.st, L.off.dot, L.np, 0, 0);
+    hipLaunchKernelGGL(k_b_init, dim3(L.np), dim3(256), 0, s, L.P, L.st, L.np, L.m);
+    return hipGetLastError();
+}
+
+hipError_t bl_restart(const BLaunch &L, hipStream_t s) {
+    // restart vector V_0 = F - A x, its norm, the convergence test, V_0 /= beta
+    hipError_t e;
+    if ((e = matvec_step(L, s, 0, 0)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_b_dots, dim3(L.tot_dot), dim3(256), 0, s, L.P, L.st, L.off.dot, L.np, 1, 0);
+    hipLaunchKernelGGL(k_b_restart, dim3(L.np), dim3(256), 0, s, L.P, L.st, L.a, L.prm);
+    hipLaunchKernelGGL(k_b_lincomb, dim3(L.tot_lc), dim3(256), 0, s, L.P, L.st, L.a, L.prm, L.off.lc, L.np, 0, 0);
+    return hipGetLastError();
+}
+
+hipError_t bl_cycle(const BLaunch &L, hipStream_t s) {
+    hipError_t e;
+    if ((e = bl_restart(L, s)) != hipSuccess) return e;
+    for (int j = 0; j < L.m; ++j) {
+        e = L.fp32 ? precond_steps<float>(L, s, j) : precond_steps<double>(L, s, j);
+        if (e != hipSuccess) return e;
+        if ((e = matvec_step(L, s, 1, j)) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_b_dots, dim3(L.tot_dot), dim3(256), 0, s, L.P, L.st, L.off.dot, L.np, 2, j);
+        hipLaunchKernelGGL(k_b_arnoldi, dim3(L.np), dim3(256), 0, s, L.P, L.st, L.a, L.prm, j);
+        hipLaunchKernelGGL(k_b_lincomb, dim3(L.tot_lc), dim3(256), 0, s, L.P, L.st, L.a, L.prm, L.off.lc, L.np, 1, j);
+    }
+    hipLaunchKernelGGL(k_b_trisolve, dim3((L.np + 63) / 64), dim3(64), 0, s, L.st, L.a, L.prm, L.np);
+    hipLaunchKernelGGL(k_b_lincomb, dim3(L.tot_lc), dim3(256), 0, s, L.P, L.st, L.a, L.prm, L.off.lc, L.np, 2, 0);
+    return hipGetLastError();
+}
+
+}  // namespace helm

@@ -85,6 +85,15 @@ def lib():
     L.helm_profile_read.restype = c_int
     L.helm_profile_name.argtypes = [c_int]
     L.helm_profile_name.restype = ctypes.c_char_p
+    L.helm_batch_create.argtypes = [POINTER(c_void_p), POINTER(c_void_p), c_int, c_int, c_int]
+    L.helm_batch_create.restype = c_int
+    L.helm_batch_solve.argtypes = [c_void_p, POINTER(c_void_p), POINTER(c_void_p), c_int, c_double, c_int, c_int,
+                                   POINTER(helm_solve_info)]
+    L.helm_batch_solve.restype = c_int
+    L.helm_batch_destroy.argtypes = [c_void_p]
+    L.helm_batch_destroy.restype = None
+    L.helm_batch_last_error.argtypes = [c_void_p]
+    L.helm_batch_last_error.restype = ctypes.c_char_p
     _lib = L
     return L
 
@@ -233,6 +242,67 @@ def helm_profile_read(ctx: Context) -> dict:
         if n.value:
             out[lib().helm_profile_name(k).decode()] = dict(ms=ms.value, launches=n.value, work=w.value)
     return out
+
+
+class Batch:
+    """Owns a helm_batch*: P FGMRES(m) solves (shared or distinct contexts) advanced together."""
+
+    def __init__(self, ptr, ctxs, m, fp32):
+        self.ptr = ptr
+        self.ctxs = list(ctxs)   # keeps the contexts alive
+        self.m = m
+        self.fp32 = fp32
+
+    def error(self) -> str:
+        return lib().helm_batch_last_error(self.ptr).decode()
+
+    def __del__(self):
+        try:
+            if self.ptr:
+                lib().helm_batch_destroy(self.ptr)
+                self.ptr = None
+        except Exception:
+            pass
+
+
+def helm_batch_create(ctxs, m: int = 30, prec_fp32: bool = True) -> Batch:
+    arr = (c_void_p * len(ctxs))(*(c.ptr for c in ctxs))
+    ptr = c_void_p()
+    st = lib().helm_batch_create(byref(ptr), arr, len(ctxs), int(m), int(bool(prec_fp32)))
+    if st != HELM_OK:
+        raise HelmError(st, lib().helm_batch_last_error(None).decode())
+    return Batch(ptr, ctxs, m, prec_fp32)
+
+
+def helm_batch_solve(batch: Batch, Fs, xs=None, x0_given: bool = False, rtol: float = 1e-8, maxit: int = 1000,
+                     use_graph: bool = True, raise_on_noconv: bool = True):
+    """Solve every problem of the batch; Fs/xs are lists of complex128 GPU vectors (xs allocated if None).
+    Returns (xs, infos) with one info dict per problem."""
+    P = len(batch.ctxs)
+    if len(Fs) != P:
+        raise ValueError("one right-hand side per problem")
+    if xs is None:
+        xs = [torch.empty_like(F) for F in Fs]
+        x0_given = False
+    for c, F, x in zip(batch.ctxs, Fs, xs):
+        _check(F, torch.complex128, c.n, "F")
+        _check(x, torch.complex128, c.n, "x")
+    Fa = (c_void_p * P)(*(F.data_ptr() for F in Fs))
+    xa = (c_void_p * P)(*(x.data_ptr() for x in xs))
+    infos = (helm_solve_info * P)()
+    st = lib().helm_batch_solve(batch.ptr, Fa, xa, int(bool(x0_given)), float(rtol), int(maxit), int(bool(use_graph)),
+                                infos)
+    out = [dict(iters=i.iters, restarts=i.restarts, converged=bool(i.converged), relres_est=i.relres_est,
+                relres_true=i.relres_true, cancellations=i.reorths) for i in infos]
+    if st != HELM_OK and not (st == HELM_ENOCONV and not raise_on_noconv):
+        raise HelmError(st, batch.error())
+    return xs, out
+
+
+def helm_batch_destroy(batch: Batch):
+    if batch.ptr:
+        lib().helm_batch_destroy(batch.ptr)
+        batch.ptr = None
 
 
 def helm_destroy(ctx: Context):
