@@ -92,6 +92,75 @@ def cpu_baseline(n_cpu: int = 128):
                 time_to_solution_s=round(t_solve, 3), iters=info["iters"])
 
 
+def bench_batched(H, torch, dev, args):
+    """The batched workloads, FP32-EigT FGMRES(30) at rtol 1e-8, one batched solve against the same problems
+    solved one after another:
+      * multi-RHS: 64 plane waves (seeded directions) scattered by the 128^3 four-inclusion medium (k0 = 60),
+        f_m = -(k^2 - k0^2) exp(i k0 d_m . x);
+      * uneven: 16 independent problems, N_p = 64..160, k0_p ~ U[30, 90] (seed 40), four-inclusion media
+        (seeds 400 + p), Gaussian source."""
+    import synth
+    out = {}
+    m, rtol = 30, 1e-8
+
+    def run(name, ctxs, Fs):
+        batch = H.helm_batch_create(ctxs, m=m, prec_fp32=True)
+        xs = [torch.empty_like(F) for F in Fs]
+        H.helm_batch_solve(batch, Fs, xs, rtol=rtol)                     # warm-up (captures the cycle graph)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, infos = H.helm_batch_solve(batch, Fs, xs, rtol=rtol)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+        del batch
+        torch.cuda.empty_cache()
+        x1 = torch.empty_like(Fs[0])
+        seq_iters = []
+        H.helm_gmres_solve(ctxs[0], Fs[0], x1, m=m, rtol=rtol, flexible=True, prec_fp32=True, x0_given=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for c, F in zip(ctxs, Fs):
+            if x1.numel() != F.numel():
+                x1 = torch.empty_like(F)
+            _, inf = H.helm_gmres_solve(c, F, x1, m=m, rtol=rtol, flexible=True, prec_fp32=True, x0_given=False)
+            seq_iters.append(inf["iters"])
+        torch.cuda.synchronize()
+        ts = time.perf_counter() - t0
+        work = sum(c.n * i["iters"] for c, i in zip(ctxs, infos))
+        res = dict(problems=len(ctxs), batch_ms=round(1e3 * tb, 2), sequential_ms=round(1e3 * ts, 2),
+                   speedup=round(ts / tb, 3), unknowns_iters_per_s=work / tb,
+                   iters=[i["iters"] for i in infos], sequential_iters=seq_iters,
+                   all_converged=all(i["converged"] for i in infos),
+                   max_relres=max(i["relres_true"] for i in infos))
+        log(f"batched {name}: {res['batch_ms']} ms batched vs {res['sequential_ms']} ms sequential "
+            f"({res['speedup']}x), {res['unknowns_iters_per_s']:.3e} unknowns*it/s")
+        return res
+
+    w = synth.workload("inclusions")
+    k2 = torch.from_numpy(w["k2"]).to(dev)
+    ctx = H.helm_setup(k2, w["h"], 6, k0=w["k0"])
+    if not args.no_autotune:
+        H.helm_autotune(ctx, reps=3)
+    dirs = synth.unit_directions(64, seed=4)
+    Fs = []
+    for d in dirs:
+        f = synth.plane_wave_sources(w["k2"], w["k0"], d[None, :])[0]
+        Fs.append(H.helm_rhs(ctx, torch.from_numpy(f).to(dev)))
+    out["multi_rhs_64x128"] = run("64 RHS x 128^3", [ctx] * len(Fs), Fs)
+    del Fs
+    torch.cuda.empty_cache()
+    ctxs, Fs = [], []
+    for p, (n, k0) in enumerate(synth.uneven_problem_set()):
+        k2p = synth.inclusions_k2(n, k0, seed=400 + p)
+        c = H.helm_setup(torch.from_numpy(k2p).to(dev), 1.0 / (n + 1), 6, k0=k0)
+        ctxs.append(c)
+        Fs.append(H.helm_rhs(c, torch.from_numpy(synth.gaussian_source(n)).to(dev)))
+    if not args.no_autotune:
+        H.helm_autotune(ctxs[0], reps=3)
+    out["uneven_16"] = run("16 uneven 64^3..160^3", ctxs, Fs)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -100,6 +169,8 @@ def main():
     ap.add_argument("--n", type=int, default=256, help="grid points per axis (256 is the benchmark workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="fp32_eigt_fgmres,fp64_eigt_gmres,fp32_pfft_fgmres,fp64_pfft_gmres")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched workloads")
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run three plain 256 MiB device-to-device copies (reference dispatches for scaling "
                          "hardware byte counters)")
@@ -130,6 +201,10 @@ def main():
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
     log(f"setup {t_setup:.3f} s")
+    tune = None
+    if not args.no_autotune:
+        tune = H.helm_autotune(ctx, reps=5)
+        log("autotuned GEMM tiles: " + ", ".join(f"{k}={v['chosen']}" for k, v in tune.items()))
     del k2, f
     x = torch.empty_like(F)
     unknowns = n ** 3
@@ -181,6 +256,11 @@ def main():
                     frac=dk["frac"], traffic=None,
                     note="achieved = algorithmic work per launch / average launch time (HIP events on the solve "
                          "stream over the timed region)")
+    batched = None
+    if not args.no_batched:
+        del x
+        torch.cuda.empty_cache()
+        batched = bench_batched(H, torch, dev, args)
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
@@ -211,6 +291,8 @@ def main():
         "speedup_vs_fp64_eigt": round(speedup, 3) if speedup else None,
         "setup_s": round(t_setup, 3),
         "forms": forms,
+        "gemm_autotune": tune,
+        "batched": batched,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

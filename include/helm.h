@@ -167,6 +167,18 @@ helm_status helm_profile_read(helm_ctx *ctx, int kernel_class, double *ms_total,
 /* Short name of a kernel class ("matvec", "gemm_x64", ...), or "" for an unknown class. */
 const char *helm_profile_name(int kernel_class);
 
+/* GEMM tile autotuner for the EigT transforms of a context. For each of the four transform GEMMs (x and y,
+ * FP64 and FP32) it times every tile configuration (BM, BN, BK) = (64,64,16), (64,64,32), (128,64,16),
+ * (64,128,16) over `reps` launches on the context stream and keeps the fastest for this context. If the
+ * environment variable HELM_TUNE_CACHE names a file, choices are read from it by (transform, M, N, K, batch)
+ * and new ones appended to it. chosen: NULL or 4 ints (x64, y64, x32, y32); ms: NULL or 16 doubles, the
+ * average time of configuration c of transform t at ms[4 t + c] (not written for cached transforms).
+ * Batches created afterwards use the tuned choices of their first context. */
+helm_status helm_autotune(helm_ctx *ctx, int reps, int *chosen, double *ms);
+
+/* Set the tile configuration (0..3) of transform kind (0 x64, 1 y64, 2 x32, 3 y32) by hand. */
+helm_status helm_gemm_config(helm_ctx *ctx, int kind, int cfg);
+
 /* ---- Batched solves (many right-hand sides and/or many independent problems) ----
  *
  * A batch groups P FGMRES(m) solves with the EigT preconditioner. Problem p uses the operator and the

@@ -6,7 +6,9 @@ from .helm import (  # noqa: F401
     HelmError,
     helm_batch_create,
     helm_batch_destroy,
+    helm_autotune,
     helm_batch_solve,
+    helm_gemm_config,
     helm_destroy,
     helm_eig1d,
     helm_gmres_solve,

@@ -2,6 +2,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -109,18 +111,18 @@ helm_status eigt_apply(Ctx &c, const double2 *y, double2 *z, bool fp32) {
     double2 gz = d2(c.gamma[2]);
     double scale = c.hz * c.hz;
     if (!fp32) {
-        HIP_TRY(timed(c, HELM_K_GEMM_X64, gemm_flops(dx), [&] { return launch_gemm_z64(dx, y, c.BxF, c.t1, c.stream); }));
-        HIP_TRY(timed(c, HELM_K_GEMM_Y64, gemm_flops(dy), [&] { return launch_gemm_z64(dy, c.AyF, c.t1, c.t2, c.stream); }));
+        HIP_TRY(timed(c, HELM_K_GEMM_X64, gemm_flops(dx), [&] { return launch_gemm_z64(dx, y, c.BxF, c.t1, c.stream, 0, c.gemm_cfg[0]); }));
+        HIP_TRY(timed(c, HELM_K_GEMM_Y64, gemm_flops(dy), [&] { return launch_gemm_z64(dy, c.AyF, c.t1, c.t2, c.stream, 0, c.gemm_cfg[1]); }));
         HIP_TRY(timed(c, HELM_K_TRIDIAG64, 32.0 * c.n, [&] { return launch_tridiag_z64(c.t2, c.t2, c.cp, c.dxe, c.dye, c.nx, c.ny, c.nz, c.ax, c.ay, c.c0, gz, scale, c.stream); }));
-        HIP_TRY(timed(c, HELM_K_GEMM_Y64, gemm_flops(dy), [&] { return launch_gemm_z64(dy, c.AyI, c.t2, c.t1, c.stream); }));
-        HIP_TRY(timed(c, HELM_K_GEMM_X64, gemm_flops(dx), [&] { return launch_gemm_z64(dx, c.t1, c.BxI, z, c.stream); }));
+        HIP_TRY(timed(c, HELM_K_GEMM_Y64, gemm_flops(dy), [&] { return launch_gemm_z64(dy, c.AyI, c.t2, c.t1, c.stream, 0, c.gemm_cfg[1]); }));
+        HIP_TRY(timed(c, HELM_K_GEMM_X64, gemm_flops(dx), [&] { return launch_gemm_z64(dx, c.t1, c.BxI, z, c.stream, 0, c.gemm_cfg[0]); }));
     } else {
         ST_TRY(ensure_fp32_work(c));
-        HIP_TRY(timed(c, HELM_K_GEMM_X32, gemm_flops(dx), [&] { return launch_gemm_z32_in64(dx, y, c.BxF32, c.t1f, c.stream); }));
-        HIP_TRY(timed(c, HELM_K_GEMM_Y32, gemm_flops(dy), [&] { return launch_gemm_z32(dy, c.AyF32, c.t1f, c.t2f, c.stream); }));
+        HIP_TRY(timed(c, HELM_K_GEMM_X32, gemm_flops(dx), [&] { return launch_gemm_z32_in64(dx, y, c.BxF32, c.t1f, c.stream, 0, c.gemm_cfg[2]); }));
+        HIP_TRY(timed(c, HELM_K_GEMM_Y32, gemm_flops(dy), [&] { return launch_gemm_z32(dy, c.AyF32, c.t1f, c.t2f, c.stream, 0, c.gemm_cfg[3]); }));
         HIP_TRY(timed(c, HELM_K_TRIDIAG32, 16.0 * c.n, [&] { return launch_tridiag_z32(c.t2f, c.t2f, c.cpf, c.dxe, c.dye, c.nx, c.ny, c.nz, c.ax, c.ay, c.c0, gz, scale, c.stream); }));
-        HIP_TRY(timed(c, HELM_K_GEMM_Y32, gemm_flops(dy), [&] { return launch_gemm_z32(dy, c.AyI32, c.t2f, c.t1f, c.stream); }));
-        HIP_TRY(timed(c, HELM_K_GEMM_X32, gemm_flops(dx), [&] { return launch_gemm_z32_out64(dx, c.t1f, c.BxI32, z, c.stream); }));
+        HIP_TRY(timed(c, HELM_K_GEMM_Y32, gemm_flops(dy), [&] { return launch_gemm_z32(dy, c.AyI32, c.t2f, c.t1f, c.stream, 0, c.gemm_cfg[3]); }));
+        HIP_TRY(timed(c, HELM_K_GEMM_X32, gemm_flops(dx), [&] { return launch_gemm_z32_out64(dx, c.t1f, c.BxI32, z, c.stream, 0, c.gemm_cfg[2]); }));
     }
     return HELM_OK;
 }
@@ -490,6 +492,92 @@ helm_status helm_setup(helm_ctx **out, helm_grid g, const double h[3], const dou
     if ((st = dalloc(c, &c.t2, (size_t)c.n)) != HELM_OK) return bail(st);
     if ((st = dalloc(c, &c.cp, (size_t)c.n)) != HELM_OK) return bail(st);
     *out = ctx;
+    return HELM_OK;
+}
+
+// ---- GEMM tile autotuner ----
+namespace {
+std::string tune_key(int kind, const GemmDesc &d) {
+    return std::to_string(kind) + " " + std::to_string(d.M) + " " + std::to_string(d.N) + " " + std::to_string(d.K) +
+           " " + std::to_string(d.batch);
+}
+bool tune_cache_lookup(const std::string &key, int &cfg) {
+    const char *path = std::getenv("HELM_TUNE_CACHE");
+    if (!path) return false;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return false;
+    char line[256];
+    bool found = false;
+    while (std::fgets(line, sizeof line, f)) {
+        std::string ln(line);
+        auto pos = ln.rfind(' ');
+        if (pos == std::string::npos) continue;
+        if (ln.compare(0, pos, key) == 0 && pos == key.size()) { cfg = std::atoi(ln.c_str() + pos + 1); found = true; }
+    }
+    std::fclose(f);
+    return found && cfg >= 0 && cfg < GEMM_NCFG;
+}
+void tune_cache_store(const std::string &key, int cfg) {
+    const char *path = std::getenv("HELM_TUNE_CACHE");
+    if (!path) return;
+    FILE *f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%s %d\n", key.c_str(), cfg);
+    std::fclose(f);
+}
+}  // namespace
+
+helm_status helm_autotune(helm_ctx *ctx, int reps, int *chosen, double *ms) {
+    if (!ctx || reps < 1) return HELM_EINVAL;
+    Ctx &c = ctx->c;
+    ST_TRY(ensure_fp32_work(c));
+    GemmDesc dxd = desc_x(c), dyd = desc_y(c);
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    for (int kind = 0; kind < 4; ++kind) {
+        const GemmDesc &d = (kind % 2 == 0) ? dxd : dyd;
+        std::string key = tune_key(kind, d);
+        int cached = -1;
+        if (tune_cache_lookup(key, cached)) {
+            c.gemm_cfg[kind] = cached;
+            if (chosen) chosen[kind] = cached;
+            continue;
+        }
+        double best = 1e300;
+        int best_cfg = 0;
+        for (int cfg = 0; cfg < GEMM_NCFG; ++cfg) {
+            auto run = [&]() -> hipError_t {
+                switch (kind) {
+                case 0: return launch_gemm_z64(d, c.t1, c.BxF, c.t2, c.stream, 0, cfg);
+                case 1: return launch_gemm_z64(d, c.AyF, c.t1, c.t2, c.stream, 0, cfg);
+                case 2: return launch_gemm_z32(d, c.t1f, c.BxF32, c.t2f, c.stream, 0, cfg);
+                default: return launch_gemm_z32(d, c.AyF32, c.t1f, c.t2f, c.stream, 0, cfg);
+                }
+            };
+            HIP_TRY(run());
+            HIP_TRY(hipEventRecord(e0, c.stream));
+            for (int r = 0; r < reps; ++r) HIP_TRY(run());
+            HIP_TRY(hipEventRecord(e1, c.stream));
+            HIP_TRY(hipEventSynchronize(e1));
+            float t = 0.f;
+            HIP_TRY(hipEventElapsedTime(&t, e0, e1));
+            double avg = (double)t / reps;
+            if (ms) ms[kind * GEMM_NCFG + cfg] = avg;
+            if (avg < best) { best = avg; best_cfg = cfg; }
+        }
+        c.gemm_cfg[kind] = best_cfg;
+        if (chosen) chosen[kind] = best_cfg;
+        tune_cache_store(key, best_cfg);
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    return HELM_OK;
+}
+
+helm_status helm_gemm_config(helm_ctx *ctx, int kind, int cfg) {
+    if (!ctx || kind < 0 || kind > 3 || cfg < 0 || cfg >= GEMM_NCFG) return HELM_EINVAL;
+    ctx->c.gemm_cfg[kind] = cfg;
     return HELM_OK;
 }
 

@@ -90,6 +90,11 @@ helm_status helm_batch_create(helm_batch **out, helm_ctx *const *ctxs, int np, i
     if (hipEventCreateWithFlags(&b->ev, hipEventDisableTiming) != hipSuccess) return fail(HELM_EDEVICE, "event");
     const size_t esz = b->fp32 ? sizeof(float2) : sizeof(double2);
 
+    // tile configurations tuned for the first context (helm_autotune), used for every problem of the batch
+    const int cfg_x = ctxs[0]->c.gemm_cfg[b->fp32 ? 2 : 0], cfg_y = ctxs[0]->c.gemm_cfg[b->fp32 ? 3 : 1];
+    int bmx, bnx, bmy, bny;
+    gemm_cfg_tile(cfg_x, bmx, bnx);
+    gemm_cfg_tile(cfg_y, bmy, bny);
     // per-problem descriptors, work buffers and launch offsets
     long long tot_blocks_mv_target = 4096;
     std::vector<int> omv(1, 0), otri(1, 0), odot(1, 0), olc(1, 0);
@@ -138,8 +143,8 @@ helm_status helm_batch_create(helm_batch **out, helm_ctx *const *ctxs, int np, i
         otri.push_back(otri.back() + (int)(((long long)c.nx * c.ny + 63) / 64));
         odot.push_back(odot.back() + q.nblk_dots);
         olc.push_back(olc.back() + (int)((c.n + 1023) / 1024));
-        ogx.push_back(ogx.back() + (long long)((q.dx.M + 63) / 64) * ((q.dx.N + 63) / 64));
-        ogy.push_back(ogy.back() + (long long)((q.dy.M + 63) / 64) * ((q.dy.N + 63) / 64) * q.dy.batch);
+        ogx.push_back(ogx.back() + (long long)((q.dx.M + bmx - 1) / bmx) * ((q.dx.N + bnx - 1) / bnx));
+        ogy.push_back(ogy.back() + (long long)((q.dy.M + bmy - 1) / bmy) * ((q.dy.N + bny - 1) / bny) * q.dy.batch);
     }
     BLaunch &L = b->L;
     if (balloc(*b, &b->dP, np) != hipSuccess || balloc(*b, &b->dst, np) != hipSuccess ||
@@ -167,6 +172,8 @@ helm_status helm_batch_create(helm_batch **out, helm_ctx *const *ctxs, int np, i
     L.m = m;
     L.order = order;
     L.fp32 = b->fp32;
+    L.cfg_x = cfg_x;
+    L.cfg_y = cfg_y;
     L.tot_mv = omv.back();
     L.tot_tri = otri.back();
     L.tot_dot = odot.back();

@@ -92,6 +92,7 @@ struct Ctx {
     float2 *BxF32 = nullptr, *BxI32 = nullptr, *AyF32 = nullptr, *AyI32 = nullptr;
     double2 *dxe = nullptr, *dye = nullptr;    // eigenvalues d_x,i and d_y,j
     double ax, ay, c0;                          // alpha_x, alpha_y, h_z^2 k0^2 - 2(alpha_x + alpha_y + 1)
+    int gemm_cfg[4] = {0, 0, 0, 0};             // tile configuration of the x64, y64, x32, y32 transforms
 
     // preconditioner work buffers
     double2 *t1 = nullptr, *t2 = nullptr, *cp = nullptr;
@@ -192,13 +193,17 @@ hipError_t launch_matvec(const StencilParams &p, const double2 *x, const double 
 hipError_t launch_rhs(const StencilParams &p, const double2 *f_halo, const double *k2, const double4 *fld,
                       double h3[3], double2 *F, hipStream_t s);
 
-// rw: 0 = both operands complex, 1 = A real (imaginary parts ignored), 2 = B real
-hipError_t launch_gemm_z64(const GemmDesc &d, const double2 *A, const double2 *B, double2 *C, hipStream_t s, int rw = 0);
-hipError_t launch_gemm_z32(const GemmDesc &d, const float2 *A, const float2 *B, float2 *C, hipStream_t s, int rw = 0);
+// rw: 0 = both operands complex, 1 = A real (imaginary parts ignored), 2 = B real.
+// cfg: tile configuration 0..GEMM_NCFG-1 = (BM, BN, BK) of (64,64,16), (64,64,32), (128,64,16), (64,128,16).
+constexpr int GEMM_NCFG = 4;
+hipError_t launch_gemm_z64(const GemmDesc &d, const double2 *A, const double2 *B, double2 *C, hipStream_t s,
+                           int rw = 0, int cfg = 0);
+hipError_t launch_gemm_z32(const GemmDesc &d, const float2 *A, const float2 *B, float2 *C, hipStream_t s,
+                           int rw = 0, int cfg = 0);
 hipError_t launch_gemm_z32_in64(const GemmDesc &d, const double2 *A, const float2 *B, float2 *C, hipStream_t s,
-                                int rw = 0);
+                                int rw = 0, int cfg = 0);
 hipError_t launch_gemm_z32_out64(const GemmDesc &d, const float2 *A, const float2 *B, double2 *C, hipStream_t s,
-                                 int rw = 0);
+                                 int rw = 0, int cfg = 0);
 
 // `in` (may equal r) supplies the right-hand side; the solution is written to r.
 hipError_t launch_tridiag_z64(const double2 *in, double2 *r, double2 *cp, const double2 *dx, const double2 *dy, int nx,
@@ -235,7 +240,12 @@ struct BLaunch {
     int tot_mv, tot_tri, tot_dot, tot_lc;       // total blocks per grouped launch
     long long tot_gx, tot_gy;                   // total GEMM tiles
     int gemm_grid;                              // persistent GEMM grid size
+    int cfg_x, cfg_y;                           // GEMM tile configurations of the x- and y-transforms
 };
+inline void gemm_cfg_tile(int cfg, int &bm, int &bn) {
+    bm = cfg == 2 ? 128 : 64;
+    bn = cfg == 3 ? 128 : 64;
+}
 hipError_t bl_init(const BLaunch &L, hipStream_t s);                 // ||F||, state reset (outside graphs)
 hipError_t bl_zero_x(const BLaunch &L, hipStream_t s);
 hipError_t bl_cycle(const BLaunch &L, hipStream_t s);                // one restart cycle: restart + m steps + update

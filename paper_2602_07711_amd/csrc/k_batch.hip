@@ -17,8 +17,6 @@ namespace helm {
 
 namespace {
 
-constexpr int BM = 64, BN = 64, BK = 16;
-
 __device__ __forceinline__ int find_prob(const int *off, int np, int b) {
     int lo = 0, hi = np - 1;
     while (lo < hi) {
@@ -41,7 +39,7 @@ __device__ __forceinline__ int find_prob64(const long long *off, int np, long lo
 // ---------------------------------------------------------------------------------------------- GEMMs
 // ROLE 0: x-forward  t1 = V_j  W_xF       ROLE 1: y-forward  t2 = W_yF t1
 // ROLE 2: y-inverse  t1 = W_yI t2         ROLE 3: x-inverse  Z_j = t1 W_xI
-template <int ROLE, typename T>
+template <int ROLE, typename T, int BM, int BN, int BK>
 __global__ __launch_bounds__(256) void k_b_gemm(const BProb *__restrict__ P, const BState *__restrict__ st,
                                                 const long long *__restrict__ toff, int np, int j) {
     typedef typename cplx<T>::t CT;
@@ -335,12 +333,22 @@ __global__ void k_b_zero_x(const BProb *__restrict__ P, const int *__restrict__ 
     }
 }
 
+template <int ROLE, typename T>
+void gemm_role(const BLaunch &L, hipStream_t s, int j, int cfg, const long long *off) {
+    switch (cfg) {
+    case 1: hipLaunchKernelGGL((k_b_gemm<ROLE, T, 64, 64, 32>), dim3(L.gemm_grid), dim3(256), 0, s, L.P, L.st, off, L.np, j); break;
+    case 2: hipLaunchKernelGGL((k_b_gemm<ROLE, T, 128, 64, 16>), dim3(L.gemm_grid), dim3(256), 0, s, L.P, L.st, off, L.np, j); break;
+    case 3: hipLaunchKernelGGL((k_b_gemm<ROLE, T, 64, 128, 16>), dim3(L.gemm_grid), dim3(256), 0, s, L.P, L.st, off, L.np, j); break;
+    default: hipLaunchKernelGGL((k_b_gemm<ROLE, T, 64, 64, 16>), dim3(L.gemm_grid), dim3(256), 0, s, L.P, L.st, off, L.np, j); break;
+    }
+}
+
 template <typename T> hipError_t precond_steps(const BLaunch &L, hipStream_t s, int j) {
-    hipLaunchKernelGGL((k_b_gemm<0, T>), dim3(L.gemm_grid), dim3(256), 0, s, L.P, L.st, L.off.gx, L.np, j);
-    hipLaunchKernelGGL((k_b_gemm<1, T>), dim3(L.gemm_grid), dim3(256), 0, s, L.P, L.st, L.off.gy, L.np, j);
+    gemm_role<0, T>(L, s, j, L.cfg_x, L.off.gx);
+    gemm_role<1, T>(L, s, j, L.cfg_y, L.off.gy);
     hipLaunchKernelGGL(k_b_tridiag<T>, dim3(L.tot_tri), dim3(64), 0, s, L.P, L.st, L.off.tri, L.np);
-    hipLaunchKernelGGL((k_b_gemm<2, T>), dim3(L.gemm_grid), dim3(256), 0, s, L.P, L.st, L.off.gy, L.np, j);
-    hipLaunchKernelGGL((k_b_gemm<3, T>), dim3(L.gemm_grid), dim3(256), 0, s, L.P, L.st, L.off.gx, L.np, j);
+    gemm_role<2, T>(L, s, j, L.cfg_y, L.off.gy);
+    gemm_role<3, T>(L, s, j, L.cfg_x, L.off.gx);
     return hipGetLastError();
 }
 

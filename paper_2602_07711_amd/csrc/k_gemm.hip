@@ -35,9 +35,8 @@ __global__ __launch_bounds__(256) void k_zgemm(const TA *__restrict__ A, const T
     gemm_tile<TA, TB, TC, T, BM, BN, BK, RW>(A, B, C, d, tile);
 }
 
-template <typename TA, typename TB, typename TC, typename T>
-hipError_t launch(const GemmDesc &d, const TA *A, const TB *B, TC *C, hipStream_t s, int rw = 0) {
-    constexpr int BM = 64, BN = 64, BK = 16;
+template <typename TA, typename TB, typename TC, typename T, int BM, int BN, int BK>
+hipError_t launch_tile(const GemmDesc &d, const TA *A, const TB *B, TC *C, hipStream_t s, int rw) {
     long long tiles = (long long)((d.M + BM - 1) / BM) * ((d.N + BN - 1) / BN) * d.batch;
     long long grid = 8 * ((tiles + 7) / 8);
     if (tiles == 0) return hipSuccess;
@@ -50,21 +49,35 @@ hipError_t launch(const GemmDesc &d, const TA *A, const TB *B, TC *C, hipStream_
     return hipGetLastError();
 }
 
+// Tile configurations (BM, BN, BK) the autotuner chooses from; the real-operand (sine) products use config 0.
+template <typename TA, typename TB, typename TC, typename T>
+hipError_t launch(const GemmDesc &d, const TA *A, const TB *B, TC *C, hipStream_t s, int rw, int cfg) {
+    if (rw != 0) cfg = 0;
+    switch (cfg) {
+    case 1: return launch_tile<TA, TB, TC, T, 64, 64, 32>(d, A, B, C, s, 0);
+    case 2: return launch_tile<TA, TB, TC, T, 128, 64, 16>(d, A, B, C, s, 0);
+    case 3: return launch_tile<TA, TB, TC, T, 64, 128, 16>(d, A, B, C, s, 0);
+    default: return launch_tile<TA, TB, TC, T, 64, 64, 16>(d, A, B, C, s, rw);
+    }
+}
+
 }  // namespace
 
-hipError_t launch_gemm_z64(const GemmDesc &d, const double2 *A, const double2 *B, double2 *C, hipStream_t s, int rw) {
-    return launch<double2, double2, double2, double>(d, A, B, C, s, rw);
+hipError_t launch_gemm_z64(const GemmDesc &d, const double2 *A, const double2 *B, double2 *C, hipStream_t s, int rw,
+                           int cfg) {
+    return launch<double2, double2, double2, double>(d, A, B, C, s, rw, cfg);
 }
-hipError_t launch_gemm_z32(const GemmDesc &d, const float2 *A, const float2 *B, float2 *C, hipStream_t s, int rw) {
-    return launch<float2, float2, float2, float>(d, A, B, C, s, rw);
+hipError_t launch_gemm_z32(const GemmDesc &d, const float2 *A, const float2 *B, float2 *C, hipStream_t s, int rw,
+                           int cfg) {
+    return launch<float2, float2, float2, float>(d, A, B, C, s, rw, cfg);
 }
 hipError_t launch_gemm_z32_in64(const GemmDesc &d, const double2 *A, const float2 *B, float2 *C, hipStream_t s,
-                                int rw) {
-    return launch<double2, float2, float2, float>(d, A, B, C, s, rw);
+                                int rw, int cfg) {
+    return launch<double2, float2, float2, float>(d, A, B, C, s, rw, cfg);
 }
 hipError_t launch_gemm_z32_out64(const GemmDesc &d, const float2 *A, const float2 *B, double2 *C, hipStream_t s,
-                                 int rw) {
-    return launch<float2, float2, double2, float>(d, A, B, C, s, rw);
+                                 int rw, int cfg) {
+    return launch<float2, float2, double2, float>(d, A, B, C, s, rw, cfg);
 }
 
 }  // namespace helm

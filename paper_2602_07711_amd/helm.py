@@ -85,6 +85,10 @@ def lib():
     L.helm_profile_read.restype = c_int
     L.helm_profile_name.argtypes = [c_int]
     L.helm_profile_name.restype = ctypes.c_char_p
+    L.helm_autotune.argtypes = [c_void_p, c_int, POINTER(c_int), POINTER(c_double)]
+    L.helm_autotune.restype = c_int
+    L.helm_gemm_config.argtypes = [c_void_p, c_int, c_int]
+    L.helm_gemm_config.restype = c_int
     L.helm_batch_create.argtypes = [POINTER(c_void_p), POINTER(c_void_p), c_int, c_int, c_int]
     L.helm_batch_create.restype = c_int
     L.helm_batch_solve.argtypes = [c_void_p, POINTER(c_void_p), POINTER(c_void_p), c_int, c_double, c_int, c_int,
@@ -242,6 +246,27 @@ def helm_profile_read(ctx: Context) -> dict:
         if n.value:
             out[lib().helm_profile_name(k).decode()] = dict(ms=ms.value, launches=n.value, work=w.value)
     return out
+
+
+GEMM_CONFIGS = [(64, 64, 16), (64, 64, 32), (128, 64, 16), (64, 128, 16)]
+GEMM_KINDS = ["x64", "y64", "x32", "y32"]
+
+
+def helm_autotune(ctx: Context, reps: int = 5) -> dict:
+    """Time every tile configuration of the four EigT transform GEMMs on this context and keep the fastest.
+    Returns {kind: {"chosen": (BM, BN, BK), "ms": [per-config average ms or None]}}."""
+    chosen = (c_int * 4)()
+    ms = (c_double * 16)(*([-1.0] * 16))
+    ctx.check(lib().helm_autotune(ctx.ptr, int(reps), chosen, ms))
+    out = {}
+    for k, name in enumerate(GEMM_KINDS):
+        t = [ms[4 * k + c] for c in range(4)]
+        out[name] = dict(chosen=GEMM_CONFIGS[chosen[k]], ms=[v if v >= 0 else None for v in t])
+    return out
+
+
+def helm_gemm_config(ctx: Context, kind: str, cfg: int):
+    ctx.check(lib().helm_gemm_config(ctx.ptr, GEMM_KINDS.index(kind), int(cfg)))
 
 
 class Batch:

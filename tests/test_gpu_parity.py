@@ -290,3 +290,43 @@ def test_solve_pfft_matches_sparse_lu(fp32):
     rel = np.linalg.norm(host(x) - xs) / np.linalg.norm(xs)
     print("pfft solve", fp32, info["iters"], rel)
     assert info["converged"] and rel <= 1e-8
+
+
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3])
+def test_gemm_tile_configs_parity(cfg):
+    """Every tile configuration the autotuner may pick computes the same EigT preconditioner."""
+    h = H()
+    shape = (12, 20, 70)
+    h3 = (1.0 / 71, 1.0 / 21, 1.0 / 13)
+    k0 = 0.47 / h3[0]
+    k2 = np.full(tuple(s + 4 for s in shape), k0 * k0)
+    ctx = h.helm_setup(dev(k2), h3, 4, k0=k0, shape=shape)
+    for kind in ("x64", "y64", "x32", "y32"):
+        h.helm_gemm_config(ctx, kind, cfg)
+    y = cvec(int(np.prod(shape)), 21)
+    gs = tuple(op.gamma_abc(k0, hh) for hh in h3)
+    zr = pc.EigT(shape, h3, k0, gs).solve(y)
+    z64 = host(h.helm_precond_apply(ctx, dev(y)))
+    z32 = host(h.helm_precond_apply(ctx, dev(y), fp32=True))
+    assert np.linalg.norm(z64 - zr) <= 1e-11 * np.linalg.norm(zr)
+    assert np.linalg.norm(z32 - zr) <= 2e-4 * np.linalg.norm(zr)
+
+
+def test_autotune_runs_and_keeps_parity():
+    h = H()
+    n = 24
+    k0 = 0.47 * (n + 1)
+    hh, k2, f = _problem(6, n, k0)
+    ctx = h.helm_setup(dev(k2), hh, 6, k0=k0)
+    res = h.helm_autotune(ctx, reps=2)
+    print("autotune", res)
+    assert set(res) == {"x64", "y64", "x32", "y32"}
+    F = h.helm_rhs(ctx, dev(f))
+    x, info = h.helm_gmres_solve(ctx, F, m=50, rtol=1e-10, flexible=True, prec_fp32=True)
+    A, Fr = op.problem(6, k2, f, hh, k0)
+    xs = spla.splu(A.tocsc()).solve(Fr)
+    assert np.linalg.norm(host(x) - xs) <= 1e-8 * np.linalg.norm(xs)
+    batch = h.helm_batch_create([ctx, ctx], m=30, prec_fp32=True)
+    xb, ib = h.helm_batch_solve(batch, [F, F.clone()], rtol=1e-10)
+    for xx in xb:
+        assert np.linalg.norm(host(xx) - xs) <= 1e-8 * np.linalg.norm(xs)
