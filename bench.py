@@ -161,6 +161,38 @@ def bench_batched(H, torch, dev, args):
     return out
 
 
+def bench_learned(H, torch, args):
+    """Learned warm start: 64^3 four-inclusion problems (k0 = 60, source width 0.03) solved by FP32-EigT
+    FGMRES generate the training set, the CNN trains on the GPU with the library's BF16 kernels, and held-out
+    128^3 problems are solved to rtol 1e-8 from zero and from the prolonged prediction. By default a reduced
+    training budget keeps the run short (--ws-samples / --ws-epochs give the full 2000-solve configuration)."""
+    from paper_2602_07711_amd import warmstart as W
+    S = 64
+    ws, rep = W.fit(size=S, samples=args.ws_samples, epochs=args.ws_epochs, batch=4, lr=1e-3, k0=60.0,
+                    log=None)
+    fwd, train = W.cnn_flops(S)
+    step_ms = 1e3 * rep["train_s"] / max(1, rep["train_steps"])
+    control = W.WarmStart(H.Cnn(S, 1, bf16=True, seed=999), ws.t_scale, 60.0)
+    ev = W.evaluate(ws, 128, range(1_000_000, 1_000_000 + args.ws_eval), control=control)
+    m = ev["mean"]
+    out = dict(train=dict(samples=rep["samples"], epochs=rep["epochs"], steps=rep["train_steps"], batch=4,
+                          gen_s=rep["gen_s"], train_s=rep["train_s"], ms_per_step=round(step_ms, 3),
+                          tflops=round(4 * train / (step_ms * 1e-3) / 1e12, 2), loss_first=rep["loss_first"],
+                          loss_last=rep["loss_last"]),
+               infer_ms=round(m["infer_ms"], 3), forward_gflop=round(fwd / 1e9, 2),
+               eval_problems=args.ws_eval, iters_zero=m["zero_iters"], iters_warm=m["warm_iters"],
+               iters_warm_trilinear=m.get("warm_linear_iters"), iters_untrained=m["control_iters"],
+               e0_warm=round(m["warm_e0"], 4), e0_untrained=round(m["control_e0"], 4),
+               r0_warm=round(m["warm_r0"], 4),
+               ms_fp32_zero=round(m["zero_ms"], 3), ms_fp32_learned=round(m["warm_ms"], 3),
+               ms_fp64_zero=round(m["fp64_ms"], 3))
+    log(f"learned warm start: {out['iters_warm']} vs {out['iters_zero']} iterations (untrained "
+        f"{out['iters_untrained']}), e0 {out['e0_warm']}, {out['ms_fp32_learned']} ms vs {out['ms_fp32_zero']} ms "
+        f"(FP64 plain {out['ms_fp64_zero']} ms); training {out['train']['ms_per_step']} ms/step "
+        f"({out['train']['tflops']} TFLOP/s)")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -171,6 +203,10 @@ def main():
     ap.add_argument("--forms", default="fp32_eigt_fgmres,fp64_eigt_gmres,fp32_pfft_fgmres,fp64_pfft_gmres")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched workloads")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-warm-start leg")
+    ap.add_argument("--ws-samples", type=int, default=400, help="training solves of the learned leg (full: 2000)")
+    ap.add_argument("--ws-epochs", type=int, default=6, help="training epochs of the learned leg (full: 20)")
+    ap.add_argument("--ws-eval", type=int, default=2, help="held-out 128^3 problems of the learned leg")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run three plain 256 MiB device-to-device copies (reference dispatches for scaling "
                          "hardware byte counters)")
@@ -261,6 +297,10 @@ def main():
         del x
         torch.cuda.empty_cache()
         batched = bench_batched(H, torch, dev, args)
+    learned = None
+    if not args.no_learned:
+        torch.cuda.empty_cache()
+        learned = bench_learned(H, torch, args)
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
@@ -293,6 +333,7 @@ def main():
         "forms": forms,
         "gemm_autotune": tune,
         "batched": batched,
+        "learned_warm_start": learned,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -229,6 +229,82 @@ void helm_destroy(helm_ctx *ctx);
  * d[n], V[n*n] and Vinv[n*n] in row-major order. Returns HELM_ENUMERIC if the residual checks fail. */
 helm_status helm_eig1d(int n, double gamma_re, double gamma_im, double *d, double *V, double *Vinv);
 
+/* ---------------------------------------------------------------------------------------------------------
+ * Learned warm start: a 3D encoder-decoder CNN that maps (contrast, source) sampled on an S^3 grid to an
+ * initial guess (Re u, Im u) on the same grid, trained and run on the GPU. It only supplies x0: the solver
+ * (helm_gmres_solve with x0_given = 1) still converges to the caller's tolerance relative to ||F||, so a poor
+ * prediction costs iterations, never accuracy.
+ *
+ * Network (channels 16/32/64/64 on levels S, S/2, S/4, S/8): per level two 3x3x3 convolutions with bias and
+ * ReLU, 2x average pooling between levels; decoder: nearest 2x upsampling, concatenation [upsampled | skip],
+ * one 3x3x3 convolution with ReLU per level; a linear 1x1x1 head to 2 channels. Convolutions have zero
+ * padding and are cross-correlations, out[co][v] = b[co] + sum_{ci, tap} W[co][ci][tap] in[ci][v + off(tap)],
+ * tap = 9 (dz+1) + 3 (dy+1) + (dx+1). Parameters are one FP32 array: per layer in the order above, W[co][ci][tap]
+ * then b[co] (helm_cnn_num_params entries). MFMA operands are BF16 (bf16 = 1) or FP32, accumulation is FP32,
+ * activations are stored in FP32. Tensors: device FP32, [batch][channel][z][y][x], x fastest.
+ * All calls are ordered on the stream given at creation and return once the work is queued, except those that
+ * copy to or from host memory, which return when the copy is done.
+ * --------------------------------------------------------------------------------------------------------- */
+typedef struct helm_cnn helm_cnn;
+
+/* Create a network for S^3 volumes (size S: multiple of 8, >= 8) and batches up to max_batch, with He-uniform
+ * initial weights drawn from `seed` and zero biases. stream: a hipStream_t or NULL (default stream).
+ * Allocates all activations and their gradients (about 0.9 KiB per voxel of S^3 per sample) and the Adam moments.
+ * Returns HELM_EINVAL on bad sizes, HELM_ENOMEM / HELM_EDEVICE on allocation or copy failure. */
+helm_status helm_cnn_create(helm_cnn **net, int size, int max_batch, int bf16, unsigned long long seed, void *stream);
+
+/* Number of FP32 parameters. */
+long long helm_cnn_num_params(const helm_cnn *net);
+
+/* Copy all parameters to / from host memory (helm_cnn_num_params floats, layout above). Setting them also
+ * refreshes the packed MFMA operands. */
+helm_status helm_cnn_get_params(helm_cnn *net, float *host_params);
+helm_status helm_cnn_set_params(helm_cnn *net, const float *host_params);
+
+/* Copy the gradient of the last helm_cnn_loss_grad call to host memory (same layout as the parameters). */
+helm_status helm_cnn_get_grads(helm_cnn *net, float *host_grads);
+
+/* Inference: x [B][2][S^3] (device) -> y [B][2][S^3] (device, may be NULL to keep the result internal).
+ * 1 <= B <= max_batch. */
+helm_status helm_cnn_forward(helm_cnn *net, const float *x, float *y, int B);
+
+/* Forward, mean-squared-error loss L = mean((y - t)^2) over all B*2*S^3 outputs, and backward: dL/dparams into
+ * the gradient buffer. t: device targets [B][2][S^3]. loss: NULL or host double receiving L (then the call
+ * waits for it). */
+helm_status helm_cnn_loss_grad(helm_cnn *net, const float *x, const float *t, int B, double *loss);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) on the FP32 master parameters with the
+ * current gradient, learning rate lr > 0. */
+helm_status helm_cnn_adam_step(helm_cnn *net, double lr);
+
+/* helm_cnn_loss_grad followed by helm_cnn_adam_step. */
+helm_status helm_cnn_train_step(helm_cnn *net, const float *x, const float *t, int B, double lr, double *loss);
+
+/* Trilinear prolongation of a 2-channel prediction (Re, Im) on nc^3 nodes (i+1)/(nc+1) to the nf^3 nodes
+ * (I+1)/(nf+1) of the unit cube, times `scale`, written as complex128 into `fine` (device, nf^3 entries).
+ * Beyond the outermost coarse nodes the field follows the coarse grid's ghost rule, one factor
+ * gamma = gamma_re + i gamma_im per axis crossed: U(-1) = gamma U(0), U(nc) = gamma U(nc-1) (Sec. 2.3, eq.
+ * D_bc; gamma = (2 + i k0 h_c)/(2 - i k0 h_c) with h_c = 1/(nc+1) for the absorbing closure, 0 for Dirichlet).
+ * cubic = 1 replaces the trilinear weights by Keys' cubic convolution (a = -1/2, coarse indices i0-1..i0+2 per
+ * axis), the second ghost layer taking gamma^2 U(0) (the closure applied twice). */
+helm_status helm_cnn_prolong(helm_cnn *net, const float *coarse, int nc, double scale, double gamma_re,
+                             double gamma_im, int cubic, void *fine, int nf);
+
+/* Network input for a solver problem on nf^3 unknowns: k2_halo (FP64) and f_halo (complex128) are the device
+ * arrays given to helm_setup and helm_rhs, with `halo` >= 1 cells per side, nf >= S. Node (i, j, l) of the S^3
+ * network grid is the point ((i, j, l) + 1)/(S + 1) of the unit cube; k^2 and f there are interpolated
+ * trilinearly from the solver nodes (I + 1)/(nf + 1) (exact injection when nf + 1 is a multiple of S + 1).
+ * Writes x [2][S^3] (device FP32): channel 0 = c_scale (k^2/k0^2 - 1), channel 1 = f_scale Re f.
+ * Returns HELM_EINVAL on a halo below 1 or nf < S. */
+helm_status helm_cnn_features(helm_cnn *net, const double *k2_halo, const void *f_halo, int halo, int nf, double k0,
+                              double c_scale, double f_scale, float *x);
+
+/* Message of the last failure of `net`, or of the last helm_cnn_create failure when net is NULL. */
+const char *helm_cnn_last_error(const helm_cnn *net);
+
+/* Free the network. NULL is allowed. */
+void helm_cnn_destroy(helm_cnn *net);
+
 #ifdef __cplusplus
 }
 #endif

@@ -3,6 +3,7 @@
 The compute path lives in libhelm.so (C ABI, include/helm.h); `helm` is its ctypes binding.
 """
 from .helm import (  # noqa: F401
+    Cnn,
     HelmError,
     helm_batch_create,
     helm_batch_destroy,

@@ -1,0 +1,641 @@
+// Kernels of the learned warm start: a 3D encoder-decoder CNN trained and run on the GPU.
+//
+// Convolutions are implicit GEMMs on MFMA: out[co][v] = sum_{ci, tap} W[co][ci tap] in[ci][v + off(tap)], the
+// im2col operand gathered on the fly into LDS. Operands are BF16 (v_mfma_f32_16x16x16bf16_1k) or FP32
+// (v_mfma_f32_16x16x4f32), accumulation FP32, activations stored FP32. Lane layout (checked on gfx950):
+// A(row = lane%16, k = KL*(lane/16) + e), B(k = KL*(lane/16) + e, col = lane%16), accumulator register r =
+// D(row = 4*(lane/16) + r, col = lane%16), KL = 4 (bf16) or 1 (f32).
+//   * forward:  rows = output channels (padded to COP), cols = 64 voxels per workgroup;
+//   * dgrad:    the same kernel with W'[ci][co tap'] = W[co][ci tap], tap' the mirrored offset;
+//   * wgrad:    dW[co][ci tap] = sum_v g[co][v] in[ci][v + off(tap)], rows = co, cols = 64 (ci tap), the
+//               voxel sum split over chunks into FP32 partials reduced in a fixed order.
+// Also: bias add + ReLU in the epilogue, ReLU backward, 2x average pooling and nearest upsampling (both
+// directions), MSE loss, Adam, and trilinear prolongation of a coarse prediction to the solver's grid.
+#include <hip/hip_runtime.h>
+
+#include "helm_internal.h"
+
+namespace helm {
+
+namespace {
+
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+struct bf16 { unsigned short u; };
+
+__device__ __forceinline__ unsigned short f2bf(float f) {   // round to nearest even
+    unsigned u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (unsigned short)(u >> 16);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+
+template <typename T> struct MT;
+template <> struct MT<float> {
+    static constexpr int KL = 1;
+    typedef float op;
+    __device__ static float cvt(float f) { return f; }
+    __device__ static v4f mma(op a, op b, v4f c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+};
+template <> struct MT<bf16> {
+    static constexpr int KL = 4;
+    typedef v4s op;
+    __device__ static bf16 cvt(float f) { bf16 r; r.u = f2bf(f); return r; }
+    __device__ static v4f mma(op a, op b, v4f c) { return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0); }
+};
+
+template <typename T> __device__ __forceinline__ typename MT<T>::op load_op(const T *p);
+template <> __device__ __forceinline__ float load_op<float>(const float *p) { return *p; }
+template <> __device__ __forceinline__ v4s load_op<bf16>(const bf16 *p) {
+    v4s r;
+    r[0] = (short)p[0].u; r[1] = (short)p[1].u; r[2] = (short)p[2].u; r[3] = (short)p[3].u;
+    return r;
+}
+
+constexpr int CT = 64;   // voxels (or k columns) per workgroup
+constexpr int KC = 32;   // k (or voxel) chunk staged in LDS per step
+
+__device__ __forceinline__ void tap_off(int taps, int t, int &dz, int &dy, int &dx) {
+    if (taps == 1) { dz = dy = dx = 0; return; }
+    dz = t / 9 - 1;
+    dy = (t / 3) % 3 - 1;
+    dx = t % 3 - 1;
+}
+
+// forward / dgrad convolution (cubic volume S^3, zero padding, stride 1); out channels at out + co*V
+template <typename T, int COP>
+__global__ __launch_bounds__(256) void k_conv_fwd(const float *__restrict__ in, long long in_bs, int Ci, int S,
+                                                  int taps, const T *__restrict__ wt, int Kp,
+                                                  const float *__restrict__ bias, int Co, float *__restrict__ out,
+                                                  long long out_bs, int relu) {
+    constexpr int KL = MT<T>::KL;
+    constexpr int FR = COP / 16;
+    __shared__ T sA[COP][KC + 4];
+    __shared__ T sB[CT][KC + 4];
+    const int V = S * S * S;
+    const int tiles = (V + CT - 1) / CT;
+    const int b = (int)(blockIdx.x / tiles);
+    const int v0 = (int)(blockIdx.x % tiles) * CT;
+    const float *inb = in + (long long)b * in_bs;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // this thread stages voxel column `col` for k = kq, kq + 4, kq + 8, ... (all chunks in sequence)
+    const int col = tid & 63, kq = tid >> 6;
+    const int v = v0 + col;
+    const bool vin = v < V;
+    const int xw = v % S, yh = (v / S) % S, zd = v / (S * S);
+    int ci = kq / taps, t = kq - (kq / taps) * taps;
+    v4f acc[FR];
+#pragma unroll
+    for (int f = 0; f < FR; ++f) acc[f] = v4f{0, 0, 0, 0};
+    for (int k0 = 0; k0 < Kp; k0 += KC) {
+        __syncthreads();
+        for (int e = tid; e < COP * KC; e += 256) {
+            int r = e / KC, kk = e % KC;
+            sA[r][kk] = wt[(long long)r * Kp + k0 + kk];
+        }
+#pragma unroll
+        for (int j = 0; j < KC / 4; ++j) {
+            float val = 0.f;
+            if (vin && ci < Ci) {
+                int dz = 0, dy = 0, dx = 0;
+                if (taps == 27) { dz = t / 9 - 1; dy = (t / 3) % 3 - 1; dx = t % 3 - 1; }
+                const int zz = zd + dz, yy = yh + dy, xx = xw + dx;
+                if ((unsigned)zz < (unsigned)S && (unsigned)yy < (unsigned)S && (unsigned)xx < (unsigned)S)
+                    val = inb[(long long)ci * V + (zz * S + yy) * S + xx];
+            }
+            sB[col][kq + 4 * j] = MT<T>::cvt(val);
+            t += 4;
+            while (t >= taps) { t -= taps; ++ci; }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < KC; ks += 4 * KL) {
+            const int kofs = ks + KL * (lane >> 4);
+            typename MT<T>::op bf = load_op<T>(&sB[wave * 16 + (lane & 15)][kofs]);
+#pragma unroll
+            for (int f = 0; f < FR; ++f) {
+                typename MT<T>::op af = load_op<T>(&sA[f * 16 + (lane & 15)][kofs]);
+                acc[f] = MT<T>::mma(af, bf, acc[f]);
+            }
+        }
+    }
+    float *outb = out + (long long)b * out_bs;
+    const int vo = v0 + wave * 16 + (lane & 15);
+#pragma unroll
+    for (int f = 0; f < FR; ++f)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            int co = f * 16 + 4 * (lane >> 4) + r;
+            if (co < Co && vo < V) {
+                float y = acc[f][r] + (bias ? bias[co] : 0.f);
+                if (relu) y = fmaxf(y, 0.f);
+                outb[(long long)co * V + vo] = y;
+            }
+        }
+}
+
+// weight gradient partials: part[ch][co][k] = sum over voxel chunk ch of g[co][v] X[k][v]
+// (u = b V + v runs over the batch's voxels; chunk ch covers u in [ch vchunk, (ch+1) vchunk))
+template <typename T, int COP>
+__global__ __launch_bounds__(256) void k_conv_wgrad(const float *__restrict__ g, long long g_bs, int Co,
+                                                    const float *__restrict__ in, long long in_bs, int Ci, int S,
+                                                    int taps, int B, int Kp, int vchunk, float *__restrict__ part) {
+    constexpr int KL = MT<T>::KL;
+    constexpr int FR = COP / 16;
+    __shared__ T sA[COP][KC + 4];
+    __shared__ T sB[CT][KC + 4];
+    const int V = S * S * S;
+    const int NV = V * B;
+    const int ktiles = Kp / CT;
+    const int kt = blockIdx.x % ktiles, ch = blockIdx.x / ktiles;
+    const int vs = ch * vchunk, ve = vs + vchunk < NV ? vs + vchunk : NV;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // g tile: this thread loads voxel kk_a of each chunk for rows ra, ra + 8, ...
+    const int kk_a = tid & 31, ra = tid >> 5;
+    // im2col tile: this thread owns column k (fixed ci, tap) and voxels kq, kq + 4, ... of each chunk
+    const int colk = tid & 63, kq = tid >> 6;
+    const int k = kt * CT + colk;
+    const bool kin = k < Ci * taps;
+    const int ci = k / taps, t = k - (k / taps) * taps;
+    int dz = 0, dy = 0, dx = 0;
+    if (taps == 27) { dz = t / 9 - 1; dy = (t / 3) % 3 - 1; dx = t % 3 - 1; }
+    v4f acc[FR];
+#pragma unroll
+    for (int f = 0; f < FR; ++f) acc[f] = v4f{0, 0, 0, 0};
+    for (int u0 = vs; u0 < ve; u0 += KC) {
+        __syncthreads();
+        {
+            const int u = u0 + kk_a;
+            const bool uin = u < ve;
+            const int b = u / V, v = u - (u / V) * V;
+            const float *gp = g + (long long)b * g_bs + v;
+            for (int r = ra; r < COP; r += 8)
+                sA[r][kk_a] = MT<T>::cvt(uin && r < Co ? gp[(long long)r * V] : 0.f);
+        }
+        {
+            int u = u0 + kq;
+            int b = u / V, rem = u - (u / V) * V;
+            int zd = rem / (S * S), yh = (rem / S) % S, xw = rem % S;
+#pragma unroll
+            for (int j = 0; j < KC / 4; ++j) {
+                float val = 0.f;
+                if (kin && u < ve) {
+                    const int zz = zd + dz, yy = yh + dy, xx = xw + dx;
+                    if ((unsigned)zz < (unsigned)S && (unsigned)yy < (unsigned)S && (unsigned)xx < (unsigned)S)
+                        val = in[(long long)b * in_bs + (long long)ci * V + (zz * S + yy) * S + xx];
+                }
+                sB[colk][kq + 4 * j] = MT<T>::cvt(val);
+                u += 4;
+                xw += 4;
+                while (xw >= S) { xw -= S; ++yh; }
+                while (yh >= S) { yh -= S; ++zd; }
+                while (zd >= S) { zd -= S; ++b; }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < KC; ks += 4 * KL) {
+            const int kofs = ks + KL * (lane >> 4);
+            typename MT<T>::op bf = load_op<T>(&sB[wave * 16 + (lane & 15)][kofs]);
+#pragma unroll
+            for (int f = 0; f < FR; ++f) {
+                typename MT<T>::op af = load_op<T>(&sA[f * 16 + (lane & 15)][kofs]);
+                acc[f] = MT<T>::mma(af, bf, acc[f]);
+            }
+        }
+    }
+    float *pp = part + (long long)ch * COP * Kp;
+    const int kw = kt * CT + wave * 16 + (lane & 15);
+#pragma unroll
+    for (int f = 0; f < FR; ++f)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) pp[(long long)(f * 16 + 4 * (lane >> 4) + r) * Kp + kw] = acc[f][r];
+}
+
+// dW[co][k] = sum_ch part[ch][co][k] (fixed order), k < K, co < Co
+__global__ void k_wgrad_reduce(const float *__restrict__ part, int nch, int COP, int Kp, int Co, int K,
+                               float *__restrict__ dW) {
+    long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= (long long)Co * K) return;
+    int co = (int)(i / K), k = (int)(i % K);
+    float s = 0.f;
+    for (int c = 0; c < nch; ++c) s += part[((long long)c * COP + co) * Kp + k];
+    dW[i] = s;
+}
+
+// db[co] = sum_{b,v} g[b][co][v]: block (co, s) sums slice s of the B V voxels into part[co][s]; a second
+// kernel adds the slices in order
+constexpr int BG_SLICES = 64;
+__global__ __launch_bounds__(256) void k_bias_part(const float *__restrict__ g, long long g_bs, int B, int V,
+                                                   float *__restrict__ part) {
+    __shared__ float sm[256];
+    const int co = blockIdx.x / BG_SLICES, sl = blockIdx.x % BG_SLICES;
+    const int NV = B * V;
+    const int per = (NV + BG_SLICES - 1) / BG_SLICES;
+    const int u0 = sl * per, u1 = u0 + per < NV ? u0 + per : NV;
+    float s = 0.f;
+    for (int u = u0 + threadIdx.x; u < u1; u += 256) {
+        const int b = u / V;
+        s += g[(long long)b * g_bs + (long long)co * V + (u - b * V)];
+    }
+    sm[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) sm[threadIdx.x] += sm[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sm[0];
+}
+__global__ void k_bias_reduce(const float *__restrict__ part, int Co, float *__restrict__ db) {
+    const int co = blockIdx.x * blockDim.x + threadIdx.x;
+    if (co >= Co) return;
+    float s = 0.f;
+    for (int i = 0; i < BG_SLICES; ++i) s += part[co * BG_SLICES + i];
+    db[co] = s;
+}
+
+// pack FP32 weights W[co][k] (k = ci*taps + tap) into the padded operand layout wt[COP][Kp];
+// transpose = 1 builds the dgrad weights W'[ci][co*taps + (taps-1-tap)] from W (Co, Ci swapped)
+template <typename T>
+__global__ void k_pack_weights(const float *__restrict__ W, int Co, int Ci, int taps, int transpose, int COP, int Kp,
+                               T *__restrict__ wt) {
+    long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= (long long)COP * Kp) return;
+    int r = (int)(i / Kp), k = (int)(i % Kp);
+    float v = 0.f;
+    if (!transpose) {
+        if (r < Co && k < Ci * taps) v = W[(long long)r * Ci * taps + k];
+    } else {   // r = ci (row of W'), k = co*taps + tap'
+        if (r < Ci && k < Co * taps) {
+            int co = k / taps, tp = k % taps;
+            v = W[(long long)co * Ci * taps + (long long)r * taps + (taps - 1 - tp)];
+        }
+    }
+    wt[i] = MT<T>::cvt(v);
+}
+
+__global__ void k_relu_bwd(float *__restrict__ g, long long g_bs, const float *__restrict__ y, long long y_bs,
+                           long long per, int B) {
+    long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= per * B) return;
+    long long b = i / per, o = i % per;
+    if (!(y[b * y_bs + o] > 0.f)) g[b * g_bs + o] = 0.f;
+}
+
+// 2x average pooling S -> S/2 over C channels; backward spreads g/8 to the 8 children (accumulate = add)
+__global__ void k_pool_fwd(const float *__restrict__ in, long long in_bs, float *__restrict__ out, long long out_bs,
+                           int C, int S, int B) {
+    const int s2 = S / 2;
+    const long long per = (long long)C * s2 * s2 * s2;
+    long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= per * B) return;
+    long long b = i / per, o = i % per;
+    int c = (int)(o / ((long long)s2 * s2 * s2));
+    long long r = o % ((long long)s2 * s2 * s2);
+    int x = (int)(r % s2), y = (int)((r / s2) % s2), z = (int)(r / ((long long)s2 * s2));
+    const float *p = in + b * in_bs + (long long)c * S * S * S;
+    float s = 0.f;
+    for (int dz = 0; dz < 2; ++dz)
+        for (int dy = 0; dy < 2; ++dy)
+            for (int dx = 0; dx < 2; ++dx) s += p[((long long)(2 * z + dz) * S + 2 * y + dy) * S + 2 * x + dx];
+    out[b * out_bs + o] = 0.125f * s;
+}
+__global__ void k_pool_bwd(const float *__restrict__ gout, long long gout_bs, float *__restrict__ gin,
+                           long long gin_bs, int C, int S, int B, int accumulate) {
+    const int s2 = S / 2;
+    const long long per = (long long)C * S * S * S;
+    long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= per * B) return;
+    long long b = i / per, o = i % per;
+    int c = (int)(o / ((long long)S * S * S));
+    long long r = o % ((long long)S * S * S);
+    int x = (int)(r % S), y = (int)((r / S) % S), z = (int)(r / ((long long)S * S));
+    float v = 0.125f * gout[b * gout_bs + (long long)c * s2 * s2 * s2 + ((long long)(z / 2) * s2 + y / 2) * s2 + x / 2];
+    float *q = gin + b * gin_bs + o;
+    *q = accumulate ? *q + v : v;
+}
+
+// nearest 2x upsampling S -> 2S; backward sums the 8 children
+__global__ void k_up_fwd(const float *__restrict__ in, long long in_bs, float *__restrict__ out, long long out_bs,
+                         int C, int S, int B) {
+    const int S2 = 2 * S;
+    const long long per = (long long)C * S2 * S2 * S2;
+    long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= per * B) return;
+    long long b = i / per, o = i % per;
+    int c = (int)(o / ((long long)S2 * S2 * S2));
+    long long r = o % ((long long)S2 * S2 * S2);
+    int x = (int)(r % S2), y = (int)((r / S2) % S2), z = (int)(r / ((long long)S2 * S2));
+    out[b * out_bs + o] = in[b * in_bs + (long long)c * S * S * S + ((long long)(z / 2) * S + y / 2) * S + x / 2];
+}
+__global__ void k_up_bwd(const float *__restrict__ gout, long long gout_bs, float *__restrict__ gin, long long gin_bs,
+                         int C, int S, int B) {
+    const int S2 = 2 * S;
+    const long long per = (long long)C * S * S * S;
+    long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= per * B) return;
+    long long b = i / per, o = i % per;
+    int c = (int)(o / ((long long)S * S * S));
+    long long r = o % ((long long)S * S * S);
+    int x = (int)(r % S), y = (int)((r / S) % S), z = (int)(r / ((long long)S * S));
+    const float *p = gout + b * gout_bs + (long long)c * S2 * S2 * S2;
+    float s = 0.f;
+    for (int dz = 0; dz < 2; ++dz)
+        for (int dy = 0; dy < 2; ++dy)
+            for (int dx = 0; dx < 2; ++dx) s += p[((long long)(2 * z + dz) * S2 + 2 * y + dy) * S2 + 2 * x + dx];
+    gin[b * gin_bs + o] = s;
+}
+
+// MSE: partial sums of (y - t)^2 per block and the gradient 2 (y - t) / N
+__global__ __launch_bounds__(256) void k_mse(const float *__restrict__ y, const float *__restrict__ t, long long n,
+                                             float *__restrict__ g, double *__restrict__ part) {
+    __shared__ double sm[256];
+    long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    double s = 0.0;
+    if (i < n) {
+        float d = y[i] - t[i];
+        g[i] = 2.f * d / (float)n;
+        s = (double)d * d;
+    }
+    sm[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) sm[threadIdx.x] += sm[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sm[0];
+}
+__global__ __launch_bounds__(256) void k_sum_d(const double *__restrict__ part, int np, double *__restrict__ out,
+                                               double scale) {
+    __shared__ double sm[256];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < np; i += 256) s += part[i];
+    sm[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) sm[threadIdx.x] += sm[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = sm[0] * scale;
+}
+
+// Adam on the FP32 master parameters
+__global__ void k_adam(float *__restrict__ w, const float *__restrict__ g, float *__restrict__ m, float *__restrict__ v,
+                       long long n, float lr, float b1, float b2, float eps, float c1, float c2) {
+    long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    float gi = g[i];
+    float mi = b1 * m[i] + (1.f - b1) * gi;
+    float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// trilinear interpolation of a coarse prediction (channels Re, Im on nodes (i+1)/(nc+1)) to the fine nodes
+// (I+1)/(nf+1), times `scale`, written as complex128. Beyond the outermost coarse nodes the values follow the
+// ghost rule of the scheme on the coarse grid, U(-1) = gamma U(0) and U(nc) = gamma U(nc-1) per axis (gamma = 0
+// gives zero extension).
+__global__ void k_prolong(const float *__restrict__ coarse, int nc, double scale, double gre, double gim,
+                          double2 *__restrict__ fine, int nf) {
+    long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    long long nfn = (long long)nf * nf * nf;
+    if (i >= nfn) return;
+    const int F[3] = {(int)(i % nf), (int)((i / nf) % nf), (int)(i / ((long long)nf * nf))};
+    int i0[3];
+    double w1[3];
+    for (int a = 0; a < 3; ++a) {                          // coarse index coordinate (F+1)(nc+1)/(nf+1) - 1
+        long long num = (long long)(F[a] + 1) * (nc + 1);
+        long long q = num / (nf + 1);
+        i0[a] = (int)q - 1;
+        w1[a] = (double)(num - q * (nf + 1)) / (nf + 1);
+    }
+    const long long V = (long long)nc * nc * nc;
+    double re = 0.0, im = 0.0;
+    for (int dz = 0; dz < 2; ++dz)
+        for (int dy = 0; dy < 2; ++dy)
+            for (int dx = 0; dx < 2; ++dx) {
+                const int d[3] = {dx, dy, dz};
+                double w = 1.0, fr = 1.0, fi = 0.0;          // weight and ghost factor gamma^(#clamped axes)
+                int idx[3];
+                for (int a = 0; a < 3; ++a) {
+                    w *= d[a] ? w1[a] : 1.0 - w1[a];
+                    int c = i0[a] + d[a];
+                    if (c < 0 || c >= nc) {
+                        c = c < 0 ? 0 : nc - 1;
+                        const double nr = fr * gre - fi * gim, ni = fr * gim + fi * gre;
+                        fr = nr;
+                        fi = ni;
+                    }
+                    idx[a] = c;
+                }
+                if (w == 0.0) continue;
+                const long long o = ((long long)idx[2] * nc + idx[1]) * nc + idx[0];
+                const double ur = coarse[o], ui = coarse[V + o];
+                re += w * (fr * ur - fi * ui);
+                im += w * (fr * ui + fi * ur);
+            }
+    fine[i] = make_double2(scale * re, scale * im);
+}
+
+// the same prolongation with Keys' cubic convolution (a = -1/2) per axis: coarse indices i0-1 .. i0+2 around
+// the fine node; ghost indices -m and nc-1+m (m = 1, 2) fold onto the boundary node with factor gamma^m
+__global__ void k_prolong3(const float *__restrict__ coarse, int nc, double scale, double gre, double gim,
+                           double2 *__restrict__ fine, int nf) {
+    long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    long long nfn = (long long)nf * nf * nf;
+    if (i >= nfn) return;
+    const int F[3] = {(int)(i % nf), (int)((i / nf) % nf), (int)(i / ((long long)nf * nf))};
+    double w[3][4];
+    int idx[3][4], pw[3][4];
+    for (int a = 0; a < 3; ++a) {
+        long long num = (long long)(F[a] + 1) * (nc + 1);
+        long long q = num / (nf + 1);
+        const int i0 = (int)q - 1;
+        const double t = (double)(num - q * (nf + 1)) / (nf + 1), t2 = t * t, t3 = t2 * t;
+        w[a][0] = -0.5 * t3 + t2 - 0.5 * t;
+        w[a][1] = 1.5 * t3 - 2.5 * t2 + 1.0;
+        w[a][2] = -1.5 * t3 + 2.0 * t2 + 0.5 * t;
+        w[a][3] = 0.5 * t3 - 0.5 * t2;
+        for (int k = 0; k < 4; ++k) {
+            int c = i0 - 1 + k, m = 0;
+            if (c < 0) { m = -c; c = 0; }
+            else if (c >= nc) { m = c - nc + 1; c = nc - 1; }
+            idx[a][k] = c;
+            pw[a][k] = m;
+        }
+    }
+    double gr[7], gi[7];                                   // gamma^0 .. gamma^6
+    gr[0] = 1.0; gi[0] = 0.0;
+    for (int m = 1; m < 7; ++m) { gr[m] = gr[m - 1] * gre - gi[m - 1] * gim; gi[m] = gr[m - 1] * gim + gi[m - 1] * gre; }
+    const long long V = (long long)nc * nc * nc;
+    double re = 0.0, im = 0.0;
+    for (int kz = 0; kz < 4; ++kz)
+        for (int ky = 0; ky < 4; ++ky)
+            for (int kx = 0; kx < 4; ++kx) {
+                const double wt = w[0][kx] * w[1][ky] * w[2][kz];
+                if (wt == 0.0) continue;
+                const int m = pw[0][kx] + pw[1][ky] + pw[2][kz];
+                const long long o = ((long long)idx[2][kz] * nc + idx[1][ky]) * nc + idx[0][kx];
+                const double ur = coarse[o], ui = coarse[V + o];
+                re += wt * (gr[m] * ur - gi[m] * ui);
+                im += wt * (gr[m] * ui + gi[m] * ur);
+            }
+    fine[i] = make_double2(scale * re, scale * im);
+}
+
+// network input from the solver's arrays: node (i, j, l) of the S^3 grid sits at ((i, j, l) + 1)/(S+1) in the unit
+// cube, which is fine-grid index coordinate (i+1)(nf+1)/(S+1) - 1 per axis; k^2 and Re f are interpolated
+// trilinearly there (weights from integer arithmetic, so nested grids inject exactly). Channel 0 =
+// cs (k^2/k0^2 - 1), channel 1 = fs Re f. Arrays carry `halo` >= 1 cells; the upper neighbour index can be nf
+// (a halo cell) only with weight zero.
+__global__ void k_features(const double *__restrict__ k2h, const double2 *__restrict__ fh, int halo, int nf, int S,
+                           double inv_k0sq, double cs, double fs, float *__restrict__ x) {
+    long long v = (long long)blockIdx.x * 256 + threadIdx.x;
+    const long long V = (long long)S * S * S;
+    if (v >= V) return;
+    const int c[3] = {(int)(v % S), (int)((v / S) % S), (int)(v / ((long long)S * S))};
+    int i0[3];
+    double w1[3];
+    for (int a = 0; a < 3; ++a) {
+        long long num = (long long)(c[a] + 1) * (nf + 1);
+        i0[a] = (int)(num / (S + 1)) - 1;
+        w1[a] = (double)(num % (S + 1)) / (S + 1);
+    }
+    const long long P = nf + 2 * halo;
+    double k2 = 0.0, fr = 0.0;
+    for (int dz = 0; dz < 2; ++dz)
+        for (int dy = 0; dy < 2; ++dy)
+            for (int dx = 0; dx < 2; ++dx) {
+                double w = (dx ? w1[0] : 1.0 - w1[0]) * (dy ? w1[1] : 1.0 - w1[1]) * (dz ? w1[2] : 1.0 - w1[2]);
+                if (w == 0.0) continue;
+                long long o = ((long long)(i0[2] + dz + halo) * P + (i0[1] + dy + halo)) * P + (i0[0] + dx + halo);
+                k2 += w * k2h[o];
+                fr += w * fh[o].x;
+            }
+    x[v] = (float)(cs * (k2 * inv_k0sq - 1.0));
+    x[V + v] = (float)(fs * fr);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------------- launchers
+template <typename T>
+hipError_t cnn_conv_fwd_t(const float *in, long long in_bs, int Ci, int S, int taps, const void *wt, int Kp, int COP,
+                          const float *bias, int Co, float *out, long long out_bs, int relu, int B, hipStream_t s) {
+    long long V = (long long)S * S * S;
+    unsigned grid = (unsigned)(B * ((V + CT - 1) / CT));
+    const T *w = (const T *)wt;
+    if (COP == 16) hipLaunchKernelGGL((k_conv_fwd<T, 16>), dim3(grid), dim3(256), 0, s, in, in_bs, Ci, S, taps, w, Kp, bias, Co, out, out_bs, relu);
+    else if (COP == 32) hipLaunchKernelGGL((k_conv_fwd<T, 32>), dim3(grid), dim3(256), 0, s, in, in_bs, Ci, S, taps, w, Kp, bias, Co, out, out_bs, relu);
+    else if (COP == 64) hipLaunchKernelGGL((k_conv_fwd<T, 64>), dim3(grid), dim3(256), 0, s, in, in_bs, Ci, S, taps, w, Kp, bias, Co, out, out_bs, relu);
+    else if (COP == 48) hipLaunchKernelGGL((k_conv_fwd<T, 48>), dim3(grid), dim3(256), 0, s, in, in_bs, Ci, S, taps, w, Kp, bias, Co, out, out_bs, relu);
+    else if (COP == 96) hipLaunchKernelGGL((k_conv_fwd<T, 96>), dim3(grid), dim3(256), 0, s, in, in_bs, Ci, S, taps, w, Kp, bias, Co, out, out_bs, relu);
+    else if (COP == 128) hipLaunchKernelGGL((k_conv_fwd<T, 128>), dim3(grid), dim3(256), 0, s, in, in_bs, Ci, S, taps, w, Kp, bias, Co, out, out_bs, relu);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t cnn_conv_fwd(int use_bf16, const float *in, long long in_bs, int Ci, int S, int taps, const void *wt, int Kp,
+                        int COP, const float *bias, int Co, float *out, long long out_bs, int relu, int B,
+                        hipStream_t s) {
+    return use_bf16 ? cnn_conv_fwd_t<bf16>(in, in_bs, Ci, S, taps, wt, Kp, COP, bias, Co, out, out_bs, relu, B, s)
+                : cnn_conv_fwd_t<float>(in, in_bs, Ci, S, taps, wt, Kp, COP, bias, Co, out, out_bs, relu, B, s);
+}
+
+template <typename T>
+hipError_t cnn_conv_wgrad_t(const float *g, long long g_bs, int Co, int COP, const float *in, long long in_bs, int Ci,
+                            int S, int taps, int B, int Kp, int vchunk, int nch, float *part, hipStream_t s) {
+    unsigned grid = (unsigned)((Kp / CT) * nch);
+    if (COP == 16) hipLaunchKernelGGL((k_conv_wgrad<T, 16>), dim3(grid), dim3(256), 0, s, g, g_bs, Co, in, in_bs, Ci, S, taps, B, Kp, vchunk, part);
+    else if (COP == 32) hipLaunchKernelGGL((k_conv_wgrad<T, 32>), dim3(grid), dim3(256), 0, s, g, g_bs, Co, in, in_bs, Ci, S, taps, B, Kp, vchunk, part);
+    else if (COP == 64) hipLaunchKernelGGL((k_conv_wgrad<T, 64>), dim3(grid), dim3(256), 0, s, g, g_bs, Co, in, in_bs, Ci, S, taps, B, Kp, vchunk, part);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t cnn_conv_wgrad(int use_bf16, const float *g, long long g_bs, int Co, int COP, const float *in, long long in_bs,
+                          int Ci, int S, int taps, int B, int Kp, int vchunk, int nch, float *part, float *dW,
+                          hipStream_t s) {
+    hipError_t e = use_bf16 ? cnn_conv_wgrad_t<bf16>(g, g_bs, Co, COP, in, in_bs, Ci, S, taps, B, Kp, vchunk, nch, part, s)
+                        : cnn_conv_wgrad_t<float>(g, g_bs, Co, COP, in, in_bs, Ci, S, taps, B, Kp, vchunk, nch, part, s);
+    if (e != hipSuccess) return e;
+    long long n = (long long)Co * Ci * taps;
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part, nch, COP, Kp, Co,
+                       Ci * taps, dW);
+    return hipGetLastError();
+}
+
+hipError_t cnn_bias_grad(const float *g, long long g_bs, int B, long long V, int Co, float *part, float *db,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(k_bias_part, dim3(Co * BG_SLICES), dim3(256), 0, s, g, g_bs, B, (int)V, part);
+    hipLaunchKernelGGL(k_bias_reduce, dim3((Co + 63) / 64), dim3(64), 0, s, part, Co, db);
+    return hipGetLastError();
+}
+
+hipError_t cnn_pack_weights(int use_bf16, const float *W, int Co, int Ci, int taps, int transpose, int COP, int Kp,
+                            void *wt, hipStream_t s) {
+    long long n = (long long)COP * Kp;
+    unsigned grid = (unsigned)((n + 255) / 256);
+    if (use_bf16) hipLaunchKernelGGL(k_pack_weights<bf16>, dim3(grid), dim3(256), 0, s, W, Co, Ci, taps, transpose, COP, Kp, (bf16 *)wt);
+    else hipLaunchKernelGGL(k_pack_weights<float>, dim3(grid), dim3(256), 0, s, W, Co, Ci, taps, transpose, COP, Kp, (float *)wt);
+    return hipGetLastError();
+}
+
+hipError_t cnn_relu_bwd(float *g, long long g_bs, const float *y, long long y_bs, long long per, int B, hipStream_t s) {
+    hipLaunchKernelGGL(k_relu_bwd, dim3((unsigned)((per * B + 255) / 256)), dim3(256), 0, s, g, g_bs, y, y_bs, per, B);
+    return hipGetLastError();
+}
+hipError_t cnn_pool_fwd(const float *in, long long in_bs, float *out, long long out_bs, int C, int S, int B, hipStream_t s) {
+    long long n = (long long)C * (S / 2) * (S / 2) * (S / 2) * B;
+    hipLaunchKernelGGL(k_pool_fwd, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, in, in_bs, out, out_bs, C, S, B);
+    return hipGetLastError();
+}
+hipError_t cnn_pool_bwd(const float *gout, long long gout_bs, float *gin, long long gin_bs, int C, int S, int B,
+                        int accumulate, hipStream_t s) {
+    long long n = (long long)C * S * S * S * B;
+    hipLaunchKernelGGL(k_pool_bwd, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, gout, gout_bs, gin, gin_bs, C, S, B, accumulate);
+    return hipGetLastError();
+}
+hipError_t cnn_up_fwd(const float *in, long long in_bs, float *out, long long out_bs, int C, int S, int B, hipStream_t s) {
+    long long n = (long long)C * 8 * S * S * S * B;
+    hipLaunchKernelGGL(k_up_fwd, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, in, in_bs, out, out_bs, C, S, B);
+    return hipGetLastError();
+}
+hipError_t cnn_up_bwd(const float *gout, long long gout_bs, float *gin, long long gin_bs, int C, int S, int B, hipStream_t s) {
+    long long n = (long long)C * S * S * S * B;
+    hipLaunchKernelGGL(k_up_bwd, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, gout, gout_bs, gin, gin_bs, C, S, B);
+    return hipGetLastError();
+}
+hipError_t cnn_mse(const float *y, const float *t, long long n, float *g, double *part, double *loss, hipStream_t s) {
+    unsigned nb = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(k_mse, dim3(nb), dim3(256), 0, s, y, t, n, g, part);
+    hipLaunchKernelGGL(k_sum_d, dim3(1), dim3(256), 0, s, part, (int)nb, loss, 1.0 / (double)n);
+    return hipGetLastError();
+}
+hipError_t cnn_adam(float *w, const float *g, float *m, float *v, long long n, float lr, float b1, float b2, float eps,
+                    float c1, float c2, hipStream_t s) {
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, w, g, m, v, n, lr, b1, b2, eps, c1, c2);
+    return hipGetLastError();
+}
+hipError_t cnn_features(const double *k2h, const double2 *fh, int halo, int nf, int S, double k0sq, double cs,
+                        double fs, float *x, hipStream_t s) {
+    long long V = (long long)S * S * S;
+    hipLaunchKernelGGL(k_features, dim3((unsigned)((V + 255) / 256)), dim3(256), 0, s, k2h, fh, halo, nf, S,
+                       1.0 / k0sq, cs, fs, x);
+    return hipGetLastError();
+}
+hipError_t cnn_prolong(const float *coarse, int nc, double scale, double gre, double gim, int cubic, double2 *fine,
+                       int nf, hipStream_t s) {
+    long long n = (long long)nf * nf * nf;
+    if (cubic)
+        hipLaunchKernelGGL(k_prolong3, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, coarse, nc, scale, gre, gim,
+                           fine, nf);
+    else
+        hipLaunchKernelGGL(k_prolong, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, coarse, nc, scale, gre, gim,
+                           fine, nf);
+    return hipGetLastError();
+}
+
+}  // namespace helm

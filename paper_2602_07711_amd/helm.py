@@ -98,6 +98,31 @@ def lib():
     L.helm_batch_destroy.restype = None
     L.helm_batch_last_error.argtypes = [c_void_p]
     L.helm_batch_last_error.restype = ctypes.c_char_p
+    L.helm_cnn_create.argtypes = [POINTER(c_void_p), c_int, c_int, c_int, ctypes.c_ulonglong, c_void_p]
+    L.helm_cnn_create.restype = c_int
+    L.helm_cnn_num_params.argtypes = [c_void_p]
+    L.helm_cnn_num_params.restype = c_longlong
+    for name in ("helm_cnn_get_params", "helm_cnn_set_params", "helm_cnn_get_grads"):
+        getattr(L, name).argtypes = [c_void_p, c_void_p]
+        getattr(L, name).restype = c_int
+    L.helm_cnn_forward.argtypes = [c_void_p, c_void_p, c_void_p, c_int]
+    L.helm_cnn_forward.restype = c_int
+    L.helm_cnn_loss_grad.argtypes = [c_void_p, c_void_p, c_void_p, c_int, POINTER(c_double)]
+    L.helm_cnn_loss_grad.restype = c_int
+    L.helm_cnn_adam_step.argtypes = [c_void_p, c_double]
+    L.helm_cnn_adam_step.restype = c_int
+    L.helm_cnn_train_step.argtypes = [c_void_p, c_void_p, c_void_p, c_int, c_double, POINTER(c_double)]
+    L.helm_cnn_train_step.restype = c_int
+    L.helm_cnn_prolong.argtypes = [c_void_p, c_void_p, c_int, c_double, c_double, c_double, c_int, c_void_p,
+                                   c_int]
+    L.helm_cnn_prolong.restype = c_int
+    L.helm_cnn_features.argtypes = [c_void_p, c_void_p, c_void_p, c_int, c_int, c_double, c_double, c_double,
+                                    c_void_p]
+    L.helm_cnn_features.restype = c_int
+    L.helm_cnn_last_error.argtypes = [c_void_p]
+    L.helm_cnn_last_error.restype = ctypes.c_char_p
+    L.helm_cnn_destroy.argtypes = [c_void_p]
+    L.helm_cnn_destroy.restype = None
     _lib = L
     return L
 
@@ -347,3 +372,125 @@ def helm_eig1d(n: int, gamma: complex):
     if st != HELM_OK:
         raise HelmError(st, "helm_eig1d failed")
     return d, V, Vi
+
+
+# ------------------------------------------------------------------------------------------ learned warm start
+class Cnn:
+    """Owns a helm_cnn* (the warm-start encoder-decoder network of include/helm.h). All its work is ordered on
+    the stream that was current at creation."""
+
+    def __init__(self, size: int, max_batch: int = 1, bf16: bool = True, seed: int = 0):
+        L = lib()
+        self.size = int(size)
+        self.max_batch = int(max_batch)
+        self.bf16 = bool(bf16)
+        self.stream = torch.cuda.current_stream()
+        p = c_void_p()
+        st = L.helm_cnn_create(byref(p), self.size, self.max_batch, int(self.bf16), ctypes.c_ulonglong(seed),
+                               c_void_p(self.stream.cuda_stream))
+        if st != HELM_OK:
+            raise HelmError(st, L.helm_cnn_last_error(None).decode())
+        self.ptr = p
+        self.num_params = int(L.helm_cnn_num_params(p))
+
+    def _raise(self, st):
+        if st != HELM_OK:
+            raise HelmError(st, lib().helm_cnn_last_error(self.ptr).decode())
+
+    def _batch(self, x: torch.Tensor, name: str) -> int:
+        V = self.size ** 3
+        if x.dim() != 3 or x.shape[1:] != (2, V):
+            raise ValueError(f"{name} must have shape [B, 2, {V}], got {tuple(x.shape)}")
+        B = x.shape[0]
+        if not 1 <= B <= self.max_batch:
+            raise ValueError(f"batch {B} outside 1..{self.max_batch}")
+        _check(x, torch.float32, B * 2 * V, name)
+        return B
+
+    def params(self) -> torch.Tensor:
+        out = torch.empty(self.num_params, dtype=torch.float32)
+        self._raise(lib().helm_cnn_get_params(self.ptr, c_void_p(out.data_ptr())))
+        return out
+
+    def set_params(self, w: torch.Tensor):
+        w = w.detach().to(torch.float32).contiguous().cpu()
+        if w.numel() != self.num_params:
+            raise ValueError(f"expected {self.num_params} parameters, got {w.numel()}")
+        self._raise(lib().helm_cnn_set_params(self.ptr, c_void_p(w.data_ptr())))
+
+    def grads(self) -> torch.Tensor:
+        out = torch.empty(self.num_params, dtype=torch.float32)
+        self._raise(lib().helm_cnn_get_grads(self.ptr, c_void_p(out.data_ptr())))
+        return out
+
+    def forward(self, x: torch.Tensor, y: torch.Tensor | None = None) -> torch.Tensor:
+        B = self._batch(x, "x")
+        if y is None:
+            y = torch.empty_like(x)
+        self._batch(y, "y")
+        self._raise(lib().helm_cnn_forward(self.ptr, c_void_p(x.data_ptr()), c_void_p(y.data_ptr()), B))
+        return y
+
+    def loss_grad(self, x: torch.Tensor, t: torch.Tensor) -> float:
+        B = self._batch(x, "x")
+        if self._batch(t, "t") != B:
+            raise ValueError("x and t batch sizes differ")
+        loss = c_double()
+        self._raise(lib().helm_cnn_loss_grad(self.ptr, c_void_p(x.data_ptr()), c_void_p(t.data_ptr()), B,
+                                             byref(loss)))
+        return loss.value
+
+    def adam_step(self, lr: float):
+        self._raise(lib().helm_cnn_adam_step(self.ptr, float(lr)))
+
+    def train_step(self, x: torch.Tensor, t: torch.Tensor, lr: float, want_loss: bool = True) -> float | None:
+        B = self._batch(x, "x")
+        if self._batch(t, "t") != B:
+            raise ValueError("x and t batch sizes differ")
+        loss = c_double()
+        self._raise(lib().helm_cnn_train_step(self.ptr, c_void_p(x.data_ptr()), c_void_p(t.data_ptr()), B,
+                                              float(lr), byref(loss) if want_loss else None))
+        return loss.value if want_loss else None
+
+    def prolong(self, coarse: torch.Tensor, nf: int, scale: float = 1.0, gamma: complex = 0.0,
+                fine: torch.Tensor | None = None, cubic: bool = False):
+        """Trilinear (or cubic) prolongation of a [2, nc^3] prediction to a complex128 vector of nf^3 entries;
+        `gamma` is the coarse grid's ghost factor (0: zero extension)."""
+        nc = round((coarse.numel() / 2) ** (1 / 3))
+        if 2 * nc ** 3 != coarse.numel():
+            raise ValueError("coarse must hold 2 * nc^3 values")
+        _check(coarse, torch.float32, 2 * nc ** 3, "coarse")
+        if fine is None:
+            fine = torch.empty(nf ** 3, dtype=torch.complex128, device=coarse.device)
+        _check(fine, torch.complex128, nf ** 3, "fine")
+        g = complex(gamma)
+        self._raise(lib().helm_cnn_prolong(self.ptr, c_void_p(coarse.data_ptr()), nc, float(scale), g.real, g.imag,
+                                           int(bool(cubic)), c_void_p(fine.data_ptr()), nf))
+        return fine
+
+    def features(self, k2_halo: torch.Tensor, f_halo: torch.Tensor, k0: float, c_scale: float = 1.0,
+                 f_scale: float = 1.0, halo: int = 2, out: torch.Tensor | None = None) -> torch.Tensor:
+        """Network input [1, 2, S^3] from the solver's k^2 (float64) and f (complex128) arrays with halo."""
+        P = round(k2_halo.numel() ** (1 / 3))
+        if P ** 3 != k2_halo.numel():
+            raise ValueError("k2_halo must be a cube")
+        _check(k2_halo, torch.float64, P ** 3, "k2_halo")
+        _check(f_halo, torch.complex128, P ** 3, "f_halo")
+        if out is None:
+            out = torch.empty(1, 2, self.size ** 3, dtype=torch.float32, device=k2_halo.device)
+        _check(out, torch.float32, 2 * self.size ** 3, "out")
+        self._raise(lib().helm_cnn_features(self.ptr, c_void_p(k2_halo.data_ptr()), c_void_p(f_halo.data_ptr()),
+                                            halo, P - 2 * halo, float(k0), float(c_scale), float(f_scale),
+                                            c_void_p(out.data_ptr())))
+        return out
+
+    def close(self):
+        if getattr(self, "ptr", None):
+            lib().helm_cnn_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

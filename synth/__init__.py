@@ -11,5 +11,6 @@ from .media import (  # noqa: F401
     unit_directions,
     plane_wave_sources,
     uneven_problem_set,
+    warmstart_problem,
     workload,
 )

@@ -96,6 +96,14 @@ def uneven_problem_set(count: int = 16, n_lo: int = 64, n_hi: int = 160, k_lo: f
     return list(zip(ns, ks.tolist()))
 
 
+def warmstart_problem(n: int, seed: int, k0: float = 60.0, sigma: float = 0.03):
+    """Learned-warm-start sample: the four-inclusion medium (centres seeded by `seed`, amplitude 0.3, width 0.1)
+    with a unit-peak Gaussian source of fixed physical width `sigma` at the centre, 6th order. The width does
+    not scale with h, so grids of different N discretise the same continuous problem."""
+    return dict(n=n, h=1.0 / (n + 1), order=6, k0=k0, k2=inclusions_k2(n, k0, seed=seed),
+                f=gaussian_source(n, sigma_cells=sigma * (n + 1)))
+
+
 def workload(name: str, n: int | None = None):
     """The named synthetic workloads. Returns dict(n, h, order, k0, k2 (halo), f (halo), m, ...).
 
