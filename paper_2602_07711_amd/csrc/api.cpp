@@ -98,6 +98,14 @@ GemmDesc desc_y(const Ctx &c) {
     return d;
 }
 
+// pivots entering each z-chunk of the partitioned tridiagonal solve, per set of x-y eigenvalues
+helm_status ensure_tpiv(Ctx &c, const double2 *dx, const double2 *dy, double2 **piv) {
+    if (*piv) return HELM_OK;
+    ST_TRY(dalloc(c, piv, (size_t)tri_chunks(c.nz) * c.nx * c.ny));
+    HIP_TRY(launch_tri_pivots(dx, dy, c.nx, c.ny, c.nz, c.ax, c.ay, c.c0, d2(c.gamma[2]), *piv, c.stream));
+    return HELM_OK;
+}
+
 helm_status ensure_fp32_work(Ctx &c) {
     if (c.t1f) return HELM_OK;
     ST_TRY(dalloc(c, &c.t1f, (size_t)c.n));
@@ -113,14 +121,16 @@ helm_status eigt_apply(Ctx &c, const double2 *y, double2 *z, bool fp32) {
     if (!fp32) {
         HIP_TRY(timed(c, HELM_K_GEMM_X64, gemm_flops(dx), [&] { return launch_gemm_z64(dx, y, c.BxF, c.t1, c.stream, 0, c.gemm_cfg[0]); }));
         HIP_TRY(timed(c, HELM_K_GEMM_Y64, gemm_flops(dy), [&] { return launch_gemm_z64(dy, c.AyF, c.t1, c.t2, c.stream, 0, c.gemm_cfg[1]); }));
-        HIP_TRY(timed(c, HELM_K_TRIDIAG64, 32.0 * c.n, [&] { return launch_tridiag_z64(c.t2, c.t2, c.cp, c.dxe, c.dye, c.nx, c.ny, c.nz, c.ax, c.ay, c.c0, gz, scale, c.stream); }));
+        ST_TRY(ensure_tpiv(c, c.dxe, c.dye, &c.tpiv_eig));
+        HIP_TRY(timed(c, HELM_K_TRIDIAG64, 32.0 * c.n, [&] { return launch_tridiag_chunk_z64(c.t2, c.t2, c.tpiv_eig, c.dxe, c.dye, c.nx, c.ny, c.nz, c.ax, c.ay, c.c0, gz, scale, c.stream); }));
         HIP_TRY(timed(c, HELM_K_GEMM_Y64, gemm_flops(dy), [&] { return launch_gemm_z64(dy, c.AyI, c.t2, c.t1, c.stream, 0, c.gemm_cfg[1]); }));
         HIP_TRY(timed(c, HELM_K_GEMM_X64, gemm_flops(dx), [&] { return launch_gemm_z64(dx, c.t1, c.BxI, z, c.stream, 0, c.gemm_cfg[0]); }));
     } else {
         ST_TRY(ensure_fp32_work(c));
         HIP_TRY(timed(c, HELM_K_GEMM_X32, gemm_flops(dx), [&] { return launch_gemm_z32_in64(dx, y, c.BxF32, c.t1f, c.stream, 0, c.gemm_cfg[2]); }));
         HIP_TRY(timed(c, HELM_K_GEMM_Y32, gemm_flops(dy), [&] { return launch_gemm_z32(dy, c.AyF32, c.t1f, c.t2f, c.stream, 0, c.gemm_cfg[3]); }));
-        HIP_TRY(timed(c, HELM_K_TRIDIAG32, 16.0 * c.n, [&] { return launch_tridiag_z32(c.t2f, c.t2f, c.cpf, c.dxe, c.dye, c.nx, c.ny, c.nz, c.ax, c.ay, c.c0, gz, scale, c.stream); }));
+        ST_TRY(ensure_tpiv(c, c.dxe, c.dye, &c.tpiv_eig));
+        HIP_TRY(timed(c, HELM_K_TRIDIAG32, 16.0 * c.n, [&] { return launch_tridiag_chunk_z32(c.t2f, c.t2f, c.tpiv_eig, c.dxe, c.dye, c.nx, c.ny, c.nz, c.ax, c.ay, c.c0, gz, scale, c.stream); }));
         HIP_TRY(timed(c, HELM_K_GEMM_Y32, gemm_flops(dy), [&] { return launch_gemm_z32(dy, c.AyI32, c.t2f, c.t1f, c.stream, 0, c.gemm_cfg[3]); }));
         HIP_TRY(timed(c, HELM_K_GEMM_X32, gemm_flops(dx), [&] { return launch_gemm_z32_out64(dx, c.t1f, c.BxI32, z, c.stream, 0, c.gemm_cfg[2]); }));
     }
@@ -200,6 +210,8 @@ helm_status ensure_pfft(Ctx &c, bool fp32) {
 
 helm_status pfft_apply(Ctx &c, const double2 *y, double2 *z, bool fp32) {
     ST_TRY(ensure_pfft(c, fp32));
+    ST_TRY(ensure_tpiv(c, c.dxe, c.dye, &c.tpiv_eig));
+    ST_TRY(ensure_tpiv(c, c.pfft->dFx, c.pfft->dFy, &c.tpiv_dir));
     GemmDesc dx = desc_x(c), dy = desc_y(c);
     PfftPlan &P = *c.pfft;
     const double2 gz = d2(c.gamma[2]);
@@ -212,13 +224,13 @@ helm_status pfft_apply(Ctx &c, const double2 *y, double2 *z, bool fp32) {
         auto &m = P.m64;
         HIP_TRY(timed(c, HELM_K_PFFT, 4.0 * dx.M * (double)dx.N * dx.K, [&] { return launch_gemm_z64(dx, y, m.Sx, c.t1, c.stream, 2); }));
         HIP_TRY(timed(c, HELM_K_PFFT, 4.0 * dy.M * (double)dy.N * dy.K * dy.batch, [&] { return launch_gemm_z64(dy, m.Sy, c.t1, m.yhat, c.stream, 1); }));
-        HIP_TRY(timed(c, HELM_K_TRIDIAG64, 32.0 * c.n, [&] { return launch_tridiag_z64(m.yhat, c.t2, c.cp, P.dFx, P.dFy, nx, ny, nz, c.ax, c.ay, c.c0, gz, hz2, c.stream); }));
+        HIP_TRY(timed(c, HELM_K_TRIDIAG64, 32.0 * c.n, [&] { return launch_tridiag_chunk_z64(m.yhat, c.t2, c.tpiv_dir, P.dFx, P.dFy, nx, ny, nz, c.ax, c.ay, c.c0, gz, hz2, c.stream); }));
         HIP_TRY(timed(c, HELM_K_RING, 16.0 * c.n + ring_work, [&] { return launch_ring_inverse_z64(c.t2, m.ringT, m.Sy, m.Sy, m.Sx, m.Sx, nx, ny, nz, c.stream); }));
         HIP_TRY(timed(c, HELM_K_RING, 16.0 * c.n + ring_work, [&] { return launch_ring_forward_z64(m.ringT, nullptr, nullptr, 0.0, c.t2, c.AyF, m.VyiT, m.Vxi, c.BxF, ex, ey, nx, ny, nz, c.stream); }));
-        HIP_TRY(timed(c, HELM_K_TRIDIAG64, 32.0 * c.n, [&] { return launch_tridiag_z64(c.t2, c.t2, c.cp, c.dxe, c.dye, nx, ny, nz, c.ax, c.ay, c.c0, gz, 1.0, c.stream); }));
+        HIP_TRY(timed(c, HELM_K_TRIDIAG64, 32.0 * c.n, [&] { return launch_tridiag_chunk_z64(c.t2, c.t2, c.tpiv_eig, c.dxe, c.dye, nx, ny, nz, c.ax, c.ay, c.c0, gz, 1.0, c.stream); }));
         HIP_TRY(timed(c, HELM_K_RING, 16.0 * c.n + ring_work, [&] { return launch_ring_inverse_z64(c.t2, m.ringW, c.AyI, m.VyT, m.Vx, c.BxI, nx, ny, nz, c.stream); }));
         HIP_TRY(timed(c, HELM_K_RING, 32.0 * c.n + 2 * ring_work, [&] { return launch_ring_forward_z64(m.ringT, m.ringW, m.yhat, hz2, c.t2, m.Sy, m.Sy, m.Sx, m.Sx, ex, ey, nx, ny, nz, c.stream); }));
-        HIP_TRY(timed(c, HELM_K_TRIDIAG64, 32.0 * c.n, [&] { return launch_tridiag_z64(c.t2, c.t2, c.cp, P.dFx, P.dFy, nx, ny, nz, c.ax, c.ay, c.c0, gz, 1.0, c.stream); }));
+        HIP_TRY(timed(c, HELM_K_TRIDIAG64, 32.0 * c.n, [&] { return launch_tridiag_chunk_z64(c.t2, c.t2, c.tpiv_dir, P.dFx, P.dFy, nx, ny, nz, c.ax, c.ay, c.c0, gz, 1.0, c.stream); }));
         HIP_TRY(timed(c, HELM_K_PFFT, 4.0 * dy.M * (double)dy.N * dy.K * dy.batch, [&] { return launch_gemm_z64(dy, m.Sy, c.t2, c.t1, c.stream, 1); }));
         HIP_TRY(timed(c, HELM_K_PFFT, 4.0 * dx.M * (double)dx.N * dx.K, [&] { return launch_gemm_z64(dx, c.t1, m.Sx, z, c.stream, 2); }));
     } else {
@@ -226,13 +238,13 @@ helm_status pfft_apply(Ctx &c, const double2 *y, double2 *z, bool fp32) {
         auto &m = P.m32;
         HIP_TRY(timed(c, HELM_K_PFFT, 4.0 * dx.M * (double)dx.N * dx.K, [&] { return launch_gemm_z32_in64(dx, y, m.Sx, c.t1f, c.stream, 2); }));
         HIP_TRY(timed(c, HELM_K_PFFT, 4.0 * dy.M * (double)dy.N * dy.K * dy.batch, [&] { return launch_gemm_z32(dy, m.Sy, c.t1f, m.yhat, c.stream, 1); }));
-        HIP_TRY(timed(c, HELM_K_TRIDIAG32, 16.0 * c.n, [&] { return launch_tridiag_z32(m.yhat, c.t2f, c.cpf, P.dFx, P.dFy, nx, ny, nz, c.ax, c.ay, c.c0, gz, hz2, c.stream); }));
+        HIP_TRY(timed(c, HELM_K_TRIDIAG32, 16.0 * c.n, [&] { return launch_tridiag_chunk_z32(m.yhat, c.t2f, c.tpiv_dir, P.dFx, P.dFy, nx, ny, nz, c.ax, c.ay, c.c0, gz, hz2, c.stream); }));
         HIP_TRY(timed(c, HELM_K_RING, 8.0 * c.n + ring_work / 2, [&] { return launch_ring_inverse_z32(c.t2f, m.ringT, m.Sy, m.Sy, m.Sx, m.Sx, nx, ny, nz, c.stream); }));
         HIP_TRY(timed(c, HELM_K_RING, 8.0 * c.n + ring_work / 2, [&] { return launch_ring_forward_z32(m.ringT, nullptr, nullptr, 0.0, c.t2f, c.AyF32, m.VyiT, m.Vxi, c.BxF32, ex, ey, nx, ny, nz, c.stream); }));
-        HIP_TRY(timed(c, HELM_K_TRIDIAG32, 16.0 * c.n, [&] { return launch_tridiag_z32(c.t2f, c.t2f, c.cpf, c.dxe, c.dye, nx, ny, nz, c.ax, c.ay, c.c0, gz, 1.0, c.stream); }));
+        HIP_TRY(timed(c, HELM_K_TRIDIAG32, 16.0 * c.n, [&] { return launch_tridiag_chunk_z32(c.t2f, c.t2f, c.tpiv_eig, c.dxe, c.dye, nx, ny, nz, c.ax, c.ay, c.c0, gz, 1.0, c.stream); }));
         HIP_TRY(timed(c, HELM_K_RING, 8.0 * c.n + ring_work / 2, [&] { return launch_ring_inverse_z32(c.t2f, m.ringW, c.AyI32, m.VyT, m.Vx, c.BxI32, nx, ny, nz, c.stream); }));
         HIP_TRY(timed(c, HELM_K_RING, 16.0 * c.n + ring_work, [&] { return launch_ring_forward_z32(m.ringT, m.ringW, m.yhat, hz2, c.t2f, m.Sy, m.Sy, m.Sx, m.Sx, ex, ey, nx, ny, nz, c.stream); }));
-        HIP_TRY(timed(c, HELM_K_TRIDIAG32, 16.0 * c.n, [&] { return launch_tridiag_z32(c.t2f, c.t2f, c.cpf, P.dFx, P.dFy, nx, ny, nz, c.ax, c.ay, c.c0, gz, 1.0, c.stream); }));
+        HIP_TRY(timed(c, HELM_K_TRIDIAG32, 16.0 * c.n, [&] { return launch_tridiag_chunk_z32(c.t2f, c.t2f, c.tpiv_dir, P.dFx, P.dFy, nx, ny, nz, c.ax, c.ay, c.c0, gz, 1.0, c.stream); }));
         HIP_TRY(timed(c, HELM_K_PFFT, 4.0 * dy.M * (double)dy.N * dy.K * dy.batch, [&] { return launch_gemm_z32(dy, m.Sy, c.t2f, c.t1f, c.stream, 1); }));
         HIP_TRY(timed(c, HELM_K_PFFT, 4.0 * dx.M * (double)dx.N * dx.K, [&] { return launch_gemm_z32_out64(dx, c.t1f, m.Sx, z, c.stream, 2); }));
     }

@@ -97,6 +97,7 @@ struct Ctx {
     // preconditioner work buffers
     double2 *t1 = nullptr, *t2 = nullptr, *cp = nullptr;
     float2 *t1f = nullptr, *t2f = nullptr, *cpf = nullptr;
+    double2 *tpiv_eig = nullptr, *tpiv_dir = nullptr;  // pivots entering each z-chunk (absorbing / Dirichlet x-y eigenvalues)
 
     PfftPlan *pfft = nullptr;
     std::vector<cd> hVx, hVxi, hVy, hVyi;        // host copies of the eigenvector matrices (PFFT plan build)
@@ -206,6 +207,15 @@ hipError_t launch_gemm_z32_out64(const GemmDesc &d, const float2 *A, const float
                                  int rw = 0, int cfg = 0);
 
 // `in` (may equal r) supplies the right-hand side; the solution is written to r.
+int tri_chunks(int nz);
+hipError_t launch_tri_pivots(const double2 *dx, const double2 *dy, int nx, int ny, int nz, double ax, double ay,
+                             double c0, double2 gz, double2 *piv, hipStream_t s);
+hipError_t launch_tridiag_chunk_z64(const double2 *in, double2 *out, const double2 *piv, const double2 *dx,
+                                    const double2 *dy, int nx, int ny, int nz, double ax, double ay, double c0,
+                                    double2 gz, double scale, hipStream_t s);
+hipError_t launch_tridiag_chunk_z32(const float2 *in, float2 *out, const double2 *piv, const double2 *dx,
+                                    const double2 *dy, int nx, int ny, int nz, double ax, double ay, double c0,
+                                    double2 gz, double scale, hipStream_t s);
 hipError_t launch_tridiag_z64(const double2 *in, double2 *r, double2 *cp, const double2 *dx, const double2 *dy, int nx,
                               int ny, int nz, double ax, double ay, double c0, double2 gz, double scale, hipStream_t s);
 hipError_t launch_ring_inverse_z64(const double2 *Xh, double2 *ring, const double2 *Vy, const double2 *VyT,

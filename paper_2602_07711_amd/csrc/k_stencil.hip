@@ -121,6 +121,13 @@ __global__ __launch_bounds__(256) void k_matvec(const double2 *__restrict__ x, c
     matvec_tile<ORDER, RESID>(x, k2, fld, F, y, p, blockIdx.x);
 }
 
+template <int ORDER, bool RESID>
+__global__ __launch_bounds__(512) void k_matvec2(const double2 *__restrict__ x, const double *__restrict__ k2,
+                                                 const double4 *__restrict__ fld, const double2 *__restrict__ F,
+                                                 double2 *__restrict__ y, StencilParams p) {
+    matvec_tile2<ORDER, RESID>(x, k2, fld, F, y, p, blockIdx.x);
+}
+
 }  // namespace
 
 hipError_t launch_derived_fields(const double *k2_halo, int halo, double *k2, double4 *fld, const StencilParams &p,
@@ -147,16 +154,16 @@ hipError_t launch_matvec(const StencilParams &p, const double2 *x, const double 
                          const double2 *F, double2 *y, hipStream_t s) {
     int T = p.tiles_x * p.tiles_y * p.zchunks;
     int grid = 8 * ((T + 7) / 8);
-    dim3 blk(64, 4);
+    dim3 blk(64, MV2_TY);
     if (p.order == 6) {
-        if (F) hipLaunchKernelGGL((k_matvec<6, true>), dim3(grid), blk, 0, s, x, k2, fld, F, y, p);
-        else hipLaunchKernelGGL((k_matvec<6, false>), dim3(grid), blk, 0, s, x, k2, fld, F, y, p);
+        if (F) hipLaunchKernelGGL((k_matvec2<6, true>), dim3(grid), blk, 0, s, x, k2, fld, F, y, p);
+        else hipLaunchKernelGGL((k_matvec2<6, false>), dim3(grid), blk, 0, s, x, k2, fld, F, y, p);
     } else if (p.order == 4) {
-        if (F) hipLaunchKernelGGL((k_matvec<4, true>), dim3(grid), blk, 0, s, x, k2, fld, F, y, p);
-        else hipLaunchKernelGGL((k_matvec<4, false>), dim3(grid), blk, 0, s, x, k2, fld, F, y, p);
+        if (F) hipLaunchKernelGGL((k_matvec2<4, true>), dim3(grid), blk, 0, s, x, k2, fld, F, y, p);
+        else hipLaunchKernelGGL((k_matvec2<4, false>), dim3(grid), blk, 0, s, x, k2, fld, F, y, p);
     } else {
-        if (F) hipLaunchKernelGGL((k_matvec<2, true>), dim3(grid), blk, 0, s, x, k2, fld, F, y, p);
-        else hipLaunchKernelGGL((k_matvec<2, false>), dim3(grid), blk, 0, s, x, k2, fld, F, y, p);
+        if (F) hipLaunchKernelGGL((k_matvec2<2, true>), dim3(grid), blk, 0, s, x, k2, fld, F, y, p);
+        else hipLaunchKernelGGL((k_matvec2<2, false>), dim3(grid), blk, 0, s, x, k2, fld, F, y, p);
     }
     return hipGetLastError();
 }

@@ -10,6 +10,14 @@
 // The forward sweep reads the right-hand side from `in` (which may be r itself), writes the eliminated
 // right-hand side to r and the reciprocal pivots to `cp`; the backward sweep reads both and overwrites r with
 // the solution. Loads are issued UNR levels ahead of use.
+//
+// Partitioned form (k_tridiag_chunk): each line's rows are split into chunks of TL rows, one thread per chunk,
+// with the chunk held in registers. The reciprocal pivots depend only on the line's shift b, so the pivot
+// entering each chunk is computed once per context (k_tri_pivots) and each thread restarts the pivot recurrence
+// from it. With zero incoming values each chunk's forward sweep gives d'_e = A d'_{s-1} + B and its backward
+// sweep u_s = A u_{e+1} + D (A = prod of -1/pivot over the chunk); these affine maps are composed along the line
+// in LDS, and a last pass adds the incoming contributions. The result equals Thomas elimination up to the
+// order of rounding; HBM traffic is one read and one write per unknown (plus one pivot per chunk).
 #include "tridiag_dev.h"
 
 namespace helm {
@@ -26,7 +34,178 @@ __global__ __launch_bounds__(64) void k_tridiag(const typename c2<T>::t *in, typ
     tridiag_line<T>(in, r, cp, dx, dy, nx, ny, nz, ax, ay, c0, gz, scale, line);
 }
 
+constexpr int TL = 8;    // rows per chunk
+
+// reciprocal pivot entering each chunk: piv[k * lines + line] = 1/pivot_{k TL - 1} (k >= 1), 0 for k = 0
+__global__ void k_tri_pivots(const double2 *__restrict__ dx, const double2 *__restrict__ dy, int nx, int ny, int nz,
+                             double ax, double ay, double c0, double2 g, double2 *__restrict__ piv) {
+    const long long lines = (long long)nx * ny;
+    const long long line = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (line >= lines) return;
+    const int i = (int)(line % nx), j = (int)(line / nx);
+    const double2 ex = dx[i], ey = dy[j];
+    const double2 b = make_double2(ax * ex.x + ay * ey.x + c0, ax * ex.y + ay * ey.y);
+    double2 inv = make_double2(0.0, 0.0);
+    piv[line] = inv;
+    for (int l = 0; l < nz; ++l) {
+        double2 d = b;
+        if (l == 0 || l == nz - 1) { d.x += g.x; d.y += g.y; }
+        if (l > 0) { d.x -= inv.x; d.y -= inv.y; }
+        inv = crecip(d);
+        if ((l + 1) % TL == 0 && l + 1 < nz) piv[(long long)((l + 1) / TL) * lines + line] = inv;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_tridiag_chunk(const typename c2<T>::t *in, typename c2<T>::t *out,
+                                                        const double2 *__restrict__ piv,
+                                                        const double2 *__restrict__ dx, const double2 *__restrict__ dy,
+                                                        int nx, int ny, int nz, int P, int LX, double ax, double ay,
+                                                        double c0, double2 gz, double scale) {
+    typedef typename c2<T>::t CT;
+    extern __shared__ unsigned char smraw[];
+    CT *sA = reinterpret_cast<CT *>(smraw);                // [P][LX]
+    CT *sB = sA + P * LX;
+    const int t = threadIdx.x, li = t % LX, k = t / LX;
+    const long long lines = (long long)nx * ny;
+    const long long line = (long long)blockIdx.x * LX + li;
+    const bool lin = line < lines;
+    const int s = k * TL;
+    const int nrow = lin ? (nz - s < TL ? nz - s : TL) : 0;
+    CT b = mk<T, CT>(0, 0);
+    if (lin) {
+        const double2 ex = dx[(int)(line % nx)], ey = dy[(int)(line / nx)];
+        b = mk<T, CT>((T)(ax * ex.x + ay * ey.x + c0), (T)(ax * ex.y + ay * ey.y));
+    }
+    const CT g = mk<T, CT>((T)gz.x, (T)gz.y);
+    const T sc = (T)scale;
+    CT v[TL], inv[TL];
+#pragma unroll
+    for (int r = 0; r < TL; ++r)
+        if (r < nrow) v[r] = in[line + (long long)(s + r) * lines];
+    // pivots of this chunk, restarted from the pivot entering it
+    CT ip = mk<T, CT>(0, 0);
+    if (lin && k > 0) {
+        const double2 q = piv[(long long)k * lines + line];
+        ip = mk<T, CT>((T)q.x, (T)q.y);
+    }
+#pragma unroll
+    for (int r = 0; r < TL; ++r)
+        if (r < nrow) {
+            const int l = s + r;
+            CT d = b;
+            if (l == 0 || l == nz - 1) { d.x += g.x; d.y += g.y; }
+            if (l > 0) { d.x -= ip.x; d.y -= ip.y; }
+            ip = crecip(d);
+            inv[r] = ip;
+        }
+    // forward sweep with d'_{s-1} = 0; A = prod(-inv)
+    CT dp = mk<T, CT>(0, 0), A = mk<T, CT>(1, 0);
+#pragma unroll
+    for (int r = 0; r < TL; ++r)
+        if (r < nrow) {
+            dp = cm(mk<T, CT>(sc * v[r].x - dp.x, sc * v[r].y - dp.y), inv[r]);
+            v[r] = dp;
+            const CT na = cm(inv[r], A);
+            A = mk<T, CT>(-na.x, -na.y);
+        }
+    sA[k * LX + li] = A;
+    sB[k * LX + li] = dp;
+    __syncthreads();
+    if (k == 0 && lin) {             // incoming d'_{s-1} of every chunk, in order
+        CT acc = mk<T, CT>(0, 0);
+        for (int kk = 0; kk < P; ++kk) {
+            const CT a = sA[kk * LX + li], bb = sB[kk * LX + li];
+            sB[kk * LX + li] = acc;
+            const CT m = cm(a, acc);
+            acc = mk<T, CT>(m.x + bb.x, m.y + bb.y);
+        }
+    }
+    __syncthreads();
+    CT fix = sB[k * LX + li];
+#pragma unroll
+    for (int r = 0; r < TL; ++r)
+        if (r < nrow) {
+            const CT m = cm(inv[r], fix);
+            fix = mk<T, CT>(-m.x, -m.y);
+            v[r].x += fix.x;
+            v[r].y += fix.y;
+        }
+    // backward sweep with u_{e+1} = 0: u_s = A u_{e+1} + D
+    CT un = mk<T, CT>(0, 0);
+#pragma unroll
+    for (int r = TL - 1; r >= 0; --r)
+        if (r < nrow) {
+            const CT m = cm(inv[r], un);
+            un = mk<T, CT>(v[r].x - m.x, v[r].y - m.y);
+            v[r] = un;
+        }
+    __syncthreads();                 // everyone has read its incoming d' before sB is reused
+    sB[k * LX + li] = un;
+    __syncthreads();
+    if (k == 0 && lin) {             // incoming u_{e+1} of every chunk, from the top
+        CT acc = mk<T, CT>(0, 0);
+        for (int kk = P - 1; kk >= 0; --kk) {
+            const CT a = sA[kk * LX + li], dd = sB[kk * LX + li];
+            sB[kk * LX + li] = acc;
+            const CT m = cm(a, acc);
+            acc = mk<T, CT>(m.x + dd.x, m.y + dd.y);
+        }
+    }
+    __syncthreads();
+    fix = sB[k * LX + li];
+#pragma unroll
+    for (int r = TL - 1; r >= 0; --r)
+        if (r < nrow) {
+            const CT m = cm(inv[r], fix);
+            fix = mk<T, CT>(-m.x, -m.y);
+            v[r].x += fix.x;
+            v[r].y += fix.y;
+        }
+#pragma unroll
+    for (int r = 0; r < TL; ++r)
+        if (r < nrow) out[line + (long long)(s + r) * lines] = v[r];
+}
+
+template <typename T>
+hipError_t launch_chunk(const typename c2<T>::t *in, typename c2<T>::t *out, const double2 *piv, const double2 *dx,
+                        const double2 *dy, int nx, int ny, int nz, double ax, double ay, double c0, double2 gz,
+                        double scale, hipStream_t s) {
+    const int P = (nz + TL - 1) / TL;
+    if (P > 1024) return hipErrorInvalidValue;
+    int LX = 16;
+    while (LX > 1 && LX * P > 1024) LX /= 2;
+    const long long lines = (long long)nx * ny;
+    const unsigned grid = (unsigned)((lines + LX - 1) / LX);
+    const size_t sm = 2 * sizeof(typename c2<T>::t) * (size_t)P * LX;
+    hipLaunchKernelGGL(k_tridiag_chunk<T>, dim3(grid), dim3(LX * P), sm, s, in, out, piv, dx, dy, nx, ny, nz, P, LX,
+                       ax, ay, c0, gz, scale);
+    return hipGetLastError();
+}
+
 }  // namespace
+
+int tri_chunks(int nz) { return (nz + TL - 1) / TL; }
+
+hipError_t launch_tri_pivots(const double2 *dx, const double2 *dy, int nx, int ny, int nz, double ax, double ay,
+                             double c0, double2 gz, double2 *piv, hipStream_t s) {
+    const long long lines = (long long)nx * ny;
+    hipLaunchKernelGGL(k_tri_pivots, dim3((unsigned)((lines + 255) / 256)), dim3(256), 0, s, dx, dy, nx, ny, nz, ax,
+                       ay, c0, gz, piv);
+    return hipGetLastError();
+}
+
+hipError_t launch_tridiag_chunk_z64(const double2 *in, double2 *out, const double2 *piv, const double2 *dx,
+                                    const double2 *dy, int nx, int ny, int nz, double ax, double ay, double c0,
+                                    double2 gz, double scale, hipStream_t s) {
+    return launch_chunk<double>(in, out, piv, dx, dy, nx, ny, nz, ax, ay, c0, gz, scale, s);
+}
+
+hipError_t launch_tridiag_chunk_z32(const float2 *in, float2 *out, const double2 *piv, const double2 *dx,
+                                    const double2 *dy, int nx, int ny, int nz, double ax, double ay, double c0,
+                                    double2 gz, double scale, hipStream_t s) {
+    return launch_chunk<float>(in, out, piv, dx, dy, nx, ny, nz, ax, ay, c0, gz, scale, s);
+}
 
 hipError_t launch_tridiag_z64(const double2 *in, double2 *r, double2 *cp, const double2 *dx, const double2 *dy, int nx,
                               int ny, int nz, double ax, double ay, double c0, double2 gz, double scale, hipStream_t s) {

@@ -1,5 +1,7 @@
 // Device code of the compact-stencil matvec, shared by the single-problem and the grouped (batched) kernels.
 #pragma once
+#include <type_traits>
+
 #include "helm_internal.h"
 
 namespace helm {
@@ -162,6 +164,180 @@ __device__ __forceinline__ void matvec_tile(const double2 *__restrict__ x, const
     }
 }
 
+
+}  // namespace
+}  // namespace helm
+
+namespace helm {
+namespace {
+
+// --------------------------------------------------------------------------- plane-streaming matvec
+// The same operator as matvec_tile, organised so that every node's value is read from LDS once per plane:
+// a block of 64 x 8 threads owns a 64 x 8 column of outputs; it streams planes p = z0-1 .. z1 through a
+// double-buffered LDS tile (with the ghost rule applied on load) and scatters each plane's 3 x 3 in-plane
+// neighbourhood into three register accumulators, for the outputs at p+1, p and p-1 (the plane is their lower,
+// centre and upper plane). Output p-1 is complete after plane p. The plane's nine values are first reduced to
+// sums that do not depend on the output (for the off-plane role: the z-face, the xz/yz edges, the corners and
+// their k^2-weighted and signed forms; for the centre role: the x/y faces and xy edges), and each output adds
+// them with its own coefficients (order 6: dg, g_x, g_y, g_z of that node).
+// The next plane's global loads and the output coefficients / F are issued one plane ahead of their use, so
+// one barrier per plane suffices.
+constexpr int MV2_TY = 8;      // rows per tile, one per thread row (block 64 x 8)
+
+template <int ORDER, bool RESID>
+__device__ __forceinline__ void matvec_tile2(const double2 *__restrict__ x, const double *__restrict__ k2,
+                                             const double4 *__restrict__ fld, const double2 *__restrict__ F,
+                                             double2 *__restrict__ y, const StencilParams &p, int bid) {
+    __shared__ double2 su[2][LY][LX];
+    __shared__ double sk[2][LY][LX];
+    const int T = p.tiles_x * p.tiles_y * p.zchunks;
+    const int per = (T + 7) / 8;
+    const int tile = (bid % 8) * per + bid / 8;   // consecutive tiles share an XCD (and its L2)
+    if (tile >= T) return;
+    const int x0 = (tile % p.tiles_x) * TX, y0 = ((tile / p.tiles_x) % p.tiles_y) * MV2_TY;
+    const int z0 = (tile / (p.tiles_x * p.tiles_y)) * p.zchunk;
+    const int z1 = min(z0 + p.zchunk, p.nz);
+    const int nx = p.nx, ny = p.ny, nz = p.nz;
+    const long long plane = (long long)nx * ny;
+    const int tid = threadIdx.y * 64 + threadIdx.x;
+    const int lx = threadIdx.x + 1, ly = threadIdx.y + 1;
+    const int gxo = x0 + threadIdx.x, gyo = y0 + threadIdx.y;
+    const bool valid = gxo < nx && gyo < ny;
+    const long long col = valid ? (long long)gyo * nx + gxo : 0;
+
+    // plane prefetch registers, two sets (planes alternate between them): elements tid and tid + 512 of the
+    // (LY x LX) tile; the in-plane part of the ghost factor is fixed per element, the z part per plane
+    int offs[2];
+    double2 fxy[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int e = tid + 512 * q;
+        const int ex = e % LX, ey = e / LX;
+        const int gx = x0 - 1 + ex, gy = y0 - 1 + ey;
+        double2 fac = make_double2(1.0, 0.0);
+        int cx = gx, cy = gy;
+        if (gx < 0) { cx = 0; fac = cmul(fac, p.gx); }
+        else if (gx >= nx) { cx = nx - 1; fac = cmul(fac, p.gx); }
+        if (gy < 0) { cy = 0; fac = cmul(fac, p.gy); }
+        else if (gy >= ny) { cy = ny - 1; fac = cmul(fac, p.gy); }
+        offs[q] = cy * nx + cx;
+        fxy[q] = fac;
+    }
+    double2 ru[2][2];
+    double rk[2][2];
+    auto gload = [&](auto setc, int z) {
+        constexpr int S = decltype(setc)::value;
+        const int cz = z < 0 ? 0 : (z >= nz ? nz - 1 : z);
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+            if (tid + 512 * q < LX * LY) {
+                const long long idx = (long long)cz * plane + offs[q];
+                ru[S][q] = x[idx];
+                rk[S][q] = k2[idx];
+            }
+    };
+    auto sstore = [&](auto setc, int z) {
+        constexpr int S = decltype(setc)::value;
+        const bool gh = z < 0 || z >= nz;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int e = tid + 512 * q;
+            if (e < LX * LY) {
+                const double2 f = gh ? cmul(p.gz, fxy[q]) : fxy[q];
+                su[S][e / LX][e % LX] = cmul(f, ru[S][q]);
+                sk[S][e / LX][e % LX] = rk[S][q];
+            }
+        }
+    };
+    auto fload = [&](int z) -> double4 {
+        return (ORDER == 6 && valid && z >= 0 && z < nz) ? fld[(long long)z * plane + col] : make_double4(0, 0, 0, 0);
+    };
+    auto Fload = [&](int z) -> double2 {
+        return (RESID && valid && z >= 0 && z < nz) ? F[(long long)z * plane + col] : make_double2(0, 0);
+    };
+
+    // output coefficients for outputs p-1, p, p+1 (fm, f0, fp) and the prefetched p+2 (fn)
+    double4 fm = make_double4(0, 0, 0, 0), f0 = fload(z0 - 1), fp = fload(z0), fn;
+    double2 Fm = make_double2(0, 0), F0 = Fload(z0 - 1), Fn;
+    double2 am = make_double2(0, 0), a0 = am, ap = am;
+    gload(std::integral_constant<int, 0>(), z0 - 1);
+    gload(std::integral_constant<int, 1>(), z0);
+    auto step = [&](auto setc, int pz) {
+        constexpr int S = decltype(setc)::value;
+        const int b = S;
+        sstore(setc, pz);
+        __syncthreads();
+        if (pz + 2 <= z1) gload(setc, pz + 2);
+        fn = fload(pz + 2);
+        Fn = Fload(pz + 1);
+        {
+            // the plane's 3 x 3 neighbourhood of this column (names: x then y offset, m = -1, p = +1)
+            const double2 uc = su[b][ly][lx], uxm = su[b][ly][lx - 1], uxp = su[b][ly][lx + 1];
+            const double2 uym = su[b][ly - 1][lx], uyp = su[b][ly + 1][lx];
+            const double kc = sk[b][ly][lx];
+            const double2 Ef = cadd(cadd(uxm, uxp), cadd(uym, uyp));          // in-plane face neighbours
+            if (ORDER == 6) {
+                const double2 umm = su[b][ly - 1][lx - 1], upm = su[b][ly - 1][lx + 1];
+                const double2 ump = su[b][ly + 1][lx - 1], upp = su[b][ly + 1][lx + 1];
+                const double kxm = sk[b][ly][lx - 1], kxp = sk[b][ly][lx + 1];
+                const double kym = sk[b][ly - 1][lx], kyp = sk[b][ly + 1][lx];
+                const double kmm = sk[b][ly - 1][lx - 1], kpm = sk[b][ly - 1][lx + 1];
+                const double kmp = sk[b][ly + 1][lx - 1], kpp = sk[b][ly + 1][lx + 1];
+                const double2 C = cadd(cadd(umm, upm), cadd(ump, upp));       // in-plane diagonal neighbours
+                const double2 wxm = cscale(uxm, kxm), wxp = cscale(uxp, kxp);
+                const double2 wym = cscale(uym, kym), wyp = cscale(uyp, kyp);
+                const double2 Ew = cadd(cadd(wxm, wxp), cadd(wym, wyp));
+                const double2 wc = cscale(uc, kc);
+                const double2 Cw = cadd(cadd(cscale(umm, kmm), cscale(upm, kpm)), cadd(cscale(ump, kmp), cscale(upp, kpp)));
+                const double2 Dx = csub(uxp, uxm), Dy = csub(uyp, uym);
+                // role of an upper/lower plane (offsets (dx, dy, +-1)): centre = z-face, faces = xz/yz edges,
+                // diagonals = corners
+                double2 Piso = cfma(14.0 * p.c1, uc, cfma(3.0 * p.c1, Ef, cscale(C, p.c1)));
+                Piso = cfma(1.0 / 90.0, csub(Ew, wc), Piso);
+                const double2 Pz = cadd(cadd(cscale(uc, 2.0), cscale(wc, p.h2)), Ef);
+                am = cadd(am, cfma(fm.w, Pz, cfma(fm.y, Dx, cfma(fm.z, Dy, Piso))));
+                ap = cadd(ap, cfma(-fp.w, Pz, cfma(fp.y, Dx, cfma(fp.z, Dy, Piso))));
+                // role of the centre plane: centre, x/y faces, xy edges
+                double2 Qiso = cfma(14.0 * p.c1, Ef, cscale(C, 3.0 * p.c1));
+                Qiso = cfma(1.0 / 90.0, csub(Cw, Ew), Qiso);
+                const double2 Qx = cadd(cfma(2.0, Dx, cscale(csub(wxp, wxm), p.h2)),
+                                        csub(cadd(upm, upp), cadd(umm, ump)));
+                const double2 Qy = cadd(cfma(2.0, Dy, cscale(csub(wyp, wym), p.h2)),
+                                        csub(cadd(ump, upp), cadd(umm, upm)));
+                a0 = cadd(a0, cfma(f0.x, uc, cfma(f0.y, Qx, cfma(f0.z, Qy, Qiso))));
+            } else {
+                const double2 Fx = cadd(uxm, uxp), Fy = cadd(uym, uyp);
+                double2 P = cscale(uc, p.c_face[2]);
+                double2 Q = cfma(p.c_face[0], Fx, cfma(p.c_face[1], Fy, cscale(uc, p.c_center + p.w_center * kc)));
+                if (ORDER == 4) {
+                    const double kxm = sk[b][ly][lx - 1], kxp = sk[b][ly][lx + 1];
+                    const double kym = sk[b][ly - 1][lx], kyp = sk[b][ly + 1][lx];
+                    const double2 C = cadd(cadd(su[b][ly - 1][lx - 1], su[b][ly - 1][lx + 1]),
+                                           cadd(su[b][ly + 1][lx - 1], su[b][ly + 1][lx + 1]));
+                    const double2 Ew = cadd(cadd(cscale(uxm, kxm), cscale(uxp, kxp)),
+                                            cadd(cscale(uym, kym), cscale(uyp, kyp)));
+                    P = cfma(p.w_face * kc, uc, cfma(p.c_edge[1], Fx, cfma(p.c_edge[2], Fy, P)));
+                    Q = cfma(p.w_face, Ew, cfma(p.c_edge[0], C, Q));
+                }
+                am = cadd(am, P);
+                ap = cadd(ap, P);
+                a0 = cadd(a0, Q);
+            }
+        }
+        const int zo = pz - 1;                        // complete after this plane
+        if (zo >= z0 && valid) {
+            const long long pidx = (long long)zo * plane + col;
+            y[pidx] = RESID ? csub(Fm, am) : am;
+        }
+        am = a0; a0 = ap; ap = make_double2(0, 0);
+        fm = f0; f0 = fp; fp = fn;
+        Fm = F0; F0 = Fn;
+    };
+    for (int pz = z0 - 1; pz <= z1; pz += 2) {
+        step(std::integral_constant<int, 0>(), pz);
+        if (pz + 1 <= z1) step(std::integral_constant<int, 1>(), pz + 1);
+    }
+}
 
 }  // namespace
 }  // namespace helm
