@@ -169,10 +169,12 @@ const char *helm_profile_name(int kernel_class);
 
 /* GEMM tile autotuner for the EigT transforms of a context. For each of the four transform GEMMs (x and y,
  * FP64 and FP32) it times every tile configuration (BM, BN, BK) = (64,64,16), (64,64,32), (128,64,16),
- * (64,128,16) over `reps` launches on the context stream and keeps the fastest for this context. If the
- * environment variable HELM_TUNE_CACHE names a file, choices are read from it by (transform, M, N, K, batch)
- * and new ones appended to it. chosen: NULL or 4 ints (x64, y64, x32, y32); ms: NULL or 16 doubles, the
- * average time of configuration c of transform t at ms[4 t + c] (not written for cached transforms).
+ * (64,128,16) with the launches the preconditioner makes (the FP32 x-transform as its FP64-input forward and
+ * FP64-output inverse pair), best of three trials of `reps` launches on the context stream, and keeps the
+ * fastest for this context. If the environment variable HELM_TUNE_CACHE names a file, choices are read from it
+ * by (transform, M, N, K, batch) and new ones appended to it. chosen: NULL or 4 ints (x64, y64, x32, y32);
+ * ms: NULL or 16 doubles, the per-launch time of configuration c of transform t at ms[4 t + c] (not written for
+ * cached transforms).
  * Batches created afterwards use the tuned choices of their first context. */
 helm_status helm_autotune(helm_ctx *ctx, int reps, int *chosen, double *ms);
 

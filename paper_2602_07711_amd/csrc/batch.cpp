@@ -95,6 +95,12 @@ helm_status helm_batch_create(helm_batch **out, helm_ctx *const *ctxs, int np, i
     int bmx, bnx, bmy, bny;
     gemm_cfg_tile(cfg_x, bmx, bnx);
     gemm_cfg_tile(cfg_y, bmy, bny);
+    // z-solve block shape: 16 lines x the largest problem's chunk count (at most 1024 threads)
+    int tri_pb = 1;
+    for (int p = 0; p < np; ++p) tri_pb = std::max(tri_pb, tri_chunks(ctxs[p]->c.nz));
+    if (tri_pb > 1024) return fail(HELM_EUNSUPPORTED, "z-extent too large for the partitioned z-solve");
+    int tri_lx = 16;
+    while (tri_lx > 1 && tri_lx * tri_pb > 1024) tri_lx /= 2;
     // per-problem descriptors, work buffers and launch offsets
     long long tot_blocks_mv_target = 4096;
     std::vector<int> omv(1, 0), otri(1, 0), odot(1, 0), olc(1, 0);
@@ -127,20 +133,20 @@ helm_status helm_batch_create(helm_batch **out, helm_ctx *const *ctxs, int np, i
         q.nblk_dots = dots_blocks(c.n);
         if (balloc(*b, &q.V, (size_t)(m + 1) * c.n) != hipSuccess || balloc(*b, &q.Z, (size_t)m * c.n) != hipSuccess)
             return fail(HELM_ENOMEM, "Krylov workspace allocation failed");
-        void *t1 = nullptr, *t2 = nullptr, *cp = nullptr;
+        void *t1 = nullptr, *t2 = nullptr;
         if (hipMalloc(&t1, esz * c.n) != hipSuccess) return fail(HELM_ENOMEM, "work allocation failed");
         b->allocs.push_back(t1);
         if (hipMalloc(&t2, esz * c.n) != hipSuccess) return fail(HELM_ENOMEM, "work allocation failed");
         b->allocs.push_back(t2);
-        if (hipMalloc(&cp, esz * c.n) != hipSuccess) return fail(HELM_ENOMEM, "work allocation failed");
-        b->allocs.push_back(cp);
-        q.t1 = t1; q.t2 = t2; q.cp = cp;
+        q.t1 = t1; q.t2 = t2;
+        if (ctx_tri_pivots(c) != HELM_OK) return fail(HELM_EDEVICE, "z-solve pivots: " + c.err);
+        q.tpiv = c.tpiv_eig;
         if (balloc(*b, &q.part, (size_t)q.nblk_dots * (m + 2)) != hipSuccess) return fail(HELM_ENOMEM, "partials");
         q.x = nullptr;
         q.F = nullptr;
         int T = q.sp.tiles_x * q.sp.tiles_y * q.sp.zchunks;
         omv.push_back(omv.back() + 8 * ((T + 7) / 8));
-        otri.push_back(otri.back() + (int)(((long long)c.nx * c.ny + 63) / 64));
+        otri.push_back(otri.back() + (int)(((long long)c.nx * c.ny + tri_lx - 1) / tri_lx));
         odot.push_back(odot.back() + q.nblk_dots);
         olc.push_back(olc.back() + (int)((c.n + 1023) / 1024));
         ogx.push_back(ogx.back() + (long long)((q.dx.M + bmx - 1) / bmx) * ((q.dx.N + bnx - 1) / bnx));
@@ -174,6 +180,8 @@ helm_status helm_batch_create(helm_batch **out, helm_ctx *const *ctxs, int np, i
     L.fp32 = b->fp32;
     L.cfg_x = cfg_x;
     L.cfg_y = cfg_y;
+    L.tri_lx = tri_lx;
+    L.tri_pb = tri_pb;
     L.tot_mv = omv.back();
     L.tot_tri = otri.back();
     L.tot_dot = odot.back();

@@ -57,8 +57,13 @@ struct PfftPlan {
     bool has32 = false;
 };
 
+// basis vectors are KRYLOV_PAD elements longer than n so that equal indices of different vectors do not share
+// DRAM address bits above the vector size
+constexpr long long KRYLOV_PAD = 2048;
+
 struct KrylovWork {
     int m = 0;
+    long long ld = 0;            // leading dimension of V and Z (n + KRYLOV_PAD)
     int flexible = 0;
     double2 *V = nullptr;        // (m+1) * n
     double2 *Z = nullptr;        // m * n (flexible only)
@@ -95,8 +100,8 @@ struct Ctx {
     int gemm_cfg[4] = {0, 0, 0, 0};             // tile configuration of the x64, y64, x32, y32 transforms
 
     // preconditioner work buffers
-    double2 *t1 = nullptr, *t2 = nullptr, *cp = nullptr;
-    float2 *t1f = nullptr, *t2f = nullptr, *cpf = nullptr;
+    double2 *t1 = nullptr, *t2 = nullptr;
+    float2 *t1f = nullptr, *t2f = nullptr;
     double2 *tpiv_eig = nullptr, *tpiv_dir = nullptr;  // pivots entering each z-chunk (absorbing / Dirichlet x-y eigenvalues)
 
     PfftPlan *pfft = nullptr;
@@ -163,7 +168,8 @@ struct BProb {                    // constant during a batched solve
     GemmDesc dx, dy;
     double2 *V, *Z, *x;
     const double2 *F;
-    void *t1, *t2, *cp;                    // preconditioner work (element type by precision)
+    void *t1, *t2;                         // preconditioner work (element type by precision)
+    const double2 *tpiv;                   // pivots entering each z-chunk (the context's table)
     double2 *part;                         // inner-product partials, nblk_dots * (m + 2)
     long long n;
     int nx, ny, nz, nblk_dots;
@@ -216,8 +222,6 @@ hipError_t launch_tridiag_chunk_z64(const double2 *in, double2 *out, const doubl
 hipError_t launch_tridiag_chunk_z32(const float2 *in, float2 *out, const double2 *piv, const double2 *dx,
                                     const double2 *dy, int nx, int ny, int nz, double ax, double ay, double c0,
                                     double2 gz, double scale, hipStream_t s);
-hipError_t launch_tridiag_z64(const double2 *in, double2 *r, double2 *cp, const double2 *dx, const double2 *dy, int nx,
-                              int ny, int nz, double ax, double ay, double c0, double2 gz, double scale, hipStream_t s);
 hipError_t launch_ring_inverse_z64(const double2 *Xh, double2 *ring, const double2 *Vy, const double2 *VyT,
                                    const double2 *Vx, const double2 *VxT, int nx, int ny, int nz, hipStream_t s);
 hipError_t launch_ring_inverse_z32(const float2 *Xh, float2 *ring, const float2 *Vy, const float2 *VyT,
@@ -228,8 +232,6 @@ hipError_t launch_ring_forward_z64(const double2 *ra, const double2 *rb, const d
 hipError_t launch_ring_forward_z32(const float2 *ra, const float2 *rb, const float2 *base, double base_scale,
                                    float2 *out, const float2 *Wy, const float2 *WyT, const float2 *Wx,
                                    const float2 *WxT, double2 ex, double2 ey, int nx, int ny, int nz, hipStream_t s);
-hipError_t launch_tridiag_z32(const float2 *in, float2 *r, float2 *cp, const double2 *dx, const double2 *dy, int nx,
-                              int ny, int nz, double ax, double ay, double c0, double2 gz, double scale, hipStream_t s);
 
 // Krylov helpers
 int dots_blocks(long long n);
@@ -251,11 +253,13 @@ struct BLaunch {
     long long tot_gx, tot_gy;                   // total GEMM tiles
     int gemm_grid;                              // persistent GEMM grid size
     int cfg_x, cfg_y;                           // GEMM tile configurations of the x- and y-transforms
+    int tri_lx, tri_pb;                         // z-solve block: tri_lx lines x tri_pb chunks
 };
 inline void gemm_cfg_tile(int cfg, int &bm, int &bn) {
     bm = cfg == 2 ? 128 : 64;
     bn = cfg == 3 ? 128 : 64;
 }
+helm_status ctx_tri_pivots(Ctx &c);   // pivot table of the partitioned z-solve (built once per context)
 hipError_t bl_init(const BLaunch &L, hipStream_t s);                 // ||F||, state reset (outside graphs)
 hipError_t bl_zero_x(const BLaunch &L, hipStream_t s);
 hipError_t bl_cycle(const BLaunch &L, hipStream_t s);                // one restart cycle: restart + m steps + update

@@ -61,22 +61,21 @@ __global__ __launch_bounds__(256) void k_b_gemm(const BProb *__restrict__ P, con
 }
 
 template <typename T>
-__global__ __launch_bounds__(64) void k_b_tridiag(const BProb *__restrict__ P, const BState *__restrict__ st,
-                                                  const int *__restrict__ off, int np) {
+__global__ __launch_bounds__(1024) void k_b_tridiag(const BProb *__restrict__ P, const BState *__restrict__ st,
+                                                    const int *__restrict__ off, int np, int LX) {
     typedef typename c2<T>::t CT;
+    extern __shared__ unsigned char smraw[];
     const int p = find_prob(off, np, blockIdx.x);
-    if (!st[p].active) return;
+    if (!st[p].active) return;                 // uniform over the block
     const BProb &q = P[p];
-    const long long line = (long long)(blockIdx.x - off[p]) * 64 + threadIdx.x;
-    if (line >= (long long)q.nx * q.ny) return;
-    tridiag_line<T>((const CT *)q.t2, (CT *)q.t2, (CT *)q.cp, q.dxe, q.dye, q.nx, q.ny, q.nz, q.ax, q.ay, q.c0, q.gz,
-                    q.hz2, line);
+    tri_chunk_block<T>((const CT *)q.t2, (CT *)q.t2, q.tpiv, q.dxe, q.dye, q.nx, q.ny, q.nz, (q.nz + TL - 1) / TL, LX,
+                       q.ax, q.ay, q.c0, q.gz, q.hz2, blockIdx.x - off[p], smraw);
 }
 
 // ---------------------------------------------------------------------------------------------- matvec
 // mode 0: restart, V_0 = F - A x (problems not done); mode 1: step j, V_{j+1} = V_j - A Z_j (active problems)
 template <int ORDER>
-__global__ __launch_bounds__(256) void k_b_matvec(const BProb *__restrict__ P, const BState *__restrict__ st,
+__global__ __launch_bounds__(512) void k_b_matvec(const BProb *__restrict__ P, const BState *__restrict__ st,
                                                   const int *__restrict__ off, int np, int mode, int j) {
     const int p = find_prob(off, np, blockIdx.x);
     if (mode == 0 ? st[p].done : !st[p].active) return;
@@ -346,7 +345,8 @@ void gemm_role(const BLaunch &L, hipStream_t s, int j, int cfg, const long long 
 template <typename T> hipError_t precond_steps(const BLaunch &L, hipStream_t s, int j) {
     gemm_role<0, T>(L, s, j, L.cfg_x, L.off.gx);
     gemm_role<1, T>(L, s, j, L.cfg_y, L.off.gy);
-    hipLaunchKernelGGL(k_b_tridiag<T>, dim3(L.tot_tri), dim3(64), 0, s, L.P, L.st, L.off.tri, L.np);
+    hipLaunchKernelGGL(k_b_tridiag<T>, dim3(L.tot_tri), dim3(L.tri_lx * L.tri_pb),
+                       2 * sizeof(typename c2<T>::t) * (size_t)L.tri_lx * L.tri_pb, s, L.P, L.st, L.off.tri, L.np, L.tri_lx);
     gemm_role<2, T>(L, s, j, L.cfg_y, L.off.gy);
     gemm_role<3, T>(L, s, j, L.cfg_x, L.off.gx);
     return hipGetLastError();
@@ -354,11 +354,11 @@ template <typename T> hipError_t precond_steps(const BLaunch &L, hipStream_t s, 
 
 hipError_t matvec_step(const BLaunch &L, hipStream_t s, int mode, int j) {
     if (L.order == 6)
-        hipLaunchKernelGGL(k_b_matvec<6>, dim3(L.tot_mv), dim3(64, 4), 0, s, L.P, L.st, L.off.mv, L.np, mode, j);
+        hipLaunchKernelGGL(k_b_matvec<6>, dim3(L.tot_mv), dim3(64, TY), 0, s, L.P, L.st, L.off.mv, L.np, mode, j);
     else if (L.order == 4)
-        hipLaunchKernelGGL(k_b_matvec<4>, dim3(L.tot_mv), dim3(64, 4), 0, s, L.P, L.st, L.off.mv, L.np, mode, j);
+        hipLaunchKernelGGL(k_b_matvec<4>, dim3(L.tot_mv), dim3(64, TY), 0, s, L.P, L.st, L.off.mv, L.np, mode, j);
     else
-        hipLaunchKernelGGL(k_b_matvec<2>, dim3(L.tot_mv), dim3(64, 4), 0, s, L.P, L.st, L.off.mv, L.np, mode, j);
+        hipLaunchKernelGGL(k_b_matvec<2>, dim3(L.tot_mv), dim3(64, TY), 0, s, L.P, L.st, L.off.mv, L.np, mode, j);
     return hipGetLastError();
 }
 

@@ -9,9 +9,10 @@ namespace helm {
 
 namespace {
 
+// partials of output t are contiguous: part[t * gridDim.x + block], so the reduction reads them coalesced
 __global__ __launch_bounds__(256) void k_dots(const double2 *__restrict__ V, long long ldv, int nv,
                                               const double2 *__restrict__ w, long long n, double2 *__restrict__ part) {
-    dots_chunk(V, ldv, nv, w, n, part, blockIdx.x);
+    dots_chunk(V, ldv, nv, w, n, part, blockIdx.x, 1, gridDim.x);
 }
 
 __global__ __launch_bounds__(256) void k_reduce(const double2 *__restrict__ part, int nblocks, int nout,
@@ -20,7 +21,7 @@ __global__ __launch_bounds__(256) void k_reduce(const double2 *__restrict__ part
     const int t = blockIdx.x, tid = threadIdx.x;
     double re = 0.0, im = 0.0;
     for (int b = tid; b < nblocks; b += 256) {
-        double2 v = part[(long long)b * nout + t];
+        double2 v = part[(long long)t * nblocks + b];
         re += v.x;
         im += v.y;
     }
@@ -55,7 +56,27 @@ __global__ __launch_bounds__(256) void k_lincomb(double2 *out, const double2 *ba
             acc[e].y = alpha.x * b.y + alpha.y * b.x;
         }
     }
-    for (int i = 0; i < nv; ++i) {
+    int i = 0;
+    for (; i + 4 <= nv; i += 4) {            // four vectors per round: 16 loads in flight per thread
+        double2 v[4][LC_EPT];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int e = 0; e < LC_EPT; ++e) {
+                const long long idx = start + (long long)e * 256;
+                v[q][e] = ok[e] ? V[(long long)(i + q) * ldv + idx] : make_double2(0.0, 0.0);
+            }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const double2 c = co.c[i + q];
+#pragma unroll
+            for (int e = 0; e < LC_EPT; ++e) {
+                acc[e].x += c.x * v[q][e].x - c.y * v[q][e].y;
+                acc[e].y += c.x * v[q][e].y + c.y * v[q][e].x;
+            }
+        }
+    }
+    for (; i < nv; ++i) {
         const double2 *vi = V + (long long)i * ldv;
         const double2 c = co.c[i];
         double2 v[LC_EPT];

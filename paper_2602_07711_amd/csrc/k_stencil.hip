@@ -13,9 +13,9 @@
 // times gamma of that axis (per clamped axis), and k^2 there is the boundary node's k^2, so the products
 // k^2 U obey the same rule.
 //
-// The matvec stages a (64+2) x (8+2) tile of U and k^2 per z-plane in LDS, keeps three planes in a ring and
-// marches along z; each thread produces two nodes per plane. Per node it streams x (16 B), k^2 (8 B), the
-// order-6 field block (32 B) and writes y (16 B).
+// The matvec (stencil_dev.h) streams z-planes of U and k^2 (with a one-node halo) through LDS, one thread per
+// output column. Per node it streams x (16 B), k^2 (8 B), the order-6 field block (32 B), F in the residual form
+// (16 B) and writes y (16 B).
 #include "stencil_dev.h"
 
 namespace helm {
@@ -115,17 +115,10 @@ __global__ void k_rhs(const double2 *__restrict__ f, const double *__restrict__ 
 }
 
 template <int ORDER, bool RESID>
-__global__ __launch_bounds__(256) void k_matvec(const double2 *__restrict__ x, const double *__restrict__ k2,
-                                                const double4 *__restrict__ fld, const double2 *__restrict__ F,
-                                                double2 *__restrict__ y, StencilParams p) {
-    matvec_tile<ORDER, RESID>(x, k2, fld, F, y, p, blockIdx.x);
-}
-
-template <int ORDER, bool RESID>
-__global__ __launch_bounds__(512) void k_matvec2(const double2 *__restrict__ x, const double *__restrict__ k2,
+__global__ __launch_bounds__(512) void k_matvec(const double2 *__restrict__ x, const double *__restrict__ k2,
                                                  const double4 *__restrict__ fld, const double2 *__restrict__ F,
                                                  double2 *__restrict__ y, StencilParams p) {
-    matvec_tile2<ORDER, RESID>(x, k2, fld, F, y, p, blockIdx.x);
+    matvec_tile<ORDER, RESID>(x, k2, fld, F, y, p, blockIdx.x);
 }
 
 }  // namespace
@@ -154,16 +147,16 @@ hipError_t launch_matvec(const StencilParams &p, const double2 *x, const double 
                          const double2 *F, double2 *y, hipStream_t s) {
     int T = p.tiles_x * p.tiles_y * p.zchunks;
     int grid = 8 * ((T + 7) / 8);
-    dim3 blk(64, MV2_TY);
+    dim3 blk(64, TY);
     if (p.order == 6) {
-        if (F) hipLaunchKernelGGL((k_matvec2<6, true>), dim3(grid), blk, 0, s, x, k2, fld, F, y, p);
-        else hipLaunchKernelGGL((k_matvec2<6, false>), dim3(grid), blk, 0, s, x, k2, fld, F, y, p);
+        if (F) hipLaunchKernelGGL((k_matvec<6, true>), dim3(grid), blk, 0, s, x, k2, fld, F, y, p);
+        else hipLaunchKernelGGL((k_matvec<6, false>), dim3(grid), blk, 0, s, x, k2, fld, F, y, p);
     } else if (p.order == 4) {
-        if (F) hipLaunchKernelGGL((k_matvec2<4, true>), dim3(grid), blk, 0, s, x, k2, fld, F, y, p);
-        else hipLaunchKernelGGL((k_matvec2<4, false>), dim3(grid), blk, 0, s, x, k2, fld, F, y, p);
+        if (F) hipLaunchKernelGGL((k_matvec<4, true>), dim3(grid), blk, 0, s, x, k2, fld, F, y, p);
+        else hipLaunchKernelGGL((k_matvec<4, false>), dim3(grid), blk, 0, s, x, k2, fld, F, y, p);
     } else {
-        if (F) hipLaunchKernelGGL((k_matvec2<2, true>), dim3(grid), blk, 0, s, x, k2, fld, F, y, p);
-        else hipLaunchKernelGGL((k_matvec2<2, false>), dim3(grid), blk, 0, s, x, k2, fld, F, y, p);
+        if (F) hipLaunchKernelGGL((k_matvec<2, true>), dim3(grid), blk, 0, s, x, k2, fld, F, y, p);
+        else hipLaunchKernelGGL((k_matvec<2, false>), dim3(grid), blk, 0, s, x, k2, fld, F, y, p);
     }
     return hipGetLastError();
 }

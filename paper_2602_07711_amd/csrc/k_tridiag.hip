@@ -24,18 +24,6 @@ namespace helm {
 
 namespace {
 
-template <typename T>
-__global__ __launch_bounds__(64) void k_tridiag(const typename c2<T>::t *in, typename c2<T>::t *r,
-                                                typename c2<T>::t *__restrict__ cp, const double2 *__restrict__ dx,
-                                                const double2 *__restrict__ dy, int nx, int ny, int nz, double ax,
-                                                double ay, double c0, double2 gz, double scale) {
-    const long long line = (long long)blockIdx.x * 64 + threadIdx.x;
-    if (line >= (long long)nx * ny) return;
-    tridiag_line<T>(in, r, cp, dx, dy, nx, ny, nz, ax, ay, c0, gz, scale, line);
-}
-
-constexpr int TL = 8;    // rows per chunk
-
 // reciprocal pivot entering each chunk: piv[k * lines + line] = 1/pivot_{k TL - 1} (k >= 1), 0 for k = 0
 __global__ void k_tri_pivots(const double2 *__restrict__ dx, const double2 *__restrict__ dy, int nx, int ny, int nz,
                              double ax, double ay, double c0, double2 g, double2 *__restrict__ piv) {
@@ -62,109 +50,8 @@ __global__ __launch_bounds__(1024) void k_tridiag_chunk(const typename c2<T>::t 
                                                         const double2 *__restrict__ dx, const double2 *__restrict__ dy,
                                                         int nx, int ny, int nz, int P, int LX, double ax, double ay,
                                                         double c0, double2 gz, double scale) {
-    typedef typename c2<T>::t CT;
     extern __shared__ unsigned char smraw[];
-    CT *sA = reinterpret_cast<CT *>(smraw);                // [P][LX]
-    CT *sB = sA + P * LX;
-    const int t = threadIdx.x, li = t % LX, k = t / LX;
-    const long long lines = (long long)nx * ny;
-    const long long line = (long long)blockIdx.x * LX + li;
-    const bool lin = line < lines;
-    const int s = k * TL;
-    const int nrow = lin ? (nz - s < TL ? nz - s : TL) : 0;
-    CT b = mk<T, CT>(0, 0);
-    if (lin) {
-        const double2 ex = dx[(int)(line % nx)], ey = dy[(int)(line / nx)];
-        b = mk<T, CT>((T)(ax * ex.x + ay * ey.x + c0), (T)(ax * ex.y + ay * ey.y));
-    }
-    const CT g = mk<T, CT>((T)gz.x, (T)gz.y);
-    const T sc = (T)scale;
-    CT v[TL], inv[TL];
-#pragma unroll
-    for (int r = 0; r < TL; ++r)
-        if (r < nrow) v[r] = in[line + (long long)(s + r) * lines];
-    // pivots of this chunk, restarted from the pivot entering it
-    CT ip = mk<T, CT>(0, 0);
-    if (lin && k > 0) {
-        const double2 q = piv[(long long)k * lines + line];
-        ip = mk<T, CT>((T)q.x, (T)q.y);
-    }
-#pragma unroll
-    for (int r = 0; r < TL; ++r)
-        if (r < nrow) {
-            const int l = s + r;
-            CT d = b;
-            if (l == 0 || l == nz - 1) { d.x += g.x; d.y += g.y; }
-            if (l > 0) { d.x -= ip.x; d.y -= ip.y; }
-            ip = crecip(d);
-            inv[r] = ip;
-        }
-    // forward sweep with d'_{s-1} = 0; A = prod(-inv)
-    CT dp = mk<T, CT>(0, 0), A = mk<T, CT>(1, 0);
-#pragma unroll
-    for (int r = 0; r < TL; ++r)
-        if (r < nrow) {
-            dp = cm(mk<T, CT>(sc * v[r].x - dp.x, sc * v[r].y - dp.y), inv[r]);
-            v[r] = dp;
-            const CT na = cm(inv[r], A);
-            A = mk<T, CT>(-na.x, -na.y);
-        }
-    sA[k * LX + li] = A;
-    sB[k * LX + li] = dp;
-    __syncthreads();
-    if (k == 0 && lin) {             // incoming d'_{s-1} of every chunk, in order
-        CT acc = mk<T, CT>(0, 0);
-        for (int kk = 0; kk < P; ++kk) {
-            const CT a = sA[kk * LX + li], bb = sB[kk * LX + li];
-            sB[kk * LX + li] = acc;
-            const CT m = cm(a, acc);
-            acc = mk<T, CT>(m.x + bb.x, m.y + bb.y);
-        }
-    }
-    __syncthreads();
-    CT fix = sB[k * LX + li];
-#pragma unroll
-    for (int r = 0; r < TL; ++r)
-        if (r < nrow) {
-            const CT m = cm(inv[r], fix);
-            fix = mk<T, CT>(-m.x, -m.y);
-            v[r].x += fix.x;
-            v[r].y += fix.y;
-        }
-    // backward sweep with u_{e+1} = 0: u_s = A u_{e+1} + D
-    CT un = mk<T, CT>(0, 0);
-#pragma unroll
-    for (int r = TL - 1; r >= 0; --r)
-        if (r < nrow) {
-            const CT m = cm(inv[r], un);
-            un = mk<T, CT>(v[r].x - m.x, v[r].y - m.y);
-            v[r] = un;
-        }
-    __syncthreads();                 // everyone has read its incoming d' before sB is reused
-    sB[k * LX + li] = un;
-    __syncthreads();
-    if (k == 0 && lin) {             // incoming u_{e+1} of every chunk, from the top
-        CT acc = mk<T, CT>(0, 0);
-        for (int kk = P - 1; kk >= 0; --kk) {
-            const CT a = sA[kk * LX + li], dd = sB[kk * LX + li];
-            sB[kk * LX + li] = acc;
-            const CT m = cm(a, acc);
-            acc = mk<T, CT>(m.x + dd.x, m.y + dd.y);
-        }
-    }
-    __syncthreads();
-    fix = sB[k * LX + li];
-#pragma unroll
-    for (int r = TL - 1; r >= 0; --r)
-        if (r < nrow) {
-            const CT m = cm(inv[r], fix);
-            fix = mk<T, CT>(-m.x, -m.y);
-            v[r].x += fix.x;
-            v[r].y += fix.y;
-        }
-#pragma unroll
-    for (int r = 0; r < TL; ++r)
-        if (r < nrow) out[line + (long long)(s + r) * lines] = v[r];
+    tri_chunk_block<T>(in, out, piv, dx, dy, nx, ny, nz, P, LX, ax, ay, c0, gz, scale, blockIdx.x, smraw);
 }
 
 template <typename T>
@@ -205,22 +92,6 @@ hipError_t launch_tridiag_chunk_z32(const float2 *in, float2 *out, const double2
                                     const double2 *dy, int nx, int ny, int nz, double ax, double ay, double c0,
                                     double2 gz, double scale, hipStream_t s) {
     return launch_chunk<float>(in, out, piv, dx, dy, nx, ny, nz, ax, ay, c0, gz, scale, s);
-}
-
-hipError_t launch_tridiag_z64(const double2 *in, double2 *r, double2 *cp, const double2 *dx, const double2 *dy, int nx,
-                              int ny, int nz, double ax, double ay, double c0, double2 gz, double scale, hipStream_t s) {
-    long long lines = (long long)nx * ny;
-    hipLaunchKernelGGL(k_tridiag<double>, dim3((unsigned)((lines + 63) / 64)), dim3(64), 0, s, in, r, cp, dx, dy, nx,
-                       ny, nz, ax, ay, c0, gz, scale);
-    return hipGetLastError();
-}
-
-hipError_t launch_tridiag_z32(const float2 *in, float2 *r, float2 *cp, const double2 *dx, const double2 *dy, int nx,
-                              int ny, int nz, double ax, double ay, double c0, double2 gz, double scale, hipStream_t s) {
-    long long lines = (long long)nx * ny;
-    hipLaunchKernelGGL(k_tridiag<float>, dim3((unsigned)((lines + 63) / 64)), dim3(64), 0, s, in, r, cp, dx, dy, nx,
-                       ny, nz, ax, ay, c0, gz, scale);
-    return hipGetLastError();
 }
 
 }  // namespace helm

@@ -16,10 +16,11 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // Partial sums of V_i^H w (i < nv) and ||w||^2 over chunk `lb` (DOT_CHUNK elements), written to
-// part[lb * (nv + 1) + t]. Every thread of the block must call it.
+// part[lb * bstride + t * tstride] (t = 0..nv). Every thread of the block must call it.
 __device__ __forceinline__ void dots_chunk(const double2 *__restrict__ V, long long ldv, int nv,
                                            const double2 *__restrict__ w, long long n, double2 *__restrict__ part,
-                                           long long lb) {
+                                           long long lb, long long bstride = -1, long long tstride = 1) {
+    if (bstride < 0) bstride = nv + 1;
     __shared__ double2 red[4][MAXV];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const long long base = lb * DOT_CHUNK + tid;
@@ -79,7 +80,7 @@ __device__ __forceinline__ void dots_chunk(const double2 *__restrict__ V, long l
     for (int t = tid; t <= nv; t += 256) {
         double2 s = red[0][t];
         for (int q = 1; q < 4; ++q) { s.x += red[q][t].x; s.y += red[q][t].y; }
-        part[lb * (nv + 1) + t] = s;
+        part[lb * bstride + t * tstride] = s;
     }
 }
 

@@ -29,64 +29,121 @@ template <typename CT> __device__ __forceinline__ CT crecip(CT a) {
     return r;
 }
 
-constexpr int UNR = 8;
+constexpr int TL = 8;    // rows per chunk of the partitioned z-solve
 
-// Thomas elimination of one z-line (i, j) = (line % nx, line / nx).
+// One block of the partitioned z-solve: LX consecutive lines starting at line blk * LX, P chunks of TL rows per
+// line (threads with chunk index >= P, present when the block is shaped for a larger problem, hold no rows but
+// take part in every barrier). smraw: 2 * Pb * LX complex values, Pb = blockDim.x / LX.
 template <typename T>
-__device__ __forceinline__ void tridiag_line(const typename c2<T>::t *in, typename c2<T>::t *r,
-                                             typename c2<T>::t *__restrict__ cp, const double2 *__restrict__ dx,
-                                             const double2 *__restrict__ dy, int nx, int ny, int nz, double ax,
-                                             double ay, double c0, double2 gz, double scale, long long line) {
+__device__ __forceinline__ void tri_chunk_block(const typename c2<T>::t *in, typename c2<T>::t *out,
+                                                const double2 *__restrict__ piv, const double2 *__restrict__ dx,
+                                                const double2 *__restrict__ dy, int nx, int ny, int nz, int P, int LX,
+                                                double ax, double ay, double c0, double2 gz, double scale,
+                                                long long blk, unsigned char *smraw) {
     typedef typename c2<T>::t CT;
+    CT *sA = reinterpret_cast<CT *>(smraw);                // [P][LX]
+    CT *sB = sA + (blockDim.x / LX) * LX;
+    const int t = threadIdx.x, li = t % LX, k = t / LX;
     const long long lines = (long long)nx * ny;
-    const int i = (int)(line % nx), j = (int)(line / nx);
-    const double2 ex = dx[i], ey = dy[j];
-    const CT b = mk<T, CT>((T)(ax * ex.x + ay * ey.x + c0), (T)(ax * ex.y + ay * ey.y));
+    const long long line = blk * LX + li;
+    const bool lin = line < lines && k < P;
+    const int s = k * TL;
+    const int nrow = lin ? (nz - s < TL ? nz - s : TL) : 0;
+    CT b = mk<T, CT>(0, 0);
+    if (lin) {
+        const double2 ex = dx[(int)(line % nx)], ey = dy[(int)(line / nx)];
+        b = mk<T, CT>((T)(ax * ex.x + ay * ey.x + c0), (T)(ax * ex.y + ay * ey.y));
+    }
     const CT g = mk<T, CT>((T)gz.x, (T)gz.y);
     const T sc = (T)scale;
-    CT *rl = r + line;
-    const CT *il = in + line;
-    CT *cl = cp + line;
-
-    CT inv = mk<T, CT>(0, 0), dprev = mk<T, CT>(0, 0);
-    for (int l0 = 0; l0 < nz; l0 += UNR) {
-        CT v[UNR];
+    CT v[TL], inv[TL];
 #pragma unroll
-        for (int u = 0; u < UNR; ++u)
-            if (l0 + u < nz) v[u] = il[(long long)(l0 + u) * lines];
+    for (int r = 0; r < TL; ++r)
+        if (r < nrow) v[r] = in[line + (long long)(s + r) * lines];
+    // pivots of this chunk, restarted from the pivot entering it
+    CT ip = mk<T, CT>(0, 0);
+    if (lin && k > 0) {
+        const double2 q = piv[(long long)k * lines + line];
+        ip = mk<T, CT>((T)q.x, (T)q.y);
+    }
 #pragma unroll
-        for (int u = 0; u < UNR; ++u) {
-            const int l = l0 + u;
-            if (l >= nz) break;
-            CT diag = b;
-            if (l == 0 || l == nz - 1) { diag.x += g.x; diag.y += g.y; }
-            if (l > 0) { diag.x -= inv.x; diag.y -= inv.y; }
-            inv = crecip(diag);
-            CT rhs = mk<T, CT>(sc * v[u].x - dprev.x, sc * v[u].y - dprev.y);
-            dprev = cm(rhs, inv);
-            rl[(long long)l * lines] = dprev;
-            cl[(long long)l * lines] = inv;
+    for (int r = 0; r < TL; ++r)
+        if (r < nrow) {
+            const int l = s + r;
+            CT d = b;
+            if (l == 0 || l == nz - 1) { d.x += g.x; d.y += g.y; }
+            if (l > 0) { d.x -= ip.x; d.y -= ip.y; }
+            ip = crecip(d);
+            inv[r] = ip;
+        }
+    // forward sweep with d'_{s-1} = 0; A = prod(-inv)
+    CT dp = mk<T, CT>(0, 0), A = mk<T, CT>(1, 0);
+#pragma unroll
+    for (int r = 0; r < TL; ++r)
+        if (r < nrow) {
+            dp = cm(mk<T, CT>(sc * v[r].x - dp.x, sc * v[r].y - dp.y), inv[r]);
+            v[r] = dp;
+            const CT na = cm(inv[r], A);
+            A = mk<T, CT>(-na.x, -na.y);
+        }
+    sA[k * LX + li] = A;
+    sB[k * LX + li] = dp;
+    __syncthreads();
+    if (k == 0 && lin) {             // incoming d'_{s-1} of every chunk, in order
+        CT acc = mk<T, CT>(0, 0);
+        for (int kk = 0; kk < P; ++kk) {
+            const CT a = sA[kk * LX + li], bb = sB[kk * LX + li];
+            sB[kk * LX + li] = acc;
+            const CT m = cm(a, acc);
+            acc = mk<T, CT>(m.x + bb.x, m.y + bb.y);
         }
     }
-    CT unext = dprev;   // u_N = d'_N, already stored
-    for (int l1 = nz - 2; l1 >= 0; l1 -= UNR) {
-        CT dv[UNR], cv[UNR];
+    __syncthreads();
+    CT fix = sB[k * LX + li];
 #pragma unroll
-        for (int u = 0; u < UNR; ++u)
-            if (l1 - u >= 0) {
-                dv[u] = rl[(long long)(l1 - u) * lines];
-                cv[u] = cl[(long long)(l1 - u) * lines];
-            }
+    for (int r = 0; r < TL; ++r)
+        if (r < nrow) {
+            const CT m = cm(inv[r], fix);
+            fix = mk<T, CT>(-m.x, -m.y);
+            v[r].x += fix.x;
+            v[r].y += fix.y;
+        }
+    // backward sweep with u_{e+1} = 0: u_s = A u_{e+1} + D
+    CT un = mk<T, CT>(0, 0);
 #pragma unroll
-        for (int u = 0; u < UNR; ++u) {
-            const int l = l1 - u;
-            if (l < 0) break;
-            CT t = cm(cv[u], unext);
-            unext = mk<T, CT>(dv[u].x - t.x, dv[u].y - t.y);
-            rl[(long long)l * lines] = unext;
+    for (int r = TL - 1; r >= 0; --r)
+        if (r < nrow) {
+            const CT m = cm(inv[r], un);
+            un = mk<T, CT>(v[r].x - m.x, v[r].y - m.y);
+            v[r] = un;
+        }
+    __syncthreads();                 // everyone has read its incoming d' before sB is reused
+    sB[k * LX + li] = un;
+    __syncthreads();
+    if (k == 0 && lin) {             // incoming u_{e+1} of every chunk, from the top
+        CT acc = mk<T, CT>(0, 0);
+        for (int kk = P - 1; kk >= 0; --kk) {
+            const CT a = sA[kk * LX + li], dd = sB[kk * LX + li];
+            sB[kk * LX + li] = acc;
+            const CT m = cm(a, acc);
+            acc = mk<T, CT>(m.x + dd.x, m.y + dd.y);
         }
     }
+    __syncthreads();
+    fix = sB[k * LX + li];
+#pragma unroll
+    for (int r = TL - 1; r >= 0; --r)
+        if (r < nrow) {
+            const CT m = cm(inv[r], fix);
+            fix = mk<T, CT>(-m.x, -m.y);
+            v[r].x += fix.x;
+            v[r].y += fix.y;
+        }
+#pragma unroll
+    for (int r = 0; r < TL; ++r)
+        if (r < nrow) out[line + (long long)(s + r) * lines] = v[r];
 }
+
 
 }  // namespace
 }  // namespace helm
