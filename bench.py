@@ -42,6 +42,27 @@ KCLASS = {
 }
 
 
+# HBM traffic per dispatch measured by rocprofv3 (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy) for the
+# headline form; kernel class -> kernel name in that summary. Classes whose launches use several kernel
+# variants (the GEMMs) have no single row and report no traffic.
+TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                            "noise256_fp32_eigt_fgmres_hbm_traffic.md")
+TRAFFIC_KERNEL = {"lincomb": "k_lincomb", "dots": "k_dots", "matvec": "k_matvec<6, true>",
+                  "tridiag32": "k_tridiag_chunk<float>"}
+
+
+def measured_traffic(kclass: str):
+    """Bytes per dispatch (read + write) of the kernel class from the committed counter summary, or None."""
+    name = TRAFFIC_KERNEL.get(kclass)
+    if name is None or not os.path.exists(TRAFFIC_FILE):
+        return None
+    for line in open(TRAFFIC_FILE):
+        cells = [c.strip() for c in line.strip().strip("|").split("|")]
+        if len(cells) == 4 and cells[0] == f"`{name}`":
+            return (float(cells[2]) + float(cells[3])) * 2 ** 20
+    return None
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -288,10 +309,13 @@ def main():
     hf = forms[head]
     dom = max(hf["kernels"].items(), key=lambda kv: kv[1]["total_ms"])
     dname, dk = dom
+    traffic = measured_traffic(dname) if (head == "fp32_eigt_fgmres" and n == 256) else None
     roofline = dict(kernel=dname, bound=dk["bound"], achieved=dk["achieved"], peak=dk["peak"], unit=dk["unit"],
-                    frac=dk["frac"], traffic=None,
+                    frac=dk["frac"], traffic=traffic,
+                    algorithmic_bytes_per_launch=dk["work_per_launch"] if dk["bound"] == "hbm" else None,
                     note="achieved = algorithmic work per launch / average launch time (HIP events on the solve "
-                         "stream over the timed region)")
+                         "stream over the timed region); traffic = HBM bytes per launch from rocprofv3 FETCH_SIZE "
+                         "and WRITE_SIZE (scaled by a plain copy) in profiles/noise256_fp32_eigt_fgmres_hbm_traffic.md")
     batched = None
     if not args.no_batched:
         del x
