@@ -31,6 +31,11 @@ hipError_t cnn_adam(float *w, const float *g, float *m, float *v, long long n, f
                     float c1, float c2, hipStream_t s);
 hipError_t cnn_prolong(const float *coarse, int nc, double scale, double gre, double gim, int cubic, double2 *fine,
                        int nf, hipStream_t s);
+hipError_t cnn_conv_direct(int use_bf16, const float *in, long long in_bs, int Ci, int S, const void *wt, int COP,
+                           const float *bias, int Co, float *out, long long out_bs, int relu, int B, float *part,
+                           long long part_elems, hipStream_t s);
+long long cnn_direct_size(int Co, int Ci);
+hipError_t cnn_pack_direct(int use_bf16, const float *W, int Co, int Ci, int transpose, void *wt, hipStream_t s);
 hipError_t cnn_features(const double *k2h, const double2 *fh, int halo, int nf, int S, double k0sq, double cs,
                         double fs, float *x, hipStream_t s);
 }  // namespace helm
@@ -106,19 +111,30 @@ View view(helm_cnn &n, float *const *arr, int buf, int ch0) {
         }                                                                                               \
     } while (0)
 
+// 27-tap layers: direct-convolution format (forward, and the data gradient with mirrored taps); the 1-tap head:
+// implicit-GEMM format
 helm_status pack_all(helm_cnn &n) {
     for (int l = 0; l < NL; ++l) {
         const int ci = LAYERS[l][0], co = LAYERS[l][1], taps = LAYERS[l][2];
-        NTRY(cnn_pack_weights(n.bf16, n.params + n.woff[l], co, ci, taps, 0, n.COP[l], n.Kp[l], n.wt[l], n.stream));
-        NTRY(cnn_pack_weights(n.bf16, n.params + n.woff[l], co, ci, taps, 1, n.COPt[l], n.Kpt[l], n.wtT[l], n.stream));
+        if (taps == 27) {
+            NTRY(cnn_pack_direct(n.bf16, n.params + n.woff[l], co, ci, 0, n.wt[l], n.stream));
+            NTRY(cnn_pack_direct(n.bf16, n.params + n.woff[l], ci, co, 1, n.wtT[l], n.stream));
+        } else {
+            NTRY(cnn_pack_weights(n.bf16, n.params + n.woff[l], co, ci, taps, 0, n.COP[l], n.Kp[l], n.wt[l], n.stream));
+            NTRY(cnn_pack_weights(n.bf16, n.params + n.woff[l], co, ci, taps, 1, n.COPt[l], n.Kpt[l], n.wtT[l], n.stream));
+        }
     }
     return HELM_OK;
 }
 
 helm_status conv_fwd(helm_cnn &n, int l, View in, View out, int B) {
     const int ci = LAYERS[l][0], co = LAYERS[l][1], taps = LAYERS[l][2], relu = LAYERS[l][3];
-    NTRY(cnn_conv_fwd(n.bf16, in.p, in.bs, ci, S_of(n, LAYERS[l][4]), taps, n.wt[l], n.Kp[l], n.COP[l],
-                      n.params + n.boff[l], co, out.p, out.bs, relu, B, n.stream));
+    if (taps == 27)
+        NTRY(cnn_conv_direct(n.bf16, in.p, in.bs, ci, S_of(n, LAYERS[l][4]), n.wt[l], n.COP[l], n.params + n.boff[l],
+                             co, out.p, out.bs, relu, B, n.part, n.part_elems, n.stream));
+    else
+        NTRY(cnn_conv_fwd(n.bf16, in.p, in.bs, ci, S_of(n, LAYERS[l][4]), taps, n.wt[l], n.Kp[l], n.COP[l],
+                          n.params + n.boff[l], co, out.p, out.bs, relu, B, n.stream));
     return HELM_OK;
 }
 
@@ -136,7 +152,10 @@ helm_status conv_bwd(helm_cnn &n, int l, View in, View g, View *gin, int B) {
     NTRY(cnn_conv_wgrad(n.bf16, g.p, g.bs, co, pad16(co), in.p, in.bs, ci, S, taps, B, Kp, (int)vchunk, nch, n.part,
                         n.grads + n.woff[l], n.stream));
     NTRY(cnn_bias_grad(g.p, g.bs, B, V_of(n, lev), co, n.bias_part, n.grads + n.boff[l], n.stream));
-    if (gin)
+    if (gin && taps == 27)
+        NTRY(cnn_conv_direct(n.bf16, g.p, g.bs, co, S, n.wtT[l], n.COPt[l], nullptr, ci, gin->p, gin->bs, 0, B,
+                             n.part, n.part_elems, n.stream));
+    else if (gin)
         NTRY(cnn_conv_fwd(n.bf16, g.p, g.bs, co, S, taps, n.wtT[l], n.Kpt[l], n.COPt[l], nullptr, ci, gin->p, gin->bs,
                           0, B, n.stream));
     return HELM_OK;
@@ -265,9 +284,12 @@ helm_status helm_cnn_create(helm_cnn **out, int size, int max_batch, int bf16, u
     n->nparams = off;
     const size_t esz = n->bf16 ? 2 : 4;
     for (int l = 0; l < NL; ++l) {
-        if (hipMalloc(&n->wt[l], esz * n->COP[l] * n->Kp[l]) != hipSuccess) return fail(HELM_ENOMEM, "weights");
+        const int ci = LAYERS[l][0], co = LAYERS[l][1], taps = LAYERS[l][2];
+        const size_t nf = taps == 27 ? (size_t)cnn_direct_size(co, ci) : (size_t)n->COP[l] * n->Kp[l];
+        const size_t nt = taps == 27 ? (size_t)cnn_direct_size(ci, co) : (size_t)n->COPt[l] * n->Kpt[l];
+        if (hipMalloc(&n->wt[l], esz * nf) != hipSuccess) return fail(HELM_ENOMEM, "weights");
         n->allocs.push_back(n->wt[l]);
-        if (hipMalloc(&n->wtT[l], esz * n->COPt[l] * n->Kpt[l]) != hipSuccess) return fail(HELM_ENOMEM, "weights");
+        if (hipMalloc(&n->wtT[l], esz * nt) != hipSuccess) return fail(HELM_ENOMEM, "weights");
         n->allocs.push_back(n->wtT[l]);
     }
     if (nalloc(*n, &n->params, off) || nalloc(*n, &n->grads, off) || nalloc(*n, &n->am, off) || nalloc(*n, &n->av, off))

@@ -13,6 +13,8 @@
 // directions), MSE loss, Adam, and trilinear prolongation of a coarse prediction to the solver's grid.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "helm_internal.h"
 
 namespace helm {
@@ -518,6 +520,150 @@ __global__ void k_features(const double *__restrict__ k2h, const double2 *__rest
     x[V + v] = (float)(fs * fr);
 }
 
+
+// ---------------------------------------------------------------------------------------------- direct 3x3x3
+// Direct convolution for the 27-tap layers: a workgroup owns an 8 x 8 x 4 output tile (one 8 x 8 plane per wave,
+// four 16-voxel MFMA column blocks each) and all output channels (COP rows). Per chunk of 16 input channels the
+// input tile with its one-voxel halo (10 x 10 x 6) is staged once in LDS, channel-last in the operand type, so the
+// B fragment of tap (dz, dy, dx) is one LDS read at the shifted voxel. Weights are packed as
+// wt[chunk][tap][COP][16] and read as A fragments straight from global memory (each 64-lane read is one
+// contiguous 512 B block shared by every wave and workgroup).
+constexpr int DT_X = 8, DT_Y = 8, DT_Z = 4;
+constexpr int DH_X = DT_X + 2, DH_Y = DT_Y + 2, DH_Z = DT_Z + 2;
+constexpr int DH_V = DH_X * DH_Y * DH_Z;
+constexpr int DCC = 16;                    // input channels per chunk
+constexpr int DPAD = 4;                    // LDS row padding (elements)
+
+// Work split: a workgroup covers one tile, FR row blocks (16 output channels each) starting at row block rg*FR,
+// and the input-channel chunks [ks*cpb, (ks+1)*cpb). With one K split (nsplit = 1) it applies bias and ReLU and
+// writes the output; otherwise it writes FP32 partial sums part[ks][b][co][v] that k_conv_split_sum adds in order.
+template <typename T, int FR>
+__global__ __launch_bounds__(256) void k_conv_direct(const float *__restrict__ in, long long in_bs, int Ci, int S,
+                                                     const T *__restrict__ wt, int COP, const float *__restrict__ bias,
+                                                     int Co, float *__restrict__ out, long long out_bs, int relu,
+                                                     int rowgroups, int nsplit, int cpb, float *__restrict__ part,
+                                                     int B) {
+    constexpr int KL = MT<T>::KL;
+    __shared__ T sIn[DH_V][DCC + DPAD];
+    const int ntx = (S + DT_X - 1) / DT_X, nty = (S + DT_Y - 1) / DT_Y, ntz = (S + DT_Z - 1) / DT_Z;
+    const int tiles = ntx * nty * ntz;
+    int idx = blockIdx.x;
+    const int ks = idx % nsplit;
+    idx /= nsplit;
+    const int rg = idx % rowgroups;
+    idx /= rowgroups;
+    const int t = idx % tiles, b = idx / tiles;
+    const int x0 = (t % ntx) * DT_X, y0 = ((t / ntx) % nty) * DT_Y, z0 = (t / (ntx * nty)) * DT_Z;
+    const int row0 = rg * FR * 16;
+    const float *inb = in + (long long)b * in_bs;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int V = S * S * S;
+    v4f acc[FR][4];
+#pragma unroll
+    for (int f = 0; f < FR; ++f)
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) acc[f][nb] = v4f{0, 0, 0, 0};
+    const int nchunk = (Ci + DCC - 1) / DCC;
+    const int c_lo = ks * cpb, c_hi = min(nchunk, c_lo + cpb);
+    for (int ch = c_lo; ch < c_hi; ++ch) {
+        __syncthreads();
+        // the tile's loads are issued in groups of eight before their LDS stores, so they overlap
+        constexpr int NIT = (DCC * DH_V + 255) / 256;
+#pragma unroll 8
+        for (int it = 0; it < NIT; ++it) {
+            const int e = tid + it * 256;
+            if (e < DCC * DH_V) {
+                const int c = e / DH_V, v = e - c * DH_V;
+                const int hx = v % DH_X, hy = (v / DH_X) % DH_Y, hz = v / (DH_X * DH_Y);
+                const int gx = x0 + hx - 1, gy = y0 + hy - 1, gz = z0 + hz - 1;
+                const int ci = ch * DCC + c;
+                float val = 0.f;
+                if (ci < Ci && (unsigned)gx < (unsigned)S && (unsigned)gy < (unsigned)S && (unsigned)gz < (unsigned)S)
+                    val = inb[(long long)ci * V + (gz * S + gy) * S + gx];
+                sIn[v][c] = MT<T>::cvt(val);
+            }
+        }
+        __syncthreads();
+        const T *wc = wt + (long long)ch * 27 * COP * DCC;
+        for (int tap = 0; tap < 27; ++tap) {
+            const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;
+#pragma unroll
+            for (int kk = 0; kk < DCC; kk += 4 * KL) {
+                const int kofs = kk + KL * (lane >> 4);
+                typename MT<T>::op af[FR];
+#pragma unroll
+                for (int f = 0; f < FR; ++f)
+                    af[f] = load_op<T>(wc + ((long long)tap * COP + row0 + f * 16 + (lane & 15)) * DCC + kofs);
+#pragma unroll
+                for (int nb = 0; nb < 4; ++nb) {
+                    const int n = nb * 16 + (lane & 15);
+                    const int hv = ((wave + dz) * DH_Y + (n / DT_X + dy)) * DH_X + (n % DT_X + dx);
+                    const typename MT<T>::op bf = load_op<T>(&sIn[hv][kofs]);
+#pragma unroll
+                    for (int f = 0; f < FR; ++f) acc[f][nb] = MT<T>::mma(af[f], bf, acc[f][nb]);
+                }
+            }
+        }
+    }
+    const int gz = z0 + wave;
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) {
+        const int n = nb * 16 + (lane & 15);
+        const int gx = x0 + n % DT_X, gy = y0 + n / DT_X;
+        const bool ok = gx < S && gy < S && gz < S;
+        const long long vo = ((long long)gz * S + gy) * S + gx;
+#pragma unroll
+        for (int f = 0; f < FR; ++f)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int co = row0 + f * 16 + 4 * (lane >> 4) + r;
+                if (!ok || co >= Co) continue;
+                if (nsplit == 1) {
+                    float y = acc[f][nb][r] + (bias ? bias[co] : 0.f);
+                    if (relu) y = fmaxf(y, 0.f);
+                    out[(long long)b * out_bs + (long long)co * V + vo] = y;
+                } else {
+                    part[(((long long)ks * B + b) * Co + co) * V + vo] = acc[f][nb][r];
+                }
+            }
+    }
+}
+
+// out[b][co][v] = act(bias[co] + sum_ks part[ks][b][co][v]) in split order
+__global__ void k_conv_split_sum(const float *__restrict__ part, int nsplit, int B, int Co, int V,
+                                 const float *__restrict__ bias, int relu, float *__restrict__ out, long long out_bs) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    const long long per = (long long)Co * V;
+    if (i >= per * B) return;
+    const int b = (int)(i / per);
+    const long long o = i - (long long)b * per;
+    const int co = (int)(o / V);
+    float s = bias ? bias[co] : 0.f;
+    for (int k = 0; k < nsplit; ++k) s += part[((long long)k * B + b) * per + o];
+    if (relu) s = fmaxf(s, 0.f);
+    out[(long long)b * out_bs + o] = s;
+}
+
+// direct-format weights wt[chunk][tap][COP][16] of a conv with Co outputs and Ci inputs; transpose = 1 takes
+// them from a layer W[Ci][Co][27] with the tap mirrored (the data-gradient convolution of that layer)
+template <typename T>
+__global__ void k_pack_direct(const float *__restrict__ W, int Co, int Ci, int transpose, int COP, long long total,
+                              T *__restrict__ wt) {
+    const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (e >= total) return;
+    const int cc = (int)(e % DCC);
+    long long r = e / DCC;
+    const int o = (int)(r % COP);
+    r /= COP;
+    const int tap = (int)(r % 27);
+    const int ch = (int)(r / 27);
+    const int i = ch * DCC + cc;
+    float v = 0.f;
+    if (o < Co && i < Ci)
+        v = transpose ? W[((long long)i * Co + o) * 27 + (26 - tap)] : W[((long long)o * Ci + i) * 27 + tap];
+    wt[e] = MT<T>::cvt(v);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------------------------- launchers
@@ -534,6 +680,78 @@ hipError_t cnn_conv_fwd_t(const float *in, long long in_bs, int Ci, int S, int t
     else if (COP == 96) hipLaunchKernelGGL((k_conv_fwd<T, 96>), dim3(grid), dim3(256), 0, s, in, in_bs, Ci, S, taps, w, Kp, bias, Co, out, out_bs, relu);
     else if (COP == 128) hipLaunchKernelGGL((k_conv_fwd<T, 128>), dim3(grid), dim3(256), 0, s, in, in_bs, Ci, S, taps, w, Kp, bias, Co, out, out_bs, relu);
     else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+// split the launch until it has about 1024 workgroups: first by output-row groups, then over input-channel chunks
+void cnn_direct_split(int Ci, int S, int COP, int B, int &fr, int &rowgroups, int &nsplit, int &cpb) {
+    const long long tiles = (long long)((S + DT_X - 1) / DT_X) * ((S + DT_Y - 1) / DT_Y) * ((S + DT_Z - 1) / DT_Z);
+    const int nchunk = (Ci + DCC - 1) / DCC;
+    const long long target = 1024;
+    fr = COP / 16;
+    rowgroups = 1;
+    nsplit = 1;
+    cpb = nchunk;
+    if (tiles * B >= target) return;
+    fr = 1;
+    rowgroups = COP / 16;
+    long long wg = tiles * B * rowgroups;
+    if (wg >= target || nchunk == 1) return;
+    int want = (int)std::min<long long>(nchunk, (target + wg - 1) / wg);
+    cpb = (nchunk + want - 1) / want;
+    nsplit = (nchunk + cpb - 1) / cpb;
+}
+
+template <typename T>
+hipError_t cnn_conv_direct_t(const float *in, long long in_bs, int Ci, int S, const void *wt, int COP, const float *bias,
+                             int Co, float *out, long long out_bs, int relu, int B, float *part, long long part_elems,
+                             hipStream_t s) {
+    int fr, rowgroups, nsplit, cpb;
+    cnn_direct_split(Ci, S, COP, B, fr, rowgroups, nsplit, cpb);
+    const long long V = (long long)S * S * S;
+    if (nsplit > 1 && (!part || (long long)nsplit * B * Co * V > part_elems)) {
+        nsplit = 1;                                         // no room for partial sums: one K split
+        cpb = (Ci + DCC - 1) / DCC;
+    }
+    const int tiles = ((S + DT_X - 1) / DT_X) * ((S + DT_Y - 1) / DT_Y) * ((S + DT_Z - 1) / DT_Z);
+    const unsigned grid = (unsigned)((long long)B * tiles * rowgroups * nsplit);
+    const T *w = (const T *)wt;
+#define DLAUNCH(F)                                                                                                   \
+    hipLaunchKernelGGL((k_conv_direct<T, F>), dim3(grid), dim3(256), 0, s, in, in_bs, Ci, S, w, COP, bias, Co, out,   \
+                       out_bs, relu, rowgroups, nsplit, cpb, part, B)
+    switch (fr) {
+    case 1: DLAUNCH(1); break;
+    case 2: DLAUNCH(2); break;
+    case 3: DLAUNCH(3); break;
+    case 4: DLAUNCH(4); break;
+    case 6: DLAUNCH(6); break;
+    case 8: DLAUNCH(8); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef DLAUNCH
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || nsplit == 1) return e;
+    const long long n = (long long)B * Co * V;
+    hipLaunchKernelGGL(k_conv_split_sum, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part, nsplit, B, Co, (int)V,
+                       bias, relu, out, out_bs);
+    return hipGetLastError();
+}
+
+hipError_t cnn_conv_direct(int use_bf16, const float *in, long long in_bs, int Ci, int S, const void *wt, int COP,
+                           const float *bias, int Co, float *out, long long out_bs, int relu, int B, float *part,
+                           long long part_elems, hipStream_t s) {
+    return use_bf16 ? cnn_conv_direct_t<bf16>(in, in_bs, Ci, S, wt, COP, bias, Co, out, out_bs, relu, B, part, part_elems, s)
+                    : cnn_conv_direct_t<float>(in, in_bs, Ci, S, wt, COP, bias, Co, out, out_bs, relu, B, part, part_elems, s);
+}
+
+long long cnn_direct_size(int Co, int Ci) { return (long long)((Ci + DCC - 1) / DCC) * 27 * ((Co + 15) / 16 * 16) * DCC; }
+
+hipError_t cnn_pack_direct(int use_bf16, const float *W, int Co, int Ci, int transpose, void *wt, hipStream_t s) {
+    const int COP = (Co + 15) / 16 * 16;
+    const long long total = cnn_direct_size(Co, Ci);
+    const unsigned grid = (unsigned)((total + 255) / 256);
+    if (use_bf16) hipLaunchKernelGGL(k_pack_direct<bf16>, dim3(grid), dim3(256), 0, s, W, Co, Ci, transpose, COP, total, (bf16 *)wt);
+    else hipLaunchKernelGGL(k_pack_direct<float>, dim3(grid), dim3(256), 0, s, W, Co, Ci, transpose, COP, total, (float *)wt);
     return hipGetLastError();
 }
 
