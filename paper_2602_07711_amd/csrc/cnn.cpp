@@ -35,6 +35,8 @@ hipError_t cnn_conv_direct(int use_bf16, const float *in, long long in_bs, int C
                            const float *bias, int Co, float *out, long long out_bs, int relu, int B, float *part,
                            long long part_elems, hipStream_t s);
 long long cnn_direct_size(int Co, int Ci);
+hipError_t cnn_wgrad_direct(int use_bf16, const float *g, long long g_bs, int Co, const float *in, long long in_bs,
+                            int Ci, int S, int B, float *part, long long part_elems, float *dW, hipStream_t s);
 hipError_t cnn_pack_direct(int use_bf16, const float *W, int Co, int Ci, int transpose, void *wt, hipStream_t s);
 hipError_t cnn_features(const double *k2h, const double2 *fh, int halo, int nf, int S, double k0sq, double cs,
                         double fs, float *x, hipStream_t s);
@@ -148,9 +150,14 @@ helm_status conv_bwd(helm_cnn &n, int l, View in, View g, View *gin, int B) {
     vchunk = (vchunk + KC - 1) / KC * KC;
     const int nch = (int)((NV + vchunk - 1) / vchunk);
     const int Kp = pad64(ci * taps);
-    if ((long long)nch * pad16(co) * Kp > n.part_elems) { n.err = "wgrad partial buffer too small"; return HELM_EINVAL; }
-    NTRY(cnn_conv_wgrad(n.bf16, g.p, g.bs, co, pad16(co), in.p, in.bs, ci, S, taps, B, Kp, (int)vchunk, nch, n.part,
-                        n.grads + n.woff[l], n.stream));
+    if (taps == 27) {
+        NTRY(cnn_wgrad_direct(n.bf16, g.p, g.bs, co, in.p, in.bs, ci, S, B, n.part, n.part_elems, n.grads + n.woff[l],
+                              n.stream));
+    } else {
+        if ((long long)nch * pad16(co) * Kp > n.part_elems) { n.err = "wgrad partial buffer too small"; return HELM_EINVAL; }
+        NTRY(cnn_conv_wgrad(n.bf16, g.p, g.bs, co, pad16(co), in.p, in.bs, ci, S, taps, B, Kp, (int)vchunk, nch, n.part,
+                            n.grads + n.woff[l], n.stream));
+    }
     NTRY(cnn_bias_grad(g.p, g.bs, B, V_of(n, lev), co, n.bias_part, n.grads + n.boff[l], n.stream));
     if (gin && taps == 27)
         NTRY(cnn_conv_direct(n.bf16, g.p, g.bs, co, S, n.wtT[l], n.COPt[l], nullptr, ci, gin->p, gin->bs, 0, B,

@@ -73,8 +73,8 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const float *__restrict__ in, 
                                                   long long out_bs, int relu) {
     constexpr int KL = MT<T>::KL;
     constexpr int FR = COP / 16;
-    __shared__ T sA[COP][KC + 4];
-    __shared__ T sB[CT][KC + 4];
+    __shared__ __attribute__((aligned(16))) T sA[COP][KC + 4];
+    __shared__ __attribute__((aligned(16))) T sB[CT][KC + 4];
     const int V = S * S * S;
     const int tiles = (V + CT - 1) / CT;
     const int b = (int)(blockIdx.x / tiles);
@@ -145,8 +145,8 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const float *__restrict__ g,
                                                     int taps, int B, int Kp, int vchunk, float *__restrict__ part) {
     constexpr int KL = MT<T>::KL;
     constexpr int FR = COP / 16;
-    __shared__ T sA[COP][KC + 4];
-    __shared__ T sB[CT][KC + 4];
+    __shared__ __attribute__((aligned(16))) T sA[COP][KC + 4];
+    __shared__ __attribute__((aligned(16))) T sB[CT][KC + 4];
     const int V = S * S * S;
     const int NV = V * B;
     const int ktiles = Kp / CT;
@@ -544,7 +544,7 @@ __global__ __launch_bounds__(256) void k_conv_direct(const float *__restrict__ i
                                                      int rowgroups, int nsplit, int cpb, float *__restrict__ part,
                                                      int B) {
     constexpr int KL = MT<T>::KL;
-    __shared__ T sIn[DH_V][DCC + DPAD];
+    __shared__ __attribute__((aligned(16))) T sIn[DH_V][DCC + DPAD];
     const int ntx = (S + DT_X - 1) / DT_X, nty = (S + DT_Y - 1) / DT_Y, ntz = (S + DT_Z - 1) / DT_Z;
     const int tiles = ntx * nty * ntz;
     int idx = blockIdx.x;
@@ -664,6 +664,123 @@ __global__ void k_pack_direct(const float *__restrict__ W, int Co, int Ci, int t
     wt[e] = MT<T>::cvt(v);
 }
 
+
+// Weight gradient of a 27-tap layer, dW[o][i][tap] = sum_{b,v} g[b][o][v] in[b][i][v + off(tap)]. A workgroup
+// (input-channel chunk ch, tile group tg) loops over the tiles tg, tg + G, ... of all samples; per tile it stages
+// g (COP rows x the tile's 256 voxels) and the chunk's input tile with halo in LDS. Wave w accumulates taps
+// w, w+4, ... as GEMMs with M = output channels, N = the chunk's 16 channels and K = voxels (16 per step: two
+// 8-voxel x-rows); the A fragment of a step is shared by the wave's taps. BF16 keeps the input tile in three
+// copies shifted by dx = 0, 1, 2 so each lane's four consecutive voxels are one aligned 8-byte read.
+// Partial sums per tile group: part[tg][o][i][tap] (o < Co, i < Ci), added in order by k_wgrad_direct_sum.
+constexpr int WG_GPAD = 8;
+template <typename T> struct WgLayout {
+    static constexpr int NSH = MT<T>::KL == 4 ? 3 : 1;      // shifted copies of the input tile
+    static constexpr int RW = MT<T>::KL == 4 ? DT_X : DH_X; // stored row width
+};
+
+template <typename T, int FR>
+__global__ __launch_bounds__(256) void k_wgrad_direct(const float *__restrict__ g, long long g_bs, int Co,
+                                                      const float *__restrict__ in, long long in_bs, int Ci, int S,
+                                                      int B, int G, float *__restrict__ part) {
+    constexpr int KL = MT<T>::KL;
+    constexpr int COP = FR * 16;
+    constexpr int NSH = WgLayout<T>::NSH, RW = WgLayout<T>::RW;
+    constexpr int NT = 7;                                     // taps per wave (27 = 7 + 7 + 7 + 6)
+    __shared__ __attribute__((aligned(16))) T sG[COP][DT_X * DT_Y * DT_Z + WG_GPAD];
+    __shared__ __attribute__((aligned(16))) T sX[NSH][DCC][DH_Z][DH_Y][RW];
+    const int ch = blockIdx.x / G, tg = blockIdx.x % G;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int ntx = (S + DT_X - 1) / DT_X, nty = (S + DT_Y - 1) / DT_Y, ntz = (S + DT_Z - 1) / DT_Z;
+    const int tiles = ntx * nty * ntz;
+    const int V = S * S * S;
+    v4f acc[NT][FR];
+#pragma unroll
+    for (int q = 0; q < NT; ++q)
+#pragma unroll
+        for (int f = 0; f < FR; ++f) acc[q][f] = v4f{0, 0, 0, 0};
+    for (int tt = tg; tt < B * tiles; tt += G) {
+        const int b = tt / tiles, t = tt % tiles;
+        const int x0 = (t % ntx) * DT_X, y0 = ((t / ntx) % nty) * DT_Y, z0 = (t / (ntx * nty)) * DT_Z;
+        const float *gb = g + (long long)b * g_bs;
+        const float *ib = in + (long long)b * in_bs;
+        __syncthreads();
+        for (int e = tid; e < COP * DT_X * DT_Y * DT_Z; e += 256) {
+            const int o = e / (DT_X * DT_Y * DT_Z), v = e % (DT_X * DT_Y * DT_Z);
+            const int gx = x0 + v % DT_X, gy = y0 + (v / DT_X) % DT_Y, gz = z0 + v / (DT_X * DT_Y);
+            float val = 0.f;
+            if (o < Co && gx < S && gy < S && gz < S) val = gb[(long long)o * V + (gz * S + gy) * S + gx];
+            sG[o][v] = MT<T>::cvt(val);
+        }
+        // input rows (c, hz, hy): the 10 values of x0-1 .. x0+8, stored once (FP32) or as three shifted 8-wide
+        // copies (BF16)
+        for (int rrow = tid; rrow < DCC * DH_Z * DH_Y; rrow += 256) {
+            const int c = rrow / (DH_Z * DH_Y), hz = (rrow / DH_Y) % DH_Z, hy = rrow % DH_Y;
+            const int ci = ch * DCC + c, gz = z0 + hz - 1, gy = y0 + hy - 1;
+            const bool rin = ci < Ci && (unsigned)gz < (unsigned)S && (unsigned)gy < (unsigned)S;
+            const float *rowp = ib + (long long)ci * V + ((long long)gz * S + gy) * S;
+            float r[DH_X];
+#pragma unroll
+            for (int hx = 0; hx < DH_X; ++hx) {
+                const int gx = x0 + hx - 1;
+                r[hx] = (rin && (unsigned)gx < (unsigned)S) ? rowp[gx] : 0.f;
+            }
+#pragma unroll
+            for (int sh = 0; sh < NSH; ++sh)
+#pragma unroll
+                for (int j = 0; j < RW; ++j) sX[sh][c][hz][hy][j] = MT<T>::cvt(r[j + sh]);
+        }
+        __syncthreads();
+#pragma unroll 1
+        for (int ks = 0; ks < 16; ++ks) {                     // K-step: output plane ks/4, rows 2(ks%4), +1
+            const int oz = ks >> 2, oy = (ks & 3) * 2;
+#pragma unroll
+            for (int sub = 0; sub < 4 / KL; ++sub) {
+                const int k = sub * 4 + KL * (lane >> 4);      // first voxel of this lane in the step
+                const int ky = oy + (k >> 3), kx = k & 7;
+                typename MT<T>::op af[FR];
+#pragma unroll
+                for (int f = 0; f < FR; ++f)
+                    af[f] = load_op<T>(&sG[f * 16 + (lane & 15)][(oz * DT_Y + ky) * DT_X + kx]);
+                const int i = lane & 15;
+#pragma unroll
+                for (int q = 0; q < NT; ++q) {
+                    const int tap = wave + 4 * q;
+                    if (tap < 27) {
+                        const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;
+                        const T *bp = (NSH == 3) ? &sX[dx][i][oz + dz][ky + dy][kx]
+                                                 : &sX[0][i][oz + dz][ky + dy][kx + dx];
+                        const typename MT<T>::op bf = load_op<T>(bp);
+#pragma unroll
+                        for (int f = 0; f < FR; ++f) acc[q][f] = MT<T>::mma(af[f], bf, acc[q][f]);
+                    }
+                }
+            }
+        }
+    }
+    // acc[q][f][r] = dW[o = 16 f + 4 (lane/16) + r][i = lane % 16][tap = wave + 4 q]
+    const int i = ch * DCC + (lane & 15);
+#pragma unroll
+    for (int q = 0; q < NT; ++q) {
+        const int tap = wave + 4 * q;
+        if (tap >= 27 || i >= Ci) continue;
+#pragma unroll
+        for (int f = 0; f < FR; ++f)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int o = f * 16 + 4 * (lane >> 4) + r;
+                if (o < Co) part[(((long long)tg * Co + o) * Ci + i) * 27 + tap] = acc[q][f][r];
+            }
+    }
+}
+
+__global__ void k_wgrad_direct_sum(const float *__restrict__ part, int G, long long n, float *__restrict__ dW) {
+    const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (e >= n) return;
+    float s = 0.f;
+    for (int q = 0; q < G; ++q) s += part[(long long)q * n + e];
+    dW[e] = s;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------------------------- launchers
@@ -742,6 +859,35 @@ hipError_t cnn_conv_direct(int use_bf16, const float *in, long long in_bs, int C
                            long long part_elems, hipStream_t s) {
     return use_bf16 ? cnn_conv_direct_t<bf16>(in, in_bs, Ci, S, wt, COP, bias, Co, out, out_bs, relu, B, part, part_elems, s)
                     : cnn_conv_direct_t<float>(in, in_bs, Ci, S, wt, COP, bias, Co, out, out_bs, relu, B, part, part_elems, s);
+}
+
+template <typename T>
+hipError_t cnn_wgrad_direct_t(const float *g, long long g_bs, int Co, const float *in, long long in_bs, int Ci, int S,
+                              int B, float *part, long long part_elems, float *dW, hipStream_t s) {
+    const int tiles = ((S + DT_X - 1) / DT_X) * ((S + DT_Y - 1) / DT_Y) * ((S + DT_Z - 1) / DT_Z);
+    const int nchunk = (Ci + DCC - 1) / DCC;
+    const long long per = (long long)Co * Ci * 27;
+    long long G = std::max<long long>(1, std::min<long long>((long long)B * tiles, (1024 + nchunk - 1) / nchunk));
+    G = std::min<long long>(G, part_elems / per);
+    if (G < 1) return hipErrorInvalidValue;
+    const int COP = (Co + 15) / 16 * 16;
+    const unsigned grid = (unsigned)(nchunk * G);
+    switch (COP / 16) {
+    case 1: hipLaunchKernelGGL((k_wgrad_direct<T, 1>), dim3(grid), dim3(256), 0, s, g, g_bs, Co, in, in_bs, Ci, S, B, (int)G, part); break;
+    case 2: hipLaunchKernelGGL((k_wgrad_direct<T, 2>), dim3(grid), dim3(256), 0, s, g, g_bs, Co, in, in_bs, Ci, S, B, (int)G, part); break;
+    case 4: hipLaunchKernelGGL((k_wgrad_direct<T, 4>), dim3(grid), dim3(256), 0, s, g, g_bs, Co, in, in_bs, Ci, S, B, (int)G, part); break;
+    default: return hipErrorInvalidValue;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_wgrad_direct_sum, dim3((unsigned)((per + 255) / 256)), dim3(256), 0, s, part, (int)G, per, dW);
+    return hipGetLastError();
+}
+
+hipError_t cnn_wgrad_direct(int use_bf16, const float *g, long long g_bs, int Co, const float *in, long long in_bs,
+                            int Ci, int S, int B, float *part, long long part_elems, float *dW, hipStream_t s) {
+    return use_bf16 ? cnn_wgrad_direct_t<bf16>(g, g_bs, Co, in, in_bs, Ci, S, B, part, part_elems, dW, s)
+                    : cnn_wgrad_direct_t<float>(g, g_bs, Co, in, in_bs, Ci, S, B, part, part_elems, dW, s);
 }
 
 long long cnn_direct_size(int Co, int Ci) { return (long long)((Ci + DCC - 1) / DCC) * 27 * ((Co + 15) / 16 * 16) * DCC; }
