@@ -13,9 +13,6 @@
 namespace helm {
 hipError_t cnn_conv_fwd(int bf16, const float *in, long long in_bs, int Ci, int S, int taps, const void *wt, int Kp,
                         int COP, const float *bias, int Co, float *out, long long out_bs, int relu, int B, hipStream_t s);
-hipError_t cnn_conv_wgrad(int bf16, const float *g, long long g_bs, int Co, int COP, const float *in, long long in_bs,
-                          int Ci, int S, int taps, int B, int Kp, int vchunk, int nch, float *part, float *dW,
-                          hipStream_t s);
 hipError_t cnn_bias_grad(const float *g, long long g_bs, int B, long long V, int Co, float *part, float *db,
                          hipStream_t s);
 hipError_t cnn_pack_weights(int bf16, const float *W, int Co, int Ci, int taps, int transpose, int COP, int Kp,
@@ -35,6 +32,8 @@ hipError_t cnn_conv_direct(int use_bf16, const float *in, long long in_bs, int C
                            const float *bias, int Co, float *out, long long out_bs, int relu, int B, float *part,
                            long long part_elems, hipStream_t s);
 long long cnn_direct_size(int Co, int Ci);
+hipError_t cnn_wgrad_1x1(const float *g, long long g_bs, int Co, const float *in, long long in_bs, int Ci, int V, int B,
+                         float *part, long long part_elems, float *dW, hipStream_t s);
 hipError_t cnn_wgrad_direct(int use_bf16, const float *g, long long g_bs, int Co, const float *in, long long in_bs,
                             int Ci, int S, int B, float *part, long long part_elems, float *dW, hipStream_t s);
 hipError_t cnn_pack_direct(int use_bf16, const float *W, int Co, int Ci, int transpose, void *wt, hipStream_t s);
@@ -144,19 +143,12 @@ helm_status conv_fwd(helm_cnn &n, int l, View in, View out, int B) {
 helm_status conv_bwd(helm_cnn &n, int l, View in, View g, View *gin, int B) {
     const int ci = LAYERS[l][0], co = LAYERS[l][1], taps = LAYERS[l][2], lev = LAYERS[l][4];
     const int S = S_of(n, lev);
-    const long long NV = V_of(n, lev) * B;
-    const int KC = 32;
-    long long vchunk = (NV + 127) / 128;
-    vchunk = (vchunk + KC - 1) / KC * KC;
-    const int nch = (int)((NV + vchunk - 1) / vchunk);
-    const int Kp = pad64(ci * taps);
     if (taps == 27) {
         NTRY(cnn_wgrad_direct(n.bf16, g.p, g.bs, co, in.p, in.bs, ci, S, B, n.part, n.part_elems, n.grads + n.woff[l],
                               n.stream));
     } else {
-        if ((long long)nch * pad16(co) * Kp > n.part_elems) { n.err = "wgrad partial buffer too small"; return HELM_EINVAL; }
-        NTRY(cnn_conv_wgrad(n.bf16, g.p, g.bs, co, pad16(co), in.p, in.bs, ci, S, taps, B, Kp, (int)vchunk, nch, n.part,
-                            n.grads + n.woff[l], n.stream));
+        NTRY(cnn_wgrad_1x1(g.p, g.bs, co, in.p, in.bs, ci, (int)V_of(n, lev), B, n.part, n.part_elems,
+                           n.grads + n.woff[l], n.stream));
     }
     NTRY(cnn_bias_grad(g.p, g.bs, B, V_of(n, lev), co, n.bias_part, n.grads + n.boff[l], n.stream));
     if (gin && taps == 27)

@@ -1,16 +1,16 @@
 // Kernels of the learned warm start: a 3D encoder-decoder CNN trained and run on the GPU.
 //
-// Convolutions are implicit GEMMs on MFMA: out[co][v] = sum_{ci, tap} W[co][ci tap] in[ci][v + off(tap)], the
-// im2col operand gathered on the fly into LDS. Operands are BF16 (v_mfma_f32_16x16x16bf16_1k) or FP32
-// (v_mfma_f32_16x16x4f32), accumulation FP32, activations stored FP32. Lane layout (checked on gfx950):
-// A(row = lane%16, k = KL*(lane/16) + e), B(k = KL*(lane/16) + e, col = lane%16), accumulator register r =
-// D(row = 4*(lane/16) + r, col = lane%16), KL = 4 (bf16) or 1 (f32).
-//   * forward:  rows = output channels (padded to COP), cols = 64 voxels per workgroup;
-//   * dgrad:    the same kernel with W'[ci][co tap'] = W[co][ci tap], tap' the mirrored offset;
-//   * wgrad:    dW[co][ci tap] = sum_v g[co][v] in[ci][v + off(tap)], rows = co, cols = 64 (ci tap), the
-//               voxel sum split over chunks into FP32 partials reduced in a fixed order.
-// Also: bias add + ReLU in the epilogue, ReLU backward, 2x average pooling and nearest upsampling (both
-// directions), MSE loss, Adam, and trilinear prolongation of a coarse prediction to the solver's grid.
+// MFMA operands are BF16 (v_mfma_f32_16x16x16bf16_1k) or FP32 (v_mfma_f32_16x16x4f32), accumulation FP32,
+// activations stored FP32. Lane layout (checked on gfx950): A(row = lane%16, k = KL*(lane/16) + e),
+// B(k = KL*(lane/16) + e, col = lane%16), accumulator register r = D(row = 4*(lane/16) + r, col = lane%16),
+// KL = 4 (bf16) or 1 (f32).
+//   * 27-tap layers: direct convolution from LDS tiles (k_conv_direct; the data gradient is the same kernel
+//     with mirrored, transposed weights) and a direct weight-gradient kernel (k_wgrad_direct);
+//   * the 1x1x1 head: an implicit GEMM out[co][v] = sum_ci W[co][ci] in[ci][v] (k_conv_fwd) and a reduction for
+//     its weight gradient (k_wgrad_1x1).
+// Also: bias add + ReLU in the epilogues, bias gradient, ReLU backward, 2x average pooling and nearest
+// upsampling (both directions), MSE loss, Adam, the network input from the solver's arrays, and the trilinear
+// or cubic prolongation of a coarse prediction to the solver's grid.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -135,95 +135,6 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const float *__restrict__ in, 
                 outb[(long long)co * V + vo] = y;
             }
         }
-}
-
-// weight gradient partials: part[ch][co][k] = sum over voxel chunk ch of g[co][v] X[k][v]
-// (u = b V + v runs over the batch's voxels; chunk ch covers u in [ch vchunk, (ch+1) vchunk))
-template <typename T, int COP>
-__global__ __launch_bounds__(256) void k_conv_wgrad(const float *__restrict__ g, long long g_bs, int Co,
-                                                    const float *__restrict__ in, long long in_bs, int Ci, int S,
-                                                    int taps, int B, int Kp, int vchunk, float *__restrict__ part) {
-    constexpr int KL = MT<T>::KL;
-    constexpr int FR = COP / 16;
-    __shared__ __attribute__((aligned(16))) T sA[COP][KC + 4];
-    __shared__ __attribute__((aligned(16))) T sB[CT][KC + 4];
-    const int V = S * S * S;
-    const int NV = V * B;
-    const int ktiles = Kp / CT;
-    const int kt = blockIdx.x % ktiles, ch = blockIdx.x / ktiles;
-    const int vs = ch * vchunk, ve = vs + vchunk < NV ? vs + vchunk : NV;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    // g tile: this thread loads voxel kk_a of each chunk for rows ra, ra + 8, ...
-    const int kk_a = tid & 31, ra = tid >> 5;
-    // im2col tile: this thread owns column k (fixed ci, tap) and voxels kq, kq + 4, ... of each chunk
-    const int colk = tid & 63, kq = tid >> 6;
-    const int k = kt * CT + colk;
-    const bool kin = k < Ci * taps;
-    const int ci = k / taps, t = k - (k / taps) * taps;
-    int dz = 0, dy = 0, dx = 0;
-    if (taps == 27) { dz = t / 9 - 1; dy = (t / 3) % 3 - 1; dx = t % 3 - 1; }
-    v4f acc[FR];
-#pragma unroll
-    for (int f = 0; f < FR; ++f) acc[f] = v4f{0, 0, 0, 0};
-    for (int u0 = vs; u0 < ve; u0 += KC) {
-        __syncthreads();
-        {
-            const int u = u0 + kk_a;
-            const bool uin = u < ve;
-            const int b = u / V, v = u - (u / V) * V;
-            const float *gp = g + (long long)b * g_bs + v;
-            for (int r = ra; r < COP; r += 8)
-                sA[r][kk_a] = MT<T>::cvt(uin && r < Co ? gp[(long long)r * V] : 0.f);
-        }
-        {
-            int u = u0 + kq;
-            int b = u / V, rem = u - (u / V) * V;
-            int zd = rem / (S * S), yh = (rem / S) % S, xw = rem % S;
-#pragma unroll
-            for (int j = 0; j < KC / 4; ++j) {
-                float val = 0.f;
-                if (kin && u < ve) {
-                    const int zz = zd + dz, yy = yh + dy, xx = xw + dx;
-                    if ((unsigned)zz < (unsigned)S && (unsigned)yy < (unsigned)S && (unsigned)xx < (unsigned)S)
-                        val = in[(long long)b * in_bs + (long long)ci * V + (zz * S + yy) * S + xx];
-                }
-                sB[colk][kq + 4 * j] = MT<T>::cvt(val);
-                u += 4;
-                xw += 4;
-                while (xw >= S) { xw -= S; ++yh; }
-                while (yh >= S) { yh -= S; ++zd; }
-                while (zd >= S) { zd -= S; ++b; }
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int ks = 0; ks < KC; ks += 4 * KL) {
-            const int kofs = ks + KL * (lane >> 4);
-            typename MT<T>::op bf = load_op<T>(&sB[wave * 16 + (lane & 15)][kofs]);
-#pragma unroll
-            for (int f = 0; f < FR; ++f) {
-                typename MT<T>::op af = load_op<T>(&sA[f * 16 + (lane & 15)][kofs]);
-                acc[f] = MT<T>::mma(af, bf, acc[f]);
-            }
-        }
-    }
-    float *pp = part + (long long)ch * COP * Kp;
-    const int kw = kt * CT + wave * 16 + (lane & 15);
-#pragma unroll
-    for (int f = 0; f < FR; ++f)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) pp[(long long)(f * 16 + 4 * (lane >> 4) + r) * Kp + kw] = acc[f][r];
-}
-
-// dW[co][k] = sum_ch part[ch][co][k] (fixed order), k < K, co < Co
-__global__ void k_wgrad_reduce(const float *__restrict__ part, int nch, int COP, int Kp, int Co, int K,
-                               float *__restrict__ dW) {
-    long long i = (long long)blockIdx.x * 256 + threadIdx.x;
-    if (i >= (long long)Co * K) return;
-    int co = (int)(i / K), k = (int)(i % K);
-    float s = 0.f;
-    for (int c = 0; c < nch; ++c) s += part[((long long)c * COP + co) * Kp + k];
-    dW[i] = s;
 }
 
 // db[co] = sum_{b,v} g[b][co][v]: block (co, s) sums slice s of the B V voxels into part[co][s]; a second
@@ -773,12 +684,61 @@ __global__ __launch_bounds__(256) void k_wgrad_direct(const float *__restrict__ 
     }
 }
 
-__global__ void k_wgrad_direct_sum(const float *__restrict__ part, int G, long long n, float *__restrict__ dW) {
-    const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
-    if (e >= n) return;
+// dW[e] = sum_q part[q][e], q = 0..G-1: a block takes 64 consecutive e; thread (e, j) adds q = j, j + 4, ...
+// (coalesced rows of 64 values), and the four partial sums are added in the order j = 0..3
+__global__ __launch_bounds__(256) void k_wgrad_direct_sum(const float *__restrict__ part, int G, long long n,
+                                                          float *__restrict__ dW) {
+    __shared__ float sm[4][64];
+    const int el = threadIdx.x & 63, j = threadIdx.x >> 6;
+    const long long e = (long long)blockIdx.x * 64 + el;
     float s = 0.f;
-    for (int q = 0; q < G; ++q) s += part[(long long)q * n + e];
-    dW[e] = s;
+    if (e < n)
+        for (int q = j; q < G; q += 4) s += part[(long long)q * n + e];
+    sm[j][el] = s;
+    __syncthreads();
+    if (j == 0 && e < n) dW[e] = ((sm[0][el] + sm[1][el]) + sm[2][el]) + sm[3][el];
+}
+
+// weight gradient of a 1x1x1 layer, dW[o][i] = sum_{b,v} g[b][o][v] in[b][i][v] (Co <= 4, Ci <= 16): each
+// thread accumulates all Co x Ci products over its voxels, blocks reduce in a fixed order into part[blk][o][i]
+constexpr int W1_CO = 4, W1_CI = 16, W1_VPT = 16;
+__global__ __launch_bounds__(256) void k_wgrad_1x1(const float *__restrict__ g, long long g_bs, int Co,
+                                                   const float *__restrict__ in, long long in_bs, int Ci, int V, int B,
+                                                   float *__restrict__ part) {
+    __shared__ float sm[256];
+    float acc[W1_CO][W1_CI];
+#pragma unroll
+    for (int o = 0; o < W1_CO; ++o)
+#pragma unroll
+        for (int i = 0; i < W1_CI; ++i) acc[o][i] = 0.f;
+    const long long NV = (long long)V * B;
+    const long long u0 = ((long long)blockIdx.x * W1_VPT) * 256 + threadIdx.x;
+    for (int k = 0; k < W1_VPT; ++k) {
+        const long long u = u0 + (long long)k * 256;
+        if (u >= NV) break;
+        const int b = (int)(u / V);
+        const long long v = u - (long long)b * V;
+        float gv[W1_CO];
+#pragma unroll
+        for (int o = 0; o < W1_CO; ++o) gv[o] = o < Co ? g[(long long)b * g_bs + (long long)o * V + v] : 0.f;
+#pragma unroll
+        for (int i = 0; i < W1_CI; ++i) {
+            const float x = i < Ci ? in[(long long)b * in_bs + (long long)i * V + v] : 0.f;
+#pragma unroll
+            for (int o = 0; o < W1_CO; ++o) acc[o][i] += gv[o] * x;
+        }
+    }
+    for (int o = 0; o < Co; ++o)
+        for (int i = 0; i < Ci; ++i) {
+            sm[threadIdx.x] = acc[o < W1_CO ? o : 0][i < W1_CI ? i : 0];
+            __syncthreads();
+            for (int w = 128; w > 0; w >>= 1) {
+                if (threadIdx.x < w) sm[threadIdx.x] += sm[threadIdx.x + w];
+                __syncthreads();
+            }
+            if (threadIdx.x == 0) part[((long long)blockIdx.x * Co + o) * Ci + i] = sm[0];
+            __syncthreads();
+        }
 }
 
 }  // namespace
@@ -880,7 +840,21 @@ hipError_t cnn_wgrad_direct_t(const float *g, long long g_bs, int Co, const floa
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_wgrad_direct_sum, dim3((unsigned)((per + 255) / 256)), dim3(256), 0, s, part, (int)G, per, dW);
+    hipLaunchKernelGGL(k_wgrad_direct_sum, dim3((unsigned)((per + 63) / 64)), dim3(256), 0, s, part, (int)G, per, dW);
+    return hipGetLastError();
+}
+
+hipError_t cnn_wgrad_1x1(const float *g, long long g_bs, int Co, const float *in, long long in_bs, int Ci, int V, int B,
+                         float *part, long long part_elems, float *dW, hipStream_t s) {
+    if (Co > W1_CO || Ci > W1_CI) return hipErrorInvalidValue;
+    const long long NV = (long long)V * B;
+    const long long nblk = (NV + 256LL * W1_VPT - 1) / (256LL * W1_VPT);
+    const long long per = (long long)Co * Ci;
+    if (nblk * per > part_elems) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_wgrad_1x1, dim3((unsigned)nblk), dim3(256), 0, s, g, g_bs, Co, in, in_bs, Ci, V, B, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_wgrad_direct_sum, dim3((unsigned)((per + 63) / 64)), dim3(256), 0, s, part, (int)nblk, per, dW);
     return hipGetLastError();
 }
 
@@ -906,29 +880,6 @@ hipError_t cnn_conv_fwd(int use_bf16, const float *in, long long in_bs, int Ci, 
                         hipStream_t s) {
     return use_bf16 ? cnn_conv_fwd_t<bf16>(in, in_bs, Ci, S, taps, wt, Kp, COP, bias, Co, out, out_bs, relu, B, s)
                 : cnn_conv_fwd_t<float>(in, in_bs, Ci, S, taps, wt, Kp, COP, bias, Co, out, out_bs, relu, B, s);
-}
-
-template <typename T>
-hipError_t cnn_conv_wgrad_t(const float *g, long long g_bs, int Co, int COP, const float *in, long long in_bs, int Ci,
-                            int S, int taps, int B, int Kp, int vchunk, int nch, float *part, hipStream_t s) {
-    unsigned grid = (unsigned)((Kp / CT) * nch);
-    if (COP == 16) hipLaunchKernelGGL((k_conv_wgrad<T, 16>), dim3(grid), dim3(256), 0, s, g, g_bs, Co, in, in_bs, Ci, S, taps, B, Kp, vchunk, part);
-    else if (COP == 32) hipLaunchKernelGGL((k_conv_wgrad<T, 32>), dim3(grid), dim3(256), 0, s, g, g_bs, Co, in, in_bs, Ci, S, taps, B, Kp, vchunk, part);
-    else if (COP == 64) hipLaunchKernelGGL((k_conv_wgrad<T, 64>), dim3(grid), dim3(256), 0, s, g, g_bs, Co, in, in_bs, Ci, S, taps, B, Kp, vchunk, part);
-    else return hipErrorInvalidValue;
-    return hipGetLastError();
-}
-
-hipError_t cnn_conv_wgrad(int use_bf16, const float *g, long long g_bs, int Co, int COP, const float *in, long long in_bs,
-                          int Ci, int S, int taps, int B, int Kp, int vchunk, int nch, float *part, float *dW,
-                          hipStream_t s) {
-    hipError_t e = use_bf16 ? cnn_conv_wgrad_t<bf16>(g, g_bs, Co, COP, in, in_bs, Ci, S, taps, B, Kp, vchunk, nch, part, s)
-                        : cnn_conv_wgrad_t<float>(g, g_bs, Co, COP, in, in_bs, Ci, S, taps, B, Kp, vchunk, nch, part, s);
-    if (e != hipSuccess) return e;
-    long long n = (long long)Co * Ci * taps;
-    hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part, nch, COP, Kp, Co,
-                       Ci * taps, dW);
-    return hipGetLastError();
 }
 
 hipError_t cnn_bias_grad(const float *g, long long g_bs, int B, long long V, int Co, float *part, float *db,
