@@ -185,8 +185,8 @@ def bench_batched(H, torch, dev, args):
 def bench_learned(H, torch, args):
     """Learned warm start: 64^3 four-inclusion problems (k0 = 60, source width 0.03) solved by FP32-EigT
     FGMRES generate the training set, the CNN trains on the GPU with the library's BF16 kernels, and held-out
-    128^3 problems are solved to rtol 1e-8 from zero and from the prolonged prediction. By default a reduced
-    training budget keeps the run short (--ws-samples / --ws-epochs give the full 2000-solve configuration)."""
+    128^3 problems are solved to rtol 1e-8 from zero and from the prolonged prediction (2000 training solves and
+    20 epochs by default; --ws-samples / --ws-epochs shorten it)."""
     from paper_2602_07711_amd import warmstart as W
     S = 64
     ws, rep = W.fit(size=S, samples=args.ws_samples, epochs=args.ws_epochs, batch=4, lr=1e-3, k0=60.0,
@@ -225,8 +225,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched workloads")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-warm-start leg")
-    ap.add_argument("--ws-samples", type=int, default=400, help="training solves of the learned leg (full: 2000)")
-    ap.add_argument("--ws-epochs", type=int, default=6, help="training epochs of the learned leg (full: 20)")
+    ap.add_argument("--ws-samples", type=int, default=2000, help="training solves of the learned leg")
+    ap.add_argument("--ws-epochs", type=int, default=20, help="training epochs of the learned leg")
     ap.add_argument("--ws-eval", type=int, default=2, help="held-out 128^3 problems of the learned leg")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run three plain 256 MiB device-to-device copies (reference dispatches for scaling "

@@ -288,7 +288,9 @@ helm_status helm_cnn_train_step(helm_cnn *net, const float *x, const float *t, i
  * gamma = gamma_re + i gamma_im per axis crossed: U(-1) = gamma U(0), U(nc) = gamma U(nc-1) (Sec. 2.3, eq.
  * D_bc; gamma = (2 + i k0 h_c)/(2 - i k0 h_c) with h_c = 1/(nc+1) for the absorbing closure, 0 for Dirichlet).
  * cubic = 1 replaces the trilinear weights by Keys' cubic convolution (a = -1/2, coarse indices i0-1..i0+2 per
- * axis), the second ghost layer taking gamma^2 U(0) (the closure applied twice). */
+ * axis), the second ghost layer taking gamma^2 U(0) (the closure applied twice), computed as three 1-D passes;
+ * it keeps a work buffer of (nf nc^2 + nf^2 nc) complex128 values in the network, allocated on first use and
+ * grown for larger grids (HELM_EDEVICE if that allocation fails). */
 helm_status helm_cnn_prolong(helm_cnn *net, const float *coarse, int nc, double scale, double gamma_re,
                              double gamma_im, int cubic, void *fine, int nf);
 

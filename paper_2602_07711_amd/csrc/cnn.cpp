@@ -3,6 +3,7 @@
 // channels 16/32/64/64, 3x3x3 convolutions with bias and ReLU, 2x average pooling, nearest upsampling with
 // skip concatenation, and a 1x1x1 linear head: 2 input channels (contrast, source) -> 2 output channels
 // (Re u, Im u).
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -27,7 +28,7 @@ hipError_t cnn_mse(const float *y, const float *t, long long n, float *g, double
 hipError_t cnn_adam(float *w, const float *g, float *m, float *v, long long n, float lr, float b1, float b2, float eps,
                     float c1, float c2, hipStream_t s);
 hipError_t cnn_prolong(const float *coarse, int nc, double scale, double gre, double gim, int cubic, double2 *fine,
-                       int nf, hipStream_t s);
+                       int nf, double2 *work, hipStream_t s);
 hipError_t cnn_conv_direct(int use_bf16, const float *in, long long in_bs, int Ci, int S, const void *wt, int COP,
                            const float *bias, int Co, float *out, long long out_bs, int relu, int B, float *part,
                            long long part_elems, hipStream_t s);
@@ -84,6 +85,8 @@ struct helm_cnn {
     long long part_elems = 0;
     double *mse_part = nullptr, *loss_dev = nullptr;
     float *bias_part = nullptr;      // 64 slices per channel of the bias-gradient reduction
+    double2 *pwork = nullptr;        // separable cubic prolongation intermediates (grown on demand)
+    long long pwork_elems = 0;
 };
 
 namespace {
@@ -404,7 +407,26 @@ helm_status helm_cnn_prolong(helm_cnn *n_, const float *coarse, int nc, double s
                              double gamma_im, int cubic, void *fine, int nf) {
     if (!n_ || !coarse || !fine || nc < 1 || nf < 1) return HELM_EINVAL;
     helm_cnn &n = *n_;
-    NTRY(cnn_prolong(coarse, nc, scale, gamma_re, gamma_im, cubic, (double2 *)fine, nf, n.stream));
+    double2 *work = nullptr;
+    if (cubic) {
+        const long long need = (long long)nf * nc * nc + (long long)nf * nf * nc;
+        if (need > n.pwork_elems) {
+            if (n.pwork) {
+                NTRY(hipStreamSynchronize(n.stream));
+                NTRY(hipFree(n.pwork));
+                n.allocs.erase(std::find(n.allocs.begin(), n.allocs.end(), (void *)n.pwork));
+                n.pwork = nullptr;
+                n.pwork_elems = 0;
+            }
+            void *q = nullptr;
+            NTRY(hipMalloc(&q, need * sizeof(double2)));
+            n.allocs.push_back(q);
+            n.pwork = (double2 *)q;
+            n.pwork_elems = need;
+        }
+        work = n.pwork;
+    }
+    NTRY(cnn_prolong(coarse, nc, scale, gamma_re, gamma_im, cubic, (double2 *)fine, nf, work, n.stream));
     return HELM_OK;
 }
 

@@ -398,6 +398,43 @@ __global__ void k_prolong3(const float *__restrict__ coarse, int nc, double scal
     fine[i] = make_double2(scale * re, scale * im);
 }
 
+
+// Separable form of the cubic prolongation (the 3-D operator is the product of three 1-D ones, ghost factors
+// included): pass a interpolates along one axis, from an array [ch][n2][n1][nin] (innermost axis interpolated) to
+// [ch][n2][n1][nout] with the output axis rotated to the front: out[ch][nout][n2][n1]. Three passes (x, y, z)
+// give [ch][z][y][x] again. Complex data as (re, im) doubles; the first pass reads the FP32 prediction.
+template <typename TIN>
+__global__ void k_prolong3_pass(const TIN *__restrict__ src, int ncplx_in, int nin, int n1, int n2, int nout,
+                                double gre, double gim, double scale, double2 *__restrict__ dst) {
+    const long long total = (long long)nout * n1 * n2;
+    const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (e >= total) return;
+    // output index: [o][a2][a1] (o slowest) so writes are contiguous along a1
+    const int a1 = (int)(e % n1), a2 = (int)((e / n1) % n2), o = (int)(e / ((long long)n1 * n2));
+    const long long num = (long long)(o + 1) * (nin + 1);
+    const long long q = num / (nout + 1);
+    const int i0 = (int)q - 1;
+    const double t = (double)(num - q * (nout + 1)) / (nout + 1), t2 = t * t, t3 = t2 * t;
+    const double w[4] = {-0.5 * t3 + t2 - 0.5 * t, 1.5 * t3 - 2.5 * t2 + 1.0, -1.5 * t3 + 2.0 * t2 + 0.5 * t,
+                         0.5 * t3 - 0.5 * t2};
+    double re = 0.0, im = 0.0;
+    for (int k = 0; k < 4; ++k) {
+        if (w[k] == 0.0) continue;
+        int c = i0 - 1 + k, m = 0;
+        if (c < 0) { m = -c; c = 0; }
+        else if (c >= nin) { m = c - nin + 1; c = nin - 1; }
+        double fr = 1.0, fi = 0.0;                     // gamma^m
+        for (int r = 0; r < m; ++r) { const double nr = fr * gre - fi * gim; fi = fr * gim + fi * gre; fr = nr; }
+        const long long si = ((long long)a2 * n1 + a1) * nin + c;
+        double ur, ui;
+        if (ncplx_in) { const double2 z = ((const double2 *)src)[si]; ur = z.x; ui = z.y; }
+        else { ur = (double)((const float *)src)[si]; ui = (double)((const float *)src)[(long long)n1 * n2 * nin + si]; }
+        re += w[k] * (fr * ur - fi * ui);
+        im += w[k] * (fr * ui + fi * ur);
+    }
+    dst[e] = make_double2(scale * re, scale * im);
+}
+
 // network input from the solver's arrays: node (i, j, l) of the S^3 grid sits at ((i, j, l) + 1)/(S+1) in the unit
 // cube, which is fine-grid index coordinate (i+1)(nf+1)/(S+1) - 1 per axis; k^2 and Re f are interpolated
 // trilinearly there (weights from integer arithmetic, so nested grids inject exactly). Channel 0 =
@@ -942,9 +979,19 @@ hipError_t cnn_features(const double *k2h, const double2 *fh, int halo, int nf, 
     return hipGetLastError();
 }
 hipError_t cnn_prolong(const float *coarse, int nc, double scale, double gre, double gim, int cubic, double2 *fine,
-                       int nf, hipStream_t s) {
+                       int nf, double2 *work, hipStream_t s) {
     long long n = (long long)nf * nf * nf;
-    if (cubic)
+    if (cubic && work) {
+        // x: [z][y][x] -> [x'][z][y]; y: [x'][z][y] -> [y'][x'][z]; z: [y'][x'][z] -> [z'][y'][x']
+        double2 *t1 = work, *t2 = work + (long long)nf * nc * nc;
+        const long long m1 = (long long)nf * nc * nc, m2 = (long long)nf * nf * nc;
+        hipLaunchKernelGGL(k_prolong3_pass<float>, dim3((unsigned)((m1 + 255) / 256)), dim3(256), 0, s, coarse, 0, nc,
+                           nc, nc, nf, gre, gim, 1.0, t1);
+        hipLaunchKernelGGL(k_prolong3_pass<double2>, dim3((unsigned)((m2 + 255) / 256)), dim3(256), 0, s, t1, 1, nc,
+                           nc, nf, nf, gre, gim, 1.0, t2);
+        hipLaunchKernelGGL(k_prolong3_pass<double2>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, t2, 1, nc,
+                           nf, nf, nf, gre, gim, scale, fine);
+    } else if (cubic)
         hipLaunchKernelGGL(k_prolong3, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, coarse, nc, scale, gre, gim,
                            fine, nf);
     else
