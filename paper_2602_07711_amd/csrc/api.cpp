@@ -182,6 +182,8 @@ template <typename CT> helm_status build_pfft_mats(Ctx &c, PfftMats<CT> &m) {
     ST_TRY(dalloc(c, &m.ringW, ring));
     ST_TRY(dalloc(c, &m.rpart, (size_t)c.nz * ring_rowgroups() * 2 * c.nx));
     ST_TRY(dalloc(c, &m.sv, (size_t)c.nz * 2 * c.ny));
+    ST_TRY(dalloc(c, &m.rsum, (size_t)c.nz * 2 * c.nx));
+    ST_TRY(dalloc(c, &m.rbuf, ring));
     ST_TRY(dalloc(c, &m.fvec, ring));
     return HELM_OK;
 }
@@ -227,11 +229,11 @@ helm_status pfft_apply(Ctx &c, const double2 *y, double2 *z, bool fp32) {
         HIP_TRY(timed(c, HELM_K_PFFT, 4.0 * dx.M * (double)dx.N * dx.K, [&] { return launch_gemm_z64(dx, y, m.Sx, c.t1, c.stream, 2); }));
         HIP_TRY(timed(c, HELM_K_PFFT, 4.0 * dy.M * (double)dy.N * dy.K * dy.batch, [&] { return launch_gemm_z64(dy, m.Sy, c.t1, m.yhat, c.stream, 1); }));
         HIP_TRY(timed(c, HELM_K_TRIDIAG64, 32.0 * c.n, [&] { return launch_tridiag_chunk_z64(m.yhat, c.t2, c.tpiv_dir, P.dFx, P.dFy, nx, ny, nz, c.ax, c.ay, c.c0, gz, hz2, c.stream); }));
-        HIP_TRY(timed(c, HELM_K_RING, 16.0 * c.n + ring_work, [&] { return launch_ring_inverse_z64(c.t2, m.ringT, m.Sy, m.Sy, m.Sx, m.Sx, nx, ny, nz, m.rpart, m.sv, c.stream); }));
-        HIP_TRY(timed(c, HELM_K_RING, 16.0 * c.n + ring_work, [&] { return launch_ring_forward_z64(m.ringT, nullptr, nullptr, 0.0, c.t2, m.VyiT, c.BxF, ex, ey, nx, ny, nz, m.fvec, c.stream); }));
+        HIP_TRY(timed(c, HELM_K_RING, 16.0 * c.n + ring_work, [&] { return launch_ring_inverse_z64(c.t2, m.ringT, m.Sy, m.Sy, m.Sx, m.Sx, nx, ny, nz, m.rpart, m.sv, m.rsum, c.stream); }));
+        HIP_TRY(timed(c, HELM_K_RING, 16.0 * c.n + ring_work, [&] { return launch_ring_forward_z64(m.ringT, nullptr, nullptr, 0.0, c.t2, m.VyiT, c.BxF, ex, ey, nx, ny, nz, m.rbuf, m.fvec, c.stream); }));
         HIP_TRY(timed(c, HELM_K_TRIDIAG64, 32.0 * c.n, [&] { return launch_tridiag_chunk_z64(c.t2, c.t2, c.tpiv_eig, c.dxe, c.dye, nx, ny, nz, c.ax, c.ay, c.c0, gz, 1.0, c.stream); }));
-        HIP_TRY(timed(c, HELM_K_RING, 16.0 * c.n + ring_work, [&] { return launch_ring_inverse_z64(c.t2, m.ringW, c.AyI, m.VyT, m.Vx, c.BxI, nx, ny, nz, m.rpart, m.sv, c.stream); }));
-        HIP_TRY(timed(c, HELM_K_RING, 32.0 * c.n + 2 * ring_work, [&] { return launch_ring_forward_z64(m.ringT, m.ringW, m.yhat, hz2, c.t2, m.Sy, m.Sx, ex, ey, nx, ny, nz, m.fvec, c.stream); }));
+        HIP_TRY(timed(c, HELM_K_RING, 16.0 * c.n + ring_work, [&] { return launch_ring_inverse_z64(c.t2, m.ringW, c.AyI, m.VyT, m.Vx, c.BxI, nx, ny, nz, m.rpart, m.sv, m.rsum, c.stream); }));
+        HIP_TRY(timed(c, HELM_K_RING, 32.0 * c.n + 2 * ring_work, [&] { return launch_ring_forward_z64(m.ringT, m.ringW, m.yhat, hz2, c.t2, m.Sy, m.Sx, ex, ey, nx, ny, nz, m.rbuf, m.fvec, c.stream); }));
         HIP_TRY(timed(c, HELM_K_TRIDIAG64, 32.0 * c.n, [&] { return launch_tridiag_chunk_z64(c.t2, c.t2, c.tpiv_dir, P.dFx, P.dFy, nx, ny, nz, c.ax, c.ay, c.c0, gz, 1.0, c.stream); }));
         HIP_TRY(timed(c, HELM_K_PFFT, 4.0 * dy.M * (double)dy.N * dy.K * dy.batch, [&] { return launch_gemm_z64(dy, m.Sy, c.t2, c.t1, c.stream, 1); }));
         HIP_TRY(timed(c, HELM_K_PFFT, 4.0 * dx.M * (double)dx.N * dx.K, [&] { return launch_gemm_z64(dx, c.t1, m.Sx, z, c.stream, 2); }));
@@ -241,11 +243,11 @@ helm_status pfft_apply(Ctx &c, const double2 *y, double2 *z, bool fp32) {
         HIP_TRY(timed(c, HELM_K_PFFT, 4.0 * dx.M * (double)dx.N * dx.K, [&] { return launch_gemm_z32_in64(dx, y, m.Sx, c.t1f, c.stream, 2); }));
         HIP_TRY(timed(c, HELM_K_PFFT, 4.0 * dy.M * (double)dy.N * dy.K * dy.batch, [&] { return launch_gemm_z32(dy, m.Sy, c.t1f, m.yhat, c.stream, 1); }));
         HIP_TRY(timed(c, HELM_K_TRIDIAG32, 16.0 * c.n, [&] { return launch_tridiag_chunk_z32(m.yhat, c.t2f, c.tpiv_dir, P.dFx, P.dFy, nx, ny, nz, c.ax, c.ay, c.c0, gz, hz2, c.stream); }));
-        HIP_TRY(timed(c, HELM_K_RING, 8.0 * c.n + ring_work / 2, [&] { return launch_ring_inverse_z32(c.t2f, m.ringT, m.Sy, m.Sy, m.Sx, m.Sx, nx, ny, nz, m.rpart, m.sv, c.stream); }));
-        HIP_TRY(timed(c, HELM_K_RING, 8.0 * c.n + ring_work / 2, [&] { return launch_ring_forward_z32(m.ringT, nullptr, nullptr, 0.0, c.t2f, m.VyiT, c.BxF32, ex, ey, nx, ny, nz, m.fvec, c.stream); }));
+        HIP_TRY(timed(c, HELM_K_RING, 8.0 * c.n + ring_work / 2, [&] { return launch_ring_inverse_z32(c.t2f, m.ringT, m.Sy, m.Sy, m.Sx, m.Sx, nx, ny, nz, m.rpart, m.sv, m.rsum, c.stream); }));
+        HIP_TRY(timed(c, HELM_K_RING, 8.0 * c.n + ring_work / 2, [&] { return launch_ring_forward_z32(m.ringT, nullptr, nullptr, 0.0, c.t2f, m.VyiT, c.BxF32, ex, ey, nx, ny, nz, m.rbuf, m.fvec, c.stream); }));
         HIP_TRY(timed(c, HELM_K_TRIDIAG32, 16.0 * c.n, [&] { return launch_tridiag_chunk_z32(c.t2f, c.t2f, c.tpiv_eig, c.dxe, c.dye, nx, ny, nz, c.ax, c.ay, c.c0, gz, 1.0, c.stream); }));
-        HIP_TRY(timed(c, HELM_K_RING, 8.0 * c.n + ring_work / 2, [&] { return launch_ring_inverse_z32(c.t2f, m.ringW, c.AyI32, m.VyT, m.Vx, c.BxI32, nx, ny, nz, m.rpart, m.sv, c.stream); }));
-        HIP_TRY(timed(c, HELM_K_RING, 16.0 * c.n + ring_work, [&] { return launch_ring_forward_z32(m.ringT, m.ringW, m.yhat, hz2, c.t2f, m.Sy, m.Sx, ex, ey, nx, ny, nz, m.fvec, c.stream); }));
+        HIP_TRY(timed(c, HELM_K_RING, 8.0 * c.n + ring_work / 2, [&] { return launch_ring_inverse_z32(c.t2f, m.ringW, c.AyI32, m.VyT, m.Vx, c.BxI32, nx, ny, nz, m.rpart, m.sv, m.rsum, c.stream); }));
+        HIP_TRY(timed(c, HELM_K_RING, 16.0 * c.n + ring_work, [&] { return launch_ring_forward_z32(m.ringT, m.ringW, m.yhat, hz2, c.t2f, m.Sy, m.Sx, ex, ey, nx, ny, nz, m.rbuf, m.fvec, c.stream); }));
         HIP_TRY(timed(c, HELM_K_TRIDIAG32, 16.0 * c.n, [&] { return launch_tridiag_chunk_z32(c.t2f, c.t2f, c.tpiv_dir, P.dFx, P.dFy, nx, ny, nz, c.ax, c.ay, c.c0, gz, 1.0, c.stream); }));
         HIP_TRY(timed(c, HELM_K_PFFT, 4.0 * dy.M * (double)dy.N * dy.K * dy.batch, [&] { return launch_gemm_z32(dy, m.Sy, c.t2f, c.t1f, c.stream, 1); }));
         HIP_TRY(timed(c, HELM_K_PFFT, 4.0 * dx.M * (double)dx.N * dx.K, [&] { return launch_gemm_z32_out64(dx, c.t1f, m.Sx, z, c.stream, 2); }));

@@ -49,7 +49,8 @@ template <typename CT> struct PfftMats {
     CT *VyiT = nullptr, *VyT = nullptr;          // transposes of V_y^{-1}, V_y (the plain ones are AyF, AyI)
     CT *yhat = nullptr;                          // sine transform of the input (reused in step 3)
     CT *ringT = nullptr, *ringW = nullptr;       // face values of Theta and W, (2 Nx + 2 Ny) per slice
-    CT *rpart = nullptr, *sv = nullptr, *fvec = nullptr;   // ring-transform work: row-group partials, row sums, factors
+    CT *rpart = nullptr, *sv = nullptr, *rsum = nullptr;   // ring inverse work: row-group partials, row sums, their total
+    CT *rbuf = nullptr, *fvec = nullptr;                   // ring forward work: face data R, factors S and T
 };
 struct PfftPlan {
     double2 *dFx = nullptr, *dFy = nullptr;      // Dirichlet eigenvalues 2 cos(pi i/(N+1))
@@ -226,16 +227,16 @@ hipError_t launch_tridiag_chunk_z32(const float2 *in, float2 *out, const double2
 int ring_rowgroups();
 hipError_t launch_ring_inverse_z64(const double2 *Xh, double2 *ring, const double2 *Vy, const double2 *VyT,
                                    const double2 *Vx, const double2 *VxT, int nx, int ny, int nz, double2 *rpart,
-                                   double2 *sv, hipStream_t s);
+                                   double2 *sv, double2 *rsum, hipStream_t s);
 hipError_t launch_ring_inverse_z32(const float2 *Xh, float2 *ring, const float2 *Vy, const float2 *VyT,
                                    const float2 *Vx, const float2 *VxT, int nx, int ny, int nz, float2 *rpart,
-                                   float2 *sv, hipStream_t s);
+                                   float2 *sv, float2 *rsum, hipStream_t s);
 hipError_t launch_ring_forward_z64(const double2 *ra, const double2 *rb, const double2 *base, double base_scale,
                                    double2 *out, const double2 *WyT, const double2 *WxT, double2 ex, double2 ey,
-                                   int nx, int ny, int nz, double2 *fvec, hipStream_t s);
+                                   int nx, int ny, int nz, double2 *rbuf, double2 *fvec, hipStream_t s);
 hipError_t launch_ring_forward_z32(const float2 *ra, const float2 *rb, const float2 *base, double base_scale,
                                    float2 *out, const float2 *WyT, const float2 *WxT, double2 ex, double2 ey, int nx,
-                                   int ny, int nz, float2 *fvec, hipStream_t s);
+                                   int ny, int nz, float2 *rbuf, float2 *fvec, hipStream_t s);
 
 // Krylov helpers
 int dots_blocks(long long n);

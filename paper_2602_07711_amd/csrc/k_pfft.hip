@@ -1,19 +1,20 @@
 // Thin per-slice transforms of the PFFT preconditioner (Sec. 4.2): only the boundary faces of every slice
 // take part, so each costs O(N_x N_y) per slice instead of a dense transform.
 //
-// Ring layout of one slice (stride RS = 2 Nx + 2 Ny): [0, Nx) row j = 0; [Nx, 2Nx) row j = Ny-1;
-// [2Nx, 2Nx+Ny) column i = 0 for all j; [2Nx+Ny, 2Nx+2Ny) column i = Nx-1 for all j (the corners appear in
-// both a row and a column; consumers take them from the rows).
+// Ring layout (all slices): rows [Nz][2][Nx] (row j = 0, then row j = Ny-1 of each slice), followed by columns
+// [Nz][2][Ny] (column i = 0, then i = Nx-1, for all j); the corners appear in both a row and a column and
+// consumers take them from the rows. The products with the transposed eigenvector or sine matrices are single
+// complex GEMMs over all slices (M = 2 Nz).
 //
-// Inverse (k_ring_inv_rows + k_ring_inv_finish): the inverse transform X = V_y Xh V_x^T evaluated on the faces
+// Inverse (k_ring_inv_rows, k_ring_inv_sum, two GEMMs): the inverse transform X = V_y Xh V_x^T evaluated on the faces
 //   only (eq. PFFT_INV): the two boundary rows via r_j = V_y[j,:] Xh then X[j,i] = sum_k V_x[i,k] r_j[k], the two
 //   boundary columns via s_i = Xh V_x[i,:]^T then X[j,i] = sum_m V_y[j,m] s_i[m]. The pass over the data runs
-//   with several row groups per slice; the small products follow per slice.
-// Forward (k_ring_fwd_prep + k_ring_fwd_write): the forward transform of ring-supported data R (Steps 1, 2*):
+//   with several row groups per slice; the products with V_x^T and V_y^T are GEMMs over all slices.
+// Forward (k_ring_fwd_R, two GEMMs, k_ring_fwd_write): the forward transform of ring-supported data R (Steps 1, 2*):
 //   R = E (a + b) with E the diagonal (A_p^F - A_p) restricted to the faces, E = -a_x gamma_x on the x-faces plus
 //   -a_y gamma_y on the y-faces; out = s * base + W_y R W_x^T computed as two rank-2 updates from the boundary rows
 //   (S_m = R[m,:] W_x^T) and the interior parts of the boundary columns (T_k = W_y[:, inner] R[inner, k]); the
-//   factors per slice first, then every element in parallel.
+//   factors as GEMMs over all slices, then every element in parallel.
 #include "helm_internal.h"
 
 namespace helm {
@@ -109,114 +110,47 @@ __global__ __launch_bounds__(256) void k_ring_inv_rows(const typename c2<T>::t *
     }
 }
 
-// Inverse, per slice: r0, rN summed over the row groups in order, then the boundary rows
-// X[j][i] = sum_k V_x[i][k] r_j[k] and the boundary columns X[j][i] = sum_m V_y[j][m] s_i[m] into the ring.
+// Inverse: r0, rN of every slice summed over the row groups in order, rsum[l][w][k]
 template <typename T>
-__global__ __launch_bounds__(256) void k_ring_inv_finish(const typename c2<T>::t *__restrict__ rpart,
-                                                         const typename c2<T>::t *__restrict__ sv,
-                                                         const typename c2<T>::t *__restrict__ VyT,
-                                                         const typename c2<T>::t *__restrict__ VxT, int nx, int ny,
-                                                         typename c2<T>::t *__restrict__ ring) {
+__global__ void k_ring_inv_sum(const typename c2<T>::t *__restrict__ rpart, int nx, long long total,
+                               typename c2<T>::t *__restrict__ rsum) {
     typedef typename c2<T>::t CT;
-    extern __shared__ unsigned char smem[];
-    CT *r = (CT *)smem;          // [2][nx]
-    CT *sl = r + 2 * nx;         // [2][ny]
-    const int tid = threadIdx.x, l = blockIdx.x;
-    const CT *rp = rpart + (long long)l * RING_RG * 2 * nx;
-    for (int k = tid; k < 2 * nx; k += 256) {
-        CT acc = rp[k];
-        for (int g = 1; g < RING_RG; ++g) acc = cadd(acc, rp[(long long)g * 2 * nx + k]);
-        r[k] = acc;
-    }
-    for (int m = tid; m < 2 * ny; m += 256) sl[m] = sv[(long long)l * 2 * ny + m];
-    __syncthreads();
-    CT *out = ring + (long long)l * (2 * nx + 2 * ny);
-    for (int i = tid; i < nx; i += 256) {
-        CT o0 = cz<CT>(), oN = cz<CT>();
-        for (int k = 0; k < nx; ++k) {
-            const CT v = VxT[(long long)k * nx + i];
-            o0 = cfma(v, r[k], o0);
-            oN = cfma(v, r[nx + k], oN);
-        }
-        out[i] = o0;
-        out[nx + i] = oN;
-    }
-    for (int j = tid; j < ny; j += 256) {
-        CT o0 = cz<CT>(), oN = cz<CT>();
-        for (int m = 0; m < ny; ++m) {
-            const CT v = VyT[(long long)m * ny + j];
-            o0 = cfma(v, sl[m], o0);
-            oN = cfma(v, sl[ny + m], oN);
-        }
-        out[2 * nx + j] = o0;
-        out[2 * nx + ny + j] = oN;
-    }
+    const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (e >= total) return;
+    const long long l = e / (2 * nx), q = e % (2 * nx);
+    const CT *rp = rpart + l * RING_RG * 2 * nx + q;
+    CT acc = rp[0];
+    for (int g = 1; g < RING_RG; ++g) acc = cadd(acc, rp[(long long)g * 2 * nx]);
+    rsum[e] = acc;
 }
 
-// Forward, per slice: R = E (a + b) on the faces, then S_m[i] = sum_k W_x[i][k] R[m][k] for the boundary rows
-// m and T_k[j] = sum_{m inner} W_y[j][m] R[m][k] for the interior parts of the boundary columns, written to
-// fvec[l] = [S_0 | S_N | T_0 | T_N].
+// Forward: R = E (a + b) on the faces (E = -a_x gamma_x on the x-faces plus -a_y gamma_y on the y-faces): the
+// boundary rows Rr[l][w][k] in full and the interior parts of the boundary columns Rc[l][w][m] (ends zero)
 template <typename T>
-__global__ __launch_bounds__(256) void k_ring_fwd_prep(const typename c2<T>::t *__restrict__ ra,
-                                                       const typename c2<T>::t *__restrict__ rb,
-                                                       const typename c2<T>::t *__restrict__ WyT,
-                                                       const typename c2<T>::t *__restrict__ WxT, double2 ex,
-                                                       double2 ey, int nx, int ny,
-                                                       typename c2<T>::t *__restrict__ fvec) {
+__global__ void k_ring_fwd_R(const typename c2<T>::t *__restrict__ ra, const typename c2<T>::t *__restrict__ rb,
+                             double2 ex, double2 ey, int nx, int ny, int nz, typename c2<T>::t *__restrict__ Rr,
+                             typename c2<T>::t *__restrict__ Rc) {
     typedef typename c2<T>::t CT;
-    extern __shared__ unsigned char smem[];
-    CT *R0 = (CT *)smem;        // R row 0        [nx]
-    CT *RN = R0 + nx;           // R row ny-1     [nx]
-    CT *C0 = RN + nx;           // R column 0     [ny] (interior rows only)
-    CT *CN = C0 + ny;           // R column nx-1  [ny]
-    const int tid = threadIdx.x, l = blockIdx.x;
-    const int RS = 2 * nx + 2 * ny;
-    const CT *A = ra + (long long)l * RS;
-    const CT *B = rb ? rb + (long long)l * RS : nullptr;
+    const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+    const long long nrow = 2LL * nz * nx, ncol = 2LL * nz * ny;
+    if (e >= nrow + ncol) return;
     CT ecx, ecy;
     ecx.x = (T)ex.x; ecx.y = (T)ex.y;
     ecy.x = (T)ey.x; ecy.y = (T)ey.y;
-    const CT ecc = cadd(ecx, ecy);
-    for (int k = tid; k < nx; k += 256) {
-        CT v0 = A[k], vN = A[nx + k];
-        if (B) { v0 = cadd(v0, B[k]); vN = cadd(vN, B[nx + k]); }
-        const CT e = (k == 0 || k == nx - 1) ? ecc : ecy;
-        R0[k] = cmul(e, v0);
-        RN[k] = cmul(e, vN);
-    }
-    for (int m = tid; m < ny; m += 256) {
-        CT v0 = A[2 * nx + m], vN = A[2 * nx + ny + m];
-        if (B) { v0 = cadd(v0, B[2 * nx + m]); vN = cadd(vN, B[2 * nx + ny + m]); }
-        const bool inner = m > 0 && m < ny - 1;
-        C0[m] = inner ? cmul(ecx, v0) : cz<CT>();
-        CN[m] = inner ? cmul(ecx, vN) : cz<CT>();
-    }
-    __syncthreads();
-    CT *fv = fvec + (long long)l * RS;
-    for (int i = tid; i < nx; i += 256) {
-        CT s0 = cz<CT>(), sN = cz<CT>();
-        for (int k = 0; k < nx; ++k) {
-            const CT v = WxT[(long long)k * nx + i];
-            s0 = cfma(v, R0[k], s0);
-            sN = cfma(v, RN[k], sN);
-        }
-        fv[i] = s0;
-        fv[nx + i] = sN;
-    }
-    for (int j = tid; j < ny; j += 256) {
-        CT t0 = cz<CT>(), tN = cz<CT>();
-        for (int m = 1; m < ny - 1; ++m) {
-            const CT v = WyT[(long long)m * ny + j];
-            t0 = cfma(v, C0[m], t0);
-            tN = cfma(v, CN[m], tN);
-        }
-        fv[2 * nx + j] = t0;
-        fv[2 * nx + ny + j] = tN;
+    CT v = ra[e];
+    if (rb) v = cadd(v, rb[e]);
+    if (e < nrow) {
+        const int k = (int)(e % nx);
+        Rr[e] = cmul((k == 0 || k == nx - 1) ? cadd(ecx, ecy) : ecy, v);
+    } else {
+        const int m = (int)((e - nrow) % ny);
+        Rc[e - nrow] = (m > 0 && m < ny - 1) ? cmul(ecx, v) : cz<CT>();
     }
 }
 
 // Forward, every element of every slice: out = s base + W_y[j][0] S_0[i] + W_y[j][ny-1] S_N[i]
-// + T_0[j] W_x[i][0] + T_N[j] W_x[i][nx-1] (the boundary columns of W read as rows of the transposes)
+// + T_0[j] W_x[i][0] + T_N[j] W_x[i][nx-1] (the boundary columns of W read as rows of the transposes);
+// fvec = [S: Nz x 2 x Nx | T: Nz x 2 x Ny] with S = Rr W_x^T and T = Rc W_y^T
 template <typename T>
 __global__ __launch_bounds__(256) void k_ring_fwd_write(const typename c2<T>::t *__restrict__ fvec,
                                                         const typename c2<T>::t *base, T base_scale,
@@ -231,38 +165,59 @@ __global__ __launch_bounds__(256) void k_ring_fwd_write(const typename c2<T>::t 
     const int l = (int)(e / plane);
     const long long p = e - (long long)l * plane;
     const int j = (int)(p / nx), i = (int)(p % nx);
-    const CT *fv = fvec + (long long)l * (2 * nx + 2 * ny);
+    const CT *S = fvec + (long long)l * 2 * nx;                                  // S_0, S_N of slice l
+    const CT *Tc = fvec + 2LL * (long long)(n / plane) * nx + (long long)l * 2 * ny;   // T_0, T_N of slice l
     CT acc = cz<CT>();
     if (base) { acc = base[e]; acc.x *= base_scale; acc.y *= base_scale; }
-    acc = cfma(WyT[j], fv[i], acc);
-    acc = cfma(WyT[(long long)(ny - 1) * ny + j], fv[nx + i], acc);
-    acc = cfma(fv[2 * nx + j], WxT[i], acc);
-    acc = cfma(fv[2 * nx + ny + j], WxT[(long long)(nx - 1) * nx + i], acc);
+    acc = cfma(WyT[j], S[i], acc);
+    acc = cfma(WyT[(long long)(ny - 1) * ny + j], S[nx + i], acc);
+    acc = cfma(Tc[j], WxT[i], acc);
+    acc = cfma(Tc[ny + j], WxT[(long long)(nx - 1) * nx + i], acc);
     out[e] = acc;
 }
 
+inline hipError_t gemm_c(const GemmDesc &d, const double2 *A, const double2 *B, double2 *C, hipStream_t s) {
+    return launch_gemm_z64(d, A, B, C, s);
+}
+inline hipError_t gemm_c(const GemmDesc &d, const float2 *A, const float2 *B, float2 *C, hipStream_t s) {
+    return launch_gemm_z32(d, A, B, C, s);
+}
+// C (M x N) = A (M x K) B (K x N), all row-major and contiguous
+inline GemmDesc plain_desc(int M, int N, int K) { return GemmDesc{M, N, K, K, N, N, 0, 0, 0, 1}; }
+
+// work: rpart (Nz * RING_RG * 2 Nx), sv (Nz * 2 Ny), rsum (Nz * 2 Nx)
 template <typename T>
 hipError_t inv_launch(const typename c2<T>::t *Xh, typename c2<T>::t *ring, const typename c2<T>::t *Vy,
                       const typename c2<T>::t *VyT, const typename c2<T>::t *Vx, const typename c2<T>::t *VxT, int nx,
-                      int ny, int nz, typename c2<T>::t *rpart, typename c2<T>::t *sv, hipStream_t s) {
+                      int ny, int nz, typename c2<T>::t *rpart, typename c2<T>::t *sv, typename c2<T>::t *rsum,
+                      hipStream_t s) {
     if (nx > 64 * MAXC || ny > 64 * MAXC) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_ring_inv_rows<T>, dim3(nz * RING_RG), dim3(256), 0, s, Xh, Vy, Vx, nx, ny, rpart, sv);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const size_t shm = sizeof(typename c2<T>::t) * (size_t)(2 * nx + 2 * ny);
-    hipLaunchKernelGGL(k_ring_inv_finish<T>, dim3(nz), dim3(256), shm, s, rpart, sv, VyT, VxT, nx, ny, ring);
-    return hipGetLastError();
+    const long long nr = 2LL * nz * nx;
+    hipLaunchKernelGGL(k_ring_inv_sum<T>, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, s, rpart, nx, nr, rsum);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // boundary rows X[j][i] = sum_k V_x[i][k] r_j[k]: rows (2 Nz x Nx) = rsum V_x^T
+    if ((e = gemm_c(plain_desc(2 * nz, nx, nx), rsum, VxT, ring, s)) != hipSuccess) return e;
+    // boundary columns X[j][i] = sum_m V_y[j][m] s_i[m]: columns (2 Nz x Ny) = sv V_y^T
+    return gemm_c(plain_desc(2 * nz, ny, ny), sv, VyT, ring + nr, s);
 }
 
+// work: Rr (Nz * 2 Nx) and Rc (Nz * 2 Ny) contiguous in rbuf, fvec (Nz * (2 Nx + 2 Ny))
 template <typename T>
 hipError_t fwd_launch(const typename c2<T>::t *ra, const typename c2<T>::t *rb, const typename c2<T>::t *base,
                       double base_scale, typename c2<T>::t *out, const typename c2<T>::t *WyT,
                       const typename c2<T>::t *WxT, double2 ex, double2 ey, int nx, int ny, int nz,
-                      typename c2<T>::t *fvec, hipStream_t s) {
-    const size_t shm = sizeof(typename c2<T>::t) * (size_t)(2 * nx + 2 * ny);
-    hipLaunchKernelGGL(k_ring_fwd_prep<T>, dim3(nz), dim3(256), shm, s, ra, rb, WyT, WxT, ex, ey, nx, ny, fvec);
+                      typename c2<T>::t *rbuf, typename c2<T>::t *fvec, hipStream_t s) {
+    const long long nr = 2LL * nz * nx, nc = 2LL * nz * ny;
+    typename c2<T>::t *Rr = rbuf, *Rc = rbuf + nr;
+    hipLaunchKernelGGL(k_ring_fwd_R<T>, dim3((unsigned)((nr + nc + 255) / 256)), dim3(256), 0, s, ra, rb, ex, ey, nx,
+                       ny, nz, Rr, Rc);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if ((e = gemm_c(plain_desc(2 * nz, nx, nx), Rr, WxT, fvec, s)) != hipSuccess) return e;        // S = Rr W_x^T
+    if ((e = gemm_c(plain_desc(2 * nz, ny, ny), Rc, WyT, fvec + nr, s)) != hipSuccess) return e;   // T = Rc W_y^T
     const long long n = (long long)nx * ny * nz;
     hipLaunchKernelGGL(k_ring_fwd_write<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, fvec, base,
                        (T)base_scale, out, WyT, WxT, nx, ny, n);
@@ -275,23 +230,23 @@ int ring_rowgroups() { return RING_RG; }
 
 hipError_t launch_ring_inverse_z64(const double2 *Xh, double2 *ring, const double2 *Vy, const double2 *VyT,
                                    const double2 *Vx, const double2 *VxT, int nx, int ny, int nz, double2 *rpart,
-                                   double2 *sv, hipStream_t s) {
-    return inv_launch<double>(Xh, ring, Vy, VyT, Vx, VxT, nx, ny, nz, rpart, sv, s);
+                                   double2 *sv, double2 *rsum, hipStream_t s) {
+    return inv_launch<double>(Xh, ring, Vy, VyT, Vx, VxT, nx, ny, nz, rpart, sv, rsum, s);
 }
 hipError_t launch_ring_inverse_z32(const float2 *Xh, float2 *ring, const float2 *Vy, const float2 *VyT,
                                    const float2 *Vx, const float2 *VxT, int nx, int ny, int nz, float2 *rpart,
-                                   float2 *sv, hipStream_t s) {
-    return inv_launch<float>(Xh, ring, Vy, VyT, Vx, VxT, nx, ny, nz, rpart, sv, s);
+                                   float2 *sv, float2 *rsum, hipStream_t s) {
+    return inv_launch<float>(Xh, ring, Vy, VyT, Vx, VxT, nx, ny, nz, rpart, sv, rsum, s);
 }
 hipError_t launch_ring_forward_z64(const double2 *ra, const double2 *rb, const double2 *base, double base_scale,
                                    double2 *out, const double2 *WyT, const double2 *WxT, double2 ex, double2 ey,
-                                   int nx, int ny, int nz, double2 *fvec, hipStream_t s) {
-    return fwd_launch<double>(ra, rb, base, base_scale, out, WyT, WxT, ex, ey, nx, ny, nz, fvec, s);
+                                   int nx, int ny, int nz, double2 *rbuf, double2 *fvec, hipStream_t s) {
+    return fwd_launch<double>(ra, rb, base, base_scale, out, WyT, WxT, ex, ey, nx, ny, nz, rbuf, fvec, s);
 }
 hipError_t launch_ring_forward_z32(const float2 *ra, const float2 *rb, const float2 *base, double base_scale,
                                    float2 *out, const float2 *WyT, const float2 *WxT, double2 ex, double2 ey, int nx,
-                                   int ny, int nz, float2 *fvec, hipStream_t s) {
-    return fwd_launch<float>(ra, rb, base, base_scale, out, WyT, WxT, ex, ey, nx, ny, nz, fvec, s);
+                                   int ny, int nz, float2 *rbuf, float2 *fvec, hipStream_t s) {
+    return fwd_launch<float>(ra, rb, base, base_scale, out, WyT, WxT, ex, ey, nx, ny, nz, rbuf, fvec, s);
 }
 
 }  // namespace helm
