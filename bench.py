@@ -183,18 +183,20 @@ def bench_batched(H, torch, dev, args):
 
 
 def bench_learned(H, torch, args):
-    """Learned warm start: 64^3 four-inclusion problems (k0 = 60, source width 0.03) solved by FP32-EigT
-    FGMRES generate the training set, the CNN trains on the GPU with the library's BF16 kernels, and held-out
-    128^3 problems are solved to rtol 1e-8 from zero and from the prolonged prediction (2000 training solves and
-    20 epochs by default; --ws-samples / --ws-epochs shorten it)."""
+    """Learned warm start: 64^3 four-inclusion problems (k0 = 60, source width 0.03, inclusion and source
+    centres seeded per problem) solved by FP32-EigT FGMRES generate the training set (targets unit-RMS per
+    sample), the CNN trains on the GPU with the library's BF16 kernels, and held-out 128^3 problems (seeds
+    100000, ...) are solved to rtol 1e-8 from zero and from the prolonged, residual-scaled prediction (2000
+    training solves, 20 epochs and 16 evaluation problems by default; --ws-samples / --ws-epochs / --ws-eval
+    shorten it)."""
     from paper_2602_07711_amd import warmstart as W
     S = 64
     ws, rep = W.fit(size=S, samples=args.ws_samples, epochs=args.ws_epochs, batch=4, lr=1e-3, k0=60.0,
                     log=None)
     fwd, train = W.cnn_flops(S)
     step_ms = 1e3 * rep["train_s"] / max(1, rep["train_steps"])
-    control = W.WarmStart(H.Cnn(S, 1, bf16=True, seed=999), ws.t_scale, 60.0)
-    ev = W.evaluate(ws, 128, range(1_000_000, 1_000_000 + args.ws_eval), control=control)
+    control = W.WarmStart(H.Cnn(S, 1, bf16=True, seed=999), 60.0, ws.t_scale)
+    ev = W.evaluate(ws, 128, range(W.EVAL_SEED0, W.EVAL_SEED0 + args.ws_eval), control=control)
     m = ev["mean"]
     out = dict(train=dict(samples=rep["samples"], epochs=rep["epochs"], steps=rep["train_steps"], batch=4,
                           gen_s=rep["gen_s"], train_s=rep["train_s"], ms_per_step=round(step_ms, 3),
@@ -204,7 +206,8 @@ def bench_learned(H, torch, args):
                eval_problems=args.ws_eval, iters_zero=m["zero_iters"], iters_warm=m["warm_iters"],
                iters_warm_trilinear=m.get("warm_linear_iters"), iters_untrained=m["control_iters"],
                e0_warm=round(m["warm_e0"], 4), e0_untrained=round(m["control_e0"], 4),
-               r0_warm=round(m["warm_r0"], 4),
+               r0_warm=round(m["warm_r0"], 4), iters_warm_residual_amplitude=m["other_amp_iters"],
+               e0_warm_residual_amplitude=round(m["other_amp_e0"], 4),
                ms_fp32_zero=round(m["zero_ms"], 3), ms_fp32_learned=round(m["warm_ms"], 3),
                ms_fp64_zero=round(m["fp64_ms"], 3))
     log(f"learned warm start: {out['iters_warm']} vs {out['iters_zero']} iterations (untrained "
@@ -227,7 +230,7 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-warm-start leg")
     ap.add_argument("--ws-samples", type=int, default=2000, help="training solves of the learned leg")
     ap.add_argument("--ws-epochs", type=int, default=20, help="training epochs of the learned leg")
-    ap.add_argument("--ws-eval", type=int, default=2, help="held-out 128^3 problems of the learned leg")
+    ap.add_argument("--ws-eval", type=int, default=16, help="held-out 128^3 problems of the learned leg")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run three plain 256 MiB device-to-device copies (reference dispatches for scaling "
                          "hardware byte counters)")

@@ -181,6 +181,14 @@ helm_status helm_autotune(helm_ctx *ctx, int reps, int *chosen, double *ms);
 /* Set the tile configuration (0..3) of transform kind (0 x64, 1 y64, 2 x32, 3 y32) by hand. */
 helm_status helm_gemm_config(helm_ctx *ctx, int kind, int cfg);
 
+/* Scale an initial guess known up to its amplitude: x <- alpha x with the complex alpha minimising
+ * ||F - alpha A x||_2, i.e. alpha = (A x)^H F / ||A x||^2 (the one-dimensional minimal-residual step of GMRES,
+ * Sec. 3.1, taken over span{x}; alpha = 0 when A x = 0). Afterwards ||F - A x|| <= ||F||. F, x: device complex128
+ * vectors of n entries (x overwritten). alpha_re, alpha_im: NULL or host doubles receiving alpha. Uses one matvec
+ * and two inner products on the context stream and returns when alpha is known (the scaling is queued). The
+ * first call allocates one vector of work in the context. */
+helm_status helm_scale_guess(helm_ctx *ctx, const void *F, void *x, double *alpha_re, double *alpha_im);
+
 /* ---- Batched solves (many right-hand sides and/or many independent problems) ----
  *
  * A batch groups P FGMRES(m) solves with the EigT preconditioner. Problem p uses the operator and the

@@ -18,6 +18,7 @@ from .helm import (  # noqa: F401
     helm_profile_enable,
     helm_profile_read,
     helm_rhs,
+    helm_scale_guess,
     helm_setup,
     lib,
 )

@@ -388,6 +388,7 @@ void helm_destroy(helm_ctx *ctx) {
     for (void *p : c.allocs) hipFree(p);
     c.allocs.clear();
     if (c.kw.red_host) hipHostFree(c.kw.red_host);
+    if (c.sg_host) hipHostFree(c.sg_host);
     delete c.pfft;
     c.pfft = nullptr;
     hipSetDevice(cur);
@@ -621,6 +622,41 @@ helm_status helm_matvec(helm_ctx *ctx, const void *x_dev, void *y_dev) {
     if (!x_dev || !y_dev) { c.err = "NULL pointer"; return HELM_EINVAL; }
     if (x_dev == y_dev) { c.err = "matvec input and output must not overlap"; return HELM_EINVAL; }
     HIP_TRY(timed(c, HELM_K_MATVEC, matvec_bytes(c, false), [&] { return launch_matvec(c.sp, (const double2 *)x_dev, c.k2, c.fld, nullptr, (double2 *)y_dev, c.stream); }));
+    return HELM_OK;
+}
+
+helm_status helm_scale_guess(helm_ctx *ctx, const void *F_dev, void *x_dev, double *alpha_re, double *alpha_im) {
+    if (!ctx) return HELM_EINVAL;
+    Ctx &c = ctx->c;
+    if (!F_dev || !x_dev) { c.err = "NULL pointer"; return HELM_EINVAL; }
+    const int nb = dots_blocks(c.n);
+    if (!c.sg_y) {
+        ST_TRY(dalloc(c, &c.sg_y, (size_t)c.n));
+        ST_TRY(dalloc(c, &c.sg_part, (size_t)nb * 2));
+        ST_TRY(dalloc(c, &c.sg_red, 2));
+        HIP_TRY(hipHostMalloc((void **)&c.sg_host, 2 * sizeof(double2), hipHostMallocDefault));
+    }
+    double2 *x = (double2 *)x_dev;
+    const double2 *F = (const double2 *)F_dev;
+    // y = A x; (y^H F, ||F||^2) then ||y||^2
+    HIP_TRY(timed(c, HELM_K_MATVEC, matvec_bytes(c, false), [&] { return launch_matvec(c.sp, x, c.k2, c.fld, nullptr, c.sg_y, c.stream); }));
+    HIP_TRY(timed(c, HELM_K_DOTS, 32.0 * c.n, [&] { return launch_dots(c.sg_y, c.n, 1, F, c.n, c.sg_part, nb, c.sg_red, c.stream); }));
+    HIP_TRY(hipMemcpyAsync(c.sg_host, c.sg_red, sizeof(double2), hipMemcpyDeviceToHost, c.stream));
+    HIP_TRY(timed(c, HELM_K_DOTS, 16.0 * c.n, [&] { return launch_dots(nullptr, c.n, 0, c.sg_y, c.n, c.sg_part, nb, c.sg_red, c.stream); }));
+    HIP_TRY(hipMemcpyAsync(c.sg_host + 1, c.sg_red, sizeof(double2), hipMemcpyDeviceToHost, c.stream));
+    HIP_TRY(hipStreamSynchronize(c.stream));
+    prof_resolve(c);
+    const cd yf(c.sg_host[0].x, c.sg_host[0].y);
+    const double yy = c.sg_host[1].x;
+    if (!std::isfinite(yf.real()) || !std::isfinite(yf.imag()) || !std::isfinite(yy)) {
+        c.err = "non-finite value in the initial-guess scaling";
+        return HELM_ENUMERIC;
+    }
+    const cd alpha = yy > 0.0 ? yf / yy : cd(0.0, 0.0);
+    std::vector<double2> coef(1);
+    HIP_TRY(timed(c, HELM_K_LINCOMB, 32.0 * c.n, [&] { return launch_lincomb(x, x, d2(alpha), nullptr, c.n, 0, coef.data(), c.n, c.stream); }));
+    if (alpha_re) *alpha_re = alpha.real();
+    if (alpha_im) *alpha_im = alpha.imag();
     return HELM_OK;
 }
 

@@ -105,6 +105,7 @@ struct Ctx {
     double2 *t1 = nullptr, *t2 = nullptr;
     float2 *t1f = nullptr, *t2f = nullptr;
     double2 *tpiv_eig = nullptr, *tpiv_dir = nullptr;  // pivots entering each z-chunk (absorbing / Dirichlet x-y eigenvalues)
+    double2 *sg_y = nullptr, *sg_part = nullptr, *sg_red = nullptr, *sg_host = nullptr;   // helm_scale_guess work
 
     PfftPlan *pfft = nullptr;
     std::vector<cd> hVx, hVxi, hVy, hVyi;        // host copies of the eigenvector matrices (PFFT plan build)

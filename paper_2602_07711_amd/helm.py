@@ -98,6 +98,8 @@ def lib():
     L.helm_batch_destroy.restype = None
     L.helm_batch_last_error.argtypes = [c_void_p]
     L.helm_batch_last_error.restype = ctypes.c_char_p
+    L.helm_scale_guess.argtypes = [c_void_p, c_void_p, c_void_p, POINTER(c_double), POINTER(c_double)]
+    L.helm_scale_guess.restype = c_int
     L.helm_cnn_create.argtypes = [POINTER(c_void_p), c_int, c_int, c_int, ctypes.c_ulonglong, c_void_p]
     L.helm_cnn_create.restype = c_int
     L.helm_cnn_num_params.argtypes = [c_void_p]
@@ -225,6 +227,15 @@ def helm_precond_apply(ctx: Context, y: torch.Tensor, z: torch.Tensor | None = N
     ctx.check(lib().helm_precond_apply(ctx.ptr, c_void_p(y.data_ptr()), c_void_p(z.data_ptr()), _PREC[kind],
                                        int(bool(fp32))))
     return z
+
+
+def helm_scale_guess(ctx: Context, F: torch.Tensor, x: torch.Tensor) -> complex:
+    """x <- alpha x with alpha minimising ||F - alpha A x|| (in place); returns alpha."""
+    _check(F, torch.complex128, ctx.n, "F")
+    _check(x, torch.complex128, ctx.n, "x")
+    ar, ai = c_double(), c_double()
+    ctx.check(lib().helm_scale_guess(ctx.ptr, c_void_p(F.data_ptr()), c_void_p(x.data_ptr()), byref(ar), byref(ai)))
+    return complex(ar.value, ai.value)
 
 
 def helm_gmres_solve(ctx: Context, F: torch.Tensor, x: torch.Tensor | None = None, m: int = 50, maxit: int = 1000,

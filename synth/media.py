@@ -96,12 +96,15 @@ def uneven_problem_set(count: int = 16, n_lo: int = 64, n_hi: int = 160, k_lo: f
     return list(zip(ns, ks.tolist()))
 
 
-def warmstart_problem(n: int, seed: int, k0: float = 60.0, sigma: float = 0.03):
+def warmstart_problem(n: int, seed: int, k0: float = 60.0, sigma: float = 0.03, center=None):
     """Learned-warm-start sample: the four-inclusion medium (centres seeded by `seed`, amplitude 0.3, width 0.1)
-    with a unit-peak Gaussian source of fixed physical width `sigma` at the centre, 6th order. The width does
-    not scale with h, so grids of different N discretise the same continuous problem."""
+    with a unit-peak Gaussian source of fixed physical width `sigma` whose centre is drawn from U[0.3, 0.7]^3 by a
+    second stream of the same seed (or given), 6th order. The width does not scale with h, so grids of different
+    N discretise the same continuous problem."""
+    if center is None:
+        center = np.random.default_rng((seed, 77)).uniform(0.3, 0.7, size=3)
     return dict(n=n, h=1.0 / (n + 1), order=6, k0=k0, k2=inclusions_k2(n, k0, seed=seed),
-                f=gaussian_source(n, sigma_cells=sigma * (n + 1)))
+                f=gaussian_source(n, sigma_cells=sigma * (n + 1), center=tuple(center)), center=tuple(center))
 
 
 def workload(name: str, n: int | None = None):

@@ -330,3 +330,32 @@ def test_autotune_runs_and_keeps_parity():
     xb, ib = h.helm_batch_solve(batch, [F, F.clone()], rtol=1e-10)
     for xx in xb:
         assert np.linalg.norm(host(xx) - xs) <= 1e-8 * np.linalg.norm(xs)
+
+
+@pytest.mark.parametrize("shape,order", [((12, 20, 70), 6), ((16, 16, 16), 4)])
+def test_scale_guess_matches_least_squares(shape, order):
+    """helm_scale_guess (the 1-D minimal-residual step of GMRES, Sec. 3.1, over span{x}) against numpy's
+    least-squares solve of min_alpha ||F - alpha (A x)|| with the oracle's A: alpha to 1e-11 relative, x scaled
+    in place, and ||F - A (alpha x)|| <= ||F||. x = 0 leaves alpha = 0 and x = 0."""
+    h = H()
+    h3 = _h3(shape, order)
+    k0 = 0.5 / h3[0]
+    k2 = medium(shape, h3, k0, seed=21)
+    ctx = h.helm_setup(dev(k2), h3, order, k0=k0, shape=shape)
+    n = int(np.prod(shape))
+    gs = tuple(op.gamma_abc(k0, hh) for hh in h3)
+    fields = op.derived_fields(k2, h3[0]) if order == 6 else None
+    A = op.A_kron(order, k2[2:-2, 2:-2, 2:-2], h3, gs, fields)
+    xr = cvec(n, 31)
+    F = 3.0 * (A @ xr) * (0.4 - 0.7j) + 0.2 * np.abs(A @ xr).max() * cvec(n, 32)   # F correlated with A x
+    alpha_ref = np.linalg.lstsq((A @ xr)[:, None], F, rcond=None)[0][0]
+    xd = dev(xr)
+    alpha = h.helm_scale_guess(ctx, dev(F), xd)
+    assert abs(alpha - alpha_ref) <= 1e-11 * abs(alpha_ref)
+    xs = host(xd)
+    assert np.abs(xs - alpha_ref * xr).max() <= 1e-11 * np.abs(alpha_ref * xr).max()
+    assert np.linalg.norm(F - A @ xs) <= np.linalg.norm(F)
+    z = torch.zeros(n, dtype=torch.complex128, device="cuda")
+    assert h.helm_scale_guess(ctx, dev(F), z) == 0
+    assert float(torch.linalg.vector_norm(z)) == 0.0
+    h.helm_destroy(ctx)
