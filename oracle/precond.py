@@ -28,6 +28,13 @@ def M_matrix(shape, h3, k0: float, gammas) -> sp.csr_matrix:
     return (M + k0 * k0 * sp.identity(nx * ny * nz, np.complex128)).tocsr()
 
 
+def M_dirichlet(shape, h3, k0: float) -> sp.csr_matrix:
+    """The comparison preconditioner FFT2 (Sec. 5.1; the FFT-type approach recalled at the start of Sec. 4): the
+    same 7-point operator with the constant k0 but zero Dirichlet values on all six faces, i.e. M with gamma = 0
+    on every axis. Its inverse applied to y is the sparse LU solve of this matrix."""
+    return M_matrix(shape, h3, k0, (0.0, 0.0, 0.0))
+
+
 def eig1d(n: int, gamma: complex, zeta: complex = 1.0):
     """Step 1 of eq. EIG_SOLVER: D, V, V^{-1} of Lambda-bar (numpy eig and inv). Returns (d, V, Vinv)."""
     Lb = lambda_bar(n, gamma, zeta).toarray()

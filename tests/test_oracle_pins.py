@@ -248,6 +248,31 @@ def test_dirichlet_eigt_is_the_sine_solver():
     assert np.linalg.norm(e.solve(y) - p.solve_F(ys).ravel()) <= 1e-12 * np.linalg.norm(y)
 
 
+def test_fft2_matrix_sine_modes_closed_form():
+    """FFT2's matrix (gamma = 0 on every axis) has the product sine modes sin(pi p x) sin(pi q y) sin(pi r z) as
+    eigenvectors with eigenvalue sum_a (2 cos(pi p_a h_a) - 2) / h_a^2 + k0^2 (h_a = 1/(N_a + 1)); checked for
+    several modes on a box with three different N, and against the absorbing M (which differs on the faces)."""
+    nz, ny, nx = 5, 7, 6
+    h3 = (1.0 / (nx + 1), 1.0 / (ny + 1), 1.0 / (nz + 1))
+    k0 = 9.0
+    M = pc.M_dirichlet((nz, ny, nx), h3, k0)
+    x = np.arange(1, nx + 1) * h3[0]
+    y = np.arange(1, ny + 1) * h3[1]
+    z = np.arange(1, nz + 1) * h3[2]
+    for p, q, r in [(1, 1, 1), (6, 2, 3), (3, 7, 5), (2, 5, 1)]:
+        u = (np.sin(np.pi * r * z)[:, None, None] * np.sin(np.pi * q * y)[None, :, None]
+             * np.sin(np.pi * p * x)[None, None, :]).ravel()
+        lam = sum((2 * np.cos(np.pi * m * hh) - 2) / hh ** 2 for m, hh in zip((p, q, r), h3)) + k0 * k0
+        assert np.linalg.norm(M @ u - lam * u) <= 1e-12 * abs(lam) * np.linalg.norm(u)
+    g = tuple(op.gamma_abc(k0, hh) for hh in h3)
+    D = (pc.M_matrix((nz, ny, nx), h3, k0, g) - M).tocoo()
+    face = lambda k: np.unravel_index(k, (nz, ny, nx))
+    for r_, c_ in zip(D.row, D.col):
+        assert r_ == c_
+        l, j, i = face(r_)
+        assert l in (0, nz - 1) or j in (0, ny - 1) or i in (0, nx - 1)
+
+
 # ------------------------------------------------------------------------------------------- GMRES
 
 def _small_problem(order=6, n=14, k0=None):
