@@ -9,7 +9,8 @@ closure on all faces. Every input is synthetic and seeded.
 One step = one complete solve to ||F - A x|| <= 1e-8 ||F|| from x = 0 with inputs resident in HBM:
   * headline form: FGMRES(50) in FP64 with the EigT preconditioner in complex FP32 on MFMA;
   * reference form: plain right-preconditioned GMRES(50) with the EigT preconditioner in FP64;
-  * the PFFT preconditioner (second path) in the same two forms.
+  * the PFFT preconditioner (second path) in the same two forms;
+  * optionally (--forms), the Dirichlet comparison preconditioner FFT2 in both forms, capped at 1000 iterations.
 value = unknowns x iterations / s of the headline form; ms_per_step = its time-to-solution.
 
 Prints one JSON line. Per-kernel device times come from HIP events recorded on the solve's stream over the
@@ -281,6 +282,10 @@ def main():
         "fp64_eigt_fgmres": dict(m=50, flexible=True, prec_fp32=False, prec="eigt"),
         "fp32_pfft_fgmres": dict(m=50, flexible=True, prec_fp32=True, prec="pfft"),
         "fp64_pfft_gmres": dict(m=50, flexible=False, prec_fp32=False, prec="pfft"),
+        # the Dirichlet comparison preconditioner FFT2 (not in the default set)
+        "fp32_fft2_fgmres": dict(m=50, flexible=True, prec_fp32=True, prec="fft2", maxit=1000, raise_on_noconv=False),
+        "fp64_fft2_gmres": dict(m=50, flexible=False, prec_fp32=False, prec="fft2", maxit=1000,
+                                raise_on_noconv=False),
     }
     forms = {}
     for name in args.forms.split(","):

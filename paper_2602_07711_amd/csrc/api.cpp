@@ -98,12 +98,15 @@ GemmDesc desc_y(const Ctx &c) {
     return d;
 }
 
-// pivots entering each z-chunk of the partitioned tridiagonal solve, per set of x-y eigenvalues
-helm_status ensure_tpiv(Ctx &c, const double2 *dx, const double2 *dy, double2 **piv) {
+// pivots entering each z-chunk of the partitioned tridiagonal solve, per set of x-y eigenvalues and z closure
+helm_status ensure_tpiv(Ctx &c, const double2 *dx, const double2 *dy, double2 **piv, double2 gz) {
     if (*piv) return HELM_OK;
     ST_TRY(dalloc(c, piv, (size_t)tri_chunks(c.nz) * c.nx * c.ny));
-    HIP_TRY(launch_tri_pivots(dx, dy, c.nx, c.ny, c.nz, c.ax, c.ay, c.c0, d2(c.gamma[2]), *piv, c.stream));
+    HIP_TRY(launch_tri_pivots(dx, dy, c.nx, c.ny, c.nz, c.ax, c.ay, c.c0, gz, *piv, c.stream));
     return HELM_OK;
+}
+helm_status ensure_tpiv(Ctx &c, const double2 *dx, const double2 *dy, double2 **piv) {
+    return ensure_tpiv(c, dx, dy, piv, d2(c.gamma[2]));
 }
 
 helm_status ensure_fp32_work(Ctx &c) {
@@ -168,10 +171,14 @@ template <typename CT> helm_status upload_one(Ctx &c, const std::vector<cd> &M, 
     return HELM_OK;
 }
 
-template <typename CT> helm_status build_pfft_mats(Ctx &c, PfftMats<CT> &m) {
+template <typename CT> helm_status build_sine_mats(Ctx &c, PfftMats<CT> &m) {
     std::vector<cd> Sx = sine_matrix(c.nx), Sy = sine_matrix(c.ny);
     ST_TRY(upload_one(c, Sx, c.nx, false, &m.Sx));
     ST_TRY(upload_one(c, Sy, c.ny, false, &m.Sy));
+    return HELM_OK;
+}
+
+template <typename CT> helm_status build_ring_mats(Ctx &c, PfftMats<CT> &m) {
     ST_TRY(upload_one(c, c.hVxi, c.nx, false, &m.Vxi));
     ST_TRY(upload_one(c, c.hVx, c.nx, false, &m.Vx));
     ST_TRY(upload_one(c, c.hVyi, c.ny, true, &m.VyiT));
@@ -188,8 +195,9 @@ template <typename CT> helm_status build_pfft_mats(Ctx &c, PfftMats<CT> &m) {
     return HELM_OK;
 }
 
-helm_status ensure_pfft(Ctx &c, bool fp32) {
-    if (c.nx > 256 || c.ny > 256) {
+// Sine matrices and Dirichlet eigenvalues (shared by PFFT and FFT2); `ring` adds PFFT's face-correction data.
+helm_status ensure_sine(Ctx &c, bool fp32, bool ring) {
+    if (ring && (c.nx > 256 || c.ny > 256)) {
         c.err = "the PFFT preconditioner supports N_x, N_y <= 256";
         return HELM_EUNSUPPORTED;
     }
@@ -203,14 +211,18 @@ helm_status ensure_pfft(Ctx &c, bool fp32) {
         ST_TRY(dalloc(c, &c.pfft->dFy, (size_t)c.ny));
         HIP_TRY(hipMemcpy(c.pfft->dFx, fx.data(), fx.size() * sizeof(double2), hipMemcpyHostToDevice));
         HIP_TRY(hipMemcpy(c.pfft->dFy, fy.data(), fy.size() * sizeof(double2), hipMemcpyHostToDevice));
-        ST_TRY(build_pfft_mats(c, c.pfft->m64));
     }
-    if (fp32 && !c.pfft->has32) {
-        ST_TRY(build_pfft_mats(c, c.pfft->m32));
-        c.pfft->has32 = true;
+    PfftPlan &P = *c.pfft;
+    if (!P.m64.Sx) ST_TRY(build_sine_mats(c, P.m64));
+    if (ring && !P.m64.ringT) ST_TRY(build_ring_mats(c, P.m64));
+    if (fp32) {
+        if (!P.m32.Sx) ST_TRY(build_sine_mats(c, P.m32));
+        if (ring && !P.m32.ringT) ST_TRY(build_ring_mats(c, P.m32));
     }
     return HELM_OK;
 }
+
+helm_status ensure_pfft(Ctx &c, bool fp32) { return ensure_sine(c, fp32, true); }
 
 helm_status pfft_apply(Ctx &c, const double2 *y, double2 *z, bool fp32) {
     ST_TRY(ensure_pfft(c, fp32));
@@ -255,6 +267,36 @@ helm_status pfft_apply(Ctx &c, const double2 *y, double2 *z, bool fp32) {
     return HELM_OK;
 }
 
+// FFT2 (the Dirichlet comparison preconditioner): M_D = T_x^D + T_y^D + T_z^D + k0^2 I with gamma = 0 on every
+// axis. The orthonormal sine matrices diagonalise T_x^D and T_y^D; each (i, j) line is then the z-tridiagonal
+// of the EigT solve with the Dirichlet eigenvalues and no closure term at l = 1, N_z.
+helm_status fft2_apply(Ctx &c, const double2 *y, double2 *z, bool fp32) {
+    ST_TRY(ensure_sine(c, fp32, false));
+    PfftPlan &P = *c.pfft;
+    ST_TRY(ensure_tpiv(c, P.dFx, P.dFy, &c.tpiv_fft2, make_double2(0.0, 0.0)));
+    GemmDesc dx = desc_x(c), dy = desc_y(c);
+    const double2 g0 = make_double2(0.0, 0.0);
+    const double hz2 = c.hz * c.hz;
+    const int nx = c.nx, ny = c.ny, nz = c.nz;
+    if (!fp32) {
+        auto &m = P.m64;
+        HIP_TRY(timed(c, HELM_K_PFFT, 4.0 * dx.M * (double)dx.N * dx.K, [&] { return launch_gemm_z64(dx, y, m.Sx, c.t1, c.stream, 2); }));
+        HIP_TRY(timed(c, HELM_K_PFFT, 4.0 * dy.M * (double)dy.N * dy.K * dy.batch, [&] { return launch_gemm_z64(dy, m.Sy, c.t1, c.t2, c.stream, 1); }));
+        HIP_TRY(timed(c, HELM_K_TRIDIAG64, 32.0 * c.n, [&] { return launch_tridiag_chunk_z64(c.t2, c.t2, c.tpiv_fft2, P.dFx, P.dFy, nx, ny, nz, c.ax, c.ay, c.c0, g0, hz2, c.stream); }));
+        HIP_TRY(timed(c, HELM_K_PFFT, 4.0 * dy.M * (double)dy.N * dy.K * dy.batch, [&] { return launch_gemm_z64(dy, m.Sy, c.t2, c.t1, c.stream, 1); }));
+        HIP_TRY(timed(c, HELM_K_PFFT, 4.0 * dx.M * (double)dx.N * dx.K, [&] { return launch_gemm_z64(dx, c.t1, m.Sx, z, c.stream, 2); }));
+    } else {
+        ST_TRY(ensure_fp32_work(c));
+        auto &m = P.m32;
+        HIP_TRY(timed(c, HELM_K_PFFT, 4.0 * dx.M * (double)dx.N * dx.K, [&] { return launch_gemm_z32_in64(dx, y, m.Sx, c.t1f, c.stream, 2); }));
+        HIP_TRY(timed(c, HELM_K_PFFT, 4.0 * dy.M * (double)dy.N * dy.K * dy.batch, [&] { return launch_gemm_z32(dy, m.Sy, c.t1f, c.t2f, c.stream, 1); }));
+        HIP_TRY(timed(c, HELM_K_TRIDIAG32, 16.0 * c.n, [&] { return launch_tridiag_chunk_z32(c.t2f, c.t2f, c.tpiv_fft2, P.dFx, P.dFy, nx, ny, nz, c.ax, c.ay, c.c0, g0, hz2, c.stream); }));
+        HIP_TRY(timed(c, HELM_K_PFFT, 4.0 * dy.M * (double)dy.N * dy.K * dy.batch, [&] { return launch_gemm_z32(dy, m.Sy, c.t2f, c.t1f, c.stream, 1); }));
+        HIP_TRY(timed(c, HELM_K_PFFT, 4.0 * dx.M * (double)dx.N * dx.K, [&] { return launch_gemm_z32_out64(dx, c.t1f, m.Sx, z, c.stream, 2); }));
+    }
+    return HELM_OK;
+}
+
 helm_status precond(Ctx &c, const double2 *y, double2 *z, int kind, int fp32) {
     if (kind == HELM_PREC_EIGT) return eigt_apply(c, y, z, fp32 != 0);
     if (kind == HELM_PREC_NONE) {
@@ -262,6 +304,7 @@ helm_status precond(Ctx &c, const double2 *y, double2 *z, int kind, int fp32) {
         return HELM_OK;
     }
     if (kind == HELM_PREC_PFFT) return pfft_apply(c, y, z, fp32 != 0);
+    if (kind == HELM_PREC_FFT2) return fft2_apply(c, y, z, fp32 != 0);
     c.err = "unknown preconditioner kind";
     return HELM_EINVAL;
 }
@@ -680,7 +723,8 @@ helm_status helm_gmres_solve(helm_ctx *ctx, const void *F_dev, void *x_dev, cons
         c.err = "an FP32 preconditioner needs flexible GMRES (flexible = 1)";
         return HELM_EINVAL;
     }
-    if (opts->prec != HELM_PREC_EIGT && opts->prec != HELM_PREC_PFFT && opts->prec != HELM_PREC_NONE) {
+    if (opts->prec != HELM_PREC_EIGT && opts->prec != HELM_PREC_PFFT && opts->prec != HELM_PREC_NONE &&
+        opts->prec != HELM_PREC_FFT2) {
         c.err = "unknown preconditioner kind";
         return HELM_EINVAL;
     }

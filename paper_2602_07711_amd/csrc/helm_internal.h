@@ -56,7 +56,6 @@ struct PfftPlan {
     double2 *dFx = nullptr, *dFy = nullptr;      // Dirichlet eigenvalues 2 cos(pi i/(N+1))
     PfftMats<double2> m64;
     PfftMats<float2> m32;
-    bool has32 = false;
 };
 
 // basis vectors are KRYLOV_PAD elements longer than n so that equal indices of different vectors do not share
@@ -105,6 +104,7 @@ struct Ctx {
     double2 *t1 = nullptr, *t2 = nullptr;
     float2 *t1f = nullptr, *t2f = nullptr;
     double2 *tpiv_eig = nullptr, *tpiv_dir = nullptr;  // pivots entering each z-chunk (absorbing / Dirichlet x-y eigenvalues)
+    double2 *tpiv_fft2 = nullptr;                        // the same for Dirichlet x-y eigenvalues and a Dirichlet z closure
     double2 *sg_y = nullptr, *sg_part = nullptr, *sg_red = nullptr, *sg_host = nullptr;   // helm_scale_guess work
 
     PfftPlan *pfft = nullptr;

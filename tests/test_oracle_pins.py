@@ -248,6 +248,13 @@ def test_dirichlet_eigt_is_the_sine_solver():
     assert np.linalg.norm(e.solve(y) - p.solve_F(ys).ravel()) <= 1e-12 * np.linalg.norm(y)
 
 
+def test_eigt_with_dirichlet_closures_inverts_fft2_matrix():
+    shape, h3, k0, _, y = _prec_case()
+    z = pc.EigT(shape, h3, k0, (0.0, 0.0, 0.0)).solve(y)
+    zs = spla.splu(pc.M_dirichlet(shape, h3, k0).tocsc()).solve(y)
+    assert np.linalg.norm(z - zs) <= 1e-11 * np.linalg.norm(zs)
+
+
 def test_fft2_matrix_sine_modes_closed_form():
     """FFT2's matrix (gamma = 0 on every axis) has the product sine modes sin(pi p x) sin(pi q y) sin(pi r z) as
     eigenvectors with eigenvalue sum_a (2 cos(pi p_a h_a) - 2) / h_a^2 + k0^2 (h_a = 1/(N_a + 1)); checked for
