@@ -62,12 +62,15 @@ def test_thomas_matches_dense_solve():
 
 # ------------------------------------------------------------------------------------------- operator A
 
+@pytest.mark.parametrize("cplx", [False, True], ids=["real_k2", "complex_k2"])
 @pytest.mark.parametrize("order", [2, 4, 6])
-def test_kron_route_equals_stencil_route(order):
+def test_kron_route_equals_stencil_route(order, cplx):
     rng = np.random.default_rng(order)
     shape = (5, 6, 7)
     h3 = (0.1, 0.1, 0.1) if order == 6 else (0.1, 0.13, 0.07)
     k2h = 30 + 10 * rng.random(tuple(s + 4 for s in shape))
+    if cplx:
+        k2h = k2h + 1j * (3 + 2 * rng.random(k2h.shape))
     k2i = k2h[2:-2, 2:-2, 2:-2]
     g = (0.3 + 0.8j, 0.5 + 0.2j, -0.4 + 0.9j)
     fields = op.derived_fields(k2h, h3[0]) if order == 6 else None
@@ -77,8 +80,9 @@ def test_kron_route_equals_stencil_route(order):
     assert np.diff(A1.indptr).max() == {2: 7, 4: 19, 6: 27}[order]
 
 
-def _smooth_case(n):
-    """u = exp(i k.x)(1 + 0.3 x y) with k = (2.1, -1.3, 1.7); k^2 = 30 (1 + 0.5 sin 2x cos(3y + z)), on the halo grid."""
+def _smooth_case(n, cplx=False):
+    """u = exp(i k.x)(1 + 0.3 x y) with k = (2.1, -1.3, 1.7); k^2 = 30 (1 + 0.5 sin 2x cos(3y + z)), plus, for an
+    attenuating medium, 6i (1 + 0.5 cos(x + 2y)), on the halo grid."""
     c = synth.halo_coords(n)
     z, y, x = c[:, None, None], c[None, :, None], c[None, None, :]
     kv = np.array([2.1, -1.3, 1.7])
@@ -86,12 +90,14 @@ def _smooth_case(n):
     u = E * (1 + 0.3 * x * y)
     lapu = E * (-(kv @ kv) * (1 + 0.3 * x * y) + 2j * 0.3 * (kv[0] * y + kv[1] * x))
     k2 = 30.0 * (1 + 0.5 * np.sin(2 * x) * np.cos(3 * y + z))
+    if cplx:
+        k2 = k2 + 6j * (1 + 0.5 * np.cos(x + 2 * y)) + 0 * z
     return u, k2, lapu + k2 * u
 
 
-def _truncation(order, n):
+def _truncation(order, n, cplx=False):
     h = 1.0 / (n + 1)
-    u, k2, f = _smooth_case(n)
+    u, k2, f = _smooth_case(n, cplx)
     fields = op.derived_fields(k2, h) if order == 6 else None
     coefs = op.stencil_coefficients(order, (h, h, h), k2[1:-1, 1:-1, 1:-1], fields)
     Au = op.apply_unfolded(coefs, u[1:-1, 1:-1, 1:-1])
@@ -99,10 +105,12 @@ def _truncation(order, n):
     return np.abs(Au - F).max()
 
 
+@pytest.mark.parametrize("cplx", [False, True], ids=["real_k2", "complex_k2"])
 @pytest.mark.parametrize("order,slope", [(2, 1.85), (4, 3.75), (6, 5.6)])
-def test_truncation_order(order, slope):
-    """Local truncation error of A u - F on smooth u and variable k^2 falls as h^order (Sec. 2.2, 2.3)."""
-    e1, e2 = _truncation(order, 16), _truncation(order, 32)
+def test_truncation_order(order, slope, cplx):
+    """Local truncation error of A u - F on smooth u and variable k^2 falls as h^order (Sec. 2.2, 2.3); with a
+    complex k^2 too (a dropped imaginary part of any k^2 term would leave an O(1) error)."""
+    e1, e2 = _truncation(order, 16, cplx), _truncation(order, 32, cplx)
     assert np.log2(e1 / e2) > slope
 
 
