@@ -389,8 +389,10 @@ def rhs(order: int, f_halo: np.ndarray, h3, k2_int=None, fields=None) -> np.ndar
 def problem(order: int, k2_halo: np.ndarray, f_halo: np.ndarray, h: float, k0: float, bc: str = "abc",
             route: str = "kron"):
     """Assemble (A, F) for k^2 and f sampled on a two-cell halo, uniform h, gamma from k0 (bc="abc") or
-    gamma = 0 (bc="dirichlet")."""
-    k2_int = _interior(k2_halo, 2).astype(np.float64)
+    gamma = 0 (bc="dirichlet"). k^2 may be complex (an attenuating medium, as in the scattering test of
+    Sec. 5.1); the scheme is the same."""
+    k2_int = _interior(k2_halo, 2)
+    k2_int = k2_int.astype(np.complex128 if np.iscomplexobj(k2_int) else np.float64)
     g = gamma_abc(k0, h) if bc == "abc" else 0.0
     gammas = (g, g, g)
     h3 = (h, h, h)

@@ -12,5 +12,7 @@ from .media import (  # noqa: F401
     plane_wave_sources,
     uneven_problem_set,
     warmstart_problem,
+    staggered_coords,
+    single_inclusion_problem,
     workload,
 )

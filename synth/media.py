@@ -107,6 +107,27 @@ def warmstart_problem(n: int, seed: int, k0: float = 60.0, sigma: float = 0.03, 
                 f=gaussian_source(n, sigma_cells=sigma * (n + 1), center=tuple(center)), center=tuple(center))
 
 
+def staggered_coords(n: int) -> np.ndarray:
+    """Staggered node coordinates (j + 1/2) h, h = 1/N, for j = -2..N+1 (length N+4): the grid of the
+    scattering experiment of Sec. 5.1 (the boundary lies half a cell outside the first and last nodes)."""
+    return (np.arange(n + 4) - 2 + 0.5) / n
+
+
+def single_inclusion_problem(n: int, k2_in: complex = 1050 + 2.26j, k0sq: float = 439.2,
+                             center=(0.5, 0.5, 0.7), radius: float = 0.1):
+    """The single-inclusion scattering problem of Sec. 5.1 on the staggered N^3 grid (h = 1/N): k^2 = k2_in
+    inside the sphere |x - c| <= r, k0^2 outside (sampled at the nodes, no smoothing), and the scattered-field
+    source f = -(k^2 - k0^2) exp(i k0 z) of the incident plane wave exp(i k0 z). Returns dict(n, h, k0, k2, f)
+    with complex128 k2 and f on the halo grid."""
+    c = staggered_coords(n)
+    z, y, x = c[:, None, None], c[None, :, None], c[None, None, :]
+    inside = (x - center[0]) ** 2 + (y - center[1]) ** 2 + (z - center[2]) ** 2 <= radius * radius
+    k2 = np.where(inside, complex(k2_in), complex(k0sq)).astype(np.complex128)
+    k0 = float(np.sqrt(k0sq))
+    f = (-(k2 - k0sq) * np.exp(1j * k0 * z)).astype(np.complex128)
+    return dict(n=n, h=1.0 / n, k0=k0, k2=k2, f=f)
+
+
 def workload(name: str, n: int | None = None):
     """The named synthetic workloads. Returns dict(n, h, order, k0, k2 (halo), f (halo), m, ...).
 
