@@ -48,7 +48,7 @@ KCLASS = {
 # variants (the GEMMs) have no single row and report no traffic.
 TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
                             "noise256_fp32_eigt_fgmres_hbm_traffic.md")
-TRAFFIC_KERNEL = {"lincomb": "k_lincomb", "dots": "k_dots", "matvec": "k_matvec<6, true>",
+TRAFFIC_KERNEL = {"lincomb": "k_lincomb<z64>", "dots": "k_dots", "matvec": "k_matvec<6, true, z32, false>",
                   "tridiag32": "k_tridiag_chunk<float>"}
 
 
@@ -218,6 +218,54 @@ def bench_learned(H, torch, args):
     return out
 
 
+def bench_direct_sweep(H, torch, dev, sizes):
+    """The paper's Table 2 workload: the preconditioner as a direct solver of the second-order system of the
+    Sec. 5.1 test problem (u = phi(x) phi(y) phi(z), k0^2 = 439.2, staggered nodes, two-point absorbing closure).
+    Per grid: setup time, the direct-solve time of EigT (FP64/FP32) and PFFT (FP64/FP32, N <= 256) on the solve
+    stream (mean of 3 after one untimed call), and max-err / L2-err of the FP64 EigT solution against u."""
+    import math
+    k0 = math.sqrt(439.2)
+    rows = []
+    for n in sizes:
+        x = ((torch.arange(n, dtype=torch.float64, device=dev) + 0.5) / n).to(torch.complex128)
+        e1, e2 = torch.exp(1j * k0 * x), torch.exp(-1j * k0 * (x - 1.0))
+        ph, p2 = e1 + e2 - 2, -k0 * k0 * (e1 + e2)
+        u = ph[:, None, None] * ph[None, :, None] * ph[None, None, :]
+        f = p2[:, None, None] * ph[None, :, None] * ph[None, None, :]
+        f += ph[:, None, None] * p2[None, :, None] * ph[None, None, :]
+        f += ph[:, None, None] * ph[None, :, None] * p2[None, None, :]
+        f += k0 * k0 * u
+        k2 = torch.full((n, n, n), k0 * k0, dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx = H.helm_setup(k2, 1.0 / n, 2, "abc", k0, shape=(n, n, n))
+        torch.cuda.synchronize()
+        row = dict(n=n, setup_s=round(time.perf_counter() - t0, 3))
+        del k2
+        fv = f.reshape(-1)
+        z = torch.empty_like(fv)
+        for kind in ["eigt"] + (["pfft"] if n <= 256 else []):
+            for fp32 in (False, True):
+                H.helm_precond_apply(ctx, fv, z, kind=kind, fp32=fp32)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(3):
+                    H.helm_precond_apply(ctx, fv, z, kind=kind, fp32=fp32)
+                torch.cuda.synchronize()
+                row[f"{kind}_{'fp32' if fp32 else 'fp64'}_ms"] = round((time.perf_counter() - t0) / 3 * 1e3, 3)
+                if kind == "eigt" and not fp32:
+                    d = z.view(n, n, n) - u
+                    row["max_err"] = float(d.abs().max())
+                    row["l2_err"] = float(torch.linalg.vector_norm(d) / torch.linalg.vector_norm(u))
+                    del d
+        log(f"direct solve {n}^3: {row}")
+        rows.append(row)
+        H.helm_destroy(ctx)
+        del u, f, fv, z
+        torch.cuda.empty_cache()
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -232,6 +280,9 @@ def main():
     ap.add_argument("--ws-samples", type=int, default=2000, help="training solves of the learned leg")
     ap.add_argument("--ws-epochs", type=int, default=20, help="training epochs of the learned leg")
     ap.add_argument("--ws-eval", type=int, default=16, help="held-out 128^3 problems of the learned leg")
+    ap.add_argument("--direct-sweep", default=None,
+                    help="comma-separated grid sizes: also time the preconditioner as a direct solver of the paper's "
+                         "second-order test problem (Table 2 workload), e.g. 100,127,200,255,400,511,600,767,800")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run three plain 256 MiB device-to-device copies (reference dispatches for scaling "
                          "hardware byte counters)")
@@ -333,6 +384,10 @@ def main():
     if not args.no_learned:
         torch.cuda.empty_cache()
         learned = bench_learned(H, torch, args)
+    direct = None
+    if args.direct_sweep:
+        torch.cuda.empty_cache()
+        direct = bench_direct_sweep(H, torch, dev, [int(v) for v in args.direct_sweep.split(",")])
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
@@ -366,6 +421,7 @@ def main():
         "gemm_autotune": tune,
         "batched": batched,
         "learned_warm_start": learned,
+        "direct_sweep": direct,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -117,6 +117,13 @@ typedef struct {
 helm_status helm_setup(helm_ctx **ctx, helm_grid g, const double h[3], const double *k2_dev, int k2_halo,
                        int order, helm_bc bc, void *stream);
 
+/* The same with a complex k^2 (attenuating media, e.g. the inclusion k^2 = 1050 + 2.26i of the scattering
+ * experiment of Sec. 5.1): k2_dev holds complex128 samples in the layout above. The scheme is unchanged
+ * (Sec. 2.2 eq. scheme4, Sec. 2.3 eq. scheme6 with complex k^2 and complex derived fields); the preconditioner
+ * keeps the real constant k0 of `bc`. Batched solves do not accept such contexts (HELM_EUNSUPPORTED). */
+helm_status helm_setup_complex(helm_ctx **ctx, helm_grid g, const double h[3], const void *k2_dev, int k2_halo,
+                               int order, helm_bc bc, void *stream);
+
 /* F = R_h f, the modified right-hand side of the scheme (Sec. 2.2 f^(IV), Sec. 2.3 f^(VI) together with the
  * k^2 f and f_nu terms of Delta_h(k^2 U)). f_dev: complex128 samples of f with a two-cell halo.
  * F_dev: n complex128. f is data: its halo samples are used as they are. */

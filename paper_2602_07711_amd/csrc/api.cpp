@@ -116,7 +116,8 @@ helm_status ensure_fp32_work(Ctx &c) {
     return HELM_OK;
 }
 
-helm_status eigt_apply(Ctx &c, const double2 *y, double2 *z, bool fp32) {
+// z32 (FP32 form only): write the result as complex64 there instead of complex128 into z
+helm_status eigt_apply(Ctx &c, const double2 *y, double2 *z, bool fp32, float2 *z32 = nullptr) {
     GemmDesc dx = desc_x(c), dy = desc_y(c);
     double2 gz = d2(c.gamma[2]);
     double scale = c.hz * c.hz;
@@ -134,7 +135,7 @@ helm_status eigt_apply(Ctx &c, const double2 *y, double2 *z, bool fp32) {
         ST_TRY(ensure_tpiv(c, c.dxe, c.dye, &c.tpiv_eig));
         HIP_TRY(timed(c, HELM_K_TRIDIAG32, 16.0 * c.n, [&] { return launch_tridiag_chunk_z32(c.t2f, c.t2f, c.tpiv_eig, c.dxe, c.dye, c.nx, c.ny, c.nz, c.ax, c.ay, c.c0, gz, scale, c.stream); }));
         HIP_TRY(timed(c, HELM_K_GEMM_Y32, gemm_flops(dy), [&] { return launch_gemm_z32(dy, c.AyI32, c.t2f, c.t1f, c.stream, 0, c.gemm_cfg[3]); }));
-        HIP_TRY(timed(c, HELM_K_GEMM_X32, gemm_flops(dx), [&] { return launch_gemm_z32_out64(dx, c.t1f, c.BxI32, z, c.stream, 0, c.gemm_cfg[2]); }));
+        HIP_TRY(timed(c, HELM_K_GEMM_X32, gemm_flops(dx), [&] { return z32 ? launch_gemm_z32(dx, c.t1f, c.BxI32, z32, c.stream, 0, c.gemm_cfg[2]) : launch_gemm_z32_out64(dx, c.t1f, c.BxI32, z, c.stream, 0, c.gemm_cfg[2]); }));
     }
     return HELM_OK;
 }
@@ -224,7 +225,7 @@ helm_status ensure_sine(Ctx &c, bool fp32, bool ring) {
 
 helm_status ensure_pfft(Ctx &c, bool fp32) { return ensure_sine(c, fp32, true); }
 
-helm_status pfft_apply(Ctx &c, const double2 *y, double2 *z, bool fp32) {
+helm_status pfft_apply(Ctx &c, const double2 *y, double2 *z, bool fp32, float2 *z32 = nullptr) {
     ST_TRY(ensure_pfft(c, fp32));
     ST_TRY(ensure_tpiv(c, c.dxe, c.dye, &c.tpiv_eig));
     ST_TRY(ensure_tpiv(c, c.pfft->dFx, c.pfft->dFy, &c.tpiv_dir));
@@ -262,7 +263,7 @@ helm_status pfft_apply(Ctx &c, const double2 *y, double2 *z, bool fp32) {
         HIP_TRY(timed(c, HELM_K_RING, 16.0 * c.n + ring_work, [&] { return launch_ring_forward_z32(m.ringT, m.ringW, m.yhat, hz2, c.t2f, m.Sy, m.Sx, ex, ey, nx, ny, nz, m.rbuf, m.fvec, c.stream); }));
         HIP_TRY(timed(c, HELM_K_TRIDIAG32, 16.0 * c.n, [&] { return launch_tridiag_chunk_z32(c.t2f, c.t2f, c.tpiv_dir, P.dFx, P.dFy, nx, ny, nz, c.ax, c.ay, c.c0, gz, 1.0, c.stream); }));
         HIP_TRY(timed(c, HELM_K_PFFT, 4.0 * dy.M * (double)dy.N * dy.K * dy.batch, [&] { return launch_gemm_z32(dy, m.Sy, c.t2f, c.t1f, c.stream, 1); }));
-        HIP_TRY(timed(c, HELM_K_PFFT, 4.0 * dx.M * (double)dx.N * dx.K, [&] { return launch_gemm_z32_out64(dx, c.t1f, m.Sx, z, c.stream, 2); }));
+        HIP_TRY(timed(c, HELM_K_PFFT, 4.0 * dx.M * (double)dx.N * dx.K, [&] { return z32 ? launch_gemm_z32(dx, c.t1f, m.Sx, z32, c.stream, 2) : launch_gemm_z32_out64(dx, c.t1f, m.Sx, z, c.stream, 2); }));
     }
     return HELM_OK;
 }
@@ -270,7 +271,7 @@ helm_status pfft_apply(Ctx &c, const double2 *y, double2 *z, bool fp32) {
 // FFT2 (the Dirichlet comparison preconditioner): M_D = T_x^D + T_y^D + T_z^D + k0^2 I with gamma = 0 on every
 // axis. The orthonormal sine matrices diagonalise T_x^D and T_y^D; each (i, j) line is then the z-tridiagonal
 // of the EigT solve with the Dirichlet eigenvalues and no closure term at l = 1, N_z.
-helm_status fft2_apply(Ctx &c, const double2 *y, double2 *z, bool fp32) {
+helm_status fft2_apply(Ctx &c, const double2 *y, double2 *z, bool fp32, float2 *z32 = nullptr) {
     ST_TRY(ensure_sine(c, fp32, false));
     PfftPlan &P = *c.pfft;
     ST_TRY(ensure_tpiv(c, P.dFx, P.dFy, &c.tpiv_fft2, make_double2(0.0, 0.0)));
@@ -292,7 +293,7 @@ helm_status fft2_apply(Ctx &c, const double2 *y, double2 *z, bool fp32) {
         HIP_TRY(timed(c, HELM_K_PFFT, 4.0 * dy.M * (double)dy.N * dy.K * dy.batch, [&] { return launch_gemm_z32(dy, m.Sy, c.t1f, c.t2f, c.stream, 1); }));
         HIP_TRY(timed(c, HELM_K_TRIDIAG32, 16.0 * c.n, [&] { return launch_tridiag_chunk_z32(c.t2f, c.t2f, c.tpiv_fft2, P.dFx, P.dFy, nx, ny, nz, c.ax, c.ay, c.c0, g0, hz2, c.stream); }));
         HIP_TRY(timed(c, HELM_K_PFFT, 4.0 * dy.M * (double)dy.N * dy.K * dy.batch, [&] { return launch_gemm_z32(dy, m.Sy, c.t2f, c.t1f, c.stream, 1); }));
-        HIP_TRY(timed(c, HELM_K_PFFT, 4.0 * dx.M * (double)dx.N * dx.K, [&] { return launch_gemm_z32_out64(dx, c.t1f, m.Sx, z, c.stream, 2); }));
+        HIP_TRY(timed(c, HELM_K_PFFT, 4.0 * dx.M * (double)dx.N * dx.K, [&] { return z32 ? launch_gemm_z32(dx, c.t1f, m.Sx, z32, c.stream, 2) : launch_gemm_z32_out64(dx, c.t1f, m.Sx, z, c.stream, 2); }));
     }
     return HELM_OK;
 }
@@ -309,20 +310,31 @@ helm_status precond(Ctx &c, const double2 *y, double2 *z, int kind, int fp32) {
     return HELM_EINVAL;
 }
 
+// the FP32 preconditioner with a complex64 output (EigT, PFFT or FFT2)
+helm_status precond32(Ctx &c, const double2 *y, float2 *z, int kind) {
+    if (kind == HELM_PREC_EIGT) return eigt_apply(c, y, nullptr, true, z);
+    if (kind == HELM_PREC_PFFT) return pfft_apply(c, y, nullptr, true, z);
+    if (kind == HELM_PREC_FFT2) return fft2_apply(c, y, nullptr, true, z);
+    c.err = "no complex64 output for this preconditioner kind";
+    return HELM_EINVAL;
+}
+
 // ---------------------------------------------------------------------------------------------------------
 // Krylov workspace and reductions
 // ---------------------------------------------------------------------------------------------------------
 
+// flexible: 1 = Z basis in complex128, 2 = Z basis in complex64 (FP32 preconditioner)
 helm_status ensure_krylov(Ctx &c, int m, int flexible) {
     KrylovWork &k = c.kw;
     if (k.V && k.m == m && k.flexible == flexible) return HELM_OK;
-    dfree(c, k.V); dfree(c, k.Z); dfree(c, k.tmp); dfree(c, k.partials); dfree(c, k.red);
+    dfree(c, k.V); dfree(c, k.Z); dfree(c, k.Zf); dfree(c, k.tmp); dfree(c, k.partials); dfree(c, k.red);
     if (k.red_host) { hipHostFree(k.red_host); k.red_host = nullptr; }
     k = KrylovWork{};
     k.nblocks = dots_blocks(c.n);
     k.ld = c.n + KRYLOV_PAD;
     ST_TRY(dalloc(c, &k.V, (size_t)(m + 1) * k.ld));
-    if (flexible) ST_TRY(dalloc(c, &k.Z, (size_t)m * k.ld));
+    if (flexible == 1) ST_TRY(dalloc(c, &k.Z, (size_t)m * k.ld));
+    if (flexible == 2) ST_TRY(dalloc(c, &k.Zf, (size_t)m * k.ld));
     ST_TRY(dalloc(c, &k.tmp, (size_t)c.n));
     ST_TRY(dalloc(c, &k.partials, (size_t)k.nblocks * (m + 2)));
     ST_TRY(dalloc(c, &k.red, (size_t)(m + 2)));
@@ -438,8 +450,9 @@ void helm_destroy(helm_ctx *ctx) {
     delete ctx;
 }
 
-helm_status helm_setup(helm_ctx **out, helm_grid g, const double h[3], const double *k2_dev, int k2_halo, int order,
-                       helm_bc bc, void *stream) {
+namespace {
+helm_status setup_impl(helm_ctx **out, helm_grid g, const double h[3], const void *k2_dev, bool k2_complex,
+                       int k2_halo, int order, helm_bc bc, void *stream) {
     g_setup_err.clear();
     auto fail = [&](helm_status s, const std::string &m) {
         g_setup_err = m;
@@ -485,6 +498,7 @@ helm_status helm_setup(helm_ctx **out, helm_grid g, const double h[3], const dou
     // stencil parameters
     StencilParams &p = c.sp;
     p.nx = c.nx; p.ny = c.ny; p.nz = c.nz; p.order = order;
+    p.k2i = nullptr; p.fldi = nullptr;
     p.gx = d2(c.gamma[0]); p.gy = d2(c.gamma[1]); p.gz = d2(c.gamma[2]);
     double hs[3] = {c.hx, c.hy, c.hz};
     double ih2[3] = {1.0 / (hs[0] * hs[0]), 1.0 / (hs[1] * hs[1]), 1.0 / (hs[2] * hs[2])};
@@ -521,7 +535,16 @@ helm_status helm_setup(helm_ctx **out, helm_grid g, const double h[3], const dou
     helm_status st;
     if ((st = dalloc(c, &c.k2, (size_t)c.n)) != HELM_OK) return bail(st);
     if (order == 6 && (st = dalloc(c, &c.fld, (size_t)c.n)) != HELM_OK) return bail(st);
-    hipError_t he = launch_derived_fields(k2_dev, k2_halo, c.k2, c.fld, p, c.hx, c.stream);
+    hipError_t he;
+    if (k2_complex) {
+        if ((st = dalloc(c, &c.k2i, (size_t)c.n)) != HELM_OK) return bail(st);
+        if (order == 6 && (st = dalloc(c, &c.fldi, (size_t)c.n)) != HELM_OK) return bail(st);
+        he = launch_derived_fields_c((const double2 *)k2_dev, k2_halo, c.k2, c.k2i, c.fld, c.fldi, p, c.hx, c.stream);
+        p.k2i = c.k2i;
+        p.fldi = c.fldi;
+    } else {
+        he = launch_derived_fields((const double *)k2_dev, k2_halo, c.k2, c.fld, p, c.hx, c.stream);
+    }
     if (he == hipErrorInvalidValue) { c.err = "k^2 contains NaN or Inf"; return bail(HELM_EINVAL); }
     if (he != hipSuccess) { c.err = std::string("derived fields: ") + hipGetErrorString(he); return bail(HELM_EDEVICE); }
 
@@ -556,11 +579,22 @@ helm_status helm_setup(helm_ctx **out, helm_grid g, const double h[3], const dou
     *out = ctx;
     return HELM_OK;
 }
+}  // namespace
+
+helm_status helm_setup(helm_ctx **out, helm_grid g, const double h[3], const double *k2_dev, int k2_halo, int order,
+                       helm_bc bc, void *stream) {
+    return setup_impl(out, g, h, k2_dev, false, k2_halo, order, bc, stream);
+}
+
+helm_status helm_setup_complex(helm_ctx **out, helm_grid g, const double h[3], const void *k2_dev, int k2_halo,
+                               int order, helm_bc bc, void *stream) {
+    return setup_impl(out, g, h, k2_dev, true, k2_halo, order, bc, stream);
+}
 
 // ---- GEMM tile autotuner ----
 namespace {
 std::string tune_key(int kind, const GemmDesc &d) {
-    return "v2 " + std::to_string(kind) + " " + std::to_string(d.M) + " " + std::to_string(d.N) + " " + std::to_string(d.K) +
+    return "v3 " + std::to_string(kind) + " " + std::to_string(d.M) + " " + std::to_string(d.N) + " " + std::to_string(d.K) +
            " " + std::to_string(d.batch);
 }
 bool tune_cache_lookup(const std::string &key, int &cfg) {
@@ -697,7 +731,7 @@ helm_status helm_scale_guess(helm_ctx *ctx, const void *F_dev, void *x_dev, doub
     }
     const cd alpha = yy > 0.0 ? yf / yy : cd(0.0, 0.0);
     std::vector<double2> coef(1);
-    HIP_TRY(timed(c, HELM_K_LINCOMB, 32.0 * c.n, [&] { return launch_lincomb(x, x, d2(alpha), nullptr, c.n, 0, coef.data(), c.n, c.stream); }));
+    HIP_TRY(timed(c, HELM_K_LINCOMB, 32.0 * c.n, [&] { return launch_lincomb(x, x, d2(alpha), (const double2 *)nullptr, c.n, 0, coef.data(), c.n, c.stream); }));
     if (alpha_re) *alpha_re = alpha.real();
     if (alpha_im) *alpha_im = alpha.imag();
     return HELM_OK;
@@ -730,7 +764,9 @@ helm_status helm_gmres_solve(helm_ctx *ctx, const void *F_dev, void *x_dev, cons
     }
     helm_solve_info inf{};
     const bool flex = opts->flexible != 0;
-    ST_TRY(ensure_krylov(c, m, flex ? 1 : 0));
+    // FGMRES with an FP32 preconditioner keeps Z in complex64: its vectors are FP32 results, so this is exact
+    const bool zf32 = flex && opts->prec_fp32 && opts->prec != HELM_PREC_NONE;
+    ST_TRY(ensure_krylov(c, m, flex ? (zf32 ? 2 : 1) : 0));
     KrylovWork &k = c.kw;
     const double2 *F = (const double2 *)F_dev;
     double2 *x = (double2 *)x_dev;
@@ -792,7 +828,7 @@ helm_status helm_gmres_solve(helm_ctx *ctx, const void *F_dev, void *x_dev, cons
         push_hist(inf.relres_true);
         if (beta <= opts->rtol * bnorm) { result = HELM_OK; inf.converged = 1; break; }
         if (its >= opts->maxit) { result = HELM_ENOCONV; break; }
-        HIP_TRY(timed(c, HELM_K_LINCOMB, 16.0 * c.n * 2, [&] { return launch_lincomb(k.V, k.V, make_double2(1.0 / beta, 0.0), nullptr, n, 0, coef.data(), n, c.stream); }));
+        HIP_TRY(timed(c, HELM_K_LINCOMB, 16.0 * c.n * 2, [&] { return launch_lincomb(k.V, k.V, make_double2(1.0 / beta, 0.0), (const double2 *)nullptr, n, 0, coef.data(), n, c.stream); }));
         std::fill(H.begin(), H.end(), cd(0.0));
         std::fill(g.begin(), g.end(), cd(0.0));
         g[0] = beta;
@@ -801,15 +837,20 @@ helm_status helm_gmres_solve(helm_ctx *ctx, const void *F_dev, void *x_dev, cons
         for (int j = 0; j < m; ++j) {
             double2 *vj = k.V + (long long)j * k.ld;
             double2 *w = k.V + (long long)(j + 1) * k.ld;
-            double2 *z = flex ? k.Z + (long long)j * k.ld : k.tmp;
+            double2 *z = zf32 ? nullptr : (flex ? k.Z + (long long)j * k.ld : k.tmp);
+            float2 *zf = zf32 ? k.Zf + (long long)j * k.ld : nullptr;
             HIP_TRY(hipEventRecord(ev[2], c.stream));
-            ST_TRY(precond(c, vj, z, opts->prec, opts->prec_fp32));
+            if (zf32) ST_TRY(precond32(c, vj, zf, opts->prec));
+            else ST_TRY(precond(c, vj, z, opts->prec, opts->prec_fp32));
             HIP_TRY(hipEventRecord(ev[3], c.stream));
             // Arnoldi on A M^{-1} - I (same Krylov space; column j of H gains +1 on its diagonal): the matvec in
             // residual form writes y = v_j - A z_j = -(A M^{-1} v_j - v_j). With a good preconditioner
             // A M^{-1} v_j is close to v_j, so orthogonalising the shifted vector avoids the cancellation that
             // classical Gram-Schmidt on A M^{-1} v_j itself would suffer.
-            HIP_TRY(timed(c, HELM_K_MATVEC, matvec_bytes(c, true), [&] { return launch_matvec(c.sp, z, c.k2, c.fld, vj, w, c.stream); }));
+            if (zf32)
+                HIP_TRY(timed(c, HELM_K_MATVEC, matvec_bytes(c, true) - 8.0 * c.n, [&] { return launch_matvec(c.sp, zf, c.k2, c.fld, vj, w, c.stream); }));
+            else
+                HIP_TRY(timed(c, HELM_K_MATVEC, matvec_bytes(c, true), [&] { return launch_matvec(c.sp, z, c.k2, c.fld, vj, w, c.stream); }));
             HIP_TRY(hipEventRecord(ev[4], c.stream));
             // classical Gram-Schmidt: V^H y and ||y||^2 in one pass
             ST_TRY(dots(c, k.V, j + 1, w, hv));
@@ -885,7 +926,9 @@ helm_status helm_gmres_solve(helm_ctx *ctx, const void *F_dev, void *x_dev, cons
         }
         for (int i = 0; i < kk; ++i) coef[i] = d2(yv[i]);
         HIP_TRY(hipEventRecord(ev[2], c.stream));
-        if (flex) {
+        if (zf32) {
+            HIP_TRY(timed(c, HELM_K_LINCOMB, 16.0 * c.n * 2 + 8.0 * c.n * kk, [&] { return launch_lincomb(x, x, make_double2(1.0, 0.0), k.Zf, k.ld, kk, coef.data(), n, c.stream); }));
+        } else if (flex) {
             HIP_TRY(timed(c, HELM_K_LINCOMB, 16.0 * c.n * (kk + 2), [&] { return launch_lincomb(x, x, make_double2(1.0, 0.0), k.Z, k.ld, kk, coef.data(), n, c.stream); }));
         } else {
             HIP_TRY(timed(c, HELM_K_LINCOMB, 16.0 * c.n * (kk + 1), [&] { return launch_lincomb(k.tmp, nullptr, make_double2(0.0, 0.0), k.V, k.ld, kk, coef.data(), n, c.stream); }));

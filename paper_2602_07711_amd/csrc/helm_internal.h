@@ -31,6 +31,9 @@ struct StencilParams {
     double h2;                   // h^2
     int zchunk;                  // z-planes per block
     int tiles_x, tiles_y, zchunks;
+    // complex k^2 (NULL for real k^2): imaginary parts of k^2 and of the order-6 field block
+    const double *k2i;
+    const double4 *fldi;
 };
 
 // Complex GEMM description: C[b] = A[b] * B[b], row-major, complex, strides in complex elements.
@@ -68,6 +71,8 @@ struct KrylovWork {
     int flexible = 0;
     double2 *V = nullptr;        // (m+1) * n
     double2 *Z = nullptr;        // m * n (flexible only)
+    float2 *Zf = nullptr;        // m * n complex64 instead of Z when the preconditioner runs in FP32: its outputs
+                                 // are FP32 values, so this storage is exact
     double2 *tmp = nullptr;      // n
     double2 *partials = nullptr; // nblocks * (m + 2)
     double2 *red = nullptr;      // m + 2 reduced values
@@ -92,6 +97,8 @@ struct Ctx {
     StencilParams sp{};
     double *k2 = nullptr;        // interior k^2 (n)
     double4 *fld = nullptr;      // order 6: (diag, g_x, g_y, g_z) per node
+    double *k2i = nullptr;       // complex k^2 only: imaginary parts of k^2 and of the field block
+    double4 *fldi = nullptr;
 
     // EigT data (complex, row-major N x N). x: transposed for the B operand, y: as is for the A operand.
     double2 *BxF = nullptr, *BxI = nullptr, *AyF = nullptr, *AyI = nullptr;
@@ -196,9 +203,15 @@ struct BOffsets {                 // prefix sums of blocks/tiles per problem for
 };
 
 // ----- kernel launchers (defined in the .hip files); all enqueue on `s` and return hipError_t -----
+// complex k^2 (complex128 samples with the same halo): real and imaginary parts into separate arrays
+hipError_t launch_derived_fields_c(const double2 *k2_halo, int halo, double *k2, double *k2i, double4 *fld,
+                                   double4 *fldi, const StencilParams &p, double h, hipStream_t s);
 hipError_t launch_derived_fields(const double *k2_halo, int halo, double *k2, double4 *fld, const StencilParams &p,
                                  double h, hipStream_t s);
 hipError_t launch_matvec(const StencilParams &p, const double2 *x, const double *k2, const double4 *fld,
+                         const double2 *F, double2 *y, hipStream_t s);
+// the same with a complex64 input (widened exactly to complex128 on load)
+hipError_t launch_matvec(const StencilParams &p, const float2 *x, const double *k2, const double4 *fld,
                          const double2 *F, double2 *y, hipStream_t s);   // F != nullptr: y = F - A x
 hipError_t launch_rhs(const StencilParams &p, const double2 *f_halo, const double *k2, const double4 *fld,
                       double h3[3], double2 *F, hipStream_t s);
@@ -244,6 +257,9 @@ int dots_blocks(long long n);
 hipError_t launch_dots(const double2 *V, long long ldv, int nv, const double2 *w, long long n, double2 *partials,
                        int nblocks, double2 *red, hipStream_t s);   // red[0..nv-1] = V_i^H w, red[nv] = (|w|^2, 0)
 hipError_t launch_lincomb(double2 *out, const double2 *base, double2 alpha, const double2 *V, long long ldv, int nv,
+                          const double2 *coef, long long n, hipStream_t s);
+// the same over complex64 vectors V (the complex64 Z basis of FGMRES with the FP32 preconditioner)
+hipError_t launch_lincomb(double2 *out, const double2 *base, double2 alpha, const float2 *V, long long ldv, int nv,
                           const double2 *coef, long long n, hipStream_t s);   // out = alpha base + sum coef_i V_i
 hipError_t launch_fill_zero(double2 *x, long long n, hipStream_t s);
 

@@ -307,7 +307,7 @@ __global__ __launch_bounds__(256) void k_b_lincomb(const BProb *__restrict__ P, 
 #pragma unroll
         for (int e = 0; e < BLC_EPT; ++e) {
             const long long idx = start + (long long)e * 256;
-            v[e] = ok[e] ? vi[idx] : make_double2(0.0, 0.0);
+            v[e] = ok[e] ? ld_stream(vi + idx) : make_double2(0.0, 0.0);
         }
 #pragma unroll
         for (int e = 0; e < BLC_EPT; ++e) {

@@ -39,8 +39,15 @@ constexpr int LC_MAX = 48;
 struct LcCoef { double2 c[LC_MAX]; };
 constexpr int LC_EPT = 4;   // elements per thread (independent loads in flight per vector)
 
+__device__ __forceinline__ double2 wide(const double2 *p) { return ld_stream(p); }
+__device__ __forceinline__ double2 wide(const float2 *p) {
+    const float2 v = *p;
+    return make_double2((double)v.x, (double)v.y);
+}
+
+template <typename VT>
 __global__ __launch_bounds__(256) void k_lincomb(double2 *out, const double2 *base, double2 alpha,
-                                                 const double2 *__restrict__ V, long long ldv, int nv, LcCoef co,
+                                                 const VT *__restrict__ V, long long ldv, int nv, LcCoef co,
                                                  long long n) {
     const long long start = (long long)blockIdx.x * (256 * LC_EPT) + threadIdx.x;
     double2 acc[LC_EPT];
@@ -51,7 +58,7 @@ __global__ __launch_bounds__(256) void k_lincomb(double2 *out, const double2 *ba
         ok[e] = idx < n;
         acc[e] = make_double2(0.0, 0.0);
         if (base && ok[e]) {
-            double2 b = base[idx];
+            double2 b = ld_stream(base + idx);
             acc[e].x = alpha.x * b.x - alpha.y * b.y;
             acc[e].y = alpha.x * b.y + alpha.y * b.x;
         }
@@ -64,7 +71,7 @@ __global__ __launch_bounds__(256) void k_lincomb(double2 *out, const double2 *ba
 #pragma unroll
             for (int e = 0; e < LC_EPT; ++e) {
                 const long long idx = start + (long long)e * 256;
-                v[q][e] = ok[e] ? V[(long long)(i + q) * ldv + idx] : make_double2(0.0, 0.0);
+                v[q][e] = ok[e] ? wide(V + (long long)(i + q) * ldv + idx) : make_double2(0.0, 0.0);
             }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -77,13 +84,13 @@ __global__ __launch_bounds__(256) void k_lincomb(double2 *out, const double2 *ba
         }
     }
     for (; i < nv; ++i) {
-        const double2 *vi = V + (long long)i * ldv;
+        const VT *vi = V + (long long)i * ldv;
         const double2 c = co.c[i];
         double2 v[LC_EPT];
 #pragma unroll
         for (int e = 0; e < LC_EPT; ++e) {
             const long long idx = start + (long long)e * 256;
-            v[e] = ok[e] ? vi[idx] : make_double2(0.0, 0.0);
+            v[e] = ok[e] ? wide(vi + idx) : make_double2(0.0, 0.0);
         }
 #pragma unroll
         for (int e = 0; e < LC_EPT; ++e) {
@@ -117,8 +124,9 @@ hipError_t launch_dots(const double2 *V, long long ldv, int nv, const double2 *w
     return hipGetLastError();
 }
 
-hipError_t launch_lincomb(double2 *out, const double2 *base, double2 alpha, const double2 *V, long long ldv, int nv,
-                          const double2 *coef, long long n, hipStream_t s) {
+template <typename VT>
+hipError_t lincomb_t(double2 *out, const double2 *base, double2 alpha, const VT *V, long long ldv, int nv,
+                     const double2 *coef, long long n, hipStream_t s) {
     long long grid_ll = (n + 256 * LC_EPT - 1) / (256 * LC_EPT);
     int grid = (int)(grid_ll < 1 ? 1 : grid_ll);
     int done = 0;
@@ -128,13 +136,23 @@ hipError_t launch_lincomb(double2 *out, const double2 *base, double2 alpha, cons
         for (int i = 0; i < cnt; ++i) co.c[i] = coef[done + i];
         const double2 *b = done == 0 ? base : out;
         double2 a = done == 0 ? alpha : make_double2(1.0, 0.0);
-        hipLaunchKernelGGL(k_lincomb, dim3(grid), dim3(256), 0, s, out, b, a, V + (long long)done * ldv, ldv, cnt, co,
-                           n);
+        hipLaunchKernelGGL(k_lincomb<VT>, dim3(grid), dim3(256), 0, s, out, b, a, V + (long long)done * ldv, ldv, cnt,
+                           co, n);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         done += cnt;
     } while (done < nv);
     return hipSuccess;
+}
+
+hipError_t launch_lincomb(double2 *out, const double2 *base, double2 alpha, const double2 *V, long long ldv, int nv,
+                          const double2 *coef, long long n, hipStream_t s) {
+    return lincomb_t<double2>(out, base, alpha, V, ldv, nv, coef, n, s);
+}
+
+hipError_t launch_lincomb(double2 *out, const double2 *base, double2 alpha, const float2 *V, long long ldv, int nv,
+                          const double2 *coef, long long n, hipStream_t s) {
+    return lincomb_t<float2>(out, base, alpha, V, ldv, nv, coef, n, s);
 }
 
 hipError_t launch_fill_zero(double2 *x, long long n, hipStream_t s) {

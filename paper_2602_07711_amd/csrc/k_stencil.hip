@@ -53,9 +53,46 @@ __global__ void k_derived(const double *__restrict__ k2h, int halo, double *__re
     fld[p] = make_double4(dg, h * g[0] / 120.0, h * g[1] / 120.0, h * g[2] / 120.0);
 }
 
+// complex k^2: the same differences on complex samples, real and imaginary parts stored separately
+__global__ void k_derived_c(const double2 *__restrict__ k2h, int halo, double *__restrict__ k2,
+                            double *__restrict__ k2i, double4 *__restrict__ fld, double4 *__restrict__ fldi, int nx,
+                            int ny, int nz, int order, double h, int *__restrict__ bad) {
+    long long n = (long long)nx * ny * nz;
+    long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    int i = (int)(p % nx);
+    int j = (int)((p / nx) % ny);
+    int l = (int)(p / ((long long)nx * ny));
+    const int px = nx + 2 * halo, py = ny + 2 * halo;
+    auto at = [&](int di, int dj, int dl) -> double2 {
+        return k2h[((long long)(l + halo + dl) * py + (j + halo + dj)) * px + (i + halo + di)];
+    };
+    const double2 c = at(0, 0, 0);
+    if (!isfinite(c.x) || !isfinite(c.y)) atomicOr(bad, 1);
+    k2[p] = c.x;
+    k2i[p] = c.y;
+    if (order != 6) return;
+    double2 g[3], lap = make_double2(0.0, 0.0);
+    for (int a = 0; a < 3; ++a) {
+        int dx = (a == 0), dy = (a == 1), dz = (a == 2);
+        double2 p1 = at(dx, dy, dz), m1 = at(-dx, -dy, -dz), p2 = at(2 * dx, 2 * dy, 2 * dz), m2 = at(-2 * dx, -2 * dy, -2 * dz);
+        if (!isfinite(p1.x + p1.y + m1.x + m1.y + p2.x + p2.y + m2.x + m2.y)) atomicOr(bad, 1);
+        g[a] = cscale(cadd(csub(m2, p2), cscale(csub(p1, m1), 8.0)), 1.0 / (12.0 * h));
+        lap = cadd(lap, cscale(cadd(cadd(cscale(cadd(p1, m1), 16.0), cscale(c, -30.0)), cscale(cadd(p2, m2), -1.0)),
+                               1.0 / (12.0 * h * h)));
+    }
+    const double h2 = h * h;
+    const double2 dg = cadd(make_double2(-64.0 / (15.0 * h2) + 14.0 / 15.0 * c.x, 14.0 / 15.0 * c.y),
+                            cscale(csub(lap, cmul(c, c)), h2 / 20.0));
+    fld[p] = make_double4(dg.x, h * g[0].x / 120.0, h * g[1].x / 120.0, h * g[2].x / 120.0);
+    fldi[p] = make_double4(dg.y, h * g[0].y / 120.0, h * g[1].y / 120.0, h * g[2].y / 120.0);
+}
+
 // --------------------------------------------------------------------------- right-hand side
+// k2i, fldi: imaginary parts for complex k^2 (NULL for real k^2)
 __global__ void k_rhs(const double2 *__restrict__ f, const double *__restrict__ k2, const double4 *__restrict__ fld,
-                      double2 *__restrict__ F, int nx, int ny, int nz, int order, double hx, double hy, double hz) {
+                      const double *__restrict__ k2i, const double4 *__restrict__ fldi, double2 *__restrict__ F,
+                      int nx, int ny, int nz, int order, double hx, double hy, double hz) {
     long long n = (long long)nx * ny * nz;
     long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
@@ -86,8 +123,9 @@ __global__ void k_rhs(const double2 *__restrict__ f, const double *__restrict__ 
     double h = hx, h2 = h * h;
     double2 out = c;
     out = cfma(h2 / 12.0, cadd(cadd(d2[0], d2[1]), d2[2]), out);
-    double4 fl = fld[p];
-    double gg[3] = {fl.y, fl.z, fl.w};
+    const double4 fl = fld[p];
+    const double4 fli = fldi ? fldi[p] : make_double4(0, 0, 0, 0);
+    const double2 gg[3] = {make_double2(fl.y, fli.y), make_double2(fl.z, fli.z), make_double2(fl.w, fli.w)};
     for (int a = 0; a < 3; ++a) {
         int dx = (a == 0), dy = (a == 1), dz = (a == 2);
         double2 p1 = at(dx, dy, dz), m1 = at(-dx, -dy, -dz);
@@ -95,7 +133,7 @@ __global__ void k_rhs(const double2 *__restrict__ f, const double *__restrict__ 
         double2 d4 = cadd(cadd(cadd(p2, m2), cscale(cadd(p1, m1), -4.0)), cscale(c, 6.0));
         out = cfma(-1.0 / 240.0, d4, out);                       // h^4/240 * delta^4 f (delta^4 carries 1/h^4)
         double2 d1 = csub(p1, m1);                               // 2 h delta f
-        out = cfma(h2 * gg[a], d1, out);                         // h^4/60 * (120 g/h) * d1/(2h) = h^2 g d1
+        out = cadd(out, cscale(cmul(gg[a], d1), h2));            // h^4/60 * (120 g/h) * d1/(2h) = h^2 g d1
     }
     const int pairs[3][2] = {{0, 1}, {0, 2}, {1, 2}};
     for (int q = 0; q < 3; ++q) {
@@ -110,15 +148,42 @@ __global__ void k_rhs(const double2 *__restrict__ f, const double *__restrict__ 
             }
         out = cfma(1.0 / 90.0, acc, out);                        // h^4/90 * P_h f (P_h carries 1/h^4)
     }
-    out = cfma(-h2 / 20.0 * k2[p], c, out);
+    const double2 kk = make_double2(k2[p], k2i ? k2i[p] : 0.0);
+    out = csub(out, cscale(cmul(kk, c), h2 / 20.0));
     F[p] = out;
 }
 
-template <int ORDER, bool RESID>
-__global__ __launch_bounds__(512) void k_matvec(const double2 *__restrict__ x, const double *__restrict__ k2,
+template <int ORDER, bool RESID, typename XT, bool KC>
+__global__ __launch_bounds__(512) void k_matvec(const XT *__restrict__ x, const double *__restrict__ k2,
                                                  const double4 *__restrict__ fld, const double2 *__restrict__ F,
                                                  double2 *__restrict__ y, StencilParams p) {
-    matvec_tile<ORDER, RESID>(x, k2, fld, F, y, p, blockIdx.x);
+    matvec_tile<ORDER, RESID, XT, KC>(x, k2, fld, F, y, p, blockIdx.x);
+}
+
+template <typename XT, bool KC>
+hipError_t launch_matvec_k(const StencilParams &p, const XT *x, const double *k2, const double4 *fld,
+                           const double2 *F, double2 *y, hipStream_t s) {
+    int T = p.tiles_x * p.tiles_y * p.zchunks;
+    int grid = 8 * ((T + 7) / 8);
+    dim3 blk(64, TY);
+    if (p.order == 6) {
+        if (F) hipLaunchKernelGGL((k_matvec<6, true, XT, KC>), dim3(grid), blk, 0, s, x, k2, fld, F, y, p);
+        else hipLaunchKernelGGL((k_matvec<6, false, XT, KC>), dim3(grid), blk, 0, s, x, k2, fld, F, y, p);
+    } else if (p.order == 4) {
+        if (F) hipLaunchKernelGGL((k_matvec<4, true, XT, KC>), dim3(grid), blk, 0, s, x, k2, fld, F, y, p);
+        else hipLaunchKernelGGL((k_matvec<4, false, XT, KC>), dim3(grid), blk, 0, s, x, k2, fld, F, y, p);
+    } else {
+        if (F) hipLaunchKernelGGL((k_matvec<2, true, XT, KC>), dim3(grid), blk, 0, s, x, k2, fld, F, y, p);
+        else hipLaunchKernelGGL((k_matvec<2, false, XT, KC>), dim3(grid), blk, 0, s, x, k2, fld, F, y, p);
+    }
+    return hipGetLastError();
+}
+
+template <typename XT>
+hipError_t launch_matvec_t(const StencilParams &p, const XT *x, const double *k2, const double4 *fld,
+                           const double2 *F, double2 *y, hipStream_t s) {
+    if (p.k2i) return launch_matvec_k<XT, true>(p, x, k2, fld, F, y, s);
+    return launch_matvec_k<XT, false>(p, x, k2, fld, F, y, s);
 }
 
 }  // namespace
@@ -143,30 +208,42 @@ hipError_t launch_derived_fields(const double *k2_halo, int halo, double *k2, do
     return hbad ? hipErrorInvalidValue : hipSuccess;
 }
 
+hipError_t launch_derived_fields_c(const double2 *k2_halo, int halo, double *k2, double *k2i, double4 *fld,
+                                   double4 *fldi, const StencilParams &p, double h, hipStream_t s) {
+    long long n = (long long)p.nx * p.ny * p.nz;
+    int *bad = nullptr;
+    hipError_t e = hipMalloc(&bad, sizeof(int));
+    if (e != hipSuccess) return e;
+    e = hipMemsetAsync(bad, 0, sizeof(int), s);
+    if (e != hipSuccess) { hipFree(bad); return e; }
+    int blocks = (int)((n + 255) / 256);
+    hipLaunchKernelGGL(k_derived_c, dim3(blocks), dim3(256), 0, s, k2_halo, halo, k2, k2i, fld, fldi, p.nx, p.ny, p.nz,
+                       p.order, h, bad);
+    e = hipGetLastError();
+    int hbad = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    hipFree(bad);
+    if (e != hipSuccess) return e;
+    return hbad ? hipErrorInvalidValue : hipSuccess;
+}
+
 hipError_t launch_matvec(const StencilParams &p, const double2 *x, const double *k2, const double4 *fld,
                          const double2 *F, double2 *y, hipStream_t s) {
-    int T = p.tiles_x * p.tiles_y * p.zchunks;
-    int grid = 8 * ((T + 7) / 8);
-    dim3 blk(64, TY);
-    if (p.order == 6) {
-        if (F) hipLaunchKernelGGL((k_matvec<6, true>), dim3(grid), blk, 0, s, x, k2, fld, F, y, p);
-        else hipLaunchKernelGGL((k_matvec<6, false>), dim3(grid), blk, 0, s, x, k2, fld, F, y, p);
-    } else if (p.order == 4) {
-        if (F) hipLaunchKernelGGL((k_matvec<4, true>), dim3(grid), blk, 0, s, x, k2, fld, F, y, p);
-        else hipLaunchKernelGGL((k_matvec<4, false>), dim3(grid), blk, 0, s, x, k2, fld, F, y, p);
-    } else {
-        if (F) hipLaunchKernelGGL((k_matvec<2, true>), dim3(grid), blk, 0, s, x, k2, fld, F, y, p);
-        else hipLaunchKernelGGL((k_matvec<2, false>), dim3(grid), blk, 0, s, x, k2, fld, F, y, p);
-    }
-    return hipGetLastError();
+    return launch_matvec_t<double2>(p, x, k2, fld, F, y, s);
+}
+
+hipError_t launch_matvec(const StencilParams &p, const float2 *x, const double *k2, const double4 *fld,
+                         const double2 *F, double2 *y, hipStream_t s) {
+    return launch_matvec_t<float2>(p, x, k2, fld, F, y, s);
 }
 
 hipError_t launch_rhs(const StencilParams &p, const double2 *f_halo, const double *k2, const double4 *fld,
                       double h3[3], double2 *F, hipStream_t s) {
     long long n = (long long)p.nx * p.ny * p.nz;
     int blocks = (int)((n + 255) / 256);
-    hipLaunchKernelGGL(k_rhs, dim3(blocks), dim3(256), 0, s, f_halo, k2, fld, F, p.nx, p.ny, p.nz, p.order, h3[0],
-                       h3[1], h3[2]);
+    hipLaunchKernelGGL(k_rhs, dim3(blocks), dim3(256), 0, s, f_halo, k2, fld, p.k2i, p.fldi, F, p.nx, p.ny, p.nz,
+                       p.order, h3[0], h3[1], h3[2]);
     return hipGetLastError();
 }
 

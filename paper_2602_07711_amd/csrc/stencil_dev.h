@@ -35,12 +35,30 @@ constexpr int TY = 8;          // tile height along y, one thread row each (bloc
 constexpr int LX = TX + 2;
 constexpr int LY = TY + 2;
 
-template <int ORDER, bool RESID>
-__device__ __forceinline__ void matvec_tile(const double2 *__restrict__ x, const double *__restrict__ k2,
+// k^2-valued quantities: double for real k^2, double2 for complex k^2
+__device__ __forceinline__ double2 kmul(double k, double2 u) { return cscale(u, k); }
+__device__ __forceinline__ double2 kmul(double2 k, double2 u) { return cmul(k, u); }
+__device__ __forceinline__ double2 kfma(double k, double2 u, double2 acc) { return cfma(k, u, acc); }
+__device__ __forceinline__ double2 kfma(double2 k, double2 u, double2 acc) { return cadd(acc, cmul(k, u)); }
+__device__ __forceinline__ double2 kfms(double k, double2 u, double2 acc) { return cfma(-k, u, acc); }        // acc - k u
+__device__ __forceinline__ double2 kfms(double2 k, double2 u, double2 acc) { return csub(acc, cmul(k, u)); }
+__device__ __forceinline__ double kaff(double a, double b, double k) { return a + b * k; }      // a + b k
+__device__ __forceinline__ double2 kaff(double a, double b, double2 k) { return make_double2(a + b * k.x, b * k.y); }
+struct F4C { double2 x, y, z, w; };          // complex order-6 field block (dg, g_x, g_y, g_z)
+
+__device__ __forceinline__ double2 to_d2(double2 v) { return v; }
+__device__ __forceinline__ double2 to_d2(float2 v) { return make_double2((double)v.x, (double)v.y); }
+
+// XT: the input's element type, complex128 or complex64 (the FP32 preconditioner's output, widened exactly).
+// KC: complex k^2 (imaginary parts in p.k2i and p.fldi); the arithmetic is the same with complex k^2 factors.
+template <int ORDER, bool RESID, typename XT = double2, bool KC = false>
+__device__ __forceinline__ void matvec_tile(const XT *__restrict__ x, const double *__restrict__ k2,
                                              const double4 *__restrict__ fld, const double2 *__restrict__ F,
                                              double2 *__restrict__ y, const StencilParams &p, int bid) {
+    typedef typename std::conditional<KC, double2, double>::type KT;
+    typedef typename std::conditional<KC, F4C, double4>::type FT;
     __shared__ double2 su[2][LY][LX];
-    __shared__ double sk[2][LY][LX];
+    __shared__ KT sk[2][LY][LX];
     const int T = p.tiles_x * p.tiles_y * p.zchunks;
     const int per = (T + 7) / 8;
     const int tile = (bid % 8) * per + bid / 8;   // consecutive tiles share an XCD (and its L2)
@@ -75,7 +93,7 @@ __device__ __forceinline__ void matvec_tile(const double2 *__restrict__ x, const
         fxy[q] = fac;
     }
     double2 ru[2][2];
-    double rk[2][2];
+    KT rk[2][2];
     auto gload = [&](auto setc, int z) {
         constexpr int S = decltype(setc)::value;
         const int cz = z < 0 ? 0 : (z >= nz ? nz - 1 : z);
@@ -83,8 +101,9 @@ __device__ __forceinline__ void matvec_tile(const double2 *__restrict__ x, const
         for (int q = 0; q < 2; ++q)
             if (tid + 512 * q < LX * LY) {
                 const long long idx = (long long)cz * plane + offs[q];
-                ru[S][q] = x[idx];
-                rk[S][q] = k2[idx];
+                ru[S][q] = to_d2(x[idx]);
+                if constexpr (KC) rk[S][q] = make_double2(k2[idx], p.k2i[idx]);
+                else rk[S][q] = k2[idx];
             }
     };
     auto sstore = [&](auto setc, int z) {
@@ -100,15 +119,22 @@ __device__ __forceinline__ void matvec_tile(const double2 *__restrict__ x, const
             }
         }
     };
-    auto fload = [&](int z) -> double4 {
-        return (ORDER == 6 && valid && z >= 0 && z < nz) ? fld[(long long)z * plane + col] : make_double4(0, 0, 0, 0);
+    auto fload = [&](int z) -> FT {
+        const bool in = ORDER == 6 && valid && z >= 0 && z < nz;
+        if constexpr (KC) {
+            const double4 a = in ? fld[(long long)z * plane + col] : make_double4(0, 0, 0, 0);
+            const double4 b = in ? p.fldi[(long long)z * plane + col] : make_double4(0, 0, 0, 0);
+            return F4C{make_double2(a.x, b.x), make_double2(a.y, b.y), make_double2(a.z, b.z), make_double2(a.w, b.w)};
+        } else {
+            return in ? fld[(long long)z * plane + col] : make_double4(0, 0, 0, 0);
+        }
     };
     auto Fload = [&](int z) -> double2 {
         return (RESID && valid && z >= 0 && z < nz) ? F[(long long)z * plane + col] : make_double2(0, 0);
     };
 
     // output coefficients for outputs p-1, p, p+1 (fm, f0, fp) and the prefetched p+2 (fn)
-    double4 fm = make_double4(0, 0, 0, 0), f0 = fload(z0 - 1), fp = fload(z0), fn;
+    FT fm = fload(-1), f0 = fload(z0 - 1), fp = fload(z0), fn;     // fload(-1) is the zero block
     double2 Fm = make_double2(0, 0), F0 = Fload(z0 - 1), Fn;
     double2 am = make_double2(0, 0), a0 = am, ap = am;
     gload(std::integral_constant<int, 0>(), z0 - 1);
@@ -125,29 +151,29 @@ __device__ __forceinline__ void matvec_tile(const double2 *__restrict__ x, const
             // the plane's 3 x 3 neighbourhood of this column (names: x then y offset, m = -1, p = +1)
             const double2 uc = su[b][ly][lx], uxm = su[b][ly][lx - 1], uxp = su[b][ly][lx + 1];
             const double2 uym = su[b][ly - 1][lx], uyp = su[b][ly + 1][lx];
-            const double kc = sk[b][ly][lx];
+            const KT kc = sk[b][ly][lx];
             const double2 Ef = cadd(cadd(uxm, uxp), cadd(uym, uyp));          // in-plane face neighbours
             if (ORDER == 6) {
                 const double2 umm = su[b][ly - 1][lx - 1], upm = su[b][ly - 1][lx + 1];
                 const double2 ump = su[b][ly + 1][lx - 1], upp = su[b][ly + 1][lx + 1];
-                const double kxm = sk[b][ly][lx - 1], kxp = sk[b][ly][lx + 1];
-                const double kym = sk[b][ly - 1][lx], kyp = sk[b][ly + 1][lx];
-                const double kmm = sk[b][ly - 1][lx - 1], kpm = sk[b][ly - 1][lx + 1];
-                const double kmp = sk[b][ly + 1][lx - 1], kpp = sk[b][ly + 1][lx + 1];
+                const KT kxm = sk[b][ly][lx - 1], kxp = sk[b][ly][lx + 1];
+                const KT kym = sk[b][ly - 1][lx], kyp = sk[b][ly + 1][lx];
+                const KT kmm = sk[b][ly - 1][lx - 1], kpm = sk[b][ly - 1][lx + 1];
+                const KT kmp = sk[b][ly + 1][lx - 1], kpp = sk[b][ly + 1][lx + 1];
                 const double2 C = cadd(cadd(umm, upm), cadd(ump, upp));       // in-plane diagonal neighbours
-                const double2 wxm = cscale(uxm, kxm), wxp = cscale(uxp, kxp);
-                const double2 wym = cscale(uym, kym), wyp = cscale(uyp, kyp);
+                const double2 wxm = kmul(kxm, uxm), wxp = kmul(kxp, uxp);
+                const double2 wym = kmul(kym, uym), wyp = kmul(kyp, uyp);
                 const double2 Ew = cadd(cadd(wxm, wxp), cadd(wym, wyp));
-                const double2 wc = cscale(uc, kc);
-                const double2 Cw = cadd(cadd(cscale(umm, kmm), cscale(upm, kpm)), cadd(cscale(ump, kmp), cscale(upp, kpp)));
+                const double2 wc = kmul(kc, uc);
+                const double2 Cw = cadd(cadd(kmul(kmm, umm), kmul(kpm, upm)), cadd(kmul(kmp, ump), kmul(kpp, upp)));
                 const double2 Dx = csub(uxp, uxm), Dy = csub(uyp, uym);
                 // role of an upper/lower plane (offsets (dx, dy, +-1)): centre = z-face, faces = xz/yz edges,
                 // diagonals = corners
                 double2 Piso = cfma(14.0 * p.c1, uc, cfma(3.0 * p.c1, Ef, cscale(C, p.c1)));
                 Piso = cfma(1.0 / 90.0, csub(Ew, wc), Piso);
                 const double2 Pz = cadd(cadd(cscale(uc, 2.0), cscale(wc, p.h2)), Ef);
-                am = cadd(am, cfma(fm.w, Pz, cfma(fm.y, Dx, cfma(fm.z, Dy, Piso))));
-                ap = cadd(ap, cfma(-fp.w, Pz, cfma(fp.y, Dx, cfma(fp.z, Dy, Piso))));
+                am = cadd(am, kfma(fm.w, Pz, kfma(fm.y, Dx, kfma(fm.z, Dy, Piso))));
+                ap = cadd(ap, kfms(fp.w, Pz, kfma(fp.y, Dx, kfma(fp.z, Dy, Piso))));
                 // role of the centre plane: centre, x/y faces, xy edges
                 double2 Qiso = cfma(14.0 * p.c1, Ef, cscale(C, 3.0 * p.c1));
                 Qiso = cfma(1.0 / 90.0, csub(Cw, Ew), Qiso);
@@ -155,19 +181,19 @@ __device__ __forceinline__ void matvec_tile(const double2 *__restrict__ x, const
                                         csub(cadd(upm, upp), cadd(umm, ump)));
                 const double2 Qy = cadd(cfma(2.0, Dy, cscale(csub(wyp, wym), p.h2)),
                                         csub(cadd(ump, upp), cadd(umm, upm)));
-                a0 = cadd(a0, cfma(f0.x, uc, cfma(f0.y, Qx, cfma(f0.z, Qy, Qiso))));
+                a0 = cadd(a0, kfma(f0.x, uc, kfma(f0.y, Qx, kfma(f0.z, Qy, Qiso))));
             } else {
                 const double2 Fx = cadd(uxm, uxp), Fy = cadd(uym, uyp);
                 double2 P = cscale(uc, p.c_face[2]);
-                double2 Q = cfma(p.c_face[0], Fx, cfma(p.c_face[1], Fy, cscale(uc, p.c_center + p.w_center * kc)));
+                double2 Q = cfma(p.c_face[0], Fx, cfma(p.c_face[1], Fy, kmul(kaff(p.c_center, p.w_center, kc), uc)));
                 if (ORDER == 4) {
-                    const double kxm = sk[b][ly][lx - 1], kxp = sk[b][ly][lx + 1];
-                    const double kym = sk[b][ly - 1][lx], kyp = sk[b][ly + 1][lx];
+                    const KT kxm = sk[b][ly][lx - 1], kxp = sk[b][ly][lx + 1];
+                    const KT kym = sk[b][ly - 1][lx], kyp = sk[b][ly + 1][lx];
                     const double2 C = cadd(cadd(su[b][ly - 1][lx - 1], su[b][ly - 1][lx + 1]),
                                            cadd(su[b][ly + 1][lx - 1], su[b][ly + 1][lx + 1]));
-                    const double2 Ew = cadd(cadd(cscale(uxm, kxm), cscale(uxp, kxp)),
-                                            cadd(cscale(uym, kym), cscale(uyp, kyp)));
-                    P = cfma(p.w_face * kc, uc, cfma(p.c_edge[1], Fx, cfma(p.c_edge[2], Fy, P)));
+                    const double2 Ew = cadd(cadd(kmul(kxm, uxm), kmul(kxp, uxp)),
+                                            cadd(kmul(kym, uym), kmul(kyp, uyp)));
+                    P = kfma(kaff(0.0, p.w_face, kc), uc, cfma(p.c_edge[1], Fx, cfma(p.c_edge[2], Fy, P)));
                     Q = cfma(p.w_face, Ew, cfma(p.c_edge[0], C, Q));
                 }
                 am = cadd(am, P);

@@ -61,6 +61,9 @@ def lib():
     L = ctypes.CDLL(LIB_PATH)
     L.helm_setup.argtypes = [POINTER(c_void_p), helm_grid, POINTER(c_double), c_void_p, c_int, c_int, helm_bc, c_void_p]
     L.helm_setup.restype = c_int
+    L.helm_setup_complex.argtypes = [POINTER(c_void_p), helm_grid, POINTER(c_double), c_void_p, c_int, c_int, helm_bc,
+                                     c_void_p]
+    L.helm_setup_complex.restype = c_int
     L.helm_rhs.argtypes = [c_void_p, c_void_p, c_void_p]
     L.helm_rhs.restype = c_int
     L.helm_matvec.argtypes = [c_void_p, c_void_p, c_void_p]
@@ -174,10 +177,12 @@ class Context:
 
 
 def helm_setup(k2: torch.Tensor, h, order: int, bc: str = "abc", k0: float = 0.0, shape=None) -> Context:
-    """Create a context from k^2 (float64 on the GPU). k2 has shape (Nz+4, Ny+4, Nx+4) (two-cell halo) or,
-    for order 2/4 only, (Nz, Ny, Nx); `shape` = (Nz, Ny, Nx) can be given to disambiguate."""
-    if not isinstance(k2, torch.Tensor) or not k2.is_cuda or k2.dtype != torch.float64 or not k2.is_contiguous():
-        raise ValueError("k2 must be a contiguous float64 GPU tensor")
+    """Create a context from k^2 (float64, or complex128 for an attenuating medium, on the GPU). k2 has shape
+    (Nz+4, Ny+4, Nx+4) (two-cell halo) or, for order 2/4 only, (Nz, Ny, Nx); `shape` = (Nz, Ny, Nx) can be given
+    to disambiguate."""
+    if (not isinstance(k2, torch.Tensor) or not k2.is_cuda or k2.dtype not in (torch.float64, torch.complex128)
+            or not k2.is_contiguous()):
+        raise ValueError("k2 must be a contiguous float64 or complex128 GPU tensor")
     if k2.dim() != 3:
         raise ValueError("k2 must be 3-D (z, y, x)")
     if shape is None:
@@ -192,8 +197,9 @@ def helm_setup(k2: torch.Tensor, h, order: int, bc: str = "abc", k0: float = 0.0
         raise ValueError(f"k2 shape {tuple(k2.shape)} does not match grid {shape} with halo 0 or 2")
     hh = (c_double * 3)(*(float(v) for v in (h if hasattr(h, "__len__") else (h, h, h))))
     ptr = c_void_p()
-    st = lib().helm_setup(byref(ptr), helm_grid(nx, ny, nz), hh, c_void_p(k2.data_ptr()), halo, int(order),
-                          helm_bc(_BC[bc], float(k0)), _stream_ptr())
+    fn = lib().helm_setup_complex if k2.dtype == torch.complex128 else lib().helm_setup
+    st = fn(byref(ptr), helm_grid(nx, ny, nz), hh, c_void_p(k2.data_ptr()), halo, int(order),
+            helm_bc(_BC[bc], float(k0)), _stream_ptr())
     if st != HELM_OK:
         raise HelmError(st, lib().helm_last_setup_error().decode())
     return Context(ptr, shape, tuple(hh), order, bc, k0, k2.device)

@@ -421,3 +421,65 @@ def test_fft2_solve_matches_oracle_gmres():
     assert abs(info["iters"] - ir["iters"]) <= 1
     assert info["iters"] > info_e["iters"]
     h.helm_destroy(ctx)
+
+
+@pytest.mark.parametrize("order", [2, 4, 6])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_matvec_rhs_parity_complex_k2(order, shape):
+    """helm_setup_complex: the same scheme with an attenuating medium k^2 = k_r + i k_i (Sec. 5.1 uses one):
+    matvec and right-hand side against the oracle's assembly with the complex k^2, to the real-k^2 bound."""
+    h = H()
+    h3 = _h3(shape, order)
+    k0 = 0.5 / h3[0]
+    kr_ = medium(shape, h3, k0, seed=13)
+    ki = 0.05 * medium(shape, h3, k0, seed=14)
+    k2 = kr_ + 1j * ki
+    ctx = h.helm_setup(dev(k2), h3, order, k0=k0, shape=shape)
+    n = int(np.prod(shape))
+    x = cvec(n, 5)
+    y = host(h.helm_matvec(ctx, dev(x)))
+    gs = tuple(op.gamma_abc(k0, hh) for hh in h3)
+    fields = op.derived_fields(k2, h3[0]) if order == 6 else None
+    A = op.A_kron(order, k2[2:-2, 2:-2, 2:-2], h3, gs, fields)
+    yr = A @ x
+    assert np.abs(y - yr).max() <= 1e-12 * np.abs(yr).max()
+    rng = np.random.default_rng(15)
+    f = rng.standard_normal(k2.shape) + 1j * rng.standard_normal(k2.shape)
+    F = host(h.helm_rhs(ctx, dev(f)))
+    Fr = op.rhs(order, f, h3, k2[2:-2, 2:-2, 2:-2], fields).ravel()
+    assert np.abs(F - Fr).max() <= 1e-12 * np.abs(Fr).max()
+    h.helm_destroy(ctx)
+
+
+def test_solve_scattering_40_matches_oracle():
+    """The single-inclusion scattering problem of Sec. 5.1 (complex k^2, staggered 40^3, sixth order): GPU FP64
+    GMRES(50) and FP32-EigT FGMRES(50) at rtol 1e-10 against the sparse LU solution of the oracle's system
+    (relative L2 <= 1e-8) and the oracle GMRES's iteration count (+-1)."""
+    h = H()
+    n = 40
+    w = synth.single_inclusion_problem(n)
+    ctx = h.helm_setup(dev(w["k2"]), w["h"], 6, k0=w["k0"])
+    F = h.helm_rhs(ctx, dev(w["f"]))
+    A, Fr = op.problem(6, w["k2"], w["f"], w["h"], w["k0"])
+    assert np.abs(host(F) - Fr).max() <= 1e-12 * np.abs(Fr).max()
+    xs = spla.splu(A.tocsc()).solve(Fr)
+    g = op.gamma_abc(w["k0"], w["h"])
+    e = pc.EigT((n, n, n), (w["h"],) * 3, w["k0"], (g, g, g))
+    _, ir = kr.gmres(lambda v: A @ v, e.solve, Fr, m=50, rtol=1e-10)
+    for kw in (dict(), dict(flexible=True, prec_fp32=True)):
+        x, info = h.helm_gmres_solve(ctx, F, m=50, rtol=1e-10, **kw)
+        rel = np.linalg.norm(host(x) - xs) / np.linalg.norm(xs)
+        print("scattering40", kw, info["iters"], ir["iters"], rel)
+        assert info["converged"] and rel <= 1e-8
+        assert abs(info["iters"] - ir["iters"]) <= 1
+    h.helm_destroy(ctx)
+
+
+def test_batch_rejects_complex_k2():
+    h = H()
+    n = 8
+    w = synth.single_inclusion_problem(n)
+    ctx = h.helm_setup(dev(w["k2"]), w["h"], 6, k0=w["k0"])
+    with pytest.raises(h.HelmError):
+        h.helm_batch_create([ctx])
+    h.helm_destroy(ctx)
