@@ -35,6 +35,20 @@ def M_dirichlet(shape, h3, k0: float) -> sp.csr_matrix:
     return M_matrix(shape, h3, k0, (0.0, 0.0, 0.0))
 
 
+def M_dirichlet_compact(shape, h3, k0: float, order: int) -> sp.csr_matrix:
+    """The comparison preconditioners FFT4 / FFT6 (Sec. 5.1): the fourth- / sixth-order compact operator of
+    eq. scheme4 / scheme6 with the constant background k0 (so every derivative of k^2 vanishes) and zero Dirichlet
+    values on all six faces (gamma = 0). Its inverse applied to y is the sparse LU solve of this matrix."""
+    from .operators import A_kron
+    nz, ny, nx = shape
+    k2 = np.full(shape, k0 * k0)
+    fields = None
+    if order == 6:
+        z = np.zeros(shape)
+        fields = (z, z, z, z)
+    return A_kron(order, k2, h3, (0.0, 0.0, 0.0), fields)
+
+
 def eig1d(n: int, gamma: complex, zeta: complex = 1.0):
     """Step 1 of eq. EIG_SOLVER: D, V, V^{-1} of Lambda-bar (numpy eig and inv). Returns (d, V, Vinv)."""
     Lb = lambda_bar(n, gamma, zeta).toarray()

@@ -294,6 +294,35 @@ def test_eigt_with_dirichlet_closures_inverts_fft2_matrix():
     assert np.linalg.norm(z - zs) <= 1e-11 * np.linalg.norm(zs)
 
 
+@pytest.mark.parametrize("order", [4, 6])
+def test_fft46_matrix_sine_modes_closed_form(order):
+    """FFT4 / FFT6's matrices (compact scheme, constant k0, gamma = 0) have the product sine modes as eigenvectors;
+    with t_a = (2 cos(pi p_a h_a) - 2)/h_a^2 the eigenvalue is the scheme's symbol:
+      order 4: sum t_a + sum_{a<b} (h_a^2 + h_b^2)/12 t_a t_b + k0^2 (1 + sum h_a^2/12 t_a);
+      order 6: (1 + h^2 k0^2/30) sum t_a + h^4/30 t_x t_y t_z + k0^2 + h^2/6 (1 + h^2 k0^2/15) sum_{a<b} t_a t_b
+               - h^2 k0^4/20."""
+    nz, ny, nx = (5, 7, 6) if order == 4 else (6, 6, 6)
+    h3 = (1.0 / (nx + 1), 1.0 / (ny + 1), 1.0 / (nz + 1))
+    k0 = 9.0
+    M = pc.M_dirichlet_compact((nz, ny, nx), h3, k0, order)
+    x = np.arange(1, nx + 1) * h3[0]
+    y = np.arange(1, ny + 1) * h3[1]
+    z = np.arange(1, nz + 1) * h3[2]
+    for p, q, r in [(1, 1, 1), (6, 2, 3), (3, 5, 5), (2, 6, 1)]:
+        u = (np.sin(np.pi * r * z)[:, None, None] * np.sin(np.pi * q * y)[None, :, None]
+             * np.sin(np.pi * p * x)[None, None, :]).ravel()
+        t = [(2 * np.cos(np.pi * m * hh) - 2) / hh ** 2 for m, hh in zip((p, q, r), h3)]
+        pairs = [(0, 1), (0, 2), (1, 2)]
+        if order == 4:
+            lam = (sum(t) + sum((h3[a] ** 2 + h3[b] ** 2) / 12 * t[a] * t[b] for a, b in pairs)
+                   + k0 ** 2 * (1 + sum(h3[a] ** 2 / 12 * t[a] for a in range(3))))
+        else:
+            h2, k2 = h3[0] ** 2, k0 ** 2
+            lam = ((1 + h2 * k2 / 30) * sum(t) + h2 * h2 / 30 * t[0] * t[1] * t[2] + k2
+                   + h2 / 6 * (1 + h2 * k2 / 15) * sum(t[a] * t[b] for a, b in pairs) - h2 * k2 * k2 / 20)
+        assert np.linalg.norm(M @ u - lam * u) <= 1e-12 * abs(lam) * np.linalg.norm(u)
+
+
 def test_fft2_matrix_sine_modes_closed_form():
     """FFT2's matrix (gamma = 0 on every axis) has the product sine modes sin(pi p x) sin(pi q y) sin(pi r z) as
     eigenvectors with eigenvalue sum_a (2 cos(pi p_a h_a) - 2) / h_a^2 + k0^2 (h_a = 1/(N_a + 1)); checked for
