@@ -70,10 +70,15 @@ typedef enum {
     HELM_PREC_EIGT = 0,    /* eigenvector transforms in x and y + z-tridiagonal solves (Sec. 4.1)            */
     HELM_PREC_PFFT = 1,    /* sine transforms + boundary correction on the x/y faces (Sec. 4.2)               */
     HELM_PREC_NONE = 2,    /* identity (unpreconditioned GMRES)                                              */
-    HELM_PREC_FFT2 = 3     /* the comparison preconditioner FFT2 of Sec. 5.1 (the earlier FFT-type approach
+    HELM_PREC_FFT2 = 3,    /* the comparison preconditioner FFT2 of Sec. 5.1 (the earlier FFT-type approach
                               recalled at the start of Sec. 4): the same 7-point operator with constant k0 but
                               zero Dirichlet closures on all six faces (gamma = 0 on every axis), inverted by
                               sine transforms in x and y and z-tridiagonal solves                            */
+    HELM_PREC_FFT4 = 4,    /* FFT4 of Sec. 5.1: the fourth-order compact operator (Sec. 2.2 eq. scheme4) with
+                              the constant k0 and zero Dirichlet closures, inverted by the 3D sine transform
+                              (sine-matrix GEMMs along x, y and z) and division by the scheme's symbol         */
+    HELM_PREC_FFT6 = 5     /* FFT6 of Sec. 5.1: the same with the sixth-order scheme (Sec. 2.3 eq. scheme6;
+                              needs h_x = h_y = h_z, HELM_EINVAL otherwise)                                   */
 } helm_prec_kind;
 
 typedef struct {
@@ -134,7 +139,8 @@ helm_status helm_rhs(helm_ctx *ctx, const void *f_dev, void *F_dev);
 helm_status helm_matvec(helm_ctx *ctx, const void *x_dev, void *y_dev);
 
 /* z = M^{-1} y with M = Delta_2 + k0^2 I (Sec. 4). kind: HELM_PREC_EIGT or HELM_PREC_PFFT (M with the
- * operator's absorbing closure), HELM_PREC_FFT2 (M with zero Dirichlet closures), HELM_PREC_NONE (z = y);
+ * operator's absorbing closure), HELM_PREC_FFT2 (M with zero Dirichlet closures), HELM_PREC_FFT4 / FFT6 (the
+ * compact operators with constant k0 and zero Dirichlet closures), HELM_PREC_NONE (z = y);
  * fp32: 1 runs the transforms and tridiagonal solves in complex FP32 (input read as FP64, output written as
  * FP64). y_dev, z_dev: n complex128; they may be the same buffer. PFFT requires N_x, N_y <= 256
  * (HELM_EUNSUPPORTED otherwise). */

@@ -225,6 +225,36 @@ helm_status ensure_sine(Ctx &c, bool fp32, bool ring) {
 
 helm_status ensure_pfft(Ctx &c, bool fp32) { return ensure_sine(c, fp32, true); }
 
+// FFT4 / FFT6: the z sine matrix and the 1D second-difference eigenvalues (2 cos(pi i/(N+1)) - 2)/h^2
+helm_status ensure_fftk(Ctx &c, bool fp32) {
+    ST_TRY(ensure_sine(c, fp32, false));
+    PfftPlan &P = *c.pfft;
+    if (!P.tx) {
+        const double pi = 3.14159265358979323846;
+        const int ns[3] = {c.nx, c.ny, c.nz};
+        const double hs[3] = {c.hx, c.hy, c.hz};
+        double **dst[3] = {&P.tx, &P.ty, &P.tz};
+        for (int a = 0; a < 3; ++a) {
+            std::vector<double> t(ns[a]);
+            for (int i = 0; i < ns[a]; ++i) t[i] = (2.0 * std::cos(pi * (i + 1) / (ns[a] + 1)) - 2.0) / (hs[a] * hs[a]);
+            ST_TRY(dalloc(c, dst[a], (size_t)ns[a]));
+            HIP_TRY(hipMemcpy(*dst[a], t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice));
+        }
+    }
+    if (!P.m64.Sz) ST_TRY(upload_one(c, sine_matrix(c.nz), c.nz, false, &P.m64.Sz));
+    if (fp32 && !P.m32.Sz) ST_TRY(upload_one(c, sine_matrix(c.nz), c.nz, false, &P.m32.Sz));
+    return HELM_OK;
+}
+
+// the z transform as one GEMM: C[l'][(j,i)] = sum_l S[l'][l] Y[l][(j,i)]
+GemmDesc desc_z(const Ctx &c) {
+    GemmDesc d{};
+    d.M = c.nz; d.N = c.nx * c.ny; d.K = c.nz;
+    d.lda = c.nz; d.ldb = (long long)c.nx * c.ny; d.ldc = (long long)c.nx * c.ny;
+    d.sA = d.sB = d.sC = 0; d.batch = 1;
+    return d;
+}
+
 helm_status pfft_apply(Ctx &c, const double2 *y, double2 *z, bool fp32, float2 *z32 = nullptr) {
     ST_TRY(ensure_pfft(c, fp32));
     ST_TRY(ensure_tpiv(c, c.dxe, c.dye, &c.tpiv_eig));
@@ -298,6 +328,47 @@ helm_status fft2_apply(Ctx &c, const double2 *y, double2 *z, bool fp32, float2 *
     return HELM_OK;
 }
 
+// FFT4 / FFT6 (the Dirichlet comparison preconditioners of Sec. 5.1 built on the compact schemes): the 3D sine
+// transform (x, y and z sine-matrix GEMMs), division by the operator's symbol, and the inverse transform (the
+// orthonormal sine matrices are their own inverses).
+helm_status fftk_apply(Ctx &c, const double2 *y, double2 *z, bool fp32, int order, float2 *z32 = nullptr) {
+    if (order == 6 && (std::fabs(c.hy - c.hx) > 1e-12 * c.hx || std::fabs(c.hz - c.hx) > 1e-12 * c.hx)) {
+        c.err = "FFT6 needs h_x = h_y = h_z";
+        return HELM_EINVAL;
+    }
+    ST_TRY(ensure_fftk(c, fp32));
+    PfftPlan &P = *c.pfft;
+    GemmDesc dx = desc_x(c), dy = desc_y(c), dz = desc_z(c);
+    SymParams q{};
+    q.order = order;
+    q.h2[0] = c.hx * c.hx; q.h2[1] = c.hy * c.hy; q.h2[2] = c.hz * c.hz;
+    q.k2 = c.k0 * c.k0;
+    const int nx = c.nx, ny = c.ny, nz = c.nz;
+    const double fx = 4.0 * dx.M * (double)dx.N * dx.K, fy = 4.0 * dy.M * (double)dy.N * dy.K * dy.batch,
+                 fz = 4.0 * dz.M * (double)dz.N * dz.K;
+    if (!fp32) {
+        auto &m = P.m64;
+        HIP_TRY(timed(c, HELM_K_PFFT, fx, [&] { return launch_gemm_z64(dx, y, m.Sx, c.t1, c.stream, 2); }));
+        HIP_TRY(timed(c, HELM_K_PFFT, fy, [&] { return launch_gemm_z64(dy, m.Sy, c.t1, c.t2, c.stream, 1); }));
+        HIP_TRY(timed(c, HELM_K_PFFT, fz, [&] { return launch_gemm_z64(dz, m.Sz, c.t2, c.t1, c.stream, 1); }));
+        HIP_TRY(launch_sym_divide_z64(c.t1, P.tx, P.ty, P.tz, nx, ny, nz, q, c.stream));
+        HIP_TRY(timed(c, HELM_K_PFFT, fz, [&] { return launch_gemm_z64(dz, m.Sz, c.t1, c.t2, c.stream, 1); }));
+        HIP_TRY(timed(c, HELM_K_PFFT, fy, [&] { return launch_gemm_z64(dy, m.Sy, c.t2, c.t1, c.stream, 1); }));
+        HIP_TRY(timed(c, HELM_K_PFFT, fx, [&] { return launch_gemm_z64(dx, c.t1, m.Sx, z, c.stream, 2); }));
+    } else {
+        ST_TRY(ensure_fp32_work(c));
+        auto &m = P.m32;
+        HIP_TRY(timed(c, HELM_K_PFFT, fx, [&] { return launch_gemm_z32_in64(dx, y, m.Sx, c.t1f, c.stream, 2); }));
+        HIP_TRY(timed(c, HELM_K_PFFT, fy, [&] { return launch_gemm_z32(dy, m.Sy, c.t1f, c.t2f, c.stream, 1); }));
+        HIP_TRY(timed(c, HELM_K_PFFT, fz, [&] { return launch_gemm_z32(dz, m.Sz, c.t2f, c.t1f, c.stream, 1); }));
+        HIP_TRY(launch_sym_divide_z32(c.t1f, P.tx, P.ty, P.tz, nx, ny, nz, q, c.stream));
+        HIP_TRY(timed(c, HELM_K_PFFT, fz, [&] { return launch_gemm_z32(dz, m.Sz, c.t1f, c.t2f, c.stream, 1); }));
+        HIP_TRY(timed(c, HELM_K_PFFT, fy, [&] { return launch_gemm_z32(dy, m.Sy, c.t2f, c.t1f, c.stream, 1); }));
+        HIP_TRY(timed(c, HELM_K_PFFT, fx, [&] { return z32 ? launch_gemm_z32(dx, c.t1f, m.Sx, z32, c.stream, 2) : launch_gemm_z32_out64(dx, c.t1f, m.Sx, z, c.stream, 2); }));
+    }
+    return HELM_OK;
+}
+
 helm_status precond(Ctx &c, const double2 *y, double2 *z, int kind, int fp32) {
     if (kind == HELM_PREC_EIGT) return eigt_apply(c, y, z, fp32 != 0);
     if (kind == HELM_PREC_NONE) {
@@ -306,6 +377,8 @@ helm_status precond(Ctx &c, const double2 *y, double2 *z, int kind, int fp32) {
     }
     if (kind == HELM_PREC_PFFT) return pfft_apply(c, y, z, fp32 != 0);
     if (kind == HELM_PREC_FFT2) return fft2_apply(c, y, z, fp32 != 0);
+    if (kind == HELM_PREC_FFT4) return fftk_apply(c, y, z, fp32 != 0, 4);
+    if (kind == HELM_PREC_FFT6) return fftk_apply(c, y, z, fp32 != 0, 6);
     c.err = "unknown preconditioner kind";
     return HELM_EINVAL;
 }
@@ -315,6 +388,8 @@ helm_status precond32(Ctx &c, const double2 *y, float2 *z, int kind) {
     if (kind == HELM_PREC_EIGT) return eigt_apply(c, y, nullptr, true, z);
     if (kind == HELM_PREC_PFFT) return pfft_apply(c, y, nullptr, true, z);
     if (kind == HELM_PREC_FFT2) return fft2_apply(c, y, nullptr, true, z);
+    if (kind == HELM_PREC_FFT4) return fftk_apply(c, y, nullptr, true, 4, z);
+    if (kind == HELM_PREC_FFT6) return fftk_apply(c, y, nullptr, true, 6, z);
     c.err = "no complex64 output for this preconditioner kind";
     return HELM_EINVAL;
 }
@@ -758,7 +833,7 @@ helm_status helm_gmres_solve(helm_ctx *ctx, const void *F_dev, void *x_dev, cons
         return HELM_EINVAL;
     }
     if (opts->prec != HELM_PREC_EIGT && opts->prec != HELM_PREC_PFFT && opts->prec != HELM_PREC_NONE &&
-        opts->prec != HELM_PREC_FFT2) {
+        opts->prec != HELM_PREC_FFT2 && opts->prec != HELM_PREC_FFT4 && opts->prec != HELM_PREC_FFT6) {
         c.err = "unknown preconditioner kind";
         return HELM_EINVAL;
     }

@@ -44,10 +44,22 @@ struct GemmDesc {
     int batch;
 };
 
+// symbol of the compact operators with constant k0 (FFT4 / FFT6): order, h_a^2 per axis, k0^2
+struct SymParams {
+    int order;
+    double h2[3];
+    double k2;
+};
+hipError_t launch_sym_divide_z64(double2 *u, const double *tx, const double *ty, const double *tz, int nx, int ny,
+                                 int nz, const SymParams &q, hipStream_t s);
+hipError_t launch_sym_divide_z32(float2 *u, const double *tx, const double *ty, const double *tz, int nx, int ny,
+                                 int nz, const SymParams &q, hipStream_t s);
+
 // PFFT second path (Sec. 4.2): sine matrices, Dirichlet eigenvalues, the plain/transposed eigenvector
 // matrices the thin ring transforms need, and work buffers. FP64 and FP32 copies.
 template <typename CT> struct PfftMats {
     CT *Sx = nullptr, *Sy = nullptr;             // orthonormal sine matrices (symmetric; imaginary part 0)
+    CT *Sz = nullptr;                            // the same along z (FFT4 / FFT6 only)
     CT *Vxi = nullptr, *Vx = nullptr;            // V_x^{-1}, V_x row-major (the transposes are BxF, BxI)
     CT *VyiT = nullptr, *VyT = nullptr;          // transposes of V_y^{-1}, V_y (the plain ones are AyF, AyI)
     CT *yhat = nullptr;                          // sine transform of the input (reused in step 3)
@@ -57,6 +69,7 @@ template <typename CT> struct PfftMats {
 };
 struct PfftPlan {
     double2 *dFx = nullptr, *dFy = nullptr;      // Dirichlet eigenvalues 2 cos(pi i/(N+1))
+    double *tx = nullptr, *ty = nullptr, *tz = nullptr;   // (2 cos(pi i/(N+1)) - 2) / h^2 per axis (FFT4 / FFT6)
     PfftMats<double2> m64;
     PfftMats<float2> m32;
 };

@@ -224,7 +224,54 @@ hipError_t fwd_launch(const typename c2<T>::t *ra, const typename c2<T>::t *rb, 
     return hipGetLastError();
 }
 
+// FFT4 / FFT6 (the compact operators with constant k0 and Dirichlet closures): after the 3D sine transform every
+// mode (p, q, r) is an eigenvector; divide by the scheme's symbol in t_a = (2 cos(pi p_a h_a) - 2) / h_a^2:
+//   order 4: sum t + sum_{a<b} (h_a^2 + h_b^2)/12 t_a t_b + k0^2 (1 + sum h_a^2/12 t_a)   (eq. scheme4)
+//   order 6: (1 + h^2 k0^2/30) sum t + h^4/30 t_x t_y t_z + k0^2 + h^2/6 (1 + h^2 k0^2/15) sum_{a<b} t_a t_b
+//            - h^2 k0^4/20                                                                (eq. scheme6, uniform h)
+template <typename T>
+__global__ __launch_bounds__(256) void k_sym_divide(typename c2<T>::t *__restrict__ u, const double *__restrict__ tx,
+                                                    const double *__restrict__ ty, const double *__restrict__ tz,
+                                                    int nx, int ny, int nz, SymParams q) {
+    const long long n = (long long)nx * ny * nz;
+    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const int i = (int)(p % nx), j = (int)((p / nx) % ny), l = (int)(p / ((long long)nx * ny));
+    const double a = tx[i], b = ty[j], c = tz[l];
+    const double s1 = a + b + c, s2 = a * b + a * c + b * c;
+    double lam;
+    if (q.order == 4) {
+        lam = s1 + (q.h2[0] + q.h2[1]) / 12.0 * a * b + (q.h2[0] + q.h2[2]) / 12.0 * a * c +
+              (q.h2[1] + q.h2[2]) / 12.0 * b * c + q.k2 * (1.0 + (q.h2[0] * a + q.h2[1] * b + q.h2[2] * c) / 12.0);
+    } else {
+        const double h2 = q.h2[0];
+        lam = (1.0 + h2 * q.k2 / 30.0) * s1 + h2 * h2 / 30.0 * a * b * c + q.k2 + h2 / 6.0 * (1.0 + h2 * q.k2 / 15.0) * s2 -
+              h2 * q.k2 * q.k2 / 20.0;
+    }
+    const T r = (T)(1.0 / lam);
+    typename c2<T>::t v = u[p];
+    v.x *= r;
+    v.y *= r;
+    u[p] = v;
+}
+
 }  // namespace
+
+hipError_t launch_sym_divide_z64(double2 *u, const double *tx, const double *ty, const double *tz, int nx, int ny,
+                                 int nz, const SymParams &q, hipStream_t s) {
+    const long long n = (long long)nx * ny * nz;
+    hipLaunchKernelGGL(k_sym_divide<double>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, u, tx, ty, tz, nx, ny,
+                       nz, q);
+    return hipGetLastError();
+}
+
+hipError_t launch_sym_divide_z32(float2 *u, const double *tx, const double *ty, const double *tz, int nx, int ny,
+                                 int nz, const SymParams &q, hipStream_t s) {
+    const long long n = (long long)nx * ny * nz;
+    hipLaunchKernelGGL(k_sym_divide<float>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, u, tx, ty, tz, nx, ny,
+                       nz, q);
+    return hipGetLastError();
+}
 
 int ring_rowgroups() { return RING_RG; }
 

@@ -19,8 +19,9 @@ HELM_OK, HELM_EINVAL, HELM_ENOMEM, HELM_EDEVICE, HELM_ENOCONV, HELM_EBREAKDOWN, 
 STATUS_NAMES = ["HELM_OK", "HELM_EINVAL", "HELM_ENOMEM", "HELM_EDEVICE", "HELM_ENOCONV", "HELM_EBREAKDOWN",
                 "HELM_ENUMERIC", "HELM_EUNSUPPORTED"]
 BC_ABC2, BC_DIRICHLET = 0, 1
-PREC_EIGT, PREC_PFFT, PREC_NONE, PREC_FFT2 = 0, 1, 2, 3
-_PREC = {"eigt": PREC_EIGT, "pfft": PREC_PFFT, "none": PREC_NONE, "fft2": PREC_FFT2}
+PREC_EIGT, PREC_PFFT, PREC_NONE, PREC_FFT2, PREC_FFT4, PREC_FFT6 = 0, 1, 2, 3, 4, 5
+_PREC = {"eigt": PREC_EIGT, "pfft": PREC_PFFT, "none": PREC_NONE, "fft2": PREC_FFT2, "fft4": PREC_FFT4,
+         "fft6": PREC_FFT6}
 _BC = {"abc": BC_ABC2, "dirichlet": BC_DIRICHLET}
 
 

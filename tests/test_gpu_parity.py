@@ -483,3 +483,56 @@ def test_batch_rejects_complex_k2():
     with pytest.raises(h.HelmError):
         h.helm_batch_create([ctx])
     h.helm_destroy(ctx)
+
+
+def _fftk_symbol(shape, h3, k0, order):
+    """Eigenvalues of FFT4 / FFT6's matrix on the product sine modes (the closed form pinned on the CPU)."""
+    nz, ny, nx = shape
+    t = [(2 * np.cos(np.pi * np.arange(1, nn + 1) / (nn + 1)) - 2) / hh ** 2 for nn, hh in zip((nx, ny, nz), h3)]
+    a, b, c = t[0][None, None, :], t[1][None, :, None], t[2][:, None, None]
+    s1, s2 = a + b + c, a * b + a * c + b * c
+    if order == 4:
+        hx2, hy2, hz2 = (hh ** 2 for hh in h3)
+        return (s1 + (hx2 + hy2) / 12 * a * b + (hx2 + hz2) / 12 * a * c + (hy2 + hz2) / 12 * b * c
+                + k0 ** 2 * (1 + (hx2 * a + hy2 * b + hz2 * c) / 12))
+    h2, k2 = h3[0] ** 2, k0 ** 2
+    return (1 + h2 * k2 / 30) * s1 + h2 * h2 / 30 * a * b * c + k2 + h2 / 6 * (1 + h2 * k2 / 15) * s2 - h2 * k2 * k2 / 20
+
+
+@pytest.mark.parametrize("order", [4, 6])
+@pytest.mark.parametrize("fp32", [False, True])
+def test_fft46_precond_parity(order, fp32):
+    """FFT4 / FFT6 (compact operators, constant k0, Dirichlet closures; Sec. 5.1) against the sparse LU of the
+    oracle's matrix on a 10 x 12 x 14 box (uniform h for both orders). The 3D sine transform is orthonormal, so the
+    error is the symbol's conditioning times the rounding: bound 100 kappa u (u = 1.1e-16 / 6e-8), kappa from the
+    closed-form eigenvalues. Also ||M z - y|| on a 40^3 grid (no LU there)."""
+    h = H()
+    shape = (10, 12, 14)
+    hh = 1.0 / 15
+    h3 = (hh, hh, hh)
+    k0 = 0.47 / hh
+    lam = np.abs(_fftk_symbol(shape, h3, k0, order))
+    kappa = lam.max() / lam.min()
+    u = 6e-8 if fp32 else 1.1e-16
+    k2 = np.full(tuple(s + 4 for s in shape), k0 * k0)
+    ctx = h.helm_setup(dev(k2), h3, order, k0=k0, shape=shape)
+    y = cvec(int(np.prod(shape)), 9)
+    M = pc.M_dirichlet_compact(shape, h3, k0, order)
+    zr = spla.splu(M.tocsc()).solve(y)
+    z = host(h.helm_precond_apply(ctx, dev(y), kind=f"fft{order}", fp32=fp32))
+    err = np.linalg.norm(z - zr) / np.linalg.norm(zr)
+    print(f"fft{order} fp32={fp32} rel err {err:.3e} kappa {kappa:.1f} bound {100 * kappa * u:.2e}")
+    assert err <= 100 * kappa * u
+    h.helm_destroy(ctx)
+    n = 40
+    hh = 1.0 / (n + 1)
+    k0 = 0.47 / hh
+    ctx = h.helm_setup(dev(np.full((n + 4,) * 3, k0 * k0)), hh, order, k0=k0)
+    y = cvec(n ** 3, 10)
+    z = host(h.helm_precond_apply(ctx, dev(y), kind=f"fft{order}", fp32=fp32))
+    M = pc.M_dirichlet_compact((n, n, n), (hh,) * 3, k0, order)
+    lam = np.abs(_fftk_symbol((n, n, n), (hh,) * 3, k0, order))
+    res = np.linalg.norm(M @ z - y) / np.linalg.norm(y)
+    print(f"fft{order} 40^3 residual {res:.3e}")
+    assert res <= 100 * (lam.max() / lam.min()) * u
+    h.helm_destroy(ctx)
