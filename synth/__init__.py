@@ -14,5 +14,6 @@ from .media import (  # noqa: F401
     warmstart_problem,
     staggered_coords,
     single_inclusion_problem,
+    paper_test_problem,
     workload,
 )

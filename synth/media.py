@@ -128,6 +128,22 @@ def single_inclusion_problem(n: int, k2_in: complex = 1050 + 2.26j, k0sq: float 
     return dict(n=n, h=1.0 / n, k0=k0, k2=k2, f=f)
 
 
+def paper_test_problem(n: int, k0sq: float = 439.2):
+    """The 3D test problem of Sec. 5.1 on the staggered N^3 grid (h = 1/N): u = phi(x) phi(y) phi(z) with
+    phi(t) = exp(i k0 t) + exp(-i k0 (t - 1)) - 2 (it satisfies the absorbing condition on every face),
+    f = Delta u + k0^2 u in closed form, constant k^2 = k0^2. Returns dict(n, h, k0, k2, f, u) on the halo grid
+    (u also on the halo grid)."""
+    k0 = float(np.sqrt(k0sq))
+    c = staggered_coords(n)
+    e1, e2 = np.exp(1j * k0 * c), np.exp(-1j * k0 * (c - 1.0))
+    ph, p2 = e1 + e2 - 2.0, -k0sq * (e1 + e2)
+    Z, Y, X = (slice(None), None, None), (None, slice(None), None), (None, None, slice(None))
+    u = ph[Z] * ph[Y] * ph[X]
+    f = p2[Z] * ph[Y] * ph[X] + ph[Z] * p2[Y] * ph[X] + ph[Z] * ph[Y] * p2[X] + k0sq * u
+    return dict(n=n, h=1.0 / n, k0=k0, k2=np.full(u.shape, k0sq), f=f.astype(np.complex128),
+                u=u.astype(np.complex128))
+
+
 def workload(name: str, n: int | None = None):
     """The named synthetic workloads. Returns dict(n, h, order, k0, k2 (halo), f (halo), m, ...).
 
