@@ -60,3 +60,40 @@ def test_tables34_iteration_comparison(order):
             assert it["ffth"] >= 0.85 * it["fft2"]                         # the higher order helps only marginally
     fft = [r[1]["fft2"] for r in rows]
     assert fft[-1] > 2 * fft[0]                                             # the Dirichlet count grows with N
+
+
+def test_table5_wavenumber_sweep():
+    """The paper's Table 5: the test problem with k0 = k in {10, 20, 50, 100} on 100^3 ... 511^3, sixth order, the
+    absorbing-closure preconditioner (EigT; PFFT too for N <= 256, which must take the same number of iterations).
+    Checked: every count at most the printed one (the preconditioner here carries exactly the operator's closure),
+    counts non-increasing in N for every k and non-decreasing in k for every N."""
+    import paper_2602_07711_amd as H
+    H.lib()
+    with open(os.path.join(os.path.dirname(__file__), "golden", "table5_wavenumbers.json")) as fh:
+        g = json.load(fh)
+    ks = g["k"]
+    dev = torch.device("cuda")
+    got = {}
+    for row in g["rows"]:
+        n = row[0]
+        for k, n0 in zip(ks, row[1:]):
+            w = synth.paper_test_problem(n, k0sq=float(k * k))
+            ctx = H.helm_setup(torch.from_numpy(w["k2"]).to(dev), w["h"], 6, k0=w["k0"])
+            F = H.helm_rhs(ctx, torch.from_numpy(w["f"]).to(dev))
+            del w
+            x = torch.empty_like(F)
+            its = []
+            for prec in (["eigt", "pfft"] if n <= 256 else ["eigt"]):
+                _, info = H.helm_gmres_solve(ctx, F, x, m=50, maxit=300, rtol=1e-8, x0_given=False, prec=prec)
+                its.append(info["iters"])
+            print(f"table5 N={n} k={k}: {its} (paper {n0})", flush=True)
+            assert len(set(its)) == 1 and its[0] <= n0
+            got[(n, k)] = its[0]
+            H.helm_destroy(ctx)
+            del F, x
+            torch.cuda.empty_cache()
+    ns = [r[0] for r in g["rows"]]
+    for k in ks:
+        assert all(got[(b, k)] <= got[(a, k)] for a, b in zip(ns, ns[1:]))
+    for n in ns:
+        assert all(got[(n, b)] >= got[(n, a)] for a, b in zip(ks, ks[1:]))
