@@ -60,7 +60,8 @@ hipError_t launch_chunk(const typename c2<T>::t *in, typename c2<T>::t *out, con
                         double scale, hipStream_t s) {
     const int P = (nz + TL - 1) / TL;
     if (P > 1024) return hipErrorInvalidValue;
-    int LX = 16;
+    // 16 lines per block (256 B per row access) for complex128, 32 for complex64 (measured 10% faster at 256^3)
+    int LX = sizeof(T) == 4 ? 32 : 16;
     while (LX > 1 && LX * P > 1024) LX /= 2;
     const long long lines = (long long)nx * ny;
     const unsigned grid = (unsigned)((lines + LX - 1) / LX);
