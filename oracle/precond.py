@@ -9,7 +9,8 @@ scale (reading: the library solves M z = y, i.e. A_p z = h_z^2 y).
 
 Readings: the diagonal of the decoupled z-systems is a_x d_x,i + a_y d_y,j + h_z^2 k0^2 - 2(a_x + a_y + 1)
 (eq. DIAGprec; the unscaled d_x,i + d_y,j printed under eq. Indep_precond_system agrees when a = 1);
-zeta = 1 (staggered two-point closure) on every axis.
+zeta = 1 (staggered two-point closure) on every axis; zeta = 2 (the three-point closure of collocated grids, the
+boundary nodes being unknowns, gamma = 2 i k0 h) for EigT as a direct solver (M_collocated).
 """
 from __future__ import annotations
 
@@ -25,6 +26,16 @@ def M_matrix(shape, h3, k0: float, gammas) -> sp.csr_matrix:
     nz, ny, nx = shape
     ns = (nx, ny, nz)
     M = sum(_lift(shape, d2_1d(ns[a], h3[a], gammas[a]), a) for a in range(3))
+    return (M + k0 * k0 * sp.identity(nx * ny * nz, np.complex128)).tocsr()
+
+
+def M_collocated(shape, h3, k0: float, gammas, zeta: complex = 2.0) -> sp.csr_matrix:
+    """The second-order operator with the three-point closure of collocated grids (Sec. 4.1: Lambda-bar with
+    corners gamma and zeta = 2, the boundary nodes being unknowns): sum_a (Lambda-bar_a - 2I)/h_a^2 + k0^2 I."""
+    nz, ny, nx = shape
+    ns = (nx, ny, nz)
+    M = sum(_lift(shape, ((lambda_bar(ns[a], gammas[a], zeta) - 2.0 * sp.identity(ns[a], np.complex128))
+                          / (h3[a] * h3[a])).tocsr(), a) for a in range(3))
     return (M + k0 * k0 * sp.identity(nx * ny * nz, np.complex128)).tocsr()
 
 
@@ -56,22 +67,25 @@ def eig1d(n: int, gamma: complex, zeta: complex = 1.0):
     return d, V, np.linalg.inv(V)
 
 
-def thomas(bbar: np.ndarray, gz: complex, r: np.ndarray) -> np.ndarray:
-    """Solve, for every line (j, i) at once, the z-systems of eq. Indep_precond_system with zeta_z = 1:
-        (gz + b) u_1 + u_2 = r_1,  u_{l-1} + b u_l + u_{l+1} = r_l,  u_{N-1} + (gz + b) u_N = r_N.
-    bbar has shape (Ny, Nx); r has shape (Nz, Ny, Nx). Plain Thomas elimination without pivoting."""
+def thomas(bbar: np.ndarray, gz: complex, r: np.ndarray, zeta: complex = 1.0) -> np.ndarray:
+    """Solve, for every line (j, i) at once, the z-systems of eq. Indep_precond_system:
+        (gz + b) u_1 + zeta u_2 = r_1,  u_{l-1} + b u_l + u_{l+1} = r_l,  zeta u_{N-1} + (gz + b) u_N = r_N.
+    bbar has shape (Ny, Nx); r has shape (Nz, Ny, Nx). Plain Thomas elimination without pivoting on the
+    tridiagonal with sub-diagonal a_l, diagonal d_l and super-diagonal c_l."""
     nz = r.shape[0]
     cp = np.empty_like(r)
     dp = np.empty_like(r)
     for l in range(nz):
-        diag = bbar + (gz if (l == 0 or l == nz - 1) else 0.0)
+        d = bbar + (gz if (l == 0 or l == nz - 1) else 0.0)
+        c = zeta if l == 0 else 1.0                     # super-diagonal of row l
+        a = zeta if l == nz - 1 else 1.0                # sub-diagonal of row l
         if l == 0:
-            p = diag
+            p = d
             dp[0] = r[0] / p
         else:
-            p = diag - cp[l - 1]
-            dp[l] = (r[l] - dp[l - 1]) / p
-        cp[l] = 1.0 / p
+            p = d - a * cp[l - 1]
+            dp[l] = (r[l] - a * dp[l - 1]) / p
+        cp[l] = c / p
     u = np.empty_like(r)
     u[-1] = dp[-1]
     for l in range(nz - 2, -1, -1):
@@ -82,15 +96,16 @@ def thomas(bbar: np.ndarray, gz: complex, r: np.ndarray) -> np.ndarray:
 class EigT:
     """The EigT direct solver of M z = y (Sec. 4.1, eq. EIG_SOLVER)."""
 
-    def __init__(self, shape, h3, k0: float, gammas):
+    def __init__(self, shape, h3, k0: float, gammas, zeta: complex = 1.0):
         self.shape = shape
         nz, ny, nx = shape
         hx, hy, hz = h3
         self.ax, self.ay = hz * hz / (hx * hx), hz * hz / (hy * hy)
         self.hz2 = hz * hz
         self.gz = gammas[2]
-        self.dx, self.Vx, self.Vxi = eig1d(nx, gammas[0])       # Step 1
-        self.dy, self.Vy, self.Vyi = eig1d(ny, gammas[1])
+        self.zeta = zeta
+        self.dx, self.Vx, self.Vxi = eig1d(nx, gammas[0], zeta)       # Step 1
+        self.dy, self.Vy, self.Vyi = eig1d(ny, gammas[1], zeta)
         self.bbar = (self.ax * self.dx[None, :] + self.ay * self.dy[:, None] + hz * hz * k0 * k0
                      - 2.0 * (self.ax + self.ay + 1.0))
 
@@ -105,7 +120,7 @@ class EigT:
     def solve(self, y: np.ndarray) -> np.ndarray:
         Y = y.reshape(self.shape)
         Yb = self.forward(Y)
-        Ub = thomas(self.bbar, self.gz, self.hz2 * Yb)  # Step 3 (A_p z = h_z^2 y)
+        Ub = thomas(self.bbar, self.gz, self.hz2 * Yb, self.zeta)  # Step 3 (A_p z = h_z^2 y)
         return self.inverse(Ub).ravel()
 
 

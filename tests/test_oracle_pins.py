@@ -348,6 +348,45 @@ def test_fft2_matrix_sine_modes_closed_form():
         assert l in (0, nz - 1) or j in (0, ny - 1) or i in (0, nx - 1)
 
 
+def test_eigt_collocated_zeta2_inverts_its_matrix():
+    """EigT with zeta = 2 (the collocated three-point closure, gamma = 2 i k0 h) equals the sparse LU solve of the
+    collocated second-order matrix, on a box with three different N and h."""
+    shape = (9, 11, 13)
+    h3 = (1.0 / 12, 1.0 / 10, 1.0 / 8)
+    k0 = 7.0
+    gs = tuple(2j * k0 * hh for hh in h3)
+    rng = np.random.default_rng(12)
+    y = rng.standard_normal(np.prod(shape)) + 1j * rng.standard_normal(np.prod(shape))
+    M = pc.M_collocated(shape, h3, k0, gs)
+    z = pc.EigT(shape, h3, k0, gs, zeta=2.0).solve(y)
+    zs = spla.splu(M.tocsc()).solve(y)
+    assert np.linalg.norm(z - zs) <= 1e-11 * np.linalg.norm(zs)
+    assert np.linalg.norm(M @ z - y) <= 1e-11 * np.linalg.norm(y)
+
+
+def _collocated_test_error(n):
+    """The Sec. 5.1 test problem on the collocated grid x_j = j h, j = 0..N-1, h = 1/(N-1) (boundary nodes are
+    unknowns): the second-order system with the three-point closure solved by EigT(zeta = 2)."""
+    k0 = np.sqrt(439.2)
+    h = 1.0 / (n - 1)
+    x = np.arange(n) * h
+    X, Y, Z = x[None, None, :], x[None, :, None], x[:, None, None]
+    ph = lambda t: np.exp(1j * k0 * t) + np.exp(-1j * k0 * (t - 1.0)) - 2
+    p2 = lambda t: -k0 * k0 * (np.exp(1j * k0 * t) + np.exp(-1j * k0 * (t - 1.0)))
+    u = ph(X) * ph(Y) * ph(Z)
+    f = p2(X) * ph(Y) * ph(Z) + ph(X) * p2(Y) * ph(Z) + ph(X) * ph(Y) * p2(Z) + k0 * k0 * u
+    g = 2j * k0 * h
+    U = pc.EigT((n, n, n), (h, h, h), k0, (g, g, g), zeta=2.0).solve(f.ravel()).reshape(u.shape)
+    return np.linalg.norm(U - u) / np.linalg.norm(u)
+
+
+def test_collocated_closure_second_order():
+    """The three-point closure (central difference of u_n + i k0 u = 0 at the boundary node) makes the collocated
+    second-order solution converge at O(h^2) to the analytic test solution, which satisfies that condition."""
+    e1, e2 = _collocated_test_error(33), _collocated_test_error(65)
+    assert 1.8 < np.log2(e1 / e2) < 2.3
+
+
 # ------------------------------------------------------------------------------------------- GMRES
 
 def _small_problem(order=6, n=14, k0=None):
