@@ -222,7 +222,8 @@ def bench_direct_sweep(H, torch, dev, sizes):
     """The paper's Table 2 workload: the preconditioner as a direct solver of the second-order system of the
     Sec. 5.1 test problem (u = phi(x) phi(y) phi(z), k0^2 = 439.2, staggered nodes, two-point absorbing closure).
     Per grid: setup time, the direct-solve time of EigT (FP64/FP32) and PFFT (FP64/FP32, N <= 256) on the solve
-    stream (mean of 3 after one untimed call), and max-err / L2-err of the FP64 EigT solution against u."""
+    stream (mean of 3 after one untimed call), and max-err / L2-err of the FP64 EigT solution against u; then the
+    same for EigT with the collocated three-point closure (EigT3) on the nodes j/(N-1)."""
     import math
     k0 = math.sqrt(439.2)
     rows = []
@@ -258,6 +259,32 @@ def bench_direct_sweep(H, torch, dev, sizes):
                     row["max_err"] = float(d.abs().max())
                     row["l2_err"] = float(torch.linalg.vector_norm(d) / torch.linalg.vector_norm(u))
                     del d
+        # the collocated three-point closure (EigT3): the same test problem on the nodes j/(N-1), j = 0..N-1
+        xc = (torch.arange(n, dtype=torch.float64, device=dev) / (n - 1)).to(torch.complex128)
+        e1, e2 = torch.exp(1j * k0 * xc), torch.exp(-1j * k0 * (xc - 1.0))
+        ph, p2 = e1 + e2 - 2, -k0 * k0 * (e1 + e2)
+        u.copy_(ph[:, None, None] * ph[None, :, None] * ph[None, None, :])
+        f.copy_(p2[:, None, None] * ph[None, :, None] * ph[None, None, :])
+        f += ph[:, None, None] * p2[None, :, None] * ph[None, None, :]
+        f += ph[:, None, None] * ph[None, :, None] * p2[None, None, :]
+        f += k0 * k0 * u
+        H.helm_destroy(ctx)
+        k2 = torch.full((n, n, n), k0 * k0, dtype=torch.float64, device=dev)
+        ctx = H.helm_setup(k2, 1.0 / (n - 1), 2, "abc3", k0, shape=(n, n, n))
+        del k2
+        for fp32 in (False, True):
+            H.helm_precond_apply(ctx, fv, z, kind="eigt", fp32=fp32)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(3):
+                H.helm_precond_apply(ctx, fv, z, kind="eigt", fp32=fp32)
+            torch.cuda.synchronize()
+            row[f"eigt3_{'fp32' if fp32 else 'fp64'}_ms"] = round((time.perf_counter() - t0) / 3 * 1e3, 3)
+            if not fp32:
+                d = z.view(n, n, n) - u
+                row["eigt3_max_err"] = float(d.abs().max())
+                row["eigt3_l2_err"] = float(torch.linalg.vector_norm(d) / torch.linalg.vector_norm(u))
+                del d
         log(f"direct solve {n}^3: {row}")
         rows.append(row)
         H.helm_destroy(ctx)

@@ -57,7 +57,14 @@ typedef struct { int nx, ny, nz; } helm_grid;   /* unknowns per axis, each >= 3 
 
 typedef enum {
     HELM_BC_ABC2 = 0,      /* two-point absorbing closure, gamma = (2 + i k0 h)/(2 - i k0 h), zeta = 1 (Sec. 2.3) */
-    HELM_BC_DIRICHLET = 1  /* gamma = 0: zero ghost values                                                     */
+    HELM_BC_DIRICHLET = 1, /* gamma = 0: zero ghost values                                                     */
+    HELM_BC_ABC3 = 2       /* the three-point closure of collocated grids (Sec. 4.1, zeta = 2): the boundary
+                              nodes are unknowns and the central difference of u_n + i k0 u = 0 eliminates the
+                              ghost, so Lambda-bar has gamma = 2 i k0 h and zeta = 2 in its corners. Direct
+                              solves of the second-order system only (helm_precond_apply with HELM_PREC_EIGT,
+                              the EigT3 of Table 2); the paper does not give the high-order closures of its
+                              collocated runs, so helm_rhs, helm_matvec, helm_gmres_solve, helm_scale_guess,
+                              PFFT and batches return HELM_EUNSUPPORTED for such contexts                   */
 } helm_bc_kind;
 
 typedef struct {
@@ -257,6 +264,11 @@ void helm_destroy(helm_ctx *ctx);
  * Lambda-bar = V diag(d) V^{-1}. n >= 2; gamma as (re, im). Outputs are host arrays of complex128 (re, im):
  * d[n], V[n*n] and Vinv[n*n] in row-major order. Returns HELM_ENUMERIC if the residual checks fail. */
 helm_status helm_eig1d(int n, double gamma_re, double gamma_im, double *d, double *V, double *Vinv);
+
+/* The same with a corner off-diagonal zeta > 0 (eq. lambda_mat_definition; zeta = 2 for the collocated
+ * three-point closure): Lambda-bar has zeta at (1, 2) and (N, N-1). Exported for tests. */
+helm_status helm_eig1d_zeta(int n, double gamma_re, double gamma_im, double zeta, double *d, double *V,
+                            double *Vinv);
 
 /* ---------------------------------------------------------------------------------------------------------
  * Learned warm start: a 3D encoder-decoder CNN that maps (contrast, source) sampled on an S^3 grid to an

@@ -99,14 +99,15 @@ GemmDesc desc_y(const Ctx &c) {
 }
 
 // pivots entering each z-chunk of the partitioned tridiagonal solve, per set of x-y eigenvalues and z closure
-helm_status ensure_tpiv(Ctx &c, const double2 *dx, const double2 *dy, double2 **piv, double2 gz) {
+helm_status ensure_tpiv(Ctx &c, const double2 *dx, const double2 *dy, double2 **piv, double2 gz, double zi = 1.0) {
     if (*piv) return HELM_OK;
     ST_TRY(dalloc(c, piv, (size_t)tri_chunks(c.nz) * c.nx * c.ny));
-    HIP_TRY(launch_tri_pivots(dx, dy, c.nx, c.ny, c.nz, c.ax, c.ay, c.c0, gz, *piv, c.stream));
+    HIP_TRY(launch_tri_pivots(dx, dy, c.nx, c.ny, c.nz, c.ax, c.ay, c.c0, gz, *piv, c.stream, zi));
     return HELM_OK;
 }
+// the operator's own closure (gamma_z and, for the collocated closure, zeta)
 helm_status ensure_tpiv(Ctx &c, const double2 *dx, const double2 *dy, double2 **piv) {
-    return ensure_tpiv(c, dx, dy, piv, d2(c.gamma[2]));
+    return ensure_tpiv(c, dx, dy, piv, d2(c.gamma[2]), 1.0 / c.zeta);
 }
 
 helm_status ensure_fp32_work(Ctx &c) {
@@ -125,7 +126,7 @@ helm_status eigt_apply(Ctx &c, const double2 *y, double2 *z, bool fp32, float2 *
         HIP_TRY(timed(c, HELM_K_GEMM_X64, gemm_flops(dx), [&] { return launch_gemm_z64(dx, y, c.BxF, c.t1, c.stream, 0, c.gemm_cfg[0]); }));
         HIP_TRY(timed(c, HELM_K_GEMM_Y64, gemm_flops(dy), [&] { return launch_gemm_z64(dy, c.AyF, c.t1, c.t2, c.stream, 0, c.gemm_cfg[1]); }));
         ST_TRY(ensure_tpiv(c, c.dxe, c.dye, &c.tpiv_eig));
-        HIP_TRY(timed(c, HELM_K_TRIDIAG64, 32.0 * c.n, [&] { return launch_tridiag_chunk_z64(c.t2, c.t2, c.tpiv_eig, c.dxe, c.dye, c.nx, c.ny, c.nz, c.ax, c.ay, c.c0, gz, scale, c.stream); }));
+        HIP_TRY(timed(c, HELM_K_TRIDIAG64, 32.0 * c.n, [&] { return launch_tridiag_chunk_z64(c.t2, c.t2, c.tpiv_eig, c.dxe, c.dye, c.nx, c.ny, c.nz, c.ax, c.ay, c.c0, gz, scale, c.stream, 1.0 / c.zeta); }));
         HIP_TRY(timed(c, HELM_K_GEMM_Y64, gemm_flops(dy), [&] { return launch_gemm_z64(dy, c.AyI, c.t2, c.t1, c.stream, 0, c.gemm_cfg[1]); }));
         HIP_TRY(timed(c, HELM_K_GEMM_X64, gemm_flops(dx), [&] { return launch_gemm_z64(dx, c.t1, c.BxI, z, c.stream, 0, c.gemm_cfg[0]); }));
     } else {
@@ -133,7 +134,7 @@ helm_status eigt_apply(Ctx &c, const double2 *y, double2 *z, bool fp32, float2 *
         HIP_TRY(timed(c, HELM_K_GEMM_X32, gemm_flops(dx), [&] { return launch_gemm_z32_in64(dx, y, c.BxF32, c.t1f, c.stream, 0, c.gemm_cfg[2]); }));
         HIP_TRY(timed(c, HELM_K_GEMM_Y32, gemm_flops(dy), [&] { return launch_gemm_z32(dy, c.AyF32, c.t1f, c.t2f, c.stream, 0, c.gemm_cfg[3]); }));
         ST_TRY(ensure_tpiv(c, c.dxe, c.dye, &c.tpiv_eig));
-        HIP_TRY(timed(c, HELM_K_TRIDIAG32, 16.0 * c.n, [&] { return launch_tridiag_chunk_z32(c.t2f, c.t2f, c.tpiv_eig, c.dxe, c.dye, c.nx, c.ny, c.nz, c.ax, c.ay, c.c0, gz, scale, c.stream); }));
+        HIP_TRY(timed(c, HELM_K_TRIDIAG32, 16.0 * c.n, [&] { return launch_tridiag_chunk_z32(c.t2f, c.t2f, c.tpiv_eig, c.dxe, c.dye, c.nx, c.ny, c.nz, c.ax, c.ay, c.c0, gz, scale, c.stream, 1.0 / c.zeta); }));
         HIP_TRY(timed(c, HELM_K_GEMM_Y32, gemm_flops(dy), [&] { return launch_gemm_z32(dy, c.AyI32, c.t2f, c.t1f, c.stream, 0, c.gemm_cfg[3]); }));
         HIP_TRY(timed(c, HELM_K_GEMM_X32, gemm_flops(dx), [&] { return z32 ? launch_gemm_z32(dx, c.t1f, c.BxI32, z32, c.stream, 0, c.gemm_cfg[2]) : launch_gemm_z32_out64(dx, c.t1f, c.BxI32, z, c.stream, 0, c.gemm_cfg[2]); }));
     }
@@ -256,6 +257,10 @@ GemmDesc desc_z(const Ctx &c) {
 }
 
 helm_status pfft_apply(Ctx &c, const double2 *y, double2 *z, bool fp32, float2 *z32 = nullptr) {
+    if (c.bc_kind == HELM_BC_ABC3) {
+        c.err = "PFFT is built for the two-point closure (zeta = 1) only";
+        return HELM_EUNSUPPORTED;
+    }
     ST_TRY(ensure_pfft(c, fp32));
     ST_TRY(ensure_tpiv(c, c.dxe, c.dye, &c.tpiv_eig));
     ST_TRY(ensure_tpiv(c, c.pfft->dFx, c.pfft->dFy, &c.tpiv_dir));
@@ -492,10 +497,15 @@ helm_status helm_profile_read(helm_ctx *ctx, int cls, double *ms_total, long lon
 }
 
 helm_status helm_eig1d(int n, double gamma_re, double gamma_im, double *d, double *V, double *Vinv) {
-    if (n < 2 || !d || !V || !Vinv) return HELM_EINVAL;
+    return helm_eig1d_zeta(n, gamma_re, gamma_im, 1.0, d, V, Vinv);
+}
+
+helm_status helm_eig1d_zeta(int n, double gamma_re, double gamma_im, double zeta, double *d, double *V,
+                            double *Vinv) {
+    if (n < 2 || !d || !V || !Vinv || !(zeta > 0.0)) return HELM_EINVAL;
     std::vector<cd> dd, VV, VI;
     std::string err;
-    if (!eig_lambda_bar(n, cd(gamma_re, gamma_im), dd, VV, VI, err)) return HELM_ENUMERIC;
+    if (!eig_lambda_bar(n, cd(gamma_re, gamma_im), dd, VV, VI, err, zeta)) return HELM_ENUMERIC;
     for (int i = 0; i < n; ++i) { d[2 * i] = dd[i].real(); d[2 * i + 1] = dd[i].imag(); }
     for (size_t i = 0; i < (size_t)n * n; ++i) {
         V[2 * i] = VV[i].real(); V[2 * i + 1] = VV[i].imag();
@@ -546,7 +556,8 @@ helm_status setup_impl(helm_ctx **out, helm_grid g, const double h[3], const voi
     if (k2_halo != 0 && k2_halo != 2) return fail(HELM_EINVAL, "k2_halo must be 0 or 2");
     if (order == 6 && k2_halo != 2) return fail(HELM_EINVAL, "order 6 needs k^2 with a two-cell halo");
     if (!k2_dev) return fail(HELM_EINVAL, "k2_dev is NULL");
-    if (bc.kind != HELM_BC_ABC2 && bc.kind != HELM_BC_DIRICHLET) return fail(HELM_EINVAL, "unknown bc kind");
+    if (bc.kind != HELM_BC_ABC2 && bc.kind != HELM_BC_DIRICHLET && bc.kind != HELM_BC_ABC3)
+        return fail(HELM_EINVAL, "unknown bc kind");
     if (!(bc.k0 >= 0.0) || !std::isfinite(bc.k0)) return fail(HELM_EINVAL, "k0 must be finite and >= 0");
 
     helm_ctx *ctx = new helm_ctx();
@@ -559,9 +570,11 @@ helm_status setup_impl(helm_ctx **out, helm_grid g, const double h[3], const voi
     c.k0 = bc.k0;
     c.stream = (hipStream_t)stream;
     hipGetDevice(&c.device);
+    c.zeta = bc.kind == HELM_BC_ABC3 ? 2.0 : 1.0;
     for (int a = 0; a < 3; ++a) {
         double ha = h[a];
-        c.gamma[a] = bc.kind == HELM_BC_ABC2 ? cd(2.0, bc.k0 * ha) / cd(2.0, -bc.k0 * ha) : cd(0.0, 0.0);
+        c.gamma[a] = bc.kind == HELM_BC_ABC2 ? cd(2.0, bc.k0 * ha) / cd(2.0, -bc.k0 * ha)
+                   : bc.kind == HELM_BC_ABC3 ? cd(0.0, 2.0 * bc.k0 * ha) : cd(0.0, 0.0);
     }
 
     auto bail = [&](helm_status s) {
@@ -625,9 +638,9 @@ helm_status setup_impl(helm_ctx **out, helm_grid g, const double h[3], const voi
 
     // EigT Step 1: 1D eigen-decompositions of Lambda-bar_x and Lambda-bar_y
     std::vector<cd> dxv, Vx, Vxi, dyv, Vy, Vyi;
-    if (!eig_lambda_bar(c.nx, c.gamma[0], dxv, Vx, Vxi, c.err)) return bail(HELM_ENUMERIC);
+    if (!eig_lambda_bar(c.nx, c.gamma[0], dxv, Vx, Vxi, c.err, c.zeta)) return bail(HELM_ENUMERIC);
     if (c.ny == c.nx && c.gamma[1] == c.gamma[0]) { dyv = dxv; Vy = Vx; Vyi = Vxi; }
-    else if (!eig_lambda_bar(c.ny, c.gamma[1], dyv, Vy, Vyi, c.err)) return bail(HELM_ENUMERIC);
+    else if (!eig_lambda_bar(c.ny, c.gamma[1], dyv, Vy, Vyi, c.err, c.zeta)) return bail(HELM_ENUMERIC);
     c.hVx = Vx; c.hVxi = Vxi; c.hVy = Vy; c.hVyi = Vyi;
     // x-transform uses the transposed matrices as the B operand; y-transform uses them as the A operand
     if ((st = upload_matrix(c, Vxi, c.nx, true, &c.BxF, &c.BxF32)) != HELM_OK) return bail(st);
@@ -762,6 +775,10 @@ helm_status helm_gemm_config(helm_ctx *ctx, int kind, int cfg) {
 helm_status helm_rhs(helm_ctx *ctx, const void *f_dev, void *F_dev) {
     if (!ctx) return HELM_EINVAL;
     Ctx &c = ctx->c;
+    if (c.bc_kind == HELM_BC_ABC3) {
+        c.err = "the collocated three-point closure supports direct solves with the EigT preconditioner only";
+        return HELM_EUNSUPPORTED;
+    }
     if (!f_dev || !F_dev) { c.err = "NULL pointer"; return HELM_EINVAL; }
     double h3[3] = {c.hx, c.hy, c.hz};
     HIP_TRY(launch_rhs(c.sp, (const double2 *)f_dev, c.k2, c.fld, h3, (double2 *)F_dev, c.stream));
@@ -771,6 +788,10 @@ helm_status helm_rhs(helm_ctx *ctx, const void *f_dev, void *F_dev) {
 helm_status helm_matvec(helm_ctx *ctx, const void *x_dev, void *y_dev) {
     if (!ctx) return HELM_EINVAL;
     Ctx &c = ctx->c;
+    if (c.bc_kind == HELM_BC_ABC3) {
+        c.err = "the collocated three-point closure supports direct solves with the EigT preconditioner only";
+        return HELM_EUNSUPPORTED;
+    }
     if (!x_dev || !y_dev) { c.err = "NULL pointer"; return HELM_EINVAL; }
     if (x_dev == y_dev) { c.err = "matvec input and output must not overlap"; return HELM_EINVAL; }
     HIP_TRY(timed(c, HELM_K_MATVEC, matvec_bytes(c, false), [&] { return launch_matvec(c.sp, (const double2 *)x_dev, c.k2, c.fld, nullptr, (double2 *)y_dev, c.stream); }));
@@ -780,6 +801,10 @@ helm_status helm_matvec(helm_ctx *ctx, const void *x_dev, void *y_dev) {
 helm_status helm_scale_guess(helm_ctx *ctx, const void *F_dev, void *x_dev, double *alpha_re, double *alpha_im) {
     if (!ctx) return HELM_EINVAL;
     Ctx &c = ctx->c;
+    if (c.bc_kind == HELM_BC_ABC3) {
+        c.err = "the collocated three-point closure supports direct solves with the EigT preconditioner only";
+        return HELM_EUNSUPPORTED;
+    }
     if (!F_dev || !x_dev) { c.err = "NULL pointer"; return HELM_EINVAL; }
     const int nb = dots_blocks(c.n);
     if (!c.sg_y) {
@@ -823,6 +848,10 @@ helm_status helm_gmres_solve(helm_ctx *ctx, const void *F_dev, void *x_dev, cons
                              helm_solve_info *info) {
     if (!ctx) return HELM_EINVAL;
     Ctx &c = ctx->c;
+    if (c.bc_kind == HELM_BC_ABC3) {
+        c.err = "the collocated three-point closure supports direct solves with the EigT preconditioner only";
+        return HELM_EUNSUPPORTED;
+    }
     if (!F_dev || !x_dev || !opts) { c.err = "NULL pointer"; return HELM_EINVAL; }
     const int m = opts->m;
     if (m < 1 || m > 256) { c.err = "restart length m must be in 1..256"; return HELM_EINVAL; }

@@ -73,6 +73,7 @@ helm_status helm_batch_create(helm_batch **out, helm_ctx *const *ctxs, int np, i
         if (ctxs[p]->c.order != order) { g_batch_err = "all problems of a batch need the same order"; return HELM_EINVAL; }
         if (ctxs[p]->c.device != dev) { g_batch_err = "all contexts must live on the current device"; return HELM_EINVAL; }
         if (ctxs[p]->c.k2i) { g_batch_err = "batched solves take real k^2 only"; return HELM_EUNSUPPORTED; }
+        if (ctxs[p]->c.bc_kind == HELM_BC_ABC3) { g_batch_err = "batched solves take the two-point closure"; return HELM_EUNSUPPORTED; }
     }
     helm_batch *b = new helm_batch();
     b->ctxs.assign(ctxs, ctxs + np);

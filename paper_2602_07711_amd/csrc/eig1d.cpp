@@ -1,7 +1,9 @@
 // Host 1D eigen-decomposition of Lambda-bar (EigT Step 1, Sec. 4.1 eq. EIG_SOLVER; matrix of eq.
-// lambda_mat_definition with zeta = 1): the N x N tridiagonal with zero diagonal, unit off-diagonals and
-// gamma in both corners. Lambda-bar is complex symmetric but not Hermitian, so the decomposition is
-// Lambda-bar = V diag(d) V^{-1} with a non-unitary V.
+// lambda_mat_definition): the N x N tridiagonal with zero diagonal, unit off-diagonals, gamma in both corners
+// and zeta in the corner off-diagonals (row 1 column 2 and row N column N-1). With S = diag(sqrt(zeta), 1, ...,
+// 1, sqrt(zeta)), B = S^{-1} Lambda-bar S is complex symmetric (sqrt(zeta) on both corner off-diagonals); B is
+// decomposed as W diag(d) W^{-1} and Lambda-bar = (S W) diag(d) (W^{-1} S^{-1}). For zeta = 1, S = I. B is
+// complex symmetric but not Hermitian, so W is non-unitary.
 //
 //   1. eigenvalues: shifted QR iteration (Wilkinson shift, unitary Givens rotations) on the dense upper
 //      Hessenberg copy of the matrix, with deflation on small subdiagonal entries;
@@ -178,12 +180,16 @@ bool invert(std::vector<cd> &A, int n) {
 }  // namespace
 
 bool eig_lambda_bar(int n, cd gamma, std::vector<cd> &d, std::vector<cd> &V, std::vector<cd> &Vinv,
-                    std::string &err) {
+                    std::string &err, double zeta) {
     if (n < 2) { err = "eig1d: n must be >= 2"; return false; }
-    // tridiagonal entries of Lambda-bar
+    if (!(zeta > 0.0)) { err = "eig1d: zeta must be positive"; return false; }
+    // tridiagonal entries of the symmetrised B
+    const double sz = std::sqrt(zeta);
     std::vector<cd> lo(n - 1, 1.0), up(n - 1, 1.0), di(n, 0.0);
     di[0] += gamma;
     di[n - 1] += gamma;
+    lo[0] = up[0] = sz;
+    lo[n - 2] = up[n - 2] = sz;
     std::vector<cd> H((size_t)n * n, 0.0);
     for (int i = 0; i < n; ++i) {
         H[(size_t)i * n + i] = di[i];
@@ -200,7 +206,7 @@ bool eig_lambda_bar(int n, cd gamma, std::vector<cd> &d, std::vector<cd> &V, std
             y[i] = s;
         }
     };
-    const double anorm = 2.0 + std::abs(gamma);
+    const double anorm = 2.0 * sz + std::abs(gamma);
     const double tiny = 1e-300 + anorm * 1e-18;
     V.assign((size_t)n * n, 0.0);
     d.assign(n, 0.0);
@@ -244,6 +250,14 @@ bool eig_lambda_bar(int n, cd gamma, std::vector<cd> &d, std::vector<cd> &V, std
         }
     }
     if (!(ortho <= 1e-9)) { err = "eig1d: V^{-1} V differs from I"; return false; }
+    if (zeta != 1.0) {              // V = S W, V^{-1} = W^{-1} S^{-1}
+        for (int k = 0; k < n; ++k) {
+            V[k] *= sz;
+            V[(size_t)(n - 1) * n + k] *= sz;
+            Vinv[(size_t)k * n] /= sz;
+            Vinv[(size_t)k * n + n - 1] /= sz;
+        }
+    }
     return true;
 }
 

@@ -14,7 +14,7 @@ namespace helm {
 using cd = std::complex<double>;
 
 bool eig_lambda_bar(int n, cd gamma, std::vector<cd> &d, std::vector<cd> &V, std::vector<cd> &Vinv,
-                    std::string &err);
+                    std::string &err, double zeta = 1.0);
 
 // Stencil coefficients that depend only on the grid (the k^2-dependent parts are per node).
 struct StencilParams {
@@ -103,6 +103,7 @@ struct Ctx {
     int bc_kind;
     double k0;
     cd gamma[3];
+    double zeta = 1.0;           // corner off-diagonal of Lambda-bar (2 for the collocated closure)
     hipStream_t stream = nullptr;
     int device = 0;
     std::string err;
@@ -244,13 +245,13 @@ hipError_t launch_gemm_z32_out64(const GemmDesc &d, const float2 *A, const float
 // `in` (may equal r) supplies the right-hand side; the solution is written to r.
 int tri_chunks(int nz);
 hipError_t launch_tri_pivots(const double2 *dx, const double2 *dy, int nx, int ny, int nz, double ax, double ay,
-                             double c0, double2 gz, double2 *piv, hipStream_t s);
+                             double c0, double2 gz, double2 *piv, hipStream_t s, double zi = 1.0);
 hipError_t launch_tridiag_chunk_z64(const double2 *in, double2 *out, const double2 *piv, const double2 *dx,
                                     const double2 *dy, int nx, int ny, int nz, double ax, double ay, double c0,
-                                    double2 gz, double scale, hipStream_t s);
+                                    double2 gz, double scale, hipStream_t s, double zi = 1.0);
 hipError_t launch_tridiag_chunk_z32(const float2 *in, float2 *out, const double2 *piv, const double2 *dx,
                                     const double2 *dy, int nx, int ny, int nz, double ax, double ay, double c0,
-                                    double2 gz, double scale, hipStream_t s);
+                                    double2 gz, double scale, hipStream_t s, double zi = 1.0);
 int ring_rowgroups();
 hipError_t launch_ring_inverse_z64(const double2 *Xh, double2 *ring, const double2 *Vy, const double2 *VyT,
                                    const double2 *Vx, const double2 *VxT, int nx, int ny, int nz, double2 *rpart,

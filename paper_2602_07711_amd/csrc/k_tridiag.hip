@@ -26,7 +26,7 @@ namespace {
 
 // reciprocal pivot entering each chunk: piv[k * lines + line] = 1/pivot_{k TL - 1} (k >= 1), 0 for k = 0
 __global__ void k_tri_pivots(const double2 *__restrict__ dx, const double2 *__restrict__ dy, int nx, int ny, int nz,
-                             double ax, double ay, double c0, double2 g, double2 *__restrict__ piv) {
+                             double ax, double ay, double c0, double2 g, double zi, double2 *__restrict__ piv) {
     const long long lines = (long long)nx * ny;
     const long long line = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (line >= lines) return;
@@ -37,7 +37,7 @@ __global__ void k_tri_pivots(const double2 *__restrict__ dx, const double2 *__re
     piv[line] = inv;
     for (int l = 0; l < nz; ++l) {
         double2 d = b;
-        if (l == 0 || l == nz - 1) { d.x += g.x; d.y += g.y; }
+        if (l == 0 || l == nz - 1) { d.x = (d.x + g.x) * zi; d.y = (d.y + g.y) * zi; }
         if (l > 0) { d.x -= inv.x; d.y -= inv.y; }
         inv = crecip(d);
         if ((l + 1) % TL == 0 && l + 1 < nz) piv[(long long)((l + 1) / TL) * lines + line] = inv;
@@ -49,15 +49,15 @@ __global__ __launch_bounds__(1024) void k_tridiag_chunk(const typename c2<T>::t 
                                                         const double2 *__restrict__ piv,
                                                         const double2 *__restrict__ dx, const double2 *__restrict__ dy,
                                                         int nx, int ny, int nz, int P, int LX, double ax, double ay,
-                                                        double c0, double2 gz, double scale) {
+                                                        double c0, double2 gz, double scale, double zi) {
     extern __shared__ unsigned char smraw[];
-    tri_chunk_block<T>(in, out, piv, dx, dy, nx, ny, nz, P, LX, ax, ay, c0, gz, scale, blockIdx.x, smraw);
+    tri_chunk_block<T>(in, out, piv, dx, dy, nx, ny, nz, P, LX, ax, ay, c0, gz, scale, blockIdx.x, smraw, zi);
 }
 
 template <typename T>
 hipError_t launch_chunk(const typename c2<T>::t *in, typename c2<T>::t *out, const double2 *piv, const double2 *dx,
                         const double2 *dy, int nx, int ny, int nz, double ax, double ay, double c0, double2 gz,
-                        double scale, hipStream_t s) {
+                        double scale, hipStream_t s, double zi) {
     const int P = (nz + TL - 1) / TL;
     if (P > 1024) return hipErrorInvalidValue;
     // 16 lines per block (256 B per row access) for complex128, 32 for complex64 (measured 10% faster at 256^3)
@@ -67,7 +67,7 @@ hipError_t launch_chunk(const typename c2<T>::t *in, typename c2<T>::t *out, con
     const unsigned grid = (unsigned)((lines + LX - 1) / LX);
     const size_t sm = 2 * sizeof(typename c2<T>::t) * (size_t)P * LX;
     hipLaunchKernelGGL(k_tridiag_chunk<T>, dim3(grid), dim3(LX * P), sm, s, in, out, piv, dx, dy, nx, ny, nz, P, LX,
-                       ax, ay, c0, gz, scale);
+                       ax, ay, c0, gz, scale, zi);
     return hipGetLastError();
 }
 
@@ -76,23 +76,23 @@ hipError_t launch_chunk(const typename c2<T>::t *in, typename c2<T>::t *out, con
 int tri_chunks(int nz) { return (nz + TL - 1) / TL; }
 
 hipError_t launch_tri_pivots(const double2 *dx, const double2 *dy, int nx, int ny, int nz, double ax, double ay,
-                             double c0, double2 gz, double2 *piv, hipStream_t s) {
+                             double c0, double2 gz, double2 *piv, hipStream_t s, double zi) {
     const long long lines = (long long)nx * ny;
     hipLaunchKernelGGL(k_tri_pivots, dim3((unsigned)((lines + 255) / 256)), dim3(256), 0, s, dx, dy, nx, ny, nz, ax,
-                       ay, c0, gz, piv);
+                       ay, c0, gz, zi, piv);
     return hipGetLastError();
 }
 
 hipError_t launch_tridiag_chunk_z64(const double2 *in, double2 *out, const double2 *piv, const double2 *dx,
                                     const double2 *dy, int nx, int ny, int nz, double ax, double ay, double c0,
-                                    double2 gz, double scale, hipStream_t s) {
-    return launch_chunk<double>(in, out, piv, dx, dy, nx, ny, nz, ax, ay, c0, gz, scale, s);
+                                    double2 gz, double scale, hipStream_t s, double zi) {
+    return launch_chunk<double>(in, out, piv, dx, dy, nx, ny, nz, ax, ay, c0, gz, scale, s, zi);
 }
 
 hipError_t launch_tridiag_chunk_z32(const float2 *in, float2 *out, const double2 *piv, const double2 *dx,
                                     const double2 *dy, int nx, int ny, int nz, double ax, double ay, double c0,
-                                    double2 gz, double scale, hipStream_t s) {
-    return launch_chunk<float>(in, out, piv, dx, dy, nx, ny, nz, ax, ay, c0, gz, scale, s);
+                                    double2 gz, double scale, hipStream_t s, double zi) {
+    return launch_chunk<float>(in, out, piv, dx, dy, nx, ny, nz, ax, ay, c0, gz, scale, s, zi);
 }
 
 }  // namespace helm

@@ -39,7 +39,7 @@ __device__ __forceinline__ void tri_chunk_block(const typename c2<T>::t *in, typ
                                                 const double2 *__restrict__ piv, const double2 *__restrict__ dx,
                                                 const double2 *__restrict__ dy, int nx, int ny, int nz, int P, int LX,
                                                 double ax, double ay, double c0, double2 gz, double scale,
-                                                long long blk, unsigned char *smraw) {
+                                                long long blk, unsigned char *smraw, double zi = 1.0) {
     typedef typename c2<T>::t CT;
     CT *sA = reinterpret_cast<CT *>(smraw);                // [P][LX]
     CT *sB = sA + (blockDim.x / LX) * LX;
@@ -60,6 +60,12 @@ __device__ __forceinline__ void tri_chunk_block(const typename c2<T>::t *in, typ
 #pragma unroll
     for (int r = 0; r < TL; ++r)
         if (r < nrow) v[r] = in[line + (long long)(s + r) * lines];
+    // a corner off-diagonal zeta (collocated closure): the first and last equations are divided by zeta
+    // (zi = 1/zeta), which restores unit off-diagonals; end diagonal (gamma + b)/zeta, end right-hand side y/zeta
+    const T zt = (T)zi;
+#pragma unroll
+    for (int r = 0; r < TL; ++r)
+        if (r < nrow && (s + r == 0 || s + r == nz - 1)) { v[r].x *= zt; v[r].y *= zt; }
     // pivots of this chunk, restarted from the pivot entering it
     CT ip = mk<T, CT>(0, 0);
     if (lin && k > 0) {
@@ -71,7 +77,7 @@ __device__ __forceinline__ void tri_chunk_block(const typename c2<T>::t *in, typ
         if (r < nrow) {
             const int l = s + r;
             CT d = b;
-            if (l == 0 || l == nz - 1) { d.x += g.x; d.y += g.y; }
+            if (l == 0 || l == nz - 1) { d.x = (d.x + g.x) * zt; d.y = (d.y + g.y) * zt; }
             if (l > 0) { d.x -= ip.x; d.y -= ip.y; }
             ip = crecip(d);
             inv[r] = ip;

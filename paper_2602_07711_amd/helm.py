@@ -18,11 +18,11 @@ LIB_PATH = os.path.join(_HERE, "libhelm.so")
 HELM_OK, HELM_EINVAL, HELM_ENOMEM, HELM_EDEVICE, HELM_ENOCONV, HELM_EBREAKDOWN, HELM_ENUMERIC, HELM_EUNSUPPORTED = range(8)
 STATUS_NAMES = ["HELM_OK", "HELM_EINVAL", "HELM_ENOMEM", "HELM_EDEVICE", "HELM_ENOCONV", "HELM_EBREAKDOWN",
                 "HELM_ENUMERIC", "HELM_EUNSUPPORTED"]
-BC_ABC2, BC_DIRICHLET = 0, 1
+BC_ABC2, BC_DIRICHLET, BC_ABC3 = 0, 1, 2
 PREC_EIGT, PREC_PFFT, PREC_NONE, PREC_FFT2, PREC_FFT4, PREC_FFT6 = 0, 1, 2, 3, 4, 5
 _PREC = {"eigt": PREC_EIGT, "pfft": PREC_PFFT, "none": PREC_NONE, "fft2": PREC_FFT2, "fft4": PREC_FFT4,
          "fft6": PREC_FFT6}
-_BC = {"abc": BC_ABC2, "dirichlet": BC_DIRICHLET}
+_BC = {"abc": BC_ABC2, "dirichlet": BC_DIRICHLET, "abc3": BC_ABC3}
 
 
 class HelmError(RuntimeError):
@@ -83,6 +83,8 @@ def lib():
     L.helm_destroy.restype = None
     L.helm_eig1d.argtypes = [c_int, c_double, c_double, c_void_p, c_void_p, c_void_p]
     L.helm_eig1d.restype = c_int
+    L.helm_eig1d_zeta.argtypes = [c_int, c_double, c_double, c_double, c_void_p, c_void_p, c_void_p]
+    L.helm_eig1d_zeta.restype = c_int
     L.helm_profile_enable.argtypes = [c_void_p, c_int]
     L.helm_profile_enable.restype = c_int
     L.helm_profile_read.argtypes = [c_void_p, c_int, POINTER(c_double), POINTER(c_longlong), POINTER(c_double)]
@@ -379,14 +381,14 @@ def helm_destroy(ctx: Context):
         ctx.ptr = None
 
 
-def helm_eig1d(n: int, gamma: complex):
+def helm_eig1d(n: int, gamma: complex, zeta: float = 1.0):
     """Host 1D eigen-decomposition of Lambda-bar (no GPU). Returns numpy (d, V, Vinv)."""
     import numpy as np
     d = np.zeros(n, np.complex128)
     V = np.zeros((n, n), np.complex128)
     Vi = np.zeros((n, n), np.complex128)
-    st = lib().helm_eig1d(int(n), float(gamma.real), float(gamma.imag), c_void_p(d.ctypes.data),
-                          c_void_p(V.ctypes.data), c_void_p(Vi.ctypes.data))
+    st = lib().helm_eig1d_zeta(int(n), float(gamma.real), float(gamma.imag), float(zeta), c_void_p(d.ctypes.data),
+                               c_void_p(V.ctypes.data), c_void_p(Vi.ctypes.data))
     if st != HELM_OK:
         raise HelmError(st, "helm_eig1d failed")
     return d, V, Vi

@@ -43,6 +43,21 @@ def test_host_eigensolver(n, k0):
     assert abs(np.sort_complex(d) - ref).max() < 1e-12
 
 
+@pytest.mark.parametrize("n,k0", [(5, 3.0), (33, 20.0), (128, 60.0), (256, 120.0)])
+def test_host_eigensolver_collocated_zeta2(n, k0):
+    """Lambda-bar of the collocated closure (gamma = 2 i k0 h, zeta = 2 in the corner off-diagonals) is not
+    symmetric; the host eigensolver must still give Lambda-bar V = V diag(d), V^{-1} V = I and numpy's eigenvalues."""
+    helm = _lib()
+    h = 1.0 / (n - 1)
+    g = 2j * k0 * h
+    d, V, Vi = helm.helm_eig1d(n, g, 2.0)
+    L = op.lambda_bar(n, g, 2.0).toarray()
+    assert abs(L @ V - V * d).max() < 1e-12
+    assert abs(Vi @ V - np.eye(n)).max() < 1e-11
+    ref = np.sort_complex(np.linalg.eigvals(L))
+    assert abs(np.sort_complex(d) - ref).max() < 1e-11
+
+
 def test_host_eigensolver_dirichlet_closed_form():
     helm = _lib()
     n = 17

@@ -536,3 +536,40 @@ def test_fft46_precond_parity(order, fp32):
     print(f"fft{order} 40^3 residual {res:.3e}")
     assert res <= 100 * (lam.max() / lam.min()) * u
     h.helm_destroy(ctx)
+
+
+@pytest.mark.parametrize("shape", [(12, 20, 70), (33, 33, 33), (5, 7, 3)])
+@pytest.mark.parametrize("fp32", [False, True])
+def test_eigt3_collocated_parity(shape, fp32):
+    """EigT with the collocated three-point closure (HELM_BC_ABC3: gamma = 2 i k0 h, zeta = 2) against the oracle's
+    EigT(zeta = 2) and the collocated second-order matrix: FP64 1e-11 relative, FP32 2e-4 (the EigT bounds)."""
+    h = H()
+    h3 = (1.0 / (shape[2] - 1), 1.0 / (shape[1] - 1), 1.0 / (shape[0] - 1))
+    k0 = 0.47 / h3[0]
+    ctx = h.helm_setup(dev(np.full(shape, k0 * k0)), h3, 2, bc="abc3", k0=k0, shape=shape)
+    y = cvec(int(np.prod(shape)), 17)
+    z = host(h.helm_precond_apply(ctx, dev(y), fp32=fp32))
+    gs = tuple(2j * k0 * hh for hh in h3)
+    zr = pc.EigT(shape, h3, k0, gs, zeta=2.0).solve(y)
+    err = np.linalg.norm(z - zr) / np.linalg.norm(zr)
+    print(f"eigt3 {shape} fp32={fp32} rel err {err:.3e}")
+    assert err <= (2e-4 if fp32 else 1e-11)
+    if not fp32:
+        M = pc.M_collocated(shape, h3, k0, gs)
+        assert np.linalg.norm(M @ z - y) <= 1e-11 * np.linalg.norm(y)
+    h.helm_destroy(ctx)
+
+
+def test_eigt3_unsupported_entry_points():
+    """Contexts with the collocated closure do direct EigT solves only: the operator entry points, PFFT and batches
+    return HELM_EUNSUPPORTED (raised as HelmError)."""
+    h = H()
+    n = 10
+    ctx = h.helm_setup(dev(np.full((n, n, n), 100.0)), 1.0 / (n - 1), 2, bc="abc3", k0=10.0, shape=(n, n, n))
+    x = dev(cvec(n ** 3, 1))
+    for call in (lambda: h.helm_matvec(ctx, x), lambda: h.helm_gmres_solve(ctx, x),
+                 lambda: h.helm_precond_apply(ctx, x, kind="pfft"),
+                 lambda: h.helm_rhs(ctx, dev(cvec((n + 4) ** 3, 2))), lambda: h.helm_batch_create([ctx])):
+        with pytest.raises(h.HelmError):
+            call()
+    h.helm_destroy(ctx)
