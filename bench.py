@@ -221,7 +221,7 @@ def bench_learned(H, torch, args):
 def bench_direct_sweep(H, torch, dev, sizes):
     """The paper's Table 2 workload: the preconditioner as a direct solver of the second-order system of the
     Sec. 5.1 test problem (u = phi(x) phi(y) phi(z), k0^2 = 439.2, staggered nodes, two-point absorbing closure).
-    Per grid: setup time, the direct-solve time of EigT (FP64/FP32) and PFFT (FP64/FP32, N <= 256) on the solve
+    Per grid: setup time, the direct-solve time of EigT (FP64/FP32) and PFFT (FP64/FP32) on the solve
     stream (mean of 3 after one untimed call), and max-err / L2-err of the FP64 EigT solution against u; then the
     same for EigT with the collocated three-point closure (EigT3) on the nodes j/(N-1)."""
     import math
@@ -245,7 +245,7 @@ def bench_direct_sweep(H, torch, dev, sizes):
         del k2
         fv = f.reshape(-1)
         z = torch.empty_like(fv)
-        for kind in ["eigt"] + (["pfft"] if n <= 256 else []):
+        for kind in ["eigt", "pfft"]:
             for fp32 in (False, True):
                 H.helm_precond_apply(ctx, fv, z, kind=kind, fp32=fp32)
                 torch.cuda.synchronize()

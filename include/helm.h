@@ -149,7 +149,7 @@ helm_status helm_matvec(helm_ctx *ctx, const void *x_dev, void *y_dev);
  * operator's absorbing closure), HELM_PREC_FFT2 (M with zero Dirichlet closures), HELM_PREC_FFT4 / FFT6 (the
  * compact operators with constant k0 and zero Dirichlet closures), HELM_PREC_NONE (z = y);
  * fp32: 1 runs the transforms and tridiagonal solves in complex FP32 (input read as FP64, output written as
- * FP64). y_dev, z_dev: n complex128; they may be the same buffer. PFFT requires N_x, N_y <= 256
+ * FP64). y_dev, z_dev: n complex128; they may be the same buffer. PFFT requires N_x, N_y <= 832
  * (HELM_EUNSUPPORTED otherwise). */
 helm_status helm_precond_apply(helm_ctx *ctx, const void *y_dev, void *z_dev, int kind, int fp32);
 

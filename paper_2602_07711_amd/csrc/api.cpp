@@ -199,8 +199,8 @@ template <typename CT> helm_status build_ring_mats(Ctx &c, PfftMats<CT> &m) {
 
 // Sine matrices and Dirichlet eigenvalues (shared by PFFT and FFT2); `ring` adds PFFT's face-correction data.
 helm_status ensure_sine(Ctx &c, bool fp32, bool ring) {
-    if (ring && (c.nx > 256 || c.ny > 256)) {
-        c.err = "the PFFT preconditioner supports N_x, N_y <= 256";
+    if (ring && (c.nx > ring_max_n() || c.ny > ring_max_n())) {
+        c.err = "the PFFT preconditioner supports N_x, N_y <= " + std::to_string(ring_max_n());
         return HELM_EUNSUPPORTED;
     }
     if (!c.pfft) {

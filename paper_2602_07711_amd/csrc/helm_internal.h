@@ -253,6 +253,7 @@ hipError_t launch_tridiag_chunk_z32(const float2 *in, float2 *out, const double2
                                     const double2 *dy, int nx, int ny, int nz, double ax, double ay, double c0,
                                     double2 gz, double scale, hipStream_t s, double zi = 1.0);
 int ring_rowgroups();
+int ring_max_n();            // widest N_x the PFFT ring pass supports
 hipError_t launch_ring_inverse_z64(const double2 *Xh, double2 *ring, const double2 *Vy, const double2 *VyT,
                                    const double2 *Vx, const double2 *VxT, int nx, int ny, int nz, double2 *rpart,
                                    double2 *sv, double2 *rsum, hipStream_t s);

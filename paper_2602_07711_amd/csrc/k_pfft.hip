@@ -45,13 +45,14 @@ template <typename T> __device__ __forceinline__ T wsum(T v) {
     return v;
 }
 
-constexpr int MAXC = 4;   // N <= 256 (the PFFT limit): up to 4 chunks of 64 columns per lane
 constexpr int RING_RG = 8; // row groups per slice in the inverse's pass over the data
+constexpr int RING_NMAX = 64 * 13;   // widest slice the ring pass supports (MAXC = 13 chunks of 64 columns)
 
 // Inverse, pass over the data: block (slice l, row group rg) takes rows m of its group and accumulates, per
 // column k, r0[k] += V_y[0][m] X[m][k] and rN[k] += V_y[ny-1][m] X[m][k] (partials per group), and per row the
-// complete s0[m] = sum_k V_x[0][k] X[m][k], sN[m] = sum_k V_x[nx-1][k] X[m][k].
-template <typename T>
+// complete s0[m] = sum_k V_x[0][k] X[m][k], sN[m] = sum_k V_x[nx-1][k] X[m][k]. Each lane holds MAXC chunks of
+// 64 columns (N_x <= 64 MAXC; the launcher picks 4, 8 or 13).
+template <typename T, int MAXC>
 __global__ __launch_bounds__(256) void k_ring_inv_rows(const typename c2<T>::t *__restrict__ Xh,
                                                        const typename c2<T>::t *__restrict__ Vy,
                                                        const typename c2<T>::t *__restrict__ Vx, int nx, int ny,
@@ -191,8 +192,14 @@ hipError_t inv_launch(const typename c2<T>::t *Xh, typename c2<T>::t *ring, cons
                       const typename c2<T>::t *VyT, const typename c2<T>::t *Vx, const typename c2<T>::t *VxT, int nx,
                       int ny, int nz, typename c2<T>::t *rpart, typename c2<T>::t *sv, typename c2<T>::t *rsum,
                       hipStream_t s) {
-    if (nx > 64 * MAXC || ny > 64 * MAXC) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_ring_inv_rows<T>, dim3(nz * RING_RG), dim3(256), 0, s, Xh, Vy, Vx, nx, ny, rpart, sv);
+    if (nx > RING_NMAX || ny > RING_NMAX) return hipErrorInvalidValue;
+    if (nx <= 256)
+        hipLaunchKernelGGL((k_ring_inv_rows<T, 4>), dim3(nz * RING_RG), dim3(256), 0, s, Xh, Vy, Vx, nx, ny, rpart, sv);
+    else if (nx <= 512)
+        hipLaunchKernelGGL((k_ring_inv_rows<T, 8>), dim3(nz * RING_RG), dim3(256), 0, s, Xh, Vy, Vx, nx, ny, rpart, sv);
+    else
+        hipLaunchKernelGGL((k_ring_inv_rows<T, 13>), dim3(nz * RING_RG), dim3(256), 0, s, Xh, Vy, Vx, nx, ny, rpart,
+                           sv);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const long long nr = 2LL * nz * nx;
@@ -274,6 +281,7 @@ hipError_t launch_sym_divide_z32(float2 *u, const double *tx, const double *ty, 
 }
 
 int ring_rowgroups() { return RING_RG; }
+int ring_max_n() { return RING_NMAX; }
 
 hipError_t launch_ring_inverse_z64(const double2 *Xh, double2 *ring, const double2 *Vy, const double2 *VyT,
                                    const double2 *Vx, const double2 *VxT, int nx, int ny, int nz, double2 *rpart,

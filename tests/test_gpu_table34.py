@@ -64,7 +64,7 @@ def test_tables34_iteration_comparison(order):
 
 def test_table5_wavenumber_sweep():
     """The paper's Table 5: the test problem with k0 = k in {10, 20, 50, 100} on 100^3 ... 511^3, sixth order, the
-    absorbing-closure preconditioner (EigT; PFFT too for N <= 256, which must take the same number of iterations).
+    absorbing-closure preconditioner (EigT and PFFT, which must take the same number of iterations).
     Checked: every count at most the printed one (the preconditioner here carries exactly the operator's closure),
     counts non-increasing in N for every k and non-decreasing in k for every N."""
     import paper_2602_07711_amd as H
@@ -83,7 +83,7 @@ def test_table5_wavenumber_sweep():
             del w
             x = torch.empty_like(F)
             its = []
-            for prec in (["eigt", "pfft"] if n <= 256 else ["eigt"]):
+            for prec in ["eigt", "pfft"]:
                 _, info = H.helm_gmres_solve(ctx, F, x, m=50, maxit=300, rtol=1e-8, x0_given=False, prec=prec)
                 its.append(info["iters"])
             print(f"table5 N={n} k={k}: {its} (paper {n0})", flush=True)
