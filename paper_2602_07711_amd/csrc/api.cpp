@@ -70,12 +70,36 @@ helm_status upload_matrix(Ctx &c, const std::vector<cd> &M, int n, bool transpos
     return HELM_OK;
 }
 
+// The half blocks of one axis for the folded transforms (k_gemm.hip), with the butterfly's 1/sqrt(2) folded in
+// (1/2 forward and 1 inverse at the middle position of an odd axis). Layouts: x forward [position][mode], x
+// inverse [mode][position]; y forward [mode][position], y inverse [position][mode].
+helm_status upload_fold(Ctx &c, const EigFold &f, bool xaxis, FoldMats<double2> &m64, FoldMats<float2> &m32) {
+    const double r = 1.0 / std::sqrt(2.0);
+    auto block = [&](int nb, const std::vector<cd> &Vi, const std::vector<cd> &V, bool sym, double2 **f64,
+                     float2 **f32, double2 **i64, float2 **i32) -> helm_status {
+        std::vector<cd> fw((size_t)nb * nb), iv((size_t)nb * nb);
+        for (int k = 0; k < nb; ++k)
+            for (int i = 0; i < nb; ++i) {
+                const bool mid = sym && i >= f.ma;            // middle of an odd axis: no mirror partner
+                const cd vf = Vi[(size_t)k * nb + i] * (mid ? 0.5 : r);   // mode k from position i
+                const cd vi = V[(size_t)i * nb + k] * (mid ? 1.0 : r);    // position i from mode k
+                fw[xaxis ? (size_t)i * nb + k : (size_t)k * nb + i] = vf;
+                iv[xaxis ? (size_t)k * nb + i : (size_t)i * nb + k] = vi;
+            }
+        ST_TRY(upload_matrix(c, fw, nb, false, f64, f32));
+        ST_TRY(upload_matrix(c, iv, nb, false, i64, i32));
+        return HELM_OK;
+    };
+    ST_TRY(block(f.ms, f.Vsi, f.Vs, true, &m64.fs, &m32.fs, &m64.is, &m32.is));
+    ST_TRY(block(f.ma, f.Vai, f.Va, false, &m64.fa, &m32.fa, &m64.ia, &m32.ia));
+    return HELM_OK;
+}
+
 // ---------------------------------------------------------------------------------------------------------
 // Preconditioner chain (EigT, Sec. 4.1 eq. EIG_SOLVER): forward x-transform, forward y-transform (batched
 // over slices), z-tridiagonal solves, inverse y-transform, inverse x-transform.
 // ---------------------------------------------------------------------------------------------------------
 
-double gemm_flops(const GemmDesc &d) { return 8.0 * d.M * (double)d.N * d.K * d.batch; }
 
 // minimum HBM bytes of one matvec: x, k^2 (and the order-6 field block) read once, y written once
 double matvec_bytes(const Ctx &c, bool resid) {
@@ -96,6 +120,24 @@ GemmDesc desc_y(const Ctx &c) {
     d.lda = c.ny; d.ldb = c.nx; d.ldc = c.nx;
     d.sA = 0; d.sB = d.sC = (long long)c.nx * c.ny; d.batch = c.nz;
     return d;
+}
+
+// folded transforms along x (every line is a row) and along y (slices of Nx columns)
+FoldDesc fold_x(const Ctx &c) {
+    FoldDesc f{};
+    f.n = c.nx; f.ms = c.nx - c.nx / 2; f.ma = c.nx / 2;
+    f.rows = c.ny * c.nz; f.ld = c.nx; f.sD = 0; f.batch = 1;
+    return f;
+}
+FoldDesc fold_y(const Ctx &c) {
+    FoldDesc f{};
+    f.n = c.ny; f.ms = c.ny - c.ny / 2; f.ma = c.ny / 2;
+    f.rows = c.nx; f.ld = c.nx; f.sD = (long long)c.nx * c.ny; f.batch = c.nz;
+    return f;
+}
+// real flops of one folded transform: 8 per complex MAC, ms^2 + ma^2 MACs per line
+double fold_flops(const FoldDesc &f) {
+    return 8.0 * (double)f.rows * f.batch * ((double)f.ms * f.ms + (double)f.ma * f.ma);
 }
 
 // pivots entering each z-chunk of the partitioned tridiagonal solve, per set of x-y eigenvalues and z closure
@@ -119,24 +161,25 @@ helm_status ensure_fp32_work(Ctx &c) {
 
 // z32 (FP32 form only): write the result as complex64 there instead of complex128 into z
 helm_status eigt_apply(Ctx &c, const double2 *y, double2 *z, bool fp32, float2 *z32 = nullptr) {
-    GemmDesc dx = desc_x(c), dy = desc_y(c);
+    const FoldDesc fx = fold_x(c), fy = fold_y(c);
+    const double wx = fold_flops(fx), wy = fold_flops(fy);
     double2 gz = d2(c.gamma[2]);
     double scale = c.hz * c.hz;
     if (!fp32) {
-        HIP_TRY(timed(c, HELM_K_GEMM_X64, gemm_flops(dx), [&] { return launch_gemm_z64(dx, y, c.BxF, c.t1, c.stream, 0, c.gemm_cfg[0]); }));
-        HIP_TRY(timed(c, HELM_K_GEMM_Y64, gemm_flops(dy), [&] { return launch_gemm_z64(dy, c.AyF, c.t1, c.t2, c.stream, 0, c.gemm_cfg[1]); }));
+        HIP_TRY(timed(c, HELM_K_GEMM_X64, wx, [&] { return launch_fold_z64(FOLD_XF, fx, y, c.fx64.fs, c.fx64.fa, c.t1, c.stream, c.gemm_cfg[0]); }));
+        HIP_TRY(timed(c, HELM_K_GEMM_Y64, wy, [&] { return launch_fold_z64(FOLD_YF, fy, c.t1, c.fy64.fs, c.fy64.fa, c.t2, c.stream, c.gemm_cfg[1]); }));
         ST_TRY(ensure_tpiv(c, c.dxe, c.dye, &c.tpiv_eig));
         HIP_TRY(timed(c, HELM_K_TRIDIAG64, 32.0 * c.n, [&] { return launch_tridiag_chunk_z64(c.t2, c.t2, c.tpiv_eig, c.dxe, c.dye, c.nx, c.ny, c.nz, c.ax, c.ay, c.c0, gz, scale, c.stream, 1.0 / c.zeta); }));
-        HIP_TRY(timed(c, HELM_K_GEMM_Y64, gemm_flops(dy), [&] { return launch_gemm_z64(dy, c.AyI, c.t2, c.t1, c.stream, 0, c.gemm_cfg[1]); }));
-        HIP_TRY(timed(c, HELM_K_GEMM_X64, gemm_flops(dx), [&] { return launch_gemm_z64(dx, c.t1, c.BxI, z, c.stream, 0, c.gemm_cfg[0]); }));
+        HIP_TRY(timed(c, HELM_K_GEMM_Y64, wy, [&] { return launch_fold_z64(FOLD_YI, fy, c.t2, c.fy64.is, c.fy64.ia, c.t1, c.stream, c.gemm_cfg[1]); }));
+        HIP_TRY(timed(c, HELM_K_GEMM_X64, wx, [&] { return launch_fold_z64(FOLD_XI, fx, c.t1, c.fx64.is, c.fx64.ia, z, c.stream, c.gemm_cfg[0]); }));
     } else {
         ST_TRY(ensure_fp32_work(c));
-        HIP_TRY(timed(c, HELM_K_GEMM_X32, gemm_flops(dx), [&] { return launch_gemm_z32_in64(dx, y, c.BxF32, c.t1f, c.stream, 0, c.gemm_cfg[2]); }));
-        HIP_TRY(timed(c, HELM_K_GEMM_Y32, gemm_flops(dy), [&] { return launch_gemm_z32(dy, c.AyF32, c.t1f, c.t2f, c.stream, 0, c.gemm_cfg[3]); }));
+        HIP_TRY(timed(c, HELM_K_GEMM_X32, wx, [&] { return launch_fold_z32_in64(FOLD_XF, fx, y, c.fx32.fs, c.fx32.fa, c.t1f, c.stream, c.gemm_cfg[2]); }));
+        HIP_TRY(timed(c, HELM_K_GEMM_Y32, wy, [&] { return launch_fold_z32(FOLD_YF, fy, c.t1f, c.fy32.fs, c.fy32.fa, c.t2f, c.stream, c.gemm_cfg[3]); }));
         ST_TRY(ensure_tpiv(c, c.dxe, c.dye, &c.tpiv_eig));
         HIP_TRY(timed(c, HELM_K_TRIDIAG32, 16.0 * c.n, [&] { return launch_tridiag_chunk_z32(c.t2f, c.t2f, c.tpiv_eig, c.dxe, c.dye, c.nx, c.ny, c.nz, c.ax, c.ay, c.c0, gz, scale, c.stream, 1.0 / c.zeta); }));
-        HIP_TRY(timed(c, HELM_K_GEMM_Y32, gemm_flops(dy), [&] { return launch_gemm_z32(dy, c.AyI32, c.t2f, c.t1f, c.stream, 0, c.gemm_cfg[3]); }));
-        HIP_TRY(timed(c, HELM_K_GEMM_X32, gemm_flops(dx), [&] { return z32 ? launch_gemm_z32(dx, c.t1f, c.BxI32, z32, c.stream, 0, c.gemm_cfg[2]) : launch_gemm_z32_out64(dx, c.t1f, c.BxI32, z, c.stream, 0, c.gemm_cfg[2]); }));
+        HIP_TRY(timed(c, HELM_K_GEMM_Y32, wy, [&] { return launch_fold_z32(FOLD_YI, fy, c.t2f, c.fy32.is, c.fy32.ia, c.t1f, c.stream, c.gemm_cfg[3]); }));
+        HIP_TRY(timed(c, HELM_K_GEMM_X32, wx, [&] { return z32 ? launch_fold_z32(FOLD_XI, fx, c.t1f, c.fx32.is, c.fx32.ia, z32, c.stream, c.gemm_cfg[2]) : launch_fold_z32_out64(FOLD_XI, fx, c.t1f, c.fx32.is, c.fx32.ia, z, c.stream, c.gemm_cfg[2]); }));
     }
     return HELM_OK;
 }
@@ -637,10 +680,16 @@ helm_status setup_impl(helm_ctx **out, helm_grid g, const double h[3], const voi
     if (he != hipSuccess) { c.err = std::string("derived fields: ") + hipGetErrorString(he); return bail(HELM_EDEVICE); }
 
     // EigT Step 1: 1D eigen-decompositions of Lambda-bar_x and Lambda-bar_y
+    // (folded: Lambda-bar is centrosymmetric; modes ordered [symmetric | skew] in every copy below)
+    EigFold fxv, fyv;
+    if (!eig_lambda_bar_folded(c.nx, c.gamma[0], c.zeta, fxv, c.err)) return bail(HELM_ENUMERIC);
+    if (c.ny == c.nx && c.gamma[1] == c.gamma[0]) fyv = fxv;
+    else if (!eig_lambda_bar_folded(c.ny, c.gamma[1], c.zeta, fyv, c.err)) return bail(HELM_ENUMERIC);
     std::vector<cd> dxv, Vx, Vxi, dyv, Vy, Vyi;
-    if (!eig_lambda_bar(c.nx, c.gamma[0], dxv, Vx, Vxi, c.err, c.zeta)) return bail(HELM_ENUMERIC);
-    if (c.ny == c.nx && c.gamma[1] == c.gamma[0]) { dyv = dxv; Vy = Vx; Vyi = Vxi; }
-    else if (!eig_lambda_bar(c.ny, c.gamma[1], dyv, Vy, Vyi, c.err, c.zeta)) return bail(HELM_ENUMERIC);
+    eig_fold_dense(fxv, dxv, Vx, Vxi);
+    eig_fold_dense(fyv, dyv, Vy, Vyi);
+    if ((st = upload_fold(c, fxv, true, c.fx64, c.fx32)) != HELM_OK) return bail(st);
+    if ((st = upload_fold(c, fyv, false, c.fy64, c.fy32)) != HELM_OK) return bail(st);
     c.hVx = Vx; c.hVxi = Vxi; c.hVy = Vy; c.hVyi = Vyi;
     // x-transform uses the transposed matrices as the B operand; y-transform uses them as the A operand
     if ((st = upload_matrix(c, Vxi, c.nx, true, &c.BxF, &c.BxF32)) != HELM_OK) return bail(st);
@@ -681,9 +730,9 @@ helm_status helm_setup_complex(helm_ctx **out, helm_grid g, const double h[3], c
 
 // ---- GEMM tile autotuner ----
 namespace {
-std::string tune_key(int kind, const GemmDesc &d) {
-    return "v3 " + std::to_string(kind) + " " + std::to_string(d.M) + " " + std::to_string(d.N) + " " + std::to_string(d.K) +
-           " " + std::to_string(d.batch);
+std::string tune_key(int kind, const FoldDesc &d) {
+    return "v4 " + std::to_string(kind) + " " + std::to_string(d.n) + " " + std::to_string(d.rows) + " " +
+           std::to_string(d.batch);
 }
 bool tune_cache_lookup(const std::string &key, int &cfg) {
     const char *path = std::getenv("HELM_TUNE_CACHE");
@@ -715,12 +764,12 @@ helm_status helm_autotune(helm_ctx *ctx, int reps, int *chosen, double *ms) {
     if (!ctx || reps < 1) return HELM_EINVAL;
     Ctx &c = ctx->c;
     ST_TRY(ensure_fp32_work(c));
-    GemmDesc dxd = desc_x(c), dyd = desc_y(c);
+    const FoldDesc fxd = fold_x(c), fyd = fold_y(c);
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     for (int kind = 0; kind < 4; ++kind) {
-        const GemmDesc &d = (kind % 2 == 0) ? dxd : dyd;
+        const FoldDesc &d = (kind % 2 == 0) ? fxd : fyd;
         std::string key = tune_key(kind, d);
         int cached = -1;
         if (tune_cache_lookup(key, cached)) {
@@ -731,16 +780,22 @@ helm_status helm_autotune(helm_ctx *ctx, int reps, int *chosen, double *ms) {
         double best = 1e300;
         int best_cfg = 0;
         for (int cfg = 0; cfg < GEMM_NCFG; ++cfg) {
-            // the exact launches the preconditioner makes for this kind (FP32 x: FP64 in, FP64 out)
+            // the forward and inverse launches the preconditioner makes for this kind (FP32 x: FP64 in, FP64 out)
             auto run = [&]() -> hipError_t {
+                hipError_t e;
                 switch (kind) {
-                case 0: return launch_gemm_z64(d, c.t1, c.BxF, c.t2, c.stream, 0, cfg);
-                case 1: return launch_gemm_z64(d, c.AyF, c.t1, c.t2, c.stream, 0, cfg);
-                case 2: {
-                    hipError_t e = launch_gemm_z32_in64(d, c.t1, c.BxF32, c.t1f, c.stream, 0, cfg);
-                    return e != hipSuccess ? e : launch_gemm_z32_out64(d, c.t1f, c.BxI32, c.t2, c.stream, 0, cfg);
-                }
-                default: return launch_gemm_z32(d, c.AyF32, c.t1f, c.t2f, c.stream, 0, cfg);
+                case 0:
+                    e = launch_fold_z64(FOLD_XF, d, c.t1, c.fx64.fs, c.fx64.fa, c.t2, c.stream, cfg);
+                    return e != hipSuccess ? e : launch_fold_z64(FOLD_XI, d, c.t2, c.fx64.is, c.fx64.ia, c.t1, c.stream, cfg);
+                case 1:
+                    e = launch_fold_z64(FOLD_YF, d, c.t1, c.fy64.fs, c.fy64.fa, c.t2, c.stream, cfg);
+                    return e != hipSuccess ? e : launch_fold_z64(FOLD_YI, d, c.t2, c.fy64.is, c.fy64.ia, c.t1, c.stream, cfg);
+                case 2:
+                    e = launch_fold_z32_in64(FOLD_XF, d, c.t1, c.fx32.fs, c.fx32.fa, c.t1f, c.stream, cfg);
+                    return e != hipSuccess ? e : launch_fold_z32_out64(FOLD_XI, d, c.t1f, c.fx32.is, c.fx32.ia, c.t2, c.stream, cfg);
+                default:
+                    e = launch_fold_z32(FOLD_YF, d, c.t1f, c.fy32.fs, c.fy32.fa, c.t2f, c.stream, cfg);
+                    return e != hipSuccess ? e : launch_fold_z32(FOLD_YI, d, c.t2f, c.fy32.is, c.fy32.ia, c.t1f, c.stream, cfg);
                 }
             };
             HIP_TRY(run());
@@ -752,7 +807,7 @@ helm_status helm_autotune(helm_ctx *ctx, int reps, int *chosen, double *ms) {
                 HIP_TRY(hipEventSynchronize(e1));
                 float t = 0.f;
                 HIP_TRY(hipEventElapsedTime(&t, e0, e1));
-                avg = std::min(avg, (double)t / reps / (kind == 2 ? 2 : 1));
+                avg = std::min(avg, (double)t / reps / 2);
             }
             if (ms) ms[kind * GEMM_NCFG + cfg] = avg;
             if (avg < best) { best = avg; best_cfg = cfg; }

@@ -5,13 +5,25 @@
 // decomposed as W diag(d) W^{-1} and Lambda-bar = (S W) diag(d) (W^{-1} S^{-1}). For zeta = 1, S = I. B is
 // complex symmetric but not Hermitian, so W is non-unitary.
 //
+// Both ends carry the same closure, so B is centrosymmetric (J B J = B, J the exchange matrix). With the
+// orthogonal Q whose columns are (e_i + e_{N-1-i})/sqrt(2) (symmetric half, plus e_m in the middle for odd
+// N) and (e_i - e_{N-1-i})/sqrt(2) (skew half), Q^T B Q = diag(B_s, B_a): two tridiagonal blocks of sizes
+// ceil(N/2) and floor(N/2). For even N = 2m they are the leading m x m block of B with b_{m-1,m} added to
+// (B_s) or subtracted from (B_a) its last diagonal entry; for odd N = 2m+1, B_s is the leading (m+1) x
+// (m+1) block with its last off-diagonal scaled by sqrt(2) and B_a the leading m x m block. Each block is
+// decomposed separately and V = S Q diag(W_s, W_a) = Q diag(S_h W_s, S_h W_a), S_h = diag(sqrt(zeta), 1,
+// ..., 1); the modes are ordered [symmetric | skew]. The preconditioner's transforms apply Q and the two
+// half-size blocks instead of the dense V (half the flops); the dense V and V^{-1} are assembled for the
+// other users.
+//
+// Per block:
 //   1. eigenvalues: shifted QR iteration (Wilkinson shift, unitary Givens rotations) on the dense upper
 //      Hessenberg copy of the matrix, with deflation on small subdiagonal entries;
 //   2. eigenvectors: inverse iteration with the tridiagonal matrix (LU with partial pivoting), alternating
 //      with the two-sided Rayleigh quotient x^T A x / x^T x (left = right eigenvector for a complex
 //      symmetric matrix), which also polishes each eigenvalue;
-//   3. V^{-1}: LU with partial pivoting of the dense V;
-//   4. checks: ||A V - V D||_max and ||V^{-1} V - I||_max.
+//   3. W^{-1}: LU with partial pivoting of the dense W;
+//   4. checks: ||B W - W D||_max and ||W^{-1} W - I||_max.
 #include <algorithm>
 #include <cmath>
 #include <complex>
@@ -177,24 +189,21 @@ bool invert(std::vector<cd> &A, int n) {
     return true;
 }
 
-}  // namespace
-
-bool eig_lambda_bar(int n, cd gamma, std::vector<cd> &d, std::vector<cd> &V, std::vector<cd> &Vinv,
-                    std::string &err, double zeta) {
-    if (n < 2) { err = "eig1d: n must be >= 2"; return false; }
-    if (!(zeta > 0.0)) { err = "eig1d: zeta must be positive"; return false; }
-    // tridiagonal entries of the symmetrised B
-    const double sz = std::sqrt(zeta);
-    std::vector<cd> lo(n - 1, 1.0), up(n - 1, 1.0), di(n, 0.0);
-    di[0] += gamma;
-    di[n - 1] += gamma;
-    lo[0] = up[0] = sz;
-    lo[n - 2] = up[n - 2] = sz;
+// Eigen-decomposition B = W diag(d) W^{-1} of the complex symmetric tridiagonal B with diagonal di and
+// off-diagonal off (both sides). Returns false with err set when the QR iteration fails or a check fails.
+bool eig_sym_tridiag(const std::vector<cd> &di, const std::vector<cd> &off, std::vector<cd> &d, std::vector<cd> &W,
+                     std::vector<cd> &Winv, std::string &err) {
+    const int n = (int)di.size();
+    const std::vector<cd> &lo = off, &up = off;
     std::vector<cd> H((size_t)n * n, 0.0);
+    double anorm = 0.0;
     for (int i = 0; i < n; ++i) {
         H[(size_t)i * n + i] = di[i];
         if (i + 1 < n) { H[(size_t)i * n + i + 1] = up[i]; H[(size_t)(i + 1) * n + i] = lo[i]; }
+        double row = std::abs(di[i]) + (i > 0 ? std::abs(off[i - 1]) : 0.0) + (i + 1 < n ? std::abs(off[i]) : 0.0);
+        anorm = std::max(anorm, row);
     }
+    if (anorm == 0.0) anorm = 1.0;
     std::vector<cd> ev;
     if (!hessenberg_qr_eigenvalues(H, n, ev)) { err = "eig1d: QR iteration did not converge"; return false; }
 
@@ -206,9 +215,8 @@ bool eig_lambda_bar(int n, cd gamma, std::vector<cd> &d, std::vector<cd> &V, std
             y[i] = s;
         }
     };
-    const double anorm = 2.0 * sz + std::abs(gamma);
     const double tiny = 1e-300 + anorm * 1e-18;
-    V.assign((size_t)n * n, 0.0);
+    W.assign((size_t)n * n, 0.0);
     d.assign(n, 0.0);
     std::vector<cd> x(n), y(n);
     for (int k = 0; k < n; ++k) {
@@ -229,35 +237,101 @@ bool eig_lambda_bar(int n, cd gamma, std::vector<cd> &d, std::vector<cd> &V, std
             }
         }
         d[k] = lam;
-        for (int i = 0; i < n; ++i) V[(size_t)i * n + k] = x[i];
+        for (int i = 0; i < n; ++i) W[(size_t)i * n + k] = x[i];
     }
-    // checks: ||A V - V D||_max relative to ||A|| and ||V^{-1} V - I||_max
+    // checks: ||B W - W D||_max relative to ||B|| and ||W^{-1} W - I||_max
     double res = 0.0;
     for (int k = 0; k < n; ++k) {
-        for (int i = 0; i < n; ++i) x[i] = V[(size_t)i * n + k];
+        for (int i = 0; i < n; ++i) x[i] = W[(size_t)i * n + k];
         apply(x, y);
         for (int i = 0; i < n; ++i) res = std::max(res, std::abs(y[i] - d[k] * x[i]));
     }
     if (!(res <= 1e-11 * anorm)) { err = "eig1d: eigenpair residual too large"; return false; }
-    Vinv = V;
-    if (!invert(Vinv, n)) { err = "eig1d: eigenvector matrix is singular"; return false; }
+    Winv = W;
+    if (!invert(Winv, n)) { err = "eig1d: eigenvector matrix is singular"; return false; }
     double ortho = 0.0;
     for (int i = 0; i < n; ++i) {
         for (int j = 0; j < n; ++j) {
             cd s = 0.0;
-            for (int k = 0; k < n; ++k) s += Vinv[(size_t)i * n + k] * V[(size_t)k * n + j];
+            for (int k = 0; k < n; ++k) s += Winv[(size_t)i * n + k] * W[(size_t)k * n + j];
             ortho = std::max(ortho, std::abs(s - (i == j ? cd(1.0) : cd(0.0))));
         }
     }
     if (!(ortho <= 1e-9)) { err = "eig1d: V^{-1} V differs from I"; return false; }
-    if (zeta != 1.0) {              // V = S W, V^{-1} = W^{-1} S^{-1}
-        for (int k = 0; k < n; ++k) {
-            V[k] *= sz;
-            V[(size_t)(n - 1) * n + k] *= sz;
-            Vinv[(size_t)k * n] /= sz;
-            Vinv[(size_t)k * n + n - 1] /= sz;
+    return true;
+}
+
+}  // namespace
+
+bool eig_lambda_bar_folded(int n, cd gamma, double zeta, EigFold &f, std::string &err) {
+    if (n < 2) { err = "eig1d: n must be >= 2"; return false; }
+    if (!(zeta > 0.0)) { err = "eig1d: zeta must be positive"; return false; }
+    const double sz = std::sqrt(zeta);
+    // tridiagonal entries of the symmetrised B
+    std::vector<cd> di(n, 0.0), off(n - 1, 1.0);
+    di[0] += gamma;
+    di[n - 1] += gamma;
+    off[0] = sz;
+    off[n - 2] = sz;
+    if (n == 2) off[0] = zeta;   // both corners are the one off-diagonal pair and S = sqrt(zeta) I
+    const int m = n / 2;
+    f.n = n;
+    f.ms = n - m;
+    f.ma = m;
+    // the two blocks of Q^T B Q (B is centrosymmetric)
+    std::vector<cd> ds(di.begin(), di.begin() + f.ms), da(di.begin(), di.begin() + m);
+    std::vector<cd> os(off.begin(), off.begin() + (f.ms - 1)), oa(off.begin(), off.begin() + (m - 1));
+    if (n % 2 == 0) {
+        ds[m - 1] += off[m - 1];
+        da[m - 1] -= off[m - 1];
+    } else {
+        os[m - 1] = std::sqrt(2.0) * off[m - 1];
+    }
+    if (!eig_sym_tridiag(ds, os, f.ds, f.Vs, f.Vsi, err)) return false;
+    if (!eig_sym_tridiag(da, oa, f.da, f.Va, f.Vai, err)) return false;
+    if (zeta != 1.0) {   // block position 0 is the corner of both halves: V = S W, V^{-1} = W^{-1} S^{-1}
+        for (int k = 0; k < f.ms; ++k) { f.Vs[k] *= sz; f.Vsi[(size_t)k * f.ms] /= sz; }
+        for (int k = 0; k < f.ma; ++k) { f.Va[k] *= sz; f.Vai[(size_t)k * f.ma] /= sz; }
+    }
+    return true;
+}
+
+void eig_fold_dense(const EigFold &f, std::vector<cd> &d, std::vector<cd> &V, std::vector<cd> &Vinv) {
+    // V = Q diag(Vs, Va), V^{-1} = diag(Vs^{-1}, Va^{-1}) Q^T; modes ordered [symmetric | skew]
+    const int n = f.n, ms = f.ms, ma = f.ma;
+    const double r = 1.0 / std::sqrt(2.0);
+    d.assign(n, 0.0);
+    V.assign((size_t)n * n, 0.0);
+    Vinv.assign((size_t)n * n, 0.0);
+    for (int k = 0; k < ms; ++k) d[k] = f.ds[k];
+    for (int k = 0; k < ma; ++k) d[ms + k] = f.da[k];
+    for (int i = 0; i < ma; ++i) {
+        for (int k = 0; k < ms; ++k) {
+            V[(size_t)i * n + k] = f.Vs[(size_t)i * ms + k] * r;
+            V[(size_t)(n - 1 - i) * n + k] = f.Vs[(size_t)i * ms + k] * r;
+            Vinv[(size_t)k * n + i] = f.Vsi[(size_t)k * ms + i] * r;
+            Vinv[(size_t)k * n + n - 1 - i] = f.Vsi[(size_t)k * ms + i] * r;
+        }
+        for (int k = 0; k < ma; ++k) {
+            V[(size_t)i * n + ms + k] = f.Va[(size_t)i * ma + k] * r;
+            V[(size_t)(n - 1 - i) * n + ms + k] = -f.Va[(size_t)i * ma + k] * r;
+            Vinv[(size_t)(ms + k) * n + i] = f.Vai[(size_t)k * ma + i] * r;
+            Vinv[(size_t)(ms + k) * n + n - 1 - i] = -f.Vai[(size_t)k * ma + i] * r;
         }
     }
+    if (ms > ma) {   // odd n: the middle position belongs to the symmetric half only
+        for (int k = 0; k < ms; ++k) {
+            V[(size_t)ma * n + k] = f.Vs[(size_t)ma * ms + k];
+            Vinv[(size_t)k * n + ma] = f.Vsi[(size_t)k * ms + ma];
+        }
+    }
+}
+
+bool eig_lambda_bar(int n, cd gamma, std::vector<cd> &d, std::vector<cd> &V, std::vector<cd> &Vinv,
+                    std::string &err, double zeta) {
+    EigFold f;
+    if (!eig_lambda_bar_folded(n, gamma, zeta, f, err)) return false;
+    eig_fold_dense(f, d, V, Vinv);
     return true;
 }
 

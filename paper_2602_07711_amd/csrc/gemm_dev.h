@@ -33,6 +33,83 @@ template <typename TC, typename T> __device__ __forceinline__ TC pack(T re, T im
     return r;
 }
 
+// The MFMA products of one k-step of four: fragments fa (A, FM blocks of 16 rows) and fb (B, FN blocks of 16
+// columns) into the accumulator sets t. RW = 1: A is real, RW = 2: B is real (the sine matrix of the PFFT
+// transforms); then each complex MAC needs two real products. Otherwise 3M for FP32 (NS = 3) and 4M for FP64.
+template <typename T, int RW, int NS, int FM, int FN>
+__device__ __forceinline__ void mma_kstep(typename cplx<T>::acc (&t)[NS][FM][FN], const typename cplx<T>::t (&fa)[FM],
+                                          const typename cplx<T>::t (&fb)[FN]) {
+    if constexpr (RW == 1) {
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j) {
+                t[0][i][j] = mfma(fa[i].x, fb[j].x, t[0][i][j]);
+                t[1][i][j] = mfma(fa[i].x, fb[j].y, t[1][i][j]);
+            }
+    } else if constexpr (RW == 2) {
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j) {
+                t[0][i][j] = mfma(fa[i].x, fb[j].x, t[0][i][j]);
+                t[1][i][j] = mfma(fa[i].y, fb[j].x, t[1][i][j]);
+            }
+    } else if constexpr (NS == 3) {
+        T sa[FM], sb[FN];
+#pragma unroll
+        for (int i = 0; i < FM; ++i) sa[i] = fa[i].x + fa[i].y;
+#pragma unroll
+        for (int j = 0; j < FN; ++j) sb[j] = fb[j].x + fb[j].y;
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j) t[0][i][j] = mfma(fa[i].x, fb[j].x, t[0][i][j]);
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j) t[1][i][j] = mfma(fa[i].y, fb[j].y, t[1][i][j]);
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j) t[2][i][j] = mfma(sa[i], sb[j], t[2][i][j]);
+    } else {
+        // t[0] = real part, t[1] = imaginary part
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j) {
+                t[0][i][j] = mfma(fa[i].x, fb[j].x, t[0][i][j]);
+                t[1][i][j] = mfma(fa[i].x, fb[j].y, t[1][i][j]);
+            }
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j) {
+                t[0][i][j] = mfma(-fa[i].y, fb[j].y, t[0][i][j]);
+                t[1][i][j] = mfma(fa[i].y, fb[j].x, t[1][i][j]);
+            }
+    }
+}
+
+// Complex value held in accumulator register r of block (i, j): 3M (T1, T2, T3) -> (T1 - T2, T3 - T1 - T2).
+template <typename T, int NS, int FM, int FN>
+__device__ __forceinline__ void acc_value(const typename cplx<T>::acc (&t)[NS][FM][FN], int i, int j, int r, T &re,
+                                          T &im) {
+    if constexpr (NS == 3) {
+        re = t[0][i][j][r] - t[1][i][j][r];
+        im = t[2][i][j][r] - t[0][i][j][r] - t[1][i][j][r];
+    } else {
+        re = t[0][i][j][r];
+        im = t[1][i][j][r];
+    }
+}
+
+// Row of accumulator register r within a 16x16 block: f64 holds rows 4r + lane/16, f32 rows 4(lane/16) + r.
+template <typename T> __device__ __forceinline__ int acc_row(int lane, int r) {
+    return sizeof(T) == 8 ? 4 * r + (lane >> 4) : 4 * (lane >> 4) + r;
+}
+
 // One BM x BN output tile of C[b] = A[b] B[b]; `tile` enumerates (batch, m-tile, n-tile) with n fastest.
 template <typename TA, typename TB, typename TC, typename T, int BM, int BN, int BK, int RW>
 __device__ __forceinline__ void gemm_tile(const TA *__restrict__ A, const TB *__restrict__ B, TC *__restrict__ C,
@@ -118,57 +195,7 @@ __device__ __forceinline__ void gemm_tile(const TA *__restrict__ A, const TB *__
             for (int i = 0; i < FM; ++i) fa[i] = sA[kk + kl][rowA + i * 16];
 #pragma unroll
             for (int j = 0; j < FN; ++j) fb[j] = sB[kk + kl][colB + j * 16];
-            if constexpr (RW == 1) {
-#pragma unroll
-                for (int i = 0; i < FM; ++i)
-#pragma unroll
-                    for (int j = 0; j < FN; ++j) {
-                        t[0][i][j] = mfma(fa[i].x, fb[j].x, t[0][i][j]);
-                        t[1][i][j] = mfma(fa[i].x, fb[j].y, t[1][i][j]);
-                    }
-            } else if constexpr (RW == 2) {
-#pragma unroll
-                for (int i = 0; i < FM; ++i)
-#pragma unroll
-                    for (int j = 0; j < FN; ++j) {
-                        t[0][i][j] = mfma(fa[i].x, fb[j].x, t[0][i][j]);
-                        t[1][i][j] = mfma(fa[i].y, fb[j].x, t[1][i][j]);
-                    }
-            } else if constexpr (G3) {
-                T sa[FM], sb[FN];
-#pragma unroll
-                for (int i = 0; i < FM; ++i) sa[i] = fa[i].x + fa[i].y;
-#pragma unroll
-                for (int j = 0; j < FN; ++j) sb[j] = fb[j].x + fb[j].y;
-#pragma unroll
-                for (int i = 0; i < FM; ++i)
-#pragma unroll
-                    for (int j = 0; j < FN; ++j) t[0][i][j] = mfma(fa[i].x, fb[j].x, t[0][i][j]);
-#pragma unroll
-                for (int i = 0; i < FM; ++i)
-#pragma unroll
-                    for (int j = 0; j < FN; ++j) t[1][i][j] = mfma(fa[i].y, fb[j].y, t[1][i][j]);
-#pragma unroll
-                for (int i = 0; i < FM; ++i)
-#pragma unroll
-                    for (int j = 0; j < FN; ++j) t[NS - 1][i][j] = mfma(sa[i], sb[j], t[NS - 1][i][j]);
-            } else {
-                // t[0] = real part, t[1] = imaginary part
-#pragma unroll
-                for (int i = 0; i < FM; ++i)
-#pragma unroll
-                    for (int j = 0; j < FN; ++j) {
-                        t[0][i][j] = mfma(fa[i].x, fb[j].x, t[0][i][j]);
-                        t[1][i][j] = mfma(fa[i].x, fb[j].y, t[1][i][j]);
-                    }
-#pragma unroll
-                for (int i = 0; i < FM; ++i)
-#pragma unroll
-                    for (int j = 0; j < FN; ++j) {
-                        t[0][i][j] = mfma(-fa[i].y, fb[j].y, t[0][i][j]);
-                        t[1][i][j] = mfma(fa[i].y, fb[j].x, t[1][i][j]);
-                    }
-            }
+            mma_kstep<T, RW, NS>(t, fa, fb);
         }
     }
 
@@ -179,14 +206,11 @@ __device__ __forceinline__ void gemm_tile(const TA *__restrict__ A, const TB *__
             const int gn = n0 + wn * (BN / 2) + j * 16 + (lane & 15);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int rr = sizeof(T) == 8 ? 4 * r + (lane >> 4) : 4 * (lane >> 4) + r;
-                const int gm = m0 + wm * (BM / 2) + i * 16 + rr;
+                const int gm = m0 + wm * (BM / 2) + i * 16 + acc_row<T>(lane, r);
                 if (gm < d.M && gn < d.N) {
-                    if constexpr (G3)
-                        C[(long long)gm * d.ldc + gn] = pack<TC, T>(t[0][i][j][r] - t[1][i][j][r],
-                                                                    t[NS - 1][i][j][r] - t[0][i][j][r] - t[1][i][j][r]);
-                    else
-                        C[(long long)gm * d.ldc + gn] = pack<TC, T>(t[0][i][j][r], t[1][i][j][r]);
+                    T re, im;
+                    acc_value<T>(t, i, j, r, re, im);
+                    C[(long long)gm * d.ldc + gn] = pack<TC, T>(re, im);
                 }
             }
         }

@@ -16,6 +16,16 @@ using cd = std::complex<double>;
 bool eig_lambda_bar(int n, cd gamma, std::vector<cd> &d, std::vector<cd> &V, std::vector<cd> &Vinv,
                     std::string &err, double zeta = 1.0);
 
+// Lambda-bar = Q diag(Vs, Va) diag(ds, da) diag(Vsi, Vai) Q^T with Q the symmetric/skew butterfly (Lambda-bar is
+// centrosymmetric); blocks row-major, ms = ceil(n/2), ma = floor(n/2). The modes of eig_lambda_bar are [ds, da].
+struct EigFold {
+    int n = 0, ms = 0, ma = 0;
+    std::vector<cd> ds, Vs, Vsi, da, Va, Vai;
+};
+bool eig_lambda_bar_folded(int n, cd gamma, double zeta, EigFold &f, std::string &err);
+// the dense V, V^{-1} and eigenvalues of a folded decomposition (what eig_lambda_bar returns)
+void eig_fold_dense(const EigFold &f, std::vector<cd> &d, std::vector<cd> &V, std::vector<cd> &Vinv);
+
 // Stencil coefficients that depend only on the grid (the k^2-dependent parts are per node).
 struct StencilParams {
     int nx, ny, nz;
@@ -43,6 +53,31 @@ struct GemmDesc {
     long long sA, sB, sC;        // batch strides (0 = shared operand)
     int batch;
 };
+
+// Folded EigT transform (Lambda-bar centrosymmetric: V = Q diag(Vs, Va), modes [symmetric | skew]) over the
+// length-n axis of the data: x (rows = lines, each a contiguous row of n) or y (rows = columns x of a slice, the
+// axis strided by ld; batch slices sD apart). Data and result share the layout.
+struct FoldDesc {
+    int n, ms, ma;               // axis length, ceil(n/2), floor(n/2)
+    int rows;                    // x: number of lines; y: columns per slice
+    long long ld;                // stride between consecutive rows (x) or axis positions (y)
+    long long sD;                // slice stride (y)
+    int batch;                   // slices (y; 1 for x)
+};
+// the blocks of one axis, row-major: forward (x: [position][mode], y: [mode][position]) and inverse
+// (x: [mode][position], y: [position][mode]), each for the symmetric (ms x ms) and skew (ma x ma) half
+template <typename CT> struct FoldMats {
+    CT *fs = nullptr, *fa = nullptr, *is = nullptr, *ia = nullptr;
+};
+enum { FOLD_XF = 0, FOLD_YF = 1, FOLD_XI = 2, FOLD_YI = 3 };
+hipError_t launch_fold_z64(int mode, const FoldDesc &f, const double2 *D, const double2 *Ms, const double2 *Ma,
+                           double2 *C, hipStream_t s, int cfg);
+hipError_t launch_fold_z32(int mode, const FoldDesc &f, const float2 *D, const float2 *Ms, const float2 *Ma, float2 *C,
+                           hipStream_t s, int cfg);
+hipError_t launch_fold_z32_in64(int mode, const FoldDesc &f, const double2 *D, const float2 *Ms, const float2 *Ma,
+                                float2 *C, hipStream_t s, int cfg);
+hipError_t launch_fold_z32_out64(int mode, const FoldDesc &f, const float2 *D, const float2 *Ms, const float2 *Ma,
+                                 double2 *C, hipStream_t s, int cfg);
 
 // symbol of the compact operators with constant k0 (FFT4 / FFT6): order, h_a^2 per axis, k0^2
 struct SymParams {
@@ -117,6 +152,9 @@ struct Ctx {
     // EigT data (complex, row-major N x N). x: transposed for the B operand, y: as is for the A operand.
     double2 *BxF = nullptr, *BxI = nullptr, *AyF = nullptr, *AyI = nullptr;
     float2 *BxF32 = nullptr, *BxI32 = nullptr, *AyF32 = nullptr, *AyI32 = nullptr;
+    // the same transforms as symmetric / skew half blocks (what the single-problem preconditioner applies)
+    FoldMats<double2> fx64, fy64;
+    FoldMats<float2> fx32, fy32;
     double2 *dxe = nullptr, *dye = nullptr;    // eigenvalues d_x,i and d_y,j
     double ax, ay, c0;                          // alpha_x, alpha_y, h_z^2 k0^2 - 2(alpha_x + alpha_y + 1)
     int gemm_cfg[4] = {0, 0, 0, 0};             // tile configuration of the x64, y64, x32, y32 transforms

@@ -58,6 +58,28 @@ def test_host_eigensolver_collocated_zeta2(n, k0):
     assert abs(np.sort_complex(d) - ref).max() < 1e-11
 
 
+@pytest.mark.parametrize("n", [2, 3, 4, 7, 40, 41])
+@pytest.mark.parametrize("zeta", [1.0, 2.0])
+def test_host_eigensolver_small_and_centrosymmetric(n, zeta):
+    """Smallest axes (blocks of one or two modes) and the structure the preconditioner relies on: Lambda-bar has the
+    same closure at both ends, so the first ceil(n/2) eigenvectors are symmetric about the middle of the axis and the
+    rest skew; rows of V^{-1} likewise."""
+    helm = _lib()
+    k0 = 5.0
+    g = op.gamma_abc(k0, 1.0 / (n + 1)) if zeta == 1.0 else 2j * k0 / (n - 1)
+    d, V, Vi = helm.helm_eig1d(n, g, zeta)
+    L = op.lambda_bar(n, g, zeta).toarray()
+    assert abs(L @ V - V * d).max() < 1e-12
+    assert abs(Vi @ V - np.eye(n)).max() < 1e-11
+    ev = np.linalg.eigvals(L)
+    assert max(np.abs(ev - x).min() for x in d) < 1e-11
+    ms = n - n // 2
+    assert abs(V[:, :ms] - V[::-1, :ms]).max() < 1e-13
+    assert abs(V[:, ms:] + V[::-1, ms:]).max() < 1e-13
+    assert abs(Vi[:ms] - Vi[:ms, ::-1]).max() < 1e-13
+    assert abs(Vi[ms:] + Vi[ms:, ::-1]).max() < 1e-13
+
+
 def test_host_eigensolver_dirichlet_closed_form():
     helm = _lib()
     n = 17

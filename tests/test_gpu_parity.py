@@ -107,8 +107,9 @@ def test_rhs_parity(order):
     assert np.abs(F - Fr).max() <= 1e-12 * np.abs(Fr).max()
 
 
+# (4, 6, 150) and (3, 131, 5): half blocks of 75 and 66/65 modes, more than one 64-wide tile with a ragged tail
 @pytest.mark.parametrize("shape,bc", [((12, 20, 70), "abc"), ((33, 33, 33), "abc"), ((24, 24, 24), "dirichlet"),
-                                      ((5, 7, 3), "abc")])
+                                      ((5, 7, 3), "abc"), ((4, 6, 150), "abc"), ((3, 131, 5), "abc")])
 def test_precond_parity_fp64(shape, bc):
     h = H()
     h3 = (1.0 / (shape[2] + 1), 1.0 / (shape[1] + 1), 1.0 / (shape[0] + 1))
@@ -129,7 +130,7 @@ def test_precond_parity_fp64(shape, bc):
     assert np.linalg.norm(host(yd) - zr) <= 1e-11 * np.linalg.norm(zr)
 
 
-@pytest.mark.parametrize("shape", [(12, 20, 70), (33, 33, 33)])
+@pytest.mark.parametrize("shape", [(12, 20, 70), (33, 33, 33), (4, 6, 150), (3, 131, 5)])
 def test_precond_parity_fp32(shape):
     h = H()
     h3 = (1.0 / (shape[2] + 1), 1.0 / (shape[1] + 1), 1.0 / (shape[0] + 1))
@@ -300,11 +301,12 @@ def test_solve_pfft_matches_sparse_lu(fp32):
 
 
 @pytest.mark.parametrize("cfg", [0, 1, 2, 3])
-def test_gemm_tile_configs_parity(cfg):
-    """Every tile configuration the autotuner may pick computes the same EigT preconditioner."""
+@pytest.mark.parametrize("shape", [(12, 20, 70), (5, 135, 131)])
+def test_gemm_tile_configs_parity(cfg, shape):
+    """Every tile configuration the autotuner may pick computes the same EigT preconditioner (even axes, and odd
+    axes whose halves span several tiles with ragged tails)."""
     h = H()
-    shape = (12, 20, 70)
-    h3 = (1.0 / 71, 1.0 / 21, 1.0 / 13)
+    h3 = (1.0 / (shape[2] + 1), 1.0 / (shape[1] + 1), 1.0 / (shape[0] + 1))
     k0 = 0.47 / h3[0]
     k2 = np.full(tuple(s + 4 for s in shape), k0 * k0)
     ctx = h.helm_setup(dev(k2), h3, 4, k0=k0, shape=shape)
