@@ -106,7 +106,8 @@ helm_status helm_batch_create(helm_batch **out, helm_ctx *const *ctxs, int np, i
     // per-problem descriptors, work buffers and launch offsets
     long long tot_blocks_mv_target = 4096;
     std::vector<int> omv(1, 0), otri(1, 0), odot(1, 0), olc(1, 0);
-    std::vector<long long> ogx(1, 0), ogy(1, 0);
+    std::vector<long long> og[4];
+    for (auto &v : og) v.assign(1, 0);
     b->hP.resize(np);
     for (int p = 0; p < np; ++p) {
         Ctx &c = ctxs[p]->c;
@@ -122,14 +123,19 @@ helm_status helm_batch_create(helm_batch **out, helm_ctx *const *ctxs, int np, i
         }
         q.k2 = c.k2;
         q.fld = c.fld;
-        if (b->fp32) { q.BxF = c.BxF32; q.BxI = c.BxI32; q.AyF = c.AyF32; q.AyI = c.AyI32; }
-        else { q.BxF = c.BxF; q.BxI = c.BxI; q.AyF = c.AyF; q.AyI = c.AyI; }
+        if (b->fp32) {
+            q.xfs = c.fx32.fs; q.xfa = c.fx32.fa; q.xis = c.fx32.is; q.xia = c.fx32.ia;
+            q.yfs = c.fy32.fs; q.yfa = c.fy32.fa; q.yis = c.fy32.is; q.yia = c.fy32.ia;
+        } else {
+            q.xfs = c.fx64.fs; q.xfa = c.fx64.fa; q.xis = c.fx64.is; q.xia = c.fx64.ia;
+            q.yfs = c.fy64.fs; q.yfa = c.fy64.fa; q.yis = c.fy64.is; q.yia = c.fy64.ia;
+        }
         q.dxe = c.dxe;
         q.dye = c.dye;
         q.ax = c.ax; q.ay = c.ay; q.c0 = c.c0; q.hz2 = c.hz * c.hz;
         q.gz = make_double2(c.gamma[2].real(), c.gamma[2].imag());
-        q.dx = GemmDesc{c.ny * c.nz, c.nx, c.nx, c.nx, c.nx, c.nx, 0, 0, 0, 1};
-        q.dy = GemmDesc{c.ny, c.nx, c.ny, c.ny, c.nx, c.nx, 0, (long long)c.nx * c.ny, (long long)c.nx * c.ny, c.nz};
+        q.fx = FoldDesc{c.nx, c.nx - c.nx / 2, c.nx / 2, c.ny * c.nz, c.nx, 0, 1};
+        q.fy = FoldDesc{c.ny, c.ny - c.ny / 2, c.ny / 2, c.nx, c.nx, (long long)c.nx * c.ny, c.nz};
         q.n = c.n;
         q.nx = c.nx; q.ny = c.ny; q.nz = c.nz;
         q.nblk_dots = dots_blocks(c.n);
@@ -151,8 +157,10 @@ helm_status helm_batch_create(helm_batch **out, helm_ctx *const *ctxs, int np, i
         otri.push_back(otri.back() + (int)(((long long)c.nx * c.ny + tri_lx - 1) / tri_lx));
         odot.push_back(odot.back() + q.nblk_dots);
         olc.push_back(olc.back() + (int)((c.n + 1023) / 1024));
-        ogx.push_back(ogx.back() + (long long)((q.dx.M + bmx - 1) / bmx) * ((q.dx.N + bnx - 1) / bnx));
-        ogy.push_back(ogy.back() + (long long)((q.dy.M + bmy - 1) / bmy) * ((q.dy.N + bny - 1) / bny) * q.dy.batch);
+        og[0].push_back(og[0].back() + fold_tile_count(FOLD_XF, q.fx, bmx, bnx));
+        og[1].push_back(og[1].back() + fold_tile_count(FOLD_YF, q.fy, bmy, bny));
+        og[2].push_back(og[2].back() + fold_tile_count(FOLD_YI, q.fy, bmy, bny));
+        og[3].push_back(og[3].back() + fold_tile_count(FOLD_XI, q.fx, bmx, bnx));
     }
     BLaunch &L = b->L;
     if (balloc(*b, &b->dP, np) != hipSuccess || balloc(*b, &b->dst, np) != hipSuccess ||
@@ -164,14 +172,17 @@ helm_status helm_batch_create(helm_batch **out, helm_ctx *const *ctxs, int np, i
         return fail(HELM_ENOMEM, "state allocation failed");
     if (balloc(*b, &L.off.mv, np + 1) != hipSuccess || balloc(*b, &L.off.tri, np + 1) != hipSuccess ||
         balloc(*b, &L.off.dot, np + 1) != hipSuccess || balloc(*b, &L.off.lc, np + 1) != hipSuccess ||
-        balloc(*b, &L.off.gx, np + 1) != hipSuccess || balloc(*b, &L.off.gy, np + 1) != hipSuccess)
+        balloc(*b, &L.off.g[0], np + 1) != hipSuccess || balloc(*b, &L.off.g[1], np + 1) != hipSuccess ||
+        balloc(*b, &L.off.g[2], np + 1) != hipSuccess || balloc(*b, &L.off.g[3], np + 1) != hipSuccess)
         return fail(HELM_ENOMEM, "offset allocation failed");
     if (hipMemcpy(L.off.mv, omv.data(), omv.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(L.off.tri, otri.data(), otri.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(L.off.dot, odot.data(), odot.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(L.off.lc, olc.data(), olc.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(L.off.gx, ogx.data(), ogx.size() * sizeof(long long), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(L.off.gy, ogy.data(), ogy.size() * sizeof(long long), hipMemcpyHostToDevice) != hipSuccess)
+        hipMemcpy(L.off.g[0], og[0].data(), og[0].size() * sizeof(long long), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(L.off.g[1], og[1].data(), og[1].size() * sizeof(long long), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(L.off.g[2], og[2].data(), og[2].size() * sizeof(long long), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(L.off.g[3], og[3].data(), og[3].size() * sizeof(long long), hipMemcpyHostToDevice) != hipSuccess)
         return fail(HELM_EDEVICE, "offset upload failed");
     L.P = b->dP;
     L.st = b->dst;
@@ -188,10 +199,12 @@ helm_status helm_batch_create(helm_batch **out, helm_ctx *const *ctxs, int np, i
     L.tot_tri = otri.back();
     L.tot_dot = odot.back();
     L.tot_lc = olc.back();
-    L.tot_gx = ogx.back();
-    L.tot_gy = ogy.back();
+    long long gmax = 0;
+    for (int r = 0; r < 4; ++r) {
+        L.tot_g[r] = og[r].back();
+        gmax = std::max(gmax, L.tot_g[r]);
+    }
     // persistent GEMM grid: at most 4 workgroups per CU of a 256-CU device, never more than the tiles
-    long long gmax = std::max(L.tot_gx, L.tot_gy);
     L.gemm_grid = (int)std::max<long long>(1, std::min<long long>(gmax, 1024));
     *out = b;
     return HELM_OK;

@@ -70,6 +70,17 @@ template <typename CT> struct FoldMats {
     CT *fs = nullptr, *fa = nullptr, *is = nullptr, *ia = nullptr;
 };
 enum { FOLD_XF = 0, FOLD_YF = 1, FOLD_XI = 2, FOLD_YI = 3 };
+// tiles of a folded transform with bm x bn output tiles: the forward ones cover both halves' outputs, the inverse
+// ones the first half of the positions (each writes its mirror too)
+__host__ __device__ inline long long fold_tile_count(int mode, const FoldDesc &f, int bm, int bn) {
+    const long long tm = (f.rows + bm - 1) / bm, tn = (f.rows + bn - 1) / bn;
+    const long long hs_m = (f.ms + bm - 1) / bm, ha_m = (f.ma + bm - 1) / bm;
+    const long long hs_n = (f.ms + bn - 1) / bn, ha_n = (f.ma + bn - 1) / bn;
+    if (mode == FOLD_XF) return tm * (hs_n + ha_n);
+    if (mode == FOLD_YF) return (long long)f.batch * (hs_m + ha_m) * tn;
+    if (mode == FOLD_XI) return tm * hs_n;
+    return (long long)f.batch * hs_m * tn;
+}
 hipError_t launch_fold_z64(int mode, const FoldDesc &f, const double2 *D, const double2 *Ms, const double2 *Ma,
                            double2 *C, hipStream_t s, int cfg);
 hipError_t launch_fold_z32(int mode, const FoldDesc &f, const float2 *D, const float2 *Ms, const float2 *Ma, float2 *C,
@@ -149,7 +160,7 @@ struct Ctx {
     double *k2i = nullptr;       // complex k^2 only: imaginary parts of k^2 and of the field block
     double4 *fldi = nullptr;
 
-    // EigT data (complex, row-major N x N). x: transposed for the B operand, y: as is for the A operand.
+    // dense eigenvector matrices (complex, row-major N x N; x: transposed, y: as is), which PFFT's face corrections use
     double2 *BxF = nullptr, *BxI = nullptr, *AyF = nullptr, *AyI = nullptr;
     float2 *BxF32 = nullptr, *BxI32 = nullptr, *AyF32 = nullptr, *AyI32 = nullptr;
     // the same transforms as symmetric / skew half blocks (what the single-problem preconditioner applies)
@@ -223,11 +234,12 @@ struct BProb {                    // constant during a batched solve
     StencilParams sp;
     const double *k2;
     const double4 *fld;
-    const void *BxF, *BxI, *AyF, *AyI;     // eigenvector matrices (double2* or float2* by precision)
+    const void *xfs, *xfa, *xis, *xia;     // folded transform blocks (double2* or float2* by precision): x forward /
+    const void *yfs, *yfa, *yis, *yia;     // inverse and y forward / inverse, symmetric and skew halves
     const double2 *dxe, *dye;
     double ax, ay, c0, hz2;
     double2 gz;
-    GemmDesc dx, dy;
+    FoldDesc fx, fy;
     double2 *V, *Z, *x;
     const double2 *F;
     void *t1, *t2;                         // preconditioner work (element type by precision)
@@ -251,7 +263,7 @@ struct BArrays {                  // per-problem small arrays, problem p at p * 
 };
 struct BOffsets {                 // prefix sums of blocks/tiles per problem for each grouped launch
     int *mv, *tri, *dot, *lc;     // np + 1 each
-    long long *gx, *gy;           // GEMM tiles of the x- and y-transforms
+    long long *g[4];              // tiles of the x forward, y forward, y inverse and x inverse transforms
 };
 
 // ----- kernel launchers (defined in the .hip files); all enqueue on `s` and return hipError_t -----
@@ -325,7 +337,7 @@ struct BLaunch {
     BOffsets off;                 // device arrays
     int np, m, order, fp32;
     int tot_mv, tot_tri, tot_dot, tot_lc;       // total blocks per grouped launch
-    long long tot_gx, tot_gy;                   // total GEMM tiles
+    long long tot_g[4];                         // total transform tiles per role
     int gemm_grid;                              // persistent GEMM grid size
     int cfg_x, cfg_y;                           // GEMM tile configurations of the x- and y-transforms
     int tri_lx, tri_pb;                         // z-solve block: tri_lx lines x tri_pb chunks

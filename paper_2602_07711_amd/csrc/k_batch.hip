@@ -39,9 +39,10 @@ __device__ __forceinline__ int find_prob64(const long long *off, int np, long lo
 // ---------------------------------------------------------------------------------------------- GEMMs
 // ROLE 0: x-forward  t1 = V_j  W_xF       ROLE 1: y-forward  t2 = W_yF t1
 // ROLE 2: y-inverse  t1 = W_yI t2         ROLE 3: x-inverse  Z_j = t1 W_xI
+// (the folded transforms of the single-problem preconditioner: symmetric and skew half blocks of each axis)
 template <int ROLE, typename T, int BM, int BN, int BK>
-__global__ __launch_bounds__(256) void k_b_gemm(const BProb *__restrict__ P, const BState *__restrict__ st,
-                                                const long long *__restrict__ toff, int np, int j) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(fold_waves<T, BM, BN, BK>()))) void k_b_gemm(
+    const BProb *__restrict__ P, const BState *__restrict__ st, const long long *__restrict__ toff, int np, int j) {
     typedef typename cplx<T>::t CT;
     const long long total = toff[np];
     for (long long t = blockIdx.x; t < total; t += gridDim.x) {
@@ -50,13 +51,17 @@ __global__ __launch_bounds__(256) void k_b_gemm(const BProb *__restrict__ P, con
         const BProb &q = P[p];
         const long long lt = t - toff[p];
         if (ROLE == 0)
-            gemm_tile<double2, CT, CT, T, BM, BN, BK, 0>(q.V + (long long)j * q.n, (const CT *)q.BxF, (CT *)q.t1, q.dx, lt);
+            fold_tile<FOLD_XF, double2, CT, CT, T, BM, BN, BK>(q.V + (long long)j * q.n, (const CT *)q.xfs,
+                                                               (const CT *)q.xfa, (CT *)q.t1, q.fx, lt);
         else if (ROLE == 1)
-            gemm_tile<CT, CT, CT, T, BM, BN, BK, 0>((const CT *)q.AyF, (const CT *)q.t1, (CT *)q.t2, q.dy, lt);
+            fold_tile<FOLD_YF, CT, CT, CT, T, BM, BN, BK>((const CT *)q.t1, (const CT *)q.yfs, (const CT *)q.yfa,
+                                                          (CT *)q.t2, q.fy, lt);
         else if (ROLE == 2)
-            gemm_tile<CT, CT, CT, T, BM, BN, BK, 0>((const CT *)q.AyI, (const CT *)q.t2, (CT *)q.t1, q.dy, lt);
+            fold_tile<FOLD_YI, CT, CT, CT, T, BM, BN, BK>((const CT *)q.t2, (const CT *)q.yis, (const CT *)q.yia,
+                                                          (CT *)q.t1, q.fy, lt);
         else
-            gemm_tile<CT, CT, double2, T, BM, BN, BK, 0>((const CT *)q.t1, (const CT *)q.BxI, q.Z + (long long)j * q.n, q.dx, lt);
+            fold_tile<FOLD_XI, CT, CT, double2, T, BM, BN, BK>((const CT *)q.t1, (const CT *)q.xis, (const CT *)q.xia,
+                                                               q.Z + (long long)j * q.n, q.fx, lt);
     }
 }
 
@@ -343,12 +348,12 @@ void gemm_role(const BLaunch &L, hipStream_t s, int j, int cfg, const long long 
 }
 
 template <typename T> hipError_t precond_steps(const BLaunch &L, hipStream_t s, int j) {
-    gemm_role<0, T>(L, s, j, L.cfg_x, L.off.gx);
-    gemm_role<1, T>(L, s, j, L.cfg_y, L.off.gy);
+    gemm_role<0, T>(L, s, j, L.cfg_x, L.off.g[0]);
+    gemm_role<1, T>(L, s, j, L.cfg_y, L.off.g[1]);
     hipLaunchKernelGGL(k_b_tridiag<T>, dim3(L.tot_tri), dim3(L.tri_lx * L.tri_pb),
                        2 * sizeof(typename c2<T>::t) * (size_t)L.tri_lx * L.tri_pb, s, L.P, L.st, L.off.tri, L.np, L.tri_lx);
-    gemm_role<2, T>(L, s, j, L.cfg_y, L.off.gy);
-    gemm_role<3, T>(L, s, j, L.cfg_x, L.off.gx);
+    gemm_role<2, T>(L, s, j, L.cfg_y, L.off.g[2]);
+    gemm_role<3, T>(L, s, j, L.cfg_x, L.off.g[3]);
     return hipGetLastError();
 }
 
