@@ -132,16 +132,19 @@ def dst_matrix(n: int) -> np.ndarray:
 
 
 class PFFT:
-    """The PFFT direct solver of M z = y (Sec. 4.2, eq. PFFT_SOLVER), zeta = 1 on x and y.
+    """The PFFT direct solver of M z = y (Sec. 4.2, eq. PFFT_SOLVER).
 
     Step 1: Theta = (A_p^F)^{-1} Y with a 2D sine transform per slice (scipy DST-I) and z-solves.
     Step 2: A_p W = (A_p^F - A_p) Theta; the right-hand side lives on the faces i in {1, N_x} and
             j in {1, N_y} of every slice, and only W on those faces is used afterwards.
     Step 3: U = (A_p^F)^{-1} [Y + (A_p^F - A_p)(Theta + W)].
     A_p^F uses the Dirichlet Lambda in x and y and the absorbing Lambda-bar in z (eq. TFprec).
+    With zeta != 1 (the collocated closure) Lambda - Lambda-bar has rows 1 and N only, but each reaches two
+    layers: gamma on the face node and zeta - 1 on its inner neighbour (eq. lambda_mat_definition), so W is kept
+    on two layers per face.
     """
 
-    def __init__(self, shape, h3, k0: float, gammas):
+    def __init__(self, shape, h3, k0: float, gammas, zeta: complex = 1.0):
         self.shape = shape
         nz, ny, nx = shape
         hx, hy, hz = h3
@@ -152,7 +155,8 @@ class PFFT:
         lam_y = 2.0 * np.cos(np.pi * np.arange(1, ny + 1) / (ny + 1))
         self.bF = (self.ax * lam_x[None, :] + self.ay * lam_y[:, None] + hz * hz * k0 * k0
                    - 2.0 * (self.ax + self.ay + 1.0)).astype(np.complex128)
-        self.eig = EigT(shape, h3, k0, gammas)
+        self.zeta = zeta
+        self.eig = EigT(shape, h3, k0, gammas, zeta)
 
     @staticmethod
     def _dst2(Y):
@@ -161,27 +165,30 @@ class PFFT:
 
     def solve_F(self, Ys):
         """(A_p^F)^{-1} Ys for an h_z^2-scaled right-hand side."""
-        return self._dst2(thomas(self.bF, self.gz, self._dst2(Ys)))
+        return self._dst2(thomas(self.bF, self.gz, self._dst2(Ys), self.zeta))
 
     def E_apply(self, X):
-        """(A_p^F - A_p) X: -a_x gamma_x X on the x-faces and -a_y gamma_y X on the y-faces (eq. PFFT_SOLVER,
-        the vectors Theta^x_l, Theta^y_l with zeta = 1)."""
+        """(A_p^F - A_p) X = a_x (Lambda - Lambda-bar)_x X + a_y (Lambda - Lambda-bar)_y X: on the face row 1,
+        -a (gamma X_1 + (zeta - 1) X_2), and the mirror on row N (eq. PFFT_SOLVER, the vectors Theta^x_l,
+        Theta^y_l)."""
         out = np.zeros_like(X)
-        out[:, :, 0] -= self.ax * self.gx * X[:, :, 0]
-        out[:, :, -1] -= self.ax * self.gx * X[:, :, -1]
-        out[:, 0, :] -= self.ay * self.gy * X[:, 0, :]
-        out[:, -1, :] -= self.ay * self.gy * X[:, -1, :]
+        z1 = self.zeta - 1.0
+        out[:, :, 0] -= self.ax * (self.gx * X[:, :, 0] + z1 * X[:, :, 1])
+        out[:, :, -1] -= self.ax * (self.gx * X[:, :, -1] + z1 * X[:, :, -2])
+        out[:, 0, :] -= self.ay * (self.gy * X[:, 0, :] + z1 * X[:, 1, :])
+        out[:, -1, :] -= self.ay * (self.gy * X[:, -1, :] + z1 * X[:, -2, :])
         return out
 
     def solve(self, y: np.ndarray) -> np.ndarray:
         Ys = self.hz2 * y.reshape(self.shape)
         theta = self.solve_F(Ys)                                        # Step 1
         rhs_w = self.E_apply(theta)
-        W = self.eig.inverse(thomas(self.eig.bbar, self.gz, self.eig.forward(rhs_w)))  # Step 2
+        W = self.eig.inverse(thomas(self.eig.bbar, self.gz, self.eig.forward(rhs_w), self.zeta))  # Step 2
         ring = np.zeros(self.shape, bool)
-        ring[:, :, [0, -1]] = True
-        ring[:, [0, -1], :] = True
-        W = np.where(ring, W, 0.0)                                      # only W on the faces is kept
+        layers = [0, -1] if self.zeta == 1.0 else [0, 1, -2, -1]
+        ring[:, :, layers] = True
+        ring[:, layers, :] = True
+        W = np.where(ring, W, 0.0)                                      # only W where E reads it is kept
         U = self.solve_F(Ys + self.E_apply(theta + W))                  # Step 3
         return U.ravel()
 

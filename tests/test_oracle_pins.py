@@ -364,6 +364,32 @@ def test_eigt_collocated_zeta2_inverts_its_matrix():
     assert np.linalg.norm(M @ z - y) <= 1e-11 * np.linalg.norm(y)
 
 
+def test_pfft_collocated_zeta2_equals_eigt_and_inverts_its_matrix():
+    """PFFT with zeta = 2: the correction E = A_p^F - A_p reaches two layers per face, and the result must still be
+    the exact solve: equal to EigT(zeta = 2) and to the sparse LU of the collocated matrix (odd and even axes)."""
+    for shape in [(9, 11, 13), (8, 6, 10)]:
+        h3 = (1.0 / (shape[2] - 1), 1.0 / (shape[1] - 1), 1.0 / (shape[0] - 1))
+        k0 = 7.0
+        gs = tuple(2j * k0 * hh for hh in h3)
+        rng = np.random.default_rng(13)
+        y = rng.standard_normal(np.prod(shape)) + 1j * rng.standard_normal(np.prod(shape))
+        zp = pc.PFFT(shape, h3, k0, gs, zeta=2.0).solve(y)
+        ze = pc.EigT(shape, h3, k0, gs, zeta=2.0).solve(y)
+        M = pc.M_collocated(shape, h3, k0, gs)
+        assert np.linalg.norm(zp - ze) <= 1e-11 * np.linalg.norm(ze)
+        assert np.linalg.norm(M @ zp - y) <= 1e-11 * np.linalg.norm(y)
+        # one layer per face (dropping the zeta - 1 term's inner layer) is not the solve: the pin sees the second layer
+        p1 = pc.PFFT(shape, h3, k0, gs, zeta=2.0)
+        Ys = p1.hz2 * y.reshape(shape)
+        theta = p1.solve_F(Ys)
+        W = p1.eig.inverse(pc.thomas(p1.eig.bbar, p1.gz, p1.eig.forward(p1.E_apply(theta)), 2.0))
+        ring = np.zeros(shape, bool)
+        ring[:, :, [0, -1]] = True
+        ring[:, [0, -1], :] = True
+        bad = p1.solve_F(Ys + p1.E_apply(theta + np.where(ring, W, 0.0))).ravel()
+        assert np.linalg.norm(bad - ze) > 1e-3 * np.linalg.norm(ze)
+
+
 def _collocated_test_error(n):
     """The Sec. 5.1 test problem on the collocated grid x_j = j h, j = 0..N-1, h = 1/(N-1) (boundary nodes are
     unknowns): the second-order system with the three-point closure solved by EigT(zeta = 2)."""
