@@ -223,7 +223,7 @@ def bench_direct_sweep(H, torch, dev, sizes):
     Sec. 5.1 test problem (u = phi(x) phi(y) phi(z), k0^2 = 439.2, staggered nodes, two-point absorbing closure).
     Per grid: setup time, the direct-solve time of EigT (FP64/FP32) and PFFT (FP64/FP32) on the solve
     stream (mean of 3 after one untimed call), and max-err / L2-err of the FP64 EigT solution against u; then the
-    same for EigT with the collocated three-point closure (EigT3) on the nodes j/(N-1)."""
+    same for EigT and PFFT with the collocated three-point closure (EigT3, PFFT3) on the nodes j/(N-1)."""
     import math
     k0 = math.sqrt(439.2)
     rows = []
@@ -272,19 +272,20 @@ def bench_direct_sweep(H, torch, dev, sizes):
         k2 = torch.full((n, n, n), k0 * k0, dtype=torch.float64, device=dev)
         ctx = H.helm_setup(k2, 1.0 / (n - 1), 2, "abc3", k0, shape=(n, n, n))
         del k2
-        for fp32 in (False, True):
-            H.helm_precond_apply(ctx, fv, z, kind="eigt", fp32=fp32)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(3):
-                H.helm_precond_apply(ctx, fv, z, kind="eigt", fp32=fp32)
-            torch.cuda.synchronize()
-            row[f"eigt3_{'fp32' if fp32 else 'fp64'}_ms"] = round((time.perf_counter() - t0) / 3 * 1e3, 3)
-            if not fp32:
-                d = z.view(n, n, n) - u
-                row["eigt3_max_err"] = float(d.abs().max())
-                row["eigt3_l2_err"] = float(torch.linalg.vector_norm(d) / torch.linalg.vector_norm(u))
-                del d
+        for kind in ["eigt", "pfft"]:
+            for fp32 in (False, True):
+                H.helm_precond_apply(ctx, fv, z, kind=kind, fp32=fp32)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(3):
+                    H.helm_precond_apply(ctx, fv, z, kind=kind, fp32=fp32)
+                torch.cuda.synchronize()
+                row[f"{kind}3_{'fp32' if fp32 else 'fp64'}_ms"] = round((time.perf_counter() - t0) / 3 * 1e3, 3)
+                if not fp32:
+                    d = z.view(n, n, n) - u
+                    row[f"{kind}3_max_err"] = float(d.abs().max())
+                    row[f"{kind}3_l2_err"] = float(torch.linalg.vector_norm(d) / torch.linalg.vector_norm(u))
+                    del d
         log(f"direct solve {n}^3: {row}")
         rows.append(row)
         H.helm_destroy(ctx)

@@ -61,10 +61,11 @@ typedef enum {
     HELM_BC_ABC3 = 2       /* the three-point closure of collocated grids (Sec. 4.1, zeta = 2): the boundary
                               nodes are unknowns and the central difference of u_n + i k0 u = 0 eliminates the
                               ghost, so Lambda-bar has gamma = 2 i k0 h and zeta = 2 in its corners. Direct
-                              solves of the second-order system only (helm_precond_apply with HELM_PREC_EIGT,
-                              the EigT3 of Table 2); the paper does not give the high-order closures of its
-                              collocated runs, so helm_rhs, helm_matvec, helm_gmres_solve, helm_scale_guess,
-                              PFFT and batches return HELM_EUNSUPPORTED for such contexts                   */
+                              solves of the second-order system only (helm_precond_apply with HELM_PREC_EIGT or
+                              HELM_PREC_PFFT, the EigT3 and PFFT3 of Table 2); the paper does not give the
+                              high-order closures of its collocated runs, so helm_rhs, helm_matvec,
+                              helm_gmres_solve, helm_scale_guess and batches return HELM_EUNSUPPORTED for such
+                              contexts                                                                        */
 } helm_bc_kind;
 
 typedef struct {
@@ -75,7 +76,8 @@ typedef struct {
 
 typedef enum {
     HELM_PREC_EIGT = 0,    /* eigenvector transforms in x and y + z-tridiagonal solves (Sec. 4.1)            */
-    HELM_PREC_PFFT = 1,    /* sine transforms + boundary correction on the x/y faces (Sec. 4.2)               */
+    HELM_PREC_PFFT = 1,    /* sine transforms + boundary correction on the x/y faces (Sec. 4.2; two layers per
+                              face with the collocated closure)                                               */
     HELM_PREC_NONE = 2,    /* identity (unpreconditioned GMRES)                                              */
     HELM_PREC_FFT2 = 3,    /* the comparison preconditioner FFT2 of Sec. 5.1 (the earlier FFT-type approach
                               recalled at the start of Sec. 4): the same 7-point operator with constant k0 but

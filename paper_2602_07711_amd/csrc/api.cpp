@@ -185,13 +185,16 @@ helm_status eigt_apply(Ctx &c, const double2 *y, double2 *z, bool fp32, float2 *
 }
 
 // ---------------------------------------------------------------------------------------------------------
-// PFFT (Sec. 4.2, eq. PFFT_SOLVER), zeta = 1:
+// PFFT (Sec. 4.2, eq. PFFT_SOLVER):
 //   Step 1  Theta = (A_p^F)^{-1} Y: sine transforms in x and y (MFMA GEMMs against the real sine matrix),
 //           z-solves with the Dirichlet eigenvalues, Theta evaluated on the faces only (restricted inverse).
 //   Step 2  W = A_p^{-1} (A_p^F - A_p) Theta on the faces: sparse forward EigT transform of the face data,
 //           z-solves with the absorbing eigenvalues, restricted inverse EigT transform.
 //   Step 3  U = (A_p^F)^{-1} [Y + (A_p^F - A_p)(Theta + W)]: the sine transform of Y from Step 1 plus the sparse
 //           forward sine transform of the face correction, z-solves, full inverse sine transforms.
+// With the collocated closure (zeta = 2) A_p^F - A_p still lives on the face rows, but each face row also takes
+// (zeta - 1) times its inner neighbour (eq. lambda_mat_definition): Theta and W are evaluated on two layers per
+// face, and every z-solve carries the zeta closure.
 // ---------------------------------------------------------------------------------------------------------
 
 std::vector<cd> sine_matrix(int n) {
@@ -230,8 +233,9 @@ template <typename CT> helm_status build_ring_mats(Ctx &c, PfftMats<CT> &m) {
     ST_TRY(upload_one(c, c.hVy, c.ny, true, &m.VyT));
     ST_TRY(dalloc(c, &m.yhat, (size_t)c.n));
     size_t ring = (size_t)c.nz * (2 * c.nx + 2 * c.ny);
-    ST_TRY(dalloc(c, &m.ringT, ring));
-    ST_TRY(dalloc(c, &m.ringW, ring));
+    const size_t layers = c.zeta != 1.0 ? 2 : 1;     // the collocated closure reads a second layer per face
+    ST_TRY(dalloc(c, &m.ringT, layers * ring));
+    ST_TRY(dalloc(c, &m.ringW, layers * ring));
     ST_TRY(dalloc(c, &m.rpart, (size_t)c.nz * ring_rowgroups() * 2 * c.nx));
     ST_TRY(dalloc(c, &m.sv, (size_t)c.nz * 2 * c.ny));
     ST_TRY(dalloc(c, &m.rsum, (size_t)c.nz * 2 * c.nx));
@@ -300,10 +304,6 @@ GemmDesc desc_z(const Ctx &c) {
 }
 
 helm_status pfft_apply(Ctx &c, const double2 *y, double2 *z, bool fp32, float2 *z32 = nullptr) {
-    if (c.bc_kind == HELM_BC_ABC3) {
-        c.err = "PFFT is built for the two-point closure (zeta = 1) only";
-        return HELM_EUNSUPPORTED;
-    }
     ST_TRY(ensure_pfft(c, fp32));
     ST_TRY(ensure_tpiv(c, c.dxe, c.dye, &c.tpiv_eig));
     ST_TRY(ensure_tpiv(c, c.pfft->dFx, c.pfft->dFy, &c.tpiv_dir));
@@ -312,34 +312,46 @@ helm_status pfft_apply(Ctx &c, const double2 *y, double2 *z, bool fp32, float2 *
     const double2 gz = d2(c.gamma[2]);
     const double hz2 = c.hz * c.hz;
     const double2 ex = d2(-c.ax * c.gamma[0]), ey = d2(-c.ay * c.gamma[1]);
+    // collocated closure: E also reaches the inner neighbour of every face node with -a (zeta - 1)
+    const bool two = c.zeta != 1.0;
+    const double2 ex1 = make_double2(-c.ax * (c.zeta - 1.0), 0.0), ey1 = make_double2(-c.ay * (c.zeta - 1.0), 0.0);
+    const double zi = 1.0 / c.zeta;
     const int nx = c.nx, ny = c.ny, nz = c.nz;
+    const long long rsz = (long long)nz * (2 * nx + 2 * ny);
     // the same z-systems with the Dirichlet eigenvalues in x and y (A_p^F) or the absorbing ones (A_p)
-    const double ring_work = 16.0 * nz * (2.0 * nx + 2.0 * ny);
+    const double ring_work = 16.0 * nz * (2.0 * nx + 2.0 * ny) * (two ? 2 : 1);
+    const double ring_pass = two ? 2.0 : 1.0;
     if (!fp32) {
         auto &m = P.m64;
+        double2 *T1 = two ? m.ringT + rsz : nullptr, *W1 = two ? m.ringW + rsz : nullptr;
         HIP_TRY(timed(c, HELM_K_PFFT, 4.0 * dx.M * (double)dx.N * dx.K, [&] { return launch_gemm_z64(dx, y, m.Sx, c.t1, c.stream, 2); }));
         HIP_TRY(timed(c, HELM_K_PFFT, 4.0 * dy.M * (double)dy.N * dy.K * dy.batch, [&] { return launch_gemm_z64(dy, m.Sy, c.t1, m.yhat, c.stream, 1); }));
-        HIP_TRY(timed(c, HELM_K_TRIDIAG64, 32.0 * c.n, [&] { return launch_tridiag_chunk_z64(m.yhat, c.t2, c.tpiv_dir, P.dFx, P.dFy, nx, ny, nz, c.ax, c.ay, c.c0, gz, hz2, c.stream); }));
-        HIP_TRY(timed(c, HELM_K_RING, 16.0 * c.n + ring_work, [&] { return launch_ring_inverse_z64(c.t2, m.ringT, m.Sy, m.Sy, m.Sx, m.Sx, nx, ny, nz, m.rpart, m.sv, m.rsum, c.stream); }));
-        HIP_TRY(timed(c, HELM_K_RING, 16.0 * c.n + ring_work, [&] { return launch_ring_forward_z64(m.ringT, nullptr, nullptr, 0.0, c.t2, m.VyiT, c.BxF, ex, ey, nx, ny, nz, m.rbuf, m.fvec, c.stream); }));
-        HIP_TRY(timed(c, HELM_K_TRIDIAG64, 32.0 * c.n, [&] { return launch_tridiag_chunk_z64(c.t2, c.t2, c.tpiv_eig, c.dxe, c.dye, nx, ny, nz, c.ax, c.ay, c.c0, gz, 1.0, c.stream); }));
-        HIP_TRY(timed(c, HELM_K_RING, 16.0 * c.n + ring_work, [&] { return launch_ring_inverse_z64(c.t2, m.ringW, c.AyI, m.VyT, m.Vx, c.BxI, nx, ny, nz, m.rpart, m.sv, m.rsum, c.stream); }));
-        HIP_TRY(timed(c, HELM_K_RING, 32.0 * c.n + 2 * ring_work, [&] { return launch_ring_forward_z64(m.ringT, m.ringW, m.yhat, hz2, c.t2, m.Sy, m.Sx, ex, ey, nx, ny, nz, m.rbuf, m.fvec, c.stream); }));
-        HIP_TRY(timed(c, HELM_K_TRIDIAG64, 32.0 * c.n, [&] { return launch_tridiag_chunk_z64(c.t2, c.t2, c.tpiv_dir, P.dFx, P.dFy, nx, ny, nz, c.ax, c.ay, c.c0, gz, 1.0, c.stream); }));
+        HIP_TRY(timed(c, HELM_K_TRIDIAG64, 32.0 * c.n, [&] { return launch_tridiag_chunk_z64(m.yhat, c.t2, c.tpiv_dir, P.dFx, P.dFy, nx, ny, nz, c.ax, c.ay, c.c0, gz, hz2, c.stream, zi); }));
+        for (int layer = 0; layer < (two ? 2 : 1); ++layer)
+            HIP_TRY(timed(c, HELM_K_RING, 16.0 * c.n + ring_work / ring_pass, [&] { return launch_ring_inverse_z64(c.t2, m.ringT + layer * rsz, m.Sy, m.Sy, m.Sx, m.Sx, nx, ny, nz, layer, m.rpart, m.sv, m.rsum, c.stream); }));
+        HIP_TRY(timed(c, HELM_K_RING, 16.0 * c.n + ring_work, [&] { return launch_ring_forward_z64(m.ringT, nullptr, T1, nullptr, nullptr, 0.0, c.t2, m.VyiT, c.BxF, ex, ey, ex1, ey1, nx, ny, nz, m.rbuf, m.fvec, c.stream); }));
+        HIP_TRY(timed(c, HELM_K_TRIDIAG64, 32.0 * c.n, [&] { return launch_tridiag_chunk_z64(c.t2, c.t2, c.tpiv_eig, c.dxe, c.dye, nx, ny, nz, c.ax, c.ay, c.c0, gz, 1.0, c.stream, zi); }));
+        for (int layer = 0; layer < (two ? 2 : 1); ++layer)
+            HIP_TRY(timed(c, HELM_K_RING, 16.0 * c.n + ring_work / ring_pass, [&] { return launch_ring_inverse_z64(c.t2, m.ringW + layer * rsz, c.AyI, m.VyT, m.Vx, c.BxI, nx, ny, nz, layer, m.rpart, m.sv, m.rsum, c.stream); }));
+        HIP_TRY(timed(c, HELM_K_RING, 32.0 * c.n + 2 * ring_work, [&] { return launch_ring_forward_z64(m.ringT, m.ringW, T1, W1, m.yhat, hz2, c.t2, m.Sy, m.Sx, ex, ey, ex1, ey1, nx, ny, nz, m.rbuf, m.fvec, c.stream); }));
+        HIP_TRY(timed(c, HELM_K_TRIDIAG64, 32.0 * c.n, [&] { return launch_tridiag_chunk_z64(c.t2, c.t2, c.tpiv_dir, P.dFx, P.dFy, nx, ny, nz, c.ax, c.ay, c.c0, gz, 1.0, c.stream, zi); }));
         HIP_TRY(timed(c, HELM_K_PFFT, 4.0 * dy.M * (double)dy.N * dy.K * dy.batch, [&] { return launch_gemm_z64(dy, m.Sy, c.t2, c.t1, c.stream, 1); }));
         HIP_TRY(timed(c, HELM_K_PFFT, 4.0 * dx.M * (double)dx.N * dx.K, [&] { return launch_gemm_z64(dx, c.t1, m.Sx, z, c.stream, 2); }));
     } else {
         ST_TRY(ensure_fp32_work(c));
         auto &m = P.m32;
+        float2 *T1 = two ? m.ringT + rsz : nullptr, *W1 = two ? m.ringW + rsz : nullptr;
         HIP_TRY(timed(c, HELM_K_PFFT, 4.0 * dx.M * (double)dx.N * dx.K, [&] { return launch_gemm_z32_in64(dx, y, m.Sx, c.t1f, c.stream, 2); }));
         HIP_TRY(timed(c, HELM_K_PFFT, 4.0 * dy.M * (double)dy.N * dy.K * dy.batch, [&] { return launch_gemm_z32(dy, m.Sy, c.t1f, m.yhat, c.stream, 1); }));
-        HIP_TRY(timed(c, HELM_K_TRIDIAG32, 16.0 * c.n, [&] { return launch_tridiag_chunk_z32(m.yhat, c.t2f, c.tpiv_dir, P.dFx, P.dFy, nx, ny, nz, c.ax, c.ay, c.c0, gz, hz2, c.stream); }));
-        HIP_TRY(timed(c, HELM_K_RING, 8.0 * c.n + ring_work / 2, [&] { return launch_ring_inverse_z32(c.t2f, m.ringT, m.Sy, m.Sy, m.Sx, m.Sx, nx, ny, nz, m.rpart, m.sv, m.rsum, c.stream); }));
-        HIP_TRY(timed(c, HELM_K_RING, 8.0 * c.n + ring_work / 2, [&] { return launch_ring_forward_z32(m.ringT, nullptr, nullptr, 0.0, c.t2f, m.VyiT, c.BxF32, ex, ey, nx, ny, nz, m.rbuf, m.fvec, c.stream); }));
-        HIP_TRY(timed(c, HELM_K_TRIDIAG32, 16.0 * c.n, [&] { return launch_tridiag_chunk_z32(c.t2f, c.t2f, c.tpiv_eig, c.dxe, c.dye, nx, ny, nz, c.ax, c.ay, c.c0, gz, 1.0, c.stream); }));
-        HIP_TRY(timed(c, HELM_K_RING, 8.0 * c.n + ring_work / 2, [&] { return launch_ring_inverse_z32(c.t2f, m.ringW, c.AyI32, m.VyT, m.Vx, c.BxI32, nx, ny, nz, m.rpart, m.sv, m.rsum, c.stream); }));
-        HIP_TRY(timed(c, HELM_K_RING, 16.0 * c.n + ring_work, [&] { return launch_ring_forward_z32(m.ringT, m.ringW, m.yhat, hz2, c.t2f, m.Sy, m.Sx, ex, ey, nx, ny, nz, m.rbuf, m.fvec, c.stream); }));
-        HIP_TRY(timed(c, HELM_K_TRIDIAG32, 16.0 * c.n, [&] { return launch_tridiag_chunk_z32(c.t2f, c.t2f, c.tpiv_dir, P.dFx, P.dFy, nx, ny, nz, c.ax, c.ay, c.c0, gz, 1.0, c.stream); }));
+        HIP_TRY(timed(c, HELM_K_TRIDIAG32, 16.0 * c.n, [&] { return launch_tridiag_chunk_z32(m.yhat, c.t2f, c.tpiv_dir, P.dFx, P.dFy, nx, ny, nz, c.ax, c.ay, c.c0, gz, hz2, c.stream, zi); }));
+        for (int layer = 0; layer < (two ? 2 : 1); ++layer)
+            HIP_TRY(timed(c, HELM_K_RING, 8.0 * c.n + ring_work / 2 / ring_pass, [&] { return launch_ring_inverse_z32(c.t2f, m.ringT + layer * rsz, m.Sy, m.Sy, m.Sx, m.Sx, nx, ny, nz, layer, m.rpart, m.sv, m.rsum, c.stream); }));
+        HIP_TRY(timed(c, HELM_K_RING, 8.0 * c.n + ring_work / 2, [&] { return launch_ring_forward_z32(m.ringT, nullptr, T1, nullptr, nullptr, 0.0, c.t2f, m.VyiT, c.BxF32, ex, ey, ex1, ey1, nx, ny, nz, m.rbuf, m.fvec, c.stream); }));
+        HIP_TRY(timed(c, HELM_K_TRIDIAG32, 16.0 * c.n, [&] { return launch_tridiag_chunk_z32(c.t2f, c.t2f, c.tpiv_eig, c.dxe, c.dye, nx, ny, nz, c.ax, c.ay, c.c0, gz, 1.0, c.stream, zi); }));
+        for (int layer = 0; layer < (two ? 2 : 1); ++layer)
+            HIP_TRY(timed(c, HELM_K_RING, 8.0 * c.n + ring_work / 2 / ring_pass, [&] { return launch_ring_inverse_z32(c.t2f, m.ringW + layer * rsz, c.AyI32, m.VyT, m.Vx, c.BxI32, nx, ny, nz, layer, m.rpart, m.sv, m.rsum, c.stream); }));
+        HIP_TRY(timed(c, HELM_K_RING, 16.0 * c.n + ring_work, [&] { return launch_ring_forward_z32(m.ringT, m.ringW, T1, W1, m.yhat, hz2, c.t2f, m.Sy, m.Sx, ex, ey, ex1, ey1, nx, ny, nz, m.rbuf, m.fvec, c.stream); }));
+        HIP_TRY(timed(c, HELM_K_TRIDIAG32, 16.0 * c.n, [&] { return launch_tridiag_chunk_z32(c.t2f, c.t2f, c.tpiv_dir, P.dFx, P.dFy, nx, ny, nz, c.ax, c.ay, c.c0, gz, 1.0, c.stream, zi); }));
         HIP_TRY(timed(c, HELM_K_PFFT, 4.0 * dy.M * (double)dy.N * dy.K * dy.batch, [&] { return launch_gemm_z32(dy, m.Sy, c.t2f, c.t1f, c.stream, 1); }));
         HIP_TRY(timed(c, HELM_K_PFFT, 4.0 * dx.M * (double)dx.N * dx.K, [&] { return z32 ? launch_gemm_z32(dx, c.t1f, m.Sx, z32, c.stream, 2) : launch_gemm_z32_out64(dx, c.t1f, m.Sx, z, c.stream, 2); }));
     }
@@ -831,7 +843,7 @@ helm_status helm_rhs(helm_ctx *ctx, const void *f_dev, void *F_dev) {
     if (!ctx) return HELM_EINVAL;
     Ctx &c = ctx->c;
     if (c.bc_kind == HELM_BC_ABC3) {
-        c.err = "the collocated three-point closure supports direct solves with the EigT preconditioner only";
+        c.err = "the collocated three-point closure supports direct solves with the EigT and PFFT preconditioners only";
         return HELM_EUNSUPPORTED;
     }
     if (!f_dev || !F_dev) { c.err = "NULL pointer"; return HELM_EINVAL; }
@@ -844,7 +856,7 @@ helm_status helm_matvec(helm_ctx *ctx, const void *x_dev, void *y_dev) {
     if (!ctx) return HELM_EINVAL;
     Ctx &c = ctx->c;
     if (c.bc_kind == HELM_BC_ABC3) {
-        c.err = "the collocated three-point closure supports direct solves with the EigT preconditioner only";
+        c.err = "the collocated three-point closure supports direct solves with the EigT and PFFT preconditioners only";
         return HELM_EUNSUPPORTED;
     }
     if (!x_dev || !y_dev) { c.err = "NULL pointer"; return HELM_EINVAL; }
@@ -857,7 +869,7 @@ helm_status helm_scale_guess(helm_ctx *ctx, const void *F_dev, void *x_dev, doub
     if (!ctx) return HELM_EINVAL;
     Ctx &c = ctx->c;
     if (c.bc_kind == HELM_BC_ABC3) {
-        c.err = "the collocated three-point closure supports direct solves with the EigT preconditioner only";
+        c.err = "the collocated three-point closure supports direct solves with the EigT and PFFT preconditioners only";
         return HELM_EUNSUPPORTED;
     }
     if (!F_dev || !x_dev) { c.err = "NULL pointer"; return HELM_EINVAL; }
@@ -904,7 +916,7 @@ helm_status helm_gmres_solve(helm_ctx *ctx, const void *F_dev, void *x_dev, cons
     if (!ctx) return HELM_EINVAL;
     Ctx &c = ctx->c;
     if (c.bc_kind == HELM_BC_ABC3) {
-        c.err = "the collocated three-point closure supports direct solves with the EigT preconditioner only";
+        c.err = "the collocated three-point closure supports direct solves with the EigT and PFFT preconditioners only";
         return HELM_EUNSUPPORTED;
     }
     if (!F_dev || !x_dev || !opts) { c.err = "NULL pointer"; return HELM_EINVAL; }

@@ -304,18 +304,22 @@ hipError_t launch_tridiag_chunk_z32(const float2 *in, float2 *out, const double2
                                     double2 gz, double scale, hipStream_t s, double zi = 1.0);
 int ring_rowgroups();
 int ring_max_n();            // widest N_x the PFFT ring pass supports
+// layer 0: the face rows 1, N_y and columns 1, N_x; layer 1: rows 2, N_y - 1 and columns 2, N_x - 1 (zeta != 1)
 hipError_t launch_ring_inverse_z64(const double2 *Xh, double2 *ring, const double2 *Vy, const double2 *VyT,
-                                   const double2 *Vx, const double2 *VxT, int nx, int ny, int nz, double2 *rpart,
-                                   double2 *sv, double2 *rsum, hipStream_t s);
+                                   const double2 *Vx, const double2 *VxT, int nx, int ny, int nz, int layer,
+                                   double2 *rpart, double2 *sv, double2 *rsum, hipStream_t s);
 hipError_t launch_ring_inverse_z32(const float2 *Xh, float2 *ring, const float2 *Vy, const float2 *VyT,
-                                   const float2 *Vx, const float2 *VxT, int nx, int ny, int nz, float2 *rpart,
-                                   float2 *sv, float2 *rsum, hipStream_t s);
-hipError_t launch_ring_forward_z64(const double2 *ra, const double2 *rb, const double2 *base, double base_scale,
-                                   double2 *out, const double2 *WyT, const double2 *WxT, double2 ex, double2 ey,
-                                   int nx, int ny, int nz, double2 *rbuf, double2 *fvec, hipStream_t s);
-hipError_t launch_ring_forward_z32(const float2 *ra, const float2 *rb, const float2 *base, double base_scale,
-                                   float2 *out, const float2 *WyT, const float2 *WxT, double2 ex, double2 ey, int nx,
-                                   int ny, int nz, float2 *rbuf, float2 *fvec, hipStream_t s);
+                                   const float2 *Vx, const float2 *VxT, int nx, int ny, int nz, int layer,
+                                   float2 *rpart, float2 *sv, float2 *rsum, hipStream_t s);
+// ra1, rb1: the second-layer rings (zeta != 1) or null; ex1, ey1 = -a (zeta - 1) per axis
+hipError_t launch_ring_forward_z64(const double2 *ra, const double2 *rb, const double2 *ra1, const double2 *rb1,
+                                   const double2 *base, double base_scale, double2 *out, const double2 *WyT,
+                                   const double2 *WxT, double2 ex, double2 ey, double2 ex1, double2 ey1, int nx,
+                                   int ny, int nz, double2 *rbuf, double2 *fvec, hipStream_t s);
+hipError_t launch_ring_forward_z32(const float2 *ra, const float2 *rb, const float2 *ra1, const float2 *rb1,
+                                   const float2 *base, double base_scale, float2 *out, const float2 *WyT,
+                                   const float2 *WxT, double2 ex, double2 ey, double2 ex1, double2 ey1, int nx, int ny,
+                                   int nz, float2 *rbuf, float2 *fvec, hipStream_t s);
 
 // Krylov helpers
 int dots_blocks(long long n);

@@ -11,10 +11,14 @@
 //   boundary columns via s_i = Xh V_x[i,:]^T then X[j,i] = sum_m V_y[j,m] s_i[m]. The pass over the data runs
 //   with several row groups per slice; the products with V_x^T and V_y^T are GEMMs over all slices.
 // Forward (k_ring_fwd_R, two GEMMs, k_ring_fwd_write): the forward transform of ring-supported data R (Steps 1, 2*):
-//   R = E (a + b) with E the diagonal (A_p^F - A_p) restricted to the faces, E = -a_x gamma_x on the x-faces plus
-//   -a_y gamma_y on the y-faces; out = s * base + W_y R W_x^T computed as two rank-2 updates from the boundary rows
-//   (S_m = R[m,:] W_x^T) and the interior parts of the boundary columns (T_k = W_y[:, inner] R[inner, k]); the
-//   factors as GEMMs over all slices, then every element in parallel.
+//   R = E (a + b) with E = A_p^F - A_p restricted to the faces: on face row 1 of an axis -a (gamma v_1 + (zeta - 1)
+//   v_2), and the mirror on row N (eq. lambda_mat_definition); with zeta = 1 only the face layer enters. out = s *
+//   base + W_y R W_x^T computed as two rank-2 updates from the boundary rows (S_m = R[m,:] W_x^T) and the interior
+//   parts of the boundary columns (T_k = W_y[:, inner] R[inner, k]); the factors as GEMMs over all slices, then
+//   every element in parallel.
+// Second layer (zeta != 1): the inverse is run a second time for rows 2, N_y - 1 and columns 2, N_x - 1 into a
+// second ring of the same layout; R takes the inner neighbours from it (the x-neighbours of the corners from the
+// full boundary rows of the first).
 #include "helm_internal.h"
 
 namespace helm {
@@ -48,15 +52,16 @@ template <typename T> __device__ __forceinline__ T wsum(T v) {
 constexpr int RING_RG = 8; // row groups per slice in the inverse's pass over the data
 constexpr int RING_NMAX = 64 * 13;   // widest slice the ring pass supports (MAXC = 13 chunks of 64 columns)
 
-// Inverse, pass over the data: block (slice l, row group rg) takes rows m of its group and accumulates, per
-// column k, r0[k] += V_y[0][m] X[m][k] and rN[k] += V_y[ny-1][m] X[m][k] (partials per group), and per row the
-// complete s0[m] = sum_k V_x[0][k] X[m][k], sN[m] = sum_k V_x[nx-1][k] X[m][k]. Each lane holds MAXC chunks of
-// 64 columns (N_x <= 64 MAXC; the launcher picks 4, 8 or 13).
+// Inverse, pass over the data for face layer `layer` (0: rows/columns 1 and N, 1: 2 and N-1): block (slice l,
+// row group rg) takes rows m of its group and accumulates, per column k, r0[k] += V_y[ja][m] X[m][k] and
+// rN[k] += V_y[jb][m] X[m][k] (partials per group; ja = layer, jb = ny-1-layer), and per row the complete
+// s0[m] = sum_k V_x[ia][k] X[m][k], sN[m] = sum_k V_x[ib][k] X[m][k] (ia = layer, ib = nx-1-layer). Each lane
+// holds MAXC chunks of 64 columns (N_x <= 64 MAXC; the launcher picks 4, 8 or 13).
 template <typename T, int MAXC>
 __global__ __launch_bounds__(256) void k_ring_inv_rows(const typename c2<T>::t *__restrict__ Xh,
                                                        const typename c2<T>::t *__restrict__ Vy,
                                                        const typename c2<T>::t *__restrict__ Vx, int nx, int ny,
-                                                       typename c2<T>::t *__restrict__ rpart,
+                                                       int layer, typename c2<T>::t *__restrict__ rpart,
                                                        typename c2<T>::t *__restrict__ sv) {
     typedef typename c2<T>::t CT;
     __shared__ CT red[4][2][64 * MAXC];
@@ -69,14 +74,14 @@ __global__ __launch_bounds__(256) void k_ring_inv_rows(const typename c2<T>::t *
 #pragma unroll
     for (int c = 0; c < MAXC; ++c) {
         const int k = lane + 64 * c;
-        vx0[c] = k < nx ? Vx[k] : cz<CT>();
-        vxN[c] = k < nx ? Vx[(long long)(nx - 1) * nx + k] : cz<CT>();
+        vx0[c] = k < nx ? Vx[(long long)layer * nx + k] : cz<CT>();
+        vxN[c] = k < nx ? Vx[(long long)(nx - 1 - layer) * nx + k] : cz<CT>();
         a0[c] = cz<CT>();
         aN[c] = cz<CT>();
     }
     for (int m = m0 + wave; m < m1; m += 4) {
         const CT *row = X + (long long)m * nx;
-        const CT w0 = Vy[m], wN = Vy[(long long)(ny - 1) * ny + m];
+        const CT w0 = Vy[(long long)layer * ny + m], wN = Vy[(long long)(ny - 1 - layer) * ny + m];
         CT s0 = cz<CT>(), sN = cz<CT>();
 #pragma unroll
         for (int c = 0; c < MAXC; ++c) {
@@ -125,27 +130,46 @@ __global__ void k_ring_inv_sum(const typename c2<T>::t *__restrict__ rpart, int 
     rsum[e] = acc;
 }
 
-// Forward: R = E (a + b) on the faces (E = -a_x gamma_x on the x-faces plus -a_y gamma_y on the y-faces): the
-// boundary rows Rr[l][w][k] in full and the interior parts of the boundary columns Rc[l][w][m] (ends zero)
+// Forward: R = E (a + b) on the faces: the boundary rows Rr[l][w][k] in full and the interior parts of the
+// boundary columns Rc[l][w][m] (ends zero). E on face row 1 of an axis is -a (gamma v_1 + (zeta - 1) v_2): ex, ey
+// are -a gamma and ex1, ey1 -a (zeta - 1) per axis; ra1, rb1 (the second-layer rings) only when zeta != 1.
 template <typename T>
 __global__ void k_ring_fwd_R(const typename c2<T>::t *__restrict__ ra, const typename c2<T>::t *__restrict__ rb,
-                             double2 ex, double2 ey, int nx, int ny, int nz, typename c2<T>::t *__restrict__ Rr,
-                             typename c2<T>::t *__restrict__ Rc) {
+                             const typename c2<T>::t *__restrict__ ra1, const typename c2<T>::t *__restrict__ rb1,
+                             double2 ex, double2 ey, double2 ex1, double2 ey1, int nx, int ny, int nz,
+                             typename c2<T>::t *__restrict__ Rr, typename c2<T>::t *__restrict__ Rc) {
     typedef typename c2<T>::t CT;
     const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
     const long long nrow = 2LL * nz * nx, ncol = 2LL * nz * ny;
     if (e >= nrow + ncol) return;
-    CT ecx, ecy;
+    CT ecx, ecy, ecx1, ecy1;
     ecx.x = (T)ex.x; ecx.y = (T)ex.y;
     ecy.x = (T)ey.x; ecy.y = (T)ey.y;
-    CT v = ra[e];
-    if (rb) v = cadd(v, rb[e]);
+    ecx1.x = (T)ex1.x; ecx1.y = (T)ex1.y;
+    ecy1.x = (T)ey1.x; ecy1.y = (T)ey1.y;
+    auto val = [&](const CT *a, const CT *b, long long i) {
+        CT v = a[i];
+        if (b) v = cadd(v, b[i]);
+        return v;
+    };
+    const CT v = val(ra, rb, e);
     if (e < nrow) {
         const int k = (int)(e % nx);
-        Rr[e] = cmul((k == 0 || k == nx - 1) ? cadd(ecx, ecy) : ecy, v);
+        CT r = cmul(ecy, v);
+        if (ra1) r = cfma(ecy1, val(ra1, rb1, e), r);                 // inner neighbour across the y-face
+        if (k == 0 || k == nx - 1) {
+            r = cfma(ecx, v, r);
+            if (ra1) r = cfma(ecx1, val(ra, rb, k == 0 ? e + 1 : e - 1), r);   // inner neighbour along the row
+        }
+        Rr[e] = r;
     } else {
         const int m = (int)((e - nrow) % ny);
-        Rc[e - nrow] = (m > 0 && m < ny - 1) ? cmul(ecx, v) : cz<CT>();
+        CT r = cz<CT>();
+        if (m > 0 && m < ny - 1) {
+            r = cmul(ecx, v);
+            if (ra1) r = cfma(ecx1, val(ra1, rb1, e), r);             // inner neighbour across the x-face
+        }
+        Rc[e - nrow] = r;
     }
 }
 
@@ -190,16 +214,18 @@ inline GemmDesc plain_desc(int M, int N, int K) { return GemmDesc{M, N, K, K, N,
 template <typename T>
 hipError_t inv_launch(const typename c2<T>::t *Xh, typename c2<T>::t *ring, const typename c2<T>::t *Vy,
                       const typename c2<T>::t *VyT, const typename c2<T>::t *Vx, const typename c2<T>::t *VxT, int nx,
-                      int ny, int nz, typename c2<T>::t *rpart, typename c2<T>::t *sv, typename c2<T>::t *rsum,
-                      hipStream_t s) {
-    if (nx > RING_NMAX || ny > RING_NMAX) return hipErrorInvalidValue;
+                      int ny, int nz, int layer, typename c2<T>::t *rpart, typename c2<T>::t *sv,
+                      typename c2<T>::t *rsum, hipStream_t s) {
+    if (nx > RING_NMAX || ny > RING_NMAX || layer < 0 || layer > 1 || nx < 2 || ny < 2) return hipErrorInvalidValue;
     if (nx <= 256)
-        hipLaunchKernelGGL((k_ring_inv_rows<T, 4>), dim3(nz * RING_RG), dim3(256), 0, s, Xh, Vy, Vx, nx, ny, rpart, sv);
-    else if (nx <= 512)
-        hipLaunchKernelGGL((k_ring_inv_rows<T, 8>), dim3(nz * RING_RG), dim3(256), 0, s, Xh, Vy, Vx, nx, ny, rpart, sv);
-    else
-        hipLaunchKernelGGL((k_ring_inv_rows<T, 13>), dim3(nz * RING_RG), dim3(256), 0, s, Xh, Vy, Vx, nx, ny, rpart,
+        hipLaunchKernelGGL((k_ring_inv_rows<T, 4>), dim3(nz * RING_RG), dim3(256), 0, s, Xh, Vy, Vx, nx, ny, layer, rpart,
                            sv);
+    else if (nx <= 512)
+        hipLaunchKernelGGL((k_ring_inv_rows<T, 8>), dim3(nz * RING_RG), dim3(256), 0, s, Xh, Vy, Vx, nx, ny, layer, rpart,
+                           sv);
+    else
+        hipLaunchKernelGGL((k_ring_inv_rows<T, 13>), dim3(nz * RING_RG), dim3(256), 0, s, Xh, Vy, Vx, nx, ny, layer,
+                           rpart, sv);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const long long nr = 2LL * nz * nx;
@@ -213,14 +239,16 @@ hipError_t inv_launch(const typename c2<T>::t *Xh, typename c2<T>::t *ring, cons
 
 // work: Rr (Nz * 2 Nx) and Rc (Nz * 2 Ny) contiguous in rbuf, fvec (Nz * (2 Nx + 2 Ny))
 template <typename T>
-hipError_t fwd_launch(const typename c2<T>::t *ra, const typename c2<T>::t *rb, const typename c2<T>::t *base,
-                      double base_scale, typename c2<T>::t *out, const typename c2<T>::t *WyT,
-                      const typename c2<T>::t *WxT, double2 ex, double2 ey, int nx, int ny, int nz,
-                      typename c2<T>::t *rbuf, typename c2<T>::t *fvec, hipStream_t s) {
+hipError_t fwd_launch(const typename c2<T>::t *ra, const typename c2<T>::t *rb, const typename c2<T>::t *ra1,
+                      const typename c2<T>::t *rb1, const typename c2<T>::t *base, double base_scale,
+                      typename c2<T>::t *out, const typename c2<T>::t *WyT, const typename c2<T>::t *WxT, double2 ex,
+                      double2 ey, double2 ex1, double2 ey1, int nx, int ny, int nz, typename c2<T>::t *rbuf,
+                      typename c2<T>::t *fvec, hipStream_t s) {
     const long long nr = 2LL * nz * nx, nc = 2LL * nz * ny;
+    if (nx < 2 || ny < 2 || (rb1 && !ra1)) return hipErrorInvalidValue;
     typename c2<T>::t *Rr = rbuf, *Rc = rbuf + nr;
-    hipLaunchKernelGGL(k_ring_fwd_R<T>, dim3((unsigned)((nr + nc + 255) / 256)), dim3(256), 0, s, ra, rb, ex, ey, nx,
-                       ny, nz, Rr, Rc);
+    hipLaunchKernelGGL(k_ring_fwd_R<T>, dim3((unsigned)((nr + nc + 255) / 256)), dim3(256), 0, s, ra, rb, ra1, rb1, ex,
+                       ey, ex1, ey1, nx, ny, nz, Rr, Rc);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if ((e = gemm_c(plain_desc(2 * nz, nx, nx), Rr, WxT, fvec, s)) != hipSuccess) return e;        // S = Rr W_x^T
@@ -284,24 +312,28 @@ int ring_rowgroups() { return RING_RG; }
 int ring_max_n() { return RING_NMAX; }
 
 hipError_t launch_ring_inverse_z64(const double2 *Xh, double2 *ring, const double2 *Vy, const double2 *VyT,
-                                   const double2 *Vx, const double2 *VxT, int nx, int ny, int nz, double2 *rpart,
-                                   double2 *sv, double2 *rsum, hipStream_t s) {
-    return inv_launch<double>(Xh, ring, Vy, VyT, Vx, VxT, nx, ny, nz, rpart, sv, rsum, s);
+                                   const double2 *Vx, const double2 *VxT, int nx, int ny, int nz, int layer,
+                                   double2 *rpart, double2 *sv, double2 *rsum, hipStream_t s) {
+    return inv_launch<double>(Xh, ring, Vy, VyT, Vx, VxT, nx, ny, nz, layer, rpart, sv, rsum, s);
 }
 hipError_t launch_ring_inverse_z32(const float2 *Xh, float2 *ring, const float2 *Vy, const float2 *VyT,
-                                   const float2 *Vx, const float2 *VxT, int nx, int ny, int nz, float2 *rpart,
-                                   float2 *sv, float2 *rsum, hipStream_t s) {
-    return inv_launch<float>(Xh, ring, Vy, VyT, Vx, VxT, nx, ny, nz, rpart, sv, rsum, s);
+                                   const float2 *Vx, const float2 *VxT, int nx, int ny, int nz, int layer,
+                                   float2 *rpart, float2 *sv, float2 *rsum, hipStream_t s) {
+    return inv_launch<float>(Xh, ring, Vy, VyT, Vx, VxT, nx, ny, nz, layer, rpart, sv, rsum, s);
 }
-hipError_t launch_ring_forward_z64(const double2 *ra, const double2 *rb, const double2 *base, double base_scale,
-                                   double2 *out, const double2 *WyT, const double2 *WxT, double2 ex, double2 ey,
-                                   int nx, int ny, int nz, double2 *rbuf, double2 *fvec, hipStream_t s) {
-    return fwd_launch<double>(ra, rb, base, base_scale, out, WyT, WxT, ex, ey, nx, ny, nz, rbuf, fvec, s);
+hipError_t launch_ring_forward_z64(const double2 *ra, const double2 *rb, const double2 *ra1, const double2 *rb1,
+                                   const double2 *base, double base_scale, double2 *out, const double2 *WyT,
+                                   const double2 *WxT, double2 ex, double2 ey, double2 ex1, double2 ey1, int nx,
+                                   int ny, int nz, double2 *rbuf, double2 *fvec, hipStream_t s) {
+    return fwd_launch<double>(ra, rb, ra1, rb1, base, base_scale, out, WyT, WxT, ex, ey, ex1, ey1, nx, ny, nz, rbuf,
+                              fvec, s);
 }
-hipError_t launch_ring_forward_z32(const float2 *ra, const float2 *rb, const float2 *base, double base_scale,
-                                   float2 *out, const float2 *WyT, const float2 *WxT, double2 ex, double2 ey, int nx,
-                                   int ny, int nz, float2 *rbuf, float2 *fvec, hipStream_t s) {
-    return fwd_launch<float>(ra, rb, base, base_scale, out, WyT, WxT, ex, ey, nx, ny, nz, rbuf, fvec, s);
+hipError_t launch_ring_forward_z32(const float2 *ra, const float2 *rb, const float2 *ra1, const float2 *rb1,
+                                   const float2 *base, double base_scale, float2 *out, const float2 *WyT,
+                                   const float2 *WxT, double2 ex, double2 ey, double2 ex1, double2 ey1, int nx, int ny,
+                                   int nz, float2 *rbuf, float2 *fvec, hipStream_t s) {
+    return fwd_launch<float>(ra, rb, ra1, rb1, base, base_scale, out, WyT, WxT, ex, ey, ex1, ey1, nx, ny, nz, rbuf,
+                             fvec, s);
 }
 
 }  // namespace helm
