@@ -43,7 +43,7 @@ void dfree(Ctx &c, void *p) {
     if (!p) return;
     auto it = std::find(c.allocs.begin(), c.allocs.end(), p);
     if (it != c.allocs.end()) c.allocs.erase(it);
-    hipFree(p);
+    (void)hipFree(p);
 }
 
 #define ST_TRY(expr)                              \
@@ -107,32 +107,19 @@ double matvec_bytes(const Ctx &c, bool resid) {
     return per * c.n;
 }
 
-GemmDesc desc_x(const Ctx &c) {
-    GemmDesc d{};
-    d.M = c.ny * c.nz; d.N = c.nx; d.K = c.nx;
-    d.lda = c.nx; d.ldb = c.nx; d.ldc = c.nx;
-    d.sA = d.sB = d.sC = 0; d.batch = 1;
-    return d;
-}
-GemmDesc desc_y(const Ctx &c) {
-    GemmDesc d{};
-    d.M = c.ny; d.N = c.nx; d.K = c.ny;
-    d.lda = c.ny; d.ldb = c.nx; d.ldc = c.nx;
-    d.sA = 0; d.sB = d.sC = (long long)c.nx * c.ny; d.batch = c.nz;
-    return d;
-}
-
 // folded transforms along x (every line is a row) and along y (slices of Nx columns)
 FoldDesc fold_x(const Ctx &c) {
     FoldDesc f{};
     f.n = c.nx; f.ms = c.nx - c.nx / 2; f.ma = c.nx / 2;
     f.rows = c.ny * c.nz; f.ld = c.nx; f.sD = 0; f.batch = 1;
+    f.moff = f.ms; f.mstep = 1;
     return f;
 }
 FoldDesc fold_y(const Ctx &c) {
     FoldDesc f{};
     f.n = c.ny; f.ms = c.ny - c.ny / 2; f.ma = c.ny / 2;
     f.rows = c.nx; f.ld = c.nx; f.sD = (long long)c.nx * c.ny; f.batch = c.nz;
+    f.moff = f.ms; f.mstep = 1;
     return f;
 }
 // real flops of one folded transform: 8 per complex MAC, ms^2 + ma^2 MACs per line
@@ -219,6 +206,81 @@ template <typename CT> helm_status upload_one(Ctx &c, const std::vector<cd> &M, 
     return HELM_OK;
 }
 
+// The orthonormal sine matrix S (S[j][k] = sqrt(2/(N+1)) sin(pi (j+1)(k+1)/(N+1))) as folded real blocks: S is its
+// own inverse and S[N-1-j][k] = (-1)^k S[j][k], so the even modes are symmetric and the odd ones skew; with
+// S = Q diag(Vs, Va) in that mode order, Vs[i][k'] = sqrt(2) S[i][2k'] and Va[i][k'] = sqrt(2) S[i][2k'+1] (the middle
+// row of an odd axis unscaled), and the inverse blocks the same with S's rows. The modes stay in natural order
+// (FoldDesc moff = 1, mstep = 2).
+helm_status build_sine_fold(Ctx &c, int n, bool xaxis, FoldMats<double2> &m64, FoldMats<float2> &m32) {
+    const std::vector<cd> S = sine_matrix(n);
+    EigFold f;
+    f.n = n;
+    f.ms = n - n / 2;
+    f.ma = n / 2;
+    const int ms = f.ms, ma = f.ma;
+    const double r2 = std::sqrt(2.0);
+    f.Vs.assign((size_t)ms * ms, 0.0);
+    f.Vsi.assign((size_t)ms * ms, 0.0);
+    f.Va.assign((size_t)ma * ma, 0.0);
+    f.Vai.assign((size_t)ma * ma, 0.0);
+    for (int i = 0; i < ms; ++i)
+        for (int k = 0; k < ms; ++k) {
+            const double sc = i < ma ? r2 : 1.0;
+            f.Vs[(size_t)i * ms + k] = S[(size_t)i * n + 2 * k] * sc;
+            f.Vsi[(size_t)k * ms + i] = S[(size_t)(2 * k) * n + i] * sc;
+        }
+    for (int i = 0; i < ma; ++i)
+        for (int k = 0; k < ma; ++k) {
+            f.Va[(size_t)i * ma + k] = S[(size_t)i * n + 2 * k + 1] * r2;
+            f.Vai[(size_t)k * ma + i] = S[(size_t)(2 * k + 1) * n + i] * r2;
+        }
+    return upload_fold(c, f, xaxis, m64, m32);
+}
+
+FoldDesc sine_desc(const Ctx &c, int axis) {
+    FoldDesc f = axis == 0 ? fold_x(c) : fold_y(c);
+    if (axis == 2) {     // the z-transform as a y-type transform of one slab of N_x N_y columns
+        f.n = c.nz; f.ms = c.nz - c.nz / 2; f.ma = c.nz / 2;
+        f.rows = c.nx * c.ny; f.ld = (long long)c.nx * c.ny; f.sD = 0; f.batch = 1;
+    }
+    f.moff = 1;
+    f.mstep = 2;
+    return f;
+}
+// real flops of one folded sine transform: 4 per complex-by-real MAC
+double sine_flops(const FoldDesc &f) {
+    return 4.0 * (double)f.rows * f.batch * ((double)f.ms * f.ms + (double)f.ma * f.ma);
+}
+
+inline hipError_t fold_launch(int mode, const FoldDesc &f, const double2 *D, const double2 *Ms, const double2 *Ma,
+                              double2 *C, hipStream_t s) {
+    return launch_fold_z64(mode, f, D, Ms, Ma, C, s, 0, true);
+}
+inline hipError_t fold_launch(int mode, const FoldDesc &f, const float2 *D, const float2 *Ms, const float2 *Ma,
+                              float2 *C, hipStream_t s) {
+    return launch_fold_z32(mode, f, D, Ms, Ma, C, s, 0, true);
+}
+inline hipError_t fold_launch(int mode, const FoldDesc &f, const double2 *D, const float2 *Ms, const float2 *Ma,
+                              float2 *C, hipStream_t s) {
+    return launch_fold_z32_in64(mode, f, D, Ms, Ma, C, s, 0, true);
+}
+inline hipError_t fold_launch(int mode, const FoldDesc &f, const float2 *D, const float2 *Ms, const float2 *Ma,
+                              double2 *C, hipStream_t s) {
+    return launch_fold_z32_out64(mode, f, D, Ms, Ma, C, s, 0, true);
+}
+
+// one sine transform along `axis` (0, 1, 2 = x, y, z), forward or inverse, timed as a PFFT-class kernel
+template <typename TD, typename CT, typename TC>
+helm_status sine_tf(Ctx &c, int axis, bool fwd, const TD *in, TC *out, const PfftMats<CT> &m) {
+    const FoldMats<CT> &b = axis == 0 ? m.fsx : axis == 1 ? m.fsy : m.fsz;
+    const int mode = axis == 0 ? (fwd ? FOLD_XF : FOLD_XI) : (fwd ? FOLD_YF : FOLD_YI);
+    const FoldDesc f = sine_desc(c, axis);
+    HIP_TRY(timed(c, HELM_K_PFFT, sine_flops(f), [&] {
+        return fold_launch(mode, f, in, (const CT *)(fwd ? b.fs : b.is), (const CT *)(fwd ? b.fa : b.ia), out, c.stream);
+    }));
+    return HELM_OK;
+}
+
 template <typename CT> helm_status build_sine_mats(Ctx &c, PfftMats<CT> &m) {
     std::vector<cd> Sx = sine_matrix(c.nx), Sy = sine_matrix(c.ny);
     ST_TRY(upload_one(c, Sx, c.nx, false, &m.Sx));
@@ -263,6 +325,10 @@ helm_status ensure_sine(Ctx &c, bool fp32, bool ring) {
     }
     PfftPlan &P = *c.pfft;
     if (!P.m64.Sx) ST_TRY(build_sine_mats(c, P.m64));
+    if (!P.m64.fsx.fs) {
+        ST_TRY(build_sine_fold(c, c.nx, true, P.m64.fsx, P.m32.fsx));
+        ST_TRY(build_sine_fold(c, c.ny, false, P.m64.fsy, P.m32.fsy));
+    }
     if (ring && !P.m64.ringT) ST_TRY(build_ring_mats(c, P.m64));
     if (fp32) {
         if (!P.m32.Sx) ST_TRY(build_sine_mats(c, P.m32));
@@ -289,25 +355,14 @@ helm_status ensure_fftk(Ctx &c, bool fp32) {
             HIP_TRY(hipMemcpy(*dst[a], t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice));
         }
     }
-    if (!P.m64.Sz) ST_TRY(upload_one(c, sine_matrix(c.nz), c.nz, false, &P.m64.Sz));
-    if (fp32 && !P.m32.Sz) ST_TRY(upload_one(c, sine_matrix(c.nz), c.nz, false, &P.m32.Sz));
+    if (!P.m64.fsz.fs) ST_TRY(build_sine_fold(c, c.nz, false, P.m64.fsz, P.m32.fsz));
     return HELM_OK;
-}
-
-// the z transform as one GEMM: C[l'][(j,i)] = sum_l S[l'][l] Y[l][(j,i)]
-GemmDesc desc_z(const Ctx &c) {
-    GemmDesc d{};
-    d.M = c.nz; d.N = c.nx * c.ny; d.K = c.nz;
-    d.lda = c.nz; d.ldb = (long long)c.nx * c.ny; d.ldc = (long long)c.nx * c.ny;
-    d.sA = d.sB = d.sC = 0; d.batch = 1;
-    return d;
 }
 
 helm_status pfft_apply(Ctx &c, const double2 *y, double2 *z, bool fp32, float2 *z32 = nullptr) {
     ST_TRY(ensure_pfft(c, fp32));
     ST_TRY(ensure_tpiv(c, c.dxe, c.dye, &c.tpiv_eig));
     ST_TRY(ensure_tpiv(c, c.pfft->dFx, c.pfft->dFy, &c.tpiv_dir));
-    GemmDesc dx = desc_x(c), dy = desc_y(c);
     PfftPlan &P = *c.pfft;
     const double2 gz = d2(c.gamma[2]);
     const double hz2 = c.hz * c.hz;
@@ -324,8 +379,8 @@ helm_status pfft_apply(Ctx &c, const double2 *y, double2 *z, bool fp32, float2 *
     if (!fp32) {
         auto &m = P.m64;
         double2 *T1 = two ? m.ringT + rsz : nullptr, *W1 = two ? m.ringW + rsz : nullptr;
-        HIP_TRY(timed(c, HELM_K_PFFT, 4.0 * dx.M * (double)dx.N * dx.K, [&] { return launch_gemm_z64(dx, y, m.Sx, c.t1, c.stream, 2); }));
-        HIP_TRY(timed(c, HELM_K_PFFT, 4.0 * dy.M * (double)dy.N * dy.K * dy.batch, [&] { return launch_gemm_z64(dy, m.Sy, c.t1, m.yhat, c.stream, 1); }));
+        ST_TRY(sine_tf(c, 0, true, y, c.t1, m));
+        ST_TRY(sine_tf(c, 1, true, c.t1, m.yhat, m));
         HIP_TRY(timed(c, HELM_K_TRIDIAG64, 32.0 * c.n, [&] { return launch_tridiag_chunk_z64(m.yhat, c.t2, c.tpiv_dir, P.dFx, P.dFy, nx, ny, nz, c.ax, c.ay, c.c0, gz, hz2, c.stream, zi); }));
         for (int layer = 0; layer < (two ? 2 : 1); ++layer)
             HIP_TRY(timed(c, HELM_K_RING, 16.0 * c.n + ring_work / ring_pass, [&] { return launch_ring_inverse_z64(c.t2, m.ringT + layer * rsz, m.Sy, m.Sy, m.Sx, m.Sx, nx, ny, nz, layer, m.rpart, m.sv, m.rsum, c.stream); }));
@@ -335,14 +390,14 @@ helm_status pfft_apply(Ctx &c, const double2 *y, double2 *z, bool fp32, float2 *
             HIP_TRY(timed(c, HELM_K_RING, 16.0 * c.n + ring_work / ring_pass, [&] { return launch_ring_inverse_z64(c.t2, m.ringW + layer * rsz, c.AyI, m.VyT, m.Vx, c.BxI, nx, ny, nz, layer, m.rpart, m.sv, m.rsum, c.stream); }));
         HIP_TRY(timed(c, HELM_K_RING, 32.0 * c.n + 2 * ring_work, [&] { return launch_ring_forward_z64(m.ringT, m.ringW, T1, W1, m.yhat, hz2, c.t2, m.Sy, m.Sx, ex, ey, ex1, ey1, nx, ny, nz, m.rbuf, m.fvec, c.stream); }));
         HIP_TRY(timed(c, HELM_K_TRIDIAG64, 32.0 * c.n, [&] { return launch_tridiag_chunk_z64(c.t2, c.t2, c.tpiv_dir, P.dFx, P.dFy, nx, ny, nz, c.ax, c.ay, c.c0, gz, 1.0, c.stream, zi); }));
-        HIP_TRY(timed(c, HELM_K_PFFT, 4.0 * dy.M * (double)dy.N * dy.K * dy.batch, [&] { return launch_gemm_z64(dy, m.Sy, c.t2, c.t1, c.stream, 1); }));
-        HIP_TRY(timed(c, HELM_K_PFFT, 4.0 * dx.M * (double)dx.N * dx.K, [&] { return launch_gemm_z64(dx, c.t1, m.Sx, z, c.stream, 2); }));
+        ST_TRY(sine_tf(c, 1, false, c.t2, c.t1, m));
+        ST_TRY(sine_tf(c, 0, false, c.t1, z, m));
     } else {
         ST_TRY(ensure_fp32_work(c));
         auto &m = P.m32;
         float2 *T1 = two ? m.ringT + rsz : nullptr, *W1 = two ? m.ringW + rsz : nullptr;
-        HIP_TRY(timed(c, HELM_K_PFFT, 4.0 * dx.M * (double)dx.N * dx.K, [&] { return launch_gemm_z32_in64(dx, y, m.Sx, c.t1f, c.stream, 2); }));
-        HIP_TRY(timed(c, HELM_K_PFFT, 4.0 * dy.M * (double)dy.N * dy.K * dy.batch, [&] { return launch_gemm_z32(dy, m.Sy, c.t1f, m.yhat, c.stream, 1); }));
+        ST_TRY(sine_tf(c, 0, true, y, c.t1f, m));
+        ST_TRY(sine_tf(c, 1, true, c.t1f, m.yhat, m));
         HIP_TRY(timed(c, HELM_K_TRIDIAG32, 16.0 * c.n, [&] { return launch_tridiag_chunk_z32(m.yhat, c.t2f, c.tpiv_dir, P.dFx, P.dFy, nx, ny, nz, c.ax, c.ay, c.c0, gz, hz2, c.stream, zi); }));
         for (int layer = 0; layer < (two ? 2 : 1); ++layer)
             HIP_TRY(timed(c, HELM_K_RING, 8.0 * c.n + ring_work / 2 / ring_pass, [&] { return launch_ring_inverse_z32(c.t2f, m.ringT + layer * rsz, m.Sy, m.Sy, m.Sx, m.Sx, nx, ny, nz, layer, m.rpart, m.sv, m.rsum, c.stream); }));
@@ -352,8 +407,9 @@ helm_status pfft_apply(Ctx &c, const double2 *y, double2 *z, bool fp32, float2 *
             HIP_TRY(timed(c, HELM_K_RING, 8.0 * c.n + ring_work / 2 / ring_pass, [&] { return launch_ring_inverse_z32(c.t2f, m.ringW + layer * rsz, c.AyI32, m.VyT, m.Vx, c.BxI32, nx, ny, nz, layer, m.rpart, m.sv, m.rsum, c.stream); }));
         HIP_TRY(timed(c, HELM_K_RING, 16.0 * c.n + ring_work, [&] { return launch_ring_forward_z32(m.ringT, m.ringW, T1, W1, m.yhat, hz2, c.t2f, m.Sy, m.Sx, ex, ey, ex1, ey1, nx, ny, nz, m.rbuf, m.fvec, c.stream); }));
         HIP_TRY(timed(c, HELM_K_TRIDIAG32, 16.0 * c.n, [&] { return launch_tridiag_chunk_z32(c.t2f, c.t2f, c.tpiv_dir, P.dFx, P.dFy, nx, ny, nz, c.ax, c.ay, c.c0, gz, 1.0, c.stream, zi); }));
-        HIP_TRY(timed(c, HELM_K_PFFT, 4.0 * dy.M * (double)dy.N * dy.K * dy.batch, [&] { return launch_gemm_z32(dy, m.Sy, c.t2f, c.t1f, c.stream, 1); }));
-        HIP_TRY(timed(c, HELM_K_PFFT, 4.0 * dx.M * (double)dx.N * dx.K, [&] { return z32 ? launch_gemm_z32(dx, c.t1f, m.Sx, z32, c.stream, 2) : launch_gemm_z32_out64(dx, c.t1f, m.Sx, z, c.stream, 2); }));
+        ST_TRY(sine_tf(c, 1, false, c.t2f, c.t1f, m));
+        if (z32) ST_TRY(sine_tf(c, 0, false, c.t1f, z32, m));
+        else ST_TRY(sine_tf(c, 0, false, c.t1f, z, m));
     }
     return HELM_OK;
 }
@@ -365,25 +421,25 @@ helm_status fft2_apply(Ctx &c, const double2 *y, double2 *z, bool fp32, float2 *
     ST_TRY(ensure_sine(c, fp32, false));
     PfftPlan &P = *c.pfft;
     ST_TRY(ensure_tpiv(c, P.dFx, P.dFy, &c.tpiv_fft2, make_double2(0.0, 0.0)));
-    GemmDesc dx = desc_x(c), dy = desc_y(c);
     const double2 g0 = make_double2(0.0, 0.0);
     const double hz2 = c.hz * c.hz;
     const int nx = c.nx, ny = c.ny, nz = c.nz;
     if (!fp32) {
         auto &m = P.m64;
-        HIP_TRY(timed(c, HELM_K_PFFT, 4.0 * dx.M * (double)dx.N * dx.K, [&] { return launch_gemm_z64(dx, y, m.Sx, c.t1, c.stream, 2); }));
-        HIP_TRY(timed(c, HELM_K_PFFT, 4.0 * dy.M * (double)dy.N * dy.K * dy.batch, [&] { return launch_gemm_z64(dy, m.Sy, c.t1, c.t2, c.stream, 1); }));
+        ST_TRY(sine_tf(c, 0, true, y, c.t1, m));
+        ST_TRY(sine_tf(c, 1, true, c.t1, c.t2, m));
         HIP_TRY(timed(c, HELM_K_TRIDIAG64, 32.0 * c.n, [&] { return launch_tridiag_chunk_z64(c.t2, c.t2, c.tpiv_fft2, P.dFx, P.dFy, nx, ny, nz, c.ax, c.ay, c.c0, g0, hz2, c.stream); }));
-        HIP_TRY(timed(c, HELM_K_PFFT, 4.0 * dy.M * (double)dy.N * dy.K * dy.batch, [&] { return launch_gemm_z64(dy, m.Sy, c.t2, c.t1, c.stream, 1); }));
-        HIP_TRY(timed(c, HELM_K_PFFT, 4.0 * dx.M * (double)dx.N * dx.K, [&] { return launch_gemm_z64(dx, c.t1, m.Sx, z, c.stream, 2); }));
+        ST_TRY(sine_tf(c, 1, false, c.t2, c.t1, m));
+        ST_TRY(sine_tf(c, 0, false, c.t1, z, m));
     } else {
         ST_TRY(ensure_fp32_work(c));
         auto &m = P.m32;
-        HIP_TRY(timed(c, HELM_K_PFFT, 4.0 * dx.M * (double)dx.N * dx.K, [&] { return launch_gemm_z32_in64(dx, y, m.Sx, c.t1f, c.stream, 2); }));
-        HIP_TRY(timed(c, HELM_K_PFFT, 4.0 * dy.M * (double)dy.N * dy.K * dy.batch, [&] { return launch_gemm_z32(dy, m.Sy, c.t1f, c.t2f, c.stream, 1); }));
+        ST_TRY(sine_tf(c, 0, true, y, c.t1f, m));
+        ST_TRY(sine_tf(c, 1, true, c.t1f, c.t2f, m));
         HIP_TRY(timed(c, HELM_K_TRIDIAG32, 16.0 * c.n, [&] { return launch_tridiag_chunk_z32(c.t2f, c.t2f, c.tpiv_fft2, P.dFx, P.dFy, nx, ny, nz, c.ax, c.ay, c.c0, g0, hz2, c.stream); }));
-        HIP_TRY(timed(c, HELM_K_PFFT, 4.0 * dy.M * (double)dy.N * dy.K * dy.batch, [&] { return launch_gemm_z32(dy, m.Sy, c.t2f, c.t1f, c.stream, 1); }));
-        HIP_TRY(timed(c, HELM_K_PFFT, 4.0 * dx.M * (double)dx.N * dx.K, [&] { return z32 ? launch_gemm_z32(dx, c.t1f, m.Sx, z32, c.stream, 2) : launch_gemm_z32_out64(dx, c.t1f, m.Sx, z, c.stream, 2); }));
+        ST_TRY(sine_tf(c, 1, false, c.t2f, c.t1f, m));
+        if (z32) ST_TRY(sine_tf(c, 0, false, c.t1f, z32, m));
+        else ST_TRY(sine_tf(c, 0, false, c.t1f, z, m));
     }
     return HELM_OK;
 }
@@ -398,33 +454,31 @@ helm_status fftk_apply(Ctx &c, const double2 *y, double2 *z, bool fp32, int orde
     }
     ST_TRY(ensure_fftk(c, fp32));
     PfftPlan &P = *c.pfft;
-    GemmDesc dx = desc_x(c), dy = desc_y(c), dz = desc_z(c);
     SymParams q{};
     q.order = order;
     q.h2[0] = c.hx * c.hx; q.h2[1] = c.hy * c.hy; q.h2[2] = c.hz * c.hz;
     q.k2 = c.k0 * c.k0;
     const int nx = c.nx, ny = c.ny, nz = c.nz;
-    const double fx = 4.0 * dx.M * (double)dx.N * dx.K, fy = 4.0 * dy.M * (double)dy.N * dy.K * dy.batch,
-                 fz = 4.0 * dz.M * (double)dz.N * dz.K;
     if (!fp32) {
         auto &m = P.m64;
-        HIP_TRY(timed(c, HELM_K_PFFT, fx, [&] { return launch_gemm_z64(dx, y, m.Sx, c.t1, c.stream, 2); }));
-        HIP_TRY(timed(c, HELM_K_PFFT, fy, [&] { return launch_gemm_z64(dy, m.Sy, c.t1, c.t2, c.stream, 1); }));
-        HIP_TRY(timed(c, HELM_K_PFFT, fz, [&] { return launch_gemm_z64(dz, m.Sz, c.t2, c.t1, c.stream, 1); }));
+        ST_TRY(sine_tf(c, 0, true, y, c.t1, m));
+        ST_TRY(sine_tf(c, 1, true, c.t1, c.t2, m));
+        ST_TRY(sine_tf(c, 2, true, c.t2, c.t1, m));
         HIP_TRY(launch_sym_divide_z64(c.t1, P.tx, P.ty, P.tz, nx, ny, nz, q, c.stream));
-        HIP_TRY(timed(c, HELM_K_PFFT, fz, [&] { return launch_gemm_z64(dz, m.Sz, c.t1, c.t2, c.stream, 1); }));
-        HIP_TRY(timed(c, HELM_K_PFFT, fy, [&] { return launch_gemm_z64(dy, m.Sy, c.t2, c.t1, c.stream, 1); }));
-        HIP_TRY(timed(c, HELM_K_PFFT, fx, [&] { return launch_gemm_z64(dx, c.t1, m.Sx, z, c.stream, 2); }));
+        ST_TRY(sine_tf(c, 2, false, c.t1, c.t2, m));
+        ST_TRY(sine_tf(c, 1, false, c.t2, c.t1, m));
+        ST_TRY(sine_tf(c, 0, false, c.t1, z, m));
     } else {
         ST_TRY(ensure_fp32_work(c));
         auto &m = P.m32;
-        HIP_TRY(timed(c, HELM_K_PFFT, fx, [&] { return launch_gemm_z32_in64(dx, y, m.Sx, c.t1f, c.stream, 2); }));
-        HIP_TRY(timed(c, HELM_K_PFFT, fy, [&] { return launch_gemm_z32(dy, m.Sy, c.t1f, c.t2f, c.stream, 1); }));
-        HIP_TRY(timed(c, HELM_K_PFFT, fz, [&] { return launch_gemm_z32(dz, m.Sz, c.t2f, c.t1f, c.stream, 1); }));
+        ST_TRY(sine_tf(c, 0, true, y, c.t1f, m));
+        ST_TRY(sine_tf(c, 1, true, c.t1f, c.t2f, m));
+        ST_TRY(sine_tf(c, 2, true, c.t2f, c.t1f, m));
         HIP_TRY(launch_sym_divide_z32(c.t1f, P.tx, P.ty, P.tz, nx, ny, nz, q, c.stream));
-        HIP_TRY(timed(c, HELM_K_PFFT, fz, [&] { return launch_gemm_z32(dz, m.Sz, c.t1f, c.t2f, c.stream, 1); }));
-        HIP_TRY(timed(c, HELM_K_PFFT, fy, [&] { return launch_gemm_z32(dy, m.Sy, c.t2f, c.t1f, c.stream, 1); }));
-        HIP_TRY(timed(c, HELM_K_PFFT, fx, [&] { return z32 ? launch_gemm_z32(dx, c.t1f, m.Sx, z32, c.stream, 2) : launch_gemm_z32_out64(dx, c.t1f, m.Sx, z, c.stream, 2); }));
+        ST_TRY(sine_tf(c, 2, false, c.t1f, c.t2f, m));
+        ST_TRY(sine_tf(c, 1, false, c.t2f, c.t1f, m));
+        if (z32) ST_TRY(sine_tf(c, 0, false, c.t1f, z32, m));
+        else ST_TRY(sine_tf(c, 0, false, c.t1f, z, m));
     }
     return HELM_OK;
 }
@@ -463,7 +517,7 @@ helm_status ensure_krylov(Ctx &c, int m, int flexible) {
     KrylovWork &k = c.kw;
     if (k.V && k.m == m && k.flexible == flexible) return HELM_OK;
     dfree(c, k.V); dfree(c, k.Z); dfree(c, k.Zf); dfree(c, k.tmp); dfree(c, k.partials); dfree(c, k.red);
-    if (k.red_host) { hipHostFree(k.red_host); k.red_host = nullptr; }
+    if (k.red_host) { (void)hipHostFree(k.red_host); k.red_host = nullptr; }
     k = KrylovWork{};
     k.nblocks = dots_blocks(c.n);
     k.ld = c.n + KRYLOV_PAD;
@@ -573,22 +627,24 @@ void helm_destroy(helm_ctx *ctx) {
     if (!ctx) return;
     Ctx &c = ctx->c;
     int cur = 0;
-    hipGetDevice(&cur);
-    hipSetDevice(c.device);
-    if (c.stream) hipStreamSynchronize(c.stream);
-    else hipDeviceSynchronize();
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(c.device);
+    if (c.stream) (void)hipStreamSynchronize(c.stream);
+    else (void)hipDeviceSynchronize();
     prof_resolve(c);
-    for (hipEvent_t e : c.prof_pool) hipEventDestroy(e);
+    for (hipEvent_t e : c.prof_pool) (void)hipEventDestroy(e);
     c.prof_pool.clear();
-    for (void *p : c.allocs) hipFree(p);
+    for (void *p : c.allocs) (void)hipFree(p);
     c.allocs.clear();
-    if (c.kw.red_host) hipHostFree(c.kw.red_host);
-    if (c.sg_host) hipHostFree(c.sg_host);
+    if (c.kw.red_host) (void)hipHostFree(c.kw.red_host);
+    if (c.sg_host) (void)hipHostFree(c.sg_host);
     delete c.pfft;
     c.pfft = nullptr;
-    hipSetDevice(cur);
+    (void)hipSetDevice(cur);
     delete ctx;
 }
+
+}  // extern "C"
 
 namespace {
 helm_status setup_impl(helm_ctx **out, helm_grid g, const double h[3], const void *k2_dev, bool k2_complex,
@@ -615,8 +671,12 @@ helm_status setup_impl(helm_ctx **out, helm_grid g, const double h[3], const voi
         return fail(HELM_EINVAL, "unknown bc kind");
     if (!(bc.k0 >= 0.0) || !std::isfinite(bc.k0)) return fail(HELM_EINVAL, "k0 must be finite and >= 0");
 
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess) return fail(HELM_EDEVICE, "no HIP device");
+
     helm_ctx *ctx = new helm_ctx();
     Ctx &c = ctx->c;
+    c.device = device;
     c.nx = g.nx; c.ny = g.ny; c.nz = g.nz;
     c.n = (long long)g.nx * g.ny * g.nz;
     c.hx = h[0]; c.hy = h[1]; c.hz = h[2];
@@ -624,7 +684,6 @@ helm_status setup_impl(helm_ctx **out, helm_grid g, const double h[3], const voi
     c.bc_kind = bc.kind;
     c.k0 = bc.k0;
     c.stream = (hipStream_t)stream;
-    hipGetDevice(&c.device);
     c.zeta = bc.kind == HELM_BC_ABC3 ? 2.0 : 1.0;
     for (int a = 0; a < 3; ++a) {
         double ha = h[a];
@@ -730,6 +789,8 @@ helm_status setup_impl(helm_ctx **out, helm_grid g, const double h[3], const voi
 }
 }  // namespace
 
+extern "C" {
+
 helm_status helm_setup(helm_ctx **out, helm_grid g, const double h[3], const double *k2_dev, int k2_halo, int order,
                        helm_bc bc, void *stream) {
     return setup_impl(out, g, h, k2_dev, false, k2_halo, order, bc, stream);
@@ -741,6 +802,8 @@ helm_status helm_setup_complex(helm_ctx **out, helm_grid g, const double h[3], c
 }
 
 // ---- GEMM tile autotuner ----
+}  // extern "C"
+
 namespace {
 std::string tune_key(int kind, const FoldDesc &d) {
     return "v4 " + std::to_string(kind) + " " + std::to_string(d.n) + " " + std::to_string(d.rows) + " " +
@@ -771,6 +834,8 @@ void tune_cache_store(const std::string &key, int cfg) {
     std::fclose(f);
 }
 }  // namespace
+
+extern "C" {
 
 helm_status helm_autotune(helm_ctx *ctx, int reps, int *chosen, double *ms) {
     if (!ctx || reps < 1) return HELM_EINVAL;
@@ -828,8 +893,8 @@ helm_status helm_autotune(helm_ctx *ctx, int reps, int *chosen, double *ms) {
         if (chosen) chosen[kind] = best_cfg;
         tune_cache_store(key, best_cfg);
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     return HELM_OK;
 }
 
@@ -947,11 +1012,11 @@ helm_status helm_gmres_solve(helm_ctx *ctx, const void *F_dev, void *x_dev, cons
     // phase timers: 0 matvec, 1 preconditioner, 2 Arnoldi, 3 end-of-cycle update
     hipEvent_t ev[8];
     for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
-    struct EvGuard { hipEvent_t *e; ~EvGuard() { for (int i = 0; i < 8; ++i) hipEventDestroy(e[i]); } } guard{ev};
+    struct EvGuard { hipEvent_t *e; ~EvGuard() { for (int i = 0; i < 8; ++i) (void)hipEventDestroy(e[i]); } } guard{ev};
     auto elapsed = [&](hipEvent_t a, hipEvent_t b) {
         float ms = 0.f;
-        hipEventSynchronize(b);
-        hipEventElapsedTime(&ms, a, b);
+        (void)hipEventSynchronize(b);
+        (void)hipEventElapsedTime(&ms, a, b);
         return (double)ms;
     };
 

@@ -134,8 +134,8 @@ helm_status helm_batch_create(helm_batch **out, helm_ctx *const *ctxs, int np, i
         q.dye = c.dye;
         q.ax = c.ax; q.ay = c.ay; q.c0 = c.c0; q.hz2 = c.hz * c.hz;
         q.gz = make_double2(c.gamma[2].real(), c.gamma[2].imag());
-        q.fx = FoldDesc{c.nx, c.nx - c.nx / 2, c.nx / 2, c.ny * c.nz, c.nx, 0, 1};
-        q.fy = FoldDesc{c.ny, c.ny - c.ny / 2, c.ny / 2, c.nx, c.nx, (long long)c.nx * c.ny, c.nz};
+        q.fx = FoldDesc{c.nx, c.nx - c.nx / 2, c.nx / 2, c.ny * c.nz, c.nx, 0, 1, c.nx - c.nx / 2, 1};
+        q.fy = FoldDesc{c.ny, c.ny - c.ny / 2, c.ny / 2, c.nx, c.nx, (long long)c.nx * c.ny, c.nz, c.ny - c.ny / 2, 1};
         q.n = c.n;
         q.nx = c.nx; q.ny = c.ny; q.nz = c.nz;
         q.nblk_dots = dots_blocks(c.n);

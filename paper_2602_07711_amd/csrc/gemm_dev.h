@@ -251,7 +251,7 @@ template <typename T, typename S> __device__ __forceinline__ typename cplx<T>::t
 
 // The K loop of one tile: operands come from loadA(local row, k) and loadB(k, local column) (zero outside),
 // staged through LDS double buffered in registers, as in gemm_tile.
-template <typename T, int BM, int BN, int BK, int NS, typename LA, typename LB>
+template <typename T, int BM, int BN, int BK, int NS, int RW, typename LA, typename LB>
 __device__ __forceinline__ void fold_kloop(typename cplx<T>::acc (&t)[NS][BM / 32][BN / 32], int K, LA loadA,
                                            LB loadB, typename cplx<T>::t (*sA)[BM + 1],
                                            typename cplx<T>::t (*sB)[BN]) {
@@ -301,19 +301,19 @@ __device__ __forceinline__ void fold_kloop(typename cplx<T>::acc (&t)[NS][BM / 3
             for (int i = 0; i < FM; ++i) fa[i] = sA[kk + kl][rowA + i * 16];
 #pragma unroll
             for (int j = 0; j < FN; ++j) fb[j] = sB[kk + kl][colB + j * 16];
-            mma_kstep<T, 0, NS>(t, fa, fb);
+            mma_kstep<T, RW, NS>(t, fa, fb);
         }
     }
 }
 
 // One tile (`tile` < fold_tiles) of a folded transform.
-template <int MODE, typename TD, typename TM, typename TC, typename T, int BM, int BN, int BK>
+template <int MODE, typename TD, typename TM, typename TC, typename T, int BM, int BN, int BK, int RW = 0>
 __device__ __forceinline__ void fold_tile(const TD *__restrict__ D, const TM *__restrict__ Ms, const TM *__restrict__ Ma,
                                           TC *__restrict__ C, const FoldDesc &f, long long tile) {
     typedef typename cplx<T>::t CT;
     typedef typename cplx<T>::acc ACC;
     constexpr int FM = BM / 32, FN = BN / 32;
-    constexpr int NS = sizeof(T) == 4 ? 3 : 2;
+    constexpr int NS = (sizeof(T) == 4 && RW == 0) ? 3 : 2;
     __shared__ CT sA[BK][BM + 1];
     __shared__ CT sB[BK][BN];
 
@@ -354,7 +354,7 @@ __device__ __forceinline__ void fold_tile(const TD *__restrict__ D, const TM *__
             D += b * f.sD;
             C += b * f.sD;
         }
-        const int K = skew ? ma : ms, off = skew ? ms : 0;
+        const int K = skew ? ma : ms, off = skew ? f.moff : 0, mst = f.mstep;
         const TM *Mp = skew ? Ma : Ms;
         const int m0 = mt * BM, n0 = nt * BN;
         if constexpr (MODE == FOLD_XF) {
@@ -368,7 +368,7 @@ __device__ __forceinline__ void fold_tile(const TD *__restrict__ D, const TM *__
                 const int gn = n0 + nn;
                 return (gk < K && gn < K) ? cvt<T>(Mp[(long long)gk * K + gn]) : CT{0, 0};
             };
-            fold_kloop<T, BM, BN, BK, NS>(t, K, la, lb, sA, sB);
+            fold_kloop<T, BM, BN, BK, NS, RW>(t, K, la, lb, sA, sB);
         } else {
             auto la = [&](int mm, int gk) -> CT {
                 const int gm = m0 + mm;
@@ -379,7 +379,7 @@ __device__ __forceinline__ void fold_tile(const TD *__restrict__ D, const TM *__
                 if (gk >= K || gn >= rows) return CT{0, 0};
                 return fold2<T>(D[(long long)gk * ld + gn], D[(long long)(n - 1 - gk) * ld + gn], skew);
             };
-            fold_kloop<T, BM, BN, BK, NS>(t, K, la, lb, sA, sB);
+            fold_kloop<T, BM, BN, BK, NS, RW>(t, K, la, lb, sA, sB);
         }
 #pragma unroll
         for (int i = 0; i < FM; ++i)
@@ -392,9 +392,9 @@ __device__ __forceinline__ void fold_tile(const TD *__restrict__ D, const TM *__
                     T re, im;
                     acc_value<T>(t, i, j, r, re, im);
                     if constexpr (MODE == FOLD_XF) {
-                        if (gm < rows && gn < K) C[(long long)gm * ld + off + gn] = pack<TC, T>(re, im);
+                        if (gm < rows && gn < K) C[(long long)gm * ld + off + mst * gn] = pack<TC, T>(re, im);
                     } else {
-                        if (gm < K && gn < rows) C[(long long)(off + gm) * ld + gn] = pack<TC, T>(re, im);
+                        if (gm < K && gn < rows) C[(long long)(off + mst * gm) * ld + gn] = pack<TC, T>(re, im);
                     }
                 }
             }
@@ -422,18 +422,18 @@ __device__ __forceinline__ void fold_tile(const TD *__restrict__ D, const TM *__
         };
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
-            const int K = q ? ma : ms, off = q ? ms : 0;
+            const int K = q ? ma : ms, off = q ? f.moff : 0, mst = f.mstep;
             const TM *Mq = q ? Ma : Ms;
             if constexpr (MODE == FOLD_XI) {
                 auto la = [&](int mm, int gk) -> CT {
                     const int gm = m0 + mm;
-                    return (gm < rows && gk < K) ? cvt<T>(D[(long long)gm * ld + off + gk]) : CT{0, 0};
+                    return (gm < rows && gk < K) ? cvt<T>(D[(long long)gm * ld + off + mst * gk]) : CT{0, 0};
                 };
                 auto lb = [&](int gk, int nn) -> CT {
                     const int gn = n0 + nn;
                     return (gk < K && gn < K) ? cvt<T>(Mq[(long long)gk * K + gn]) : CT{0, 0};
                 };
-                fold_kloop<T, BM, BN, BK, NS>(t, K, la, lb, sA, sB);
+                fold_kloop<T, BM, BN, BK, NS, RW>(t, K, la, lb, sA, sB);
             } else {
                 auto la = [&](int mm, int gk) -> CT {
                     const int gm = m0 + mm;
@@ -441,9 +441,9 @@ __device__ __forceinline__ void fold_tile(const TD *__restrict__ D, const TM *__
                 };
                 auto lb = [&](int gk, int nn) -> CT {
                     const int gn = n0 + nn;
-                    return (gk < K && gn < rows) ? cvt<T>(D[(long long)(off + gk) * ld + gn]) : CT{0, 0};
+                    return (gk < K && gn < rows) ? cvt<T>(D[(long long)(off + mst * gk) * ld + gn]) : CT{0, 0};
                 };
-                fold_kloop<T, BM, BN, BK, NS>(t, K, la, lb, sA, sB);
+                fold_kloop<T, BM, BN, BK, NS, RW>(t, K, la, lb, sA, sB);
             }
             if (q == 0) {
                 // park P in this thread's own output slots (first half of the axis; the skew results go to the

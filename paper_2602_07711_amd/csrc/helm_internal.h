@@ -63,6 +63,9 @@ struct FoldDesc {
     long long ld;                // stride between consecutive rows (x) or axis positions (y)
     long long sD;                // slice stride (y)
     int batch;                   // slices (y; 1 for x)
+    int moff, mstep;             // where the modes live: symmetric mode k at k * mstep, skew mode k at moff +
+                                 // k * mstep ([symmetric | skew]: moff = ms, mstep = 1; the sine basis keeps its
+                                 // natural order, even modes symmetric and odd ones skew: moff = 1, mstep = 2)
 };
 // the blocks of one axis, row-major: forward (x: [position][mode], y: [mode][position]) and inverse
 // (x: [mode][position], y: [position][mode]), each for the symmetric (ms x ms) and skew (ma x ma) half
@@ -82,13 +85,14 @@ __host__ __device__ inline long long fold_tile_count(int mode, const FoldDesc &f
     return (long long)f.batch * hs_m * tn;
 }
 hipError_t launch_fold_z64(int mode, const FoldDesc &f, const double2 *D, const double2 *Ms, const double2 *Ma,
-                           double2 *C, hipStream_t s, int cfg);
+                           double2 *C, hipStream_t s, int cfg, bool real = false);
 hipError_t launch_fold_z32(int mode, const FoldDesc &f, const float2 *D, const float2 *Ms, const float2 *Ma, float2 *C,
-                           hipStream_t s, int cfg);
+                           hipStream_t s, int cfg, bool real = false);
 hipError_t launch_fold_z32_in64(int mode, const FoldDesc &f, const double2 *D, const float2 *Ms, const float2 *Ma,
-                                float2 *C, hipStream_t s, int cfg);
+                                float2 *C, hipStream_t s, int cfg, bool real = false);
 hipError_t launch_fold_z32_out64(int mode, const FoldDesc &f, const float2 *D, const float2 *Ms, const float2 *Ma,
-                                 double2 *C, hipStream_t s, int cfg);
+                                 double2 *C, hipStream_t s, int cfg, bool real = false);
+// real = true: the blocks are real (their imaginary parts are ignored), two real MFMA products per complex MAC
 
 // symbol of the compact operators with constant k0 (FFT4 / FFT6): order, h_a^2 per axis, k0^2
 struct SymParams {
@@ -105,7 +109,8 @@ hipError_t launch_sym_divide_z32(float2 *u, const double *tx, const double *ty, 
 // matrices the thin ring transforms need, and work buffers. FP64 and FP32 copies.
 template <typename CT> struct PfftMats {
     CT *Sx = nullptr, *Sy = nullptr;             // orthonormal sine matrices (symmetric; imaginary part 0)
-    CT *Sz = nullptr;                            // the same along z (FFT4 / FFT6 only)
+    FoldMats<CT> fsx, fsy, fsz;                  // the sine transforms (z for FFT4 / FFT6 only) as folded real
+                                                 // blocks (even modes symmetric, odd ones skew; natural order)
     CT *Vxi = nullptr, *Vx = nullptr;            // V_x^{-1}, V_x row-major (the transposes are BxF, BxI)
     CT *VyiT = nullptr, *VyT = nullptr;          // transposes of V_y^{-1}, V_y (the plain ones are AyF, AyI)
     CT *yhat = nullptr;                          // sine transform of the input (reused in step 3)

@@ -6,8 +6,9 @@
 //   y-transform: C_l[j][i] = sum_m W[j][m] Y_l[m][i]      per slice l, the data is the B operand (ldb = Nx).
 // In both the fastest memory index of the data lands on the MFMA column index, so tile loads and the
 // accumulator stores walk contiguous memory. They run as the folded kernels below (k_fold: two half-size
-// products per axis). The plain batched GEMM C[b] = A[b] B[b] (k_zgemm) carries the sine transforms of PFFT and
-// of the FFT2/4/6 comparison preconditioners.
+// products per axis), and so do the sine transforms of PFFT and of the FFT2/4/6 comparison preconditioners (real
+// blocks, modes at stride 2). The plain batched GEMM C[b] = A[b] B[b] (k_zgemm) carries PFFT's thin face-ring
+// products.
 //
 // Arithmetic, FP32: three real MFMA products per complex k-step (Gauss / 3M form: T1 += Ar Br, T2 += Ai Bi,
 // T3 += (Ar + Ai)(Br + Bi); then Cr = T1 - T2, Ci = T3 - T1 - T2), 25% fewer MFMA issues than the four-product
@@ -63,27 +64,36 @@ hipError_t launch(const GemmDesc &d, const TA *A, const TB *B, TC *C, hipStream_
     }
 }
 
-template <int MODE, typename TD, typename TM, typename TC, typename T, int BM, int BN, int BK>
+// RW = 0: complex blocks; RW = 1 / 2: real blocks (the sine basis) as the A (y) / B (x) operand
+template <int MODE, typename TD, typename TM, typename TC, typename T, int BM, int BN, int BK, int RW>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(fold_waves<T, BM, BN, BK>()))) void k_fold(
     const TD *__restrict__ D, const TM *__restrict__ Ms, const TM *__restrict__ Ma, TC *__restrict__ C, FoldDesc f) {
     const long long total = fold_tiles<MODE, BM, BN>(f);
     const long long per = (total + 7) / 8;
     const long long tile = (long long)(blockIdx.x % 8) * per + blockIdx.x / 8;   // consecutive tiles on one XCD
     if (tile >= total) return;
-    fold_tile<MODE, TD, TM, TC, T, BM, BN, BK>(D, Ms, Ma, C, f, tile);
+    fold_tile<MODE, TD, TM, TC, T, BM, BN, BK, RW>(D, Ms, Ma, C, f, tile);
 }
 
-template <int MODE, typename TD, typename TM, typename TC, typename T, int BM, int BN, int BK>
+template <int MODE, typename TD, typename TM, typename TC, typename T, int BM, int BN, int BK, int RW = 0>
 hipError_t fold_launch_tile(const FoldDesc &f, const TD *D, const TM *Ms, const TM *Ma, TC *C, hipStream_t s) {
     const long long tiles = fold_tiles<MODE, BM, BN>(f);
     if (tiles == 0) return hipSuccess;
     const long long grid = 8 * ((tiles + 7) / 8);
-    hipLaunchKernelGGL((k_fold<MODE, TD, TM, TC, T, BM, BN, BK>), dim3((unsigned)grid), dim3(256), 0, s, D, Ms, Ma, C, f);
+    hipLaunchKernelGGL((k_fold<MODE, TD, TM, TC, T, BM, BN, BK, RW>), dim3((unsigned)grid), dim3(256), 0, s, D, Ms, Ma,
+                       C, f);
     return hipGetLastError();
 }
 
+// real blocks (the sine basis): tile configuration 0, the block as the B operand of the x-transforms and the A
+// operand of the y-transforms
 template <int MODE, typename TD, typename TM, typename TC, typename T>
-hipError_t fold_launch_cfg(const FoldDesc &f, const TD *D, const TM *Ms, const TM *Ma, TC *C, hipStream_t s, int cfg) {
+hipError_t fold_launch_cfg(const FoldDesc &f, const TD *D, const TM *Ms, const TM *Ma, TC *C, hipStream_t s, int cfg,
+                           bool real) {
+    if (real) {
+        constexpr int RW = (MODE == FOLD_XF || MODE == FOLD_XI) ? 2 : 1;
+        return fold_launch_tile<MODE, TD, TM, TC, T, 64, 64, 16, RW>(f, D, Ms, Ma, C, s);
+    }
     switch (cfg) {
     case 1: return fold_launch_tile<MODE, TD, TM, TC, T, 64, 64, 32>(f, D, Ms, Ma, C, s);
     case 2: return fold_launch_tile<MODE, TD, TM, TC, T, 128, 64, 16>(f, D, Ms, Ma, C, s);
@@ -116,33 +126,33 @@ hipError_t launch_gemm_z32_out64(const GemmDesc &d, const float2 *A, const float
 namespace helm {
 
 hipError_t launch_fold_z64(int mode, const FoldDesc &f, const double2 *D, const double2 *Ms, const double2 *Ma,
-                           double2 *C, hipStream_t s, int cfg) {
+                           double2 *C, hipStream_t s, int cfg, bool real) {
     switch (mode) {
-    case FOLD_XF: return fold_launch_cfg<FOLD_XF, double2, double2, double2, double>(f, D, Ms, Ma, C, s, cfg);
-    case FOLD_YF: return fold_launch_cfg<FOLD_YF, double2, double2, double2, double>(f, D, Ms, Ma, C, s, cfg);
-    case FOLD_XI: return fold_launch_cfg<FOLD_XI, double2, double2, double2, double>(f, D, Ms, Ma, C, s, cfg);
-    case FOLD_YI: return fold_launch_cfg<FOLD_YI, double2, double2, double2, double>(f, D, Ms, Ma, C, s, cfg);
+    case FOLD_XF: return fold_launch_cfg<FOLD_XF, double2, double2, double2, double>(f, D, Ms, Ma, C, s, cfg, real);
+    case FOLD_YF: return fold_launch_cfg<FOLD_YF, double2, double2, double2, double>(f, D, Ms, Ma, C, s, cfg, real);
+    case FOLD_XI: return fold_launch_cfg<FOLD_XI, double2, double2, double2, double>(f, D, Ms, Ma, C, s, cfg, real);
+    case FOLD_YI: return fold_launch_cfg<FOLD_YI, double2, double2, double2, double>(f, D, Ms, Ma, C, s, cfg, real);
     default: return hipErrorInvalidValue;
     }
 }
 hipError_t launch_fold_z32(int mode, const FoldDesc &f, const float2 *D, const float2 *Ms, const float2 *Ma, float2 *C,
-                           hipStream_t s, int cfg) {
+                           hipStream_t s, int cfg, bool real) {
     switch (mode) {
-    case FOLD_YF: return fold_launch_cfg<FOLD_YF, float2, float2, float2, float>(f, D, Ms, Ma, C, s, cfg);
-    case FOLD_XI: return fold_launch_cfg<FOLD_XI, float2, float2, float2, float>(f, D, Ms, Ma, C, s, cfg);
-    case FOLD_YI: return fold_launch_cfg<FOLD_YI, float2, float2, float2, float>(f, D, Ms, Ma, C, s, cfg);
+    case FOLD_YF: return fold_launch_cfg<FOLD_YF, float2, float2, float2, float>(f, D, Ms, Ma, C, s, cfg, real);
+    case FOLD_XI: return fold_launch_cfg<FOLD_XI, float2, float2, float2, float>(f, D, Ms, Ma, C, s, cfg, real);
+    case FOLD_YI: return fold_launch_cfg<FOLD_YI, float2, float2, float2, float>(f, D, Ms, Ma, C, s, cfg, real);
     default: return hipErrorInvalidValue;
     }
 }
 hipError_t launch_fold_z32_in64(int mode, const FoldDesc &f, const double2 *D, const float2 *Ms, const float2 *Ma,
-                                float2 *C, hipStream_t s, int cfg) {
+                                float2 *C, hipStream_t s, int cfg, bool real) {
     if (mode != FOLD_XF) return hipErrorInvalidValue;
-    return fold_launch_cfg<FOLD_XF, double2, float2, float2, float>(f, D, Ms, Ma, C, s, cfg);
+    return fold_launch_cfg<FOLD_XF, double2, float2, float2, float>(f, D, Ms, Ma, C, s, cfg, real);
 }
 hipError_t launch_fold_z32_out64(int mode, const FoldDesc &f, const float2 *D, const float2 *Ms, const float2 *Ma,
-                                 double2 *C, hipStream_t s, int cfg) {
+                                 double2 *C, hipStream_t s, int cfg, bool real) {
     if (mode != FOLD_XI) return hipErrorInvalidValue;
-    return fold_launch_cfg<FOLD_XI, float2, float2, double2, float>(f, D, Ms, Ma, C, s, cfg);
+    return fold_launch_cfg<FOLD_XI, float2, float2, double2, float>(f, D, Ms, Ma, C, s, cfg, real);
 }
 
 }  // namespace helm
