@@ -344,7 +344,8 @@ def main():
     tune = None
     if not args.no_autotune:
         tune = H.helm_autotune(ctx, reps=5)
-        log("autotuned GEMM tiles: " + ", ".join(f"{k}={v['chosen']}" for k, v in tune.items()))
+        log("autotuned transform tiles (forward / inverse): "
+            + ", ".join(f"{k}={v['chosen']}/{v['chosen_inverse']}" for k, v in tune.items()))
     del k2, f
     x = torch.empty_like(F)
     unknowns = n ** 3

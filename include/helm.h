@@ -199,14 +199,15 @@ const char *helm_profile_name(int kernel_class);
  * FP64 and FP32) it times every tile configuration (BM, BN, BK) = (64,64,16), (64,64,32), (128,64,16),
  * (64,128,16) with the launches the preconditioner makes (the FP32 x-transform as its FP64-input forward and
  * FP64-output inverse pair), best of three trials of `reps` launches on the context stream, and keeps the
- * fastest for this context. If the environment variable HELM_TUNE_CACHE names a file, choices are read from it
- * by (transform, M, N, K, batch) and new ones appended to it. chosen: NULL or 4 ints (x64, y64, x32, y32);
- * ms: NULL or 16 doubles, the per-launch time of configuration c of transform t at ms[4 t + c] (not written for
- * cached transforms).
+ * fastest for this context, separately for the forward and the inverse transform of each kind. If the environment
+ * variable HELM_TUNE_CACHE names a file, choices are read from it by (transform, direction, axis length, lines,
+ * slices) and new ones appended to it. chosen: NULL or 8 ints, the forward choices of (x64, y64, x32, y32) then the
+ * inverse ones; ms: NULL or 32 doubles, the per-launch time of configuration c of transform t in direction d
+ * (0 forward, 1 inverse) at ms[16 d + 4 t + c] (not written for cached choices).
  * Batches created afterwards use the tuned choices of their first context. */
 helm_status helm_autotune(helm_ctx *ctx, int reps, int *chosen, double *ms);
 
-/* Set the tile configuration (0..3) of transform kind (0 x64, 1 y64, 2 x32, 3 y32) by hand. */
+/* Set the tile configuration (0..3) of transform kind (0 x64, 1 y64, 2 x32, 3 y32), forward and inverse, by hand. */
 helm_status helm_gemm_config(helm_ctx *ctx, int kind, int cfg);
 
 /* Scale an initial guess known up to its amplitude: x <- alpha x with the complex alpha minimising

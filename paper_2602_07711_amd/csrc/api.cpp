@@ -157,16 +157,16 @@ helm_status eigt_apply(Ctx &c, const double2 *y, double2 *z, bool fp32, float2 *
         HIP_TRY(timed(c, HELM_K_GEMM_Y64, wy, [&] { return launch_fold_z64(FOLD_YF, fy, c.t1, c.fy64.fs, c.fy64.fa, c.t2, c.stream, c.gemm_cfg[1]); }));
         ST_TRY(ensure_tpiv(c, c.dxe, c.dye, &c.tpiv_eig));
         HIP_TRY(timed(c, HELM_K_TRIDIAG64, 32.0 * c.n, [&] { return launch_tridiag_chunk_z64(c.t2, c.t2, c.tpiv_eig, c.dxe, c.dye, c.nx, c.ny, c.nz, c.ax, c.ay, c.c0, gz, scale, c.stream, 1.0 / c.zeta); }));
-        HIP_TRY(timed(c, HELM_K_GEMM_Y64, wy, [&] { return launch_fold_z64(FOLD_YI, fy, c.t2, c.fy64.is, c.fy64.ia, c.t1, c.stream, c.gemm_cfg[1]); }));
-        HIP_TRY(timed(c, HELM_K_GEMM_X64, wx, [&] { return launch_fold_z64(FOLD_XI, fx, c.t1, c.fx64.is, c.fx64.ia, z, c.stream, c.gemm_cfg[0]); }));
+        HIP_TRY(timed(c, HELM_K_GEMM_Y64, wy, [&] { return launch_fold_z64(FOLD_YI, fy, c.t2, c.fy64.is, c.fy64.ia, c.t1, c.stream, c.gemm_cfg_inv[1]); }));
+        HIP_TRY(timed(c, HELM_K_GEMM_X64, wx, [&] { return launch_fold_z64(FOLD_XI, fx, c.t1, c.fx64.is, c.fx64.ia, z, c.stream, c.gemm_cfg_inv[0]); }));
     } else {
         ST_TRY(ensure_fp32_work(c));
         HIP_TRY(timed(c, HELM_K_GEMM_X32, wx, [&] { return launch_fold_z32_in64(FOLD_XF, fx, y, c.fx32.fs, c.fx32.fa, c.t1f, c.stream, c.gemm_cfg[2]); }));
         HIP_TRY(timed(c, HELM_K_GEMM_Y32, wy, [&] { return launch_fold_z32(FOLD_YF, fy, c.t1f, c.fy32.fs, c.fy32.fa, c.t2f, c.stream, c.gemm_cfg[3]); }));
         ST_TRY(ensure_tpiv(c, c.dxe, c.dye, &c.tpiv_eig));
         HIP_TRY(timed(c, HELM_K_TRIDIAG32, 16.0 * c.n, [&] { return launch_tridiag_chunk_z32(c.t2f, c.t2f, c.tpiv_eig, c.dxe, c.dye, c.nx, c.ny, c.nz, c.ax, c.ay, c.c0, gz, scale, c.stream, 1.0 / c.zeta); }));
-        HIP_TRY(timed(c, HELM_K_GEMM_Y32, wy, [&] { return launch_fold_z32(FOLD_YI, fy, c.t2f, c.fy32.is, c.fy32.ia, c.t1f, c.stream, c.gemm_cfg[3]); }));
-        HIP_TRY(timed(c, HELM_K_GEMM_X32, wx, [&] { return z32 ? launch_fold_z32(FOLD_XI, fx, c.t1f, c.fx32.is, c.fx32.ia, z32, c.stream, c.gemm_cfg[2]) : launch_fold_z32_out64(FOLD_XI, fx, c.t1f, c.fx32.is, c.fx32.ia, z, c.stream, c.gemm_cfg[2]); }));
+        HIP_TRY(timed(c, HELM_K_GEMM_Y32, wy, [&] { return launch_fold_z32(FOLD_YI, fy, c.t2f, c.fy32.is, c.fy32.ia, c.t1f, c.stream, c.gemm_cfg_inv[3]); }));
+        HIP_TRY(timed(c, HELM_K_GEMM_X32, wx, [&] { return z32 ? launch_fold_z32(FOLD_XI, fx, c.t1f, c.fx32.is, c.fx32.ia, z32, c.stream, c.gemm_cfg_inv[2]) : launch_fold_z32_out64(FOLD_XI, fx, c.t1f, c.fx32.is, c.fx32.ia, z, c.stream, c.gemm_cfg_inv[2]); }));
     }
     return HELM_OK;
 }
@@ -805,9 +805,9 @@ helm_status helm_setup_complex(helm_ctx **out, helm_grid g, const double h[3], c
 }  // extern "C"
 
 namespace {
-std::string tune_key(int kind, const FoldDesc &d) {
-    return "v4 " + std::to_string(kind) + " " + std::to_string(d.n) + " " + std::to_string(d.rows) + " " +
-           std::to_string(d.batch);
+std::string tune_key(int kind, int dir, const FoldDesc &d) {
+    return "v5 " + std::to_string(kind) + " " + std::to_string(dir) + " " + std::to_string(d.n) + " " +
+           std::to_string(d.rows) + " " + std::to_string(d.batch);
 }
 bool tune_cache_lookup(const std::string &key, int &cfg) {
     const char *path = std::getenv("HELM_TUNE_CACHE");
@@ -847,51 +847,54 @@ helm_status helm_autotune(helm_ctx *ctx, int reps, int *chosen, double *ms) {
     HIP_TRY(hipEventCreate(&e1));
     for (int kind = 0; kind < 4; ++kind) {
         const FoldDesc &d = (kind % 2 == 0) ? fxd : fyd;
-        std::string key = tune_key(kind, d);
-        int cached = -1;
-        if (tune_cache_lookup(key, cached)) {
-            c.gemm_cfg[kind] = cached;
-            if (chosen) chosen[kind] = cached;
-            continue;
-        }
-        double best = 1e300;
-        int best_cfg = 0;
-        for (int cfg = 0; cfg < GEMM_NCFG; ++cfg) {
-            // the forward and inverse launches the preconditioner makes for this kind (FP32 x: FP64 in, FP64 out)
-            auto run = [&]() -> hipError_t {
-                hipError_t e;
-                switch (kind) {
-                case 0:
-                    e = launch_fold_z64(FOLD_XF, d, c.t1, c.fx64.fs, c.fx64.fa, c.t2, c.stream, cfg);
-                    return e != hipSuccess ? e : launch_fold_z64(FOLD_XI, d, c.t2, c.fx64.is, c.fx64.ia, c.t1, c.stream, cfg);
-                case 1:
-                    e = launch_fold_z64(FOLD_YF, d, c.t1, c.fy64.fs, c.fy64.fa, c.t2, c.stream, cfg);
-                    return e != hipSuccess ? e : launch_fold_z64(FOLD_YI, d, c.t2, c.fy64.is, c.fy64.ia, c.t1, c.stream, cfg);
-                case 2:
-                    e = launch_fold_z32_in64(FOLD_XF, d, c.t1, c.fx32.fs, c.fx32.fa, c.t1f, c.stream, cfg);
-                    return e != hipSuccess ? e : launch_fold_z32_out64(FOLD_XI, d, c.t1f, c.fx32.is, c.fx32.ia, c.t2, c.stream, cfg);
-                default:
-                    e = launch_fold_z32(FOLD_YF, d, c.t1f, c.fy32.fs, c.fy32.fa, c.t2f, c.stream, cfg);
-                    return e != hipSuccess ? e : launch_fold_z32(FOLD_YI, d, c.t2f, c.fy32.is, c.fy32.ia, c.t1f, c.stream, cfg);
-                }
-            };
-            HIP_TRY(run());
-            double avg = 1e300;
-            for (int trial = 0; trial < 3; ++trial) {      // best of three trials of `reps` launches
-                HIP_TRY(hipEventRecord(e0, c.stream));
-                for (int r = 0; r < reps; ++r) HIP_TRY(run());
-                HIP_TRY(hipEventRecord(e1, c.stream));
-                HIP_TRY(hipEventSynchronize(e1));
-                float t = 0.f;
-                HIP_TRY(hipEventElapsedTime(&t, e0, e1));
-                avg = std::min(avg, (double)t / reps / 2);
+        for (int dir = 0; dir < 2; ++dir) {            // 0: forward, 1: inverse
+            int *slot = dir == 0 ? &c.gemm_cfg[kind] : &c.gemm_cfg_inv[kind];
+            std::string key = tune_key(kind, dir, d);
+            int cached = -1;
+            if (tune_cache_lookup(key, cached)) {
+                *slot = cached;
+                if (chosen) chosen[4 * dir + kind] = cached;
+                continue;
             }
-            if (ms) ms[kind * GEMM_NCFG + cfg] = avg;
-            if (avg < best) { best = avg; best_cfg = cfg; }
+            double best = 1e300;
+            int best_cfg = 0;
+            for (int cfg = 0; cfg < GEMM_NCFG; ++cfg) {
+                // the launch the preconditioner makes for this kind and direction (FP32 x: FP64 in, FP64 out)
+                auto run = [&]() -> hipError_t {
+                    switch (kind) {
+                    case 0:
+                        return dir == 0 ? launch_fold_z64(FOLD_XF, d, c.t1, c.fx64.fs, c.fx64.fa, c.t2, c.stream, cfg)
+                                        : launch_fold_z64(FOLD_XI, d, c.t2, c.fx64.is, c.fx64.ia, c.t1, c.stream, cfg);
+                    case 1:
+                        return dir == 0 ? launch_fold_z64(FOLD_YF, d, c.t1, c.fy64.fs, c.fy64.fa, c.t2, c.stream, cfg)
+                                        : launch_fold_z64(FOLD_YI, d, c.t2, c.fy64.is, c.fy64.ia, c.t1, c.stream, cfg);
+                    case 2:
+                        return dir == 0
+                                   ? launch_fold_z32_in64(FOLD_XF, d, c.t1, c.fx32.fs, c.fx32.fa, c.t1f, c.stream, cfg)
+                                   : launch_fold_z32_out64(FOLD_XI, d, c.t1f, c.fx32.is, c.fx32.ia, c.t2, c.stream, cfg);
+                    default:
+                        return dir == 0 ? launch_fold_z32(FOLD_YF, d, c.t1f, c.fy32.fs, c.fy32.fa, c.t2f, c.stream, cfg)
+                                        : launch_fold_z32(FOLD_YI, d, c.t2f, c.fy32.is, c.fy32.ia, c.t1f, c.stream, cfg);
+                    }
+                };
+                HIP_TRY(run());
+                double avg = 1e300;
+                for (int trial = 0; trial < 3; ++trial) {      // best of three trials of `reps` launches
+                    HIP_TRY(hipEventRecord(e0, c.stream));
+                    for (int r = 0; r < reps; ++r) HIP_TRY(run());
+                    HIP_TRY(hipEventRecord(e1, c.stream));
+                    HIP_TRY(hipEventSynchronize(e1));
+                    float t = 0.f;
+                    HIP_TRY(hipEventElapsedTime(&t, e0, e1));
+                    avg = std::min(avg, (double)t / reps);
+                }
+                if (ms) ms[16 * dir + kind * GEMM_NCFG + cfg] = avg;
+                if (avg < best) { best = avg; best_cfg = cfg; }
+            }
+            *slot = best_cfg;
+            if (chosen) chosen[4 * dir + kind] = best_cfg;
+            tune_cache_store(key, best_cfg);
         }
-        c.gemm_cfg[kind] = best_cfg;
-        if (chosen) chosen[kind] = best_cfg;
-        tune_cache_store(key, best_cfg);
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -901,6 +904,7 @@ helm_status helm_autotune(helm_ctx *ctx, int reps, int *chosen, double *ms) {
 helm_status helm_gemm_config(helm_ctx *ctx, int kind, int cfg) {
     if (!ctx || kind < 0 || kind > 3 || cfg < 0 || cfg >= GEMM_NCFG) return HELM_EINVAL;
     ctx->c.gemm_cfg[kind] = cfg;
+    ctx->c.gemm_cfg_inv[kind] = cfg;
     return HELM_OK;
 }
 

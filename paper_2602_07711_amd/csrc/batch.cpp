@@ -93,10 +93,12 @@ helm_status helm_batch_create(helm_batch **out, helm_ctx *const *ctxs, int np, i
     const size_t esz = b->fp32 ? sizeof(float2) : sizeof(double2);
 
     // tile configurations tuned for the first context (helm_autotune), used for every problem of the batch
-    const int cfg_x = ctxs[0]->c.gemm_cfg[b->fp32 ? 2 : 0], cfg_y = ctxs[0]->c.gemm_cfg[b->fp32 ? 3 : 1];
-    int bmx, bnx, bmy, bny;
-    gemm_cfg_tile(cfg_x, bmx, bnx);
-    gemm_cfg_tile(cfg_y, bmy, bny);
+    // (roles: x forward, y forward, y inverse, x inverse)
+    const Ctx &c0 = ctxs[0]->c;
+    const int kx = b->fp32 ? 2 : 0, ky = b->fp32 ? 3 : 1;
+    const int rcfg[4] = {c0.gemm_cfg[kx], c0.gemm_cfg[ky], c0.gemm_cfg_inv[ky], c0.gemm_cfg_inv[kx]};
+    int bm[4], bn[4];
+    for (int r = 0; r < 4; ++r) gemm_cfg_tile(rcfg[r], bm[r], bn[r]);
     // z-solve block shape: 16 lines x the largest problem's chunk count (at most 1024 threads)
     int tri_pb = 1;
     for (int p = 0; p < np; ++p) tri_pb = std::max(tri_pb, tri_chunks(ctxs[p]->c.nz));
@@ -157,10 +159,10 @@ helm_status helm_batch_create(helm_batch **out, helm_ctx *const *ctxs, int np, i
         otri.push_back(otri.back() + (int)(((long long)c.nx * c.ny + tri_lx - 1) / tri_lx));
         odot.push_back(odot.back() + q.nblk_dots);
         olc.push_back(olc.back() + (int)((c.n + 1023) / 1024));
-        og[0].push_back(og[0].back() + fold_tile_count(FOLD_XF, q.fx, bmx, bnx));
-        og[1].push_back(og[1].back() + fold_tile_count(FOLD_YF, q.fy, bmy, bny));
-        og[2].push_back(og[2].back() + fold_tile_count(FOLD_YI, q.fy, bmy, bny));
-        og[3].push_back(og[3].back() + fold_tile_count(FOLD_XI, q.fx, bmx, bnx));
+        og[0].push_back(og[0].back() + fold_tile_count(FOLD_XF, q.fx, bm[0], bn[0]));
+        og[1].push_back(og[1].back() + fold_tile_count(FOLD_YF, q.fy, bm[1], bn[1]));
+        og[2].push_back(og[2].back() + fold_tile_count(FOLD_YI, q.fy, bm[2], bn[2]));
+        og[3].push_back(og[3].back() + fold_tile_count(FOLD_XI, q.fx, bm[3], bn[3]));
     }
     BLaunch &L = b->L;
     if (balloc(*b, &b->dP, np) != hipSuccess || balloc(*b, &b->dst, np) != hipSuccess ||
@@ -191,8 +193,7 @@ helm_status helm_batch_create(helm_batch **out, helm_ctx *const *ctxs, int np, i
     L.m = m;
     L.order = order;
     L.fp32 = b->fp32;
-    L.cfg_x = cfg_x;
-    L.cfg_y = cfg_y;
+    for (int r = 0; r < 4; ++r) L.cfg[r] = rcfg[r];
     L.tri_lx = tri_lx;
     L.tri_pb = tri_pb;
     L.tot_mv = omv.back();

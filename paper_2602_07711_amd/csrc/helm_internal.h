@@ -173,7 +173,8 @@ struct Ctx {
     FoldMats<float2> fx32, fy32;
     double2 *dxe = nullptr, *dye = nullptr;    // eigenvalues d_x,i and d_y,j
     double ax, ay, c0;                          // alpha_x, alpha_y, h_z^2 k0^2 - 2(alpha_x + alpha_y + 1)
-    int gemm_cfg[4] = {0, 0, 0, 0};             // tile configuration of the x64, y64, x32, y32 transforms
+    int gemm_cfg[4] = {0, 0, 0, 0};             // tile configuration of the x64, y64, x32, y32 forward transforms
+    int gemm_cfg_inv[4] = {0, 0, 0, 0};         // and of the inverse ones
 
     // preconditioner work buffers
     double2 *t1 = nullptr, *t2 = nullptr;
@@ -348,7 +349,7 @@ struct BLaunch {
     int tot_mv, tot_tri, tot_dot, tot_lc;       // total blocks per grouped launch
     long long tot_g[4];                         // total transform tiles per role
     int gemm_grid;                              // persistent GEMM grid size
-    int cfg_x, cfg_y;                           // GEMM tile configurations of the x- and y-transforms
+    int cfg[4];                                 // tile configurations of the four transform roles
     int tri_lx, tri_pb;                         // z-solve block: tri_lx lines x tri_pb chunks
 };
 inline void gemm_cfg_tile(int cfg, int &bm, int &bn) {

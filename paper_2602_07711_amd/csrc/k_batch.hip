@@ -348,12 +348,12 @@ void gemm_role(const BLaunch &L, hipStream_t s, int j, int cfg, const long long 
 }
 
 template <typename T> hipError_t precond_steps(const BLaunch &L, hipStream_t s, int j) {
-    gemm_role<0, T>(L, s, j, L.cfg_x, L.off.g[0]);
-    gemm_role<1, T>(L, s, j, L.cfg_y, L.off.g[1]);
+    gemm_role<0, T>(L, s, j, L.cfg[0], L.off.g[0]);
+    gemm_role<1, T>(L, s, j, L.cfg[1], L.off.g[1]);
     hipLaunchKernelGGL(k_b_tridiag<T>, dim3(L.tot_tri), dim3(L.tri_lx * L.tri_pb),
                        2 * sizeof(typename c2<T>::t) * (size_t)L.tri_lx * L.tri_pb, s, L.P, L.st, L.off.tri, L.np, L.tri_lx);
-    gemm_role<2, T>(L, s, j, L.cfg_y, L.off.g[2]);
-    gemm_role<3, T>(L, s, j, L.cfg_x, L.off.g[3]);
+    gemm_role<2, T>(L, s, j, L.cfg[2], L.off.g[2]);
+    gemm_role<3, T>(L, s, j, L.cfg[3], L.off.g[3]);
     return hipGetLastError();
 }
 

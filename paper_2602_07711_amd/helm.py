@@ -298,15 +298,18 @@ GEMM_KINDS = ["x64", "y64", "x32", "y32"]
 
 
 def helm_autotune(ctx: Context, reps: int = 5) -> dict:
-    """Time every tile configuration of the four EigT transform GEMMs on this context and keep the fastest.
-    Returns {kind: {"chosen": (BM, BN, BK), "ms": [per-config average ms or None]}}."""
-    chosen = (c_int * 4)()
-    ms = (c_double * 16)(*([-1.0] * 16))
+    """Time every tile configuration of the four EigT transforms (forward and inverse separately) on this context
+    and keep the fastest. Returns {kind: {"chosen": (BM, BN, BK), "ms": [per-config average ms or None],
+    "chosen_inverse": ..., "ms_inverse": [...]}}."""
+    chosen = (c_int * 8)()
+    ms = (c_double * 32)(*([-1.0] * 32))
     ctx.check(lib().helm_autotune(ctx.ptr, int(reps), chosen, ms))
     out = {}
     for k, name in enumerate(GEMM_KINDS):
-        t = [ms[4 * k + c] for c in range(4)]
-        out[name] = dict(chosen=GEMM_CONFIGS[chosen[k]], ms=[v if v >= 0 else None for v in t])
+        f = [ms[4 * k + c] for c in range(4)]
+        i = [ms[16 + 4 * k + c] for c in range(4)]
+        out[name] = dict(chosen=GEMM_CONFIGS[chosen[k]], ms=[v if v >= 0 else None for v in f],
+                         chosen_inverse=GEMM_CONFIGS[chosen[4 + k]], ms_inverse=[v if v >= 0 else None for v in i])
     return out
 
 
