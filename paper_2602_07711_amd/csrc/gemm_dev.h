@@ -236,9 +236,12 @@ template <int MODE, int BM, int BN> __host__ __device__ inline long long fold_ti
 }
 
 // Occupancy the register allocator is asked for: without it, the FP64 kernels keep their accumulators in
-// AGPRs on top of the VGPRs the operand staging needs and drop to two waves per SIMD.
-template <typename T, int BM, int BN, int BK> constexpr int fold_waves() {
-    return sizeof(T) == 8 ? (BM * BN * BK <= 64 * 64 * 16 ? 3 : 1) : (BM * BN * BK <= 64 * 64 * 16 ? 4 : 2);
+// AGPRs on top of the VGPRs the operand staging needs and drop to two waves per SIMD. The x-forward transforms
+// with FP64 data hold two raw FP64 values per operand element across a chunk (the butterfly is formed when the
+// chunk is written to LDS) and get one wave less.
+template <typename T, typename TD, int MODE, int BM, int BN, int BK> constexpr int fold_waves() {
+    return (sizeof(T) == 8 ? (BM * BN * BK <= 64 * 64 * 16 ? 3 : 1) : (BM * BN * BK <= 64 * 64 * 16 ? 4 : 2)) -
+           ((MODE == FOLD_XF && sizeof(TD) == 16 && BM * BN * BK <= 64 * 64 * 16) ? 1 : 0);
 }
 
 // a +- b in the precision the data is stored in, then converted to the arithmetic type
@@ -249,11 +252,15 @@ template <typename T, typename S> __device__ __forceinline__ typename cplx<T>::t
     return cvt<T>(r);
 }
 
-// The K loop of one tile: operands come from loadA(local row, k) and loadB(k, local column) (zero outside),
-// staged through LDS double buffered in registers, as in gemm_tile.
-template <typename T, int BM, int BN, int BK, int NS, int RW, typename LA, typename LB>
+template <typename S> struct Pair { S a, b; };
+
+// The K loop of one tile: raw operands come from loadA(local row, k) and loadB(k, local column) (zero outside) and
+// are staged through LDS double buffered in registers, as in gemm_tile. finA / finB turn a raw operand into the
+// arithmetic type (conversion, the butterfly's sum or difference) only when it is written to LDS, one chunk later:
+// doing it at load time would make every chunk wait for its own loads before the MFMAs that should hide them.
+template <typename T, int BM, int BN, int BK, int NS, int RW, typename LA, typename LB, typename FA, typename FB>
 __device__ __forceinline__ void fold_kloop(typename cplx<T>::acc (&t)[NS][BM / 32][BN / 32], int K, LA loadA,
-                                           LB loadB, typename cplx<T>::t (*sA)[BM + 1],
+                                           LB loadB, FA finA, FB finB, typename cplx<T>::t (*sA)[BM + 1],
                                            typename cplx<T>::t (*sB)[BN]) {
     typedef typename cplx<T>::t CT;
     constexpr int FM = BM / 32, FN = BN / 32, EA = BM * BK / 256, EB = BK * BN / 256;
@@ -263,7 +270,8 @@ __device__ __forceinline__ void fold_kloop(typename cplx<T>::acc (&t)[NS][BM / 3
     asm volatile("" : "+v"(tid));
     const int lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
-    CT ra[EA], rb[EB];
+    decltype(loadA(0, 0)) ra[EA];
+    decltype(loadB(0, 0)) rb[EB];
     auto fetch = [&](int k0) {
 #pragma unroll
         for (int e = 0; e < EA; ++e) {
@@ -285,12 +293,12 @@ __device__ __forceinline__ void fold_kloop(typename cplx<T>::acc (&t)[NS][BM / 3
 #pragma unroll
         for (int e = 0; e < EA; ++e) {
             const int idx = tid + e * 256;
-            sA[idx % BK][idx / BK] = ra[e];
+            sA[idx % BK][idx / BK] = finA(ra[e]);
         }
 #pragma unroll
         for (int e = 0; e < EB; ++e) {
             const int idx = tid + e * 256;
-            sB[idx / BN][idx % BN] = rb[e];
+            sB[idx / BN][idx % BN] = finB(rb[e]);
         }
         __syncthreads();
         if (k0 + BK < K) fetch(k0 + BK);
@@ -358,28 +366,32 @@ __device__ __forceinline__ void fold_tile(const TD *__restrict__ D, const TM *__
         const TM *Mp = skew ? Ma : Ms;
         const int m0 = mt * BM, n0 = nt * BN;
         if constexpr (MODE == FOLD_XF) {
-            auto la = [&](int mm, int gk) -> CT {
+            auto la = [&](int mm, int gk) -> Pair<TD> {
                 const int gm = m0 + mm;
-                if (gm >= rows || gk >= K) return CT{0, 0};
+                if (gm >= rows || gk >= K) return Pair<TD>{TD{0, 0}, TD{0, 0}};
                 const TD *row = D + (long long)gm * ld;
-                return fold2<T>(row[gk], row[n - 1 - gk], skew);
+                return Pair<TD>{row[gk], row[n - 1 - gk]};
             };
-            auto lb = [&](int gk, int nn) -> CT {
+            auto lb = [&](int gk, int nn) -> TM {
                 const int gn = n0 + nn;
-                return (gk < K && gn < K) ? cvt<T>(Mp[(long long)gk * K + gn]) : CT{0, 0};
+                return (gk < K && gn < K) ? Mp[(long long)gk * K + gn] : TM{0, 0};
             };
-            fold_kloop<T, BM, BN, BK, NS, RW>(t, K, la, lb, sA, sB);
+            auto fa = [&](const Pair<TD> &p) { return fold2<T>(p.a, p.b, skew); };
+            auto fb = [](const TM &v) { return cvt<T>(v); };
+            fold_kloop<T, BM, BN, BK, NS, RW>(t, K, la, lb, fa, fb, sA, sB);
         } else {
-            auto la = [&](int mm, int gk) -> CT {
+            auto la = [&](int mm, int gk) -> TM {
                 const int gm = m0 + mm;
-                return (gm < K && gk < K) ? cvt<T>(Mp[(long long)gm * K + gk]) : CT{0, 0};
+                return (gm < K && gk < K) ? Mp[(long long)gm * K + gk] : TM{0, 0};
             };
-            auto lb = [&](int gk, int nn) -> CT {
+            auto lb = [&](int gk, int nn) -> Pair<TD> {
                 const int gn = n0 + nn;
-                if (gk >= K || gn >= rows) return CT{0, 0};
-                return fold2<T>(D[(long long)gk * ld + gn], D[(long long)(n - 1 - gk) * ld + gn], skew);
+                if (gk >= K || gn >= rows) return Pair<TD>{TD{0, 0}, TD{0, 0}};
+                return Pair<TD>{D[(long long)gk * ld + gn], D[(long long)(n - 1 - gk) * ld + gn]};
             };
-            fold_kloop<T, BM, BN, BK, NS, RW>(t, K, la, lb, sA, sB);
+            auto fa = [](const TM &v) { return cvt<T>(v); };
+            auto fb = [&](const Pair<TD> &p) { return fold2<T>(p.a, p.b, skew); };
+            fold_kloop<T, BM, BN, BK, NS, RW>(t, K, la, lb, fa, fb, sA, sB);
         }
 #pragma unroll
         for (int i = 0; i < FM; ++i)
@@ -425,25 +437,29 @@ __device__ __forceinline__ void fold_tile(const TD *__restrict__ D, const TM *__
             const int K = q ? ma : ms, off = q ? f.moff : 0, mst = f.mstep;
             const TM *Mq = q ? Ma : Ms;
             if constexpr (MODE == FOLD_XI) {
-                auto la = [&](int mm, int gk) -> CT {
+                auto la = [&](int mm, int gk) -> TD {
                     const int gm = m0 + mm;
-                    return (gm < rows && gk < K) ? cvt<T>(D[(long long)gm * ld + off + mst * gk]) : CT{0, 0};
+                    return (gm < rows && gk < K) ? D[(long long)gm * ld + off + mst * gk] : TD{0, 0};
                 };
-                auto lb = [&](int gk, int nn) -> CT {
+                auto lb = [&](int gk, int nn) -> TM {
                     const int gn = n0 + nn;
-                    return (gk < K && gn < K) ? cvt<T>(Mq[(long long)gk * K + gn]) : CT{0, 0};
+                    return (gk < K && gn < K) ? Mq[(long long)gk * K + gn] : TM{0, 0};
                 };
-                fold_kloop<T, BM, BN, BK, NS, RW>(t, K, la, lb, sA, sB);
+                auto fa = [](const TD &v) { return cvt<T>(v); };
+                auto fb = [](const TM &v) { return cvt<T>(v); };
+                fold_kloop<T, BM, BN, BK, NS, RW>(t, K, la, lb, fa, fb, sA, sB);
             } else {
-                auto la = [&](int mm, int gk) -> CT {
+                auto la = [&](int mm, int gk) -> TM {
                     const int gm = m0 + mm;
-                    return (gm < K && gk < K) ? cvt<T>(Mq[(long long)gm * K + gk]) : CT{0, 0};
+                    return (gm < K && gk < K) ? Mq[(long long)gm * K + gk] : TM{0, 0};
                 };
-                auto lb = [&](int gk, int nn) -> CT {
+                auto lb = [&](int gk, int nn) -> TD {
                     const int gn = n0 + nn;
-                    return (gk < K && gn < rows) ? cvt<T>(D[(long long)(off + mst * gk) * ld + gn]) : CT{0, 0};
+                    return (gk < K && gn < rows) ? D[(long long)(off + mst * gk) * ld + gn] : TD{0, 0};
                 };
-                fold_kloop<T, BM, BN, BK, NS, RW>(t, K, la, lb, sA, sB);
+                auto fa = [](const TM &v) { return cvt<T>(v); };
+                auto fb = [](const TD &v) { return cvt<T>(v); };
+                fold_kloop<T, BM, BN, BK, NS, RW>(t, K, la, lb, fa, fb, sA, sB);
             }
             if (q == 0) {
                 // park P in this thread's own output slots (first half of the axis; the skew results go to the

@@ -8,6 +8,8 @@
 // the x- and y-transforms as one persistent launch each over all problems' tiles, and the grouped z-solves),
 // the shifted matvec y = v_j - A z_j, the block inner products V^H y and ||y||^2, the device Arnoldi step
 // (H column, Givens, residual estimate, stop test), and v_{j+1} = -(y - V h)/eta.
+#include <type_traits>
+
 #include "gemm_dev.h"
 #include "krylov_dev.h"
 #include "stencil_dev.h"
@@ -41,7 +43,9 @@ __device__ __forceinline__ int find_prob64(const long long *off, int np, long lo
 // ROLE 2: y-inverse  t1 = W_yI t2         ROLE 3: x-inverse  Z_j = t1 W_xI
 // (the folded transforms of the single-problem preconditioner: symmetric and skew half blocks of each axis)
 template <int ROLE, typename T, int BM, int BN, int BK>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(fold_waves<T, BM, BN, BK>()))) void k_b_gemm(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
+    fold_waves<T, typename std::conditional<ROLE == 0, double2, typename cplx<T>::t>::type,
+               ROLE == 0 ? FOLD_XF : ROLE == 1 ? FOLD_YF : ROLE == 2 ? FOLD_YI : FOLD_XI, BM, BN, BK>()))) void k_b_gemm(
     const BProb *__restrict__ P, const BState *__restrict__ st, const long long *__restrict__ toff, int np, int j) {
     typedef typename cplx<T>::t CT;
     const long long total = toff[np];

@@ -66,7 +66,7 @@ hipError_t launch(const GemmDesc &d, const TA *A, const TB *B, TC *C, hipStream_
 
 // RW = 0: complex blocks; RW = 1 / 2: real blocks (the sine basis) as the A (y) / B (x) operand
 template <int MODE, typename TD, typename TM, typename TC, typename T, int BM, int BN, int BK, int RW>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(fold_waves<T, BM, BN, BK>()))) void k_fold(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(fold_waves<T, TD, MODE, BM, BN, BK>()))) void k_fold(
     const TD *__restrict__ D, const TM *__restrict__ Ms, const TM *__restrict__ Ma, TC *__restrict__ C, FoldDesc f) {
     const long long total = fold_tiles<MODE, BM, BN>(f);
     const long long per = (total + 7) / 8;
