@@ -92,7 +92,9 @@ __device__ __forceinline__ void matvec_tile(const XT *__restrict__ x, const doub
         offs[q] = cy * nx + cx;
         fxy[q] = fac;
     }
-    double2 ru[2][2];
+    // raw prefetched values: a complex64 input is widened when the plane is written to LDS, not when its load is
+    // issued (that would make every plane wait for its own loads)
+    XT ru[2][2];
     KT rk[2][2];
     auto gload = [&](auto setc, int z) {
         constexpr int S = decltype(setc)::value;
@@ -101,7 +103,7 @@ __device__ __forceinline__ void matvec_tile(const XT *__restrict__ x, const doub
         for (int q = 0; q < 2; ++q)
             if (tid + 512 * q < LX * LY) {
                 const long long idx = (long long)cz * plane + offs[q];
-                ru[S][q] = to_d2(x[idx]);
+                ru[S][q] = x[idx];
                 if constexpr (KC) rk[S][q] = make_double2(k2[idx], p.k2i[idx]);
                 else rk[S][q] = k2[idx];
             }
@@ -114,7 +116,7 @@ __device__ __forceinline__ void matvec_tile(const XT *__restrict__ x, const doub
             const int e = tid + 512 * q;
             if (e < LX * LY) {
                 const double2 f = gh ? cmul(p.gz, fxy[q]) : fxy[q];
-                su[S][e / LX][e % LX] = cmul(f, ru[S][q]);
+                su[S][e / LX][e % LX] = cmul(f, to_d2(ru[S][q]));
                 sk[S][e / LX][e % LX] = rk[S][q];
             }
         }
