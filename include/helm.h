@@ -50,7 +50,7 @@ typedef enum {
     HELM_ENOCONV = 4,      /* GMRES hit maxit; x holds the last iterate                                    */
     HELM_EBREAKDOWN = 5,   /* Arnoldi breakdown with a residual above tolerance                            */
     HELM_ENUMERIC = 6,     /* NaN/Inf appeared in a reduction, or the 1D eigen-decomposition failed checks */
-    HELM_EUNSUPPORTED = 7  /* a valid request that this build does not implement                           */
+    HELM_EUNSUPPORTED = 7  /* a valid request that the library does not implement                          */
 } helm_status;
 
 typedef struct { int nx, ny, nz; } helm_grid;   /* unknowns per axis, each >= 3 */

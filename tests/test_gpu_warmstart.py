@@ -10,7 +10,7 @@ best multiple of its output still misses the field almost entirely), and the ini
 (the scaling guarantees <= ||F||). EigT-preconditioned FGMRES reduces the residual by a factor 3-5 per iteration here, so a guess
 accurate to 5-10 % is worth at most about one iteration: the test bounds the iteration change by one on average
 (the full-size iteration and time effect at 128^3 is measured by the benchmark). The solver
-stays the judge: every run converges to rtol 1e-8 relative to ||F||, so the warm-started and zero-started
+decides the answer: every run converges to rtol 1e-8 relative to ||F||, so the warm-started and zero-started
 solutions agree to that level whatever the network predicts.
 """
 import numpy as np
