@@ -93,3 +93,55 @@ def test_batch_restarts_and_iteration_cap():
         assert np.linalg.norm(host(x) - xr) <= 1e-8 * np.linalg.norm(xr)
     xs, infos = h.helm_batch_solve(batch, [F, F.clone()], rtol=1e-14, maxit=3, raise_on_noconv=False)
     assert all(i["iters"] == 3 and not i["converged"] for i in infos)
+
+
+@pytest.mark.parametrize("fp32", [True, False])
+def test_split_direction_tiles_single_and_batch(fp32, tmp_path, monkeypatch):
+    """Forward and inverse transforms with different tile configurations (forced through the tune cache): the
+    single-problem preconditioner keeps its parity with the oracle, and a batch, whose grouped launches take a tile
+    count per role from those choices, reaches the sparse LU solution. The box is ragged (the halves of every axis
+    span more than one tile of the forward shapes)."""
+    from oracle import precond as pc
+    h = H()
+    nx, ny, nz = 70, 20, 12
+    shape = (nz, ny, nx)
+    hh = 1.0 / (nx + 1)
+    k0 = 0.45 * (nx + 1)
+    rng = np.random.default_rng(5)
+    k2 = k0 * k0 * (1.0 + 0.2 * rng.random((nz + 4, ny + 4, nx + 4)))
+    # tune-cache keys: transform kind, direction (0 forward, 1 inverse), axis length, lines, slices
+    fwd = {0: 3, 1: 2, 2: 3, 3: 2}       # (64,128,16) on x, (128,64,16) on y
+    inv = {0: 1, 1: 1, 2: 1, 3: 1}       # (64,64,32)
+    lines = []
+    for kind in range(4):
+        n_ax, rows, batch = (nx, ny * nz, 1) if kind % 2 == 0 else (ny, nx, nz)
+        lines.append(f"v5 {kind} 0 {n_ax} {rows} {batch} {fwd[kind]}")
+        lines.append(f"v5 {kind} 1 {n_ax} {rows} {batch} {inv[kind]}")
+    cache = tmp_path / "tune.txt"
+    cache.write_text("\n".join(lines) + "\n")
+    monkeypatch.setenv("HELM_TUNE_CACHE", str(cache))
+    ctx = h.helm_setup(dev(k2), hh, 4, k0=k0, shape=shape)
+    res = h.helm_autotune(ctx, reps=1)
+    from paper_2602_07711_amd import helm as hm
+    cfgs = hm.GEMM_CONFIGS
+    for kind, name in enumerate(hm.GEMM_KINDS):
+        assert tuple(res[name]["chosen"]) == tuple(cfgs[fwd[kind]])
+        assert tuple(res[name]["chosen_inverse"]) == tuple(cfgs[inv[kind]])
+    # single-problem preconditioner
+    y = rng.standard_normal(nx * ny * nz) + 1j * rng.standard_normal(nx * ny * nz)
+    gs = tuple(op.gamma_abc(k0, hh) for _ in range(3))
+    zr = pc.EigT(shape, (hh, hh, hh), k0, gs).solve(y)
+    z = host(h.helm_precond_apply(ctx, dev(y), fp32=fp32))
+    assert np.linalg.norm(z - zr) <= (2e-4 if fp32 else 1e-11) * np.linalg.norm(zr)
+    # a batch of two right-hand sides on this context
+    fs = [rng.standard_normal((nz + 4, ny + 4, nx + 4)) + 0j for _ in range(2)]
+    Fs = [h.helm_rhs(ctx, dev(f)) for f in fs]
+    batch = h.helm_batch_create([ctx, ctx], m=30, prec_fp32=fp32)
+    xs, infos = h.helm_batch_solve(batch, Fs, rtol=1e-10)
+    A, _ = op.problem(4, k2, fs[0], hh, k0)
+    lu = spla.splu(A.tocsc())
+    for f, x, info in zip(fs, xs, infos):
+        xr = lu.solve(op.rhs(4, f, (hh, hh, hh), k2[2:-2, 2:-2, 2:-2]).ravel())
+        rel = np.linalg.norm(host(x) - xr) / np.linalg.norm(xr)
+        print("split tiles batch", fp32, info, rel)
+        assert info["converged"] and rel <= 1e-8
