@@ -465,6 +465,7 @@ helm_status fftk_apply(Ctx &c, const double2 *y, double2 *z, bool fp32, int orde
         ST_TRY(sine_tf(c, 1, true, c.t1, c.t2, m));
         ST_TRY(sine_tf(c, 2, true, c.t2, c.t1, m));
         HIP_TRY(launch_sym_divide_z64(c.t1, P.tx, P.ty, P.tz, nx, ny, nz, q, c.stream));
+        prof_gap(c);
         ST_TRY(sine_tf(c, 2, false, c.t1, c.t2, m));
         ST_TRY(sine_tf(c, 1, false, c.t2, c.t1, m));
         ST_TRY(sine_tf(c, 0, false, c.t1, z, m));
@@ -475,6 +476,7 @@ helm_status fftk_apply(Ctx &c, const double2 *y, double2 *z, bool fp32, int orde
         ST_TRY(sine_tf(c, 1, true, c.t1f, c.t2f, m));
         ST_TRY(sine_tf(c, 2, true, c.t2f, c.t1f, m));
         HIP_TRY(launch_sym_divide_z32(c.t1f, P.tx, P.ty, P.tz, nx, ny, nz, q, c.stream));
+        prof_gap(c);
         ST_TRY(sine_tf(c, 2, false, c.t1f, c.t2f, m));
         ST_TRY(sine_tf(c, 1, false, c.t2f, c.t1f, m));
         if (z32) ST_TRY(sine_tf(c, 0, false, c.t1f, z32, m));
@@ -484,6 +486,7 @@ helm_status fftk_apply(Ctx &c, const double2 *y, double2 *z, bool fp32, int orde
 }
 
 helm_status precond(Ctx &c, const double2 *y, double2 *z, int kind, int fp32) {
+    prof_gap(c);   // lazy set-up or an untimed copy may follow
     if (kind == HELM_PREC_EIGT) return eigt_apply(c, y, z, fp32 != 0);
     if (kind == HELM_PREC_NONE) {
         if (y != z) HIP_TRY(hipMemcpyAsync(z, y, (size_t)c.n * sizeof(double2), hipMemcpyDeviceToDevice, c.stream));
@@ -538,8 +541,9 @@ helm_status dots(Ctx &c, const double2 *V, int nv, const double2 *w, std::vector
     KrylovWork &k = c.kw;
     HIP_TRY(timed(c, HELM_K_DOTS, 16.0 * c.n * (nv + 1), [&] { return launch_dots(V, k.ld, nv, w, c.n, k.partials, k.nblocks, k.red, c.stream); }));
     HIP_TRY(hipMemcpyAsync(k.red_host, k.red, (nv + 1) * sizeof(double2), hipMemcpyDeviceToHost, c.stream));
+    prof_gap(c);
     HIP_TRY(hipStreamSynchronize(c.stream));
-    prof_resolve(c);
+    // (profiling events are read once per solve, not here: this is the point where the GPU waits for the host)
     out.resize(nv + 1);
     for (int i = 0; i <= nv; ++i) out[i] = cd(k.red_host[i].x, k.red_host[i].y);
     for (int i = 0; i <= nv; ++i)
@@ -589,6 +593,13 @@ helm_status helm_profile_enable(helm_ctx *ctx, int on) {
     prof_resolve(c);
     if (on) {
         for (int i = 0; i < HELM_K_COUNT; ++i) { c.prof_ms[i] = 0.0; c.prof_n[i] = 0; c.prof_work[i] = 0.0; }
+        // events are read once per solve: create enough for a few hundred Arnoldi steps up front, so that a timed
+        // solve does not create them between its launches
+        while (c.prof_pool.size() < 4096) {
+            hipEvent_t e;
+            HIP_TRY(timing_event(&e));
+            c.prof_pool.push_back(e);
+        }
     }
     c.prof = on != 0;
     return HELM_OK;
@@ -843,8 +854,8 @@ helm_status helm_autotune(helm_ctx *ctx, int reps, int *chosen, double *ms) {
     ST_TRY(ensure_fp32_work(c));
     const FoldDesc fxd = fold_x(c), fyd = fold_y(c);
     hipEvent_t e0, e1;
-    HIP_TRY(hipEventCreate(&e0));
-    HIP_TRY(hipEventCreate(&e1));
+    HIP_TRY(timing_event(&e0));
+    HIP_TRY(timing_event(&e1));
     for (int kind = 0; kind < 4; ++kind) {
         const FoldDesc &d = (kind % 2 == 0) ? fxd : fyd;
         for (int dir = 0; dir < 2; ++dir) {            // 0: forward, 1: inverse
@@ -930,6 +941,7 @@ helm_status helm_matvec(helm_ctx *ctx, const void *x_dev, void *y_dev) {
     }
     if (!x_dev || !y_dev) { c.err = "NULL pointer"; return HELM_EINVAL; }
     if (x_dev == y_dev) { c.err = "matvec input and output must not overlap"; return HELM_EINVAL; }
+    prof_gap(c);
     HIP_TRY(timed(c, HELM_K_MATVEC, matvec_bytes(c, false), [&] { return launch_matvec(c.sp, (const double2 *)x_dev, c.k2, c.fld, nullptr, (double2 *)y_dev, c.stream); }));
     return HELM_OK;
 }
@@ -951,10 +963,12 @@ helm_status helm_scale_guess(helm_ctx *ctx, const void *F_dev, void *x_dev, doub
     }
     double2 *x = (double2 *)x_dev;
     const double2 *F = (const double2 *)F_dev;
+    prof_gap(c);
     // y = A x; (y^H F, ||F||^2) then ||y||^2
     HIP_TRY(timed(c, HELM_K_MATVEC, matvec_bytes(c, false), [&] { return launch_matvec(c.sp, x, c.k2, c.fld, nullptr, c.sg_y, c.stream); }));
     HIP_TRY(timed(c, HELM_K_DOTS, 32.0 * c.n, [&] { return launch_dots(c.sg_y, c.n, 1, F, c.n, c.sg_part, nb, c.sg_red, c.stream); }));
     HIP_TRY(hipMemcpyAsync(c.sg_host, c.sg_red, sizeof(double2), hipMemcpyDeviceToHost, c.stream));
+    prof_gap(c);
     HIP_TRY(timed(c, HELM_K_DOTS, 16.0 * c.n, [&] { return launch_dots(nullptr, c.n, 0, c.sg_y, c.n, c.sg_part, nb, c.sg_red, c.stream); }));
     HIP_TRY(hipMemcpyAsync(c.sg_host + 1, c.sg_red, sizeof(double2), hipMemcpyDeviceToHost, c.stream));
     HIP_TRY(hipStreamSynchronize(c.stream));
@@ -1013,10 +1027,12 @@ helm_status helm_gmres_solve(helm_ctx *ctx, const void *F_dev, void *x_dev, cons
     const long long n = c.n;
     auto t_start = std::chrono::steady_clock::now();
 
-    // phase timers: 0 matvec, 1 preconditioner, 2 Arnoldi, 3 end-of-cycle update
-    hipEvent_t ev[8];
-    for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
-    struct EvGuard { hipEvent_t *e; ~EvGuard() { for (int i = 0; i < 8; ++i) (void)hipEventDestroy(e[i]); } } guard{ev};
+    // phase timers: 0 matvec, 1 preconditioner, 2 Arnoldi, 3 end-of-cycle update. The orthogonalisation update of
+    // step j is bracketed by ev[8 + 2 (j & 1)] and ev[9 + 2 (j & 1)], so that its timing is read one step later
+    // without the pair being recorded again in between; every timer is read after the next launch is queued.
+    hipEvent_t ev[12];
+    for (auto &e : ev) HIP_TRY(timing_event(&e));
+    struct EvGuard { hipEvent_t *e; ~EvGuard() { for (int i = 0; i < 12; ++i) (void)hipEventDestroy(e[i]); } } guard{ev};
     auto elapsed = [&](hipEvent_t a, hipEvent_t b) {
         float ms = 0.f;
         (void)hipEventSynchronize(b);
@@ -1025,6 +1041,7 @@ helm_status helm_gmres_solve(helm_ctx *ctx, const void *F_dev, void *x_dev, cons
     };
 
     double bnorm = 0.0;
+    prof_gap(c);
     ST_TRY(norm2(c, F, bnorm));
     int hist_used = 0;
     auto push_hist = [&](double v) {
@@ -1039,6 +1056,7 @@ helm_status helm_gmres_solve(helm_ctx *ctx, const void *F_dev, void *x_dev, cons
         return HELM_OK;
     }
     if (!opts->x0_given) HIP_TRY(launch_fill_zero(x, n, c.stream));
+    prof_gap(c);
 
     std::vector<cd> H((size_t)(m + 1) * m), g(m + 1), sn(m), hv, hv2;
     std::vector<double> cs(m);
@@ -1046,9 +1064,10 @@ helm_status helm_gmres_solve(helm_ctx *ctx, const void *F_dev, void *x_dev, cons
     int its = 0;
     helm_status result = HELM_ENOCONV;
     bool first = true;
-    bool pending_upd = false;   // ev[5] -> ev[6] (orthogonalisation update) not yet accumulated
+    bool pending_upd = false;   // the last orthogonalisation update's pair, not yet accumulated
+    hipEvent_t upd_a = nullptr, upd_b = nullptr;
     auto flush_upd = [&]() {
-        if (pending_upd) inf.t_ms[2] += elapsed(ev[5], ev[6]);
+        if (pending_upd) inf.t_ms[2] += elapsed(upd_a, upd_b);
         pending_upd = false;
     };
     for (;;) {
@@ -1056,6 +1075,7 @@ helm_status helm_gmres_solve(helm_ctx *ctx, const void *F_dev, void *x_dev, cons
         HIP_TRY(hipEventRecord(ev[0], c.stream));
         if (first && !opts->x0_given) {
             HIP_TRY(hipMemcpyAsync(k.V, F, n * sizeof(double2), hipMemcpyDeviceToDevice, c.stream));
+            prof_gap(c);
         } else {
             HIP_TRY(timed(c, HELM_K_MATVEC, matvec_bytes(c, true), [&] { return launch_matvec(c.sp, x, c.k2, c.fld, F, k.V, c.stream); }));
         }
@@ -1094,14 +1114,12 @@ helm_status helm_gmres_solve(helm_ctx *ctx, const void *F_dev, void *x_dev, cons
             HIP_TRY(hipEventRecord(ev[4], c.stream));
             // classical Gram-Schmidt: V^H y and ||y||^2 in one pass
             ST_TRY(dots(c, k.V, j + 1, w, hv));
-            flush_upd();
-            inf.t_ms[1] += elapsed(ev[2], ev[3]);
-            inf.t_ms[0] += elapsed(ev[3], ev[4]);
             double hh = 0.0;
             for (int i = 0; i <= j; ++i) hh += std::norm(hv[i]);
             double ww = hv[j + 1].real();
             double eta2 = ww - hh;
-            HIP_TRY(hipEventRecord(ev[5], c.stream));
+            hipEvent_t ua = ev[8 + 2 * (j & 1)], ub = ev[9 + 2 * (j & 1)];
+            HIP_TRY(hipEventRecord(ua, c.stream));
             if (!(eta2 > 0.5 * ww)) {
                 // cancellation: subtract, then re-orthogonalise once (and take the norm from the second pass)
                 ++inf.reorths;
@@ -1121,7 +1139,12 @@ helm_status helm_gmres_solve(helm_ctx *ctx, const void *F_dev, void *x_dev, cons
                 for (int i = 0; i <= j; ++i) { coef[i].x /= eta; coef[i].y /= eta; }
                 HIP_TRY(timed(c, HELM_K_LINCOMB, 16.0 * c.n * (j + 3), [&] { return launch_lincomb(w, w, make_double2(-1.0 / eta, 0.0), k.V, k.ld, j + 1, coef.data(), n, c.stream); }));
             }
-            HIP_TRY(hipEventRecord(ev[6], c.stream));
+            HIP_TRY(hipEventRecord(ub, c.stream));
+            // phase bookkeeping while the GPU runs the update
+            flush_upd();
+            inf.t_ms[1] += elapsed(ev[2], ev[3]);
+            inf.t_ms[0] += elapsed(ev[3], ev[4]);
+            inf.t_ms[2] += elapsed(ev[4], ua);
             // Hessenberg column j and Givens rotations
             for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = -hv[i];
             H[(size_t)j * m + j] += 1.0;
@@ -1147,7 +1170,8 @@ helm_status helm_gmres_solve(helm_ctx *ctx, const void *F_dev, void *x_dev, cons
                 g[j + 1] = -std::conj(sn[j]) * g[j];
                 g[j] = cs[j] * g[j];
             }
-            inf.t_ms[2] += elapsed(ev[4], ev[5]);
+            upd_a = ua;
+            upd_b = ub;
             pending_upd = true;
             ++its;
             kk = j + 1;
@@ -1190,6 +1214,7 @@ helm_status helm_gmres_solve(helm_ctx *ctx, const void *F_dev, void *x_dev, cons
     }
     inf.iters = its;
     inf.hist_used = hist_used;
+    prof_resolve(c);
     auto t_end = std::chrono::steady_clock::now();
     inf.t_ms[5] = std::chrono::duration<double, std::milli>(t_end - t_start).count();
     inf.t_ms[4] = inf.t_ms[5] - (inf.t_ms[0] + inf.t_ms[1] + inf.t_ms[2] + inf.t_ms[3]);

@@ -144,7 +144,7 @@ struct KrylovWork {
     int nblocks = 0;
 };
 
-struct ProfPending { int cls; double work; hipEvent_t a, b; };
+struct ProfPending { int cls; double work; hipEvent_t a, b; bool own_a; };   // own_a: a is not the previous b
 
 struct Ctx {
     int nx, ny, nz;
@@ -195,32 +195,48 @@ struct Ctx {
     double prof_work[HELM_K_COUNT] = {};
     std::vector<ProfPending> prof_pending;
     std::vector<hipEvent_t> prof_pool;
+    hipEvent_t prof_last = nullptr;   // end event of the last timed launch (the next one's start while it is pending)
 };
 
-// Launch through `fn` (returning hipError_t), bracketed by profiling events when enabled.
+// Events that only time work: no system-scope fence when recorded. With the default fence every record writes back
+// and invalidates the caches, which costs a few microseconds per record and slows the kernel after it; nothing is
+// read through these events (results reach the host through stream synchronisation).
+inline hipError_t timing_event(hipEvent_t *e) { return hipEventCreateWithFlags(e, hipEventDisableSystemFence); }
+
+// Launch through `fn` (returning hipError_t), bracketed by profiling events when enabled. Launches that follow each
+// other on the stream share events: the end of one is the start of the next (one record per launch). A fresh start
+// is recorded when the previous end has already completed, i.e. when the stream may have been idle in between (a
+// host synchronisation), so that idle time is not counted as kernel time. Wherever other stream work can run
+// between two timed launches (an untimed kernel or copy, the caller's own work between library calls) the chain
+// is broken first with prof_gap.
+inline void prof_gap(Ctx &c) { c.prof_last = nullptr; }
+inline hipError_t prof_event(Ctx &c, hipEvent_t *e) {
+    if (!c.prof_pool.empty()) {
+        *e = c.prof_pool.back();
+        c.prof_pool.pop_back();
+        return hipSuccess;
+    }
+    return timing_event(e);
+}
 template <typename F> hipError_t timed(Ctx &c, int cls, double work, F fn) {
     if (!c.prof) return fn();
-    hipEvent_t a, b;
-    if (c.prof_pool.size() >= 2) {
-        a = c.prof_pool.back(); c.prof_pool.pop_back();
-        b = c.prof_pool.back(); c.prof_pool.pop_back();
-    } else {
-        hipError_t e = hipEventCreate(&a);
-        if (e != hipSuccess) return e;
-        e = hipEventCreate(&b);
-        if (e != hipSuccess) return e;
+    hipEvent_t a = c.prof_last, b;
+    const bool own_a = !a || hipEventQuery(a) != hipErrorNotReady;
+    hipError_t e;
+    if (own_a) {
+        if ((e = prof_event(c, &a)) != hipSuccess) return e;
+        if ((e = hipEventRecord(a, c.stream)) != hipSuccess) return e;
     }
-    hipError_t e = hipEventRecord(a, c.stream);
-    if (e != hipSuccess) return e;
-    e = fn();
-    if (e != hipSuccess) return e;
-    e = hipEventRecord(b, c.stream);
-    if (e != hipSuccess) return e;
-    c.prof_pending.push_back({cls, work, a, b});
+    if ((e = fn()) != hipSuccess) return e;
+    if ((e = prof_event(c, &b)) != hipSuccess) return e;
+    if ((e = hipEventRecord(b, c.stream)) != hipSuccess) return e;
+    c.prof_pending.push_back({cls, work, a, b, own_a});
+    c.prof_last = b;
     return hipSuccess;
 }
 
-// Accumulate every completed pending pair (call after a stream synchronisation).
+// Accumulate every completed pending pair (call after a stream synchronisation). Each event returns to the pool
+// once: the b of every pair, and the a of pairs that recorded their own start.
 inline void prof_resolve(Ctx &c) {
     for (auto &p : c.prof_pending) {
         float ms = 0.f;
@@ -229,10 +245,11 @@ inline void prof_resolve(Ctx &c) {
             c.prof_n[p.cls] += 1;
             c.prof_work[p.cls] += p.work;
         }
-        c.prof_pool.push_back(p.a);
+        if (p.own_a) c.prof_pool.push_back(p.a);
         c.prof_pool.push_back(p.b);
     }
     c.prof_pending.clear();
+    c.prof_last = nullptr;
 }
 
 // ----- batched solves: per-problem descriptors and device-side GMRES state -----
