@@ -179,9 +179,12 @@ typedef enum {
     HELM_K_COUNT = 11
 } helm_kernel_class;
 
-/* Per-kernel device timing. With on = 1 every kernel the context launches is bracketed by HIP events on the
+/* Per-kernel device timing. With on = 1 every launch of the classes above is bracketed by HIP events on the
  * context stream and its duration is accumulated by class (counters reset); on = 0 stops recording.
- * Pending events are resolved at the library's own synchronisation points and in helm_profile_read. */
+ * Launches that follow each other on the stream share an event (the end of one is the start of the next), so
+ * a launch's time includes the few microseconds of launch gap before it. Idle time after a host
+ * synchronisation, untimed library work and work the caller enqueues between library calls are not counted.
+ * Pending events are resolved at the end of a solve and in helm_profile_read. */
 helm_status helm_profile_enable(helm_ctx *ctx, int on);
 
 /* Accumulated device milliseconds, launch count and algorithmic work of one kernel class since the last

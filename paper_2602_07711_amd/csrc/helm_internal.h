@@ -220,16 +220,24 @@ inline hipError_t prof_event(Ctx &c, hipEvent_t *e) {
 }
 template <typename F> hipError_t timed(Ctx &c, int cls, double work, F fn) {
     if (!c.prof) return fn();
-    hipEvent_t a = c.prof_last, b;
+    hipEvent_t a = c.prof_last, b = nullptr;
     const bool own_a = !a || hipEventQuery(a) != hipErrorNotReady;
     hipError_t e;
+    // on an error the events taken here go back to the pool and the chain is broken
+    auto fail = [&](hipError_t err) {
+        if (own_a && a) c.prof_pool.push_back(a);
+        if (b) c.prof_pool.push_back(b);
+        c.prof_last = nullptr;
+        return err;
+    };
     if (own_a) {
-        if ((e = prof_event(c, &a)) != hipSuccess) return e;
-        if ((e = hipEventRecord(a, c.stream)) != hipSuccess) return e;
+        a = nullptr;
+        if ((e = prof_event(c, &a)) != hipSuccess) return fail(e);
+        if ((e = hipEventRecord(a, c.stream)) != hipSuccess) return fail(e);
     }
-    if ((e = fn()) != hipSuccess) return e;
-    if ((e = prof_event(c, &b)) != hipSuccess) return e;
-    if ((e = hipEventRecord(b, c.stream)) != hipSuccess) return e;
+    if ((e = fn()) != hipSuccess) return fail(e);
+    if ((e = prof_event(c, &b)) != hipSuccess) return fail(e);
+    if ((e = hipEventRecord(b, c.stream)) != hipSuccess) return fail(e);
     c.prof_pending.push_back({cls, work, a, b, own_a});
     c.prof_last = b;
     return hipSuccess;
