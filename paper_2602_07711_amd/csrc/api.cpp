@@ -739,8 +739,9 @@ helm_status setup_impl(helm_ctx **out, helm_grid g, const double h[3], const voi
         p.h2 = c.hx * c.hx;
     }
     p.tiles_x = (c.nx + 63) / 64;
-    p.tiles_y = (c.ny + 7) / 8;
-    int want = (1024 + p.tiles_x * p.tiles_y - 1) / (p.tiles_x * p.tiles_y);
+    p.tiles_y = (c.ny + STENCIL_TY - 1) / STENCIL_TY;
+    const int blocks = STENCIL_WAVES / STENCIL_TY;   // blocks of STENCIL_TY waves
+    int want = (blocks + p.tiles_x * p.tiles_y - 1) / (p.tiles_x * p.tiles_y);
     want = std::max(1, std::min(want, c.nz));
     p.zchunk = (c.nz + want - 1) / want;
     p.zchunks = (c.nz + p.zchunk - 1) / p.zchunk;

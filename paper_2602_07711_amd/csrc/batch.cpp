@@ -106,7 +106,7 @@ helm_status helm_batch_create(helm_batch **out, helm_ctx *const *ctxs, int np, i
     int tri_lx = 16;
     while (tri_lx > 1 && tri_lx * tri_pb > 1024) tri_lx /= 2;
     // per-problem descriptors, work buffers and launch offsets
-    long long tot_blocks_mv_target = 4096;
+    long long tot_blocks_mv_target = 32768 / STENCIL_TY;   // about 32768 waves over all problems
     std::vector<int> omv(1, 0), otri(1, 0), odot(1, 0), olc(1, 0);
     std::vector<long long> og[4];
     for (auto &v : og) v.assign(1, 0);

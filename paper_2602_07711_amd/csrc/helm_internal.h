@@ -27,6 +27,11 @@ bool eig_lambda_bar_folded(int n, cd gamma, double zeta, EigFold &f, std::string
 void eig_fold_dense(const EigFold &f, std::vector<cd> &d, std::vector<cd> &V, std::vector<cd> &Vinv);
 
 // Stencil coefficients that depend only on the grid (the k^2-dependent parts are per node).
+// Matvec thread block: 64 x STENCIL_TY threads, one output column each; the z-chunk length is chosen so that a
+// launch holds about STENCIL_WAVES waves in total.
+constexpr int STENCIL_TY = 8;
+constexpr int STENCIL_WAVES = 8192;
+
 struct StencilParams {
     int nx, ny, nz;
     int order;

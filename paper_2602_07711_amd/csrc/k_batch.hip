@@ -84,7 +84,7 @@ __global__ __launch_bounds__(1024) void k_b_tridiag(const BProb *__restrict__ P,
 // ---------------------------------------------------------------------------------------------- matvec
 // mode 0: restart, V_0 = F - A x (problems not done); mode 1: step j, V_{j+1} = V_j - A Z_j (active problems)
 template <int ORDER>
-__global__ __launch_bounds__(512) void k_b_matvec(const BProb *__restrict__ P, const BState *__restrict__ st,
+__global__ __launch_bounds__(NT) void k_b_matvec(const BProb *__restrict__ P, const BState *__restrict__ st,
                                                   const int *__restrict__ off, int np, int mode, int j) {
     const int p = find_prob(off, np, blockIdx.x);
     if (mode == 0 ? st[p].done : !st[p].active) return;

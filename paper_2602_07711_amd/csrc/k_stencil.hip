@@ -154,7 +154,7 @@ __global__ void k_rhs(const double2 *__restrict__ f, const double *__restrict__ 
 }
 
 template <int ORDER, bool RESID, typename XT, bool KC>
-__global__ __launch_bounds__(512) void k_matvec(const XT *__restrict__ x, const double *__restrict__ k2,
+__global__ __launch_bounds__(NT) void k_matvec(const XT *__restrict__ x, const double *__restrict__ k2,
                                                  const double4 *__restrict__ fld, const double2 *__restrict__ F,
                                                  double2 *__restrict__ y, StencilParams p) {
     matvec_tile<ORDER, RESID, XT, KC>(x, k2, fld, F, y, p, blockIdx.x);

@@ -19,7 +19,7 @@ __device__ __forceinline__ double2 cfma(double s, double2 a, double2 acc) {
 
 // --------------------------------------------------------------------------- matvec
 // y = A x (RESID: y = F - A x) for the operators documented in k_stencil.hip, organised so that every node's
-// value is read from LDS once per plane: a block of 64 x 8 threads owns a 64 x 8 column of outputs (one z-chunk)
+// value is read from LDS once per plane: a block of 64 x TY threads owns a 64 x TY column of outputs (one z-chunk)
 // and streams planes p = z0-1 .. z1 through a
 // double-buffered LDS tile (with the ghost rule applied on load) and scatters each plane's 3 x 3 in-plane
 // neighbourhood into three register accumulators, for the outputs at p+1, p and p-1 (the plane is their lower,
@@ -31,9 +31,11 @@ __device__ __forceinline__ double2 cfma(double s, double2 a, double2 acc) {
 // plane ahead, so one barrier per plane suffices. `bid` is the block's tile slot; the tile order puts
 // consecutive tiles on one XCD when blocks are dispatched round-robin over the 8 XCDs.
 constexpr int TX = 64;         // tile width along x (one wavefront row)
-constexpr int TY = 8;          // tile height along y, one thread row each (block 64 x 8)
+constexpr int TY = STENCIL_TY; // tile height along y, one thread row each (block 64 x TY)
+constexpr int NT = TX * TY;     // threads per block
 constexpr int LX = TX + 2;
 constexpr int LY = TY + 2;
+static_assert(2 * NT >= LX * LY, "two prefetch elements per thread cover the haloed tile");
 
 // k^2-valued quantities: double for real k^2, double2 for complex k^2
 __device__ __forceinline__ double2 kmul(double k, double2 u) { return cscale(u, k); }
@@ -74,13 +76,13 @@ __device__ __forceinline__ void matvec_tile(const XT *__restrict__ x, const doub
     const bool valid = gxo < nx && gyo < ny;
     const long long col = valid ? (long long)gyo * nx + gxo : 0;
 
-    // plane prefetch registers, two sets (planes alternate between them): elements tid and tid + 512 of the
+    // plane prefetch registers, two sets (planes alternate between them): elements tid and tid + NT of the
     // (LY x LX) tile; the in-plane part of the ghost factor is fixed per element, the z part per plane
     int offs[2];
     double2 fxy[2];
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
-        const int e = tid + 512 * q;
+        const int e = tid + NT * q;
         const int ex = e % LX, ey = e / LX;
         const int gx = x0 - 1 + ex, gy = y0 - 1 + ey;
         double2 fac = make_double2(1.0, 0.0);
@@ -101,7 +103,7 @@ __device__ __forceinline__ void matvec_tile(const XT *__restrict__ x, const doub
         const int cz = z < 0 ? 0 : (z >= nz ? nz - 1 : z);
 #pragma unroll
         for (int q = 0; q < 2; ++q)
-            if (tid + 512 * q < LX * LY) {
+            if (tid + NT * q < LX * LY) {
                 const long long idx = (long long)cz * plane + offs[q];
                 ru[S][q] = x[idx];
                 if constexpr (KC) rk[S][q] = make_double2(k2[idx], p.k2i[idx]);
@@ -113,7 +115,7 @@ __device__ __forceinline__ void matvec_tile(const XT *__restrict__ x, const doub
         const bool gh = z < 0 || z >= nz;
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
-            const int e = tid + 512 * q;
+            const int e = tid + NT * q;
             if (e < LX * LY) {
                 const double2 f = gh ? cmul(p.gz, fxy[q]) : fxy[q];
                 su[S][e / LX][e % LX] = cmul(f, to_d2(ru[S][q]));
