@@ -1,0 +1,129 @@
+"""Error behaviour of the C ABI on a live context, and in-place preconditioner calls.
+
+Every invalid call returns HELM_EINVAL with a message, touches none of the caller's buffers, and leaves the
+context usable. A preconditioner applied in place (y and z the same buffer, which the header allows) gives
+exactly the out-of-place result for every kind and precision: each kind reads y only in its first kernel and
+writes z only in its last, and every kernel is deterministic.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def H():
+    import paper_2602_07711_amd.helm as mod      # the binding module (status codes, ABI structs)
+    mod.lib()   # fails loudly if the HIP library is missing
+    return mod
+
+
+SHAPE = (12, 20, 70)        # (nz, ny, nx): ragged against every tile, odd/even halves
+HH = 1.0 / 40.0             # one h on all axes (order 6 and FFT6 need it)
+K0 = 25.0
+
+
+def _k2(shape, halo=2):
+    nz, ny, nx = (s + 2 * halo for s in shape)
+    z, y, x = np.meshgrid(np.linspace(0, 1, nz), np.linspace(0, 1, ny), np.linspace(0, 1, nx), indexing="ij")
+    return K0 * K0 * (1.0 + 0.2 * np.exp(-((x - 0.4) ** 2 + (y - 0.6) ** 2 + (z - 0.5) ** 2) / 0.05))
+
+
+@pytest.fixture(scope="module")
+def live():
+    h = H()
+    ctx = h.helm_setup(torch.from_numpy(_k2(SHAPE)).cuda(), HH, 6, k0=K0, shape=SHAPE)
+    rng = np.random.default_rng(11)
+    n = ctx.n
+    F = torch.from_numpy(rng.standard_normal(n) + 1j * rng.standard_normal(n)).cuda()
+    yield h, ctx, F
+    h.helm_destroy(ctx)
+
+
+def _opts(h, **kw):
+    o = h.helm_solve_opts()
+    o.m, o.maxit, o.rtol, o.flexible, o.prec_fp32, o.prec, o.x0_given = 30, 200, 1e-8, 1, 1, h.PREC_EIGT, 0
+    o.resid_hist, o.hist_len = None, 0
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def test_invalid_solve_options_return_einval_and_leave_x(live):
+    h, ctx, F = live
+    L = h.lib()
+    x = torch.full_like(F, 3.0 + 4.0j)
+    sentinel = x.clone()
+    info = h.helm_solve_info()
+    ptr = lambda t: ctypes.c_void_p(t.data_ptr())
+    bad = [dict(m=0), dict(m=257), dict(maxit=0), dict(rtol=0.0), dict(rtol=-1e-8), dict(rtol=float("nan")),
+           dict(rtol=float("inf")), dict(prec=9), dict(prec=-1), dict(flexible=0, prec_fp32=1)]
+    for kw in bad:
+        st = L.helm_gmres_solve(ctx.ptr, ptr(F), ptr(x), ctypes.byref(_opts(h, **kw)), ctypes.byref(info))
+        assert st == h.HELM_EINVAL, kw
+        assert ctx.error(), kw
+    assert L.helm_gmres_solve(ctx.ptr, None, ptr(x), ctypes.byref(_opts(h)), ctypes.byref(info)) == h.HELM_EINVAL
+    assert L.helm_gmres_solve(ctx.ptr, ptr(F), None, ctypes.byref(_opts(h)), ctypes.byref(info)) == h.HELM_EINVAL
+    assert L.helm_gmres_solve(ctx.ptr, ptr(F), ptr(x), None, ctypes.byref(info)) == h.HELM_EINVAL
+    assert L.helm_gmres_solve(None, ptr(F), ptr(x), ctypes.byref(_opts(h)), ctypes.byref(info)) == h.HELM_EINVAL
+    torch.cuda.synchronize()
+    assert torch.equal(x, sentinel)
+    # the context still solves
+    _, inf = h.helm_gmres_solve(ctx, F, x, m=30, rtol=1e-8, flexible=True, prec_fp32=True, x0_given=False)
+    assert inf["converged"] and inf["relres_true"] <= 1.5e-8
+
+
+def test_invalid_calls_return_einval(live):
+    h, ctx, F = live
+    L = h.lib()
+    ptr = lambda t: ctypes.c_void_p(t.data_ptr())
+    y = torch.full_like(F, 1.0 - 2.0j)
+    sentinel = y.clone()
+    assert L.helm_matvec(ctx.ptr, None, ptr(y)) == h.HELM_EINVAL
+    assert L.helm_matvec(ctx.ptr, ptr(F), None) == h.HELM_EINVAL
+    assert L.helm_matvec(ctx.ptr, ptr(y), ptr(y)) == h.HELM_EINVAL      # input and output must not overlap
+    assert "overlap" in ctx.error()
+    assert L.helm_matvec(None, ptr(F), ptr(y)) == h.HELM_EINVAL
+    assert L.helm_precond_apply(ctx.ptr, None, ptr(y), h.PREC_EIGT, 0) == h.HELM_EINVAL
+    assert L.helm_precond_apply(ctx.ptr, ptr(F), None, h.PREC_EIGT, 1) == h.HELM_EINVAL
+    for kind in (9, -1):
+        assert L.helm_precond_apply(ctx.ptr, ptr(F), ptr(y), kind, 0) == h.HELM_EINVAL
+        assert "unknown preconditioner" in ctx.error()
+    assert L.helm_rhs(ctx.ptr, None, ptr(y)) == h.HELM_EINVAL
+    a_re, a_im = ctypes.c_double(), ctypes.c_double()
+    assert L.helm_scale_guess(ctx.ptr, None, ptr(y), ctypes.byref(a_re), ctypes.byref(a_im)) == h.HELM_EINVAL
+    ms, nl, wk = ctypes.c_double(), ctypes.c_longlong(), ctypes.c_double()
+    for cls in (-1, h.KERNEL_CLASSES):
+        assert L.helm_profile_read(ctx.ptr, cls, ctypes.byref(ms), ctypes.byref(nl), ctypes.byref(wk)) == h.HELM_EINVAL
+    for kind, cfg in ((4, 0), (-1, 0), (0, len(h.GEMM_CONFIGS)), (0, -1)):
+        assert L.helm_gemm_config(ctx.ptr, kind, cfg) == h.HELM_EINVAL
+    torch.cuda.synchronize()
+    assert torch.equal(y, sentinel)
+
+
+def test_fft6_needs_equal_spacing():
+    h = H()
+    shape = (10, 12, 14)
+    ctx = h.helm_setup(torch.from_numpy(_k2(shape, halo=0)).cuda(), (0.05, 0.06, 0.05), 4, k0=K0, shape=shape)
+    y = torch.ones(ctx.n, dtype=torch.complex128, device="cuda")
+    with pytest.raises(h.HelmError) as e:
+        h.helm_precond_apply(ctx, y, kind="fft6")
+    assert e.value.status == h.HELM_EINVAL
+    z = h.helm_precond_apply(ctx, y, kind="fft4")                    # FFT4 takes unequal spacing
+    assert torch.isfinite(torch.view_as_real(z)).all()
+    h.helm_destroy(ctx)
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+@pytest.mark.parametrize("kind", ["eigt", "pfft", "fft2", "fft4", "fft6"])
+def test_in_place_preconditioner_equals_out_of_place(live, kind, fp32):
+    h, ctx, F = live
+    z = h.helm_precond_apply(ctx, F, kind=kind, fp32=fp32)
+    y = F.clone()
+    h.helm_precond_apply(ctx, y, y, kind=kind, fp32=fp32)
+    torch.cuda.synchronize()
+    assert torch.isfinite(torch.view_as_real(z)).all()
+    assert torch.equal(y, z), (kind, fp32)
