@@ -127,3 +127,43 @@ def test_in_place_preconditioner_equals_out_of_place(live, kind, fp32):
     torch.cuda.synchronize()
     assert torch.isfinite(torch.view_as_real(z)).all()
     assert torch.equal(y, z), (kind, fp32)
+
+
+def test_nonfinite_rhs_returns_enumeric_and_context_recovers(live):
+    h, ctx, F = live
+    bad = F.clone()
+    bad[ctx.n // 3] = complex(float("nan"), 0.0)
+    x = torch.zeros_like(F)
+    with pytest.raises(h.HelmError) as e:
+        h.helm_gmres_solve(ctx, bad, x, m=30, rtol=1e-8, flexible=True, prec_fp32=True, x0_given=False)
+    assert e.value.status == h.HELM_ENUMERIC
+    assert "non-finite" in ctx.error()
+    _, inf = h.helm_gmres_solve(ctx, F, x, m=30, rtol=1e-8, flexible=True, prec_fp32=True, x0_given=False)
+    assert inf["converged"]
+
+
+def test_maxit_returns_enoconv_with_the_last_iterate(live):
+    """At maxit the call returns HELM_ENOCONV; x is the last iterate and relres_true is its true residual."""
+    h, ctx, F = live
+    x = torch.empty_like(F)
+    _, inf = h.helm_gmres_solve(ctx, F, x, m=2, maxit=3, rtol=1e-14, flexible=True, prec_fp32=True, x0_given=False,
+                                raise_on_noconv=False)
+    assert inf["status"] == "HELM_ENOCONV" and not inf["converged"]
+    assert inf["iters"] == 3
+    r = F - h.helm_matvec(ctx, x)
+    rel = (torch.linalg.vector_norm(r) / torch.linalg.vector_norm(F)).item()
+    assert rel < 1.0                                      # GMRES never increases the residual norm
+    assert rel == pytest.approx(inf["relres_true"], rel=1e-9)
+    with pytest.raises(h.HelmError) as e:
+        h.helm_gmres_solve(ctx, F, x, m=2, maxit=3, rtol=1e-14, flexible=True, prec_fp32=True, x0_given=False)
+    assert e.value.status == h.HELM_ENOCONV
+
+
+@pytest.mark.parametrize("x0_given", [False, True])
+def test_zero_rhs_gives_the_zero_solution(live, x0_given):
+    h, ctx, F = live
+    x = torch.full_like(F, 5.0 - 1.0j)
+    _, inf = h.helm_gmres_solve(ctx, torch.zeros_like(F), x, m=30, rtol=1e-8, flexible=True, prec_fp32=True,
+                                x0_given=x0_given)
+    assert inf["converged"] and inf["iters"] == 0
+    assert torch.count_nonzero(x).item() == 0
