@@ -175,30 +175,38 @@ __global__ void k_ring_fwd_R(const typename c2<T>::t *__restrict__ ra, const typ
 
 // Forward, every element of every slice: out = s base + W_y[j][0] S_0[i] + W_y[j][ny-1] S_N[i]
 // + T_0[j] W_x[i][0] + T_N[j] W_x[i][nx-1] (the boundary columns of W read as rows of the transposes);
-// fvec = [S: Nz x 2 x Nx | T: Nz x 2 x Ny] with S = Rr W_x^T and T = Rc W_y^T
+// fvec = [S: Nz x 2 x Nx | T: Nz x 2 x Ny] with S = Rr W_x^T and T = Rc W_y^T. A block takes FWD_RJ rows of one
+// slice; each thread keeps the four column factors of its columns i in registers and streams the rows, whose
+// four factors are the same for the whole block.
+constexpr int FWD_RJ = 16;
 template <typename T>
 __global__ __launch_bounds__(256) void k_ring_fwd_write(const typename c2<T>::t *__restrict__ fvec,
                                                         const typename c2<T>::t *base, T base_scale,
                                                         typename c2<T>::t *out,
                                                         const typename c2<T>::t *__restrict__ WyT,
                                                         const typename c2<T>::t *__restrict__ WxT, int nx, int ny,
-                                                        long long n) {
+                                                        int nz) {
     typedef typename c2<T>::t CT;
-    const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
-    if (e >= n) return;
+    const int rblocks = (ny + FWD_RJ - 1) / FWD_RJ;
+    const int l = blockIdx.x / rblocks;
+    const int j0 = (blockIdx.x % rblocks) * FWD_RJ, j1 = min(ny, j0 + FWD_RJ);
     const long long plane = (long long)nx * ny;
-    const int l = (int)(e / plane);
-    const long long p = e - (long long)l * plane;
-    const int j = (int)(p / nx), i = (int)(p % nx);
-    const CT *S = fvec + (long long)l * 2 * nx;                                  // S_0, S_N of slice l
-    const CT *Tc = fvec + 2LL * (long long)(n / plane) * nx + (long long)l * 2 * ny;   // T_0, T_N of slice l
-    CT acc = cz<CT>();
-    if (base) { acc = base[e]; acc.x *= base_scale; acc.y *= base_scale; }
-    acc = cfma(WyT[j], S[i], acc);
-    acc = cfma(WyT[(long long)(ny - 1) * ny + j], S[nx + i], acc);
-    acc = cfma(Tc[j], WxT[i], acc);
-    acc = cfma(Tc[ny + j], WxT[(long long)(nx - 1) * nx + i], acc);
-    out[e] = acc;
+    const CT *S = fvec + (long long)l * 2 * nx;                                 // S_0, S_N of slice l
+    const CT *Tc = fvec + 2LL * nz * nx + (long long)l * 2 * ny;                // T_0, T_N of slice l
+    const CT *WyN = WyT + (long long)(ny - 1) * ny, *WxN = WxT + (long long)(nx - 1) * nx;
+    for (int i = threadIdx.x; i < nx; i += 256) {
+        const CT s0 = S[i], sN = S[nx + i], x0 = WxT[i], xN = WxN[i];
+        for (int j = j0; j < j1; ++j) {
+            const long long e = (long long)l * plane + (long long)j * nx + i;
+            CT acc = cz<CT>();
+            if (base) { acc = base[e]; acc.x *= base_scale; acc.y *= base_scale; }
+            acc = cfma(WyT[j], s0, acc);
+            acc = cfma(WyN[j], sN, acc);
+            acc = cfma(Tc[j], x0, acc);
+            acc = cfma(Tc[ny + j], xN, acc);
+            out[e] = acc;
+        }
+    }
 }
 
 inline hipError_t gemm_c(const GemmDesc &d, const double2 *A, const double2 *B, double2 *C, hipStream_t s) {
@@ -253,9 +261,9 @@ hipError_t fwd_launch(const typename c2<T>::t *ra, const typename c2<T>::t *rb, 
     if (e != hipSuccess) return e;
     if ((e = gemm_c(plain_desc(2 * nz, nx, nx), Rr, WxT, fvec, s)) != hipSuccess) return e;        // S = Rr W_x^T
     if ((e = gemm_c(plain_desc(2 * nz, ny, ny), Rc, WyT, fvec + nr, s)) != hipSuccess) return e;   // T = Rc W_y^T
-    const long long n = (long long)nx * ny * nz;
-    hipLaunchKernelGGL(k_ring_fwd_write<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, fvec, base,
-                       (T)base_scale, out, WyT, WxT, nx, ny, n);
+    const long long blocks = (long long)nz * ((ny + FWD_RJ - 1) / FWD_RJ);
+    hipLaunchKernelGGL(k_ring_fwd_write<T>, dim3((unsigned)blocks), dim3(256), 0, s, fvec, base, (T)base_scale, out,
+                       WyT, WxT, nx, ny, nz);
     return hipGetLastError();
 }
 
