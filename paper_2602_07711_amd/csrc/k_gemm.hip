@@ -64,6 +64,36 @@ hipError_t launch(const GemmDesc &d, const TA *A, const TB *B, TC *C, hipStream_
     }
 }
 
+// Two independent products in one launch (PFFT's row and column face products, each only a few dozen tiles):
+// the tiles of the first product, then those of the second, mapped to XCDs together.
+template <typename CT, typename T, int BM, int BN, int BK>
+__global__ __launch_bounds__(256) void k_zgemm_pair(const CT *__restrict__ A0, const CT *__restrict__ B0,
+                                                    CT *__restrict__ C0, GemmDesc d0, const CT *__restrict__ A1,
+                                                    const CT *__restrict__ B1, CT *__restrict__ C1, GemmDesc d1) {
+    const long long t0 = (long long)((d0.M + BM - 1) / BM) * ((d0.N + BN - 1) / BN) * d0.batch;
+    const long long t1 = (long long)((d1.M + BM - 1) / BM) * ((d1.N + BN - 1) / BN) * d1.batch;
+    const long long total = t0 + t1;
+    const long long per = (total + 7) / 8;
+    const long long tile = (long long)(blockIdx.x % 8) * per + blockIdx.x / 8;   // consecutive tiles on one XCD
+    if (tile >= total) return;
+    const bool second = tile >= t0;
+    gemm_tile<CT, CT, CT, T, BM, BN, BK, 0>(second ? A1 : A0, second ? B1 : B0, second ? C1 : C0, second ? d1 : d0,
+                                           second ? tile - t0 : tile);
+}
+
+template <typename CT, typename T>
+hipError_t launch_pair(const GemmDesc &d0, const CT *A0, const CT *B0, CT *C0, const GemmDesc &d1, const CT *A1,
+                       const CT *B1, CT *C1, hipStream_t s) {
+    constexpr int BM = 64, BN = 64, BK = 16;
+    const long long tiles = (long long)((d0.M + BM - 1) / BM) * ((d0.N + BN - 1) / BN) * d0.batch +
+                            (long long)((d1.M + BM - 1) / BM) * ((d1.N + BN - 1) / BN) * d1.batch;
+    if (tiles == 0) return hipSuccess;
+    const long long grid = 8 * ((tiles + 7) / 8);
+    hipLaunchKernelGGL((k_zgemm_pair<CT, T, BM, BN, BK>), dim3((unsigned)grid), dim3(256), 0, s, A0, B0, C0, d0, A1, B1,
+                       C1, d1);
+    return hipGetLastError();
+}
+
 // RW = 0: complex blocks; RW = 1 / 2: real blocks (the sine basis) as the A (y) / B (x) operand
 template <int MODE, typename TD, typename TM, typename TC, typename T, int BM, int BN, int BK, int RW>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(fold_waves<T, TD, MODE, BM, BN, BK>()))) void k_fold(
@@ -119,6 +149,14 @@ hipError_t launch_gemm_z32_in64(const GemmDesc &d, const double2 *A, const float
 hipError_t launch_gemm_z32_out64(const GemmDesc &d, const float2 *A, const float2 *B, double2 *C, hipStream_t s,
                                  int rw, int cfg) {
     return launch<float2, float2, double2, float>(d, A, B, C, s, rw, cfg);
+}
+hipError_t launch_gemm_pair_z64(const GemmDesc &d0, const double2 *A0, const double2 *B0, double2 *C0,
+                                const GemmDesc &d1, const double2 *A1, const double2 *B1, double2 *C1, hipStream_t s) {
+    return launch_pair<double2, double>(d0, A0, B0, C0, d1, A1, B1, C1, s);
+}
+hipError_t launch_gemm_pair_z32(const GemmDesc &d0, const float2 *A0, const float2 *B0, float2 *C0,
+                                const GemmDesc &d1, const float2 *A1, const float2 *B1, float2 *C1, hipStream_t s) {
+    return launch_pair<float2, float>(d0, A0, B0, C0, d1, A1, B1, C1, s);
 }
 
 }  // namespace helm

@@ -6,16 +6,17 @@
 // consumers take them from the rows. The products with the transposed eigenvector or sine matrices are single
 // complex GEMMs over all slices (M = 2 Nz).
 //
-// Inverse (k_ring_inv_rows, k_ring_inv_sum, two GEMMs): the inverse transform X = V_y Xh V_x^T evaluated on the faces
-//   only (eq. PFFT_INV): the two boundary rows via r_j = V_y[j,:] Xh then X[j,i] = sum_k V_x[i,k] r_j[k], the two
-//   boundary columns via s_i = Xh V_x[i,:]^T then X[j,i] = sum_m V_y[j,m] s_i[m]. The pass over the data runs
-//   with several row groups per slice; the products with V_x^T and V_y^T are GEMMs over all slices.
-// Forward (k_ring_fwd_R, two GEMMs, k_ring_fwd_write): the forward transform of ring-supported data R (Steps 1, 2*):
-//   R = E (a + b) with E = A_p^F - A_p restricted to the faces: on face row 1 of an axis -a (gamma v_1 + (zeta - 1)
-//   v_2), and the mirror on row N (eq. lambda_mat_definition); with zeta = 1 only the face layer enters. out = s *
-//   base + W_y R W_x^T computed as two rank-2 updates from the boundary rows (S_m = R[m,:] W_x^T) and the interior
-//   parts of the boundary columns (T_k = W_y[:, inner] R[inner, k]); the factors as GEMMs over all slices, then
-//   every element in parallel.
+// Inverse (k_ring_inv_rows, k_ring_inv_sum, two GEMMs in one launch): the inverse transform X = V_y Xh V_x^T
+//   evaluated on the faces only (eq. PFFT_INV): the two boundary rows via r_j = V_y[j,:] Xh then
+//   X[j,i] = sum_k V_x[i,k] r_j[k], the two boundary columns via s_i = Xh V_x[i,:]^T then
+//   X[j,i] = sum_m V_y[j,m] s_i[m]. The pass over the data runs with several row groups per slice; the products
+//   with V_x^T and V_y^T are GEMMs over all slices.
+// Forward (k_ring_fwd_R, two GEMMs in one launch, k_ring_fwd_write): the forward transform of ring-supported
+//   data R (Steps 1, 2*): R = E (a + b) with E = A_p^F - A_p restricted to the faces: on face row 1 of an axis
+//   -a (gamma v_1 + (zeta - 1) v_2), and the mirror on row N (eq. lambda_mat_definition); with zeta = 1 only the
+//   face layer enters. out = s * base + W_y R W_x^T computed as two rank-2 updates from the boundary rows
+//   (S_m = R[m,:] W_x^T) and the interior parts of the boundary columns (T_k = W_y[:, inner] R[inner, k]); the
+//   factors as GEMMs over all slices, then every element in parallel.
 // Second layer (zeta != 1): the inverse is run a second time for rows 2, N_y - 1 and columns 2, N_x - 1 into a
 // second ring of the same layout; R takes the inner neighbours from it (the x-neighbours of the corners from the
 // full boundary rows of the first).
@@ -209,11 +210,14 @@ __global__ __launch_bounds__(256) void k_ring_fwd_write(const typename c2<T>::t 
     }
 }
 
-inline hipError_t gemm_c(const GemmDesc &d, const double2 *A, const double2 *B, double2 *C, hipStream_t s) {
-    return launch_gemm_z64(d, A, B, C, s);
+// the row and the column product of a face transform, in one launch
+inline hipError_t gemm_pair(const GemmDesc &d0, const double2 *A0, const double2 *B0, double2 *C0, const GemmDesc &d1,
+                            const double2 *A1, const double2 *B1, double2 *C1, hipStream_t s) {
+    return launch_gemm_pair_z64(d0, A0, B0, C0, d1, A1, B1, C1, s);
 }
-inline hipError_t gemm_c(const GemmDesc &d, const float2 *A, const float2 *B, float2 *C, hipStream_t s) {
-    return launch_gemm_z32(d, A, B, C, s);
+inline hipError_t gemm_pair(const GemmDesc &d0, const float2 *A0, const float2 *B0, float2 *C0, const GemmDesc &d1,
+                            const float2 *A1, const float2 *B1, float2 *C1, hipStream_t s) {
+    return launch_gemm_pair_z32(d0, A0, B0, C0, d1, A1, B1, C1, s);
 }
 // C (M x N) = A (M x K) B (K x N), all row-major and contiguous
 inline GemmDesc plain_desc(int M, int N, int K) { return GemmDesc{M, N, K, K, N, N, 0, 0, 0, 1}; }
@@ -239,10 +243,9 @@ hipError_t inv_launch(const typename c2<T>::t *Xh, typename c2<T>::t *ring, cons
     const long long nr = 2LL * nz * nx;
     hipLaunchKernelGGL(k_ring_inv_sum<T>, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, s, rpart, nx, nr, rsum);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    // boundary rows X[j][i] = sum_k V_x[i][k] r_j[k]: rows (2 Nz x Nx) = rsum V_x^T
-    if ((e = gemm_c(plain_desc(2 * nz, nx, nx), rsum, VxT, ring, s)) != hipSuccess) return e;
-    // boundary columns X[j][i] = sum_m V_y[j][m] s_i[m]: columns (2 Nz x Ny) = sv V_y^T
-    return gemm_c(plain_desc(2 * nz, ny, ny), sv, VyT, ring + nr, s);
+    // boundary rows X[j][i] = sum_k V_x[i][k] r_j[k]: rows (2 Nz x Nx) = rsum V_x^T; boundary columns
+    // X[j][i] = sum_m V_y[j][m] s_i[m]: columns (2 Nz x Ny) = sv V_y^T
+    return gemm_pair(plain_desc(2 * nz, nx, nx), rsum, VxT, ring, plain_desc(2 * nz, ny, ny), sv, VyT, ring + nr, s);
 }
 
 // work: Rr (Nz * 2 Nx) and Rc (Nz * 2 Ny) contiguous in rbuf, fvec (Nz * (2 Nx + 2 Ny))
@@ -259,8 +262,10 @@ hipError_t fwd_launch(const typename c2<T>::t *ra, const typename c2<T>::t *rb, 
                        ey, ex1, ey1, nx, ny, nz, Rr, Rc);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if ((e = gemm_c(plain_desc(2 * nz, nx, nx), Rr, WxT, fvec, s)) != hipSuccess) return e;        // S = Rr W_x^T
-    if ((e = gemm_c(plain_desc(2 * nz, ny, ny), Rc, WyT, fvec + nr, s)) != hipSuccess) return e;   // T = Rc W_y^T
+    // S = Rr W_x^T and T = Rc W_y^T
+    if ((e = gemm_pair(plain_desc(2 * nz, nx, nx), Rr, WxT, fvec, plain_desc(2 * nz, ny, ny), Rc, WyT, fvec + nr, s)) !=
+        hipSuccess)
+        return e;
     const long long blocks = (long long)nz * ((ny + FWD_RJ - 1) / FWD_RJ);
     hipLaunchKernelGGL(k_ring_fwd_write<T>, dim3((unsigned)blocks), dim3(256), 0, s, fvec, base, (T)base_scale, out,
                        WyT, WxT, nx, ny, nz);
