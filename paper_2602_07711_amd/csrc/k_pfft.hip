@@ -80,20 +80,39 @@ __global__ __launch_bounds__(256) void k_ring_inv_rows(const typename c2<T>::t *
         a0[c] = cz<CT>();
         aN[c] = cz<CT>();
     }
-    for (int m = m0 + wave; m < m1; m += 4) {
+    // the wave's rows m = m0 + wave, + 4, ...; the next row is loaded while the current one is reduced (its
+    // cross-lane sums would otherwise leave every row's loads exposed), where the registers allow it: slices up to
+    // 512 wide in FP32, 256 in FP64
+    constexpr bool PF = MAXC <= (sizeof(T) == 4 ? 8 : 4);
+    CT xr[MAXC], xn[PF ? MAXC : 1];
+    auto load_row = [&](CT *dst, int m) {
         const CT *row = X + (long long)m * nx;
+#pragma unroll
+        for (int c = 0; c < MAXC; ++c) {
+            const int k = lane + 64 * c;
+            dst[c] = (m < m1 && k < nx) ? row[k] : cz<CT>();
+        }
+    };
+    if (PF) load_row(xr, m0 + wave);
+    for (int m = m0 + wave; m < m1; m += 4) {
+        if (PF) {
+            load_row(xn, m + 4);
+        } else {
+            load_row(xr, m);
+        }
         const CT w0 = Vy[(long long)layer * ny + m], wN = Vy[(long long)(ny - 1 - layer) * ny + m];
         CT s0 = cz<CT>(), sN = cz<CT>();
 #pragma unroll
         for (int c = 0; c < MAXC; ++c) {
-            const int k = lane + 64 * c;
-            if (k < nx) {
-                const CT x = row[k];
-                a0[c] = cfma(w0, x, a0[c]);
-                aN[c] = cfma(wN, x, aN[c]);
-                s0 = cfma(vx0[c], x, s0);
-                sN = cfma(vxN[c], x, sN);
-            }
+            const CT x = xr[c];                       // zero beyond the slice width
+            a0[c] = cfma(w0, x, a0[c]);
+            aN[c] = cfma(wN, x, aN[c]);
+            s0 = cfma(vx0[c], x, s0);
+            sN = cfma(vxN[c], x, sN);
+        }
+        if (PF) {
+#pragma unroll
+            for (int c = 0; c < MAXC; ++c) xr[c] = xn[c];
         }
         s0.x = wsum(s0.x); s0.y = wsum(s0.y);
         sN.x = wsum(sN.x); sN.y = wsum(sN.y);
