@@ -20,6 +20,8 @@
 // Second layer (zeta != 1): the inverse is run a second time for rows 2, N_y - 1 and columns 2, N_x - 1 into a
 // second ring of the same layout; R takes the inner neighbours from it (the x-neighbours of the corners from the
 // full boundary rows of the first).
+#include <algorithm>
+
 #include "helm_internal.h"
 
 namespace helm {
@@ -50,7 +52,7 @@ template <typename T> __device__ __forceinline__ T wsum(T v) {
     return v;
 }
 
-constexpr int RING_RG = 8; // row groups per slice in the inverse's pass over the data
+constexpr int RING_RG = 8; // most row groups per slice in the inverse's pass over the data
 constexpr int RING_NMAX = 64 * 13;   // widest slice the ring pass supports (MAXC = 13 chunks of 64 columns)
 
 // Inverse, pass over the data for face layer `layer` (0: rows/columns 1 and N, 1: 2 and N-1): block (slice l,
@@ -62,13 +64,13 @@ template <typename T, int MAXC>
 __global__ __launch_bounds__(256) void k_ring_inv_rows(const typename c2<T>::t *__restrict__ Xh,
                                                        const typename c2<T>::t *__restrict__ Vy,
                                                        const typename c2<T>::t *__restrict__ Vx, int nx, int ny,
-                                                       int layer, typename c2<T>::t *__restrict__ rpart,
+                                                       int layer, int rgs, typename c2<T>::t *__restrict__ rpart,
                                                        typename c2<T>::t *__restrict__ sv) {
     typedef typename c2<T>::t CT;
     __shared__ CT red[4][2][64 * MAXC];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int l = blockIdx.x / RING_RG, rg = blockIdx.x % RING_RG;
-    const int per = (ny + RING_RG - 1) / RING_RG;
+    const int l = blockIdx.x / rgs, rg = blockIdx.x % rgs;
+    const int per = (ny + rgs - 1) / rgs;
     const int m0 = rg * per, m1 = min(ny, m0 + per);
     const CT *X = Xh + (long long)l * nx * ny;
     CT vx0[MAXC], vxN[MAXC], a0[MAXC], aN[MAXC];
@@ -127,7 +129,7 @@ __global__ __launch_bounds__(256) void k_ring_inv_rows(const typename c2<T>::t *
         red[wave][1][lane + 64 * c] = aN[c];
     }
     __syncthreads();
-    CT *rp = rpart + ((long long)l * RING_RG + rg) * 2 * nx;
+    CT *rp = rpart + ((long long)l * rgs + rg) * 2 * nx;
     for (int k = tid; k < nx; k += 256) {
         CT r0 = red[0][0][k], rN = red[0][1][k];
         for (int w = 1; w < 4; ++w) { r0 = cadd(r0, red[w][0][k]); rN = cadd(rN, red[w][1][k]); }
@@ -138,15 +140,15 @@ __global__ __launch_bounds__(256) void k_ring_inv_rows(const typename c2<T>::t *
 
 // Inverse: r0, rN of every slice summed over the row groups in order, rsum[l][w][k]
 template <typename T>
-__global__ void k_ring_inv_sum(const typename c2<T>::t *__restrict__ rpart, int nx, long long total,
+__global__ void k_ring_inv_sum(const typename c2<T>::t *__restrict__ rpart, int nx, int rgs, long long total,
                                typename c2<T>::t *__restrict__ rsum) {
     typedef typename c2<T>::t CT;
     const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
     if (e >= total) return;
     const long long l = e / (2 * nx), q = e % (2 * nx);
-    const CT *rp = rpart + l * RING_RG * 2 * nx + q;
+    const CT *rp = rpart + l * rgs * 2 * nx + q;
     CT acc = rp[0];
-    for (int g = 1; g < RING_RG; ++g) acc = cadd(acc, rp[(long long)g * 2 * nx]);
+    for (int g = 1; g < rgs; ++g) acc = cadd(acc, rp[(long long)g * 2 * nx]);
     rsum[e] = acc;
 }
 
@@ -241,6 +243,30 @@ inline hipError_t gemm_pair(const GemmDesc &d0, const float2 *A0, const float2 *
 // C (M x N) = A (M x K) B (K x N), all row-major and contiguous
 inline GemmDesc plain_desc(int M, int N, int K) { return GemmDesc{M, N, K, K, N, N, 0, 0, 0, 1}; }
 
+// Row groups per slice for the inverse's pass: as many as keep the whole grid resident at once (one round of
+// blocks, from the kernel's occupancy on this device), at most RING_RG.
+template <typename T, int MAXC> int ring_groups(int nz) {
+    static const int cap = [] {
+        int dev = 0, cus = 0, nb = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ring_inv_rows<T, MAXC>, 256, 0) != hipSuccess)
+            return 0;
+        return nb * cus;
+    }();
+    if (cap <= 0) return RING_RG;
+    return std::max(1, std::min(RING_RG, cap / std::max(1, nz)));
+}
+
+template <typename T, int MAXC>
+hipError_t inv_rows_launch(const typename c2<T>::t *Xh, const typename c2<T>::t *Vy, const typename c2<T>::t *Vx,
+                           int nx, int ny, int nz, int layer, int rgs, typename c2<T>::t *rpart,
+                           typename c2<T>::t *sv, hipStream_t s) {
+    hipLaunchKernelGGL((k_ring_inv_rows<T, MAXC>), dim3(nz * rgs), dim3(256), 0, s, Xh, Vy, Vx, nx, ny, layer, rgs,
+                       rpart, sv);
+    return hipGetLastError();
+}
+
 // work: rpart (Nz * RING_RG * 2 Nx), sv (Nz * 2 Ny), rsum (Nz * 2 Nx)
 template <typename T>
 hipError_t inv_launch(const typename c2<T>::t *Xh, typename c2<T>::t *ring, const typename c2<T>::t *Vy,
@@ -248,19 +274,21 @@ hipError_t inv_launch(const typename c2<T>::t *Xh, typename c2<T>::t *ring, cons
                       int ny, int nz, int layer, typename c2<T>::t *rpart, typename c2<T>::t *sv,
                       typename c2<T>::t *rsum, hipStream_t s) {
     if (nx > RING_NMAX || ny > RING_NMAX || layer < 0 || layer > 1 || nx < 2 || ny < 2) return hipErrorInvalidValue;
-    if (nx <= 256)
-        hipLaunchKernelGGL((k_ring_inv_rows<T, 4>), dim3(nz * RING_RG), dim3(256), 0, s, Xh, Vy, Vx, nx, ny, layer, rpart,
-                           sv);
-    else if (nx <= 512)
-        hipLaunchKernelGGL((k_ring_inv_rows<T, 8>), dim3(nz * RING_RG), dim3(256), 0, s, Xh, Vy, Vx, nx, ny, layer, rpart,
-                           sv);
-    else
-        hipLaunchKernelGGL((k_ring_inv_rows<T, 13>), dim3(nz * RING_RG), dim3(256), 0, s, Xh, Vy, Vx, nx, ny, layer,
-                           rpart, sv);
-    hipError_t e = hipGetLastError();
+    int rgs;
+    hipError_t e;
+    if (nx <= 256) {
+        rgs = ring_groups<T, 4>(nz);
+        e = inv_rows_launch<T, 4>(Xh, Vy, Vx, nx, ny, nz, layer, rgs, rpart, sv, s);
+    } else if (nx <= 512) {
+        rgs = ring_groups<T, 8>(nz);
+        e = inv_rows_launch<T, 8>(Xh, Vy, Vx, nx, ny, nz, layer, rgs, rpart, sv, s);
+    } else {
+        rgs = ring_groups<T, 13>(nz);
+        e = inv_rows_launch<T, 13>(Xh, Vy, Vx, nx, ny, nz, layer, rgs, rpart, sv, s);
+    }
     if (e != hipSuccess) return e;
     const long long nr = 2LL * nz * nx;
-    hipLaunchKernelGGL(k_ring_inv_sum<T>, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, s, rpart, nx, nr, rsum);
+    hipLaunchKernelGGL(k_ring_inv_sum<T>, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, s, rpart, nx, rgs, nr, rsum);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // boundary rows X[j][i] = sum_k V_x[i][k] r_j[k]: rows (2 Nz x Nx) = rsum V_x^T; boundary columns
     // X[j][i] = sum_m V_y[j][m] s_i[m]: columns (2 Nz x Ny) = sv V_y^T
