@@ -327,7 +327,7 @@ hipError_t launch_gemm_z32_in64(const GemmDesc &d, const double2 *A, const float
                                 int rw = 0, int cfg = 0);
 hipError_t launch_gemm_z32_out64(const GemmDesc &d, const float2 *A, const float2 *B, double2 *C, hipStream_t s,
                                  int rw = 0, int cfg = 0);
-// C0 = A0 B0 and C1 = A1 B1 (complex operands, tile configuration 0) in one launch
+// C0 = A0 B0 and C1 = A1 B1 (complex operands, 32 x 32 x 32 tiles) in one launch
 hipError_t launch_gemm_pair_z64(const GemmDesc &d0, const double2 *A0, const double2 *B0, double2 *C0,
                                 const GemmDesc &d1, const double2 *A1, const double2 *B1, double2 *C1, hipStream_t s);
 hipError_t launch_gemm_pair_z32(const GemmDesc &d0, const float2 *A0, const float2 *B0, float2 *C0,

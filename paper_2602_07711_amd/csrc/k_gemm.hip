@@ -64,8 +64,10 @@ hipError_t launch(const GemmDesc &d, const TA *A, const TB *B, TC *C, hipStream_
     }
 }
 
-// Two independent products in one launch (PFFT's row and column face products, each only a few dozen tiles):
-// the tiles of the first product, then those of the second, mapped to XCDs together.
+// Two independent products in one launch (PFFT's row and column face products, 2 N_z x N by N x N each): the
+// tiles of the first product, then those of the second, mapped to XCDs together. 32 x 32 tiles: with 64 x 64 ones
+// the products made a few dozen tiles, each a whole CU's matrix work for 10 us (FP32) or 27 us (FP64), and left
+// most of the chip idle.
 template <typename CT, typename T, int BM, int BN, int BK>
 __global__ __launch_bounds__(256) void k_zgemm_pair(const CT *__restrict__ A0, const CT *__restrict__ B0,
                                                     CT *__restrict__ C0, GemmDesc d0, const CT *__restrict__ A1,
@@ -84,7 +86,7 @@ __global__ __launch_bounds__(256) void k_zgemm_pair(const CT *__restrict__ A0, c
 template <typename CT, typename T>
 hipError_t launch_pair(const GemmDesc &d0, const CT *A0, const CT *B0, CT *C0, const GemmDesc &d1, const CT *A1,
                        const CT *B1, CT *C1, hipStream_t s) {
-    constexpr int BM = 64, BN = 64, BK = 16;
+    constexpr int BM = 32, BN = 32, BK = 32;
     const long long tiles = (long long)((d0.M + BM - 1) / BM) * ((d0.N + BN - 1) / BN) * d0.batch +
                             (long long)((d1.M + BM - 1) / BM) * ((d1.N + BN - 1) / BN) * d1.batch;
     if (tiles == 0) return hipSuccess;
