@@ -316,17 +316,8 @@ hipError_t launch_matvec(const StencilParams &p, const float2 *x, const double *
 hipError_t launch_rhs(const StencilParams &p, const double2 *f_halo, const double *k2, const double4 *fld,
                       double h3[3], double2 *F, hipStream_t s);
 
-// rw: 0 = both operands complex, 1 = A real (imaginary parts ignored), 2 = B real.
-// cfg: tile configuration 0..GEMM_NCFG-1 = (BM, BN, BK) of (64,64,16), (64,64,32), (128,64,16), (64,128,16).
+// Transform tile configurations 0..GEMM_NCFG-1 = (BM, BN, BK) of (64,64,16), (64,64,32), (128,64,16), (64,128,16).
 constexpr int GEMM_NCFG = 4;
-hipError_t launch_gemm_z64(const GemmDesc &d, const double2 *A, const double2 *B, double2 *C, hipStream_t s,
-                           int rw = 0, int cfg = 0);
-hipError_t launch_gemm_z32(const GemmDesc &d, const float2 *A, const float2 *B, float2 *C, hipStream_t s,
-                           int rw = 0, int cfg = 0);
-hipError_t launch_gemm_z32_in64(const GemmDesc &d, const double2 *A, const float2 *B, float2 *C, hipStream_t s,
-                                int rw = 0, int cfg = 0);
-hipError_t launch_gemm_z32_out64(const GemmDesc &d, const float2 *A, const float2 *B, double2 *C, hipStream_t s,
-                                 int rw = 0, int cfg = 0);
 // C0 = A0 B0 and C1 = A1 B1 (complex operands, 32 x 32 x 32 tiles) in one launch
 hipError_t launch_gemm_pair_z64(const GemmDesc &d0, const double2 *A0, const double2 *B0, double2 *C0,
                                 const GemmDesc &d1, const double2 *A1, const double2 *B1, double2 *C1, hipStream_t s);

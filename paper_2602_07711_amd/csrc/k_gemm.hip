@@ -7,8 +7,8 @@
 // In both the fastest memory index of the data lands on the MFMA column index, so tile loads and the
 // accumulator stores walk contiguous memory. They run as the folded kernels below (k_fold: two half-size
 // products per axis), and so do the sine transforms of PFFT and of the FFT2/4/6 comparison preconditioners (real
-// blocks, modes at stride 2). The plain batched GEMM C[b] = A[b] B[b] (k_zgemm) carries PFFT's thin face-ring
-// products.
+// blocks, modes at stride 2). A paired product kernel (k_zgemm_pair: two independent products C = A B in one
+// launch) carries PFFT's thin face-ring products.
 //
 // Arithmetic, FP32: three real MFMA products per complex k-step (Gauss / 3M form: T1 += Ar Br, T2 += Ai Bi,
 // T3 += (Ar + Ai)(Br + Bi); then Cr = T1 - T2, Ci = T3 - T1 - T2), 25% fewer MFMA issues than the four-product
@@ -26,43 +26,6 @@
 namespace helm {
 
 namespace {
-
-template <typename TA, typename TB, typename TC, typename T, int BM, int BN, int BK, int RW>
-__global__ __launch_bounds__(256) void k_zgemm(const TA *__restrict__ A, const TB *__restrict__ B, TC *__restrict__ C,
-                                               GemmDesc d) {
-    const int tm = (d.M + BM - 1) / BM, tn = (d.N + BN - 1) / BN;
-    const long long total = (long long)tm * tn * d.batch;
-    const long long per = (total + 7) / 8;
-    const long long tile = (long long)(blockIdx.x % 8) * per + blockIdx.x / 8;   // consecutive tiles on one XCD
-    if (tile >= total) return;
-    gemm_tile<TA, TB, TC, T, BM, BN, BK, RW>(A, B, C, d, tile);
-}
-
-template <typename TA, typename TB, typename TC, typename T, int BM, int BN, int BK>
-hipError_t launch_tile(const GemmDesc &d, const TA *A, const TB *B, TC *C, hipStream_t s, int rw) {
-    long long tiles = (long long)((d.M + BM - 1) / BM) * ((d.N + BN - 1) / BN) * d.batch;
-    long long grid = 8 * ((tiles + 7) / 8);
-    if (tiles == 0) return hipSuccess;
-    if (rw == 1)
-        hipLaunchKernelGGL((k_zgemm<TA, TB, TC, T, BM, BN, BK, 1>), dim3((unsigned)grid), dim3(256), 0, s, A, B, C, d);
-    else if (rw == 2)
-        hipLaunchKernelGGL((k_zgemm<TA, TB, TC, T, BM, BN, BK, 2>), dim3((unsigned)grid), dim3(256), 0, s, A, B, C, d);
-    else
-        hipLaunchKernelGGL((k_zgemm<TA, TB, TC, T, BM, BN, BK, 0>), dim3((unsigned)grid), dim3(256), 0, s, A, B, C, d);
-    return hipGetLastError();
-}
-
-// Tile configurations (BM, BN, BK) the autotuner chooses from; the real-operand (sine) products use config 0.
-template <typename TA, typename TB, typename TC, typename T>
-hipError_t launch(const GemmDesc &d, const TA *A, const TB *B, TC *C, hipStream_t s, int rw, int cfg) {
-    if (rw != 0) cfg = 0;
-    switch (cfg) {
-    case 1: return launch_tile<TA, TB, TC, T, 64, 64, 32>(d, A, B, C, s, 0);
-    case 2: return launch_tile<TA, TB, TC, T, 128, 64, 16>(d, A, B, C, s, 0);
-    case 3: return launch_tile<TA, TB, TC, T, 64, 128, 16>(d, A, B, C, s, 0);
-    default: return launch_tile<TA, TB, TC, T, 64, 64, 16>(d, A, B, C, s, rw);
-    }
-}
 
 // Two independent products in one launch (PFFT's row and column face products, 2 N_z x N by N x N each): the
 // tiles of the first product, then those of the second, mapped to XCDs together. 32 x 32 tiles: with 64 x 64 ones
@@ -140,22 +103,6 @@ hipError_t fold_launch_cfg(const FoldDesc &f, const TD *D, const TM *Ms, const T
 
 }  // namespace
 
-hipError_t launch_gemm_z64(const GemmDesc &d, const double2 *A, const double2 *B, double2 *C, hipStream_t s, int rw,
-                           int cfg) {
-    return launch<double2, double2, double2, double>(d, A, B, C, s, rw, cfg);
-}
-hipError_t launch_gemm_z32(const GemmDesc &d, const float2 *A, const float2 *B, float2 *C, hipStream_t s, int rw,
-                           int cfg) {
-    return launch<float2, float2, float2, float>(d, A, B, C, s, rw, cfg);
-}
-hipError_t launch_gemm_z32_in64(const GemmDesc &d, const double2 *A, const float2 *B, float2 *C, hipStream_t s,
-                                int rw, int cfg) {
-    return launch<double2, float2, float2, float>(d, A, B, C, s, rw, cfg);
-}
-hipError_t launch_gemm_z32_out64(const GemmDesc &d, const float2 *A, const float2 *B, double2 *C, hipStream_t s,
-                                 int rw, int cfg) {
-    return launch<float2, float2, double2, float>(d, A, B, C, s, rw, cfg);
-}
 hipError_t launch_gemm_pair_z64(const GemmDesc &d0, const double2 *A0, const double2 *B0, double2 *C0,
                                 const GemmDesc &d1, const double2 *A1, const double2 *B1, double2 *C1, hipStream_t s) {
     return launch_pair<double2, double>(d0, A0, B0, C0, d1, A1, B1, C1, s);
