@@ -243,8 +243,10 @@ inline hipError_t gemm_pair(const GemmDesc &d0, const float2 *A0, const float2 *
 // C (M x N) = A (M x K) B (K x N), all row-major and contiguous
 inline GemmDesc plain_desc(int M, int N, int K) { return GemmDesc{M, N, K, K, N, N, 0, 0, 0, 1}; }
 
-// Row groups per slice for the inverse's pass: as many as keep the whole grid resident at once (one round of
-// blocks, from the kernel's occupancy on this device), at most RING_RG.
+// Row groups per slice for the inverse's pass (1 .. RING_RG): the count whose grid fills its rounds of resident
+// blocks best (blocks / (rounds x resident blocks), from the kernel's occupancy on this device), the smaller one
+// on a tie. At 256^3 that is one or two full rounds; with many slices (800^3) it stays at RING_RG, where a last
+// round of a few long blocks would otherwise idle the chip.
 template <typename T, int MAXC> int ring_groups(int nz) {
     static const int cap = [] {
         int dev = 0, cus = 0, nb = 0;
@@ -255,7 +257,15 @@ template <typename T, int MAXC> int ring_groups(int nz) {
         return nb * cus;
     }();
     if (cap <= 0) return RING_RG;
-    return std::max(1, std::min(RING_RG, cap / std::max(1, nz)));
+    int best = RING_RG;
+    double best_eff = -1.0;
+    for (int r = 1; r <= RING_RG; ++r) {
+        const long long blocks = (long long)std::max(1, nz) * r;
+        const long long rounds = (blocks + cap - 1) / cap;
+        const double eff = (double)blocks / (double)(rounds * cap);
+        if (eff > best_eff + 1e-12) { best_eff = eff; best = r; }
+    }
+    return best;
 }
 
 template <typename T, int MAXC>
