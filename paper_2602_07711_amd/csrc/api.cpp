@@ -743,7 +743,7 @@ helm_status setup_impl(helm_ctx **out, helm_grid g, const double h[3], const voi
     const int blocks = STENCIL_WAVES / STENCIL_TY;   // blocks of STENCIL_TY waves
     int want = (blocks + p.tiles_x * p.tiles_y - 1) / (p.tiles_x * p.tiles_y);
     want = std::max(1, std::min(want, c.nz));
-    p.zchunk = (c.nz + want - 1) / want;
+    p.zchunk = std::max((c.nz + want - 1) / want, std::min(c.nz, STENCIL_MINZ));
     p.zchunks = (c.nz + p.zchunk - 1) / p.zchunk;
 
     // derived fields

@@ -28,9 +28,10 @@ void eig_fold_dense(const EigFold &f, std::vector<cd> &d, std::vector<cd> &V, st
 
 // Stencil coefficients that depend only on the grid (the k^2-dependent parts are per node).
 // Matvec thread block: 64 x STENCIL_TY threads, one output column each; the z-chunk length is chosen so that a
-// launch holds about STENCIL_WAVES waves in total.
+// launch holds about STENCIL_WAVES waves in total, but no shorter than STENCIL_MINZ planes.
 constexpr int STENCIL_TY = 8;
 constexpr int STENCIL_WAVES = 8192;
+constexpr int STENCIL_MINZ = 8;   // shortest z-chunk: each chunk reads two halo planes
 
 struct StencilParams {
     int nx, ny, nz;
