@@ -80,6 +80,48 @@ def test_kron_route_equals_stencil_route(order, cplx):
     assert np.diff(A1.indptr).max() == {2: 7, 4: 19, 6: 27}[order]
 
 
+@pytest.mark.parametrize("bc", ["abc", "dirichlet"])
+@pytest.mark.parametrize("cplx", [False, True], ids=["real_k2", "complex_k2"])
+@pytest.mark.parametrize("order", [2, 4, 6])
+def test_sampled_matvec_equals_kron_rows(order, cplx, bc):
+    """The row-sampled operator used for full-size checks equals A_kron @ x on every node of a ragged box: every
+    face, edge and corner class, a distinct gamma per axis (so a ghost factor taken from the wrong axis shows),
+    non-uniform h for orders 2/4 and complex k^2 (Sec. 2.2 eq. scheme4, Sec. 2.3 eq. scheme6 and eq. D_bc)."""
+    rng = np.random.default_rng(100 * order + 10 * cplx + (bc == "abc"))
+    shape = (14, 13, 9)                                   # (Nz, Ny, Nx)
+    h3 = (0.07, 0.07, 0.07) if order == 6 else (0.07, 0.09, 0.05)
+    k2h = 40 + 25 * rng.random(tuple(s + 4 for s in shape))
+    if cplx:
+        k2h = k2h + 1j * (2 + 3 * rng.random(k2h.shape))
+    gs = (0.3 + 0.8j, 0.5 + 0.2j, -0.4 + 0.9j) if bc == "abc" else (0.0, 0.0, 0.0)
+    fields = op.derived_fields(k2h, h3[0]) if order == 6 else None
+    A = op.A_kron(order, k2h[2:-2, 2:-2, 2:-2], h3, gs, fields)
+    n = int(np.prod(shape))
+    x = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    y_ref = A @ x
+    nodes = rng.permutation(n)                            # every node, in an arbitrary order
+    y = op.sampled_matvec(order, k2h, h3, gs, x, nodes)
+    assert np.linalg.norm(y - y_ref[nodes]) <= 1e-14 * np.linalg.norm(y_ref)
+
+
+@pytest.mark.parametrize("bc", ["abc", "dirichlet"])
+def test_sampled_M_equals_matrix_rows(bc):
+    """The row-sampled preconditioner operator equals M_matrix @ z on every node of a ragged box, with a distinct
+    gamma and h per axis (M = Delta + k0^2 I with the ghost-eliminated closure, Sec. 4)."""
+    rng = np.random.default_rng(11 + (bc == "abc"))
+    shape = (14, 13, 9)
+    h3 = (0.07, 0.09, 0.05)
+    k0 = 17.0
+    gs = (0.3 + 0.8j, 0.5 + 0.2j, -0.4 + 0.9j) if bc == "abc" else (0.0, 0.0, 0.0)
+    M = pc.M_matrix(shape, h3, k0, gs)
+    n = int(np.prod(shape))
+    z = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    y_ref = M @ z
+    nodes = rng.permutation(n)
+    y = pc.sampled_M(shape, h3, k0, gs, z, nodes)
+    assert np.linalg.norm(y - y_ref[nodes]) <= 1e-14 * np.linalg.norm(y_ref)
+
+
 def test_problem_keeps_complex_k2():
     """Second order, A = Delta_h + diag(k^2): adding i k_i to k^2 must add exactly i diag(k_i) to the assembled
     matrix (and leave F = f unchanged)."""
