@@ -6,8 +6,10 @@ Tolerances:
     about a 10x margin for N <= 256.
   * EigT preconditioner (FP64): four dense transforms with condition number kappa(V) <= 18 each and one
     pivot-stable Thomas solve; 1e-11 relative (measured ~1e-14).
-  * EigT preconditioner (FP32): the same chain in binary32 (eps = 6e-8) with kappa(V)^2 ~ 300 and sums of
-    N terms; bound 2e-4 relative.
+  * EigT preconditioner (FP32): the same chain in binary32 (unit round-off u = 6e-8): the four transforms
+    accumulate in FP32 over N/2 terms (MFMA sums in a tree, so the error grows like log N, not N) and the
+    z-solve's pivots are bounded away from zero, so the error is a few u times kappa(V_x) kappa(V_y). The bound
+    TOL32 = 1e-5 is 160 u; measured 4e-7 to 8e-7 on these boxes.
   * solutions: both sides solve to rtol 1e-10, so each is within kappa(A) * 1e-10 of the exact discrete
     solution; parity bar relative L2 <= 1e-8 (the parity bar of the method's target).
 """
@@ -23,6 +25,9 @@ from oracle import precond as pc
 pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
+
+
+TOL32 = 1e-5
 
 
 def H():
@@ -143,7 +148,7 @@ def test_precond_parity_fp32(shape):
     zr = pc.EigT(shape, h3, k0, gs).solve(y)
     err = np.linalg.norm(z - zr) / np.linalg.norm(zr)
     print(f"fp32 precond rel err {err:.3e}")
-    assert err <= 2e-4
+    assert err <= TOL32
 
 
 def _problem(order, n, k0, seed=2):
@@ -228,7 +233,9 @@ def _sample_nodes(shape, seed, count=3000):
 @pytest.mark.parametrize("name", ["inclusions", "noise"])
 def test_fullsize_sampled(name):
     """At the full sizes (128^3 and 256^3): matvec rows and preconditioner rows checked node by node with the
-    oracle's row-sampled operators, and the solve's residual checked on sampled rows."""
+    oracle's row-sampled operators; the solve's full residual formed with the library's matvec, its entries
+    checked against the oracle's rows at the sampled nodes. (The solutions themselves are compared with the
+    oracle's in test_gpu_fullsize.py.)"""
     h = H()
     w = synth.workload(name)
     n = w["n"]
@@ -241,7 +248,7 @@ def test_fullsize_sampled(name):
     y = host(h.helm_matvec(ctx, dev(x)))
     yr = op.sampled_matvec(w["order"], w["k2"], (hh,) * 3, (g, g, g), x, nodes)
     assert np.abs(y[nodes] - yr).max() <= 1e-12 * np.abs(yr).max()
-    for fp32, tol in ((False, 1e-11), (True, 2e-4)):
+    for fp32, tol in ((False, 1e-11), (True, TOL32)):
         z = host(h.helm_precond_apply(ctx, dev(x), fp32=fp32))
         mz = pc.sampled_M(shape, (hh,) * 3, k0, (g, g, g), z, nodes)
         err = np.abs(mz - x[nodes]).max() / np.abs(x).max()
@@ -249,11 +256,16 @@ def test_fullsize_sampled(name):
         assert err <= tol
     F = h.helm_rhs(ctx, dev(w["f"]))
     xs, info = h.helm_gmres_solve(ctx, F, m=w["m"], rtol=1e-10, flexible=True, prec_fp32=True)
-    Fh = host(F)
-    r = Fh[nodes] - op.sampled_matvec(w["order"], w["k2"], (hh,) * 3, (g, g, g), host(xs), nodes)
-    print(name, info["iters"], info["relres_true"], np.abs(r).max() / np.linalg.norm(Fh))
-    assert info["converged"]
-    assert np.abs(r).max() <= 1.01e-10 * np.linalg.norm(Fh)
+    # the full residual r = F - A x (Sec. 5.1 rel-res) with the library's matvec; its sampled entries are
+    # checked against the oracle's rows of A applied to the same x
+    rg = F - h.helm_matvec(ctx, xs)
+    relres = float(torch.linalg.vector_norm(rg) / torch.linalg.vector_norm(F))
+    Fh, xh, rh = host(F), host(xs), host(rg)
+    Ax = op.sampled_matvec(w["order"], w["k2"], (hh,) * 3, (g, g, g), xh, nodes)
+    rr = Fh[nodes] - Ax
+    print(name, info["iters"], info["relres_true"], relres, np.abs(rh[nodes] - rr).max() / np.abs(Ax).max())
+    assert info["converged"] and relres <= 1.01e-10
+    assert np.abs(rh[nodes] - rr).max() <= 1e-12 * np.abs(Ax).max()
 
 
 @pytest.mark.parametrize("shape", [(12, 20, 70), (33, 33, 33), (9, 5, 7), (6, 10, 300), (4, 6, 540), (5, 300, 6)])
@@ -278,7 +290,7 @@ def test_pfft_precond_parity(shape, fp32):
     zr = pc.EigT(shape, h3, k0, gs).solve(y)
     err = np.linalg.norm(z - zr) / np.linalg.norm(zr)
     print(f"pfft {'fp32' if fp32 else 'fp64'} {shape} rel err {err:.3e}")
-    assert err <= (2e-4 if fp32 else 1e-11)
+    assert err <= (TOL32 if fp32 else 1e-11)
     if not fp32:
         zp = pc.PFFT(shape, h3, k0, gs).solve(y)
         assert np.linalg.norm(z - zp) <= 1e-11 * np.linalg.norm(zp)
@@ -318,7 +330,7 @@ def test_gemm_tile_configs_parity(cfg, shape):
     z64 = host(h.helm_precond_apply(ctx, dev(y)))
     z32 = host(h.helm_precond_apply(ctx, dev(y), fp32=True))
     assert np.linalg.norm(z64 - zr) <= 1e-11 * np.linalg.norm(zr)
-    assert np.linalg.norm(z32 - zr) <= 2e-4 * np.linalg.norm(zr)
+    assert np.linalg.norm(z32 - zr) <= TOL32 * np.linalg.norm(zr)
 
 
 def test_autotune_runs_and_keeps_parity():
@@ -551,7 +563,7 @@ def test_fft46_precond_parity(order, fp32):
 @pytest.mark.parametrize("fp32", [False, True])
 def test_eigt3_collocated_parity(shape, fp32):
     """EigT with the collocated three-point closure (HELM_BC_ABC3: gamma = 2 i k0 h, zeta = 2) against the oracle's
-    EigT(zeta = 2) and the collocated second-order matrix: FP64 1e-11 relative, FP32 2e-4 (the EigT bounds)."""
+    EigT(zeta = 2) and the collocated second-order matrix: FP64 1e-11 relative, FP32 TOL32 (the EigT bounds)."""
     h = H()
     h3 = (1.0 / (shape[2] - 1), 1.0 / (shape[1] - 1), 1.0 / (shape[0] - 1))
     k0 = 0.47 / h3[0]
@@ -562,7 +574,7 @@ def test_eigt3_collocated_parity(shape, fp32):
     zr = pc.EigT(shape, h3, k0, gs, zeta=2.0).solve(y)
     err = np.linalg.norm(z - zr) / np.linalg.norm(zr)
     print(f"eigt3 {shape} fp32={fp32} rel err {err:.3e}")
-    assert err <= (2e-4 if fp32 else 1e-11)
+    assert err <= (TOL32 if fp32 else 1e-11)
     if not fp32:
         M = pc.M_collocated(shape, h3, k0, gs)
         assert np.linalg.norm(M @ z - y) <= 1e-11 * np.linalg.norm(y)
@@ -573,7 +585,7 @@ def test_eigt3_collocated_parity(shape, fp32):
 @pytest.mark.parametrize("fp32", [False, True])
 def test_pfft3_collocated_parity(shape, fp32):
     """PFFT with the collocated closure (zeta = 2): the face correction reaches two layers per face. Against the
-    oracle's EigT(zeta = 2), its PFFT(zeta = 2) and the collocated matrix: FP64 1e-10, FP32 2e-4. FP64 is 1e-10, not
+    oracle's EigT(zeta = 2), its PFFT(zeta = 2) and the collocated matrix: FP64 1e-10, FP32 TOL32. FP64 is 1e-10, not
     EigT's 1e-11: at (12, 20, 70) (k0 h_z = 2.9 on the short axis) the Dirichlet solves inside PFFT are less well
     conditioned, and the oracle's own PFFT(zeta = 2) differs from its EigT(zeta = 2) by 4e-11. The wide boxes take
     the ring pass with 8 column chunks per lane (N_x = 300) and the long y-axis (N_y = 300); they use one h on every
@@ -592,7 +604,7 @@ def test_pfft3_collocated_parity(shape, fp32):
     zr = pc.EigT(shape, h3, k0, gs, zeta=2.0).solve(y)
     err = np.linalg.norm(z - zr) / np.linalg.norm(zr)
     print(f"pfft3 {shape} fp32={fp32} rel err {err:.3e}")
-    assert err <= (2e-4 if fp32 else 1e-10)
+    assert err <= (TOL32 if fp32 else 1e-10)
     if not fp32:
         zp = pc.PFFT(shape, h3, k0, gs, zeta=2.0).solve(y)
         assert np.linalg.norm(z - zp) <= 1e-10 * np.linalg.norm(zp)
