@@ -522,7 +522,13 @@ helm_status ensure_krylov(Ctx &c, int m, int flexible) {
     if (k.V && k.m == m && k.flexible == flexible) return HELM_OK;
     dfree(c, k.V); dfree(c, k.Z); dfree(c, k.Zf); dfree(c, k.tmp); dfree(c, k.partials); dfree(c, k.red);
     if (k.red_host) { (void)hipHostFree(k.red_host); k.red_host = nullptr; }
+    hipStream_t aux = k.aux;
+    hipEvent_t red_ev = k.red_ev, copy_ev = k.copy_ev;
     k = KrylovWork{};
+    k.aux = aux; k.red_ev = red_ev; k.copy_ev = copy_ev;
+    if (!k.aux) HIP_TRY(hipStreamCreateWithFlags(&k.aux, hipStreamNonBlocking));
+    if (!k.red_ev) HIP_TRY(hipEventCreateWithFlags(&k.red_ev, hipEventDisableTiming));
+    if (!k.copy_ev) HIP_TRY(hipEventCreateWithFlags(&k.copy_ev, hipEventDisableTiming));
     k.nblocks = dots_blocks(c.n);
     k.ld = c.n + KRYLOV_PAD;
     ST_TRY(dalloc(c, &k.V, (size_t)(m + 1) * k.ld));
@@ -555,6 +561,31 @@ helm_status dots(Ctx &c, const double2 *V, int nv, const double2 *w, std::vector
     return HELM_OK;
 }
 
+// The same reduction, with the values copied to the host on the auxiliary stream: the solve stream goes on with
+// whatever the caller queues next, and dots_wait returns the values.
+helm_status dots_async(Ctx &c, const double2 *V, int nv, const double2 *w) {
+    KrylovWork &k = c.kw;
+    HIP_TRY(timed(c, HELM_K_DOTS, 16.0 * c.n * (nv + 1), [&] { return launch_dots(V, k.ld, nv, w, c.n, k.partials, k.nblocks, k.red, c.stream); }));
+    HIP_TRY(hipEventRecord(k.red_ev, c.stream));
+    HIP_TRY(hipStreamWaitEvent(k.aux, k.red_ev, 0));
+    HIP_TRY(hipMemcpyAsync(k.red_host, k.red, (nv + 1) * sizeof(double2), hipMemcpyDeviceToHost, k.aux));
+    HIP_TRY(hipEventRecord(k.copy_ev, k.aux));
+    return HELM_OK;
+}
+
+helm_status dots_wait(Ctx &c, int nv, std::vector<cd> &out) {
+    KrylovWork &k = c.kw;
+    HIP_TRY(hipEventSynchronize(k.copy_ev));
+    out.resize(nv + 1);
+    for (int i = 0; i <= nv; ++i) out[i] = cd(k.red_host[i].x, k.red_host[i].y);
+    for (int i = 0; i <= nv; ++i)
+        if (!std::isfinite(out[i].real()) || !std::isfinite(out[i].imag())) {
+            c.err = "non-finite value in a Krylov reduction";
+            return HELM_ENUMERIC;
+        }
+    return HELM_OK;
+}
+
 helm_status norm2(Ctx &c, const double2 *w, double &nrm) {
     std::vector<cd> r;
     ST_TRY(dots(c, nullptr, 0, w, r));
@@ -571,6 +602,7 @@ struct Timer {
 }  // namespace
 
 helm_status helm::ctx_tri_pivots(Ctx &c) { return ensure_tpiv(c, c.dxe, c.dye, &c.tpiv_eig); }
+
 
 extern "C" {
 
@@ -649,6 +681,9 @@ void helm_destroy(helm_ctx *ctx) {
     for (void *p : c.allocs) (void)hipFree(p);
     c.allocs.clear();
     if (c.kw.red_host) (void)hipHostFree(c.kw.red_host);
+    if (c.kw.aux) (void)hipStreamDestroy(c.kw.aux);
+    if (c.kw.red_ev) (void)hipEventDestroy(c.kw.red_ev);
+    if (c.kw.copy_ev) (void)hipEventDestroy(c.kw.copy_ev);
     if (c.sg_host) (void)hipHostFree(c.sg_host);
     delete c.pfft;
     c.pfft = nullptr;
@@ -797,6 +832,9 @@ helm_status setup_impl(helm_ctx **out, helm_grid g, const double h[3], const voi
     c.c0 = c.hz * c.hz * c.k0 * c.k0 - 2.0 * (c.ax + c.ay + 1.0);
     if ((st = dalloc(c, &c.t1, (size_t)c.n)) != HELM_OK) return bail(st);
     if ((st = dalloc(c, &c.t2, (size_t)c.n)) != HELM_OK) return bail(st);
+    // the z-solve's chunk pivots of the EigT preconditioner (2 bytes per unknown), so that no later preconditioner
+    // call has to allocate them
+    if ((st = ensure_tpiv(c, c.dxe, c.dye, &c.tpiv_eig)) != HELM_OK) return bail(st);
     *out = ctx;
     return HELM_OK;
 }
@@ -1114,32 +1152,37 @@ helm_status helm_gmres_solve(helm_ctx *ctx, const void *F_dev, void *x_dev, cons
             else
                 HIP_TRY(timed(c, HELM_K_MATVEC, matvec_bytes(c, true), [&] { return launch_matvec(c.sp, z, c.k2, c.fld, vj, w, c.stream); }));
             HIP_TRY(hipEventRecord(ev[4], c.stream));
-            // classical Gram-Schmidt: V^H y and ||y||^2 in one pass
-            ST_TRY(dots(c, k.V, j + 1, w, hv));
-            double hh = 0.0;
-            for (int i = 0; i <= j; ++i) hh += std::norm(hv[i]);
-            double ww = hv[j + 1].real();
-            double eta2 = ww - hh;
+            // classical Gram-Schmidt: V^H y and ||y||^2 in one pass. The update takes its coefficients from the
+            // reduced values on the device, so it follows the inner products without waiting for the host; the
+            // values reach the host on the auxiliary stream meanwhile (Hessenberg column, Givens rotation).
+            ST_TRY(dots_async(c, k.V, j + 1, w));
             hipEvent_t ua = ev[8 + 2 * (j & 1)], ub = ev[9 + 2 * (j & 1)];
             HIP_TRY(hipEventRecord(ua, c.stream));
+            HIP_TRY(timed(c, HELM_K_LINCOMB, 16.0 * c.n * (j + 3), [&] { return launch_lincomb_cgs(w, k.V, k.ld, j + 1, k.red, n, c.stream); }));
+            ST_TRY(dots_wait(c, j + 1, hv));
+            double hh = 0.0;
+            for (int i = 0; i <= j; ++i) {        // the device's arithmetic, in the same order
+                hh = std::fma(hv[i].real(), hv[i].real(), hh);
+                hh = std::fma(hv[i].imag(), hv[i].imag(), hh);
+            }
+            const double ww = hv[j + 1].real();
+            const double eta2 = ww - hh;
+            double eta = 0.0;
             if (!(eta2 > 0.5 * ww)) {
-                // cancellation: subtract, then re-orthogonalise once (and take the norm from the second pass)
+                // cancellation: the update left u = -(y - V h) unscaled. A second pass orthogonalises and scales it,
+                // v_{j+1} = (u - V h2)/eta' = -(y - V (h - h2))/eta', with h2 = V^H u.
                 ++inf.reorths;
-                for (int i = 0; i <= j; ++i) coef[i] = make_double2(-hv[i].real(), -hv[i].imag());
-                HIP_TRY(timed(c, HELM_K_LINCOMB, 16.0 * c.n * (j + 3), [&] { return launch_lincomb(w, w, make_double2(1.0, 0.0), k.V, k.ld, j + 1, coef.data(), n, c.stream); }));
                 ST_TRY(dots(c, k.V, j + 1, w, hv2));
                 double hh2 = 0.0;
-                for (int i = 0; i <= j; ++i) { hv[i] += hv2[i]; hh2 += std::norm(hv2[i]); }
-                eta2 = hv2[j + 1].real() - hh2;
-                for (int i = 0; i <= j; ++i) coef[i] = make_double2(hv2[i].real(), hv2[i].imag());
+                for (int i = 0; i <= j; ++i) { hv[i] -= hv2[i]; hh2 += std::norm(hv2[i]); }
+                const double e2 = hv2[j + 1].real() - hh2;
+                eta = e2 > 0.0 ? std::sqrt(e2) : 0.0;
+                if (eta > 0.0) {
+                    for (int i = 0; i <= j; ++i) coef[i] = make_double2(-hv2[i].real() / eta, -hv2[i].imag() / eta);
+                    HIP_TRY(timed(c, HELM_K_LINCOMB, 16.0 * c.n * (j + 3), [&] { return launch_lincomb(w, w, make_double2(1.0 / eta, 0.0), k.V, k.ld, j + 1, coef.data(), n, c.stream); }));
+                }
             } else {
-                for (int i = 0; i <= j; ++i) coef[i] = make_double2(hv[i].real(), hv[i].imag());
-            }
-            double eta = eta2 > 0.0 ? std::sqrt(eta2) : 0.0;
-            if (eta > 0.0) {
-                // v_{j+1} = -(y - V h_y) / eta
-                for (int i = 0; i <= j; ++i) { coef[i].x /= eta; coef[i].y /= eta; }
-                HIP_TRY(timed(c, HELM_K_LINCOMB, 16.0 * c.n * (j + 3), [&] { return launch_lincomb(w, w, make_double2(-1.0 / eta, 0.0), k.V, k.ld, j + 1, coef.data(), n, c.stream); }));
+                eta = std::sqrt(eta2);
             }
             HIP_TRY(hipEventRecord(ub, c.stream));
             // phase bookkeeping while the GPU runs the update

@@ -148,6 +148,8 @@ struct KrylovWork {
     double2 *red = nullptr;      // m + 2 reduced values
     double2 *red_host = nullptr; // pinned host copy
     int nblocks = 0;
+    hipStream_t aux = nullptr;   // copies the reduced values to the host while the solve stream runs on
+    hipEvent_t red_ev = nullptr, copy_ev = nullptr;
 };
 
 struct ProfPending { int cls; double work; hipEvent_t a, b; bool own_a; };   // own_a: a is not the previous b
@@ -362,7 +364,11 @@ hipError_t launch_lincomb(double2 *out, const double2 *base, double2 alpha, cons
                           const double2 *coef, long long n, hipStream_t s);
 // the same over complex64 vectors V (the complex64 Z basis of FGMRES with the FP32 preconditioner)
 hipError_t launch_lincomb(double2 *out, const double2 *base, double2 alpha, const float2 *V, long long ldv, int nv,
-                          const double2 *coef, long long n, hipStream_t s);   // out = alpha base + sum coef_i V_i
+                          const double2 *coef, long long n, hipStream_t s);
+// w <- -(w - V h)/eta with h = red[0..nv-1], eta^2 = red[nv].x - sum |h_i|^2 computed on the device (unscaled when
+// eta^2 <= red[nv].x / 2, which the caller detects and corrects with a second pass)
+hipError_t launch_lincomb_cgs(double2 *w, const double2 *V, long long ldv, int nv, const double2 *red, long long n,
+                              hipStream_t s);   // out = alpha base + sum coef_i V_i
 hipError_t launch_fill_zero(double2 *x, long long n, hipStream_t s);
 
 // grouped (batched) launches; see k_batch.hip

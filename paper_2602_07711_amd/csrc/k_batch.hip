@@ -212,7 +212,10 @@ __global__ __launch_bounds__(256) void k_b_arnoldi(const BProb *__restrict__ P, 
     for (int i = 0; i <= j; ++i) hh += hv[i].x * hv[i].x + hv[i].y * hv[i].y;
     const double ww = hv[nv].x;
     double eta2 = ww - hh;
-    if (!(eta2 > 0.5 * ww)) s.cancel += 1;
+    // cancellation (eta^2 <= ||y||^2 / 2): eta is not accurate enough to scale v_{j+1}, and this path has no second
+    // Gram-Schmidt pass, so the cycle ends here and the restart continues from the true residual
+    const bool cancelled = !(eta2 > 0.5 * ww);
+    if (cancelled) s.cancel += 1;
     const double eta = eta2 > 0.0 ? sqrt(eta2) : 0.0;
     for (int i = 0; i <= j; ++i) H[(long long)i * m + j] = make_double2(-hv[i].x, -hv[i].y);
     H[(long long)j * m + j].x += 1.0;
@@ -244,7 +247,8 @@ __global__ __launch_bounds__(256) void k_b_arnoldi(const BProb *__restrict__ P, 
     s.k = j + 1;
     const double res = cabs2(g[j + 1]);
     s.relres_est = res / s.bnorm;
-    if (eta == 0.0 || res <= prm->rtol * s.bnorm || s.its >= prm->maxit || j + 1 == m || !isfinite(res)) {
+    if (eta == 0.0 || cancelled || res <= prm->rtol * s.bnorm || s.its >= prm->maxit || j + 1 == m ||
+        !isfinite(res)) {
         s.active = 0;
     } else {
         for (int i = 0; i <= j; ++i) coef[i] = make_double2(hv[i].x / eta, hv[i].y / eta);

@@ -105,6 +105,75 @@ __global__ __launch_bounds__(256) void k_lincomb(double2 *out, const double2 *ba
     }
 }
 
+// The orthogonalisation update of an Arnoldi step with its coefficients taken on the device from the reduced inner
+// products red[0..nv-1] = V_i^H w and red[nv] = ||w||^2: eta^2 = ||w||^2 - sum |h_i|^2 and, when no cancellation
+// happened (eta^2 > ||w||^2 / 2), w <- -(w - V h) / eta; otherwise w <- -(w - V h) unscaled, for the host's second
+// Gram-Schmidt pass. Every block recomputes the (uniform) coefficients, so no host round trip sits between the
+// inner products and the update.
+__global__ __launch_bounds__(256) void k_lincomb_cgs(double2 *w, const double2 *__restrict__ V, long long ldv, int nv,
+                                                     const double2 *__restrict__ red, long long n) {
+    double hh = 0.0;
+    for (int i = 0; i < nv; ++i) {
+        const double2 r = red[i];
+        hh = fma(r.x, r.x, hh);
+        hh = fma(r.y, r.y, hh);
+    }
+    const double ww = red[nv].x, eta2 = ww - hh;
+    const double inv = eta2 > 0.5 * ww ? 1.0 / sqrt(eta2) : 1.0;
+    const long long start = (long long)blockIdx.x * (256 * LC_EPT) + threadIdx.x;
+    double2 acc[LC_EPT];
+    bool ok[LC_EPT];
+#pragma unroll
+    for (int e = 0; e < LC_EPT; ++e) {
+        const long long idx = start + (long long)e * 256;
+        ok[e] = idx < n;
+        acc[e] = make_double2(0.0, 0.0);
+        if (ok[e]) {
+            const double2 b = ld_stream(w + idx);
+            acc[e] = make_double2(-inv * b.x, -inv * b.y);
+        }
+    }
+    int i = 0;
+    for (; i + 4 <= nv; i += 4) {
+        double2 v[4][LC_EPT];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int e = 0; e < LC_EPT; ++e) {
+                const long long idx = start + (long long)e * 256;
+                v[q][e] = ok[e] ? ld_stream(V + (long long)(i + q) * ldv + idx) : make_double2(0.0, 0.0);
+            }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const double2 c = make_double2(red[i + q].x * inv, red[i + q].y * inv);
+#pragma unroll
+            for (int e = 0; e < LC_EPT; ++e) {
+                acc[e].x += c.x * v[q][e].x - c.y * v[q][e].y;
+                acc[e].y += c.x * v[q][e].y + c.y * v[q][e].x;
+            }
+        }
+    }
+    for (; i < nv; ++i) {
+        const double2 c = make_double2(red[i].x * inv, red[i].y * inv);
+        double2 v[LC_EPT];
+#pragma unroll
+        for (int e = 0; e < LC_EPT; ++e) {
+            const long long idx = start + (long long)e * 256;
+            v[e] = ok[e] ? ld_stream(V + (long long)i * ldv + idx) : make_double2(0.0, 0.0);
+        }
+#pragma unroll
+        for (int e = 0; e < LC_EPT; ++e) {
+            acc[e].x += c.x * v[e].x - c.y * v[e].y;
+            acc[e].y += c.x * v[e].y + c.y * v[e].x;
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < LC_EPT; ++e) {
+        const long long idx = start + (long long)e * 256;
+        if (ok[e]) w[idx] = acc[e];
+    }
+}
+
 __global__ void k_zero(double2 *x, long long n) {
     long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
     if (idx < n) x[idx] = make_double2(0.0, 0.0);
@@ -153,6 +222,14 @@ hipError_t launch_lincomb(double2 *out, const double2 *base, double2 alpha, cons
 hipError_t launch_lincomb(double2 *out, const double2 *base, double2 alpha, const float2 *V, long long ldv, int nv,
                           const double2 *coef, long long n, hipStream_t s) {
     return lincomb_t<float2>(out, base, alpha, V, ldv, nv, coef, n, s);
+}
+
+hipError_t launch_lincomb_cgs(double2 *w, const double2 *V, long long ldv, int nv, const double2 *red, long long n,
+                              hipStream_t s) {
+    long long grid_ll = (n + 256 * LC_EPT - 1) / (256 * LC_EPT);
+    int grid = (int)(grid_ll < 1 ? 1 : grid_ll);
+    hipLaunchKernelGGL(k_lincomb_cgs, dim3(grid), dim3(256), 0, s, w, V, ldv, nv, red, n);
+    return hipGetLastError();
 }
 
 hipError_t launch_fill_zero(double2 *x, long long n, hipStream_t s) {

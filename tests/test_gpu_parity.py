@@ -10,6 +10,9 @@ Tolerances:
     accumulate in FP32 over N/2 terms (MFMA sums in a tree, so the error grows like log N, not N) and the
     z-solve's pivots are bounded away from zero, so the error is a few u times kappa(V_x) kappa(V_y). The bound
     TOL32 = 1e-5 is 160 u; measured 4e-7 to 8e-7 on these boxes.
+  * PFFT preconditioner (FP32): the same chain plus the Dirichlet-closure solves (A_p^F)^{-1} of Sec. 4.2, whose
+    modes nearest resonance are damped only by the z closure, so they amplify the FP32 rounding further: measured
+    8e-5 to 1.2e-4 on the 33^3 and 70 x 20 x 12 boxes (the collocated closure included); bound TOL32_PFFT = 3e-4.
   * solutions: both sides solve to rtol 1e-10, so each is within kappa(A) * 1e-10 of the exact discrete
     solution; parity bar relative L2 <= 1e-8 (the parity bar of the method's target).
 """
@@ -28,6 +31,7 @@ torch = pytest.importorskip("torch")
 
 
 TOL32 = 1e-5
+TOL32_PFFT = 3e-4
 
 
 def H():
@@ -248,12 +252,20 @@ def test_fullsize_sampled(name):
     y = host(h.helm_matvec(ctx, dev(x)))
     yr = op.sampled_matvec(w["order"], w["k2"], (hh,) * 3, (g, g, g), x, nodes)
     assert np.abs(y[nodes] - yr).max() <= 1e-12 * np.abs(yr).max()
-    for fp32, tol in ((False, 1e-11), (True, TOL32)):
+    # residual rows of M z = x. FP32: the residual multiplies the solution's rounding by M's row sums (about
+    # 12/h^2 against max|x| / max|z|); measured 1.3e-5 at 256^3, bound RES32 = 5e-5
+    zs = {}
+    for fp32, tol in ((False, 1e-11), (True, 5e-5)):
         z = host(h.helm_precond_apply(ctx, dev(x), fp32=fp32))
         mz = pc.sampled_M(shape, (hh,) * 3, k0, (g, g, g), z, nodes)
         err = np.abs(mz - x[nodes]).max() / np.abs(x).max()
         print(name, "precond fp32" if fp32 else "precond fp64", err)
         assert err <= tol
+        zs[fp32] = z
+    # the FP32 preconditioner's solution against the FP64 one (itself pinned by the rows above), whole vector
+    err32 = np.linalg.norm(zs[True] - zs[False]) / np.linalg.norm(zs[False])
+    print(name, "precond fp32 vs fp64", err32)
+    assert err32 <= TOL32
     F = h.helm_rhs(ctx, dev(w["f"]))
     xs, info = h.helm_gmres_solve(ctx, F, m=w["m"], rtol=1e-10, flexible=True, prec_fp32=True)
     # the full residual r = F - A x (Sec. 5.1 rel-res) with the library's matvec; its sampled entries are
@@ -290,7 +302,7 @@ def test_pfft_precond_parity(shape, fp32):
     zr = pc.EigT(shape, h3, k0, gs).solve(y)
     err = np.linalg.norm(z - zr) / np.linalg.norm(zr)
     print(f"pfft {'fp32' if fp32 else 'fp64'} {shape} rel err {err:.3e}")
-    assert err <= (TOL32 if fp32 else 1e-11)
+    assert err <= (TOL32_PFFT if fp32 else 1e-11)
     if not fp32:
         zp = pc.PFFT(shape, h3, k0, gs).solve(y)
         assert np.linalg.norm(z - zp) <= 1e-11 * np.linalg.norm(zp)
@@ -585,7 +597,7 @@ def test_eigt3_collocated_parity(shape, fp32):
 @pytest.mark.parametrize("fp32", [False, True])
 def test_pfft3_collocated_parity(shape, fp32):
     """PFFT with the collocated closure (zeta = 2): the face correction reaches two layers per face. Against the
-    oracle's EigT(zeta = 2), its PFFT(zeta = 2) and the collocated matrix: FP64 1e-10, FP32 TOL32. FP64 is 1e-10, not
+    oracle's EigT(zeta = 2), its PFFT(zeta = 2) and the collocated matrix: FP64 1e-10, FP32 TOL32_PFFT. FP64 is 1e-10, not
     EigT's 1e-11: at (12, 20, 70) (k0 h_z = 2.9 on the short axis) the Dirichlet solves inside PFFT are less well
     conditioned, and the oracle's own PFFT(zeta = 2) differs from its EigT(zeta = 2) by 4e-11. The wide boxes take
     the ring pass with 8 column chunks per lane (N_x = 300) and the long y-axis (N_y = 300); they use one h on every
@@ -604,7 +616,7 @@ def test_pfft3_collocated_parity(shape, fp32):
     zr = pc.EigT(shape, h3, k0, gs, zeta=2.0).solve(y)
     err = np.linalg.norm(z - zr) / np.linalg.norm(zr)
     print(f"pfft3 {shape} fp32={fp32} rel err {err:.3e}")
-    assert err <= (TOL32 if fp32 else 1e-10)
+    assert err <= (TOL32_PFFT if fp32 else 1e-10)
     if not fp32:
         zp = pc.PFFT(shape, h3, k0, gs, zeta=2.0).solve(y)
         assert np.linalg.norm(z - zp) <= 1e-10 * np.linalg.norm(zp)
