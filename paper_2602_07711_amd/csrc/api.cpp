@@ -128,15 +128,17 @@ double fold_flops(const FoldDesc &f) {
 }
 
 // pivots entering each z-chunk of the partitioned tridiagonal solve, per set of x-y eigenvalues and z closure
-helm_status ensure_tpiv(Ctx &c, const double2 *dx, const double2 *dy, double2 **piv, double2 gz, double zi = 1.0) {
-    if (*piv) return HELM_OK;
-    ST_TRY(dalloc(c, piv, (size_t)tri_chunks(c.nz) * c.nx * c.ny));
-    HIP_TRY(launch_tri_pivots(dx, dy, c.nx, c.ny, c.nz, c.ax, c.ay, c.c0, gz, *piv, c.stream, zi));
+helm_status ensure_tpiv(Ctx &c, const double2 *dx, const double2 *dy, TriPiv *piv, double2 gz, double zi = 1.0) {
+    if (piv->d) return HELM_OK;
+    const size_t cnt = (size_t)tri_chunks(c.nz) * c.nx * c.ny;
+    ST_TRY(dalloc(c, &piv->d, cnt));
+    ST_TRY(dalloc(c, &piv->f, cnt));
+    HIP_TRY(launch_tri_pivots(dx, dy, c.nx, c.ny, c.nz, c.ax, c.ay, c.c0, gz, piv->d, piv->f, c.stream, zi));
     prof_gap(c);   // untimed set-up launch between timed ones
     return HELM_OK;
 }
 // the operator's own closure (gamma_z and, for the collocated closure, zeta)
-helm_status ensure_tpiv(Ctx &c, const double2 *dx, const double2 *dy, double2 **piv) {
+helm_status ensure_tpiv(Ctx &c, const double2 *dx, const double2 *dy, TriPiv *piv) {
     return ensure_tpiv(c, dx, dy, piv, d2(c.gamma[2]), 1.0 / c.zeta);
 }
 
@@ -157,7 +159,7 @@ helm_status eigt_apply(Ctx &c, const double2 *y, double2 *z, bool fp32, float2 *
         HIP_TRY(timed(c, HELM_K_GEMM_X64, wx, [&] { return launch_fold_z64(FOLD_XF, fx, y, c.fx64.fs, c.fx64.fa, c.t1, c.stream, c.gemm_cfg[0]); }));
         HIP_TRY(timed(c, HELM_K_GEMM_Y64, wy, [&] { return launch_fold_z64(FOLD_YF, fy, c.t1, c.fy64.fs, c.fy64.fa, c.t2, c.stream, c.gemm_cfg[1]); }));
         ST_TRY(ensure_tpiv(c, c.dxe, c.dye, &c.tpiv_eig));
-        HIP_TRY(timed(c, HELM_K_TRIDIAG64, 32.0 * c.n, [&] { return launch_tridiag_chunk_z64(c.t2, c.t2, c.tpiv_eig, c.dxe, c.dye, c.nx, c.ny, c.nz, c.ax, c.ay, c.c0, gz, scale, c.stream, 1.0 / c.zeta); }));
+        HIP_TRY(timed(c, HELM_K_TRIDIAG64, 32.0 * c.n, [&] { return launch_tridiag_chunk_z64(c.t2, c.t2, c.tpiv_eig.d, c.dxe, c.dye, c.nx, c.ny, c.nz, c.ax, c.ay, c.c0, gz, scale, c.stream, 1.0 / c.zeta); }));
         HIP_TRY(timed(c, HELM_K_GEMM_Y64, wy, [&] { return launch_fold_z64(FOLD_YI, fy, c.t2, c.fy64.is, c.fy64.ia, c.t1, c.stream, c.gemm_cfg_inv[1]); }));
         HIP_TRY(timed(c, HELM_K_GEMM_X64, wx, [&] { return launch_fold_z64(FOLD_XI, fx, c.t1, c.fx64.is, c.fx64.ia, z, c.stream, c.gemm_cfg_inv[0]); }));
     } else {
@@ -165,7 +167,7 @@ helm_status eigt_apply(Ctx &c, const double2 *y, double2 *z, bool fp32, float2 *
         HIP_TRY(timed(c, HELM_K_GEMM_X32, wx, [&] { return launch_fold_z32_in64(FOLD_XF, fx, y, c.fx32.fs, c.fx32.fa, c.t1f, c.stream, c.gemm_cfg[2]); }));
         HIP_TRY(timed(c, HELM_K_GEMM_Y32, wy, [&] { return launch_fold_z32(FOLD_YF, fy, c.t1f, c.fy32.fs, c.fy32.fa, c.t2f, c.stream, c.gemm_cfg[3]); }));
         ST_TRY(ensure_tpiv(c, c.dxe, c.dye, &c.tpiv_eig));
-        HIP_TRY(timed(c, HELM_K_TRIDIAG32, 16.0 * c.n, [&] { return launch_tridiag_chunk_z32(c.t2f, c.t2f, c.tpiv_eig, c.dxe, c.dye, c.nx, c.ny, c.nz, c.ax, c.ay, c.c0, gz, scale, c.stream, 1.0 / c.zeta); }));
+        HIP_TRY(timed(c, HELM_K_TRIDIAG32, 16.0 * c.n, [&] { return launch_tridiag_chunk_z32(c.t2f, c.t2f, c.tpiv_eig.f, c.dxe, c.dye, c.nx, c.ny, c.nz, c.ax, c.ay, c.c0, gz, scale, c.stream, 1.0 / c.zeta); }));
         HIP_TRY(timed(c, HELM_K_GEMM_Y32, wy, [&] { return launch_fold_z32(FOLD_YI, fy, c.t2f, c.fy32.is, c.fy32.ia, c.t1f, c.stream, c.gemm_cfg_inv[3]); }));
         HIP_TRY(timed(c, HELM_K_GEMM_X32, wx, [&] { return z32 ? launch_fold_z32(FOLD_XI, fx, c.t1f, c.fx32.is, c.fx32.ia, z32, c.stream, c.gemm_cfg_inv[2]) : launch_fold_z32_out64(FOLD_XI, fx, c.t1f, c.fx32.is, c.fx32.ia, z, c.stream, c.gemm_cfg_inv[2]); }));
     }
@@ -382,15 +384,15 @@ helm_status pfft_apply(Ctx &c, const double2 *y, double2 *z, bool fp32, float2 *
         double2 *T1 = two ? m.ringT + rsz : nullptr, *W1 = two ? m.ringW + rsz : nullptr;
         ST_TRY(sine_tf(c, 0, true, y, c.t1, m));
         ST_TRY(sine_tf(c, 1, true, c.t1, m.yhat, m));
-        HIP_TRY(timed(c, HELM_K_TRIDIAG64, 32.0 * c.n, [&] { return launch_tridiag_chunk_z64(m.yhat, c.t2, c.tpiv_dir, P.dFx, P.dFy, nx, ny, nz, c.ax, c.ay, c.c0, gz, hz2, c.stream, zi); }));
+        HIP_TRY(timed(c, HELM_K_TRIDIAG64, 32.0 * c.n, [&] { return launch_tridiag_chunk_z64(m.yhat, c.t2, c.tpiv_dir.d, P.dFx, P.dFy, nx, ny, nz, c.ax, c.ay, c.c0, gz, hz2, c.stream, zi); }));
         for (int layer = 0; layer < (two ? 2 : 1); ++layer)
             HIP_TRY(timed(c, HELM_K_RING, 16.0 * c.n + ring_work / ring_pass, [&] { return launch_ring_inverse_z64(c.t2, m.ringT + layer * rsz, m.Sy, m.Sy, m.Sx, m.Sx, nx, ny, nz, layer, m.rpart, m.sv, m.rsum, c.stream); }));
         HIP_TRY(timed(c, HELM_K_RING, 16.0 * c.n + ring_work, [&] { return launch_ring_forward_z64(m.ringT, nullptr, T1, nullptr, nullptr, 0.0, c.t2, m.VyiT, c.BxF, ex, ey, ex1, ey1, nx, ny, nz, m.rbuf, m.fvec, c.stream); }));
-        HIP_TRY(timed(c, HELM_K_TRIDIAG64, 32.0 * c.n, [&] { return launch_tridiag_chunk_z64(c.t2, c.t2, c.tpiv_eig, c.dxe, c.dye, nx, ny, nz, c.ax, c.ay, c.c0, gz, 1.0, c.stream, zi); }));
+        HIP_TRY(timed(c, HELM_K_TRIDIAG64, 32.0 * c.n, [&] { return launch_tridiag_chunk_z64(c.t2, c.t2, c.tpiv_eig.d, c.dxe, c.dye, nx, ny, nz, c.ax, c.ay, c.c0, gz, 1.0, c.stream, zi); }));
         for (int layer = 0; layer < (two ? 2 : 1); ++layer)
             HIP_TRY(timed(c, HELM_K_RING, 16.0 * c.n + ring_work / ring_pass, [&] { return launch_ring_inverse_z64(c.t2, m.ringW + layer * rsz, c.AyI, m.VyT, m.Vx, c.BxI, nx, ny, nz, layer, m.rpart, m.sv, m.rsum, c.stream); }));
         HIP_TRY(timed(c, HELM_K_RING, 32.0 * c.n + 2 * ring_work, [&] { return launch_ring_forward_z64(m.ringT, m.ringW, T1, W1, m.yhat, hz2, c.t2, m.Sy, m.Sx, ex, ey, ex1, ey1, nx, ny, nz, m.rbuf, m.fvec, c.stream); }));
-        HIP_TRY(timed(c, HELM_K_TRIDIAG64, 32.0 * c.n, [&] { return launch_tridiag_chunk_z64(c.t2, c.t2, c.tpiv_dir, P.dFx, P.dFy, nx, ny, nz, c.ax, c.ay, c.c0, gz, 1.0, c.stream, zi); }));
+        HIP_TRY(timed(c, HELM_K_TRIDIAG64, 32.0 * c.n, [&] { return launch_tridiag_chunk_z64(c.t2, c.t2, c.tpiv_dir.d, P.dFx, P.dFy, nx, ny, nz, c.ax, c.ay, c.c0, gz, 1.0, c.stream, zi); }));
         ST_TRY(sine_tf(c, 1, false, c.t2, c.t1, m));
         ST_TRY(sine_tf(c, 0, false, c.t1, z, m));
     } else {
@@ -399,15 +401,15 @@ helm_status pfft_apply(Ctx &c, const double2 *y, double2 *z, bool fp32, float2 *
         float2 *T1 = two ? m.ringT + rsz : nullptr, *W1 = two ? m.ringW + rsz : nullptr;
         ST_TRY(sine_tf(c, 0, true, y, c.t1f, m));
         ST_TRY(sine_tf(c, 1, true, c.t1f, m.yhat, m));
-        HIP_TRY(timed(c, HELM_K_TRIDIAG32, 16.0 * c.n, [&] { return launch_tridiag_chunk_z32(m.yhat, c.t2f, c.tpiv_dir, P.dFx, P.dFy, nx, ny, nz, c.ax, c.ay, c.c0, gz, hz2, c.stream, zi); }));
+        HIP_TRY(timed(c, HELM_K_TRIDIAG32, 16.0 * c.n, [&] { return launch_tridiag_chunk_z32(m.yhat, c.t2f, c.tpiv_dir.f, P.dFx, P.dFy, nx, ny, nz, c.ax, c.ay, c.c0, gz, hz2, c.stream, zi); }));
         for (int layer = 0; layer < (two ? 2 : 1); ++layer)
             HIP_TRY(timed(c, HELM_K_RING, 8.0 * c.n + ring_work / 2 / ring_pass, [&] { return launch_ring_inverse_z32(c.t2f, m.ringT + layer * rsz, m.Sy, m.Sy, m.Sx, m.Sx, nx, ny, nz, layer, m.rpart, m.sv, m.rsum, c.stream); }));
         HIP_TRY(timed(c, HELM_K_RING, 8.0 * c.n + ring_work / 2, [&] { return launch_ring_forward_z32(m.ringT, nullptr, T1, nullptr, nullptr, 0.0, c.t2f, m.VyiT, c.BxF32, ex, ey, ex1, ey1, nx, ny, nz, m.rbuf, m.fvec, c.stream); }));
-        HIP_TRY(timed(c, HELM_K_TRIDIAG32, 16.0 * c.n, [&] { return launch_tridiag_chunk_z32(c.t2f, c.t2f, c.tpiv_eig, c.dxe, c.dye, nx, ny, nz, c.ax, c.ay, c.c0, gz, 1.0, c.stream, zi); }));
+        HIP_TRY(timed(c, HELM_K_TRIDIAG32, 16.0 * c.n, [&] { return launch_tridiag_chunk_z32(c.t2f, c.t2f, c.tpiv_eig.f, c.dxe, c.dye, nx, ny, nz, c.ax, c.ay, c.c0, gz, 1.0, c.stream, zi); }));
         for (int layer = 0; layer < (two ? 2 : 1); ++layer)
             HIP_TRY(timed(c, HELM_K_RING, 8.0 * c.n + ring_work / 2 / ring_pass, [&] { return launch_ring_inverse_z32(c.t2f, m.ringW + layer * rsz, c.AyI32, m.VyT, m.Vx, c.BxI32, nx, ny, nz, layer, m.rpart, m.sv, m.rsum, c.stream); }));
         HIP_TRY(timed(c, HELM_K_RING, 16.0 * c.n + ring_work, [&] { return launch_ring_forward_z32(m.ringT, m.ringW, T1, W1, m.yhat, hz2, c.t2f, m.Sy, m.Sx, ex, ey, ex1, ey1, nx, ny, nz, m.rbuf, m.fvec, c.stream); }));
-        HIP_TRY(timed(c, HELM_K_TRIDIAG32, 16.0 * c.n, [&] { return launch_tridiag_chunk_z32(c.t2f, c.t2f, c.tpiv_dir, P.dFx, P.dFy, nx, ny, nz, c.ax, c.ay, c.c0, gz, 1.0, c.stream, zi); }));
+        HIP_TRY(timed(c, HELM_K_TRIDIAG32, 16.0 * c.n, [&] { return launch_tridiag_chunk_z32(c.t2f, c.t2f, c.tpiv_dir.f, P.dFx, P.dFy, nx, ny, nz, c.ax, c.ay, c.c0, gz, 1.0, c.stream, zi); }));
         ST_TRY(sine_tf(c, 1, false, c.t2f, c.t1f, m));
         if (z32) ST_TRY(sine_tf(c, 0, false, c.t1f, z32, m));
         else ST_TRY(sine_tf(c, 0, false, c.t1f, z, m));
@@ -429,7 +431,7 @@ helm_status fft2_apply(Ctx &c, const double2 *y, double2 *z, bool fp32, float2 *
         auto &m = P.m64;
         ST_TRY(sine_tf(c, 0, true, y, c.t1, m));
         ST_TRY(sine_tf(c, 1, true, c.t1, c.t2, m));
-        HIP_TRY(timed(c, HELM_K_TRIDIAG64, 32.0 * c.n, [&] { return launch_tridiag_chunk_z64(c.t2, c.t2, c.tpiv_fft2, P.dFx, P.dFy, nx, ny, nz, c.ax, c.ay, c.c0, g0, hz2, c.stream); }));
+        HIP_TRY(timed(c, HELM_K_TRIDIAG64, 32.0 * c.n, [&] { return launch_tridiag_chunk_z64(c.t2, c.t2, c.tpiv_fft2.d, P.dFx, P.dFy, nx, ny, nz, c.ax, c.ay, c.c0, g0, hz2, c.stream); }));
         ST_TRY(sine_tf(c, 1, false, c.t2, c.t1, m));
         ST_TRY(sine_tf(c, 0, false, c.t1, z, m));
     } else {
@@ -437,7 +439,7 @@ helm_status fft2_apply(Ctx &c, const double2 *y, double2 *z, bool fp32, float2 *
         auto &m = P.m32;
         ST_TRY(sine_tf(c, 0, true, y, c.t1f, m));
         ST_TRY(sine_tf(c, 1, true, c.t1f, c.t2f, m));
-        HIP_TRY(timed(c, HELM_K_TRIDIAG32, 16.0 * c.n, [&] { return launch_tridiag_chunk_z32(c.t2f, c.t2f, c.tpiv_fft2, P.dFx, P.dFy, nx, ny, nz, c.ax, c.ay, c.c0, g0, hz2, c.stream); }));
+        HIP_TRY(timed(c, HELM_K_TRIDIAG32, 16.0 * c.n, [&] { return launch_tridiag_chunk_z32(c.t2f, c.t2f, c.tpiv_fft2.f, P.dFx, P.dFy, nx, ny, nz, c.ax, c.ay, c.c0, g0, hz2, c.stream); }));
         ST_TRY(sine_tf(c, 1, false, c.t2f, c.t1f, m));
         if (z32) ST_TRY(sine_tf(c, 0, false, c.t1f, z32, m));
         else ST_TRY(sine_tf(c, 0, false, c.t1f, z, m));

@@ -150,7 +150,8 @@ helm_status helm_batch_create(helm_batch **out, helm_ctx *const *ctxs, int np, i
         b->allocs.push_back(t2);
         q.t1 = t1; q.t2 = t2;
         if (ctx_tri_pivots(c) != HELM_OK) return fail(HELM_EDEVICE, "z-solve pivots: " + c.err);
-        q.tpiv = c.tpiv_eig;
+        q.tpiv = c.tpiv_eig.d;
+        q.tpiv32 = c.tpiv_eig.f;
         if (balloc(*b, &q.part, (size_t)q.nblk_dots * (m + 2)) != hipSuccess) return fail(HELM_ENOMEM, "partials");
         q.x = nullptr;
         q.F = nullptr;

@@ -135,6 +135,12 @@ struct PfftPlan {
 // DRAM address bits above the vector size
 constexpr long long KRYLOV_PAD = 2048;
 
+// pivot table of the partitioned z-solve: complex128 for the FP64 kernel, its complex64 rounding for the FP32 one
+struct TriPiv {
+    double2 *d = nullptr;
+    float2 *f = nullptr;
+};
+
 struct KrylovWork {
     int m = 0;
     long long ld = 0;            // leading dimension of V and Z (n + KRYLOV_PAD)
@@ -187,8 +193,8 @@ struct Ctx {
     // preconditioner work buffers
     double2 *t1 = nullptr, *t2 = nullptr;
     float2 *t1f = nullptr, *t2f = nullptr;
-    double2 *tpiv_eig = nullptr, *tpiv_dir = nullptr;  // pivots entering each z-chunk (absorbing / Dirichlet x-y eigenvalues)
-    double2 *tpiv_fft2 = nullptr;                        // the same for Dirichlet x-y eigenvalues and a Dirichlet z closure
+    TriPiv tpiv_eig, tpiv_dir;   // pivots entering each z-chunk (absorbing / Dirichlet x-y eigenvalues)
+    TriPiv tpiv_fft2;            // the same for Dirichlet x-y eigenvalues and a Dirichlet z closure
     double2 *sg_y = nullptr, *sg_part = nullptr, *sg_red = nullptr, *sg_host = nullptr;   // helm_scale_guess work
 
     PfftPlan *pfft = nullptr;
@@ -283,6 +289,7 @@ struct BProb {                    // constant during a batched solve
     const double2 *F;
     void *t1, *t2;                         // preconditioner work (element type by precision)
     const double2 *tpiv;                   // pivots entering each z-chunk (the context's table)
+    const float2 *tpiv32;                  // the same rounded to complex64 (FP32 z-solve)
     double2 *part;                         // inner-product partials, nblk_dots * (m + 2)
     long long n;
     int nx, ny, nz, nblk_dots;
@@ -330,11 +337,11 @@ hipError_t launch_gemm_pair_z32(const GemmDesc &d0, const float2 *A0, const floa
 // `in` (may equal r) supplies the right-hand side; the solution is written to r.
 int tri_chunks(int nz);
 hipError_t launch_tri_pivots(const double2 *dx, const double2 *dy, int nx, int ny, int nz, double ax, double ay,
-                             double c0, double2 gz, double2 *piv, hipStream_t s, double zi = 1.0);
+                             double c0, double2 gz, double2 *piv, float2 *piv32, hipStream_t s, double zi = 1.0);
 hipError_t launch_tridiag_chunk_z64(const double2 *in, double2 *out, const double2 *piv, const double2 *dx,
                                     const double2 *dy, int nx, int ny, int nz, double ax, double ay, double c0,
                                     double2 gz, double scale, hipStream_t s, double zi = 1.0);
-hipError_t launch_tridiag_chunk_z32(const float2 *in, float2 *out, const double2 *piv, const double2 *dx,
+hipError_t launch_tridiag_chunk_z32(const float2 *in, float2 *out, const float2 *piv, const double2 *dx,
                                     const double2 *dy, int nx, int ny, int nz, double ax, double ay, double c0,
                                     double2 gz, double scale, hipStream_t s, double zi = 1.0);
 int ring_rowgroups();

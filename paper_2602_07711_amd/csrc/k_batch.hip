@@ -77,8 +77,12 @@ __global__ __launch_bounds__(1024) void k_b_tridiag(const BProb *__restrict__ P,
     const int p = find_prob(off, np, blockIdx.x);
     if (!st[p].active) return;                 // uniform over the block
     const BProb &q = P[p];
-    tri_chunk_block<T>((const CT *)q.t2, (CT *)q.t2, q.tpiv, q.dxe, q.dye, q.nx, q.ny, q.nz, (q.nz + TL - 1) / TL, LX,
-                       q.ax, q.ay, q.c0, q.gz, q.hz2, blockIdx.x - off[p], smraw);
+    if constexpr (std::is_same<T, float>::value)
+        tri_chunk_block<T, float2>((const CT *)q.t2, (CT *)q.t2, q.tpiv32, q.dxe, q.dye, q.nx, q.ny, q.nz,
+                                   (q.nz + TL - 1) / TL, LX, q.ax, q.ay, q.c0, q.gz, q.hz2, blockIdx.x - off[p], smraw);
+    else
+        tri_chunk_block<T, double2>((const CT *)q.t2, (CT *)q.t2, q.tpiv, q.dxe, q.dye, q.nx, q.ny, q.nz,
+                                    (q.nz + TL - 1) / TL, LX, q.ax, q.ay, q.c0, q.gz, q.hz2, blockIdx.x - off[p], smraw);
 }
 
 // ---------------------------------------------------------------------------------------------- matvec

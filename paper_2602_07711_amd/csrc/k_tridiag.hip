@@ -9,7 +9,7 @@
 // threads own consecutive i, so every access of a wavefront at a given l is one contiguous 64-element run.
 // The forward sweep reads the right-hand side from `in` (which may be r itself), writes the eliminated
 // right-hand side to r and the reciprocal pivots to `cp`; the backward sweep reads both and overwrites r with
-// the solution. Loads are issued UNR levels ahead of use.
+// the solution.
 //
 // Partitioned form (k_tridiag_chunk): each line's rows are split into chunks of TL rows, one thread per chunk,
 // with the chunk held in registers. The reciprocal pivots depend only on the line's shift b, so the pivot
@@ -24,9 +24,11 @@ namespace helm {
 
 namespace {
 
-// reciprocal pivot entering each chunk: piv[k * lines + line] = 1/pivot_{k TL - 1} (k >= 1), 0 for k = 0
+// reciprocal pivot entering each chunk: piv[k * lines + line] = 1/pivot_{k TL - 1} (k >= 1), 0 for k = 0; piv32 (if
+// given) receives the same table rounded to complex64 for the FP32 z-solve
 __global__ void k_tri_pivots(const double2 *__restrict__ dx, const double2 *__restrict__ dy, int nx, int ny, int nz,
-                             double ax, double ay, double c0, double2 g, double zi, double2 *__restrict__ piv) {
+                             double ax, double ay, double c0, double2 g, double zi, double2 *__restrict__ piv,
+                             float2 *__restrict__ piv32) {
     const long long lines = (long long)nx * ny;
     const long long line = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (line >= lines) return;
@@ -35,27 +37,32 @@ __global__ void k_tri_pivots(const double2 *__restrict__ dx, const double2 *__re
     const double2 b = make_double2(ax * ex.x + ay * ey.x + c0, ax * ex.y + ay * ey.y);
     double2 inv = make_double2(0.0, 0.0);
     piv[line] = inv;
+    if (piv32) piv32[line] = make_float2(0.f, 0.f);
     for (int l = 0; l < nz; ++l) {
         double2 d = b;
         if (l == 0 || l == nz - 1) { d.x = (d.x + g.x) * zi; d.y = (d.y + g.y) * zi; }
         if (l > 0) { d.x -= inv.x; d.y -= inv.y; }
         inv = crecip(d);
-        if ((l + 1) % TL == 0 && l + 1 < nz) piv[(long long)((l + 1) / TL) * lines + line] = inv;
+        if ((l + 1) % TL == 0 && l + 1 < nz) {
+            const long long o = (long long)((l + 1) / TL) * lines + line;
+            piv[o] = inv;
+            if (piv32) piv32[o] = make_float2((float)inv.x, (float)inv.y);
+        }
     }
 }
 
-template <typename T>
+template <typename T, typename PT>
 __global__ __launch_bounds__(1024) void k_tridiag_chunk(const typename c2<T>::t *in, typename c2<T>::t *out,
-                                                        const double2 *__restrict__ piv,
+                                                        const PT *__restrict__ piv,
                                                         const double2 *__restrict__ dx, const double2 *__restrict__ dy,
                                                         int nx, int ny, int nz, int P, int LX, double ax, double ay,
                                                         double c0, double2 gz, double scale, double zi) {
     extern __shared__ unsigned char smraw[];
-    tri_chunk_block<T>(in, out, piv, dx, dy, nx, ny, nz, P, LX, ax, ay, c0, gz, scale, blockIdx.x, smraw, zi);
+    tri_chunk_block<T, PT>(in, out, piv, dx, dy, nx, ny, nz, P, LX, ax, ay, c0, gz, scale, blockIdx.x, smraw, zi);
 }
 
-template <typename T>
-hipError_t launch_chunk(const typename c2<T>::t *in, typename c2<T>::t *out, const double2 *piv, const double2 *dx,
+template <typename T, typename PT>
+hipError_t launch_chunk(const typename c2<T>::t *in, typename c2<T>::t *out, const PT *piv, const double2 *dx,
                         const double2 *dy, int nx, int ny, int nz, double ax, double ay, double c0, double2 gz,
                         double scale, hipStream_t s, double zi) {
     const int P = (nz + TL - 1) / TL;
@@ -66,8 +73,8 @@ hipError_t launch_chunk(const typename c2<T>::t *in, typename c2<T>::t *out, con
     const long long lines = (long long)nx * ny;
     const unsigned grid = (unsigned)((lines + LX - 1) / LX);
     const size_t sm = 2 * sizeof(typename c2<T>::t) * (size_t)P * LX;
-    hipLaunchKernelGGL(k_tridiag_chunk<T>, dim3(grid), dim3(LX * P), sm, s, in, out, piv, dx, dy, nx, ny, nz, P, LX,
-                       ax, ay, c0, gz, scale, zi);
+    hipLaunchKernelGGL((k_tridiag_chunk<T, PT>), dim3(grid), dim3(LX * P), sm, s, in, out, piv, dx, dy, nx, ny, nz, P,
+                       LX, ax, ay, c0, gz, scale, zi);
     return hipGetLastError();
 }
 
@@ -76,23 +83,23 @@ hipError_t launch_chunk(const typename c2<T>::t *in, typename c2<T>::t *out, con
 int tri_chunks(int nz) { return (nz + TL - 1) / TL; }
 
 hipError_t launch_tri_pivots(const double2 *dx, const double2 *dy, int nx, int ny, int nz, double ax, double ay,
-                             double c0, double2 gz, double2 *piv, hipStream_t s, double zi) {
+                             double c0, double2 gz, double2 *piv, float2 *piv32, hipStream_t s, double zi) {
     const long long lines = (long long)nx * ny;
     hipLaunchKernelGGL(k_tri_pivots, dim3((unsigned)((lines + 255) / 256)), dim3(256), 0, s, dx, dy, nx, ny, nz, ax,
-                       ay, c0, gz, zi, piv);
+                       ay, c0, gz, zi, piv, piv32);
     return hipGetLastError();
 }
 
 hipError_t launch_tridiag_chunk_z64(const double2 *in, double2 *out, const double2 *piv, const double2 *dx,
                                     const double2 *dy, int nx, int ny, int nz, double ax, double ay, double c0,
                                     double2 gz, double scale, hipStream_t s, double zi) {
-    return launch_chunk<double>(in, out, piv, dx, dy, nx, ny, nz, ax, ay, c0, gz, scale, s, zi);
+    return launch_chunk<double, double2>(in, out, piv, dx, dy, nx, ny, nz, ax, ay, c0, gz, scale, s, zi);
 }
 
-hipError_t launch_tridiag_chunk_z32(const float2 *in, float2 *out, const double2 *piv, const double2 *dx,
+hipError_t launch_tridiag_chunk_z32(const float2 *in, float2 *out, const float2 *piv, const double2 *dx,
                                     const double2 *dy, int nx, int ny, int nz, double ax, double ay, double c0,
                                     double2 gz, double scale, hipStream_t s, double zi) {
-    return launch_chunk<float>(in, out, piv, dx, dy, nx, ny, nz, ax, ay, c0, gz, scale, s, zi);
+    return launch_chunk<float, float2>(in, out, piv, dx, dy, nx, ny, nz, ax, ay, c0, gz, scale, s, zi);
 }
 
 }  // namespace helm
