@@ -155,6 +155,16 @@ helm_status helm_matvec(helm_ctx *ctx, const void *x_dev, void *y_dev);
  * (HELM_EUNSUPPORTED otherwise). */
 helm_status helm_precond_apply(helm_ctx *ctx, const void *y_dev, void *z_dev, int kind, int fp32);
 
+/* For callers that cannot allocate device memory (code under stream capture, tight serving loops, harnesses that
+ * forbid allocation): the FP32 EigT preconditioner of helm_precond_apply(ctx, y_dev, z_dev, HELM_PREC_EIGT, 1)
+ * (same kernels, same results) without any allocation inside the call. Its two complex64 staging vectors live in one
+ * static device array of the library (32 MiB, held by every device the library runs on until the process ends), so
+ * n = Nx*Ny*Nz must not exceed 2^21 (HELM_EINVAL otherwise). Every call on a device shares that device's array:
+ * calls that overlap on one device (two streams or two host threads) race. y_dev, z_dev: n complex128 each,
+ * caller-owned; they may be the same buffer. Its launches are not counted by the per-kernel timing. HELM_EDEVICE if
+ * the array's device address cannot be resolved. */
+helm_status helm_precond_apply_noalloc(helm_ctx *ctx, const void *y_dev, void *z_dev);
+
 /* Solve A x = F by restarted (F)GMRES preconditioned on the right by M (Sec. 3.1, Sec. 4, Sec. 5).
  * F_dev: n complex128. x_dev: n complex128, initial guess on entry when opts->x0_given, solution on exit.
  * The Krylov workspace ((m+1) + (flexible ? m : 0) vectors of n complex128) is allocated on the first solve

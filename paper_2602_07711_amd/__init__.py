@@ -15,6 +15,7 @@ from .helm import (  # noqa: F401
     helm_gmres_solve,
     helm_matvec,
     helm_precond_apply,
+    helm_precond_apply_noalloc,
     helm_profile_enable,
     helm_profile_read,
     helm_rhs,

@@ -25,7 +25,7 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"),
 ]
-SOURCES = ["eig1d.cpp", "api.cpp", "k_stencil.hip", "k_gemm.hip", "k_tridiag.hip", "k_krylov.hip", "k_pfft.hip", "batch.cpp", "k_batch.hip", "k_cnn.hip", "cnn.cpp"]
+SOURCES = ["eig1d.cpp", "api.cpp", "k_stencil.hip", "k_gemm.hip", "k_tridiag.hip", "k_krylov.hip", "k_pfft.hip", "batch.cpp", "k_batch.hip", "k_cnn.hip", "cnn.cpp", "noalloc.hip"]
 
 
 def _compile(src: str) -> str:

@@ -605,6 +605,23 @@ struct Timer {
 
 helm_status helm::ctx_tri_pivots(Ctx &c) { return ensure_tpiv(c, c.dxe, c.dye, &c.tpiv_eig); }
 
+// The FP32 EigT chain of eigt_apply with caller-given complex64 staging vectors t1f, t2f (n entries each) and
+// direct launches: it allocates nothing and its launches are not counted by the per-kernel timing. The chunk
+// pivots come from the table that helm_setup builds.
+helm_status helm::eigt32_apply_ws(Ctx &c, const double2 *y, double2 *z, float2 *t1f, float2 *t2f) {
+    if (!c.tpiv_eig.f) { c.err = "the context has no z-solve pivot table"; return HELM_EUNSUPPORTED; }
+    const FoldDesc fx = fold_x(c), fy = fold_y(c);
+    const double2 gz = d2(c.gamma[2]);
+    prof_gap(c);
+    HIP_TRY(launch_fold_z32_in64(FOLD_XF, fx, y, c.fx32.fs, c.fx32.fa, t1f, c.stream, c.gemm_cfg[2]));
+    HIP_TRY(launch_fold_z32(FOLD_YF, fy, t1f, c.fy32.fs, c.fy32.fa, t2f, c.stream, c.gemm_cfg[3]));
+    HIP_TRY(launch_tridiag_chunk_z32(t2f, t2f, c.tpiv_eig.f, c.dxe, c.dye, c.nx, c.ny, c.nz, c.ax, c.ay, c.c0, gz,
+                                     c.hz * c.hz, c.stream, 1.0 / c.zeta));
+    HIP_TRY(launch_fold_z32(FOLD_YI, fy, t2f, c.fy32.is, c.fy32.ia, t1f, c.stream, c.gemm_cfg_inv[3]));
+    HIP_TRY(launch_fold_z32_out64(FOLD_XI, fx, t1f, c.fx32.is, c.fx32.ia, z, c.stream, c.gemm_cfg_inv[2]));
+    prof_gap(c);
+    return HELM_OK;
+}
 
 extern "C" {
 

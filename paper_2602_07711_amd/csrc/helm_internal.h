@@ -397,6 +397,8 @@ inline void gemm_cfg_tile(int cfg, int &bm, int &bn) {
     bn = cfg == 3 ? 128 : 64;
 }
 helm_status ctx_tri_pivots(Ctx &c);   // pivot table of the partitioned z-solve (built once per context)
+// the FP32 EigT preconditioner with caller-given staging vectors (n complex64 each); allocates nothing
+helm_status eigt32_apply_ws(Ctx &c, const double2 *y, double2 *z, float2 *t1f, float2 *t2f);
 hipError_t bl_init(const BLaunch &L, hipStream_t s);                 // ||F||, state reset (outside graphs)
 hipError_t bl_zero_x(const BLaunch &L, hipStream_t s);
 hipError_t bl_cycle(const BLaunch &L, hipStream_t s);                // one restart cycle: restart + m steps + update

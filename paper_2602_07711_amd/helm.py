@@ -71,6 +71,8 @@ def lib():
     L.helm_matvec.restype = c_int
     L.helm_precond_apply.argtypes = [c_void_p, c_void_p, c_void_p, c_int, c_int]
     L.helm_precond_apply.restype = c_int
+    L.helm_precond_apply_noalloc.argtypes = [c_void_p, c_void_p, c_void_p]
+    L.helm_precond_apply_noalloc.restype = c_int
     L.helm_gmres_solve.argtypes = [c_void_p, c_void_p, c_void_p, POINTER(helm_solve_opts), POINTER(helm_solve_info)]
     L.helm_gmres_solve.restype = c_int
     L.helm_size.argtypes = [c_void_p]
@@ -235,6 +237,15 @@ def helm_precond_apply(ctx: Context, y: torch.Tensor, z: torch.Tensor | None = N
     _check(z, torch.complex128, ctx.n, "z")
     ctx.check(lib().helm_precond_apply(ctx.ptr, c_void_p(y.data_ptr()), c_void_p(z.data_ptr()), _PREC[kind],
                                        int(bool(fp32))))
+    return z
+
+
+def helm_precond_apply_noalloc(ctx: Context, y: torch.Tensor, z: torch.Tensor) -> torch.Tensor:
+    """z = M^{-1} y by the FP32 EigT preconditioner with the library's static staging array (no device allocation
+    inside the call; n <= 2^21). z must be given."""
+    _check(y, torch.complex128, ctx.n, "y")
+    _check(z, torch.complex128, ctx.n, "z")
+    ctx.check(lib().helm_precond_apply_noalloc(ctx.ptr, c_void_p(y.data_ptr()), c_void_p(z.data_ptr())))
     return z
 
 
