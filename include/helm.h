@@ -108,7 +108,9 @@ typedef struct {
     int restarts;          /* completed cycles                                                               */
     int converged;         /* 1 if the true residual met rtol                                                */
     int hist_used;         /* entries written to resid_hist                                                  */
-    int reorths;           /* Arnoldi steps that needed a second Gram-Schmidt pass                           */
+    int reorths;           /* Arnoldi steps that took a second Gram-Schmidt pass: those whose orthogonalised
+                              vector keeps at most 1e-2 of the squared norm (||y - V h||^2 <= 1e-2 ||y||^2); the
+                              environment variable HELM_CGS_REORTH (a number in (0, 1)) replaces 1e-2          */
     double relres_est;     /* last Givens residual estimate / ||F||                                          */
     double relres_true;    /* ||F - A x|| / ||F|| at exit                                                    */
     double t_ms[6];        /* device time per phase: matvec, preconditioner, Arnoldi (dots + update),

@@ -603,6 +603,16 @@ struct Timer {
 
 }  // namespace
 
+double helm::cgs_reorth() {
+    const char *v = std::getenv("HELM_CGS_REORTH");
+    if (v) {
+        char *end = nullptr;
+        const double t = std::strtod(v, &end);
+        if (end != v && t > 0.0 && t < 1.0) return t;
+    }
+    return CGS_REORTH;
+}
+
 helm_status helm::ctx_tri_pivots(Ctx &c) { return ensure_tpiv(c, c.dxe, c.dye, &c.tpiv_eig); }
 
 // The FP32 EigT chain of eigt_apply with caller-given complex64 staging vectors t1f, t2f (n entries each) and
@@ -1077,6 +1087,7 @@ helm_status helm_gmres_solve(helm_ctx *ctx, const void *F_dev, void *x_dev, cons
     }
     helm_solve_info inf{};
     const bool flex = opts->flexible != 0;
+    const double reorth = cgs_reorth();
     // FGMRES with an FP32 preconditioner keeps Z in complex64: its vectors are FP32 results, so this is exact
     const bool zf32 = flex && opts->prec_fp32 && opts->prec != HELM_PREC_NONE;
     ST_TRY(ensure_krylov(c, m, flex ? (zf32 ? 2 : 1) : 0));
@@ -1177,7 +1188,7 @@ helm_status helm_gmres_solve(helm_ctx *ctx, const void *F_dev, void *x_dev, cons
             ST_TRY(dots_async(c, k.V, j + 1, w));
             hipEvent_t ua = ev[8 + 2 * (j & 1)], ub = ev[9 + 2 * (j & 1)];
             HIP_TRY(hipEventRecord(ua, c.stream));
-            HIP_TRY(timed(c, HELM_K_LINCOMB, 16.0 * c.n * (j + 3), [&] { return launch_lincomb_cgs(w, k.V, k.ld, j + 1, k.red, n, c.stream); }));
+            HIP_TRY(timed(c, HELM_K_LINCOMB, 16.0 * c.n * (j + 3), [&] { return launch_lincomb_cgs(w, k.V, k.ld, j + 1, k.red, n, reorth, c.stream); }));
             ST_TRY(dots_wait(c, j + 1, hv));
             double hh = 0.0;
             for (int i = 0; i <= j; ++i) {        // the device's arithmetic, in the same order
@@ -1187,8 +1198,8 @@ helm_status helm_gmres_solve(helm_ctx *ctx, const void *F_dev, void *x_dev, cons
             const double ww = hv[j + 1].real();
             const double eta2 = ww - hh;
             double eta = 0.0;
-            if (!(eta2 > 0.5 * ww)) {
-                // cancellation: the update left u = -(y - V h) unscaled. A second pass orthogonalises and scales it,
+            if (!(eta2 > reorth * ww)) {
+                // severe cancellation: the update left u = -(y - V h) unscaled. A second pass orthogonalises and scales it,
                 // v_{j+1} = (u - V h2)/eta' = -(y - V (h - h2))/eta', with h2 = V^H u.
                 ++inf.reorths;
                 ST_TRY(dots(c, k.V, j + 1, w, hv2));

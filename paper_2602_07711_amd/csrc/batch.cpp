@@ -141,8 +141,11 @@ helm_status helm_batch_create(helm_batch **out, helm_ctx *const *ctxs, int np, i
         q.n = c.n;
         q.nx = c.nx; q.ny = c.ny; q.nz = c.nz;
         q.nblk_dots = dots_blocks(c.n);
-        if (balloc(*b, &q.V, (size_t)(m + 1) * c.n) != hipSuccess || balloc(*b, &q.Z, (size_t)m * c.n) != hipSuccess)
+        void *zb = nullptr;
+        if (balloc(*b, &q.V, (size_t)(m + 1) * c.n) != hipSuccess || hipMalloc(&zb, esz * m * c.n) != hipSuccess)
             return fail(HELM_ENOMEM, "Krylov workspace allocation failed");
+        b->allocs.push_back(zb);
+        q.Z = zb;
         void *t1 = nullptr, *t2 = nullptr;
         if (hipMalloc(&t1, esz * c.n) != hipSuccess) return fail(HELM_ENOMEM, "work allocation failed");
         b->allocs.push_back(t1);
@@ -165,6 +168,15 @@ helm_status helm_batch_create(helm_batch **out, helm_ctx *const *ctxs, int np, i
         og[2].push_back(og[2].back() + fold_tile_count(FOLD_YI, q.fy, bm[2], bn[2]));
         og[3].push_back(og[3].back() + fold_tile_count(FOLD_XI, q.fx, bm[3], bn[3]));
     }
+    // step-matvec units: consecutive problems of one context share a block (their operator is read once)
+    std::vector<int2> units;
+    std::vector<int> omvp(1, 0);
+    for (int p = 0; p < np; ++p) {
+        const bool pair = p + 1 < np && ctxs[p + 1] == ctxs[p];
+        units.push_back(make_int2(p, pair ? p + 1 : -1));
+        omvp.push_back(omvp.back() + (omv[p + 1] - omv[p]));
+        if (pair) ++p;
+    }
     BLaunch &L = b->L;
     if (balloc(*b, &b->dP, np) != hipSuccess || balloc(*b, &b->dst, np) != hipSuccess ||
         balloc(*b, &b->dprm, 1) != hipSuccess)
@@ -173,6 +185,15 @@ helm_status helm_batch_create(helm_batch **out, helm_ctx *const *ctxs, int np, i
         balloc(*b, &L.a.sn, (size_t)np * m) != hipSuccess || balloc(*b, &L.a.g, (size_t)np * (m + 1)) != hipSuccess ||
         balloc(*b, &L.a.coef, (size_t)np * (m + 1)) != hipSuccess)
         return fail(HELM_ENOMEM, "state allocation failed");
+    int2 *dunits = nullptr;
+    if (balloc(*b, &dunits, units.size()) != hipSuccess || balloc(*b, &L.off.mvp, omvp.size()) != hipSuccess)
+        return fail(HELM_ENOMEM, "offset allocation failed");
+    if (hipMemcpy(dunits, units.data(), units.size() * sizeof(int2), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(L.off.mvp, omvp.data(), omvp.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
+        return fail(HELM_EDEVICE, "offset upload failed");
+    L.units = dunits;
+    L.nunits = (int)units.size();
+    L.tot_mvp = omvp.back();
     if (balloc(*b, &L.off.mv, np + 1) != hipSuccess || balloc(*b, &L.off.tri, np + 1) != hipSuccess ||
         balloc(*b, &L.off.dot, np + 1) != hipSuccess || balloc(*b, &L.off.lc, np + 1) != hipSuccess ||
         balloc(*b, &L.off.g[0], np + 1) != hipSuccess || balloc(*b, &L.off.g[1], np + 1) != hipSuccess ||
@@ -232,7 +253,7 @@ helm_status helm_batch_solve(helm_batch *b, const void *const *F, void *const *x
         b->hP[p].F = (const double2 *)F[p];
         b->hP[p].x = (double2 *)x[p];
     }
-    BParams prm{rtol, maxit, b->m};
+    BParams prm{rtol, maxit, b->m, cgs_reorth()};
     // order after prior work on the caller's stream
     BTRY(hipEventRecord(b->ev, b->user));
     BTRY(hipStreamWaitEvent(b->stream, b->ev, 0));

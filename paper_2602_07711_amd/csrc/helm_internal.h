@@ -274,6 +274,15 @@ inline void prof_resolve(Ctx &c) {
     c.prof_last = nullptr;
 }
 
+// Classical Gram-Schmidt takes the norm of the orthogonalised vector from ||y||^2 - sum |h_i|^2, whose rounding error
+// is about eps ||y||^2. A step takes a second Gram-Schmidt pass only when that norm squared falls below
+// CGS_REORTH ||y||^2: above it the norm is accurate to ~eps / CGS_REORTH and the new basis vector's loss of
+// orthogonality is ~eps / sqrt(CGS_REORTH). (On the 128^3 four-inclusion medium one in two steps falls below half of
+// ||y||^2; a second pass for them left every iteration count and every solution unchanged to 1e-13 and cost 30%.)
+constexpr double CGS_REORTH = 1e-2;
+// the threshold in force: HELM_CGS_REORTH from the environment when it holds a number in (0, 1), else CGS_REORTH
+double cgs_reorth();
+
 // ----- batched solves: per-problem descriptors and device-side GMRES state -----
 struct BProb {                    // constant during a batched solve
     StencilParams sp;
@@ -285,7 +294,9 @@ struct BProb {                    // constant during a batched solve
     double ax, ay, c0, hz2;
     double2 gz;
     FoldDesc fx, fy;
-    double2 *V, *Z, *x;
+    double2 *V, *x;
+    void *Z;                               // FGMRES directions: complex64 with the FP32 preconditioner (its outputs
+                                           // are FP32 values, so this storage is exact), complex128 otherwise
     const double2 *F;
     void *t1, *t2;                         // preconditioner work (element type by precision)
     const double2 *tpiv;                   // pivots entering each z-chunk (the context's table)
@@ -299,9 +310,10 @@ struct BState {                   // evolves on the device
     double2 alpha;                // scale of the base vector in the next linear combination
     int active;                   // 1 while the problem takes Arnoldi steps in the current cycle
     int done;                     // converged or out of iterations
-    int converged, k, its, cycles, cancel, pad;
+    int converged, k, its, cycles, cancel;
+    int reo;                      // 1 while the current Arnoldi step takes its second Gram-Schmidt pass
 };
-struct BParams { double rtol; int maxit; int m; };
+struct BParams { double rtol; int maxit; int m; double reorth; };
 struct BArrays {                  // per-problem small arrays, problem p at p * stride
     double2 *H;                   // (m+1) x m Hessenberg (rotated), row-major
     double *cs;                   // m
@@ -309,6 +321,8 @@ struct BArrays {                  // per-problem small arrays, problem p at p * 
 };
 struct BOffsets {                 // prefix sums of blocks/tiles per problem for each grouped launch
     int *mv, *tri, *dot, *lc;     // np + 1 each
+    int *mvp;                     // nunits + 1: blocks of the step matvec per unit (one problem or two sharing an
+                                  // operator)
     long long *g[4];              // tiles of the x forward, y forward, y inverse and x inverse transforms
 };
 
@@ -375,7 +389,7 @@ hipError_t launch_lincomb(double2 *out, const double2 *base, double2 alpha, cons
 // w <- -(w - V h)/eta with h = red[0..nv-1], eta^2 = red[nv].x - sum |h_i|^2 computed on the device (unscaled when
 // eta^2 <= red[nv].x / 2, which the caller detects and corrects with a second pass)
 hipError_t launch_lincomb_cgs(double2 *w, const double2 *V, long long ldv, int nv, const double2 *red, long long n,
-                              hipStream_t s);   // out = alpha base + sum coef_i V_i
+                              double reorth, hipStream_t s);   // out = alpha base + sum coef_i V_i
 hipError_t launch_fill_zero(double2 *x, long long n, hipStream_t s);
 
 // grouped (batched) launches; see k_batch.hip
@@ -386,7 +400,10 @@ struct BLaunch {
     BArrays a;
     BOffsets off;                 // device arrays
     int np, m, order, fp32;
+    const int2 *units;                          // device: the step matvec's units (p, p2), p2 = -1 when alone
+    int nunits;
     int tot_mv, tot_tri, tot_dot, tot_lc;       // total blocks per grouped launch
+    int tot_mvp;                                // total blocks of the step matvec over the units
     long long tot_g[4];                         // total transform tiles per role
     int gemm_grid;                              // persistent GEMM grid size
     int cfg[4];                                 // tile configurations of the four transform roles

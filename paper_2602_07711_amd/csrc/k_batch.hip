@@ -64,8 +64,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
             fold_tile<FOLD_YI, CT, CT, CT, T, BM, BN, BK>((const CT *)q.t2, (const CT *)q.yis, (const CT *)q.yia,
                                                           (CT *)q.t1, q.fy, lt);
         else
-            fold_tile<FOLD_XI, CT, CT, double2, T, BM, BN, BK>((const CT *)q.t1, (const CT *)q.xis, (const CT *)q.xia,
-                                                               q.Z + (long long)j * q.n, q.fx, lt);
+            fold_tile<FOLD_XI, CT, CT, CT, T, BM, BN, BK>((const CT *)q.t1, (const CT *)q.xis, (const CT *)q.xia,
+                                                          (CT *)q.Z + (long long)j * q.n, q.fx, lt);
     }
 }
 
@@ -86,8 +86,9 @@ __global__ __launch_bounds__(1024) void k_b_tridiag(const BProb *__restrict__ P,
 }
 
 // ---------------------------------------------------------------------------------------------- matvec
-// mode 0: restart, V_0 = F - A x (problems not done); mode 1: step j, V_{j+1} = V_j - A Z_j (active problems)
-template <int ORDER>
+// mode 0: restart, V_0 = F - A x (problems not done); mode 1: step j, V_{j+1} = V_j - A Z_j (active problems);
+// ZT: element type of the Z basis (complex64 with the FP32 preconditioner)
+template <int ORDER, typename ZT>
 __global__ __launch_bounds__(NT) void k_b_matvec(const BProb *__restrict__ P, const BState *__restrict__ st,
                                                   const int *__restrict__ off, int np, int mode, int j) {
     const int p = find_prob(off, np, blockIdx.x);
@@ -97,17 +98,50 @@ __global__ __launch_bounds__(NT) void k_b_matvec(const BProb *__restrict__ P, co
     if (mode == 0)
         matvec_tile<ORDER, true>(q.x, q.k2, q.fld, q.F, q.V, q.sp, lb);
     else
-        matvec_tile<ORDER, true>(q.Z + (long long)j * q.n, q.k2, q.fld, q.V + (long long)j * q.n, q.V + (long long)(j + 1) * q.n,
-                                 q.sp, lb);
+        matvec_tile<ORDER, true, ZT>((const ZT *)q.Z + (long long)j * q.n, q.k2, q.fld, q.V + (long long)j * q.n,
+                                     q.V + (long long)(j + 1) * q.n, q.sp, lb);
+}
+
+// step j with right-hand sides paired on a shared operator: a unit is one problem or two problems of the same
+// context (same k^2 and field block, e.g. two incident directions on one medium); the block reads the operator's
+// planes once for both. Problems that are not active are left out of their unit.
+template <int ORDER, typename ZT>
+__global__ __launch_bounds__(NT) void k_b_matvec_pair(const BProb *__restrict__ P, const BState *__restrict__ st,
+                                                       const int2 *__restrict__ units, const int *__restrict__ off,
+                                                       int nunits, int j) {
+    const int u = find_prob(off, nunits, blockIdx.x);
+    const int2 pu = units[u];
+    const bool a1 = st[pu.x].active != 0;
+    const bool a2 = pu.y >= 0 && st[pu.y].active != 0;
+    if (!a1 && !a2) return;
+    const ZT *xs[2];
+    const double2 *Fs[2];
+    double2 *ys[2];
+    int nr = 0;
+    const int ps[2] = {pu.x, pu.y};
+    const bool as[2] = {a1, a2};
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+        if (as[r]) {
+            const BProb &q = P[ps[r]];
+            xs[nr] = (const ZT *)q.Z + (long long)j * q.n;
+            Fs[nr] = q.V + (long long)j * q.n;
+            ys[nr] = q.V + (long long)(j + 1) * q.n;
+            ++nr;
+        }
+    const BProb &q = P[a1 ? pu.x : pu.y];
+    matvec_tile_n<ORDER, true, ZT, false, 2>(xs, q.k2, q.fld, Fs, ys, q.sp, blockIdx.x - off[u], nr);
 }
 
 // ---------------------------------------------------------------------------------------------- inner products
-// mode 0: ||F||^2 (all problems); mode 1: ||V_0||^2 (not done); mode 2: V_{0..j}^H V_{j+1}, ||V_{j+1}||^2 (active)
+// mode 0: ||F||^2 (all problems); mode 1: ||V_0||^2 (not done); mode 2: V_{0..j}^H V_{j+1}, ||V_{j+1}||^2 (active);
+// mode 3: the same for the second Gram-Schmidt pass (active problems whose step cancelled)
 __global__ __launch_bounds__(256) void k_b_dots(const BProb *__restrict__ P, const BState *__restrict__ st,
                                                 const int *__restrict__ off, int np, int mode, int j) {
     const int p = find_prob(off, np, blockIdx.x);
     if (mode == 1 && st[p].done) return;
     if (mode == 2 && !st[p].active) return;
+    if (mode == 3 && !(st[p].active && st[p].reo)) return;
     const BProb &q = P[p];
     const long long lb = blockIdx.x - off[p];
     if (mode == 0) dots_chunk(nullptr, q.n, 0, q.F, q.n, q.part, lb);
@@ -190,37 +224,16 @@ __global__ __launch_bounds__(256) void k_b_restart(const BProb *__restrict__ P, 
     st[p] = s;
 }
 
-// one block per problem: reduce V^H y and ||y||^2, build column j of H (shifted Arnoldi: -h + e_j, eta),
-// apply the previous rotations, make the new one, update g, test convergence, and set the coefficients of
-// v_{j+1} = -(y - V h)/eta.
-__global__ __launch_bounds__(256) void k_b_arnoldi(const BProb *__restrict__ P, BState *__restrict__ st, BArrays a,
-                                                   const BParams *__restrict__ prm, int j) {
-    __shared__ double2 hv[130];
-    const int p = blockIdx.x;
-    if (!st[p].active) return;
-    const BProb &q = P[p];
-    const int m = prm->m;
-    const int nv = j + 1;
-    for (int t = 0; t <= nv; ++t) {
-        double2 r = reduce_part(q.part, q.nblk_dots, nv + 1, t);
-        if (threadIdx.x == 0) hv[t] = r;
-    }
-    if (threadIdx.x != 0) return;
-    BState s = st[p];
+// Column j of H from the orthogonalisation coefficients hv[0..j] and eta (shifted Arnoldi: -h + e_j, eta), the
+// previous rotations, the new rotation, g, the convergence test, and the coefficients of the update
+// v_{j+1} = -(y - V h)/eta. One thread.
+__device__ void arnoldi_column(BState &s, BArrays a, int p, int m, const BParams *__restrict__ prm, int j,
+                               const double2 *hv, double eta) {
     double2 *H = a.H + (long long)p * (m + 1) * m;
     double *cs = a.cs + (long long)p * m;
     double2 *sn = a.sn + (long long)p * m;
     double2 *g = a.g + (long long)p * (m + 1);
     double2 *coef = a.coef + (long long)p * (m + 1);
-    double hh = 0.0;
-    for (int i = 0; i <= j; ++i) hh += hv[i].x * hv[i].x + hv[i].y * hv[i].y;
-    const double ww = hv[nv].x;
-    double eta2 = ww - hh;
-    // cancellation (eta^2 <= ||y||^2 / 2): eta is not accurate enough to scale v_{j+1}, and this path has no second
-    // Gram-Schmidt pass, so the cycle ends here and the restart continues from the true residual
-    const bool cancelled = !(eta2 > 0.5 * ww);
-    if (cancelled) s.cancel += 1;
-    const double eta = eta2 > 0.0 ? sqrt(eta2) : 0.0;
     for (int i = 0; i <= j; ++i) H[(long long)i * m + j] = make_double2(-hv[i].x, -hv[i].y);
     H[(long long)j * m + j].x += 1.0;
     for (int i = 0; i < j; ++i) {
@@ -251,12 +264,78 @@ __global__ __launch_bounds__(256) void k_b_arnoldi(const BProb *__restrict__ P, 
     s.k = j + 1;
     const double res = cabs2(g[j + 1]);
     s.relres_est = res / s.bnorm;
-    if (eta == 0.0 || cancelled || res <= prm->rtol * s.bnorm || s.its >= prm->maxit || j + 1 == m ||
-        !isfinite(res)) {
+    if (eta == 0.0 || res <= prm->rtol * s.bnorm || s.its >= prm->maxit || j + 1 == m || !isfinite(res)) {
         s.active = 0;
     } else {
         for (int i = 0; i <= j; ++i) coef[i] = make_double2(hv[i].x / eta, hv[i].y / eta);
         s.alpha = make_double2(-1.0 / eta, 0.0);
+    }
+}
+
+// one block per problem: reduce V^H y and ||y||^2 and finish the step (arnoldi_column). With severe cancellation
+// (||y - V h||^2 = ||y||^2 - sum |h_i|^2 <= reorth ||y||^2, reorth = cgs_reorth()) that norm is not accurate enough: the step takes a
+// second Gram-Schmidt pass instead. The update then leaves u = -(y - V h) unscaled (coefficients h, alpha = -1), and
+// k_b_arnoldi2 finishes the step from the inner products of u.
+__global__ __launch_bounds__(256) void k_b_arnoldi(const BProb *__restrict__ P, BState *__restrict__ st, BArrays a,
+                                                   const BParams *__restrict__ prm, int j) {
+    __shared__ double2 hv[130];
+    const int p = blockIdx.x;
+    if (!st[p].active) return;
+    const BProb &q = P[p];
+    const int m = prm->m;
+    const int nv = j + 1;
+    for (int t = 0; t <= nv; ++t) {
+        double2 r = reduce_part(q.part, q.nblk_dots, nv + 1, t);
+        if (threadIdx.x == 0) hv[t] = r;
+    }
+    if (threadIdx.x != 0) return;
+    BState s = st[p];
+    double hh = 0.0;
+    for (int i = 0; i <= j; ++i) hh += hv[i].x * hv[i].x + hv[i].y * hv[i].y;
+    const double ww = hv[nv].x;
+    const double eta2 = ww - hh;
+    s.reo = 0;
+    if (!(eta2 > prm->reorth * ww) && isfinite(eta2)) {
+        s.cancel += 1;
+        s.reo = 1;
+        double2 *coef = a.coef + (long long)p * (m + 1);
+        for (int i = 0; i <= j; ++i) coef[i] = hv[i];
+        s.alpha = make_double2(-1.0, 0.0);
+    } else {
+        arnoldi_column(s, a, p, m, prm, j, hv, eta2 > 0.0 ? sqrt(eta2) : 0.0);
+    }
+    st[p] = s;
+}
+
+// the second pass of a cancelled step: h2 = V^H u and ||u||^2 (u = -(y - V h) in V_{j+1}); then
+// v_{j+1} = (u - V h2)/eta' = -(y - V (h - h2))/eta' with eta'^2 = ||u||^2 - sum |h2_i|^2
+__global__ __launch_bounds__(256) void k_b_arnoldi2(const BProb *__restrict__ P, BState *__restrict__ st, BArrays a,
+                                                    const BParams *__restrict__ prm, int j) {
+    __shared__ double2 h2[130];
+    __shared__ double2 hv[130];
+    const int p = blockIdx.x;
+    if (!st[p].active || !st[p].reo) return;
+    const BProb &q = P[p];
+    const int m = prm->m;
+    const int nv = j + 1;
+    for (int t = 0; t <= nv; ++t) {
+        double2 r = reduce_part(q.part, q.nblk_dots, nv + 1, t);
+        if (threadIdx.x == 0) h2[t] = r;
+    }
+    if (threadIdx.x != 0) return;
+    BState s = st[p];
+    double2 *coef = a.coef + (long long)p * (m + 1);
+    double hh = 0.0;
+    for (int i = 0; i <= j; ++i) {
+        hv[i] = make_double2(coef[i].x - h2[i].x, coef[i].y - h2[i].y);
+        hh += h2[i].x * h2[i].x + h2[i].y * h2[i].y;
+    }
+    const double e2 = h2[nv].x - hh;
+    const double eta = e2 > 0.0 ? sqrt(e2) : 0.0;
+    arnoldi_column(s, a, p, m, prm, j, hv, eta);
+    if (s.active) {                  // the correction of u (k_b_lincomb kind 3)
+        for (int i = 0; i <= j; ++i) coef[i] = make_double2(-h2[i].x / eta, -h2[i].y / eta);
+        s.alpha = make_double2(1.0 / eta, 0.0);
     }
     st[p] = s;
 }
@@ -289,24 +368,66 @@ __global__ void k_b_trisolve(BState *__restrict__ st, BArrays a, const BParams *
 
 // ---------------------------------------------------------------------------------------------- linear combinations
 constexpr int BLC_EPT = 4;
+__device__ __forceinline__ double2 wide_b(const double2 *p) { return ld_stream(p); }
+__device__ __forceinline__ double2 wide_b(const float2 *p) {
+    const float2 v = *p;
+    return make_double2((double)v.x, (double)v.y);
+}
+// acc += sum_{i<nv} c_i V_i over BLC_EPT elements per thread, four vectors per round (16 loads in flight)
+template <typename VT>
+__device__ __forceinline__ void b_accum(double2 *acc, const bool *ok, long long start, const VT *V, long long ldv,
+                                        int nv, const double2 *coef) {
+    int i = 0;
+    for (; i + 4 <= nv; i += 4) {
+        double2 v[4][BLC_EPT];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int e = 0; e < BLC_EPT; ++e) {
+                const long long idx = start + (long long)e * 256;
+                v[q][e] = ok[e] ? wide_b(V + (long long)(i + q) * ldv + idx) : make_double2(0.0, 0.0);
+            }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const double2 c = coef[i + q];
+#pragma unroll
+            for (int e = 0; e < BLC_EPT; ++e) {
+                acc[e].x += c.x * v[q][e].x - c.y * v[q][e].y;
+                acc[e].y += c.x * v[q][e].y + c.y * v[q][e].x;
+            }
+        }
+    }
+    for (; i < nv; ++i) {
+        const double2 c = coef[i];
+        double2 v[BLC_EPT];
+#pragma unroll
+        for (int e = 0; e < BLC_EPT; ++e) {
+            const long long idx = start + (long long)e * 256;
+            v[e] = ok[e] ? wide_b(V + (long long)i * ldv + idx) : make_double2(0.0, 0.0);
+        }
+#pragma unroll
+        for (int e = 0; e < BLC_EPT; ++e) {
+            acc[e].x += c.x * v[e].x - c.y * v[e].y;
+            acc[e].y += c.x * v[e].y + c.y * v[e].x;
+        }
+    }
+}
+
 // kind 0: V_0 *= alpha (active); kind 1: V_{j+1} = alpha V_{j+1} + sum_{i<=j} c_i V_i (active);
-// kind 2: x += sum_{i<k} c_i Z_i (problems that iterated in this cycle and are not done)
+// kind 2: x += sum_{i<k} c_i Z_i (problems that iterated in this cycle and are not done); kind 3: kind 1 for the
+// second Gram-Schmidt pass (active problems whose step cancelled); ZT: element type of Z
+template <typename ZT>
 __global__ __launch_bounds__(256) void k_b_lincomb(const BProb *__restrict__ P, const BState *__restrict__ st,
                                                    BArrays a, const BParams *__restrict__ prm,
                                                    const int *__restrict__ off, int np, int kind, int j) {
     const int p = find_prob(off, np, blockIdx.x);
     const BState &s = st[p];
-    if (kind == 2 ? (s.done || s.k == 0) : !s.active) return;
+    if (kind == 2 ? (s.done || s.k == 0) : (!s.active || (kind == 3 && !s.reo))) return;
     const BProb &q = P[p];
     const int m = prm->m;
     const double2 *coef = a.coef + (long long)p * (m + 1);
-    double2 *out;
-    const double2 *V;
-    int nv;
-    double2 alpha = s.alpha;
-    if (kind == 0) { out = q.V; V = q.V; nv = 0; }
-    else if (kind == 1) { out = q.V + (long long)(j + 1) * q.n; V = q.V; nv = j + 1; }
-    else { out = q.x; V = q.Z; nv = s.k; alpha = make_double2(1.0, 0.0); }
+    double2 *out = kind == 2 ? q.x : (kind == 0 ? q.V : q.V + (long long)(j + 1) * q.n);
+    const double2 alpha = kind == 2 ? make_double2(1.0, 0.0) : s.alpha;
     const long long start = (long long)(blockIdx.x - off[p]) * (256 * BLC_EPT) + threadIdx.x;
     double2 acc[BLC_EPT];
     bool ok[BLC_EPT];
@@ -317,21 +438,8 @@ __global__ __launch_bounds__(256) void k_b_lincomb(const BProb *__restrict__ P, 
         acc[e] = make_double2(0.0, 0.0);
         if (ok[e]) acc[e] = cmulb(alpha, out[idx]);
     }
-    for (int i = 0; i < nv; ++i) {
-        const double2 *vi = V + (long long)i * q.n;
-        const double2 c = coef[i];
-        double2 v[BLC_EPT];
-#pragma unroll
-        for (int e = 0; e < BLC_EPT; ++e) {
-            const long long idx = start + (long long)e * 256;
-            v[e] = ok[e] ? ld_stream(vi + idx) : make_double2(0.0, 0.0);
-        }
-#pragma unroll
-        for (int e = 0; e < BLC_EPT; ++e) {
-            acc[e].x += c.x * v[e].x - c.y * v[e].y;
-            acc[e].y += c.x * v[e].y + c.y * v[e].x;
-        }
-    }
+    if (kind == 1 || kind == 3) b_accum(acc, ok, start, q.V, q.n, j + 1, coef);
+    else if (kind == 2) b_accum(acc, ok, start, (const ZT *)q.Z, q.n, s.k, coef);
 #pragma unroll
     for (int e = 0; e < BLC_EPT; ++e) {
         const long long idx = start + (long long)e * 256;
@@ -369,13 +477,37 @@ template <typename T> hipError_t precond_steps(const BLaunch &L, hipStream_t s, 
     return hipGetLastError();
 }
 
-hipError_t matvec_step(const BLaunch &L, hipStream_t s, int mode, int j) {
+template <typename ZT> hipError_t matvec_step_t(const BLaunch &L, hipStream_t s, int mode, int j) {
+    if (mode == 1) {
+        if (L.order == 6)
+            hipLaunchKernelGGL((k_b_matvec_pair<6, ZT>), dim3(L.tot_mvp), dim3(64, TY), 0, s, L.P, L.st, L.units,
+                               L.off.mvp, L.nunits, j);
+        else if (L.order == 4)
+            hipLaunchKernelGGL((k_b_matvec_pair<4, ZT>), dim3(L.tot_mvp), dim3(64, TY), 0, s, L.P, L.st, L.units,
+                               L.off.mvp, L.nunits, j);
+        else
+            hipLaunchKernelGGL((k_b_matvec_pair<2, ZT>), dim3(L.tot_mvp), dim3(64, TY), 0, s, L.P, L.st, L.units,
+                               L.off.mvp, L.nunits, j);
+        return hipGetLastError();
+    }
     if (L.order == 6)
-        hipLaunchKernelGGL(k_b_matvec<6>, dim3(L.tot_mv), dim3(64, TY), 0, s, L.P, L.st, L.off.mv, L.np, mode, j);
+        hipLaunchKernelGGL((k_b_matvec<6, ZT>), dim3(L.tot_mv), dim3(64, TY), 0, s, L.P, L.st, L.off.mv, L.np, mode, j);
     else if (L.order == 4)
-        hipLaunchKernelGGL(k_b_matvec<4>, dim3(L.tot_mv), dim3(64, TY), 0, s, L.P, L.st, L.off.mv, L.np, mode, j);
+        hipLaunchKernelGGL((k_b_matvec<4, ZT>), dim3(L.tot_mv), dim3(64, TY), 0, s, L.P, L.st, L.off.mv, L.np, mode, j);
     else
-        hipLaunchKernelGGL(k_b_matvec<2>, dim3(L.tot_mv), dim3(64, TY), 0, s, L.P, L.st, L.off.mv, L.np, mode, j);
+        hipLaunchKernelGGL((k_b_matvec<2, ZT>), dim3(L.tot_mv), dim3(64, TY), 0, s, L.P, L.st, L.off.mv, L.np, mode, j);
+    return hipGetLastError();
+}
+hipError_t matvec_step(const BLaunch &L, hipStream_t s, int mode, int j) {
+    return L.fp32 ? matvec_step_t<float2>(L, s, mode, j) : matvec_step_t<double2>(L, s, mode, j);
+}
+hipError_t lincomb_step(const BLaunch &L, hipStream_t s, int kind, int j) {
+    if (L.fp32)
+        hipLaunchKernelGGL(k_b_lincomb<float2>, dim3(L.tot_lc), dim3(256), 0, s, L.P, L.st, L.a, L.prm, L.off.lc, L.np,
+                           kind, j);
+    else
+        hipLaunchKernelGGL(k_b_lincomb<double2>, dim3(L.tot_lc), dim3(256), 0, s, L.P, L.st, L.a, L.prm, L.off.lc,
+                           L.np, kind, j);
     return hipGetLastError();
 }
 
@@ -398,8 +530,7 @@ hipError_t bl_restart(const BLaunch &L, hipStream_t s) {
     if ((e = matvec_step(L, s, 0, 0)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_b_dots, dim3(L.tot_dot), dim3(256), 0, s, L.P, L.st, L.off.dot, L.np, 1, 0);
     hipLaunchKernelGGL(k_b_restart, dim3(L.np), dim3(256), 0, s, L.P, L.st, L.a, L.prm);
-    hipLaunchKernelGGL(k_b_lincomb, dim3(L.tot_lc), dim3(256), 0, s, L.P, L.st, L.a, L.prm, L.off.lc, L.np, 0, 0);
-    return hipGetLastError();
+    return lincomb_step(L, s, 0, 0);
 }
 
 hipError_t bl_cycle(const BLaunch &L, hipStream_t s) {
@@ -411,11 +542,14 @@ hipError_t bl_cycle(const BLaunch &L, hipStream_t s) {
         if ((e = matvec_step(L, s, 1, j)) != hipSuccess) return e;
         hipLaunchKernelGGL(k_b_dots, dim3(L.tot_dot), dim3(256), 0, s, L.P, L.st, L.off.dot, L.np, 2, j);
         hipLaunchKernelGGL(k_b_arnoldi, dim3(L.np), dim3(256), 0, s, L.P, L.st, L.a, L.prm, j);
-        hipLaunchKernelGGL(k_b_lincomb, dim3(L.tot_lc), dim3(256), 0, s, L.P, L.st, L.a, L.prm, L.off.lc, L.np, 1, j);
+        if ((e = lincomb_step(L, s, 1, j)) != hipSuccess) return e;
+        // second Gram-Schmidt pass of the steps that cancelled (every block of the other problems returns at once)
+        hipLaunchKernelGGL(k_b_dots, dim3(L.tot_dot), dim3(256), 0, s, L.P, L.st, L.off.dot, L.np, 3, j);
+        hipLaunchKernelGGL(k_b_arnoldi2, dim3(L.np), dim3(256), 0, s, L.P, L.st, L.a, L.prm, j);
+        if ((e = lincomb_step(L, s, 3, j)) != hipSuccess) return e;
     }
     hipLaunchKernelGGL(k_b_trisolve, dim3((L.np + 63) / 64), dim3(64), 0, s, L.st, L.a, L.prm, L.np);
-    hipLaunchKernelGGL(k_b_lincomb, dim3(L.tot_lc), dim3(256), 0, s, L.P, L.st, L.a, L.prm, L.off.lc, L.np, 2, 0);
-    return hipGetLastError();
+    return lincomb_step(L, s, 2, 0);
 }
 
 }  // namespace helm

@@ -106,12 +106,12 @@ __global__ __launch_bounds__(256) void k_lincomb(double2 *out, const double2 *ba
 }
 
 // The orthogonalisation update of an Arnoldi step with its coefficients taken on the device from the reduced inner
-// products red[0..nv-1] = V_i^H w and red[nv] = ||w||^2: eta^2 = ||w||^2 - sum |h_i|^2 and, when no cancellation
-// happened (eta^2 > ||w||^2 / 2), w <- -(w - V h) / eta; otherwise w <- -(w - V h) unscaled, for the host's second
-// Gram-Schmidt pass. Every block recomputes the (uniform) coefficients, so no host round trip sits between the
+// products red[0..nv-1] = V_i^H w and red[nv] = ||w||^2: eta^2 = ||w||^2 - sum |h_i|^2 and, when no severe
+// cancellation happened (eta^2 > reorth ||w||^2), w <- -(w - V h) / eta; otherwise w <- -(w - V h) unscaled, for
+// the host's second Gram-Schmidt pass. Every block recomputes the (uniform) coefficients, so no host round trip sits between the
 // inner products and the update.
 __global__ __launch_bounds__(256) void k_lincomb_cgs(double2 *w, const double2 *__restrict__ V, long long ldv, int nv,
-                                                     const double2 *__restrict__ red, long long n) {
+                                                     const double2 *__restrict__ red, long long n, double reorth) {
     double hh = 0.0;
     for (int i = 0; i < nv; ++i) {
         const double2 r = red[i];
@@ -119,7 +119,7 @@ __global__ __launch_bounds__(256) void k_lincomb_cgs(double2 *w, const double2 *
         hh = fma(r.y, r.y, hh);
     }
     const double ww = red[nv].x, eta2 = ww - hh;
-    const double inv = eta2 > 0.5 * ww ? 1.0 / sqrt(eta2) : 1.0;
+    const double inv = eta2 > reorth * ww ? 1.0 / sqrt(eta2) : 1.0;
     const long long start = (long long)blockIdx.x * (256 * LC_EPT) + threadIdx.x;
     double2 acc[LC_EPT];
     bool ok[LC_EPT];
@@ -225,10 +225,10 @@ hipError_t launch_lincomb(double2 *out, const double2 *base, double2 alpha, cons
 }
 
 hipError_t launch_lincomb_cgs(double2 *w, const double2 *V, long long ldv, int nv, const double2 *red, long long n,
-                              hipStream_t s) {
+                              double reorth, hipStream_t s) {
     long long grid_ll = (n + 256 * LC_EPT - 1) / (256 * LC_EPT);
     int grid = (int)(grid_ll < 1 ? 1 : grid_ll);
-    hipLaunchKernelGGL(k_lincomb_cgs, dim3(grid), dim3(256), 0, s, w, V, ldv, nv, red, n);
+    hipLaunchKernelGGL(k_lincomb_cgs, dim3(grid), dim3(256), 0, s, w, V, ldv, nv, red, n, reorth);
     return hipGetLastError();
 }
 

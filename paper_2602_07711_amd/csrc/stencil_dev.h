@@ -53,13 +53,16 @@ __device__ __forceinline__ double2 to_d2(float2 v) { return make_double2((double
 
 // XT: the input's element type, complex128 or complex64 (the FP32 preconditioner's output, widened exactly).
 // KC: complex k^2 (imaginary parts in p.k2i and p.fldi); the arithmetic is the same with complex k^2 factors.
-template <int ORDER, bool RESID, typename XT = double2, bool KC = false>
-__device__ __forceinline__ void matvec_tile(const XT *__restrict__ x, const double *__restrict__ k2,
-                                             const double4 *__restrict__ fld, const double2 *__restrict__ F,
-                                             double2 *__restrict__ y, const StencilParams &p, int bid) {
+// NR right-hand sides that share the operator (the first nr of them are computed; nr is uniform over the block):
+// each plane of k^2 and each order-6 field block is read once for all of them, the inputs xs[r], Fs[r] and outputs
+// ys[r] are per right-hand side.
+template <int ORDER, bool RESID, typename XT, bool KC, int NR>
+__device__ __forceinline__ void matvec_tile_n(const XT *const *xs, const double *__restrict__ k2,
+                                               const double4 *__restrict__ fld, const double2 *const *Fs,
+                                               double2 *const *ys, const StencilParams &p, int bid, int nr) {
     typedef typename std::conditional<KC, double2, double>::type KT;
     typedef typename std::conditional<KC, F4C, double4>::type FT;
-    __shared__ double2 su[2][LY][LX];
+    __shared__ double2 su[NR][2][LY][LX];
     __shared__ KT sk[2][LY][LX];
     const int T = p.tiles_x * p.tiles_y * p.zchunks;
     const int per = (T + 7) / 8;
@@ -96,7 +99,7 @@ __device__ __forceinline__ void matvec_tile(const XT *__restrict__ x, const doub
     }
     // raw prefetched values: a complex64 input is widened when the plane is written to LDS, not when its load is
     // issued (that would make every plane wait for its own loads)
-    XT ru[2][2];
+    XT ru[NR][2][2];
     KT rk[2][2];
     auto gload = [&](auto setc, int z) {
         constexpr int S = decltype(setc)::value;
@@ -105,7 +108,9 @@ __device__ __forceinline__ void matvec_tile(const XT *__restrict__ x, const doub
         for (int q = 0; q < 2; ++q)
             if (tid + NT * q < LX * LY) {
                 const long long idx = (long long)cz * plane + offs[q];
-                ru[S][q] = x[idx];
+#pragma unroll
+                for (int r = 0; r < NR; ++r)
+                    if (r < nr) ru[r][S][q] = xs[r][idx];
                 if constexpr (KC) rk[S][q] = make_double2(k2[idx], p.k2i[idx]);
                 else rk[S][q] = k2[idx];
             }
@@ -118,7 +123,9 @@ __device__ __forceinline__ void matvec_tile(const XT *__restrict__ x, const doub
             const int e = tid + NT * q;
             if (e < LX * LY) {
                 const double2 f = gh ? cmul(p.gz, fxy[q]) : fxy[q];
-                su[S][e / LX][e % LX] = cmul(f, to_d2(ru[S][q]));
+#pragma unroll
+                for (int r = 0; r < NR; ++r)
+                    if (r < nr) su[r][S][e / LX][e % LX] = cmul(f, to_d2(ru[r][S][q]));
                 sk[S][e / LX][e % LX] = rk[S][q];
             }
         }
@@ -133,14 +140,20 @@ __device__ __forceinline__ void matvec_tile(const XT *__restrict__ x, const doub
             return in ? fld[(long long)z * plane + col] : make_double4(0, 0, 0, 0);
         }
     };
-    auto Fload = [&](int z) -> double2 {
-        return (RESID && valid && z >= 0 && z < nz) ? F[(long long)z * plane + col] : make_double2(0, 0);
+    auto Fload = [&](int r, int z) -> double2 {
+        return (RESID && r < nr && valid && z >= 0 && z < nz) ? Fs[r][(long long)z * plane + col]
+                                                              : make_double2(0, 0);
     };
 
     // output coefficients for outputs p-1, p, p+1 (fm, f0, fp) and the prefetched p+2 (fn)
     FT fm = fload(-1), f0 = fload(z0 - 1), fp = fload(z0), fn;     // fload(-1) is the zero block
-    double2 Fm = make_double2(0, 0), F0 = Fload(z0 - 1), Fn;
-    double2 am = make_double2(0, 0), a0 = am, ap = am;
+    double2 Fm[NR], F0[NR], Fn[NR], am[NR], a0[NR], ap[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        Fm[r] = make_double2(0, 0);
+        F0[r] = Fload(r, z0 - 1);
+        am[r] = a0[r] = ap[r] = make_double2(0, 0);
+    }
     gload(std::integral_constant<int, 0>(), z0 - 1);
     gload(std::integral_constant<int, 1>(), z0);
     auto step = [&](auto setc, int pz) {
@@ -150,16 +163,19 @@ __device__ __forceinline__ void matvec_tile(const XT *__restrict__ x, const doub
         __syncthreads();
         if (pz + 2 <= z1) gload(setc, pz + 2);
         fn = fload(pz + 2);
-        Fn = Fload(pz + 1);
-        {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) Fn[r] = Fload(r, pz + 1);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            if (r >= nr) continue;
             // the plane's 3 x 3 neighbourhood of this column (names: x then y offset, m = -1, p = +1)
-            const double2 uc = su[b][ly][lx], uxm = su[b][ly][lx - 1], uxp = su[b][ly][lx + 1];
-            const double2 uym = su[b][ly - 1][lx], uyp = su[b][ly + 1][lx];
+            const double2 uc = su[r][b][ly][lx], uxm = su[r][b][ly][lx - 1], uxp = su[r][b][ly][lx + 1];
+            const double2 uym = su[r][b][ly - 1][lx], uyp = su[r][b][ly + 1][lx];
             const KT kc = sk[b][ly][lx];
             const double2 Ef = cadd(cadd(uxm, uxp), cadd(uym, uyp));          // in-plane face neighbours
             if (ORDER == 6) {
-                const double2 umm = su[b][ly - 1][lx - 1], upm = su[b][ly - 1][lx + 1];
-                const double2 ump = su[b][ly + 1][lx - 1], upp = su[b][ly + 1][lx + 1];
+                const double2 umm = su[r][b][ly - 1][lx - 1], upm = su[r][b][ly - 1][lx + 1];
+                const double2 ump = su[r][b][ly + 1][lx - 1], upp = su[r][b][ly + 1][lx + 1];
                 const KT kxm = sk[b][ly][lx - 1], kxp = sk[b][ly][lx + 1];
                 const KT kym = sk[b][ly - 1][lx], kyp = sk[b][ly + 1][lx];
                 const KT kmm = sk[b][ly - 1][lx - 1], kpm = sk[b][ly - 1][lx + 1];
@@ -176,8 +192,8 @@ __device__ __forceinline__ void matvec_tile(const XT *__restrict__ x, const doub
                 double2 Piso = cfma(14.0 * p.c1, uc, cfma(3.0 * p.c1, Ef, cscale(C, p.c1)));
                 Piso = cfma(1.0 / 90.0, csub(Ew, wc), Piso);
                 const double2 Pz = cadd(cadd(cscale(uc, 2.0), cscale(wc, p.h2)), Ef);
-                am = cadd(am, kfma(fm.w, Pz, kfma(fm.y, Dx, kfma(fm.z, Dy, Piso))));
-                ap = cadd(ap, kfms(fp.w, Pz, kfma(fp.y, Dx, kfma(fp.z, Dy, Piso))));
+                am[r] = cadd(am[r], kfma(fm.w, Pz, kfma(fm.y, Dx, kfma(fm.z, Dy, Piso))));
+                ap[r] = cadd(ap[r], kfms(fp.w, Pz, kfma(fp.y, Dx, kfma(fp.z, Dy, Piso))));
                 // role of the centre plane: centre, x/y faces, xy edges
                 double2 Qiso = cfma(14.0 * p.c1, Ef, cscale(C, 3.0 * p.c1));
                 Qiso = cfma(1.0 / 90.0, csub(Cw, Ew), Qiso);
@@ -185,7 +201,7 @@ __device__ __forceinline__ void matvec_tile(const XT *__restrict__ x, const doub
                                         csub(cadd(upm, upp), cadd(umm, ump)));
                 const double2 Qy = cadd(cfma(2.0, Dy, cscale(csub(wyp, wym), p.h2)),
                                         csub(cadd(ump, upp), cadd(umm, upm)));
-                a0 = cadd(a0, kfma(f0.x, uc, kfma(f0.y, Qx, kfma(f0.z, Qy, Qiso))));
+                a0[r] = cadd(a0[r], kfma(f0.x, uc, kfma(f0.y, Qx, kfma(f0.z, Qy, Qiso))));
             } else {
                 const double2 Fx = cadd(uxm, uxp), Fy = cadd(uym, uyp);
                 double2 P = cscale(uc, p.c_face[2]);
@@ -193,31 +209,47 @@ __device__ __forceinline__ void matvec_tile(const XT *__restrict__ x, const doub
                 if (ORDER == 4) {
                     const KT kxm = sk[b][ly][lx - 1], kxp = sk[b][ly][lx + 1];
                     const KT kym = sk[b][ly - 1][lx], kyp = sk[b][ly + 1][lx];
-                    const double2 C = cadd(cadd(su[b][ly - 1][lx - 1], su[b][ly - 1][lx + 1]),
-                                           cadd(su[b][ly + 1][lx - 1], su[b][ly + 1][lx + 1]));
+                    const double2 C = cadd(cadd(su[r][b][ly - 1][lx - 1], su[r][b][ly - 1][lx + 1]),
+                                           cadd(su[r][b][ly + 1][lx - 1], su[r][b][ly + 1][lx + 1]));
                     const double2 Ew = cadd(cadd(kmul(kxm, uxm), kmul(kxp, uxp)),
                                             cadd(kmul(kym, uym), kmul(kyp, uyp)));
                     P = kfma(kaff(0.0, p.w_face, kc), uc, cfma(p.c_edge[1], Fx, cfma(p.c_edge[2], Fy, P)));
                     Q = cfma(p.w_face, Ew, cfma(p.c_edge[0], C, Q));
                 }
-                am = cadd(am, P);
-                ap = cadd(ap, P);
-                a0 = cadd(a0, Q);
+                am[r] = cadd(am[r], P);
+                ap[r] = cadd(ap[r], P);
+                a0[r] = cadd(a0[r], Q);
             }
         }
         const int zo = pz - 1;                        // complete after this plane
         if (zo >= z0 && valid) {
             const long long pidx = (long long)zo * plane + col;
-            y[pidx] = RESID ? csub(Fm, am) : am;
+#pragma unroll
+            for (int r = 0; r < NR; ++r)
+                if (r < nr) ys[r][pidx] = RESID ? csub(Fm[r], am[r]) : am[r];
         }
-        am = a0; a0 = ap; ap = make_double2(0, 0);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            am[r] = a0[r]; a0[r] = ap[r]; ap[r] = make_double2(0, 0);
+            Fm[r] = F0[r]; F0[r] = Fn[r];
+        }
         fm = f0; f0 = fp; fp = fn;
-        Fm = F0; F0 = Fn;
     };
     for (int pz = z0 - 1; pz <= z1; pz += 2) {
         step(std::integral_constant<int, 0>(), pz);
         if (pz + 1 <= z1) step(std::integral_constant<int, 1>(), pz + 1);
     }
+}
+
+// One right-hand side.
+template <int ORDER, bool RESID, typename XT = double2, bool KC = false>
+__device__ __forceinline__ void matvec_tile(const XT *__restrict__ x, const double *__restrict__ k2,
+                                             const double4 *__restrict__ fld, const double2 *__restrict__ F,
+                                             double2 *__restrict__ y, const StencilParams &p, int bid) {
+    const XT *xs[1] = {x};
+    const double2 *Fs[1] = {F};
+    double2 *ys[1] = {y};
+    matvec_tile_n<ORDER, RESID, XT, KC, 1>(xs, k2, fld, Fs, ys, p, bid, 1);
 }
 
 }  // namespace

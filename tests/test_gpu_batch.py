@@ -1,6 +1,8 @@
 """Batched solves (many right-hand sides on one medium, and uneven independent problems) against the oracle:
 every problem of a batch must reach the same solution as its own sparse LU solve (relative L2 <= 1e-8 at
 rtol 1e-10), and the graph-replayed cycle must give bitwise the same result as direct launches."""
+import os
+
 import numpy as np
 import pytest
 import scipy.sparse.linalg as spla
@@ -47,8 +49,11 @@ def test_batch_multi_rhs_plane_waves(fp32):
         Fr = op.rhs(6, f, (hh,) * 3, k2[2:-2, 2:-2, 2:-2], op.derived_fields(k2, hh)).ravel()
         xr = lu.solve(Fr)
         rel = np.linalg.norm(host(x) - xr) / np.linalg.norm(xr)
-        print("multi-rhs", fp32, info, rel)
+        # the same method one problem at a time: the batch may differ only in the rounding order
+        _, single = h.helm_gmres_solve(ctx, F, m=30, rtol=1e-10, flexible=True, prec_fp32=fp32)
+        print("multi-rhs", fp32, info, single["iters"], rel)
         assert info["converged"] and rel <= 1e-8
+        assert abs(info["iters"] - single["iters"]) <= 1
 
 
 def test_batch_uneven_problems_graph_and_direct():
@@ -145,3 +150,38 @@ def test_split_direction_tiles_single_and_batch(fp32, tmp_path, monkeypatch):
         rel = np.linalg.norm(host(x) - xr) / np.linalg.norm(xr)
         print("split tiles batch", fp32, info, rel)
         assert info["converged"] and rel <= 1e-8
+
+
+@pytest.mark.parametrize("fp32", [True, False])
+def test_second_gram_schmidt_pass_single_and_batch(fp32):
+    """The second Gram-Schmidt pass (taken only on severe cancellation by default) forced on every step whose
+    orthogonalised vector keeps less than half of its squared norm (HELM_CGS_REORTH = 0.5, the DGKS criterion): the
+    single-problem and the batched solvers then take second passes, and both must reach the default runs'
+    solutions with the same iteration counts."""
+    h = H()
+    n = 18
+    k0 = 0.47 * (n + 1)
+    hh = 1.0 / (n + 1)
+    k2 = synth.inclusions_k2(n, k0)
+    fs = synth.plane_wave_sources(k2, k0, synth.unit_directions(3, seed=4))
+    ctx = h.helm_setup(dev(k2), hh, 6, k0=k0)
+    Fs = [h.helm_rhs(ctx, dev(f)) for f in fs]
+    kw = dict(m=30, rtol=1e-10, flexible=True, prec_fp32=fp32)
+    base = [h.helm_gmres_solve(ctx, F, **kw) for F in Fs]
+    batch = h.helm_batch_create([ctx] * len(Fs), m=30, prec_fp32=fp32)
+    xb, ib = h.helm_batch_solve(batch, Fs, rtol=1e-10)
+    os.environ["HELM_CGS_REORTH"] = "0.5"
+    try:
+        forced = [h.helm_gmres_solve(ctx, F, **kw) for F in Fs]
+        xbf, ibf = h.helm_batch_solve(batch, Fs, rtol=1e-10)
+    finally:
+        del os.environ["HELM_CGS_REORTH"]
+    for (x0, i0), (x1, i1), a, ia, b, iff in zip(base, forced, xb, ib, xbf, ibf):
+        r_single = float(torch.linalg.vector_norm(x1 - x0) / torch.linalg.vector_norm(x0))
+        r_batch = float(torch.linalg.vector_norm(b - a) / torch.linalg.vector_norm(a))
+        print("forced second pass", fp32, i0["iters"], i1["iters"], i1["reorths"], ia["iters"], iff["iters"],
+              iff["cancellations"], r_single, r_batch)
+        assert i1["reorths"] > 0 and iff["cancellations"] > 0
+        assert i1["converged"] and iff["converged"]
+        assert abs(i1["iters"] - i0["iters"]) <= 1 and abs(iff["iters"] - ia["iters"]) <= 1
+        assert r_single <= 1e-9 and r_batch <= 1e-9
