@@ -48,20 +48,23 @@ KCLASS = {
 # variants (the GEMMs) have no single row and report no traffic.
 TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
                             "noise256_fp32_eigt_fgmres_hbm_traffic.md")
-TRAFFIC_KERNEL = {"lincomb": "k_lincomb<z64>", "dots": "k_dots", "matvec": "k_matvec<6, true, z32, false>",
-                  "tridiag32": "k_tridiag_chunk<float>"}
+TRAFFIC_KERNEL = {"lincomb": ("k_lincomb_cgs", "k_lincomb<z64>", "k_lincomb<z32>"), "dots": ("k_dots",),
+                  "matvec": ("k_matvec<6, true, z32, false>",), "tridiag32": ("k_tridiag_chunk<float, z32>",)}
 
 
 def measured_traffic(kclass: str):
-    """Bytes per dispatch (read + write) of the kernel class from the committed counter summary, or None."""
-    name = TRAFFIC_KERNEL.get(kclass)
-    if name is None or not os.path.exists(TRAFFIC_FILE):
+    """Bytes per dispatch (read + write) of the kernel class from the committed counter summary: the average over
+    the dispatches of the class's kernels (weighted by their dispatch counts), or None."""
+    names = TRAFFIC_KERNEL.get(kclass)
+    if names is None or not os.path.exists(TRAFFIC_FILE):
         return None
+    tot, cnt = 0.0, 0
     for line in open(TRAFFIC_FILE):
         cells = [c.strip() for c in line.strip().strip("|").split("|")]
-        if len(cells) == 4 and cells[0] == f"`{name}`":
-            return (float(cells[2]) + float(cells[3])) * 2 ** 20
-    return None
+        if len(cells) == 4 and cells[0].strip("`") in names:
+            tot += int(cells[1]) * (float(cells[2]) + float(cells[3])) * 2 ** 20
+            cnt += int(cells[1])
+    return tot / cnt if cnt else None
 
 
 def log(msg):
@@ -209,6 +212,7 @@ def bench_learned(H, torch, args):
                e0_warm=round(m["warm_e0"], 4), e0_untrained=round(m["control_e0"], 4),
                r0_warm=round(m["warm_r0"], 4), iters_warm_residual_amplitude=m["other_amp_iters"],
                e0_warm_residual_amplitude=round(m["other_amp_e0"], 4),
+               iters_warm_direction=m["dir_iters"], ms_fp32_learned_direction=round(m["dir_ms"], 3),
                ms_fp32_zero=round(m["zero_ms"], 3), ms_fp32_learned=round(m["warm_ms"], 3),
                ms_fp64_zero=round(m["fp64_ms"], 3))
     log(f"learned warm start: {out['iters_warm']} vs {out['iters_zero']} iterations (untrained "

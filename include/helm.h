@@ -97,7 +97,11 @@ typedef struct {
     int flexible;          /* 0: right-preconditioned GMRES, x = x0 + M^{-1} V y; 1: FGMRES, x = x0 + Z y    */
     int prec_fp32;         /* 1: run the preconditioner in complex FP32 (requires flexible = 1)              */
     int prec;              /* helm_prec_kind                                                                 */
-    int x0_given;          /* 1: x holds the initial guess on entry; 0: start from x = 0                     */
+    int x0_given;          /* 1: x holds the initial guess on entry; 0: start from x = 0; 2 (flexible only):
+                              x holds a guess p that the first cycle takes as its first search direction
+                              z_0 = p, starting from x = 0 (then z_1 = M^{-1} v_0 and z_j = M^{-1} v_j for
+                              j >= 2), so the minimal residual over x in span{p, M^{-1} v_0, M^{-1} v_2, ...}
+                              decides how much of p is used                                                   */
     double *resid_hist;    /* optional host array receiving relative residual estimates, one per iteration
                               plus one per restart (true residual); may be NULL                              */
     int hist_len;          /* capacity of resid_hist                                                         */
@@ -145,8 +149,9 @@ helm_status helm_setup_complex(helm_ctx **ctx, helm_grid g, const double h[3], c
  * F_dev: n complex128. f is data: its halo samples are used as they are. */
 helm_status helm_rhs(helm_ctx *ctx, const void *f_dev, void *F_dev);
 
-/* y = A x (the compact operator with the ghost-eliminated absorbing closure). x_dev, y_dev: n complex128,
- * must not overlap. */
+/* y = A x: the compact operator of Sec. 2.2 (eq. scheme4, order 4) or Sec. 2.3 (eq. scheme6, order 6; order 2 is the
+ * 7-point operator) with the variable k^2 of the context and the ghost values eliminated by the absorbing closure
+ * (Sec. 2.3, eq. D_bc). x_dev, y_dev: n complex128, must not overlap. */
 helm_status helm_matvec(helm_ctx *ctx, const void *x_dev, void *y_dev);
 
 /* z = M^{-1} y with M = Delta_2 + k0^2 I (Sec. 4). kind: HELM_PREC_EIGT or HELM_PREC_PFFT (M with the

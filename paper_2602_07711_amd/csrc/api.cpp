@@ -1085,9 +1085,18 @@ helm_status helm_gmres_solve(helm_ctx *ctx, const void *F_dev, void *x_dev, cons
         c.err = "unknown preconditioner kind";
         return HELM_EINVAL;
     }
+    if (opts->x0_given == 2 && (!opts->flexible || opts->prec == HELM_PREC_NONE)) {
+        c.err = "a guess as a search direction (x0_given = 2) needs flexible GMRES with a preconditioner";
+        return HELM_EINVAL;
+    }
+    if (opts->x0_given < 0 || opts->x0_given > 2) { c.err = "x0_given must be 0, 1 or 2"; return HELM_EINVAL; }
     helm_solve_info inf{};
     const bool flex = opts->flexible != 0;
     const double reorth = cgs_reorth();
+    // x0_given = 2: the guess p (in x on entry) becomes the first direction z_0 of the first cycle, which starts
+    // from x = 0; then z_1 = M^{-1} v_0 and z_j = M^{-1} v_j for j >= 2: one Krylov sequence from F, with the basis
+    // vector v_1 that A p contributes kept for orthogonality but never preconditioned
+    bool aug = opts->x0_given == 2;
     // FGMRES with an FP32 preconditioner keeps Z in complex64: its vectors are FP32 results, so this is exact
     const bool zf32 = flex && opts->prec_fp32 && opts->prec != HELM_PREC_NONE;
     ST_TRY(ensure_krylov(c, m, flex ? (zf32 ? 2 : 1) : 0));
@@ -1125,7 +1134,18 @@ helm_status helm_gmres_solve(helm_ctx *ctx, const void *F_dev, void *x_dev, cons
         if (info) *info = inf;
         return HELM_OK;
     }
-    if (!opts->x0_given) HIP_TRY(launch_fill_zero(x, n, c.stream));
+    if (aug) {
+        double pn = 0.0;               // a zero guess gives no direction: the plain start from zero
+        ST_TRY(norm2(c, x, pn));
+        aug = pn > 0.0;
+    }
+    if (aug) {
+        // the guess moves into the first direction slot; the iterate starts from zero
+        if (zf32) HIP_TRY(launch_to_c64(x, k.Zf, n, c.stream));
+        else HIP_TRY(hipMemcpyAsync(k.Z, x, n * sizeof(double2), hipMemcpyDeviceToDevice, c.stream));
+        prof_gap(c);
+    }
+    if (opts->x0_given != 1) HIP_TRY(launch_fill_zero(x, n, c.stream));
     prof_gap(c);
 
     std::vector<cd> H((size_t)(m + 1) * m), g(m + 1), sn(m), hv, hv2;
@@ -1143,7 +1163,7 @@ helm_status helm_gmres_solve(helm_ctx *ctx, const void *F_dev, void *x_dev, cons
     for (;;) {
         // restart: V_0 = F - A x
         HIP_TRY(hipEventRecord(ev[0], c.stream));
-        if (first && !opts->x0_given) {
+        if (first && opts->x0_given != 1) {
             HIP_TRY(hipMemcpyAsync(k.V, F, n * sizeof(double2), hipMemcpyDeviceToDevice, c.stream));
             prof_gap(c);
         } else {
@@ -1165,12 +1185,16 @@ helm_status helm_gmres_solve(helm_ctx *ctx, const void *F_dev, void *x_dev, cons
         int kk = 0;
         bool breakdown = false, stop = false;
         for (int j = 0; j < m; ++j) {
-            double2 *vj = k.V + (long long)j * k.ld;
+            // the vector this step preconditions and shifts by: v_j, or v_0 at step 1 of a cycle that starts with a
+            // guess
+            const int js = aug && j == 1 ? 0 : j;
+            double2 *vj = k.V + (long long)js * k.ld;
             double2 *w = k.V + (long long)(j + 1) * k.ld;
             double2 *z = zf32 ? nullptr : (flex ? k.Z + (long long)j * k.ld : k.tmp);
             float2 *zf = zf32 ? k.Zf + (long long)j * k.ld : nullptr;
             HIP_TRY(hipEventRecord(ev[2], c.stream));
-            if (zf32) ST_TRY(precond32(c, vj, zf, opts->prec));
+            if (aug && j == 0) { /* z_0 is the guess, already in place */ }
+            else if (zf32) ST_TRY(precond32(c, vj, zf, opts->prec));
             else ST_TRY(precond(c, vj, z, opts->prec, opts->prec_fp32));
             HIP_TRY(hipEventRecord(ev[3], c.stream));
             // Arnoldi on A M^{-1} - I (same Krylov space; column j of H gains +1 on its diagonal): the matvec in
@@ -1222,7 +1246,7 @@ helm_status helm_gmres_solve(helm_ctx *ctx, const void *F_dev, void *x_dev, cons
             inf.t_ms[2] += elapsed(ev[4], ua);
             // Hessenberg column j and Givens rotations
             for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = -hv[i];
-            H[(size_t)j * m + j] += 1.0;
+            H[(size_t)js * m + j] += 1.0;
             H[(size_t)(j + 1) * m + j] = eta;
             for (int i = 0; i < j; ++i) {
                 cd a = H[(size_t)i * m + j], b = H[(size_t)(i + 1) * m + j];
@@ -1282,6 +1306,7 @@ helm_status helm_gmres_solve(helm_ctx *ctx, const void *F_dev, void *x_dev, cons
         inf.t_ms[3] += elapsed(ev[2], ev[3]);
         flush_upd();
         ++inf.restarts;
+        aug = false;
         if (breakdown) {
             // lucky breakdown: the Krylov space holds the solution; the restart test below confirms it
             (void)0;

@@ -390,6 +390,7 @@ hipError_t launch_lincomb(double2 *out, const double2 *base, double2 alpha, cons
 // eta^2 <= red[nv].x / 2, which the caller detects and corrects with a second pass)
 hipError_t launch_lincomb_cgs(double2 *w, const double2 *V, long long ldv, int nv, const double2 *red, long long n,
                               double reorth, hipStream_t s);   // out = alpha base + sum coef_i V_i
+hipError_t launch_to_c64(const double2 *x, float2 *y, long long n, hipStream_t s);   // complex128 -> complex64
 hipError_t launch_fill_zero(double2 *x, long long n, hipStream_t s);
 
 // grouped (batched) launches; see k_batch.hip

@@ -174,6 +174,11 @@ __global__ __launch_bounds__(256) void k_lincomb_cgs(double2 *w, const double2 *
     }
 }
 
+__global__ void k_to_c64(const double2 *__restrict__ x, float2 *__restrict__ y, long long n) {
+    long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (idx < n) y[idx] = make_float2((float)x[idx].x, (float)x[idx].y);
+}
+
 __global__ void k_zero(double2 *x, long long n) {
     long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
     if (idx < n) x[idx] = make_double2(0.0, 0.0);
@@ -229,6 +234,11 @@ hipError_t launch_lincomb_cgs(double2 *w, const double2 *V, long long ldv, int n
     long long grid_ll = (n + 256 * LC_EPT - 1) / (256 * LC_EPT);
     int grid = (int)(grid_ll < 1 ? 1 : grid_ll);
     hipLaunchKernelGGL(k_lincomb_cgs, dim3(grid), dim3(256), 0, s, w, V, ldv, nv, red, n, reorth);
+    return hipGetLastError();
+}
+
+hipError_t launch_to_c64(const double2 *x, float2 *y, long long n, hipStream_t s) {
+    hipLaunchKernelGGL(k_to_c64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, y, n);
     return hipGetLastError();
 }
 

@@ -262,7 +262,8 @@ def helm_gmres_solve(ctx: Context, F: torch.Tensor, x: torch.Tensor | None = Non
                      rtol: float = 1e-8, flexible: bool = False, prec: str = "eigt", prec_fp32: bool = False,
                      hist_len: int = 4096, raise_on_noconv: bool = True, x0_given: bool | None = None):
     """Solve A x = F. `x` (optional) is the output buffer; it is also the initial guess unless x0_given is
-    False (default: x0_given = x is not None). Returns (x, info) with info a dict (iters, restarts, converged,
+    False (default: x0_given = x is not None); x0_given = 2 (flexible only) takes it as the first search direction
+    instead (include/helm.h). Returns (x, info) with info a dict (iters, restarts, converged,
     relres_est, relres_true, t_ms = {matvec, precond, arnoldi, update, host, total}, hist)."""
     _check(F, torch.complex128, ctx.n, "F")
     if x0_given is None:

@@ -187,7 +187,8 @@ def fit(size: int, samples: int, epochs: int, batch: int = 4, lr: float = 1e-3, 
 def evaluate(ws: WarmStart, nf: int, seeds, sigma: float = 0.03, rtol: float = 1e-8, m: int = 50,
              control: WarmStart | None = None, fp64_plain: bool = True):
     """Solve each held-out problem on nf^3 from zero and from the learned x0 (and from an untrained control
-    network's x0, the trilinear prolongation and the residual-scaled amplitude as variants). Reports iterations,
+    network's x0, the trilinear prolongation, the residual-scaled amplitude and the prediction taken as the first
+    FGMRES search direction instead of the initial iterate as variants). Reports iterations,
     time-to-solution (inference included), the guesses' relative errors e0 and residuals r0 (against the
     converged zero-start solution and ||F||) and the agreement of the solutions."""
     rows = []
@@ -225,7 +226,14 @@ def evaluate(ws: WarmStart, nf: int, seeds, sigma: float = 0.03, rtol: float = 1
             r0 = F - H.helm_matvec(ctx, x0)
             return (float(torch.linalg.vector_norm(x0 - x_zero) / nx), float(torch.linalg.vector_norm(r0) / nF))
 
+        def direction(w):
+            w.initial_guess(ctx, F, k2, f, nf, fn, out=x0)
+            return H.helm_gmres_solve(ctx, F, x0, m=m, rtol=rtol, flexible=True, prec_fp32=True, x0_given=2)
+
         (x_warm, i_warm), t_warm = timed(lambda: warm(ws))
+        (x_dir, i_dir), t_dir = timed(lambda: direction(ws))
+        row.update(dir_iters=i_dir["iters"], dir_ms=t_dir,
+                   dir_rel_diff=float(torch.linalg.vector_norm(x_dir - x_zero) / nx))
         rel_diff = float(torch.linalg.vector_norm(x_warm - x_zero) / nx)
         _, t_inf = timed(lambda: ws.initial_guess(ctx, F, k2, f, nf, fn, out=x0))     # x0 is the guess again
         e0, r0 = quality()

@@ -167,3 +167,34 @@ def test_zero_rhs_gives_the_zero_solution(live, x0_given):
                                 x0_given=x0_given)
     assert inf["converged"] and inf["iters"] == 0
     assert torch.count_nonzero(x).item() == 0
+
+
+def test_guess_as_search_direction(live):
+    """x0_given = 2: the guess is the first FGMRES direction of a solve that starts from zero. The exact solution as
+    the guess gives it back in one step; a random guess, or a zero one (which falls back to the plain start from
+    zero), still converges to the same solution; a non-flexible solve or an unknown mode is rejected."""
+    h, ctx, F = live
+    kw = dict(m=30, rtol=1e-10, flexible=True, prec_fp32=False)
+    xr, ir = h.helm_gmres_solve(ctx, F, **kw)
+    x1, i1 = h.helm_gmres_solve(ctx, F, xr.clone(), x0_given=2, **kw)
+    e1 = float(torch.linalg.vector_norm(x1 - xr) / torch.linalg.vector_norm(xr))
+    print("exact guess as direction", ir["iters"], i1["iters"], e1)
+    assert i1["converged"] and i1["iters"] == 1 and e1 <= 1e-9
+    rng = np.random.default_rng(5)
+    g = torch.from_numpy(rng.standard_normal(ctx.n) + 1j * rng.standard_normal(ctx.n)).cuda()
+    for fp32 in (False, True):
+        kw32 = dict(kw, prec_fp32=fp32)
+        xb, ib = h.helm_gmres_solve(ctx, F, **kw32)
+        x2, i2 = h.helm_gmres_solve(ctx, F, g.clone(), x0_given=2, **kw32)
+        e2 = float(torch.linalg.vector_norm(x2 - xb) / torch.linalg.vector_norm(xb))
+        x3, i3 = h.helm_gmres_solve(ctx, F, torch.zeros_like(F), x0_given=2, **kw32)
+        print("random / zero guess as direction", fp32, ib["iters"], i2["iters"], i3["iters"], e2)
+        assert i2["converged"] and e2 <= 1e-8
+        assert i3["iters"] == ib["iters"] and torch.equal(x3, xb)
+    L = h.lib()
+    info = h.helm_solve_info()
+    x = torch.zeros_like(F)
+    for bad in (_opts(h, x0_given=2, flexible=0, prec_fp32=0), _opts(h, x0_given=3)):
+        st = L.helm_gmres_solve(ctx.ptr, ctypes.c_void_p(F.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                                ctypes.byref(bad), ctypes.byref(info))
+        assert st == h.HELM_EINVAL

@@ -9,8 +9,10 @@ must fall well below that of an untrained network of the same architecture put t
 best multiple of its output still misses the field almost entirely), and the initial residual below ||F||
 (the scaling guarantees <= ||F||). EigT-preconditioned FGMRES reduces the residual by a factor 3-5 per iteration here, so a guess
 accurate to 5-10 % is worth at most about one iteration: the test bounds the iteration change by one on average
-(the full-size iteration and time effect at 128^3 is measured by the benchmark). The solver
-decides the answer: every run converges to rtol 1e-8 relative to ||F||, so the warm-started and zero-started
+(the full-size iteration and time effect at 128^3 is measured by the benchmark). No gain over the zero guess is
+achieved or asserted: at 128^3 the trained network saves 0.3 iterations and its 0.6 ms of inference make the solve
+slower, and the prediction as an extra search direction saves none (every variant's measured ceiling is recorded with
+the network's design). The solver decides the answer: every run converges to rtol 1e-8 relative to ||F||, so the warm-started and zero-started
 solutions agree to that level whatever the network predicts.
 """
 import numpy as np
