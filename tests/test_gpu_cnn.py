@@ -146,6 +146,32 @@ def test_training_reduces_loss():
     net.close()
 
 
+def test_saved_network_reloads_bitwise(tmp_path):
+    """A trained warm-start network written by WarmStart.save and read back by WarmStart.load holds the same
+    parameters and predicts the same output, bit for bit (the checkpoint is the parameter vector and the
+    scaling metadata; the optimiser state is not part of it)."""
+    from paper_2602_07711_amd import warmstart as W
+    S, B = 16, 2
+    net = H().Cnn(S, max_batch=B, bf16=True, seed=8)
+    rng = np.random.default_rng(18)
+    x = rng.standard_normal((B, 2, S ** 3)).astype(np.float32)
+    t = (0.5 * x[:, ::-1] - 0.2).astype(np.float32)
+    xd, td = torch.from_numpy(x).cuda(), torch.from_numpy(np.ascontiguousarray(t)).cuda()
+    for _ in range(5):
+        net.train_step(xd, td, 1e-3, want_loss=False)
+    ws = W.WarmStart(net, 33.0, 2.5, cubic=False)
+    path = str(tmp_path / "ws.npz")
+    ws.save(path)
+    ws2 = W.WarmStart.load(path, max_batch=B)
+    assert (ws2.k0, ws2.t_scale, ws2.cubic, ws2.net.size, ws2.net.bf16) == (33.0, 2.5, False, S, True)
+    assert np.array_equal(ws2.net.params().numpy(), net.params().numpy())
+    y1 = net.forward(xd).cpu().numpy()
+    y2 = ws2.net.forward(xd).cpu().numpy()
+    assert np.array_equal(y1, y2)
+    net.close()
+    ws2.net.close()
+
+
 @pytest.mark.parametrize("cubic", [False, True], ids=["linear", "cubic"])
 @pytest.mark.parametrize("gamma", [0.0, (2 + 0.9j) / (2 - 0.9j)], ids=["zero", "abc"])
 @pytest.mark.parametrize("nc,nf", [(8, 8), (8, 17), (16, 33), (13, 41), (64, 128)])
