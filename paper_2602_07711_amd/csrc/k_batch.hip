@@ -369,10 +369,7 @@ __global__ void k_b_trisolve(BState *__restrict__ st, BArrays a, const BParams *
 // ---------------------------------------------------------------------------------------------- linear combinations
 constexpr int BLC_EPT = 4;
 __device__ __forceinline__ double2 wide_b(const double2 *p) { return ld_stream(p); }
-__device__ __forceinline__ double2 wide_b(const float2 *p) {
-    const float2 v = *p;
-    return make_double2((double)v.x, (double)v.y);
-}
+__device__ __forceinline__ double2 wide_b(const float2 *p) { return ld_stream_wide(p); }
 // acc += sum_{i<nv} c_i V_i over BLC_EPT elements per thread, four vectors per round (16 loads in flight)
 template <typename VT>
 __device__ __forceinline__ void b_accum(double2 *acc, const bool *ok, long long start, const VT *V, long long ldv,

@@ -40,10 +40,7 @@ struct LcCoef { double2 c[LC_MAX]; };
 constexpr int LC_EPT = 4;   // elements per thread (independent loads in flight per vector)
 
 __device__ __forceinline__ double2 wide(const double2 *p) { return ld_stream(p); }
-__device__ __forceinline__ double2 wide(const float2 *p) {
-    const float2 v = *p;
-    return make_double2((double)v.x, (double)v.y);
-}
+__device__ __forceinline__ double2 wide(const float2 *p) { return ld_stream_wide(p); }
 
 template <typename VT>
 __global__ __launch_bounds__(256) void k_lincomb(double2 *out, const double2 *base, double2 alpha,

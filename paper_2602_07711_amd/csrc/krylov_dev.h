@@ -13,6 +13,12 @@ __device__ __forceinline__ double2 ld_stream(const double2 *p) {
     const v2d_nt v = __builtin_nontemporal_load(reinterpret_cast<const v2d_nt *>(p));
     return make_double2(v.x, v.y);
 }
+// a complex64 basis vector (the Z basis of FGMRES with the FP32 preconditioner), widened exactly
+typedef float v2f_nt __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double2 ld_stream_wide(const float2 *p) {
+    const v2f_nt v = __builtin_nontemporal_load(reinterpret_cast<const v2f_nt *>(p));
+    return make_double2((double)v.x, (double)v.y);
+}
 
 constexpr int DOT_EPT = 16;                // elements per thread (8: 0.35 ms slower per 256^3 solve; 32: spills)
 constexpr int DOT_CHUNK = 256 * DOT_EPT;   // elements per block
