@@ -411,6 +411,9 @@ __device__ __forceinline__ void fold_tile(const TD *__restrict__ D, const TM *__
                 }
             }
     } else {
+        // FP32 64 x 64 tiles park P in LDS (32 KiB per block, read back only by the thread that wrote it)
+        constexpr bool PLDS = sizeof(T) == 4 && FM * FN * 4 * 256 * sizeof(CT) <= 32768;
+        __shared__ CT sP[PLDS ? FM * FN * 4 * 256 : 1];
         int mt, nt;
         if constexpr (MODE == FOLD_XI) {
             const int tn = (ms + BN - 1) / BN;
@@ -463,7 +466,8 @@ __device__ __forceinline__ void fold_tile(const TD *__restrict__ D, const TM *__
             }
             if (q == 0) {
                 // park P in this thread's own output slots (first half of the axis; the skew results go to the
-                // disjoint second half) instead of holding a second accumulator set in registers
+                // disjoint second half), or for the FP32 64 x 64 tile in a per-thread LDS area, instead of holding a
+                // second accumulator set in registers
 #pragma unroll
                 for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -474,7 +478,8 @@ __device__ __forceinline__ void fold_tile(const TD *__restrict__ D, const TM *__
                             if (!slot(lane, i, j, r, gm, gn)) continue;
                             T re, im;
                             acc_value<T>(t, i, j, r, re, im);
-                            C[(long long)gm * ld + gn] = pack<TC, T>(re, im);
+                            if constexpr (PLDS) sP[((i * FN + j) * 4 + r) * 256 + threadIdx.x] = pack<CT, T>(re, im);
+                            else C[(long long)gm * ld + gn] = pack<TC, T>(re, im);
                         }
                 zero();
                 // a compiler memory barrier: the epilogue reloads P instead of the stored values being
@@ -497,14 +502,24 @@ __device__ __forceinline__ void fold_tile(const TD *__restrict__ D, const TM *__
                     T re, im;
                     acc_value<T>(t, i, j, r, re, im);
                     TC *c = C + (long long)gm * ld + gn;
-                    const TC pv = *c;
-                    const T p0 = (T)pv.x, p1 = (T)pv.y;
+                    T p0, p1;
+                    if constexpr (PLDS) {
+                        const CT pv = sP[((i * FN + j) * 4 + r) * 256 + threadIdx.x];
+                        p0 = pv.x;
+                        p1 = pv.y;
+                    } else {
+                        const TC pv = *c;
+                        p0 = (T)pv.x;
+                        p1 = (T)pv.y;
+                    }
                     const int h = MODE == FOLD_XI ? gn : gm;     // position along the transformed axis
                     if (h < ma) {
                         *c = pack<TC, T>(p0 + re, p1 + im);
                         TC *mirror = MODE == FOLD_XI ? C + (long long)gm * ld + (n - 1 - gn)
                                                      : C + (long long)(n - 1 - gm) * ld + gn;
                         *mirror = pack<TC, T>(p0 - re, p1 - im);
+                    } else if constexpr (PLDS) {
+                        *c = pack<TC, T>(p0, p1);                 // the middle of an odd axis: P alone
                     }
                 }
     }
