@@ -238,8 +238,10 @@ template <int MODE, int BM, int BN> __host__ __device__ inline long long fold_ti
 // Occupancy the register allocator is asked for: without it, the FP64 kernels keep their accumulators in
 // AGPRs on top of the VGPRs the operand staging needs and drop to two waves per SIMD. The x-forward transforms
 // with FP64 data hold two raw FP64 values per operand element across a chunk (the butterfly is formed when the
-// chunk is written to LDS) and get one wave less.
+// chunk is written to LDS) and get one wave less. The FP32 inverse transforms on 64 x 64 x 16 tiles park P in LDS
+// (fold_tile), 48 KiB per block in all, which fits three blocks per CU.
 template <typename T, typename TD, int MODE, int BM, int BN, int BK> constexpr int fold_waves() {
+    if (sizeof(T) == 4 && (MODE == FOLD_XI || MODE == FOLD_YI) && BM * BN * BK <= 64 * 64 * 16) return 3;
     return (sizeof(T) == 8 ? (BM * BN * BK <= 64 * 64 * 16 ? 3 : 1) : (BM * BN * BK <= 64 * 64 * 16 ? 4 : 2)) -
            ((MODE == FOLD_XF && sizeof(TD) == 16 && BM * BN * BK <= 64 * 64 * 16) ? 1 : 0);
 }
